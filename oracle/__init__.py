@@ -1,0 +1,220 @@
+"""CPU oracle for the Kadanoff-Baym history-integral path (TEST INFRASTRUCTURE ONLY).
+
+A ctypes shim over ``oracle.c``: plain FP64 loops written from the paper
+(arXiv:2405.08737).  Only ``tests/``, the package's ``smoke()`` check and the
+benchmark's CPU-baseline leg may import this module; the GPU library never
+does, and the two share no code.
+
+Arrays are numpy complex128 / float64, C-contiguous, in the layout stated at
+the top of ``oracle.c``.
+
+Pins: every function here is checked by ``tests/test_oracle_*.py`` against
+mathematics fixed independently of this code (closed forms, exactness on
+polynomials, textbook Adams-Moulton coefficients, symmetry and conservation
+invariants, brute force on tiny inputs, finite differences).  No function is
+"parity unpinned".
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_SO = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+F_IR, F_IL, F_ITV, F_JTV = 1, 2, 4, 8
+F_ALL = F_IR | F_IL | F_ITV | F_JTV
+
+
+def build() -> str:
+    """Compile oracle.c into liboracle.so (always recompiles). Plain FP64: no contraction."""
+    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off", "-o", _SO + ".tmp",
+           _SRC, "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(_SO + ".tmp", _SO)
+    return _SO
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        lib = ctypes.CDLL(_SO)
+        c = ctypes
+        P, I32, I64, D = c.c_void_p, c.c_int, c.c_int64, c.c_double
+        lib.orc_gauss_legendre.argtypes = [I32, P, P]
+        lib.orc_local_weights.argtypes = [P, I32, I32, P]
+        lib.orc_weights.argtypes = [P, P, I32, P]
+        lib.orc_tau_weights.argtypes = [D, I32, I32, P, P, P]
+        lib.orc_sigma_pair.argtypes = [I32, I32, I32, I64, P, P, P, I32, I32, P, P]
+        lib.orc_sigma_row.argtypes = [I32, I32, I32, I64, P, P, P, P, I32, P, P, P]
+        lib.orc_collision.argtypes = [I32, I32, I32, I64, P, P, P, P, P, P, P, P, P, P, P, I32, I32,
+                                      I32, I32, P, P, P, P]
+        lib.orc_collision_vjp.argtypes = [I32, I32, I32, I64, P, P, P, P, P, P, P, P, P, P, P, I32,
+                                          I32, I32, I32, P, P, P, P, P, P, P, P, P, P, P]
+        lib.orc_sigma_row_vjp.argtypes = [I32, I32, I32, I64, P, P, P, P, I32, P, P, P, P, P, P, P]
+        for name in ("orc_gauss_legendre", "orc_local_weights", "orc_weights", "orc_tau_weights",
+                     "orc_sigma_pair", "orc_sigma_row", "orc_collision", "orc_collision_vjp",
+                     "orc_sigma_row_vjp"):
+            getattr(lib, name).restype = None
+        _lib = lib
+    return _lib
+
+
+def _p(a):
+    if a is None:
+        return None
+    assert isinstance(a, np.ndarray) and a.flags.c_contiguous, "oracle arrays must be C-contiguous"
+    return a.ctypes.data
+
+
+def _c(a, dtype=np.complex128):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def gauss_legendre(m: int):
+    x = np.empty(m)
+    w = np.empty(m)
+    _load().orc_gauss_legendre(m, _p(x), _p(w))
+    return x, w
+
+
+def local_weights(t, p: int, k: int) -> np.ndarray:
+    t = _c(t, np.float64)
+    lam = np.empty(k)
+    _load().orc_local_weights(_p(t), p, k, _p(lam))
+    return lam
+
+
+def weights(t, order) -> np.ndarray:
+    """Composite weight matrix w[n][s] (nt x nt)."""
+    t = _c(t, np.float64)
+    order = _c(order, np.int32)
+    nt = len(t)
+    w = np.empty((nt, nt))
+    _load().orc_weights(_p(t), _p(order), nt, _p(w))
+    return w
+
+
+def tau_weights(beta: float, ntau: int, tau_order: int):
+    """(wf, wb, wfull): forward [0,tau_j] rule, backward [tau_j,beta] rule, full-range rule."""
+    wf = np.empty((ntau, ntau))
+    wb = np.empty((ntau, ntau))
+    wfull = np.empty(ntau)
+    _load().orc_tau_weights(beta, ntau, tau_order, _p(wf), _p(wb), _p(wfull))
+    return wf, wb, wfull
+
+
+class Green:
+    """Host Green's function in KP storage (see oracle.c)."""
+
+    def __init__(self, kp, rdiag, tv=None, mat=None):
+        self.kp = _c(kp)
+        self.rdiag = _c(rdiag)
+        self.nt_rows, self.ldt, self.N, _ = self.kp.shape
+        self.nt = self.rdiag.shape[0]
+        ntau = 0 if tv is None else tv.shape[1]
+        self.ntau = ntau
+        self.tv = _c(tv) if tv is not None else np.zeros((self.nt, 0, self.N, self.N), np.complex128)
+        self.mat = (_c(mat) if mat is not None
+                    else np.zeros((ntau, self.N, self.N), np.complex128))
+        assert self.tv.shape == (self.nt, ntau, self.N, self.N), self.tv.shape
+        assert self.mat.shape == (ntau, self.N, self.N), self.mat.shape
+        assert self.rdiag.shape == (self.nt, self.N, self.N) and self.nt_rows == self.nt
+
+    def args(self):
+        return (self.N, self.nt, self.ntau, self.ldt)
+
+
+def sigma_pair(G: Green, u, a: int, b: int):
+    u = _c(u, np.float64)
+    N = G.N
+    les = np.empty((N, N), np.complex128)
+    gtr = np.empty((N, N), np.complex128)
+    _load().orc_sigma_pair(*G.args(), _p(G.kp), _p(G.rdiag), _p(u), a, b, _p(les), _p(gtr))
+    return les, gtr
+
+
+def sigma_row(G: Green, u, n: int):
+    """(ret[n+1], les[n+1], stv[ntau]) at t_n."""
+    u = _c(u, np.float64)
+    N = G.N
+    ret = np.empty((n + 1, N, N), np.complex128)
+    les = np.empty((n + 1, N, N), np.complex128)
+    stv = np.empty((G.ntau, N, N), np.complex128)
+    _load().orc_sigma_row(*G.args(), _p(G.kp), _p(G.rdiag), _p(G.tv), _p(u), n, _p(ret), _p(les),
+                          _p(stv))
+    return ret, les, stv
+
+
+class Weights:
+    def __init__(self, w, wfull=None, wf=None, wb=None):
+        self.w = _c(w, np.float64)
+        self.wfull = _c(wfull if wfull is not None else np.zeros(0), np.float64)
+        self.wf = _c(wf if wf is not None else np.zeros((0, 0)), np.float64)
+        self.wb = _c(wb if wb is not None else np.zeros((0, 0)), np.float64)
+
+    @classmethod
+    def build(cls, t, order, beta=None, ntau=0, tau_order=5):
+        w = weights(t, order)
+        if ntau > 0:
+            wf, wb, wfull = tau_weights(beta, ntau, tau_order)
+            return cls(w, wfull, wf, wb)
+        return cls(w)
+
+
+def collision(G: Green, sig, W: Weights, n: int, m0: int = 0, m1: int | None = None,
+              flags: int = F_ALL):
+    """(IR, IL, Itv, Jtv) for m in [m0, m1) at row n."""
+    m1 = n + 1 if m1 is None else m1
+    ret, les, stv = (_c(x) for x in sig)
+    N, nm = G.N, m1 - m0
+    IR = np.zeros((nm, N, N), np.complex128)
+    IL = np.zeros((nm, N, N), np.complex128)
+    Itv = np.zeros((nm, N, N), np.complex128)
+    Jtv = np.zeros((G.ntau, N, N), np.complex128)
+    _load().orc_collision(*G.args(), _p(G.kp), _p(G.rdiag), _p(G.tv), _p(G.mat), _p(ret), _p(les),
+                          _p(stv), _p(W.w), _p(W.wfull), _p(W.wf), _p(W.wb), n, m0, m1, flags,
+                          _p(IR), _p(IL), _p(Itv), _p(Jtv))
+    return IR, IL, Itv, Jtv
+
+
+def collision_vjp(G: Green, sig, W: Weights, n: int, m0: int, m1: int, cot, flags: int = F_ALL,
+                  grads=None):
+    """Adjoint of collision.  cot = (gIR, gIL, gItv, gJtv).
+    Returns (gkp, grdiag, gtv, gmat, gret, gles, gstv); Green's-function gradients are
+    accumulated into ``grads`` when given (else into zeros)."""
+    ret, les, stv = (_c(x) for x in sig)
+    gIR, gIL, gItv, gJtv = (_c(x) for x in cot)
+    N = G.N
+    if grads is None:
+        grads = (np.zeros_like(G.kp), np.zeros_like(G.rdiag), np.zeros_like(G.tv),
+                 np.zeros_like(G.mat))
+    gkp, grd, gtv, gmat = grads
+    gret = np.empty((n + 1, N, N), np.complex128)
+    gles = np.empty((n + 1, N, N), np.complex128)
+    gstv = np.empty((G.ntau, N, N), np.complex128)
+    _load().orc_collision_vjp(*G.args(), _p(G.kp), _p(G.rdiag), _p(G.tv), _p(G.mat), _p(ret),
+                              _p(les), _p(stv), _p(W.w), _p(W.wfull), _p(W.wf), _p(W.wb), n, m0,
+                              m1, flags, _p(gIR), _p(gIL), _p(gItv), _p(gJtv), _p(gkp), _p(grd),
+                              _p(gtv), _p(gmat), _p(gret), _p(gles), _p(gstv))
+    return gkp, grd, gtv, gmat, gret, gles, gstv
+
+
+def sigma_row_vjp(G: Green, u, n: int, gsig, grads=None, gu=None):
+    """Adjoint of sigma_row.  gsig = (gret, gles, gstv).  Returns (gkp, grdiag, gtv, gu)."""
+    u = _c(u, np.float64)
+    gret, gles, gstv = (_c(x) for x in gsig)
+    if grads is None:
+        grads = (np.zeros_like(G.kp), np.zeros_like(G.rdiag), np.zeros_like(G.tv))
+    gkp, grd, gtv = grads
+    gu = np.zeros(G.N) if gu is None else gu
+    _load().orc_sigma_row_vjp(*G.args(), _p(G.kp), _p(G.rdiag), _p(G.tv), _p(u), n, _p(gret),
+                              _p(gles), _p(gstv), _p(gkp), _p(grd), _p(gtv), _p(gu))
+    return gkp, grd, gtv, gu

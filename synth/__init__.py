@@ -1,0 +1,161 @@
+"""Seeded synthetic inputs shared by the GPU library's tests/benchmark and the CPU oracle.
+
+The arrays are drawn by ``synth.c`` (a counter-based generator: SplitMix64
+finaliser + Box-Muller), so any slice can be regenerated independently and
+both sides of a parity check see bit-identical inputs.  Nothing here computes
+any part of the method (weights, self-energy, integrals).
+
+Layout conventions (complex128, N x N row-major blocks):
+  kp    [nt][ldt][N][N]  kp[a][b] = G^<(t_a,t_b) for a <= b, G^R(t_a,t_b) for a > b
+  rdiag [nt][N][N]       G^R(t_a,t_a) = -i * 1
+  tv    [nt][ntau][N][N] mixed component G^(t_m, tau_j)
+  mat   [ntau][N][N]     Matsubara component G^M(tau_j)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "synth.c")
+_SO = os.path.join(_HERE, "libsynth.so")
+_lib = None
+
+
+def build() -> str:
+    """Compile synth.c into libsynth.so (always recompiles)."""
+    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", _SO + ".tmp", _SRC, "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(_SO + ".tmp", _SO)
+    return _SO
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        lib = ctypes.CDLL(_SO)
+        c = ctypes
+        P = c.c_void_p
+        lib.synth_grid.argtypes = [c.c_uint64, c.c_int32, c.c_double, c.c_double, c.c_int32,
+                                   c.c_int32, P, P]
+        lib.synth_kp_rows.argtypes = [c.c_uint64, c.c_int32, c.c_int32, c.c_int64, P, c.c_double,
+                                      c.c_int32, c.c_int32, P]
+        lib.synth_rdiag.argtypes = [c.c_int32, c.c_int32, P]
+        lib.synth_tv_rows.argtypes = [c.c_uint64, c.c_int32, c.c_int32, P, c.c_double, c.c_int32,
+                                      c.c_int32, P]
+        lib.synth_mat.argtypes = [c.c_uint64, c.c_int32, c.c_int32, P]
+        lib.synth_sigma_row.argtypes = [c.c_uint64, c.c_int32, c.c_int32, c.c_int32, P, c.c_double,
+                                        P, P, P]
+        lib.synth_normal.argtypes = [c.c_uint64, c.c_uint64, c.c_int64, P]
+        for f in (lib.synth_grid, lib.synth_kp_rows, lib.synth_rdiag, lib.synth_tv_rows,
+                  lib.synth_mat, lib.synth_sigma_row, lib.synth_normal):
+            f.restype = None
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray) -> int:
+    assert a.flags.c_contiguous
+    return a.ctypes.data
+
+
+def grid(seed: int, nt: int, hmin: float, hmax: float, omin: int, omax: int):
+    """Non-uniform grid t[0]=0, steps ~ U[hmin,hmax]; per-interval orders ~ U{omin..omax}."""
+    t = np.empty(nt, np.float64)
+    order = np.empty(nt, np.int32)
+    _load().synth_grid(seed, nt, hmin, hmax, omin, omax, _ptr(t), _ptr(order))
+    return t, order
+
+
+def kp(seed: int, N: int, t: np.ndarray, decay: float = 0.3, rows=None, ldt: int | None = None,
+       out: np.ndarray | None = None) -> np.ndarray:
+    """KP two-time array rows [a0,a1) x columns [0,nt) (columns padded to ldt)."""
+    nt = len(t)
+    ldt = nt if ldt is None else ldt
+    a0, a1 = (0, nt) if rows is None else rows
+    if out is None:
+        out = np.zeros((a1 - a0, ldt, N, N), np.complex128)
+    assert out.shape == (a1 - a0, ldt, N, N) and out.dtype == np.complex128
+    _load().synth_kp_rows(seed, N, nt, ldt, _ptr(np.ascontiguousarray(t)), decay, a0, a1, _ptr(out))
+    return out
+
+
+def rdiag(N: int, nt: int) -> np.ndarray:
+    out = np.empty((nt, N, N), np.complex128)
+    _load().synth_rdiag(N, nt, _ptr(out))
+    return out
+
+
+def tv(seed: int, N: int, ntau: int, t: np.ndarray, decay: float = 0.3, rows=None,
+       out: np.ndarray | None = None) -> np.ndarray:
+    nt = len(t)
+    m0, m1 = (0, nt) if rows is None else rows
+    if out is None:
+        out = np.empty((m1 - m0, ntau, N, N), np.complex128)
+    assert out.shape == (m1 - m0, ntau, N, N)
+    if ntau > 0:
+        _load().synth_tv_rows(seed, N, ntau, _ptr(np.ascontiguousarray(t)), decay, m0, m1, _ptr(out))
+    return out
+
+
+def mat(seed: int, N: int, ntau: int) -> np.ndarray:
+    out = np.empty((ntau, N, N), np.complex128)
+    if ntau > 0:
+        _load().synth_mat(seed, N, ntau, _ptr(out))
+    return out
+
+
+def sigma_row(seed: int, N: int, n: int, ntau: int, t: np.ndarray, decay: float = 0.3):
+    """Self-energy row at t_n given as independent random input: (ret[n+1], les[n+1], tv[ntau])."""
+    ret = np.empty((n + 1, N, N), np.complex128)
+    les = np.empty((n + 1, N, N), np.complex128)
+    stv = np.empty((ntau, N, N), np.complex128)
+    _load().synth_sigma_row(seed, N, n, ntau, _ptr(np.ascontiguousarray(t)), decay, _ptr(ret),
+                            _ptr(les), _ptr(stv))
+    return ret, les, stv
+
+
+def normal(seed: int, stream: int, shape) -> np.ndarray:
+    out = np.empty(shape, np.complex128)
+    _load().synth_normal(seed, stream, out.size, _ptr(out))
+    return out
+
+
+@dataclass(frozen=True)
+class Workload:
+    """Sizes of one synthetic workload (paper-shaped, see the input recipe)."""
+    name: str
+    N: int
+    nt: int
+    ntau: int
+    beta: float
+    hmin: float
+    hmax: float
+    omin: int
+    omax: int
+    tau_order: int
+    U: float
+    seed: int
+
+    @property
+    def n(self) -> int:
+        return self.nt - 1
+
+
+# The parity-size case, the headline size, and the differentiation size.
+PARITY_SMALL = Workload("N2_nt64_ntau64", 2, 64, 64, 10.0, 0.02, 0.08, 5, 5, 5, 1.0, 1000)
+HEADLINE = Workload("N16_nt2048_ntau512", 16, 2048, 512, 20.0, 0.005, 0.05, 3, 6, 5, 1.0, 1001)
+DIFFERENTIATION = Workload("N8_nt1024_ntau256", 8, 1024, 256, 10.0, 0.005, 0.05, 3, 6, 5, 2.0, 1003)
+
+
+def green(w: Workload, decay: float = 0.3, ldt: int | None = None):
+    """Full random Green's function of a workload: dict with t, order, kp, rdiag, tv, mat."""
+    t, order = grid(w.seed, w.nt, w.hmin, w.hmax, w.omin, w.omax)
+    return dict(t=t, order=order, kp=kp(w.seed, w.N, t, decay, ldt=ldt), rdiag=rdiag(w.N, w.nt),
+                tv=tv(w.seed, w.N, w.ntau, t, decay), mat=mat(w.seed, w.N, w.ntau))
