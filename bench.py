@@ -1,0 +1,239 @@
+"""Benchmark of the history-integral hot path on one MI355X.
+
+One step = the whole path over the 16-orbital, 2048-point workload (n_tau = 512):
+  kbe_weights -> kbe_sigma_2b (row n = 2047) -> kbe_collision (all m <= n, all four integrals)
+  -> kbe_collision_vjp (all cotangents) -> kbe_sigma_2b_vjp,
+all through the C ABI of libkbe.so.  Inputs are seeded synthetic arrays (see the input recipe in
+the design doc), resident in HBM before timing starts.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "collision-integral FP64 GFLOP/s + HBM GB/s, N_orb=16 n=2048; adjoint/fwd time"
+HBM_PEAK_GBS = 8000.0
+MFMA_F64_PEAK_TFLOPS = 78.6
+RIDGE = MFMA_F64_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def counts(N, nt, ntau, n):
+    """Algorithmic FLOP and HBM bytes of one forward and one adjoint call at row n, all m.
+    FLOP = 8 per complex multiply-add of the block products the method needs; bytes = each
+    required array block read once and each output block written once."""
+    n1 = n + 1
+    blk_flop = 8.0 * N ** 3
+    blk = 16.0 * N * N
+    fwd_terms = n1 * n1 + n1 * (n1 + 1) / 2 + n1 * ntau + ntau * n1 + ntau * (ntau + 1)
+    fwd_read = (n1 * n1 + n1 + n1 * ntau + ntau + 2 * n1 + ntau) * blk + 8.0 * (n1 * (n1 + 1) / 2 + ntau * ntau)
+    fwd_write = (3 * n1 + ntau) * blk
+    # adjoint: self-energy gradients (same terms as the forward), Green's-function gradients
+    # (the upper triangle gets two terms off the diagonal), Matsubara gradient
+    adj_terms = fwd_terms + (n1 * n1 + n1 * (n1 + 1) / 2 + 2 * n1 * ntau + ntau * (ntau + 1))
+    adj_read = fwd_read + (3 * n1 + ntau) * blk
+    adj_write = (n1 * n1 + n1 + n1 * ntau + ntau + 2 * n1 + ntau) * blk
+    return dict(fwd_flop=fwd_terms * blk_flop, fwd_bytes=fwd_read + fwd_write,
+                adj_flop=adj_terms * blk_flop, adj_bytes=adj_read + adj_write)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kbe_collision.hip", "kbe_dev.h"):
+        h.update(open(os.path.join(ROOT, "paper_2405_08737_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per forward call from the committed rocprofv3 counter summary, or None when
+    the kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_collision_N16_nt2048.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_call")
+
+
+def cpu_baseline(w, host, target_s=15.0):
+    """The oracle, as it stands, on a bounded sample of the same workload: rows m in a
+    contiguous range around the middle (I^R, I^<, I^] for those m), plus J^] for a j-range."""
+    import oracle
+    t, order, kp, rd, tv, mat = host
+    n = w.nt - 1
+    N = w.N
+    G = oracle.Green(kp, rd, tv, mat)
+    W = oracle.Weights.build(t, order, w.beta, w.ntau, w.tau_order)
+    sig = oracle.sigma_row(G, np.full(N, w.U), n)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    blk_flop = 8.0 * N ** 3
+
+    def run(m0, m1):
+        t0 = time.perf_counter()
+        oracle.collision(G, sig, W, n, m0, m1, oracle.F_IR | oracle.F_IL | oracle.F_ITV)
+        dt = time.perf_counter() - t0
+        fl = sum((n + 1) + (m + 1) + w.ntau for m in range(m0, m1)) * blk_flop
+        return dt, fl
+
+    mid = n // 2
+    dt, fl = run(mid, mid + threads)  # calibration
+    rate = fl / max(dt, 1e-9)
+    per_row = ((n + 1) + mid + w.ntau) * blk_flop
+    rows = int(min(n + 1 - mid, max(threads, target_s * rate / per_row)))
+    rows = max(threads, (rows // threads) * threads)
+    m0 = max(0, mid - rows // 2)
+    dt, fl = run(m0, m0 + rows)
+    return {"value": fl / dt / 1e9, "unit": "GFLOP/s", "cores": min(threads, rows), "kind": "oracle",
+            "sample": f"rows m in [{m0},{m0 + rows}) of row n={n}: I^R, I^<, I^] "
+                      f"({fl / 1e9:.1f} GFLOP in {dt:.1f} s); Sigma row by the oracle"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
+              "multi-GPU path.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2405_08737_amd as kbe
+    import synth
+
+    kbe.lib()
+    dev = torch.device("cuda:0")
+    w = synth.HEADLINE
+    N, nt, ntau, n = w.N, w.nt, w.ntau, w.nt - 1
+    log(f"generating {w.name} inputs on the host")
+    t, order = synth.grid(w.seed, nt, w.hmin, w.hmax, w.omin, w.omax)
+    kp_h = synth.kp(w.seed, N, t)
+    rd_h = synth.rdiag(N, nt)
+    tv_h = synth.tv(w.seed, N, ntau, t)
+    mat_h = synth.mat(w.seed, N, ntau)
+    log("copying to HBM")
+    kp = torch.empty(kp_h.shape, dtype=torch.complex128, device=dev)
+    for a0 in range(0, nt, 128):
+        kp[a0:a0 + 128].copy_(torch.from_numpy(kp_h[a0:a0 + 128]))
+    tvd = torch.empty(tv_h.shape, dtype=torch.complex128, device=dev)
+    for a0 in range(0, nt, 256):
+        tvd[a0:a0 + 256].copy_(torch.from_numpy(tv_h[a0:a0 + 256]))
+    G = kbe.Green(kp, torch.from_numpy(rd_h).to(dev), tvd, torch.from_numpy(mat_h).to(dev))
+    gG = kbe.Green(torch.empty_like(kp), torch.empty_like(G.rdiag), torch.empty_like(tvd),
+                   torch.empty_like(G.mat))
+    u = torch.full((N,), w.U, dtype=torch.float64, device=dev)
+    gu = torch.zeros(N, dtype=torch.float64, device=dev)
+    cot = tuple(torch.from_numpy(synth.normal(7, k, (nt if k < 3 else ntau, N, N))).to(dev)
+                for k in range(4))
+    torch.cuda.synchronize()
+
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    phases = []
+
+    def step(record):
+        e = [ev() for _ in range(6)] if record else None
+        if record:
+            e[0].record()
+        W = kbe.weights(t, order, ntau, w.beta, w.tau_order, device=dev)
+        if record:
+            e[1].record()
+        sig = kbe.sigma_2b(G, u, n)
+        if record:
+            e[2].record()
+        kbe.collision(G, sig, W, n)
+        if record:
+            e[3].record()
+        _, gsig = kbe.collision_vjp(G, sig, W, n, 0, n + 1, cot,
+                                    kbe.OUT_ALL | kbe.GRAD_OVERWRITE, gG)
+        if record:
+            e[4].record()
+        gu.zero_()
+        kbe.sigma_2b_vjp(G, u, n, gsig, gG, gu)
+        if record:
+            e[5].record()
+            phases.append(e)
+
+    log(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} steps")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = wall / args.steps * 1e3
+    ph = np.array([[p[i].elapsed_time(p[i + 1]) for i in range(5)] for p in phases])
+    ph_ms = ph.mean(axis=0)  # weights, sigma, collision, collision_vjp, sigma_vjp
+    c = counts(N, nt, ntau, n)
+    fwd_ms = ph_ms[0] + ph_ms[1] + ph_ms[2]
+    adj_ms = ph_ms[3] + ph_ms[4]
+    coll_s = ph_ms[2] / 1e3
+    achieved = c["fwd_flop"] / coll_s / 1e12
+    traffic = measured_traffic()
+    result = {
+        "metric": METRIC,
+        "value": (c["fwd_flop"] + c["adj_flop"]) / (ms_step / 1e3) / 1e9,
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "collision_history_row", "N_orb": N, "nt": nt, "n": n,
+                   "m_range": [0, n + 1], "ntau": ntau, "beta": w.beta,
+                   "steps_dt": [w.hmin, w.hmax], "orders": [w.omin, w.omax],
+                   "tau_order": w.tau_order, "U": w.U, "seed": w.seed,
+                   "inputs": "random KP/tv/mat (N(0,1) x exp(-0.3|t-t'|)), Sigma = second Born"},
+        "forward": {"ms": fwd_ms, "collision_ms": ph_ms[2], "weights_ms": ph_ms[0],
+                    "sigma_ms": ph_ms[1],
+                    "collision_gflops": c["fwd_flop"] / coll_s / 1e9,
+                    "collision_gbps": c["fwd_bytes"] / coll_s / 1e9},
+        "adjoint": {"ms": adj_ms, "collision_vjp_ms": ph_ms[3], "sigma_vjp_ms": ph_ms[4],
+                    "collision_vjp_gflops": c["adj_flop"] / (ph_ms[3] / 1e3) / 1e9,
+                    "collision_vjp_gbps": c["adj_bytes"] / (ph_ms[3] / 1e3) / 1e9},
+        "adjoint_over_forward": adj_ms / fwd_ms,
+        "hbm_gbps": (c["fwd_bytes"] + c["adj_bytes"]) / (ms_step / 1e3) / 1e9,
+        "roofline": {
+            "kernel": "kbe_collision (stream_fused<true> + chunk reduce)",
+            "bound": "mfma" if c["fwd_flop"] / c["fwd_bytes"] > RIDGE else "hbm",
+            "achieved": achieved, "peak": MFMA_F64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / MFMA_F64_PEAK_TFLOPS,
+            "traffic": traffic,
+            "algorithmic_flop": c["fwd_flop"], "algorithmic_bytes": c["fwd_bytes"],
+            "intensity_flop_per_byte": c["fwd_flop"] / c["fwd_bytes"],
+            "hbm_frac": c["fwd_bytes"] / coll_s / 1e9 / HBM_PEAK_GBS},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle on a bounded sample)")
+        del gG, kp, tvd
+        result["cpu_baseline"] = cpu_baseline(w, (t, order, kp_h, rd_h, tv_h, mat_h))
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,264 @@
+/*
+ * kbe.h — C ABI of the MI355X history-integral library (libkbe.so).
+ *
+ * The library evaluates, on one AMD Instinct MI355X (gfx950) in FP64, the
+ * data-parallel hot path of adaptive Kadanoff-Baym propagation as described in
+ * T. Blommel, D. J. Gardner, C. S. Woodward, E. Gull, "Adaptive Time Stepping
+ * for the Two-Time Integro-Differential Kadanoff-Baym Equations",
+ * arXiv:2405.08737:
+ *   - the composite quadrature weights of Sec. "Adaptive History Integration"
+ *     (Eq. weights and the weight-row recursion),
+ *   - the second-Born (GF2) self-energy of Eq. SE for a local interaction,
+ *   - the history integrals of Eq. KBE2 (lesser form) and Eq. KBE3,
+ *   - and the adjoints (vector-Jacobian products) of the last two.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Numbers.  kbe_c128 is complex128: {re, im} doubles, the layout of C99
+ * double complex and of torch.complex128.  N x N blocks are row-major.
+ *
+ * Storage of a Keldysh function (struct kbe_green), all device memory:
+ *   kp    [nt rows][ldt][N][N]  kp[a][b] = G^<(t_a,t_b) for a <= b (upper
+ *                               triangle and diagonal), G^R(t_a,t_b) for a > b.
+ *                               The paper stores one side of the diagonal per
+ *                               component (Sec. "Implementation"); the retarded
+ *                               value below it is G^> - G^< there.
+ *   rdiag [nt][N][N]            G^R(t_a,t_a) (the equal-time retarded value;
+ *                               -i*1 for a physical G).
+ *   tv    [nt][ntau][N][N]      G^](t_m,tau_j), the mixed component.
+ *   mat   [ntau][N][N]          G^M(tau_j); mat[0] = G^M(0+), mat[ntau-1] = G^M(beta-).
+ * Values at other arguments follow from the symmetries of Sec. "Kadanoff Baym
+ * Equations": G^<(t,t') = -G^<(t',t)^dagger, G^>(t,t') = G^R + G^< for t >= t',
+ * G^>(t,t') = -G^>(t',t)^dagger, G^[(tau,t) = G^](t,beta-tau)^dagger.
+ * Every array entry is an independent variable (gradients are not tied across
+ * mirrored entries).
+ *
+ * Imaginary time.  tau_j = j*beta/(ntau-1) (a uniform, symmetric grid, so
+ * beta - tau_j = tau_{ntau-1-j}); ntau = 0 removes the thermal branch
+ * (Eq. KBE3 and the tau integrals are dropped, as the paper allows).
+ *
+ * Self-energy row at t_n (struct kbe_sigma_row), device memory:
+ *   ret [n+1][N][N]  Sigma^R(t_n,t_s), s = 0..n (s = n: the one-sided limit)
+ *   les [n+1][N][N]  Sigma^<(t_n,t_s)
+ *   tv  [ntau][N][N] Sigma^](t_n,tau_j)
+ *
+ * Ownership.  The caller owns every buffer.  The library allocates nothing:
+ * scratch memory is a caller-supplied device workspace whose size the
+ * matching *_workspace() query returns.
+ *
+ * Streams.  `stream` is a hipStream_t (NULL = the default stream).  All device
+ * work is enqueued asynchronously on it; no entry point synchronises the host
+ * except kbe_weights, which reads host arrays before returning.
+ *
+ * Errors.  Every entry point validates its arguments on the host before
+ * enqueuing anything and returns a kbe_status; on an error nothing has been
+ * enqueued and kbe_last_error() (thread-local) describes the problem.  A HIP
+ * launch failure returns KBE_EHIP.  Results are deterministic: no floating-
+ * point atomics are used, so repeated calls give bitwise-identical results.
+ */
+#ifndef KBE_H
+#define KBE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  double re, im;
+} kbe_c128;
+
+typedef enum {
+  KBE_OK = 0,
+  KBE_EINVAL = 1,  /* NULL pointer, bad size, inconsistent shapes, bad grid */
+  KBE_ERANGE = 2,  /* n, m-range or order outside the allowed range */
+  KBE_ENOMEM = 3,  /* workspace smaller than the *_workspace() query */
+  KBE_EHIP = 4,    /* a HIP runtime call or kernel launch failed */
+  KBE_ENOTSUP = 5  /* valid request this build does not support */
+} kbe_status;
+
+#define KBE_NMAX 16 /* largest orbital count N */
+#define KBE_KMAX 20 /* largest quadrature order (nodes per interval) */
+
+/* Output selection for kbe_collision / kbe_collision_vjp. */
+#define KBE_OUT_IR 0x1u  /* retarded integral   I^R(t_n,t_m) */
+#define KBE_OUT_IL 0x2u  /* lesser integral     I^<(t_n,t_m) */
+#define KBE_OUT_ITV 0x4u /* tau integral        I^](t_n,t_m) (mixing term of Eq. KBE2) */
+#define KBE_OUT_JTV 0x8u /* left-mixing RHS     J^](t_n,tau_j) (history terms of Eq. KBE3) */
+#define KBE_OUT_ALL 0xFu
+/* Execution switches. */
+#define KBE_FORCE_GENERIC 0x100u  /* use the vector-ALU kernels even where matrix-core (MFMA)
+                                     kernels exist (N = 16); results agree to rounding */
+#define KBE_GRAD_OVERWRITE 0x200u /* VJP: overwrite the Green's-function gradient blocks the
+                                     forward call reads instead of adding to them */
+
+/* One Keldysh function on the grid (G, or a gradient with the same shape). */
+typedef struct {
+  int32_t N;       /* orbitals, 1..KBE_NMAX */
+  int32_t nt;      /* real-time points stored, >= 1 */
+  int32_t ntau;    /* imaginary-time points: 0 or >= 2 */
+  int64_t ldt;     /* row stride of kp in blocks, >= nt */
+  kbe_c128 *kp;    /* device [nt][ldt][N][N] */
+  kbe_c128 *rdiag; /* device [nt][N][N] */
+  kbe_c128 *tv;    /* device [nt][ntau][N][N] (may be NULL when ntau == 0) */
+  kbe_c128 *mat;   /* device [ntau][N][N]     (may be NULL when ntau == 0) */
+} kbe_green;
+
+typedef struct {
+  kbe_c128 *ret; /* device [n+1][N][N] */
+  kbe_c128 *les; /* device [n+1][N][N] */
+  kbe_c128 *tv;  /* device [ntau][N][N] (may be NULL when ntau == 0) */
+} kbe_sigma_row;
+
+/* Time grid (host memory). */
+typedef struct {
+  int32_t nt;           /* points, >= 1 */
+  const double *t;      /* host [nt]: t[0] = 0 < t[1] < ... (the grid starts at 0, Sec. KBE) */
+  const int32_t *order; /* host [nt]: nodes of the interpolant on interval p (p >= 1),
+                           1..KBE_KMAX; order[0] is ignored */
+  int32_t ntau;         /* 0 or >= 2 */
+  double beta;          /* inverse temperature, > 0 when ntau > 0 */
+  int32_t tau_order;    /* nodes per tau interval, 1..KBE_KMAX (ignored when ntau == 0) */
+} kbe_grid;
+
+/* Quadrature weights (device memory), as produced by kbe_weights. */
+typedef struct {
+  const double *w;        /* [nt][nt]: w[n][s], integral over [0, t_n] */
+  const double *wtau;     /* [ntau]: integral over [0, beta] */
+  const double *wtau_fwd; /* [ntau][ntau]: wtau_fwd[j][l], integral over [0, tau_j] */
+} kbe_wts;
+
+/* ---------------------------------------------------------------------------
+ * kbe_weights — quadrature weights (Sec. "Adaptive History Integration",
+ * Eq. weights and the row recursion that follows it).
+ *
+ * Real time: interval p = [t_{p-1}, t_p] is integrated with the Lagrange
+ * interpolant through its k_p = min(order[p], p+1) most recent nodes
+ * t_{p-k_p+1..p}; the local weights solve the moment equations of Eq. weights
+ * (LU with full pivoting, as in the paper, but written in a Legendre basis on
+ * the window instead of monomials, which keeps order 20 well conditioned),
+ * and row n of w is row n-1 plus the local weights of interval n
+ * (so w[n][s] = 0 for s > n and row 0 is 0).  "order" counts nodes: order 2 is
+ * the trapezoid rule, order k is exact for polynomials of degree < k.
+ * Imaginary time (ntau > 0): wtau_fwd[j] integrates over [0, tau_j] using
+ * min(tau_order, j+1) nodes per interval on windows kept inside [0, tau_j];
+ * wtau[l] = (wtau_fwd[J][l] + wtau_fwd[J][J-l]) / 2 integrates over [0, beta]
+ * and is symmetric (the paper's DLR tau basis is replaced by this rule).
+ *
+ * Arguments: g (host) describes the grid; w [nt][nt], wtau [ntau] and
+ * wtau_fwd [ntau][ntau] are device outputs (the tau ones may be NULL when
+ * ntau == 0); ws is a device workspace of at least kbe_weights_workspace(g)
+ * bytes.  The host arrays may be released when the call returns.
+ * Errors: KBE_EINVAL for NULL pointers, nt < 1, t[0] != 0, t not strictly
+ * increasing, ntau == 1, beta <= 0; KBE_ERANGE for an order outside
+ * 1..KBE_KMAX; KBE_ENOMEM for a short workspace.
+ * ------------------------------------------------------------------------- */
+size_t kbe_weights_workspace(const kbe_grid *g);
+kbe_status kbe_weights(const kbe_grid *g, double *w, double *wtau, double *wtau_fwd, void *ws,
+                       size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * kbe_sigma_2b — second-Born self-energy row at t_n (Eq. SE).
+ *
+ * For a local interaction U_{ijkl} = u_i d_ij d_jk d_kl the exchange tensor is
+ * U^Ex_{jjjj} = u_j and Eq. SE reduces to
+ *   Sigma^<_ij(t,t') = u_i u_j G^<_ij(t,t')^2 G^>_ji(t',t)
+ *   Sigma^>_ij(t,t') = u_i u_j G^>_ij(t,t')^2 G^<_ji(t',t)
+ *   Sigma^]_ij(t,tau) = u_i u_j G^]_ij(t,tau)^2 G^[_ji(tau,t)
+ * evaluated for t = t_n, t' = t_s (s = 0..n) and all tau_j.  Outputs:
+ * out->ret[s] = Sigma^>(t_n,t_s) - Sigma^<(t_n,t_s) (= Sigma^R for s < n, its
+ * one-sided limit at s = n), out->les[s] = Sigma^<(t_n,t_s), out->tv[j].
+ * G values are read through the storage symmetries stated above: row n and
+ * column n of kp, rdiag[n] and tv[n].
+ *
+ * Arguments: G (device arrays); u device [N] (a scalar U fills all entries);
+ * 0 <= n < G->nt; out device arrays (overwritten).
+ * Errors: KBE_EINVAL (NULL, bad shape), KBE_ERANGE (n).
+ * ------------------------------------------------------------------------- */
+kbe_status kbe_sigma_2b(const kbe_green *G, const double *u, int32_t n, const kbe_sigma_row *out,
+                        void *stream);
+
+/* ---------------------------------------------------------------------------
+ * kbe_collision — history integrals at t = t_n for t' = t_m, m in [m0, m1)
+ * (the integrals of Eq. KBE2, lesser form, and of Eq. KBE3):
+ *   IR[m-m0]  = sum_{s=0}^{n} w[n][s] Sigma^R(t_n,t_s) G^<(t_s,t_m)
+ *   IL[m-m0]  = sum_{s=0}^{m} w[m][s] Sigma^<(t_n,t_s) G^R(t_m,t_s)^dagger
+ *               (G^A(s,t') = G^R(t',s)^dagger; s = m uses rdiag[m])
+ *   Itv[m-m0] = -i sum_j wtau[j] Sigma^](t_n,tau_j) G^](t_m,tau_{J-j})^dagger
+ *   Jtv[j]    = sum_{s=0}^{n} w[n][s] Sigma^R(t_n,t_s) G^](t_s,tau_j)
+ *             + sum_l Sigma^](t_n,tau_l) C(l,j),   J = ntau-1,
+ *     C(l,j) = -wtau_fwd[j][l] G^M(beta+tau_l-tau_j)        for l <= j
+ *            + wtau_fwd[J-j][J-l] G^M(tau_l-tau_j)          for l >= j
+ *   (the Matsubara convolution of Eq. KBE3 split at tau_j, where G^M jumps;
+ *   on [0, tau_j] antiperiodicity gives G^M(x) = -G^M(x+beta)).
+ * Selected by flags (KBE_OUT_*); unselected outputs may be NULL and are not
+ * written.  KBE_FORCE_GENERIC selects the vector-ALU kernels.
+ *
+ * Arguments: G; S the self-energy row at t_n; W weights for the same grid;
+ * 0 <= n < G->nt; 0 <= m0 <= m1 <= n+1; outputs IR/IL/Itv device
+ * [m1-m0][N][N], Jtv device [ntau][N][N] (overwritten); ws device workspace of
+ * kbe_collision_workspace(...) bytes.
+ * Errors: KBE_EINVAL, KBE_ERANGE, KBE_ENOMEM as above.
+ * ------------------------------------------------------------------------- */
+size_t kbe_collision_workspace(int32_t N, int32_t nt, int32_t ntau, int32_t n, int32_t m0,
+                               int32_t m1, uint32_t flags);
+kbe_status kbe_collision(const kbe_green *G, const kbe_sigma_row *S, const kbe_wts *W, int32_t n,
+                         int32_t m0, int32_t m1, uint32_t flags, kbe_c128 *IR, kbe_c128 *IL,
+                         kbe_c128 *Itv, kbe_c128 *Jtv, void *ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * kbe_collision_vjp — adjoint of kbe_collision (a project addition to the
+ * paper's method, used for gradients of observables).
+ *
+ * Complex gradients follow PyTorch's convention: for a real loss L and a
+ * complex variable z the gradient is dL/dRe z + i dL/dIm z.  Given the
+ * cotangents gIR, gIL, gItv ([m1-m0][N][N]) and gJtv ([ntau][N][N]) of the
+ * outputs selected by flags, the call
+ *   - overwrites gS (the gradient of the self-energy row: ret and les
+ *     [n+1][N][N], tv [ntau][N][N]), and
+ *   - adds the gradient of the Green's function into gG (kp, rdiag, tv, mat),
+ *     or overwrites the blocks the forward call reads when flags contains
+ *     KBE_GRAD_OVERWRITE (blocks it does not read are left untouched).
+ * Weights are not differentiated (they depend only on the grid).
+ *
+ * Arguments: as kbe_collision; gG must have G's shape; cotangents of
+ * unselected outputs may be NULL.  ws: kbe_collision_vjp_workspace(...) bytes.
+ * Errors: as kbe_collision.
+ * ------------------------------------------------------------------------- */
+size_t kbe_collision_vjp_workspace(int32_t N, int32_t nt, int32_t ntau, int32_t n, int32_t m0,
+                                   int32_t m1, uint32_t flags);
+kbe_status kbe_collision_vjp(const kbe_green *G, const kbe_sigma_row *S, const kbe_wts *W,
+                             int32_t n, int32_t m0, int32_t m1, uint32_t flags,
+                             const kbe_c128 *gIR, const kbe_c128 *gIL, const kbe_c128 *gItv,
+                             const kbe_c128 *gJtv, const kbe_green *gG, const kbe_sigma_row *gS,
+                             void *ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * kbe_sigma_2b_vjp — adjoint of kbe_sigma_2b (project addition).
+ *
+ * Given gS (the cotangent of the row: ret/les [n+1][N][N], tv [ntau][N][N]),
+ * adds the gradient with respect to G into gG (row n and column n of kp,
+ * rdiag[n], tv[n]) and the gradient with respect to the real interaction u
+ * into gu (device [N]).  The self-energy is recomputed from G, not stored.
+ * ws: kbe_sigma_2b_vjp_workspace(...) bytes (a deterministic reduction of gu).
+ * Errors: as kbe_sigma_2b, plus KBE_ENOMEM.
+ * ------------------------------------------------------------------------- */
+size_t kbe_sigma_2b_vjp_workspace(int32_t N, int32_t n, int32_t ntau);
+kbe_status kbe_sigma_2b_vjp(const kbe_green *G, const double *u, int32_t n,
+                            const kbe_sigma_row *gS, const kbe_green *gG, double *gu, void *ws,
+                            size_t ws_bytes, void *stream);
+
+/* Human-readable name of a status code (static string). */
+const char *kbe_status_string(kbe_status s);
+/* Detail of the last error on the calling thread ("" if none). */
+const char *kbe_last_error(void);
+/* Library version, major*10000 + minor*100 + patch. */
+int32_t kbe_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KBE_H */

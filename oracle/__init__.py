@@ -55,7 +55,7 @@ def _load():
         lib.orc_sigma_pair.argtypes = [I32, I32, I32, I64, P, P, P, I32, I32, P, P]
         lib.orc_sigma_row.argtypes = [I32, I32, I32, I64, P, P, P, P, I32, P, P, P]
         lib.orc_collision.argtypes = [I32, I32, I32, I64, P, P, P, P, P, P, P, P, P, P, P, I32, I32,
-                                      I32, I32, P, P, P, P]
+                                      I32, I32, I32, I32, P, P, P, P]
         lib.orc_collision_vjp.argtypes = [I32, I32, I32, I64, P, P, P, P, P, P, P, P, P, P, P, I32,
                                           I32, I32, I32, P, P, P, P, P, P, P, P, P, P, P]
         lib.orc_sigma_row_vjp.argtypes = [I32, I32, I32, I64, P, P, P, P, I32, P, P, P, P, P, P, P]
@@ -170,18 +170,19 @@ class Weights:
 
 
 def collision(G: Green, sig, W: Weights, n: int, m0: int = 0, m1: int | None = None,
-              flags: int = F_ALL):
-    """(IR, IL, Itv, Jtv) for m in [m0, m1) at row n."""
+              flags: int = F_ALL, jrange=None):
+    """(IR, IL, Itv, Jtv) for m in [m0, m1) at row n; Jtv for j in jrange (default all)."""
     m1 = n + 1 if m1 is None else m1
+    j0, j1 = (0, G.ntau) if jrange is None else jrange
     ret, les, stv = (_c(x) for x in sig)
     N, nm = G.N, m1 - m0
     IR = np.zeros((nm, N, N), np.complex128)
     IL = np.zeros((nm, N, N), np.complex128)
     Itv = np.zeros((nm, N, N), np.complex128)
-    Jtv = np.zeros((G.ntau, N, N), np.complex128)
+    Jtv = np.zeros((j1 - j0, N, N), np.complex128)
     _load().orc_collision(*G.args(), _p(G.kp), _p(G.rdiag), _p(G.tv), _p(G.mat), _p(ret), _p(les),
-                          _p(stv), _p(W.w), _p(W.wfull), _p(W.wf), _p(W.wb), n, m0, m1, flags,
-                          _p(IR), _p(IL), _p(Itv), _p(Jtv))
+                          _p(stv), _p(W.w), _p(W.wfull), _p(W.wf), _p(W.wb), n, m0, m1, j0, j1,
+                          flags, _p(IR), _p(IL), _p(Itv), _p(Jtv))
     return IR, IL, Itv, Jtv
 
 

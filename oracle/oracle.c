@@ -340,12 +340,13 @@ static int tau_mirror(int ntau, int j) { return ntau - 1 - j; }
  * The Matsubara convolution is split at tb = tau_j because G^M jumps there:
  * on [0, tau_j] the argument is negative and antiperiodicity gives
  * G^M(tb - tau_j) = -G^M(tb - tau_j + beta); on [tau_j, beta] it is
- * G^M(tb - tau_j) directly.  Each piece is integrated with its own rule. */
+ * G^M(tb - tau_j) directly.  Each piece is integrated with its own rule.
+ * Jtv is computed for j in [j0, j1) (stored from Jtv[0]). */
 void orc_collision(int N, int nt, int ntau, int64_t ldt, const cplx *kp, const cplx *rdiag,
                    const cplx *tv, const cplx *mat, const cplx *ret, const cplx *les,
                    const cplx *stv, const double *w, const double *wfull, const double *wf,
-                   const double *wb, int n, int m0, int m1, int flags, cplx *IR, cplx *IL,
-                   cplx *Itv, cplx *Jtv) {
+                   const double *wb, int n, int m0, int m1, int j0, int j1, int flags, cplx *IR,
+                   cplx *IL, cplx *Itv, cplx *Jtv) {
   green g = {N, nt, ntau, ldt, kp, rdiag, tv, mat};
   int64_t bs = (int64_t)N * N;
 #pragma omp parallel for schedule(dynamic, 1)
@@ -379,8 +380,8 @@ void orc_collision(int N, int nt, int ntau, int64_t ldt, const cplx *kp, const c
   if ((flags & F_JTV) && ntau > 0) {
     int J = ntau - 1;
 #pragma omp parallel for schedule(dynamic, 1)
-    for (int j = 0; j < ntau; ++j) {
-      cplx *o = Jtv + j * bs;
+    for (int j = j0; j < j1; ++j) {
+      cplx *o = Jtv + (j - j0) * bs;
       memset(o, 0, sizeof(cplx) * bs);
       for (int s = 0; s <= n; ++s)
         mm_acc(N, o, w[(int64_t)n * nt + s], ret + s * bs, tv + ((int64_t)s * ntau + j) * bs, 0);

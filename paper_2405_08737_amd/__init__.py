@@ -1,0 +1,305 @@
+"""MI355X-native history integrals for adaptive Kadanoff-Baym propagation (arXiv:2405.08737).
+
+Python binding of ``libkbe.so``: argument marshalling only.  Every step of the path runs in the
+library's HIP kernels, called through its C ABI (``include/kbe.h``); PyTorch provides device
+memory and the current stream.  Importing works without the library; the first call raises
+``RuntimeError`` if ``libkbe.so`` has not been built (``python -m paper_2405_08737_amd.build``).
+
+Arrays are torch tensors on a ROCm device: complex128 for Green's functions and self-energies
+(layout in ``include/kbe.h``), float64 for weights and the interaction.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "libkbe.so")
+
+OUT_IR, OUT_IL, OUT_ITV, OUT_JTV = 0x1, 0x2, 0x4, 0x8
+OUT_ALL = 0xF
+FORCE_GENERIC = 0x100
+GRAD_OVERWRITE = 0x200
+NMAX, KMAX = 16, 20
+
+_lib = None
+
+
+class KBEError(RuntimeError):
+    pass
+
+
+class _Green(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("nt", ctypes.c_int32), ("ntau", ctypes.c_int32),
+                ("ldt", ctypes.c_int64), ("kp", ctypes.c_void_p), ("rdiag", ctypes.c_void_p),
+                ("tv", ctypes.c_void_p), ("mat", ctypes.c_void_p)]
+
+
+class _Row(ctypes.Structure):
+    _fields_ = [("ret", ctypes.c_void_p), ("les", ctypes.c_void_p), ("tv", ctypes.c_void_p)]
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("nt", ctypes.c_int32), ("t", ctypes.c_void_p), ("order", ctypes.c_void_p),
+                ("ntau", ctypes.c_int32), ("beta", ctypes.c_double), ("tau_order", ctypes.c_int32)]
+
+
+class _Wts(ctypes.Structure):
+    _fields_ = [("w", ctypes.c_void_p), ("wtau", ctypes.c_void_p), ("wtau_fwd", ctypes.c_void_p)]
+
+
+EXPORTS = ("kbe_weights_workspace", "kbe_weights", "kbe_sigma_2b", "kbe_collision_workspace",
+           "kbe_collision", "kbe_collision_vjp_workspace", "kbe_collision_vjp",
+           "kbe_sigma_2b_vjp_workspace", "kbe_sigma_2b_vjp", "kbe_status_string",
+           "kbe_last_error", "kbe_version")
+
+
+def lib():
+    """Load libkbe.so (raises RuntimeError if it is missing)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            raise RuntimeError(f"{_SO} is not built: run `python -m paper_2405_08737_amd.build`")
+        L = ctypes.CDLL(_SO)
+        P, I32, I64, SZ, U32 = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t,
+                                ctypes.c_uint32)
+        G, R, GR, W = (ctypes.POINTER(_Green), ctypes.POINTER(_Row), ctypes.POINTER(_Grid),
+                       ctypes.POINTER(_Wts))
+        sig = {
+            "kbe_weights_workspace": (SZ, [GR]),
+            "kbe_weights": (I32, [GR, P, P, P, P, SZ, P]),
+            "kbe_sigma_2b": (I32, [G, P, I32, R, P]),
+            "kbe_collision_workspace": (SZ, [I32, I32, I32, I32, I32, I32, U32]),
+            "kbe_collision": (I32, [G, R, W, I32, I32, I32, U32, P, P, P, P, P, SZ, P]),
+            "kbe_collision_vjp_workspace": (SZ, [I32, I32, I32, I32, I32, I32, U32]),
+            "kbe_collision_vjp": (I32, [G, R, W, I32, I32, I32, U32, P, P, P, P, G, R, P, SZ, P]),
+            "kbe_sigma_2b_vjp_workspace": (SZ, [I32, I32, I32]),
+            "kbe_sigma_2b_vjp": (I32, [G, P, I32, R, G, P, P, SZ, P]),
+            "kbe_status_string": (ctypes.c_char_p, [I32]),
+            "kbe_last_error": (ctypes.c_char_p, []),
+            "kbe_version": (I32, []),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype, f.argtypes = res, args
+        _lib = L
+    return _lib
+
+
+def _check(st: int, what: str):
+    if st != 0:
+        L = lib()
+        raise KBEError(f"{what}: {L.kbe_status_string(st).decode()}: {L.kbe_last_error().decode()}")
+
+
+def _ptr(x: Optional[torch.Tensor]):
+    if x is None:
+        return None
+    assert x.is_contiguous(), "tensors passed to libkbe must be contiguous"
+    return x.data_ptr()
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _ws(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+@dataclass
+class Green:
+    """A Keldysh function in KP storage (device tensors, complex128)."""
+    kp: torch.Tensor                 # [nt, ldt, N, N]
+    rdiag: torch.Tensor              # [nt, N, N]
+    tv: Optional[torch.Tensor] = None   # [nt, ntau, N, N]
+    mat: Optional[torch.Tensor] = None  # [ntau, N, N]
+
+    @property
+    def N(self):
+        return self.kp.shape[-1]
+
+    @property
+    def nt(self):
+        return self.rdiag.shape[0]
+
+    @property
+    def ntau(self):
+        return 0 if self.tv is None else self.tv.shape[1]
+
+    @property
+    def device(self):
+        return self.kp.device
+
+    def c(self) -> _Green:
+        return _Green(self.N, self.nt, self.ntau, self.kp.shape[1], _ptr(self.kp),
+                      _ptr(self.rdiag), _ptr(self.tv), _ptr(self.mat))
+
+    def zeros_like(self) -> "Green":
+        z = lambda x: None if x is None else torch.zeros_like(x)
+        return Green(z(self.kp), z(self.rdiag), z(self.tv), z(self.mat))
+
+
+@dataclass
+class Weights:
+    w: torch.Tensor                      # [nt, nt] float64
+    wtau: Optional[torch.Tensor] = None  # [ntau]
+    wtau_fwd: Optional[torch.Tensor] = None  # [ntau, ntau]
+
+    def c(self) -> _Wts:
+        return _Wts(_ptr(self.w), _ptr(self.wtau), _ptr(self.wtau_fwd))
+
+
+def _row(ret, les, tv) -> _Row:
+    return _Row(_ptr(ret), _ptr(les), _ptr(tv))
+
+
+def weights(t, order, ntau: int = 0, beta: float = 0.0, tau_order: int = 5,
+            device="cuda") -> Weights:
+    """kbe_weights: composite real-time weights w[n][s] and the tau weights."""
+    import numpy as np
+    t = np.ascontiguousarray(t, dtype=np.float64)
+    order = np.ascontiguousarray(order, dtype=np.int32)
+    nt = len(t)
+    g = _Grid(nt, t.ctypes.data, order.ctypes.data, ntau, float(beta), int(tau_order))
+    w = torch.empty((nt, nt), dtype=torch.float64, device=device)
+    wtau = torch.empty(ntau, dtype=torch.float64, device=device) if ntau > 0 else None
+    wf = torch.empty((ntau, ntau), dtype=torch.float64, device=device) if ntau > 0 else None
+    L = lib()
+    nb = L.kbe_weights_workspace(ctypes.byref(g))
+    ws = _ws(nb, device)
+    _check(L.kbe_weights(ctypes.byref(g), _ptr(w), _ptr(wtau), _ptr(wf), _ptr(ws), nb,
+                         _stream(w.device)), "kbe_weights")
+    return Weights(w, wtau, wf)
+
+
+def sigma_2b(G: Green, u: torch.Tensor, n: int):
+    """kbe_sigma_2b: (ret[n+1], les[n+1], tv[ntau]) second-Born row at t_n."""
+    N, dev = G.N, G.device
+    ret = torch.empty((n + 1, N, N), dtype=torch.complex128, device=dev)
+    les = torch.empty_like(ret)
+    stv = torch.empty((G.ntau, N, N), dtype=torch.complex128, device=dev) if G.ntau else None
+    row = _row(ret, les, stv)
+    _check(lib().kbe_sigma_2b(ctypes.byref(G.c()), _ptr(u), n, ctypes.byref(row), _stream(dev)),
+           "kbe_sigma_2b")
+    return ret, les, stv
+
+
+def collision(G: Green, sig, W: Weights, n: int, m0: int = 0, m1: Optional[int] = None,
+              flags: int = OUT_ALL):
+    """kbe_collision: (IR, IL, Itv, Jtv); unselected outputs are None."""
+    m1 = n + 1 if m1 is None else m1
+    N, dev, M = G.N, G.device, m1 - m0
+    mk = lambda k: torch.empty((k, N, N), dtype=torch.complex128, device=dev)
+    IR = mk(M) if flags & OUT_IR else None
+    IL = mk(M) if flags & OUT_IL else None
+    Itv = mk(M) if flags & OUT_ITV else None
+    Jtv = mk(G.ntau) if (flags & OUT_JTV) and G.ntau else None
+    L = lib()
+    nb = L.kbe_collision_workspace(N, G.nt, G.ntau, n, m0, m1, flags)
+    ws = _ws(nb, dev)
+    row = _row(*sig)
+    _check(L.kbe_collision(ctypes.byref(G.c()), ctypes.byref(row), ctypes.byref(W.c()), n, m0, m1,
+                           flags, _ptr(IR), _ptr(IL), _ptr(Itv), _ptr(Jtv), _ptr(ws), nb,
+                           _stream(dev)), "kbe_collision")
+    return IR, IL, Itv, Jtv
+
+
+def collision_vjp(G: Green, sig, W: Weights, n: int, m0: int, m1: int, cot, flags: int = OUT_ALL,
+                  gG: Optional[Green] = None):
+    """kbe_collision_vjp: returns (gG, (gret, gles, gstv)); gG is accumulated into (or created
+    zero) unless flags has GRAD_OVERWRITE."""
+    N, dev = G.N, G.device
+    if gG is None:
+        gG = G.zeros_like()
+    gret = torch.empty((n + 1, N, N), dtype=torch.complex128, device=dev)
+    gles = torch.empty_like(gret)
+    gstv = torch.empty((G.ntau, N, N), dtype=torch.complex128, device=dev) if G.ntau else None
+    gIR, gIL, gItv, gJ = cot
+    L = lib()
+    nb = L.kbe_collision_vjp_workspace(N, G.nt, G.ntau, n, m0, m1, flags)
+    ws = _ws(nb, dev)
+    _check(L.kbe_collision_vjp(ctypes.byref(G.c()), ctypes.byref(_row(*sig)), ctypes.byref(W.c()),
+                               n, m0, m1, flags, _ptr(gIR), _ptr(gIL), _ptr(gItv), _ptr(gJ),
+                               ctypes.byref(gG.c()), ctypes.byref(_row(gret, gles, gstv)),
+                               _ptr(ws), nb, _stream(dev)), "kbe_collision_vjp")
+    return gG, (gret, gles, gstv)
+
+
+def sigma_2b_vjp(G: Green, u: torch.Tensor, n: int, gsig, gG: Optional[Green] = None,
+                 gu: Optional[torch.Tensor] = None):
+    """kbe_sigma_2b_vjp: accumulates into gG and gu (created zero when None)."""
+    dev = G.device
+    if gG is None:
+        gG = G.zeros_like()
+    if gu is None:
+        gu = torch.zeros(G.N, dtype=torch.float64, device=dev)
+    L = lib()
+    nb = L.kbe_sigma_2b_vjp_workspace(G.N, n, G.ntau)
+    ws = _ws(nb, dev)
+    _check(L.kbe_sigma_2b_vjp(ctypes.byref(G.c()), _ptr(u), n, ctypes.byref(_row(*gsig)),
+                              ctypes.byref(gG.c()), _ptr(gu), _ptr(ws), nb, _stream(dev)),
+           "kbe_sigma_2b_vjp")
+    return gG, gu
+
+
+# ------------------------------------------------------------------------------------------
+# torch.autograd wrappers: forward and backward both run in libkbe's kernels.
+# ------------------------------------------------------------------------------------------
+class KBESigma2B(torch.autograd.Function):
+    """(kp, rdiag, tv, u) -> (ret, les, stv) at row n; backward via kbe_sigma_2b_vjp (the row is
+    recomputed from G, never stored)."""
+
+    @staticmethod
+    def forward(ctx, kp, rdiag, tv, mat, u, n: int):
+        G = Green(kp, rdiag, tv, mat)
+        ret, les, stv = sigma_2b(G, u, n)
+        ctx.save_for_backward(kp, rdiag, tv, mat, u)
+        ctx.n = n
+        return ret, les, stv
+
+    @staticmethod
+    def backward(ctx, gret, gles, gstv):
+        kp, rdiag, tv, mat, u = ctx.saved_tensors
+        G = Green(kp, rdiag, tv, mat)
+        z = lambda g, like: torch.zeros_like(like) if g is None else g.contiguous()
+        gsig = (z(gret, kp[0, :ctx.n + 1]), z(gles, kp[0, :ctx.n + 1]),
+                None if tv is None else z(gstv, tv[0]))
+        gG, gu = sigma_2b_vjp(G, u, ctx.n, gsig)
+        return gG.kp, gG.rdiag, gG.tv, gG.mat, gu, None
+
+
+class KBECollision(torch.autograd.Function):
+    """(kp, rdiag, tv, mat, ret, les, stv) -> (IR, IL, Itv, Jtv); backward via kbe_collision_vjp."""
+
+    @staticmethod
+    def forward(ctx, kp, rdiag, tv, mat, ret, les, stv, W: Weights, n: int, m0: int, m1: int):
+        G = Green(kp, rdiag, tv, mat)
+        flags = OUT_ALL if tv is not None else (OUT_IR | OUT_IL)
+        IR, IL, Itv, Jtv = collision(G, (ret, les, stv), W, n, m0, m1, flags)
+        ctx.save_for_backward(kp, rdiag, tv, mat, ret, les, stv)
+        ctx.W, ctx.n, ctx.m0, ctx.m1, ctx.flags = W, n, m0, m1, flags
+        outs = [IR, IL] + ([Itv, Jtv] if tv is not None else [])
+        return tuple(outs)
+
+    @staticmethod
+    def backward(ctx, *grads):
+        kp, rdiag, tv, mat, ret, les, stv = ctx.saved_tensors
+        G = Green(kp, rdiag, tv, mat)
+        M = ctx.m1 - ctx.m0
+        N = kp.shape[-1]
+        zeros = lambda k: torch.zeros((k, N, N), dtype=torch.complex128, device=kp.device)
+        g = [gr.contiguous() if gr is not None else None for gr in grads]
+        gIR = g[0] if g[0] is not None else zeros(M)
+        gIL = g[1] if g[1] is not None else zeros(M)
+        gItv = gJ = None
+        if tv is not None:
+            gItv = g[2] if g[2] is not None else zeros(M)
+            gJ = g[3] if g[3] is not None else zeros(G.ntau)
+        gG, (gret, gles, gstv) = collision_vjp(G, (ret, les, stv), ctx.W, ctx.n, ctx.m0, ctx.m1,
+                                               (gIR, gIL, gItv, gJ), ctx.flags)
+        return gG.kp, gG.rdiag, gG.tv, gG.mat, gret, gles, gstv, None, None, None, None

@@ -1,0 +1,248 @@
+// C ABI of libkbe: argument validation (before anything is enqueued), dispatch to the kernel
+// files, status codes and the thread-local error text.  See include/kbe.h for the contract.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+
+#include "kbe_dev.h"
+#include "kbe_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+kbe_status fail(kbe_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+kbe_status ok() {
+  g_err.clear();
+  return KBE_OK;
+}
+
+kbe_status hip_status(hipError_t e, const char *what) {
+  if (e == hipSuccess) return ok();
+  return fail(KBE_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+kbe_status check_green(const kbe_green *G, const char *name) {
+  if (!G) return fail(KBE_EINVAL, "%s is NULL", name);
+  if (G->N < 1 || G->N > KBE_NMAX) return fail(KBE_EINVAL, "%s->N = %d outside 1..%d", name, G->N, KBE_NMAX);
+  if (G->nt < 1) return fail(KBE_EINVAL, "%s->nt = %d < 1", name, G->nt);
+  if (G->ntau < 0 || G->ntau == 1) return fail(KBE_EINVAL, "%s->ntau = %d (must be 0 or >= 2)", name, G->ntau);
+  if (G->ldt < G->nt) return fail(KBE_EINVAL, "%s->ldt = %lld < nt = %d", name, (long long)G->ldt, G->nt);
+  if (!G->kp || !G->rdiag) return fail(KBE_EINVAL, "%s->kp or %s->rdiag is NULL", name, name);
+  if (G->ntau > 0 && (!G->tv || !G->mat)) return fail(KBE_EINVAL, "%s->tv or %s->mat is NULL with ntau > 0", name, name);
+  return KBE_OK;
+}
+
+kbe_status check_same_shape(const kbe_green *G, const kbe_green *H, const char *name) {
+  kbe_status s = check_green(H, name);
+  if (s != KBE_OK) return s;
+  if (H->N != G->N || H->nt != G->nt || H->ntau != G->ntau || H->ldt != G->ldt)
+    return fail(KBE_EINVAL, "%s does not have the shape of G", name);
+  return KBE_OK;
+}
+
+kbe_status check_common(const kbe_green *G, const kbe_sigma_row *S, const kbe_wts *W, int n,
+                        int m0, int m1, unsigned flags) {
+  kbe_status s = check_green(G, "G");
+  if (s != KBE_OK) return s;
+  if (flags & ~(KBE_OUT_ALL | KBE_FORCE_GENERIC | KBE_GRAD_OVERWRITE))
+    return fail(KBE_EINVAL, "unknown flag bits 0x%x", flags);
+  if (n < 0 || n >= G->nt) return fail(KBE_ERANGE, "n = %d outside [0, nt = %d)", n, G->nt);
+  if (m0 < 0 || m0 > m1 || m1 > n + 1)
+    return fail(KBE_ERANGE, "m-range [%d, %d) not inside [0, n+1 = %d]", m0, m1, n + 1);
+  if (!S) return fail(KBE_EINVAL, "S is NULL");
+  if (!W) return fail(KBE_EINVAL, "W is NULL");
+  const bool th = G->ntau > 0;
+  if ((flags & (KBE_OUT_IR | KBE_OUT_JTV)) && !S->ret) return fail(KBE_EINVAL, "S->ret is NULL");
+  if ((flags & KBE_OUT_IL) && !S->les) return fail(KBE_EINVAL, "S->les is NULL");
+  if (th && (flags & (KBE_OUT_ITV | KBE_OUT_JTV)) && !S->tv) return fail(KBE_EINVAL, "S->tv is NULL");
+  if ((flags & (KBE_OUT_IR | KBE_OUT_IL | KBE_OUT_JTV)) && !W->w) return fail(KBE_EINVAL, "W->w is NULL");
+  if (th && (flags & KBE_OUT_ITV) && !W->wtau) return fail(KBE_EINVAL, "W->wtau is NULL");
+  if (th && (flags & KBE_OUT_JTV) && !W->wtau_fwd) return fail(KBE_EINVAL, "W->wtau_fwd is NULL");
+  return KBE_OK;
+}
+
+kbe::Params make_params(const kbe_green *G, const kbe_sigma_row *S, const kbe_wts *W, int n,
+                        int m0, int m1, unsigned flags) {
+  kbe::Params p{};
+  p.N = G->N;
+  p.nt = G->nt;
+  p.ntau = G->ntau;
+  p.J = G->ntau - 1;
+  p.n = n;
+  p.m0 = m0;
+  p.m1 = m1;
+  p.ldt = G->ldt;
+  p.kp = G->kp;
+  p.rdiag = G->rdiag;
+  p.tv = G->tv;
+  p.mat = G->mat;
+  p.ret = S->ret;
+  p.les = S->les;
+  p.stv = S->tv;
+  p.w = W->w;
+  p.wtau = W->wtau;
+  p.wf = W->wtau_fwd;
+  p.fIR = (flags & KBE_OUT_IR) != 0;
+  p.fIL = (flags & KBE_OUT_IL) != 0;
+  p.fITV = (flags & KBE_OUT_ITV) && G->ntau > 0;
+  p.fJTV = (flags & KBE_OUT_JTV) && G->ntau > 0;
+  p.overwrite = (flags & KBE_GRAD_OVERWRITE) != 0;
+  return p;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *kbe_status_string(kbe_status s) {
+  switch (s) {
+    case KBE_OK: return "KBE_OK";
+    case KBE_EINVAL: return "KBE_EINVAL: invalid argument";
+    case KBE_ERANGE: return "KBE_ERANGE: index or order out of range";
+    case KBE_ENOMEM: return "KBE_ENOMEM: workspace too small";
+    case KBE_EHIP: return "KBE_EHIP: HIP runtime error";
+    case KBE_ENOTSUP: return "KBE_ENOTSUP: not supported";
+  }
+  return "unknown kbe_status";
+}
+
+const char *kbe_last_error(void) { return g_err.c_str(); }
+
+int32_t kbe_version(void) { return 10000; }
+
+size_t kbe_weights_workspace(const kbe_grid *g) {
+  if (!g || g->nt < 1) return 0;
+  return kbe::weights_ws_bytes(g->nt, g->ntau > 0 ? g->ntau : 0);
+}
+
+kbe_status kbe_weights(const kbe_grid *g, double *w, double *wtau, double *wtau_fwd, void *ws,
+                       size_t ws_bytes, void *stream) {
+  if (!g) return fail(KBE_EINVAL, "grid is NULL");
+  if (g->nt < 1) return fail(KBE_EINVAL, "nt = %d < 1", g->nt);
+  if (!g->t || !g->order) return fail(KBE_EINVAL, "grid t or order is NULL");
+  if (!w) return fail(KBE_EINVAL, "w is NULL");
+  if (g->t[0] != 0.0) return fail(KBE_EINVAL, "t[0] = %g, the grid must start at 0", g->t[0]);
+  for (int p = 1; p < g->nt; ++p) {
+    if (!(g->t[p] > g->t[p - 1]) || !std::isfinite(g->t[p]))
+      return fail(KBE_EINVAL, "t is not strictly increasing at p = %d", p);
+    if (g->order[p] < 1 || g->order[p] > KBE_KMAX)
+      return fail(KBE_ERANGE, "order[%d] = %d outside 1..%d", p, g->order[p], KBE_KMAX);
+  }
+  if (g->ntau < 0 || g->ntau == 1) return fail(KBE_EINVAL, "ntau = %d (must be 0 or >= 2)", g->ntau);
+  if (g->ntau > 0) {
+    if (!(g->beta > 0.0) || !std::isfinite(g->beta)) return fail(KBE_EINVAL, "beta = %g must be > 0", g->beta);
+    if (g->tau_order < 1 || g->tau_order > KBE_KMAX)
+      return fail(KBE_ERANGE, "tau_order = %d outside 1..%d", g->tau_order, KBE_KMAX);
+    if (!wtau || !wtau_fwd) return fail(KBE_EINVAL, "wtau or wtau_fwd is NULL with ntau > 0");
+  }
+  const size_t need = kbe_weights_workspace(g);
+  if (!ws || ws_bytes < need) return fail(KBE_ENOMEM, "workspace %zu bytes < %zu", ws_bytes, need);
+  hipError_t e = kbe::launch_weights(g, w, wtau, wtau_fwd, ws, (hipStream_t)stream);
+  return hip_status(e, "kbe_weights");
+}
+
+kbe_status kbe_sigma_2b(const kbe_green *G, const double *u, int32_t n, const kbe_sigma_row *out,
+                        void *stream) {
+  kbe_status s = check_green(G, "G");
+  if (s != KBE_OK) return s;
+  if (n < 0 || n >= G->nt) return fail(KBE_ERANGE, "n = %d outside [0, nt = %d)", n, G->nt);
+  if (!u) return fail(KBE_EINVAL, "u is NULL");
+  if (!out || !out->ret || !out->les) return fail(KBE_EINVAL, "output row is NULL");
+  if (G->ntau > 0 && !out->tv) return fail(KBE_EINVAL, "out->tv is NULL with ntau > 0");
+  return hip_status(kbe::launch_sigma_row(G, u, n, out, (hipStream_t)stream), "kbe_sigma_2b");
+}
+
+size_t kbe_sigma_2b_vjp_workspace(int32_t N, int32_t n, int32_t ntau) {
+  if (N < 1 || n < 0 || ntau < 0) return 0;
+  return kbe::sigma_vjp_ws_bytes(N, n, ntau);
+}
+
+kbe_status kbe_sigma_2b_vjp(const kbe_green *G, const double *u, int32_t n,
+                            const kbe_sigma_row *gS, const kbe_green *gG, double *gu, void *ws,
+                            size_t ws_bytes, void *stream) {
+  kbe_status s = check_green(G, "G");
+  if (s != KBE_OK) return s;
+  if ((s = check_same_shape(G, gG, "gG")) != KBE_OK) return s;
+  if (n < 0 || n >= G->nt) return fail(KBE_ERANGE, "n = %d outside [0, nt = %d)", n, G->nt);
+  if (!u || !gu) return fail(KBE_EINVAL, "u or gu is NULL");
+  if (!gS || !gS->ret || !gS->les) return fail(KBE_EINVAL, "gS row is NULL");
+  if (G->ntau > 0 && !gS->tv) return fail(KBE_EINVAL, "gS->tv is NULL with ntau > 0");
+  const size_t need = kbe_sigma_2b_vjp_workspace(G->N, n, G->ntau);
+  if (!ws || ws_bytes < need) return fail(KBE_ENOMEM, "workspace %zu bytes < %zu", ws_bytes, need);
+  return hip_status(kbe::launch_sigma_row_vjp(G, u, n, gS, gG, gu, ws, (hipStream_t)stream),
+                    "kbe_sigma_2b_vjp");
+}
+
+size_t kbe_collision_workspace(int32_t N, int32_t nt, int32_t ntau, int32_t n, int32_t m0,
+                               int32_t m1, uint32_t flags) {
+  if (N < 1 || N > KBE_NMAX || n < 0 || m0 < 0 || m1 < m0 || ntau < 0) return 0;
+  return kbe::collision_ws_bytes(N, nt, ntau, n, m0, m1, flags);
+}
+
+kbe_status kbe_collision(const kbe_green *G, const kbe_sigma_row *S, const kbe_wts *W, int32_t n,
+                         int32_t m0, int32_t m1, uint32_t flags, kbe_c128 *IR, kbe_c128 *IL,
+                         kbe_c128 *Itv, kbe_c128 *Jtv, void *ws, size_t ws_bytes, void *stream) {
+  kbe_status s = check_common(G, S, W, n, m0, m1, flags);
+  if (s != KBE_OK) return s;
+  const bool M = m1 > m0;
+  if ((flags & KBE_OUT_IR) && M && !IR) return fail(KBE_EINVAL, "IR is NULL");
+  if ((flags & KBE_OUT_IL) && M && !IL) return fail(KBE_EINVAL, "IL is NULL");
+  if ((flags & KBE_OUT_ITV) && M && !Itv) return fail(KBE_EINVAL, "Itv is NULL");
+  if ((flags & KBE_OUT_JTV) && G->ntau > 0 && !Jtv) return fail(KBE_EINVAL, "Jtv is NULL");
+  const size_t need = kbe_collision_workspace(G->N, G->nt, G->ntau, n, m0, m1, flags);
+  if (need > 0 && (!ws || ws_bytes < need))
+    return fail(KBE_ENOMEM, "workspace %zu bytes < %zu", ws_bytes, need);
+  kbe::Params p = make_params(G, S, W, n, m0, m1, flags);
+  return hip_status(kbe::launch_collision(p, flags, IR, IL, Itv, Jtv, ws, (hipStream_t)stream),
+                    "kbe_collision");
+}
+
+size_t kbe_collision_vjp_workspace(int32_t N, int32_t nt, int32_t ntau, int32_t n, int32_t m0,
+                                   int32_t m1, uint32_t flags) {
+  if (N < 1 || N > KBE_NMAX || n < 0 || m0 < 0 || m1 < m0 || ntau < 0) return 0;
+  return kbe::collision_vjp_ws_bytes(N, nt, ntau, n, m0, m1, flags);
+}
+
+kbe_status kbe_collision_vjp(const kbe_green *G, const kbe_sigma_row *S, const kbe_wts *W,
+                             int32_t n, int32_t m0, int32_t m1, uint32_t flags,
+                             const kbe_c128 *gIR, const kbe_c128 *gIL, const kbe_c128 *gItv,
+                             const kbe_c128 *gJtv, const kbe_green *gG, const kbe_sigma_row *gS,
+                             void *ws, size_t ws_bytes, void *stream) {
+  kbe_status s = check_common(G, S, W, n, m0, m1, flags);
+  if (s != KBE_OK) return s;
+  if ((s = check_same_shape(G, gG, "gG")) != KBE_OK) return s;
+  const bool M = m1 > m0, th = G->ntau > 0;
+  if ((flags & KBE_OUT_IR) && M && !gIR) return fail(KBE_EINVAL, "gIR is NULL");
+  if ((flags & KBE_OUT_IL) && M && !gIL) return fail(KBE_EINVAL, "gIL is NULL");
+  if ((flags & KBE_OUT_ITV) && M && th && !gItv) return fail(KBE_EINVAL, "gItv is NULL");
+  if ((flags & KBE_OUT_JTV) && th && !gJtv) return fail(KBE_EINVAL, "gJtv is NULL");
+  if ((flags & KBE_OUT_IR) && !S->ret) return fail(KBE_EINVAL, "S->ret is NULL");
+  if (!gS || !gS->ret || !gS->les) return fail(KBE_EINVAL, "gS row is NULL");
+  if (th && !gS->tv) return fail(KBE_EINVAL, "gS->tv is NULL with ntau > 0");
+  const size_t need = kbe_collision_vjp_workspace(G->N, G->nt, G->ntau, n, m0, m1, flags);
+  if (need > 0 && (!ws || ws_bytes < need))
+    return fail(KBE_ENOMEM, "workspace %zu bytes < %zu", ws_bytes, need);
+  kbe::Params p = make_params(G, S, W, n, m0, m1, flags);
+  p.gIR = gIR;
+  p.gIL = gIL;
+  p.gItv = gItv;
+  p.gJ = gJtv;
+  p.gkp = gG->kp;
+  p.grdiag = gG->rdiag;
+  p.gtv = gG->tv;
+  return hip_status(kbe::launch_collision_vjp(p, flags, gG->mat, gS, ws, (hipStream_t)stream),
+                    "kbe_collision_vjp");
+}
+
+}  // extern "C"

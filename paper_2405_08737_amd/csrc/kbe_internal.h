@@ -1,0 +1,33 @@
+// Internal host-side interface between the C ABI layer and the kernel files of libkbe.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kbe.h"
+
+namespace kbe {
+
+struct Params;
+
+// Weights (kbe_weights.hip).
+size_t weights_ws_bytes(int nt, int ntau);
+hipError_t launch_weights(const kbe_grid *g, double *w, double *wtau, double *wf, void *ws,
+                          hipStream_t st);
+
+// Self-energy and its adjoint (kbe_sigma.hip).
+hipError_t launch_sigma_row(const kbe_green *G, const double *u, int n, const kbe_sigma_row *out,
+                            hipStream_t st);
+size_t sigma_vjp_ws_bytes(int N, int n, int ntau);
+hipError_t launch_sigma_row_vjp(const kbe_green *G, const double *u, int n,
+                                const kbe_sigma_row *gS, const kbe_green *gG, double *gu,
+                                void *ws, hipStream_t st);
+
+// History integrals and their adjoint (kbe_collision.hip).
+size_t collision_ws_bytes(int N, int nt, int ntau, int n, int m0, int m1, unsigned flags);
+hipError_t launch_collision(const Params &p, unsigned flags, kbe_c128 *IR, kbe_c128 *IL,
+                            kbe_c128 *Itv, kbe_c128 *Jtv, void *ws, hipStream_t st);
+size_t collision_vjp_ws_bytes(int N, int nt, int ntau, int n, int m0, int m1, unsigned flags);
+hipError_t launch_collision_vjp(const Params &p, unsigned flags, kbe_c128 *gmat,
+                                const kbe_sigma_row *gS, void *ws, hipStream_t st);
+
+}  // namespace kbe

@@ -1,0 +1,204 @@
+// Second-Born self-energy row (Eq. SE of arXiv:2405.08737, local interaction) and its adjoint.
+//
+// For U_{ijkl} = u_i d_ij d_jk d_kl, Eq. SE reduces elementwise to
+//   Sigma^<_ij(t,t') = u_i u_j G^<_ij(t,t')^2 G^>_ji(t',t)
+//   Sigma^>_ij(t,t') = u_i u_j G^>_ij(t,t')^2 G^<_ji(t',t)
+//   Sigma^]_ij(t,tau) = u_i u_j G^]_ij(t,tau)^2 conj(G^]_ij(t,beta-tau))
+// One thread per element of the row (s, i, j) or (tau_l, i, j).  With a = kp[s][n]_ji
+// (= G^<(t_s,t_n)_ji) and, for s < n, R = kp[n][s]_ij (= G^R(t_n,t_s)_ij):
+//   G^<(t_n,t_s)_ij = -conj(a),  G^>(t_n,t_s)_ij = g = R - conj(a),  G^>(t_s,t_n)_ji = -conj(g).
+// At s = n the stored diagonal block D = kp[n][n] and r = rdiag[n] are read directly:
+//   G^<_ij = D_ij, G^>_ij = r_ij + D_ij, G^<_ji = D_ji, G^>_ji = r_ji + D_ji.
+#include "kbe_dev.h"
+#include "kbe_internal.h"
+
+namespace kbe {
+
+struct SigArgs {
+  int N, ntau, J, n;
+  int64_t ldt;
+  const kbe_c128 *kp, *rdiag, *tv;
+  const double *u;
+};
+
+__global__ void __launch_bounds__(256) sigma_row_kernel(SigArgs a, kbe_c128 *ret, kbe_c128 *les,
+                                                        kbe_c128 *stv) {
+  const int64_t E = (int64_t)a.N * a.N;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nrt = (int64_t)(a.n + 1) * E;
+  if (idx < nrt) {
+    const int s = (int)(idx / E), e = (int)(idx % E), i = e / a.N, j = e % a.N;
+    const double U = a.u[i] * a.u[j];
+    const cd z1 = ld(a.kp + ((int64_t)s * a.ldt + a.n) * E + j * a.N + i);  // G^<(s,n)_ji
+    cd sl, sg;
+    if (s < a.n) {
+      const cd R = ld(a.kp + ((int64_t)a.n * a.ldt + s) * E + e);
+      const cd L = -cj(z1);
+      const cd g = R + L;
+      sl = U * (L * L * (-cj(g)));
+      sg = U * (g * g * z1);
+    } else {
+      const kbe_c128 *D = a.kp + ((int64_t)a.n * a.ldt + a.n) * E;
+      const kbe_c128 *r = a.rdiag + (int64_t)a.n * E;
+      const cd Dij = ld(D + e), rij = ld(r + e), rji = ld(r + j * a.N + i);
+      const cd gij = rij + Dij, gji = rji + z1;
+      sl = U * (Dij * Dij * gji);
+      sg = U * (gij * gij * z1);
+    }
+    st(les + s * E + e, sl);
+    st(ret + s * E + e, sg - sl);
+  } else if (idx < nrt + (int64_t)a.ntau * E) {
+    const int64_t k = idx - nrt;
+    const int l = (int)(k / E), e = (int)(k % E), i = e / a.N, j = e % a.N;
+    const double U = a.u[i] * a.u[j];
+    const cd x = ld(a.tv + ((int64_t)a.n * a.ntau + l) * E + e);
+    const cd y = ld(a.tv + ((int64_t)a.n * a.ntau + (a.J - l)) * E + e);
+    st(stv + (int64_t)l * E + e, U * (x * x * cj(y)));
+  }
+}
+
+hipError_t launch_sigma_row(const kbe_green *G, const double *u, int n, const kbe_sigma_row *out,
+                            hipStream_t st) {
+  SigArgs a{G->N, G->ntau, G->ntau - 1, n, G->ldt, G->kp, G->rdiag, G->tv, u};
+  const int64_t tot = (int64_t)(n + 1 + G->ntau) * G->N * G->N;
+  hipLaunchKernelGGL(sigma_row_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, a,
+                     out->ret, out->les, out->tv);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
+// Adjoint.  Complex gradients follow PyTorch's convention (dL/dRe + i dL/dIm); for W(z, conj z)
+// the gradient is  conj(gW) dW/dconj(z) + gW conj(dW/dz).  With G1 = gret and G2 = gles - gret
+// (Sigma^> enters ret with +, Sigma^< enters les with + and ret with -), for s < n:
+//   Sigma^< = U conj(z1)^2 (z1 - conj(z2)),  Sigma^> = U g^2 z1,  g = z2 - conj(z1)
+//   d/dz1 :  2U conj(G2) conj(z1)(z1 - conj(z2)) + U G2 z1^2 - 2U conj(G1) g z1 + U G1 conj(g)^2
+//   d/dz2 : -U conj(G2) conj(z1)^2 + 2U G1 conj(g) conj(z1)
+// Every storage entry is owned by exactly one thread (the diagonal block and the tau row are
+// gathered from the two elements that read an entry), so gradients are added without races.
+// The interaction gradient gu_k = sum Re(conj(gW) dW/du_k) is reduced deterministically in two
+// stages through the workspace.
+// ---------------------------------------------------------------------------------------------
+struct SigVjpArgs {
+  SigArgs a;
+  const kbe_c128 *gret, *gles, *gstv;
+  kbe_c128 *gkp, *grdiag, *gtv;
+  double *part;  // [blocks][N]
+};
+
+__global__ void __launch_bounds__(256) sigma_row_vjp_kernel(SigVjpArgs v) {
+  const SigArgs &a = v.a;
+  const int N = a.N;
+  const int64_t E = (int64_t)N * N;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nrt = (int64_t)(a.n + 1) * E;
+  double contrib = 0.0;
+  int ci = 0, cjx = 0;
+  if (idx < nrt) {
+    const int s = (int)(idx / E), e = (int)(idx % E), i = e / N, j = e % N;
+    const double U = a.u[i] * a.u[j];
+    ci = i;
+    cjx = j;
+    const cd G1 = ld(v.gret + s * E + e);
+    const cd G2 = ld(v.gles + s * E + e) - G1;
+    if (s < a.n) {
+      kbe_c128 *pz1 = v.gkp + ((int64_t)s * a.ldt + a.n) * E + j * N + i;
+      kbe_c128 *pz2 = v.gkp + ((int64_t)a.n * a.ldt + s) * E + e;
+      const cd z1 = ld(a.kp + ((int64_t)s * a.ldt + a.n) * E + j * N + i);
+      const cd z2 = ld(a.kp + ((int64_t)a.n * a.ldt + s) * E + e);
+      const cd g = z2 - cj(z1);
+      const cd w = z1 - cj(z2);
+      const cd c1 = cj(z1);
+      const cd gz1 = (2.0 * U) * (cj(G2) * c1 * w) + U * (G2 * z1 * z1) -
+                     (2.0 * U) * (cj(G1) * g * z1) + U * (G1 * cj(g) * cj(g));
+      const cd gz2 = (2.0 * U) * (G1 * cj(g) * c1) - U * (cj(G2) * c1 * c1);
+      st(pz1, ld(pz1) + gz1);
+      st(pz2, ld(pz2) + gz2);
+      const cd Xl = c1 * c1 * w, Xg = g * g * z1;
+      contrib = (cj(G2) * Xl).re + (cj(G1) * Xg).re;
+    } else {
+      const kbe_c128 *D = a.kp + ((int64_t)a.n * a.ldt + a.n) * E;
+      const kbe_c128 *r = a.rdiag + (int64_t)a.n * E;
+      const int et = j * N + i;
+      const cd Dij = ld(D + e), Dji = ld(D + et), rij = ld(r + e), rji = ld(r + et);
+      // element (i,j): reads D_ij, D_ji, r_ij, r_ji
+      const cd toD = G2 * cj(2.0 * U * (Dij * (rji + Dji))) + G1 * cj(2.0 * U * ((rij + Dij) * Dji));
+      const cd toR = G1 * cj(2.0 * U * ((rij + Dij) * Dji));
+      // element (j,i): its "ji" entries are D_ij, r_ij
+      const cd H1 = ld(v.gret + s * E + et);
+      const cd H2 = ld(v.gles + s * E + et) - H1;
+      const cd fromD = H2 * cj(U * (Dji * Dji)) + H1 * cj(U * ((rji + Dji) * (rji + Dji)));
+      const cd fromR = H2 * cj(U * (Dji * Dji));
+      kbe_c128 *pD = v.gkp + ((int64_t)a.n * a.ldt + a.n) * E + e;
+      kbe_c128 *pr = v.grdiag + (int64_t)a.n * E + e;
+      st(pD, ld(pD) + toD + fromD);
+      st(pr, ld(pr) + toR + fromR);
+      contrib = (cj(G2) * (Dij * Dij * (rji + Dji))).re + (cj(G1) * ((rij + Dij) * (rij + Dij) * Dji)).re;
+    }
+  } else if (idx < nrt + (int64_t)a.ntau * E) {
+    const int64_t k = idx - nrt;
+    const int l = (int)(k / E), e = (int)(k % E), i = e / N, j = e % N;
+    const double U = a.u[i] * a.u[j];
+    ci = i;
+    cjx = j;
+    const cd x = ld(a.tv + ((int64_t)a.n * a.ntau + l) * E + e);
+    const cd y = ld(a.tv + ((int64_t)a.n * a.ntau + (a.J - l)) * E + e);
+    const cd gl = ld(v.gstv + (int64_t)l * E + e);
+    const cd gm = ld(v.gstv + (int64_t)(a.J - l) * E + e);
+    kbe_c128 *px = v.gtv + ((int64_t)a.n * a.ntau + l) * E + e;
+    st(px, ld(px) + gl * cj(2.0 * U * (x * cj(y))) + cj(gm) * (U * (y * y)));
+    contrib = (cj(gl) * (x * x * cj(y))).re;
+  }
+  // stage 1 of the interaction gradient: per-block partial sums in a fixed order
+  __shared__ double sc[256];
+  __shared__ int si[256], sj[256];
+  sc[threadIdx.x] = contrib;
+  si[threadIdx.x] = ci;
+  sj[threadIdx.x] = cjx;
+  __syncthreads();
+  if ((int)threadIdx.x < N) {
+    const int q = threadIdx.x;
+    double acc = 0.0;
+    for (int t = 0; t < 256; ++t) {
+      if (si[t] == q) acc += a.u[sj[t]] * sc[t];
+      if (sj[t] == q) acc += a.u[si[t]] * sc[t];
+    }
+    v.part[(int64_t)blockIdx.x * N + q] = acc;
+  }
+}
+
+__global__ void gu_reduce_kernel(const double *part, int nblk, int N, double *gu) {
+  const int q = threadIdx.x;
+  if (q >= N) return;
+  double acc = 0.0;
+  for (int b = 0; b < nblk; ++b) acc += part[(int64_t)b * N + q];
+  gu[q] += acc;
+}
+
+static int64_t sigma_vjp_blocks(int N, int n, int ntau) {
+  return ((int64_t)(n + 1 + ntau) * N * N + 255) / 256;
+}
+
+size_t sigma_vjp_ws_bytes(int N, int n, int ntau) {
+  return sizeof(double) * (size_t)sigma_vjp_blocks(N, n, ntau) * N;
+}
+
+hipError_t launch_sigma_row_vjp(const kbe_green *G, const double *u, int n,
+                                const kbe_sigma_row *gS, const kbe_green *gG, double *gu,
+                                void *ws, hipStream_t st) {
+  SigVjpArgs v;
+  v.a = SigArgs{G->N, G->ntau, G->ntau - 1, n, G->ldt, G->kp, G->rdiag, G->tv, u};
+  v.gret = gS->ret;
+  v.gles = gS->les;
+  v.gstv = gS->tv;
+  v.gkp = gG->kp;
+  v.grdiag = gG->rdiag;
+  v.gtv = gG->tv;
+  v.part = (double *)ws;
+  const int64_t nblk = sigma_vjp_blocks(G->N, n, G->ntau);
+  hipLaunchKernelGGL(sigma_row_vjp_kernel, dim3((unsigned)nblk), dim3(256), 0, st, v);
+  hipLaunchKernelGGL(gu_reduce_kernel, dim3(1), dim3(64), 0, st, (const double *)ws, (int)nblk,
+                     G->N, gu);
+  return hipGetLastError();
+}
+
+}  // namespace kbe

@@ -1,0 +1,215 @@
+// Quadrature weights on the device (Sec. "Adaptive History Integration",
+// Eq. weights and the weight-row recursion of arXiv:2405.08737).
+//
+// Local weights: the integral over [left, right] of the Lagrange interpolant through k nodes is
+// sum_j lam_j g(x_j), where lam solves the moment equations of Eq. weights,
+//   sum_j lam_j phi_l(x_j) = int_left^right phi_l(x) dx,   l = 0..k-1,
+// solved as in the paper by LU with full pivoting.  The paper writes the equations in the
+// monomial basis phi_l = (x - x_0)^l; that Vandermonde matrix has condition ~1e14 at the
+// paper's largest order (20), so here the same equations are posed in the Legendre basis
+// phi_l = P_l(z), z the affine map of [min(x_0,left), max(x_{k-1},right)] onto [-1, 1]
+// (a change of basis: identical solution, condition ~1e6-1e7 at order 20, ~1e2 at order 6).
+// One thread per interval; k <= KBE_KMAX.
+#include "kbe_dev.h"
+#include "kbe_internal.h"
+
+namespace kbe {
+
+__device__ void local_solve(const double *x, int k, double left, double right, double *lam) {
+  if (k == 1) {
+    lam[0] = right - left;
+    return;
+  }
+  const double lo = fmin(x[0], left), hi = fmax(x[k - 1], right);
+  const double c = 0.5 * (lo + hi), h = 0.5 * (hi - lo);
+  double A[KBE_KMAX][KBE_KMAX + 1];
+  int perm[KBE_KMAX];
+  for (int j = 0; j < k; ++j) {  // column j: P_0..P_{k-1} at node j (three-term recurrence)
+    const double z = (x[j] - c) / h;
+    double p0 = 1.0, p1 = z;
+    A[0][j] = 1.0;
+    if (k > 1) A[1][j] = z;
+    for (int l = 1; l + 1 < k; ++l) {
+      const double p2 = ((2 * l + 1) * z * p1 - l * p0) / (l + 1);
+      p0 = p1;
+      p1 = p2;
+      A[l + 1][j] = p2;
+    }
+  }
+  {  // right-hand side: h * int_{za}^{zb} P_l, with int P_l = (P_{l+1} - P_{l-1}) / (2l+1)
+    const double za = (left - c) / h, zb = (right - c) / h;
+    double a0 = 1.0, a1 = za, b0 = 1.0, b1 = zb;  // P_{l-1}, P_l at za and zb (l = 1)
+    A[0][k] = h * (zb - za);
+    for (int l = 1; l < k; ++l) {
+      const double a2 = ((2 * l + 1) * za * a1 - l * a0) / (l + 1);
+      const double b2 = ((2 * l + 1) * zb * b1 - l * b0) / (l + 1);
+      A[l][k] = h * ((b2 - b0) - (a2 - a0)) / (2 * l + 1);
+      a0 = a1;
+      a1 = a2;
+      b0 = b1;
+      b1 = b2;
+    }
+  }
+  for (int j = 0; j < k; ++j) perm[j] = j;
+  for (int s = 0; s < k; ++s) {  // elimination with full pivoting
+    int pr = s, pc = s;
+    double best = -1.0;
+    for (int r = s; r < k; ++r)
+      for (int cc = s; cc < k; ++cc)
+        if (fabs(A[r][cc]) > best) {
+          best = fabs(A[r][cc]);
+          pr = r;
+          pc = cc;
+        }
+    if (pr != s)
+      for (int cc = 0; cc <= k; ++cc) {
+        double tmp = A[s][cc];
+        A[s][cc] = A[pr][cc];
+        A[pr][cc] = tmp;
+      }
+    if (pc != s) {
+      for (int r = 0; r < k; ++r) {
+        double tmp = A[r][s];
+        A[r][s] = A[r][pc];
+        A[r][pc] = tmp;
+      }
+      int tp = perm[s];
+      perm[s] = perm[pc];
+      perm[pc] = tp;
+    }
+    for (int r = s + 1; r < k; ++r) {
+      double f = A[r][s] / A[s][s];
+      for (int cc = s; cc <= k; ++cc) A[r][cc] -= f * A[s][cc];
+    }
+  }
+  double zsol[KBE_KMAX];
+  for (int s = k - 1; s >= 0; --s) {
+    double acc = A[s][k];
+    for (int cc = s + 1; cc < k; ++cc) acc -= A[s][cc] * zsol[cc];
+    zsol[s] = acc / A[s][s];
+  }
+  for (int s = 0; s < k; ++s) lam[perm[s]] = zsol[s];
+}
+
+// lam[p][0..k_p), k_p = min(order[p], p+1), nodes t[p-k_p+1 .. p], interval [t_{p-1}, t_p].
+__global__ void __launch_bounds__(64) local_weights_kernel(const double *t, const int32_t *order,
+                                                           int nt, double *lam, int32_t *kk) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x + 1;
+  if (p >= nt) return;
+  int k = order[p] < p + 1 ? order[p] : p + 1;
+  kk[p] = k;
+  double l[KBE_KMAX];
+  local_solve(t + (p - k + 1), k, t[p - 1], t[p], l);
+  for (int j = 0; j < KBE_KMAX; ++j) lam[(int64_t)p * KBE_KMAX + j] = j < k ? l[j] : 0.0;
+}
+
+// Composite rows: w[n][s] = sum over intervals p <= n whose nodes include s of the
+// local weight of s, summed in increasing p (the order of the row recursion).
+__global__ void __launch_bounds__(256) composite_kernel(const double *lam, const int32_t *kk,
+                                                        int nt, double *w) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)nt * nt) return;
+  int n = (int)(idx / nt), s = (int)(idx % nt);
+  double acc = 0.0;
+  if (s <= n) {
+    int p0 = s > 1 ? s : 1;
+    int p1 = n < s + KBE_KMAX - 1 ? n : s + KBE_KMAX - 1;
+    for (int p = p0; p <= p1; ++p) {
+      int a = p - kk[p] + 1;
+      if (a <= s) acc += lam[(int64_t)p * KBE_KMAX + (s - a)];
+    }
+  }
+  w[idx] = acc;
+}
+
+// Unit-spacing table for the uniform tau grid: tab[kk-1][r][i], the weight of node i
+// (of nodes 0..kk-1) for the interval [r-1, r], r = 1..kk-1.
+__global__ void __launch_bounds__(64) tau_table_kernel(double *tab) {
+  int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= KBE_KMAX * KBE_KMAX) return;
+  int kk = id / KBE_KMAX + 1, r = id % KBE_KMAX;
+  double *out = tab + ((int64_t)(kk - 1) * KBE_KMAX + r) * KBE_KMAX;
+  for (int i = 0; i < KBE_KMAX; ++i) out[i] = 0.0;
+  if (r < 1 || r >= kk) return;
+  double x[KBE_KMAX], l[KBE_KMAX];
+  for (int i = 0; i < kk; ++i) x[i] = (double)i;
+  local_solve(x, kk, r - 1.0, (double)r, l);
+  for (int i = 0; i < kk; ++i) out[i] = l[i];
+}
+
+// wf[j][l]: integral over [0, tau_j]; interval p in [1, j] uses kk = min(K, j+1) nodes on the
+// window starting at a = clamp(p-kk+1, 0, j-kk+1).
+__global__ void __launch_bounds__(256) tau_fwd_kernel(const double *tab, int ntau, int K,
+                                                      double h, double *wf) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)ntau * ntau) return;
+  int j = (int)(idx / ntau), l = (int)(idx % ntau);
+  double acc = 0.0;
+  if (l <= j && j > 0) {
+    int kk = K < j + 1 ? K : j + 1;
+    for (int p = 1; p <= j; ++p) {
+      int a = p - kk + 1;
+      if (a < 0) a = 0;
+      if (a > j - kk + 1) a = j - kk + 1;
+      if (l >= a && l < a + kk) acc += h * tab[((int64_t)(kk - 1) * KBE_KMAX + (p - a)) * KBE_KMAX + (l - a)];
+    }
+  }
+  wf[idx] = acc;
+}
+
+__global__ void tau_full_kernel(const double *wf, int ntau, double *wtau) {
+  int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= ntau) return;
+  int J = ntau - 1;
+  wtau[l] = 0.5 * (wf[(int64_t)J * ntau + l] + wf[(int64_t)J * ntau + (J - l)]);
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t weights_ws_bytes(int nt, int ntau) {
+  size_t b = 0;
+  b += align256(sizeof(double) * nt);                    // t
+  b += align256(sizeof(int32_t) * nt);                   // order
+  b += align256(sizeof(double) * (size_t)nt * KBE_KMAX); // lam
+  b += align256(sizeof(int32_t) * nt);                   // kk
+  if (ntau > 0) b += align256(sizeof(double) * KBE_KMAX * KBE_KMAX * KBE_KMAX);
+  return b;
+}
+
+hipError_t launch_weights(const kbe_grid *g, double *w, double *wtau, double *wf, void *ws,
+                          hipStream_t st) {
+  char *base = (char *)ws;
+  int nt = g->nt;
+  double *t_d = (double *)base;
+  base += align256(sizeof(double) * nt);
+  int32_t *o_d = (int32_t *)base;
+  base += align256(sizeof(int32_t) * nt);
+  double *lam = (double *)base;
+  base += align256(sizeof(double) * (size_t)nt * KBE_KMAX);
+  int32_t *kk = (int32_t *)base;
+  base += align256(sizeof(int32_t) * nt);
+  double *tab = (double *)base;
+  hipError_t e = hipMemcpyAsync(t_d, g->t, sizeof(double) * nt, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(o_d, g->order, sizeof(int32_t) * nt, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return e;
+  if (nt > 1)
+    hipLaunchKernelGGL(local_weights_kernel, dim3((nt - 1 + 63) / 64), dim3(64), 0, st, t_d, o_d,
+                       nt, lam, kk);
+  int64_t tot = (int64_t)nt * nt;
+  hipLaunchKernelGGL(composite_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, lam,
+                     kk, nt, w);
+  if (g->ntau > 0) {
+    int ntau = g->ntau;
+    hipLaunchKernelGGL(tau_table_kernel, dim3((KBE_KMAX * KBE_KMAX + 63) / 64), dim3(64), 0, st,
+                       tab);
+    int64_t tt = (int64_t)ntau * ntau;
+    hipLaunchKernelGGL(tau_fwd_kernel, dim3((unsigned)((tt + 255) / 256)), dim3(256), 0, st, tab,
+                       ntau, g->tau_order, g->beta / (ntau - 1), wf);
+    hipLaunchKernelGGL(tau_full_kernel, dim3((ntau + 255) / 256), dim3(256), 0, st, wf, ntau,
+                       wtau);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace kbe

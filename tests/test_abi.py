@@ -1,0 +1,165 @@
+"""C ABI of libkbe.so without a GPU: every symbol that include/kbe.h declares is exported, and
+every argument error is reported by host-side validation before anything is enqueued."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import paper_2405_08737_amd as kbe
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "kbe.h")
+
+FAKE = 0x1000  # a non-NULL pointer value; validation never dereferences device pointers
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(kbe_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_abi():
+    fns = header_functions()
+    for name in ("kbe_weights", "kbe_sigma_2b", "kbe_collision", "kbe_collision_vjp",
+                 "kbe_sigma_2b_vjp"):
+        assert name in fns
+
+
+def test_library_exports_every_declared_symbol():
+    L = kbe.lib()
+    for name in header_functions():
+        assert hasattr(L, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", kbe._SO], capture_output=True, text=True)
+    exported = set(re.findall(r"\bT (kbe_\w+)", out.stdout))
+    assert set(header_functions()) <= exported
+    assert set(kbe.EXPORTS) == set(header_functions())
+
+
+def test_status_strings_and_version():
+    L = kbe.lib()
+    for code in range(6):
+        assert L.kbe_status_string(code).decode().startswith("KBE_")
+    assert L.kbe_version() >= 10000
+
+
+def green(N=2, nt=8, ntau=4, ldt=None):
+    return kbe._Green(N, nt, ntau, nt if ldt is None else ldt, FAKE, FAKE, FAKE, FAKE)
+
+
+def row():
+    return kbe._Row(FAKE, FAKE, FAKE)
+
+
+def wts():
+    return kbe._Wts(FAKE, FAKE, FAKE)
+
+
+def call_collision(G, n=7, m0=0, m1=8, flags=kbe.OUT_ALL, ws_bytes=1 << 40, S=None, W=None,
+                   outs=(FAKE, FAKE, FAKE, FAKE)):
+    L = kbe.lib()
+    S = row() if S is None else S
+    W = wts() if W is None else W
+    return L.kbe_collision(ctypes.byref(G), ctypes.byref(S), ctypes.byref(W), n, m0, m1, flags,
+                           *outs, FAKE, ws_bytes, None)
+
+
+def err():
+    return kbe.lib().kbe_last_error().decode()
+
+
+@pytest.mark.parametrize("kw,code,msg", [
+    (dict(G=green(N=0)), 1, "N = 0"),
+    (dict(G=green(N=17)), 1, "N = 17"),
+    (dict(G=green(ntau=1)), 1, "ntau"),
+    (dict(G=green(ldt=4)), 1, "ldt"),
+    (dict(G=green(), n=8), 2, "n = 8"),
+    (dict(G=green(), n=-1), 2, "n = -1"),
+    (dict(G=green(), m0=3, m1=2), 2, "m-range"),
+    (dict(G=green(), m1=9), 2, "m-range"),
+    (dict(G=green(), flags=0x10000), 1, "unknown flag"),
+    (dict(G=green(), ws_bytes=16), 3, "workspace"),
+    (dict(G=green(), S=kbe._Row(None, FAKE, FAKE)), 1, "S->ret"),
+    (dict(G=green(), S=kbe._Row(FAKE, None, FAKE)), 1, "S->les"),
+    (dict(G=green(), S=kbe._Row(FAKE, FAKE, None)), 1, "S->tv"),
+    (dict(G=green(), W=kbe._Wts(None, FAKE, FAKE)), 1, "W->w"),
+    (dict(G=green(), W=kbe._Wts(FAKE, None, FAKE)), 1, "W->wtau"),
+    (dict(G=green(), W=kbe._Wts(FAKE, FAKE, None)), 1, "W->wtau_fwd"),
+    (dict(G=green(), outs=(None, FAKE, FAKE, FAKE)), 1, "IR is NULL"),
+    (dict(G=green(), outs=(FAKE, FAKE, FAKE, None)), 1, "Jtv is NULL"),
+])
+def test_collision_argument_errors(kw, code, msg):
+    assert call_collision(**kw) == code
+    assert msg in err()
+
+
+def test_collision_null_storage():
+    G = kbe._Green(2, 8, 4, 8, None, FAKE, FAKE, FAKE)
+    assert call_collision(G) == 1 and "kp" in err()
+    G = kbe._Green(2, 8, 4, 8, FAKE, FAKE, None, FAKE)
+    assert call_collision(G) == 1 and "tv" in err()
+
+
+def test_vjp_argument_errors():
+    L = kbe.lib()
+    G, S, W = green(), row(), wts()
+    bad = green(N=3)
+    st = L.kbe_collision_vjp(ctypes.byref(G), ctypes.byref(S), ctypes.byref(W), 7, 0, 8,
+                             kbe.OUT_ALL, FAKE, FAKE, FAKE, FAKE, ctypes.byref(bad),
+                             ctypes.byref(row()), FAKE, 1 << 40, None)
+    assert st == 1 and "shape" in err()
+    st = L.kbe_collision_vjp(ctypes.byref(G), ctypes.byref(S), ctypes.byref(W), 7, 0, 8,
+                             kbe.OUT_ALL, None, FAKE, FAKE, FAKE, ctypes.byref(green()),
+                             ctypes.byref(row()), FAKE, 1 << 40, None)
+    assert st == 1 and "gIR" in err()
+    st = L.kbe_sigma_2b_vjp(ctypes.byref(G), FAKE, 7, ctypes.byref(row()), ctypes.byref(green()),
+                            FAKE, FAKE, 0, None)
+    assert st == 3 and "workspace" in err()
+    st = L.kbe_sigma_2b(ctypes.byref(G), FAKE, 8, ctypes.byref(row()), None)
+    assert st == 2
+    st = L.kbe_sigma_2b(ctypes.byref(G), None, 3, ctypes.byref(row()), None)
+    assert st == 1 and "u" in err()
+
+
+def grid_call(t, order, ntau=0, beta=1.0, tau_order=5, ws_bytes=1 << 40):
+    L = kbe.lib()
+    t = np.ascontiguousarray(t, np.float64)
+    order = np.ascontiguousarray(order, np.int32)
+    g = kbe._Grid(len(t), t.ctypes.data, order.ctypes.data, ntau, beta, tau_order)
+    return L.kbe_weights(ctypes.byref(g), FAKE, FAKE, FAKE, FAKE, ws_bytes, None)
+
+
+@pytest.mark.parametrize("t,order,kw,code,msg", [
+    ([0.1, 0.2, 0.3], [3, 3, 3], {}, 1, "t[0]"),
+    ([0.0, 0.2, 0.2], [3, 3, 3], {}, 1, "strictly increasing"),
+    ([0.0, 0.2, 0.1], [3, 3, 3], {}, 1, "strictly increasing"),
+    ([0.0, 0.2, 0.3], [3, 0, 3], {}, 2, "order[1]"),
+    ([0.0, 0.2, 0.3], [3, 3, 21], {}, 2, "order[2]"),
+    ([0.0, 0.2, 0.3], [3, 3, 3], dict(ntau=1), 1, "ntau"),
+    ([0.0, 0.2, 0.3], [3, 3, 3], dict(ntau=4, beta=0.0), 1, "beta"),
+    ([0.0, 0.2, 0.3], [3, 3, 3], dict(ntau=4, tau_order=0), 2, "tau_order"),
+    ([0.0, 0.2, 0.3], [3, 3, 3], dict(ws_bytes=8), 3, "workspace"),
+])
+def test_weights_argument_errors(t, order, kw, code, msg):
+    assert grid_call(t, order, **kw) == code
+    assert msg in err()
+
+
+def test_workspace_queries():
+    L = kbe.lib()
+    a = L.kbe_collision_workspace(16, 2048, 512, 2047, 0, 2048, kbe.OUT_ALL)
+    b = L.kbe_collision_workspace(16, 2048, 512, 2047, 0, 2048, kbe.OUT_IR)
+    assert a > b > 0
+    assert L.kbe_collision_workspace(0, 8, 0, 7, 0, 8, kbe.OUT_ALL) == 0
+    assert L.kbe_collision_vjp_workspace(8, 1024, 256, 1023, 0, 1024, kbe.OUT_ALL) > 0
+    assert L.kbe_sigma_2b_vjp_workspace(16, 2047, 512) >= 8 * 16
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(kbe, "_SO", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(kbe, "_lib", None)
+    with pytest.raises(RuntimeError, match="not built"):
+        kbe.lib()

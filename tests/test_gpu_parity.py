@@ -1,0 +1,196 @@
+"""GPU parity: the HIP library (called through its C ABI) against the CPU oracle on the same
+seeded inputs, to the FP64 bar (per block 1e-12 of the rounding scale, and 1e-12 globally)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.cases import (RTOL, Case, assert_blocks_close, bnorm, device_green, device_weights,
+                         scales, to_dev, to_host)
+
+pytestmark = pytest.mark.gpu
+
+
+def _print(*a):
+    print(*a, flush=True)
+
+
+def run_collision(kbe, case: Case, n=None, m0=0, m1=None, flags=None, gpu_weights=False,
+                  extra_flags=0, sig_mode="random"):
+    t, order, kp, rd, tv, mat = case.host()
+    n = case.nt - 1 if n is None else n
+    m1 = n + 1 if m1 is None else m1
+    flags = oracle.F_ALL if flags is None else flags
+    W = oracle.Weights.build(t, order, case.beta, case.ntau, case.tau_order)
+    Go = oracle.Green(kp, rd, tv, mat)
+    Gd = device_green(kp, rd, tv, mat)
+    if sig_mode == "random":
+        sig = synth.sigma_row(case.seed, case.N, n, case.ntau, t)
+        if not case.ntau:
+            sig = (sig[0], sig[1], np.zeros((0, case.N, case.N), np.complex128))
+    else:  # second Born from the same G
+        sig = oracle.sigma_row(Go, np.full(case.N, case.U), n)
+    sigd = tuple(to_dev(x) if x.size else None for x in sig)
+    if gpu_weights:
+        Wd = kbe.weights(t, order, case.ntau, case.beta, case.tau_order)
+    else:
+        Wd = device_weights(W)
+    gpu = kbe.collision(Gd, sigd, Wd, n, m0, m1, flags | extra_flags)
+    ref = oracle.collision(Go, sig, W, n, m0, m1, flags)
+    sc = scales(kp, rd, tv, mat, sig, W, n, range(m0, m1), range(case.ntau))
+    return gpu, ref, sc
+
+
+def check_all(gpu, ref, sc, flags=oracle.F_ALL, rtol=RTOL):
+    names = ["IR", "IL", "Itv", "Jtv"]
+    for k, name in enumerate(names):
+        if not flags & (1 << k):
+            continue
+        g = to_host(gpu[k])
+        if g is None:
+            assert ref[k].size == 0, name
+            continue
+        assert_blocks_close(g, ref[k], sc[name], name, rtol)
+
+
+def test_weights_match_oracle(gpu):
+    kbe = gpu
+    for seed, nt, hmin, hmax, omin, omax, ntau, beta, to in [
+        (1000, 64, 0.02, 0.08, 5, 5, 64, 10.0, 5),
+        (1001, 2048, 0.005, 0.05, 3, 6, 512, 20.0, 5),
+        (7, 300, 0.005, 0.05, 1, 12, 33, 3.0, 8),
+        (8, 50, 0.01, 0.1, 2, 2, 9, 1.0, 1),
+    ]:
+        _print("weights case", seed, nt, omin, omax, ntau, to)
+        t, order = synth.grid(seed, nt, hmin, hmax, omin, omax)
+        Wd = kbe.weights(t, order, ntau, beta, to)
+        W = oracle.Weights.build(t, order, beta, ntau, to)
+        w = to_host(Wd.w)
+        scale = np.abs(W.w).max(axis=1, keepdims=True) + 1e-300
+        assert (np.abs(w - W.w) / scale).max() < 1e-12
+        assert np.all(w[np.triu_indices(nt, 1)] == 0)
+        np.testing.assert_allclose(to_host(Wd.wtau), W.wfull, rtol=0, atol=1e-12 * np.abs(W.wfull).max())
+        np.testing.assert_allclose(to_host(Wd.wtau_fwd), W.wf, rtol=0, atol=1e-12 * np.abs(W.wf).max())
+
+
+def test_weights_high_order(gpu):
+    """Orders up to KBE_KMAX = 20 (the paper's maximum history order K): the Vandermonde route
+    is ill-conditioned there, so the bar is the polynomial exactness both routes guarantee."""
+    kbe = gpu
+    t, order = synth.grid(3, 120, 0.01, 0.05, 14, 20)
+    w = to_host(kbe.weights(t, order).w)
+    W = oracle.weights(t, order)
+    assert np.abs(w - W).max() < 1e-9 * np.abs(W).max()
+    n = 119
+    for d in range(2):  # start-up intervals limit the whole-range exactness to degree 1
+        assert abs(w[n] @ (t / t[n]) ** d - t[n] / (d + 1)) < 1e-12
+
+
+@pytest.mark.parametrize("N,n", [(1, 5), (2, 0), (2, 63), (3, 17), (16, 0), (16, 39)])
+def test_sigma_row_matches_oracle(gpu, N, n):
+    kbe = gpu
+    case = Case(N=N, nt=40 if N == 16 else 64, ntau=12, beta=4.0, seed=11 + N)
+    t, order, kp, rd, tv, mat = case.host()
+    u = np.linspace(0.6, 1.4, N)
+    ref = oracle.sigma_row(oracle.Green(kp, rd, tv, mat), u, n)
+    got = kbe.sigma_2b(device_green(kp, rd, tv, mat), to_dev(u), n)
+    for g, r in zip(got, ref):
+        g = to_host(g)
+        d = bnorm(g - r)
+        assert np.all(d <= 1e-13 * (bnorm(r) + 1e-300) + 1e-300)
+
+
+def test_collision_parity_small(gpu):
+    """N = 2, nt = 64, ntau = 64, beta = 10, order 5: every output for every m."""
+    kbe = gpu
+    case = Case(N=2, nt=64, ntau=64, beta=10.0, seed=1000, omin=5, omax=5)
+    check_all(*run_collision(kbe, case))
+
+
+def test_collision_whole_path_gpu_weights(gpu):
+    kbe = gpu
+    case = Case(N=2, nt=64, ntau=64, beta=10.0, seed=1000, omin=5, omax=5)
+    gpu_out, ref, sc = run_collision(kbe, case, gpu_weights=True)
+    check_all(gpu_out, ref, sc, rtol=1e-11)  # the two weight routes differ at rounding level
+
+
+@pytest.mark.parametrize("generic", [False, True])
+def test_collision_parity_n16_several_chunks(gpu, generic):
+    """N = 16 over 300 points (two full 128-term chunks and a ragged tail), MFMA and generic."""
+    kbe = gpu
+    case = Case(N=16, nt=300, ntau=40, beta=6.0, seed=77, hmin=0.005, hmax=0.05)
+    _print("N16 nt300 generic" if generic else "N16 nt300 mfma")
+    out = run_collision(kbe, case, extra_flags=kbe.FORCE_GENERIC if generic else 0)
+    check_all(*out)
+
+
+@pytest.mark.parametrize("N", [1, 3, 4, 5, 7, 8, 9, 13, 16])
+def test_collision_orbital_counts(gpu, N):
+    kbe = gpu
+    case = Case(N=N, nt=37, ntau=9, beta=2.0, seed=100 + N)
+    check_all(*run_collision(kbe, case))
+
+
+def test_collision_ragged_ranges_and_edges(gpu):
+    kbe = gpu
+    case = Case(N=4, nt=50, ntau=10, beta=2.0, seed=5)
+    for (n, m0, m1) in [(0, 0, 1), (49, 0, 0), (49, 50, 50), (49, 13, 29), (20, 20, 21), (30, 0, 31)]:
+        _print("range", n, m0, m1)
+        check_all(*run_collision(kbe, case, n=n, m0=m0, m1=m1))
+    # no thermal branch
+    case0 = Case(N=3, nt=40, ntau=0, beta=0.0, seed=6)
+    check_all(*run_collision(kbe, case0, flags=oracle.F_IR | oracle.F_IL), oracle.F_IR | oracle.F_IL)
+    # padded leading dimension, N = 16 (MFMA path)
+    case1 = Case(N=16, nt=30, ntau=6, beta=2.0, seed=9, ldt=37)
+    check_all(*run_collision(kbe, case1))
+    # single outputs selected
+    for f in (oracle.F_IR, oracle.F_IL, oracle.F_ITV, oracle.F_JTV):
+        g, r, s = run_collision(kbe, Case(N=16, nt=25, ntau=7, beta=2.0, seed=10), flags=f)
+        check_all(g, r, s, f)
+
+
+def test_collision_partial_range_is_slice_and_deterministic(gpu):
+    kbe = gpu
+    case = Case(N=16, nt=200, ntau=20, beta=3.0, seed=12)
+    t, order, kp, rd, tv, mat = case.host()
+    W = device_weights(oracle.Weights.build(t, order, case.beta, case.ntau))
+    Gd = device_green(kp, rd, tv, mat)
+    sig = tuple(to_dev(x) for x in synth.sigma_row(case.seed, case.N, 199, case.ntau, t))
+    full = [to_host(x) for x in kbe.collision(Gd, sig, W, 199)]
+    again = [to_host(x) for x in kbe.collision(Gd, sig, W, 199)]
+    for a, b in zip(full, again):
+        assert np.array_equal(a, b)  # bitwise run-to-run determinism
+    part = [to_host(x) for x in kbe.collision(Gd, sig, W, 199, 50, 130)]
+    for a, b in zip(full[:3], part[:3]):
+        np.testing.assert_array_equal(a[50:130], b)
+    np.testing.assert_array_equal(full[3], part[3])
+
+
+def test_mfma_agrees_with_generic(gpu):
+    kbe = gpu
+    case = Case(N=16, nt=160, ntau=24, beta=3.0, seed=13)
+    t, order, kp, rd, tv, mat = case.host()
+    W = device_weights(oracle.Weights.build(t, order, case.beta, case.ntau))
+    Gd = device_green(kp, rd, tv, mat)
+    sig = tuple(to_dev(x) for x in synth.sigma_row(case.seed, case.N, 159, case.ntau, t))
+    a = kbe.collision(Gd, sig, W, 159)
+    b = kbe.collision(Gd, sig, W, 159, flags=kbe.OUT_ALL | kbe.FORCE_GENERIC)
+    for x, y in zip(a, b):
+        x, y = to_host(x), to_host(y)
+        assert np.linalg.norm((x - y).ravel()) <= 1e-13 * np.linalg.norm(y.ravel())
+
+
+def test_conservation_invariant_on_gpu(gpu):
+    """With Sigma = kbe_sigma_2b(G) and anti-Hermitian diagonal blocks, Re Tr of the m = n
+    integrals vanishes to rounding (the conservation law of the second-Born self-energy)."""
+    kbe = gpu
+    case = Case(N=16, nt=150, ntau=20, beta=3.0, seed=21)
+    t, order, kp, rd, tv, mat = case.host()
+    Gd = device_green(kp, rd, tv, mat)
+    Wd = kbe.weights(t, order, case.ntau, case.beta, 5)
+    n = 149
+    sig = kbe.sigma_2b(Gd, to_dev(np.full(16, 1.3)), n)
+    IR, IL, Itv, _ = (to_host(x) for x in kbe.collision(Gd, sig, Wd, n, n, n + 1))
+    scale = np.abs(IR[0]).sum() + np.abs(IL[0]).sum()
+    assert abs(np.trace(IR[0] + IL[0]).real) < 1e-13 * scale
+    assert abs(np.trace(Itv[0]).real) < 1e-13 * np.abs(Itv[0]).sum()
