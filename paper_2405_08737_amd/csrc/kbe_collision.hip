@@ -1,25 +1,31 @@
 // History integrals of arXiv:2405.08737 (Eq. KBE2 lesser form, history terms of Eq. KBE3) and
 // their adjoint, on gfx950.
 //
-// Every output block is a sum of block products  c_t * Q_t * op(P_t)  over a list of terms t:
-// P_t is a block of the (large) Green's-function storage streamed from HBM, Q_t a block of a
-// (small, cache-resident) self-energy row or cotangent, c_t a scalar weight.  op is one of
-//   OP_N : Q P        (contraction over P's row index)
-//   OP_H : Q P^dagger (contraction over P's column index)
-//   OP_HN: Q^dagger P
-// Each family of terms ("class") enumerates its terms for an output index o.  The term list of
-// an output is cut into chunks of SC terms; one wavefront computes one (output, chunk) partial
-// sum and writes it to the workspace, and a reduce kernel adds the chunks in a fixed order, so
-// results are deterministic (no floating-point atomics).
+// Every output block is a sum over terms t of a block product with a scalar weight,
+//   OP_N : c Q_t P_t,   OP_H : c Q_t P_t^dagger,   OP_HN : c Q_t^dagger P_t,
+// where P_t is a block of the large Green's-function storage streamed from HBM and Q_t a block
+// of a small, cache-resident operand (self-energy row or cotangent).  A family of such terms
+// ("class") is indexed so that Q depends on the term index t only: outputs that share a term
+// index share Q.  The weight and P depend on (output, t); some Matsubara terms carry two
+// (c, P) pairs, which are combined before the product.
 //
-// Two implementations of the per-wave partial sum:
-//   * stream_mfma16 (N = 16): FP64 matrix cores.  A 16x16 complex block product is 4 real
-//     products, each 4 v_mfma_f64_16x16x4 over k-slices.  Operands are loaded straight from
-//     global memory into the MFMA register layouts: the B operand (lane l holds B[k][l%16],
-//     k = 4*slice + l/16) is a contiguous 1 KiB row-slice of a row-major block; the A operand
-//     (lane l holds A[l%16][k]) reads 64-byte row segments.
-//   * stream_generic (any N <= 16): vector ALU, one output element per lane, several terms per
-//     wave for small N, lanes summed through LDS at the end.
+// Work decomposition: the term index is cut into chunks of SC terms; a wavefront computes the
+// partial sums of MO consecutive outputs over one chunk (MO = 4 on the MFMA path, so each Q
+// load serves four P blocks) and writes them to the workspace; a reduce kernel adds the chunks
+// of every output in a fixed order, so results are deterministic (no floating-point atomics).
+// Workgroups are laid out chunk-fastest and every class starts on a multiple of 8 workgroups:
+// with round-robin dispatch over the 8 XCDs, all tasks of a chunk land on one XCD and its L2
+// holds that chunk's Q blocks.
+//
+// Implementations of a task:
+//   * task_mfma16 (N = 16): FP64 matrix cores.  A 16x16 complex block product is four real
+//     products of four v_mfma_f64_16x16x4 k-slices each; two accumulators per output (real and
+//     imaginary part) with the negated imaginary part of Q prepared once per term.  Operands go
+//     from global memory straight into the MFMA register layouts: the B operand (lane l holds
+//     B[k][l%16], k = 4*slice + l/16) is a contiguous 1 KiB row-slice of a row-major block, the
+//     A operand (lane l holds A[l%16][k]) reads 64-byte row segments.
+//   * task_generic (any N <= 16): vector ALU, one output per wave, one output element per lane,
+//     several terms per wave for small N summed across lanes at the end.
 #include "kbe_dev.h"
 #include "kbe_internal.h"
 
@@ -28,12 +34,12 @@
 namespace kbe {
 
 enum Cls {
-  C_IRC,   // I^R, column part: s <= m,  w[n][s] Sigma^R(n,s) G^<(s,m),       G^< = kp[s][m]
-  C_IRR,   // I^R, row part:    s > m,  -w[n][s] Sigma^R(n,s) kp[m][s]^dagger
-  C_IL,    // I^<:              s <= m,  w[m][s] Sigma^<(n,s) G^R(m,s)^dagger
-  C_ITV,   // I^]:  -i wtau[j] Sigma^](n,j) tv[m][J-j]^dagger
-  C_JR,    // J^] real-time part:  w[n][s] Sigma^R(n,s) tv[s][j]
-  C_JM,    // J^] Matsubara part (split at tau_j)
+  C_IRC,   // I^R, s <= m:  w[n][s] Sigma^R(s) kp[s][m]               (G^<(s,m) stored)
+  C_IRR,   // I^R, s > m : -w[n][s] Sigma^R(s) kp[m][s]^dagger        (G^<(s,m) = -kp[m][s]^dag)
+  C_IL,    // I^<, s <= m:  w[m][s] Sigma^<(s) G^R(m,s)^dagger
+  C_ITV,   // I^]:  -i wtau[j] Sigma^](j) tv[m][J-j]^dagger
+  C_JR,    // J^] real-time part:  w[n][s] Sigma^R(s) tv[s][j]
+  C_JM,    // J^] Matsubara part, split at tau_j
   B_R1,    // adjoint: gSigma^R(s) from C_IRC terms
   B_R2,    // adjoint: gSigma^R(s) from C_IRR terms
   B_R3,    // adjoint: gSigma^R(s) from C_JR terms
@@ -52,178 +58,122 @@ __host__ __device__ constexpr int cls_op() {
              : (CLS == G_MAT ? OP_HN : OP_N);
 }
 
+// Term-index range [lo, hi) of output o.
 template <int CLS>
-__device__ __forceinline__ int cls_count(const Params &p, int o) {
+__device__ __forceinline__ void cls_range(const Params &p, int o, int &lo, int &hi) {
   const int m = p.m0 + o;
   switch (CLS) {
-    case C_IRC: return m + 1;
-    case C_IRR: return p.n - m;
-    case C_IL: return m + 1;
-    case C_ITV: return p.ntau;
-    case C_JR: return p.n + 1;
-    case C_JM: return p.ntau + 1;
-    case B_R1: { int lo = o > p.m0 ? o : p.m0; return p.m1 > lo ? p.m1 - lo : 0; }
-    case B_R2: { int hi = o < p.m1 ? o : p.m1; return hi > p.m0 ? hi - p.m0 : 0; }
-    case B_R3: return p.ntau;
-    case B_L: { int lo = o > p.m0 ? o : p.m0; return p.m1 > lo ? p.m1 - lo : 0; }
-    case B_T1: return p.m1 - p.m0;
-    case B_T2: return p.ntau + 1;
-    case G_MAT: return p.ntau + 1;
+    case C_IRC: lo = 0; hi = m + 1; break;
+    case C_IRR: lo = m + 1; hi = p.n + 1; break;
+    case C_IL: lo = 0; hi = m + 1; break;
+    case C_ITV: lo = 0; hi = p.ntau; break;
+    case C_JR: lo = 0; hi = p.n + 1; break;
+    case C_JM: lo = 0; hi = p.ntau; break;
+    case B_R1: lo = o > p.m0 ? o : p.m0; hi = p.m1; break;
+    case B_R2: lo = p.m0; hi = o < p.m1 ? o : p.m1; break;
+    case B_R3: lo = 0; hi = p.ntau; break;
+    case B_L: lo = o > p.m0 ? o : p.m0; hi = p.m1; break;
+    case B_T1: lo = p.m0; hi = p.m1; break;
+    case B_T2: lo = 0; hi = p.ntau; break;
+    case G_MAT: lo = 0; hi = p.ntau; break;
   }
-  return 0;
 }
 
-// Term t of output o: scalar c, small operand Q, streamed block P.
+// Shared operand of term t.
 template <int CLS>
-__device__ __forceinline__ void cls_term(const Params &p, int o, int t, cd &c, const kbe_c128 *&Q,
-                                         const kbe_c128 *&P) {
+__device__ __forceinline__ const kbe_c128 *cls_Q(const Params &p, int t) {
   const int64_t E = bsz(p);
-  const int J = p.J;
   switch (CLS) {
-    case C_IRC: {
-      const int m = p.m0 + o, s = t;
-      c = {p.w[(int64_t)p.n * p.nt + s], 0.0};
-      Q = p.ret + s * E;
-      P = kp_blk(p, s, m);
-      break;
-    }
-    case C_IRR: {
-      const int m = p.m0 + o, s = m + 1 + t;
-      c = {-p.w[(int64_t)p.n * p.nt + s], 0.0};
-      Q = p.ret + s * E;
-      P = kp_blk(p, m, s);
-      break;
-    }
-    case C_IL: {
-      const int m = p.m0 + o, s = t;
-      c = {p.w[(int64_t)m * p.nt + s], 0.0};
-      Q = p.les + s * E;
-      P = s < m ? kp_blk(p, m, s) : p.rdiag + m * E;
-      break;
-    }
-    case C_ITV: {
-      const int m = p.m0 + o, j = t;
-      c = {0.0, -p.wtau[j]};
-      Q = p.stv + j * E;
-      P = tv_blk(p, m, J - j);
-      break;
-    }
-    case C_JR: {
-      const int s = t;
-      c = {p.w[(int64_t)p.n * p.nt + s], 0.0};
-      Q = p.ret + s * E;
-      P = tv_blk(p, s, o);
-      break;
-    }
-    case C_JM: {
-      const int j = o;
-      int l;
-      if (t <= j) {  // [0, tau_j]: G^M(tau_l - tau_j) = -G^M(beta + tau_l - tau_j)
-        l = t;
-        c = {-p.wf[(int64_t)j * p.ntau + l], 0.0};
-        P = p.mat + (J + l - j) * E;
-      } else {       // [tau_j, beta]: mirror of the forward rule on the symmetric grid
-        l = t - 1;
-        c = {p.wf[(int64_t)(J - j) * p.ntau + (J - l)], 0.0};
-        P = p.mat + (l - j) * E;
-      }
-      Q = p.stv + l * E;
-      break;
-    }
-    case B_R1: {
-      const int s = o, m = (s > p.m0 ? s : p.m0) + t;
-      c = {p.w[(int64_t)p.n * p.nt + s], 0.0};
-      Q = p.gIR + (m - p.m0) * E;
-      P = kp_blk(p, s, m);
-      break;
-    }
-    case B_R2: {
-      const int s = o, m = p.m0 + t;
-      c = {-p.w[(int64_t)p.n * p.nt + s], 0.0};
-      Q = p.gIR + (m - p.m0) * E;
-      P = kp_blk(p, m, s);
-      break;
-    }
-    case B_R3: {
-      const int s = o, j = t;
-      c = {p.w[(int64_t)p.n * p.nt + s], 0.0};
-      Q = p.gJ + j * E;
-      P = tv_blk(p, s, j);
-      break;
-    }
-    case B_L: {
-      const int s = o, m = (s > p.m0 ? s : p.m0) + t;
-      c = {p.w[(int64_t)m * p.nt + s], 0.0};
-      Q = p.gIL + (m - p.m0) * E;
-      P = m > s ? kp_blk(p, m, s) : p.rdiag + s * E;
-      break;
-    }
-    case B_T1: {
-      const int j = o, m = p.m0 + t;
-      c = {0.0, p.wtau[j]};
-      Q = p.gItv + t * E;
-      P = tv_blk(p, m, J - j);
-      break;
-    }
-    case B_T2: {
-      const int l = o;
-      int j;
-      if (t < J - l + 1) {
-        j = l + t;
-        c = {-p.wf[(int64_t)j * p.ntau + l], 0.0};
-        P = p.mat + (J + l - j) * E;
-      } else {
-        j = t - (J - l + 1);
-        c = {p.wf[(int64_t)(J - j) * p.ntau + (J - l)], 0.0};
-        P = p.mat + (l - j) * E;
-      }
-      Q = p.gJ + j * E;
-      break;
-    }
-    case G_MAT: {
-      const int k = o;
-      int l, j;
-      if (t <= k) {
-        l = t;
-        j = l + J - k;
-        c = {-p.wf[(int64_t)j * p.ntau + l], 0.0};
-      } else {
-        j = t - (k + 1);
-        l = j + k;
-        c = {p.wf[(int64_t)(J - j) * p.ntau + (J - l)], 0.0};
-      }
-      Q = p.stv + l * E;
-      P = p.gJ + j * E;
-      break;
-    }
+    case C_IRC: case C_IRR: case C_JR: return p.ret + t * E;
+    case C_IL: return p.les + t * E;
+    case C_ITV: case C_JM: case G_MAT: return p.stv + t * E;
+    case B_R1: case B_R2: return p.gIR + (t - p.m0) * E;
+    case B_L: return p.gIL + (t - p.m0) * E;
+    case B_T1: return p.gItv + (t - p.m0) * E;
+    case B_R3: case B_T2: return p.gJ + t * E;
   }
+  return nullptr;
 }
 
-// Runtime dispatch of cls_count (used by the reduce to skip chunks past an output's last term).
-__device__ __forceinline__ int count_rt(int cls, const Params &p, int o) {
-  switch (cls) {
-    case C_IRC: return cls_count<C_IRC>(p, o);
-    case C_IRR: return cls_count<C_IRR>(p, o);
-    case C_IL: return cls_count<C_IL>(p, o);
-    case C_ITV: return cls_count<C_ITV>(p, o);
-    case C_JR: return cls_count<C_JR>(p, o);
-    case C_JM: return cls_count<C_JM>(p, o);
-    case B_R1: return cls_count<B_R1>(p, o);
-    case B_R2: return cls_count<B_R2>(p, o);
-    case B_R3: return cls_count<B_R3>(p, o);
-    case B_L: return cls_count<B_L>(p, o);
-    case B_T1: return cls_count<B_T1>(p, o);
-    case B_T2: return cls_count<B_T2>(p, o);
-    case G_MAT: return cls_count<G_MAT>(p, o);
+// Weight(s) and streamed block(s) of term t of output o (t inside o's range): returns 1 or 2
+// pairs (c0, P0), (c1, P1).  Two-piece terms are assembled with selects, which keeps the pairs
+// in registers.
+__device__ __forceinline__ int two_pieces(bool va, cd ca, const kbe_c128 *pa, bool vb, cd cb,
+                                          const kbe_c128 *pb, cd &c0, const kbe_c128 *&P0,
+                                          cd &c1, const kbe_c128 *&P1) {
+  c0 = va ? ca : cb;
+  P0 = va ? pa : pb;
+  c1 = cb;
+  P1 = pb;
+  return (va ? 1 : 0) + (vb ? 1 : 0);
+}
+
+template <int CLS>
+__device__ __forceinline__ int cls_P(const Params &p, int o, int t, cd &c0, const kbe_c128 *&P0,
+                                     cd &c1, const kbe_c128 *&P1) {
+  const int64_t E = bsz(p);
+  const int J = p.J, m = p.m0 + o;
+  switch (CLS) {
+    case C_IRC: c0 = {p.w[(int64_t)p.n * p.nt + t], 0.0}; P0 = kp_blk(p, t, m); return 1;
+    case C_IRR: c0 = {-p.w[(int64_t)p.n * p.nt + t], 0.0}; P0 = kp_blk(p, m, t); return 1;
+    case C_IL:
+      c0 = {p.w[(int64_t)m * p.nt + t], 0.0};
+      P0 = t < m ? kp_blk(p, m, t) : p.rdiag + m * E;
+      return 1;
+    case C_ITV: c0 = {0.0, -p.wtau[t]}; P0 = tv_blk(p, m, J - t); return 1;
+    case C_JR: c0 = {p.w[(int64_t)p.n * p.nt + t], 0.0}; P0 = tv_blk(p, t, o); return 1;
+    case C_JM:    // l = t, j = o: [0,tau_j] uses -G^M(beta+tau_l-tau_j), [tau_j,beta] G^M(tau_l-tau_j)
+    case B_T2: {  // j = t, l = o: the same pairs seen from the self-energy side
+      const int l = CLS == C_JM ? t : o, j = CLS == C_JM ? o : t;
+      const bool va = l <= j, vb = l >= j;
+      const cd ca = {va ? -p.wf[(int64_t)j * p.ntau + l] : 0.0, 0.0};
+      const cd cb = {vb ? p.wf[(int64_t)(J - j) * p.ntau + (J - l)] : 0.0, 0.0};
+      return two_pieces(va, ca, p.mat + (va ? J + l - j : 0) * E, vb, cb,
+                        p.mat + (vb ? l - j : 0) * E, c0, P0, c1, P1);
+    }
+    case B_R1: c0 = {p.w[(int64_t)p.n * p.nt + o], 0.0}; P0 = kp_blk(p, o, t); return 1;
+    case B_R2: c0 = {-p.w[(int64_t)p.n * p.nt + o], 0.0}; P0 = kp_blk(p, t, o); return 1;
+    case B_R3: c0 = {p.w[(int64_t)p.n * p.nt + o], 0.0}; P0 = tv_blk(p, o, t); return 1;
+    case B_L:
+      c0 = {p.w[(int64_t)t * p.nt + o], 0.0};
+      P0 = t > o ? kp_blk(p, t, o) : p.rdiag + o * E;
+      return 1;
+    case B_T1: c0 = {0.0, p.wtau[o]}; P0 = tv_blk(p, t, J - o); return 1;
+    case G_MAT: {  // l = t, k = o: pairs with j - l = J - k (l <= k) or l - j = k (l >= k)
+      const int l = t, kk = o;
+      const bool va = l <= kk, vb = l >= kk;
+      const int ja = va ? l + J - kk : 0, jb = vb ? l - kk : 0;
+      const cd ca = {va ? -p.wf[(int64_t)ja * p.ntau + l] : 0.0, 0.0};
+      const cd cb = {vb ? p.wf[(int64_t)(J - jb) * p.ntau + (J - l)] : 0.0, 0.0};
+      return two_pieces(va, ca, p.gJ + ja * E, vb, cb, p.gJ + jb * E, c0, P0, c1, P1);
+    }
   }
   return 0;
+}
+
+__device__ __forceinline__ void range_rt(int cls, const Params &p, int o, int &lo, int &hi) {
+  switch (cls) {
+    case C_IRC: cls_range<C_IRC>(p, o, lo, hi); break;
+    case C_IRR: cls_range<C_IRR>(p, o, lo, hi); break;
+    case C_IL: cls_range<C_IL>(p, o, lo, hi); break;
+    case C_ITV: cls_range<C_ITV>(p, o, lo, hi); break;
+    case C_JR: cls_range<C_JR>(p, o, lo, hi); break;
+    case C_JM: cls_range<C_JM>(p, o, lo, hi); break;
+    case B_R1: cls_range<B_R1>(p, o, lo, hi); break;
+    case B_R2: cls_range<B_R2>(p, o, lo, hi); break;
+    case B_R3: cls_range<B_R3>(p, o, lo, hi); break;
+    case B_L: cls_range<B_L>(p, o, lo, hi); break;
+    case B_T1: cls_range<B_T1>(p, o, lo, hi); break;
+    case B_T2: cls_range<B_T2>(p, o, lo, hi); break;
+    case G_MAT: cls_range<G_MAT>(p, o, lo, hi); break;
+    default: lo = hi = 0;
+  }
 }
 
 // ------------------------------------------------------------------------------------------
-// Generic vector-ALU partial sum of one (output, chunk) task by one wave.  For N*N <= 64 the
-// wave runs G = 64/(N*N) groups of N*N lanes over interleaved terms (lane = one output
-// element) and the groups are summed with cross-lane shuffles; for larger N each lane owns up
-// to 4 elements.
+// Generic vector-ALU task: one output o, terms t in [t0, t1).  For N*N <= 64 the wave runs
+// G = 64/(N*N) groups of N*N lanes over interleaved terms (lane = one output element) and sums
+// the groups with cross-lane shuffles; for larger N each lane owns up to 4 elements.
 // ------------------------------------------------------------------------------------------
 template <int CLS>
 __device__ __forceinline__ void task_generic(const Params &p, int o, int t0, int t1,
@@ -236,22 +186,26 @@ __device__ __forceinline__ void task_generic(const Params &p, int o, int t0, int
   cd acc[4] = {czero(), czero(), czero(), czero()};
   if (g < Gs) {
     for (int t = t0 + g; t < t1; t += Gs) {
-      cd c;
-      const kbe_c128 *Q, *P;
-      cls_term<CLS>(p, o, t, c, Q, P);
+      const kbe_c128 *Q = cls_Q<CLS>(p, t);
+      cd c0, c1;
+      const kbe_c128 *P0, *P1;
+      const int np = cls_P<CLS>(p, o, t, c0, P0, c1, P1);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         if (r >= R) break;
         const int e = E <= 64 ? lane % E : lane + 64 * r;
         if (e >= E) break;
         const int i = e / N, j = e % N;
-        cd s = czero();
-        for (int k = 0; k < N; ++k) {
-          if (OP == OP_N) s = s + ld(Q + i * N + k) * ld(P + k * N + j);
-          else if (OP == OP_H) s = s + ld(Q + i * N + k) * cj(ld(P + j * N + k));
-          else s = s + cj(ld(Q + k * N + i)) * ld(P + k * N + j);
+        for (int u = 0; u < np; ++u) {
+          const kbe_c128 *Pu = u == 0 ? P0 : P1;
+          cd s = czero();
+          for (int k = 0; k < N; ++k) {
+            if (OP == OP_N) s = s + ld(Q + i * N + k) * ld(Pu + k * N + j);
+            else if (OP == OP_H) s = s + ld(Q + i * N + k) * cj(ld(Pu + j * N + k));
+            else s = s + cj(ld(Q + k * N + i)) * ld(Pu + k * N + j);
+          }
+          acc[r] = acc[r] + (u == 0 ? c0 : c1) * s;
         }
-        acc[r] = acc[r] + c * s;
       }
     }
   }
@@ -273,13 +227,15 @@ __device__ __forceinline__ void task_generic(const Params &p, int o, int t0, int
 }
 
 // ------------------------------------------------------------------------------------------
-// FP64 MFMA partial sum (N = 16).  Raw products are accumulated as
-//   rr += A.re B.re, ii += A.im B.im, ri += A.re B.im, ir += A.im B.re
-// with the A/B slots holding, per op (Q' = c Q, or conj(c) Q for OP_HN):
-//   OP_N : A = Q'[l%16][k]   B = P[k][l%16]        -> D = Q'P:      (rr - ii, ri + ir)
-//   OP_H : A = P[l%16][k]    B = Q'[l%16][k] (raw)  -> E = P Q'^dag: (rr + ii, ir - ri), out = E^dag
-//   OP_HN: A = Q'[k][l%16]   B = P[k][l%16]   (raw) -> D = Q'^dag P: (rr + ii, ri - ir)
-// with k = 4*slice + l/16.  D/E layout: lane l holds element (4*(l/16) + r, l%16), r = 0..3.
+// FP64 MFMA task (N = 16): outputs o0..o0+no-1 (no <= MO), terms t in [t0, t1).
+// The weight goes on the streamed block: P' = c P (OP_N, OP_HN) or conj(c) P (OP_H), so that
+//   OP_N : out = sum Q P'        A = Q  (row segments),  B = P' (row slices)
+//   OP_H : out = (sum P' Q^dag)^dag   A = P' (row segments), B = Q^dag (Q row segments)
+//   OP_HN: out = sum Q^dag P'    A = Q^dag (Q row slices),   B = P' (row slices)
+// With (ar, ai) / (br, bi) the parts of the A / B operands and x' = -x for the part that
+// enters with a minus sign, each output keeps  re += ar br - ai bi,  im += ar bi + ai br.
+// D layout of v_mfma_f64_16x16x4 (checked on gfx950): lane l, register r holds element
+// (l/16 + 4*r, l%16).
 // ------------------------------------------------------------------------------------------
 typedef double v4d __attribute__((ext_vector_type(4)));
 
@@ -287,99 +243,159 @@ __device__ __forceinline__ v4d mfma(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-template <int CLS>
-__device__ __forceinline__ void task_mfma16(const Params &p, int o, int t0, int t1, kbe_c128 *out,
-                                            int lane) {
+template <int CLS, int MO>
+__device__ __forceinline__ void task_mfma16(const Params &p, int o0, int no, int t0, int t1,
+                                            kbe_c128 *const *out, int lane) {
   constexpr int OP = cls_op<CLS>();
   const int row = lane & 15, q = lane >> 4;
-  v4d rr = {0, 0, 0, 0}, ii = rr, ri = rr, ir = rr;
   const int offA = row * 16 + q;  // element (row, 4*slice + q): + 4*slice
   const int offB = q * 16 + row;  // element (4*slice + q, row): + 64*slice
+  v4d are[MO], aim[MO];
+  int lo[MO], hi[MO];
+#pragma unroll
+  for (int u = 0; u < MO; ++u) {
+    are[u] = v4d{0, 0, 0, 0};
+    aim[u] = are[u];
+    lo[u] = 0;
+    hi[u] = 0;
+    if (u < no) cls_range<CLS>(p, o0 + u, lo[u], hi[u]);
+  }
   for (int t = t0; t < t1; ++t) {
-    cd c;
-    const kbe_c128 *Q, *P;
-    cls_term<CLS>(p, o, t, c, Q, P);
-    cd a[4], b[4];
+    const kbe_c128 *Q = cls_Q<CLS>(p, t);
+    double qr[4], qi[4], nqi[4];
 #pragma unroll
     for (int sl = 0; sl < 4; ++sl) {
-      if (OP == OP_N) {
-        a[sl] = c * ld(Q + offA + 4 * sl);
-        b[sl] = ld(P + offB + 64 * sl);
-      } else if (OP == OP_H) {
-        a[sl] = ld(P + offA + 4 * sl);
-        b[sl] = c * ld(Q + offA + 4 * sl);
-      } else {
-        a[sl] = cj(c) * ld(Q + offB + 64 * sl);
-        b[sl] = ld(P + offB + 64 * sl);
-      }
+      const cd v = ld(Q + (OP == OP_HN ? offB + 64 * sl : offA + 4 * sl));
+      qr[sl] = v.re;
+      qi[sl] = v.im;
+      nqi[sl] = -v.im;
     }
 #pragma unroll
-    for (int sl = 0; sl < 4; ++sl) {
-      rr = mfma(a[sl].re, b[sl].re, rr);
-      ii = mfma(a[sl].im, b[sl].im, ii);
-      ri = mfma(a[sl].re, b[sl].im, ri);
-      ir = mfma(a[sl].im, b[sl].re, ir);
+    for (int u = 0; u < MO; ++u) {
+      if (u >= no || t < lo[u] || t >= hi[u]) continue;  // wave-uniform
+      cd c0, c1;
+      const kbe_c128 *P0, *P1;
+      const int np = cls_P<CLS>(p, o0 + u, t, c0, P0, c1, P1);
+      if (OP == OP_H) {
+        c0 = cj(c0);
+        c1 = cj(c1);
+      }
+      cd pv[4];
+#pragma unroll
+      for (int sl = 0; sl < 4; ++sl) {
+        const int off = OP == OP_H ? offA + 4 * sl : offB + 64 * sl;
+        pv[sl] = c0 * ld(P0 + off);
+        if (np > 1) pv[sl] = pv[sl] + c1 * ld(P1 + off);
+      }
+#pragma unroll
+      for (int sl = 0; sl < 4; ++sl) {
+        if (OP == OP_N) {  // A = Q, B = P'
+          are[u] = mfma(qr[sl], pv[sl].re, are[u]);
+          are[u] = mfma(nqi[sl], pv[sl].im, are[u]);
+          aim[u] = mfma(qr[sl], pv[sl].im, aim[u]);
+          aim[u] = mfma(qi[sl], pv[sl].re, aim[u]);
+        } else if (OP == OP_H) {  // A = P', B = Q^dag: br = qr, bi = -qi
+          are[u] = mfma(pv[sl].re, qr[sl], are[u]);
+          are[u] = mfma(pv[sl].im, qi[sl], are[u]);
+          aim[u] = mfma(pv[sl].re, nqi[sl], aim[u]);
+          aim[u] = mfma(pv[sl].im, qr[sl], aim[u]);
+        } else {  // A = Q^dag: ar = qr, ai = -qi; B = P'
+          are[u] = mfma(qr[sl], pv[sl].re, are[u]);
+          are[u] = mfma(qi[sl], pv[sl].im, are[u]);
+          aim[u] = mfma(qr[sl], pv[sl].im, aim[u]);
+          aim[u] = mfma(nqi[sl], pv[sl].re, aim[u]);
+        }
+      }
     }
   }
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int i = 4 * q + r;
-    if (OP == OP_N) st(out + i * 16 + row, cd{rr[r] - ii[r], ri[r] + ir[r]});
-    else if (OP == OP_H) st(out + row * 16 + i, cd{rr[r] + ii[r], ri[r] - ir[r]});
-    else st(out + i * 16 + row, cd{rr[r] + ii[r], ri[r] - ir[r]});
+  for (int u = 0; u < MO; ++u) {
+    if (u >= no || hi[u] <= t0 || lo[u] >= t1) continue;  // no term of this chunk: not written
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = q + 4 * r;
+      if (OP == OP_H) st(out[u] + row * 16 + i, cd{are[u][r], -aim[u][r]});
+      else st(out[u] + i * 16 + row, cd{are[u][r], aim[u][r]});
+    }
   }
 }
 
-// One launch covers every class of a call: classes occupy consecutive ranges of the flat task
-// index (task = wave), a class's tasks are (output, chunk) pairs with the chunk fastest.
+// One launch covers every class of a call.  Class k owns workgroups [first_wg[k],
+// first_wg[k+1]) (a multiple of 8 apart); local workgroup lb handles chunk lb % nchunk and
+// output groups 4*(lb / nchunk) + wave, each of MO outputs.
 struct FusedPlan {
-  int ncls, SC;
-  int cls[8], nout[8], nchunk[8];
-  int64_t first[9];  // first task of each class; first[ncls] = total
-  int64_t off[8];    // byte offset of each class's partials in the workspace
+  int ncls, SC, MO;
+  int cls[8], nout[8], nchunk[8], ngroup[8];
+  int64_t first_wg[9];
+  int64_t off[8];  // byte offset of each class's partials [nchunk][nout][N*N] in the workspace
 };
 
 template <bool MFMA, int CLS>
-__device__ __forceinline__ void run_task(const Params &p, const FusedPlan &pl, int k, int64_t loc,
-                                         char *ws, int lane) {
+__device__ __forceinline__ void run_task(const Params &p, const FusedPlan &pl, int k, int64_t lb,
+                                         char *ws, int lane, int wave) {
   const int nch = pl.nchunk[k];
-  const int o = (int)(loc / nch), ch = (int)(loc % nch);
-  const int cnt = cls_count<CLS>(p, o);
-  const int t0 = ch * pl.SC;
-  if (t0 >= cnt) return;  // empty chunk: nothing written, the reduce skips it
-  const int t1 = cnt < t0 + pl.SC ? cnt : t0 + pl.SC;
-  kbe_c128 *out = (kbe_c128 *)(ws + pl.off[k]) + ((int64_t)ch * pl.nout[k] + o) * bsz(p);
-  if (MFMA) task_mfma16<CLS>(p, o, t0, t1, out, lane);
-  else task_generic<CLS>(p, o, t0, t1, out, lane);
+  const int ch = (int)(lb % nch);
+  const int g = (int)(lb / nch) * 4 + wave;
+  if (g >= pl.ngroup[k]) return;
+  const int t0 = ch * pl.SC, t1 = t0 + pl.SC;
+  kbe_c128 *base = (kbe_c128 *)(ws + pl.off[k]);
+  const int64_t E = bsz(p);
+  if (MFMA) {
+    constexpr int MO = 4;
+    const int o0 = g * MO;
+    const int no = pl.nout[k] - o0 < MO ? pl.nout[k] - o0 : MO;
+    int lo = 1 << 30, hi = 0;  // union of the outputs' ranges, clipped to the chunk
+    kbe_c128 *out[MO];
+#pragma unroll
+    for (int u = 0; u < MO; ++u) {
+      out[u] = base + ((int64_t)ch * pl.nout[k] + o0 + (u < no ? u : 0)) * E;
+      if (u < no) {
+        int a, b;
+        cls_range<CLS>(p, o0 + u, a, b);
+        lo = a < lo ? a : lo;
+        hi = b > hi ? b : hi;
+      }
+    }
+    const int a = t0 > lo ? t0 : lo, b = t1 < hi ? t1 : hi;
+    if (a >= b) return;
+    task_mfma16<CLS, MO>(p, o0, no, a, b, out, lane);
+  } else {
+    const int o = g;
+    int lo, hi;
+    cls_range<CLS>(p, o, lo, hi);
+    const int a = t0 > lo ? t0 : lo, b = t1 < hi ? t1 : hi;
+    if (a >= b) return;
+    task_generic<CLS>(p, o, a, b, base + ((int64_t)ch * pl.nout[k] + o) * E, lane);
+  }
 }
 
 template <bool MFMA>
 __global__ void __launch_bounds__(256) stream_fused(Params p, FusedPlan pl, char *ws) {
-  const int lane = threadIdx.x & 63;
-  const int64_t task = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (task >= pl.first[pl.ncls]) return;  // no block-level barriers anywhere below
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t b = blockIdx.x;
+  if (b >= pl.first_wg[pl.ncls]) return;  // no block-level barriers anywhere below
   int k = 0;
-  while (task >= pl.first[k + 1]) ++k;
-  const int64_t loc = task - pl.first[k];
+  while (b >= pl.first_wg[k + 1]) ++k;
+  const int64_t lb = b - pl.first_wg[k];
   switch (pl.cls[k]) {
-    case C_IRC: run_task<MFMA, C_IRC>(p, pl, k, loc, ws, lane); break;
-    case C_IRR: run_task<MFMA, C_IRR>(p, pl, k, loc, ws, lane); break;
-    case C_IL: run_task<MFMA, C_IL>(p, pl, k, loc, ws, lane); break;
-    case C_ITV: run_task<MFMA, C_ITV>(p, pl, k, loc, ws, lane); break;
-    case C_JR: run_task<MFMA, C_JR>(p, pl, k, loc, ws, lane); break;
-    case C_JM: run_task<MFMA, C_JM>(p, pl, k, loc, ws, lane); break;
-    case B_R1: run_task<MFMA, B_R1>(p, pl, k, loc, ws, lane); break;
-    case B_R2: run_task<MFMA, B_R2>(p, pl, k, loc, ws, lane); break;
-    case B_R3: run_task<MFMA, B_R3>(p, pl, k, loc, ws, lane); break;
-    case B_L: run_task<MFMA, B_L>(p, pl, k, loc, ws, lane); break;
-    case B_T1: run_task<MFMA, B_T1>(p, pl, k, loc, ws, lane); break;
-    case B_T2: run_task<MFMA, B_T2>(p, pl, k, loc, ws, lane); break;
-    case G_MAT: run_task<MFMA, G_MAT>(p, pl, k, loc, ws, lane); break;
+    case C_IRC: run_task<MFMA, C_IRC>(p, pl, k, lb, ws, lane, wave); break;
+    case C_IRR: run_task<MFMA, C_IRR>(p, pl, k, lb, ws, lane, wave); break;
+    case C_IL: run_task<MFMA, C_IL>(p, pl, k, lb, ws, lane, wave); break;
+    case C_ITV: run_task<MFMA, C_ITV>(p, pl, k, lb, ws, lane, wave); break;
+    case C_JR: run_task<MFMA, C_JR>(p, pl, k, lb, ws, lane, wave); break;
+    case C_JM: run_task<MFMA, C_JM>(p, pl, k, lb, ws, lane, wave); break;
+    case B_R1: run_task<MFMA, B_R1>(p, pl, k, lb, ws, lane, wave); break;
+    case B_R2: run_task<MFMA, B_R2>(p, pl, k, lb, ws, lane, wave); break;
+    case B_R3: run_task<MFMA, B_R3>(p, pl, k, lb, ws, lane, wave); break;
+    case B_L: run_task<MFMA, B_L>(p, pl, k, lb, ws, lane, wave); break;
+    case B_T1: run_task<MFMA, B_T1>(p, pl, k, lb, ws, lane, wave); break;
+    case B_T2: run_task<MFMA, B_T2>(p, pl, k, lb, ws, lane, wave); break;
+    case G_MAT: run_task<MFMA, G_MAT>(p, pl, k, lb, ws, lane, wave); break;
   }
 }
 
-// out[x] (=|+=) the sum, in increasing chunk order, of the non-empty chunks of up to three
-// classes' partial arrays (chunk c of output o is non-empty when c*SC < count(o)).
+// out[x] (=|+=) the sum, in increasing chunk order, of the chunks of up to three classes'
+// partial arrays that intersect output o's term range.
 struct RedIn {
   const kbe_c128 *a[3];
   int cls[3], nchunk[3];
@@ -394,10 +410,13 @@ __global__ void __launch_bounds__(256) reduce_kernel(Params p, RedIn in, int nou
   const int o = (int)(x / E);
   cd s = czero();
   for (int k = 0; k < in.nparts; ++k) {
-    const int cnt = count_rt(in.cls[k], p, o);
-    int nc = (cnt + in.SC - 1) / in.SC;
-    if (nc > in.nchunk[k]) nc = in.nchunk[k];
-    for (int c = 0; c < nc; ++c) s = s + ld(in.a[k] + (int64_t)c * nel + x);
+    int lo, hi;
+    range_rt(in.cls[k], p, o, lo, hi);
+    if (hi <= lo) continue;
+    const int c0 = lo / in.SC;
+    int c1 = (hi - 1) / in.SC;
+    if (c1 > in.nchunk[k] - 1) c1 = in.nchunk[k] - 1;
+    for (int c = c0; c <= c1; ++c) s = s + ld(in.a[k] + (int64_t)c * nel + x);
   }
   if (accumulate) s = s + ld(out + x);
   st(out + x, s);
@@ -525,7 +544,7 @@ __global__ void __launch_bounds__(256) grad_mfma16(Params p, int64_t nblk) {
   }
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    kbe_c128 *d = dst + (4 * q + r) * 16 + row;
+    kbe_c128 *d = dst + (q + 4 * r) * 16 + row;
     cd v{rr[r] + ii[r], ri[r] - ir[r]};
     if (!p.overwrite) v = v + ld(d);
     st(d, v);
@@ -543,21 +562,24 @@ static int chunk_terms(int N, bool mfma) {
   return E >= 64 ? 256 : (E >= 16 ? 1024 : 4096);
 }
 
-// Add class cls with nout outputs of at most maxcnt terms to the plan (skipped when empty).
-static void plan_add(FusedPlan &pl, int cls, int nout, int maxcnt, int E, size_t &off) {
-  if (nout <= 0 || maxcnt <= 0) return;
+// Add class cls with nout outputs whose term indices lie below tmax (skipped when empty).
+static void plan_add(FusedPlan &pl, int cls, int nout, int tmax, int E, size_t &off) {
+  if (nout <= 0 || tmax <= 0) return;
   const int k = pl.ncls++;
   pl.cls[k] = cls;
   pl.nout[k] = nout;
-  pl.nchunk[k] = (maxcnt + pl.SC - 1) / pl.SC;
+  pl.nchunk[k] = (tmax + pl.SC - 1) / pl.SC;
+  pl.ngroup[k] = (nout + pl.MO - 1) / pl.MO;
   pl.off[k] = (int64_t)off;
-  pl.first[k + 1] = pl.first[k] + (int64_t)nout * pl.nchunk[k];
+  const int64_t wgs = (int64_t)pl.nchunk[k] * ((pl.ngroup[k] + 3) / 4);
+  pl.first_wg[k + 1] = pl.first_wg[k] + (wgs + 7) / 8 * 8;
   off += al256(sizeof(kbe_c128) * (size_t)pl.nchunk[k] * nout * E);
 }
 
 static FusedPlan plan_init(int N, bool mfma) {
   FusedPlan pl{};
   pl.SC = chunk_terms(N, mfma);
+  pl.MO = mfma ? 4 : 1;
   return pl;
 }
 
@@ -569,13 +591,13 @@ static size_t plan_forward(int N, int ntau, int n, int m0, int m1, unsigned flag
   const bool th = ntau > 0;
   if (flags & KBE_OUT_IR) {
     plan_add(pl, C_IRC, M, m1, E, off);
-    plan_add(pl, C_IRR, M, n - m0, E, off);
+    if (n > m0) plan_add(pl, C_IRR, M, n + 1, E, off);
   }
   if (flags & KBE_OUT_IL) plan_add(pl, C_IL, M, m1, E, off);
   if ((flags & KBE_OUT_ITV) && th) plan_add(pl, C_ITV, M, ntau, E, off);
   if ((flags & KBE_OUT_JTV) && th) {
     plan_add(pl, C_JR, ntau, n + 1, E, off);
-    plan_add(pl, C_JM, ntau, ntau + 1, E, off);
+    plan_add(pl, C_JM, ntau, ntau, E, off);
   }
   return off;
 }
@@ -583,20 +605,20 @@ static size_t plan_forward(int N, int ntau, int n, int m0, int m1, unsigned flag
 static size_t plan_adjoint(int N, int ntau, int n, int m0, int m1, unsigned flags, bool mfma,
                            FusedPlan &pl) {
   pl = plan_init(N, mfma);
-  const int E = N * N, M = m1 - m0;
+  const int E = N * N;
   size_t off = 0;
-  const bool th = ntau > 0;
+  const bool th = ntau > 0, M = m1 > m0;
   const bool fITV = (flags & KBE_OUT_ITV) && th, fJTV = (flags & KBE_OUT_JTV) && th;
-  if (flags & KBE_OUT_IR) {
-    plan_add(pl, B_R1, n + 1, M, E, off);
-    plan_add(pl, B_R2, n + 1, M, E, off);
+  if ((flags & KBE_OUT_IR) && M) {
+    plan_add(pl, B_R1, n + 1, m1, E, off);
+    plan_add(pl, B_R2, n + 1, m1, E, off);
   }
   if (fJTV) plan_add(pl, B_R3, n + 1, ntau, E, off);
-  if (flags & KBE_OUT_IL) plan_add(pl, B_L, n + 1, M, E, off);
-  if (fITV) plan_add(pl, B_T1, ntau, M, E, off);
+  if ((flags & KBE_OUT_IL) && M) plan_add(pl, B_L, n + 1, m1, E, off);
+  if (fITV && M) plan_add(pl, B_T1, ntau, m1, E, off);
   if (fJTV) {
-    plan_add(pl, B_T2, ntau, ntau + 1, E, off);
-    plan_add(pl, G_MAT, ntau, ntau + 1, E, off);
+    plan_add(pl, B_T2, ntau, ntau, E, off);
+    plan_add(pl, G_MAT, ntau, ntau, E, off);
   }
   return off;
 }
@@ -617,9 +639,9 @@ size_t collision_vjp_ws_bytes(int N, int nt, int ntau, int n, int m0, int m1, un
 
 static void launch_fused(const Params &p, const FusedPlan &pl, bool mfma, char *ws,
                          hipStream_t st) {
-  const int64_t tasks = pl.first[pl.ncls];
-  if (tasks == 0) return;
-  const dim3 grid((unsigned)((tasks + 3) / 4)), block(256);
+  const int64_t wgs = pl.first_wg[pl.ncls];
+  if (wgs == 0) return;
+  const dim3 grid((unsigned)wgs), block(256);
   if (mfma) hipLaunchKernelGGL(stream_fused<true>, grid, block, 0, st, p, pl, ws);
   else hipLaunchKernelGGL(stream_fused<false>, grid, block, 0, st, p, pl, ws);
 }

@@ -166,12 +166,22 @@ __global__ void __launch_bounds__(256) sigma_row_vjp_kernel(SigVjpArgs v) {
   }
 }
 
-__global__ void gu_reduce_kernel(const double *part, int nblk, int N, double *gu) {
-  const int q = threadIdx.x;
-  if (q >= N) return;
+// Stage 2: gu[q] += sum over blocks of part[b][q].  256 threads: thread (q, r) sums the blocks
+// b = r, r+16, ... in order, then the 16 partial sums of each q are added in a fixed tree.
+__global__ void __launch_bounds__(256) gu_reduce_kernel(const double *part, int nblk, int N,
+                                                        double *gu) {
+  __shared__ double red[16][17];
+  const int q = threadIdx.x & 15, r = threadIdx.x >> 4;
   double acc = 0.0;
-  for (int b = 0; b < nblk; ++b) acc += part[(int64_t)b * N + q];
-  gu[q] += acc;
+  if (q < N)
+    for (int b = r; b < nblk; b += 16) acc += part[(int64_t)b * N + q];
+  red[r][q] = acc;
+  __syncthreads();
+  for (int h = 8; h > 0; h >>= 1) {
+    if (r < h) red[r][q] += red[r + h][q];
+    __syncthreads();
+  }
+  if (r == 0 && q < N) gu[q] += red[0][q];
 }
 
 static int64_t sigma_vjp_blocks(int N, int n, int ntau) {
@@ -196,7 +206,7 @@ hipError_t launch_sigma_row_vjp(const kbe_green *G, const double *u, int n,
   v.part = (double *)ws;
   const int64_t nblk = sigma_vjp_blocks(G->N, n, G->ntau);
   hipLaunchKernelGGL(sigma_row_vjp_kernel, dim3((unsigned)nblk), dim3(256), 0, st, v);
-  hipLaunchKernelGGL(gu_reduce_kernel, dim3(1), dim3(64), 0, st, (const double *)ws, (int)nblk,
+  hipLaunchKernelGGL(gu_reduce_kernel, dim3(1), dim3(256), 0, st, (const double *)ws, (int)nblk,
                      G->N, gu);
   return hipGetLastError();
 }

@@ -9,98 +9,134 @@
 // paper's largest order (20), so here the same equations are posed in the Legendre basis
 // phi_l = P_l(z), z the affine map of [min(x_0,left), max(x_{k-1},right)] onto [-1, 1]
 // (a change of basis: identical solution, condition ~1e6-1e7 at order 20, ~1e2 at order 6).
-// One thread per interval; k <= KBE_KMAX.
+// k <= KBE_KMAX.
 #include "kbe_dev.h"
 #include "kbe_internal.h"
 
 namespace kbe {
 
-__device__ void local_solve(const double *x, int k, double left, double right, double *lam) {
+// One wavefront (a 64-thread workgroup) solves one system: the augmented k x (k+1) matrix lives
+// in LDS and every elimination step is spread over the lanes; the pivot is the first element of
+// largest modulus in row-major order of the trailing block (the order a serial search uses).
+constexpr int KP1 = KBE_KMAX + 1;
+
+struct SolveLds {
+  double A[KBE_KMAX][KP1];
+  double f[KBE_KMAX];
+  double sol[KBE_KMAX];
+  int perm[KBE_KMAX];
+};
+
+__device__ void wave_solve(const double *x, int k, double left, double right, double *lam,
+                           SolveLds &S) {
+  const int lane = threadIdx.x;
   if (k == 1) {
-    lam[0] = right - left;
+    if (lane == 0) lam[0] = right - left;
     return;
   }
   const double lo = fmin(x[0], left), hi = fmax(x[k - 1], right);
   const double c = 0.5 * (lo + hi), h = 0.5 * (hi - lo);
-  double A[KBE_KMAX][KBE_KMAX + 1];
-  int perm[KBE_KMAX];
-  for (int j = 0; j < k; ++j) {  // column j: P_0..P_{k-1} at node j (three-term recurrence)
+  if (lane < k) {  // column j = lane: P_0..P_{k-1} at node j (three-term recurrence)
+    const int j = lane;
     const double z = (x[j] - c) / h;
     double p0 = 1.0, p1 = z;
-    A[0][j] = 1.0;
-    if (k > 1) A[1][j] = z;
+    S.A[0][j] = 1.0;
+    S.A[1][j] = z;
     for (int l = 1; l + 1 < k; ++l) {
       const double p2 = ((2 * l + 1) * z * p1 - l * p0) / (l + 1);
       p0 = p1;
       p1 = p2;
-      A[l + 1][j] = p2;
+      S.A[l + 1][j] = p2;
     }
+    S.perm[j] = j;
   }
-  {  // right-hand side: h * int_{za}^{zb} P_l, with int P_l = (P_{l+1} - P_{l-1}) / (2l+1)
+  if (lane == 63) {  // right-hand side: h * int_{za}^{zb} P_l, int P_l = (P_{l+1} - P_{l-1})/(2l+1)
     const double za = (left - c) / h, zb = (right - c) / h;
-    double a0 = 1.0, a1 = za, b0 = 1.0, b1 = zb;  // P_{l-1}, P_l at za and zb (l = 1)
-    A[0][k] = h * (zb - za);
+    double a0 = 1.0, a1 = za, b0 = 1.0, b1 = zb;
+    S.A[0][k] = h * (zb - za);
     for (int l = 1; l < k; ++l) {
       const double a2 = ((2 * l + 1) * za * a1 - l * a0) / (l + 1);
       const double b2 = ((2 * l + 1) * zb * b1 - l * b0) / (l + 1);
-      A[l][k] = h * ((b2 - b0) - (a2 - a0)) / (2 * l + 1);
+      S.A[l][k] = h * ((b2 - b0) - (a2 - a0)) / (2 * l + 1);
       a0 = a1;
       a1 = a2;
       b0 = b1;
       b1 = b2;
     }
   }
-  for (int j = 0; j < k; ++j) perm[j] = j;
-  for (int s = 0; s < k; ++s) {  // elimination with full pivoting
-    int pr = s, pc = s;
+  __syncthreads();
+  for (int s = 0; s < k; ++s) {
+    const int w = k - s;
     double best = -1.0;
-    for (int r = s; r < k; ++r)
-      for (int cc = s; cc < k; ++cc)
-        if (fabs(A[r][cc]) > best) {
-          best = fabs(A[r][cc]);
-          pr = r;
-          pc = cc;
-        }
+    int bi = 1 << 30;
+    for (int e = lane; e < w * w; e += 64) {  // increasing e: first maximum of this lane
+      const double v = fabs(S.A[s + e / w][s + e % w]);
+      if (v > best) {
+        best = v;
+        bi = e;
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {  // maximum, ties to the smaller index
+      const double ob = __shfl_xor(best, off);
+      const int oi = __shfl_xor(bi, off);
+      if (ob > best || (ob == best && oi < bi)) {
+        best = ob;
+        bi = oi;
+      }
+    }
+    const int pr = s + bi / w, pc = s + bi % w;
     if (pr != s)
-      for (int cc = 0; cc <= k; ++cc) {
-        double tmp = A[s][cc];
-        A[s][cc] = A[pr][cc];
-        A[pr][cc] = tmp;
+      for (int cc = lane; cc <= k; cc += 64) {
+        const double tmp = S.A[s][cc];
+        S.A[s][cc] = S.A[pr][cc];
+        S.A[pr][cc] = tmp;
       }
+    __syncthreads();
     if (pc != s) {
-      for (int r = 0; r < k; ++r) {
-        double tmp = A[r][s];
-        A[r][s] = A[r][pc];
-        A[r][pc] = tmp;
+      for (int r = lane; r < k; r += 64) {
+        const double tmp = S.A[r][s];
+        S.A[r][s] = S.A[r][pc];
+        S.A[r][pc] = tmp;
       }
-      int tp = perm[s];
-      perm[s] = perm[pc];
-      perm[pc] = tp;
+      if (lane == 0) {
+        const int tp = S.perm[s];
+        S.perm[s] = S.perm[pc];
+        S.perm[pc] = tp;
+      }
     }
-    for (int r = s + 1; r < k; ++r) {
-      double f = A[r][s] / A[s][s];
-      for (int cc = s; cc <= k; ++cc) A[r][cc] -= f * A[s][cc];
+    __syncthreads();
+    for (int r = s + 1 + lane; r < k; r += 64) S.f[r] = S.A[r][s] / S.A[s][s];
+    __syncthreads();
+    const int wc = k - s + 1;
+    for (int e = lane; e < (w - 1) * wc; e += 64) {
+      const int r = s + 1 + e / wc, cc = s + e % wc;
+      S.A[r][cc] -= S.f[r] * S.A[s][cc];
     }
+    __syncthreads();
   }
-  double zsol[KBE_KMAX];
-  for (int s = k - 1; s >= 0; --s) {
-    double acc = A[s][k];
-    for (int cc = s + 1; cc < k; ++cc) acc -= A[s][cc] * zsol[cc];
-    zsol[s] = acc / A[s][s];
+  if (lane == 0) {
+    for (int s = k - 1; s >= 0; --s) {
+      double acc = S.A[s][k];
+      for (int cc = s + 1; cc < k; ++cc) acc -= S.A[s][cc] * S.sol[cc];
+      S.sol[s] = acc / S.A[s][s];
+    }
+    for (int s = 0; s < k; ++s) lam[S.perm[s]] = S.sol[s];
   }
-  for (int s = 0; s < k; ++s) lam[perm[s]] = zsol[s];
 }
 
 // lam[p][0..k_p), k_p = min(order[p], p+1), nodes t[p-k_p+1 .. p], interval [t_{p-1}, t_p].
+// One 64-thread workgroup per interval.
 __global__ void __launch_bounds__(64) local_weights_kernel(const double *t, const int32_t *order,
                                                            int nt, double *lam, int32_t *kk) {
-  int p = blockIdx.x * blockDim.x + threadIdx.x + 1;
+  __shared__ SolveLds S;
+  __shared__ double l[KBE_KMAX];
+  const int p = blockIdx.x + 1;
   if (p >= nt) return;
-  int k = order[p] < p + 1 ? order[p] : p + 1;
-  kk[p] = k;
-  double l[KBE_KMAX];
-  local_solve(t + (p - k + 1), k, t[p - 1], t[p], l);
-  for (int j = 0; j < KBE_KMAX; ++j) lam[(int64_t)p * KBE_KMAX + j] = j < k ? l[j] : 0.0;
+  const int k = order[p] < p + 1 ? order[p] : p + 1;
+  if (threadIdx.x == 0) kk[p] = k;
+  wave_solve(t + (p - k + 1), k, t[p - 1], t[p], l, S);
+  __syncthreads();
+  if (threadIdx.x < KBE_KMAX) lam[(int64_t)p * KBE_KMAX + threadIdx.x] = (int)threadIdx.x < k ? l[threadIdx.x] : 0.0;
 }
 
 // Composite rows: w[n][s] = sum over intervals p <= n whose nodes include s of the
@@ -123,18 +159,22 @@ __global__ void __launch_bounds__(256) composite_kernel(const double *lam, const
 }
 
 // Unit-spacing table for the uniform tau grid: tab[kk-1][r][i], the weight of node i
-// (of nodes 0..kk-1) for the interval [r-1, r], r = 1..kk-1.
-__global__ void __launch_bounds__(64) tau_table_kernel(double *tab) {
-  int id = blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= KBE_KMAX * KBE_KMAX) return;
-  int kk = id / KBE_KMAX + 1, r = id % KBE_KMAX;
+// (of nodes 0..kk-1) for the interval [r-1, r], r = 0..kk-1 (r = 0 occurs for kk = 1 only:
+// the single-node rule on the interval that ends at its node).  One wave per (kk, r).
+__global__ void __launch_bounds__(64) tau_table_kernel(double *tab, int K) {
+  __shared__ SolveLds S;
+  __shared__ double l[KBE_KMAX];
+  __shared__ double x[KBE_KMAX];
+  const int id = blockIdx.x;
+  const int kk = id / KBE_KMAX + 1, r = id % KBE_KMAX;
   double *out = tab + ((int64_t)(kk - 1) * KBE_KMAX + r) * KBE_KMAX;
-  for (int i = 0; i < KBE_KMAX; ++i) out[i] = 0.0;
-  if (r < 1 || r >= kk) return;
-  double x[KBE_KMAX], l[KBE_KMAX];
-  for (int i = 0; i < kk; ++i) x[i] = (double)i;
-  local_solve(x, kk, r - 1.0, (double)r, l);
-  for (int i = 0; i < kk; ++i) out[i] = l[i];
+  if (threadIdx.x < KBE_KMAX) out[threadIdx.x] = 0.0;
+  if (kk > K || r >= kk || (r == 0 && kk > 1)) return;  // uniform per workgroup
+  if (threadIdx.x < KBE_KMAX) x[threadIdx.x] = (double)threadIdx.x;
+  __syncthreads();
+  wave_solve(x, kk, r - 1.0, (double)r, l, S);
+  __syncthreads();
+  if ((int)threadIdx.x < kk) out[threadIdx.x] = l[threadIdx.x];
 }
 
 // wf[j][l]: integral over [0, tau_j]; interval p in [1, j] uses kk = min(K, j+1) nodes on the
@@ -194,15 +234,14 @@ hipError_t launch_weights(const kbe_grid *g, double *w, double *wtau, double *wf
   e = hipMemcpyAsync(o_d, g->order, sizeof(int32_t) * nt, hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return e;
   if (nt > 1)
-    hipLaunchKernelGGL(local_weights_kernel, dim3((nt - 1 + 63) / 64), dim3(64), 0, st, t_d, o_d,
-                       nt, lam, kk);
+    hipLaunchKernelGGL(local_weights_kernel, dim3(nt - 1), dim3(64), 0, st, t_d, o_d, nt, lam, kk);
   int64_t tot = (int64_t)nt * nt;
   hipLaunchKernelGGL(composite_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, lam,
                      kk, nt, w);
   if (g->ntau > 0) {
     int ntau = g->ntau;
-    hipLaunchKernelGGL(tau_table_kernel, dim3((KBE_KMAX * KBE_KMAX + 63) / 64), dim3(64), 0, st,
-                       tab);
+    hipLaunchKernelGGL(tau_table_kernel, dim3(KBE_KMAX * KBE_KMAX), dim3(64), 0, st, tab,
+                       g->tau_order);
     int64_t tt = (int64_t)ntau * ntau;
     hipLaunchKernelGGL(tau_fwd_kernel, dim3((unsigned)((tt + 255) / 256)), dim3(256), 0, st, tab,
                        ntau, g->tau_order, g->beta / (ntau - 1), wf);

@@ -31,8 +31,8 @@ class Case:
         t, order = synth.grid(self.seed, self.nt, self.hmin, self.hmax, self.omin, self.omax)
         kp = synth.kp(self.seed, self.N, t, ldt=self.ldt)
         rd = synth.rdiag(self.N, self.nt)
-        tv = synth.tv(self.seed, self.N, self.ntau, t) if self.ntau else None
-        mat = synth.mat(self.seed, self.N, self.ntau) if self.ntau else None
+        tv = synth.tv(self.seed, self.N, self.ntau, t)  # [nt, 0, N, N] without a thermal branch
+        mat = synth.mat(self.seed, self.N, self.ntau)
         return t, order, kp, rd, tv, mat
 
 
