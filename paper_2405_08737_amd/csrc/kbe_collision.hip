@@ -18,12 +18,9 @@
 // holds that chunk's Q blocks.
 //
 // Implementations of a task:
-//   * task_mfma16 (N = 16): FP64 matrix cores.  A 16x16 complex block product is four real
-//     products of four v_mfma_f64_16x16x4 k-slices each; two accumulators per output (real and
-//     imaginary part) with the negated imaginary part of Q prepared once per term.  Operands go
-//     from global memory straight into the MFMA register layouts: the B operand (lane l holds
-//     B[k][l%16], k = 4*slice + l/16) is a contiguous 1 KiB row-slice of a row-major block, the
-//     A operand (lane l holds A[l%16][k]) reads 64-byte row segments.
+//   * task_mfma16 (N = 16): FP64 matrix cores (v_mfma_f64_4x4x4, layout below); two
+//     accumulators per output (real and imaginary part), the negated parts of Q prepared once
+//     per term.  Operands go from global memory straight into the MFMA register layouts.
 //   * task_generic (any N <= 16): vector ALU, one output per wave, one output element per lane,
 //     several terms per wave for small N summed across lanes at the end.
 #include "kbe_dev.h"
@@ -39,23 +36,27 @@ enum Cls {
   C_IL,    // I^<, s <= m:  w[m][s] Sigma^<(s) G^R(m,s)^dagger
   C_ITV,   // I^]:  -i wtau[j] Sigma^](j) tv[m][J-j]^dagger
   C_JR,    // J^] real-time part:  w[n][s] Sigma^R(s) tv[s][j]
-  C_JM,    // J^] Matsubara part, split at tau_j
+  C_JM1,   // J^] Matsubara part on [0, tau_j]:   -wf[j][l] Sigma^](l) G^M(beta + tau_l - tau_j)
+  C_JM2,   // J^] Matsubara part on [tau_j, beta]: wb[j][l] Sigma^](l) G^M(tau_l - tau_j)
   B_R1,    // adjoint: gSigma^R(s) from C_IRC terms
   B_R2,    // adjoint: gSigma^R(s) from C_IRR terms
   B_R3,    // adjoint: gSigma^R(s) from C_JR terms
   B_L,     // adjoint: gSigma^<(s) from C_IL terms
   B_T1,    // adjoint: gSigma^](j) from C_ITV terms
-  B_T2,    // adjoint: gSigma^](l) from C_JM terms
-  G_MAT,   // adjoint: gG^M(k) from C_JM terms
+  B_T2A,   // adjoint: gSigma^](l) from C_JM1 terms
+  B_T2B,   // adjoint: gSigma^](l) from C_JM2 terms
+  G_MAT1,  // adjoint: gG^M(k) from C_JM1 terms
+  G_MAT2,  // adjoint: gG^M(k) from C_JM2 terms
   NCLS
 };
 enum Op { OP_N = 0, OP_H = 1, OP_HN = 2 };
 
 template <int CLS>
 __host__ __device__ constexpr int cls_op() {
-  return (CLS == C_IRR || CLS == C_IL || CLS == C_ITV || CLS == B_R1 || CLS == B_R3 || CLS == B_T2)
+  return (CLS == C_IRR || CLS == C_IL || CLS == C_ITV || CLS == B_R1 || CLS == B_R3 ||
+          CLS == B_T2A || CLS == B_T2B)
              ? OP_H
-             : (CLS == G_MAT ? OP_HN : OP_N);
+             : ((CLS == G_MAT1 || CLS == G_MAT2) ? OP_HN : OP_N);
 }
 
 // Term-index range [lo, hi) of output o.
@@ -68,14 +69,17 @@ __device__ __forceinline__ void cls_range(const Params &p, int o, int &lo, int &
     case C_IL: lo = 0; hi = m + 1; break;
     case C_ITV: lo = 0; hi = p.ntau; break;
     case C_JR: lo = 0; hi = p.n + 1; break;
-    case C_JM: lo = 0; hi = p.ntau; break;
+    case C_JM1: lo = 0; hi = o + 1; break;        // l <= j
+    case C_JM2: lo = o; hi = p.ntau; break;       // l >= j
     case B_R1: lo = o > p.m0 ? o : p.m0; hi = p.m1; break;
     case B_R2: lo = p.m0; hi = o < p.m1 ? o : p.m1; break;
     case B_R3: lo = 0; hi = p.ntau; break;
     case B_L: lo = o > p.m0 ? o : p.m0; hi = p.m1; break;
     case B_T1: lo = p.m0; hi = p.m1; break;
-    case B_T2: lo = 0; hi = p.ntau; break;
-    case G_MAT: lo = 0; hi = p.ntau; break;
+    case B_T2A: lo = o; hi = p.ntau; break;       // output l, terms j >= l
+    case B_T2B: lo = 0; hi = o + 1; break;        // output l, terms j <= l
+    case G_MAT1: lo = 0; hi = o + 1; break;       // output k, terms l <= k
+    case G_MAT2: lo = o; hi = p.ntau; break;      // output k, terms l >= k
   }
 }
 
@@ -86,86 +90,76 @@ __device__ __forceinline__ const kbe_c128 *cls_Q(const Params &p, int t) {
   switch (CLS) {
     case C_IRC: case C_IRR: case C_JR: return p.ret + t * E;
     case C_IL: return p.les + t * E;
-    case C_ITV: case C_JM: case G_MAT: return p.stv + t * E;
+    case C_ITV: case C_JM1: case C_JM2: case G_MAT1: case G_MAT2: return p.stv + t * E;
     case B_R1: case B_R2: return p.gIR + (t - p.m0) * E;
     case B_L: return p.gIL + (t - p.m0) * E;
     case B_T1: return p.gItv + (t - p.m0) * E;
-    case B_R3: case B_T2: return p.gJ + t * E;
+    case B_R3: case B_T2A: case B_T2B: return p.gJ + t * E;
   }
   return nullptr;
 }
 
-// Weight(s) and streamed block(s) of term t of output o (t inside o's range): returns 1 or 2
-// pairs (c0, P0), (c1, P1).  Two-piece terms are assembled with selects, which keeps the pairs
-// in registers.
-__device__ __forceinline__ int two_pieces(bool va, cd ca, const kbe_c128 *pa, bool vb, cd cb,
-                                          const kbe_c128 *pb, cd &c0, const kbe_c128 *&P0,
-                                          cd &c1, const kbe_c128 *&P1) {
-  c0 = va ? ca : cb;
-  P0 = va ? pa : pb;
-  c1 = cb;
-  P1 = pb;
-  return (va ? 1 : 0) + (vb ? 1 : 0);
-}
-
+// Weight c and streamed block P of term t of output o (t inside o's range).
 template <int CLS>
-__device__ __forceinline__ int cls_P(const Params &p, int o, int t, cd &c0, const kbe_c128 *&P0,
-                                     cd &c1, const kbe_c128 *&P1) {
+__device__ __forceinline__ void cls_P(const Params &p, int o, int t, cd &c, const kbe_c128 *&P) {
   const int64_t E = bsz(p);
   const int J = p.J, m = p.m0 + o;
   switch (CLS) {
-    case C_IRC: c0 = {p.w[(int64_t)p.n * p.nt + t], 0.0}; P0 = kp_blk(p, t, m); return 1;
-    case C_IRR: c0 = {-p.w[(int64_t)p.n * p.nt + t], 0.0}; P0 = kp_blk(p, m, t); return 1;
+    case C_IRC: c = {p.w[(int64_t)p.n * p.nt + t], 0.0}; P = kp_blk(p, t, m); break;
+    case C_IRR: c = {-p.w[(int64_t)p.n * p.nt + t], 0.0}; P = kp_blk(p, m, t); break;
     case C_IL:
-      c0 = {p.w[(int64_t)m * p.nt + t], 0.0};
-      P0 = t < m ? kp_blk(p, m, t) : p.rdiag + m * E;
-      return 1;
-    case C_ITV: c0 = {0.0, -p.wtau[t]}; P0 = tv_blk(p, m, J - t); return 1;
-    case C_JR: c0 = {p.w[(int64_t)p.n * p.nt + t], 0.0}; P0 = tv_blk(p, t, o); return 1;
-    case C_JM:    // l = t, j = o: [0,tau_j] uses -G^M(beta+tau_l-tau_j), [tau_j,beta] G^M(tau_l-tau_j)
-    case B_T2: {  // j = t, l = o: the same pairs seen from the self-energy side
-      const int l = CLS == C_JM ? t : o, j = CLS == C_JM ? o : t;
-      const bool va = l <= j, vb = l >= j;
-      const cd ca = {va ? -p.wf[(int64_t)j * p.ntau + l] : 0.0, 0.0};
-      const cd cb = {vb ? p.wf[(int64_t)(J - j) * p.ntau + (J - l)] : 0.0, 0.0};
-      return two_pieces(va, ca, p.mat + (va ? J + l - j : 0) * E, vb, cb,
-                        p.mat + (vb ? l - j : 0) * E, c0, P0, c1, P1);
-    }
-    case B_R1: c0 = {p.w[(int64_t)p.n * p.nt + o], 0.0}; P0 = kp_blk(p, o, t); return 1;
-    case B_R2: c0 = {-p.w[(int64_t)p.n * p.nt + o], 0.0}; P0 = kp_blk(p, t, o); return 1;
-    case B_R3: c0 = {p.w[(int64_t)p.n * p.nt + o], 0.0}; P0 = tv_blk(p, o, t); return 1;
+      c = {p.w[(int64_t)m * p.nt + t], 0.0};
+      P = t < m ? kp_blk(p, m, t) : p.rdiag + m * E;
+      break;
+    case C_ITV: c = {0.0, -p.wtau[t]}; P = tv_blk(p, m, J - t); break;
+    case C_JR: c = {p.w[(int64_t)p.n * p.nt + t], 0.0}; P = tv_blk(p, t, o); break;
+    case C_JM1:  // l = t <= j = o
+      c = {-p.wf[(int64_t)o * p.ntau + t], 0.0};
+      P = p.mat + (J + t - o) * E;
+      break;
+    case C_JM2:  // l = t >= j = o; the rule over [tau_j, beta] is the mirrored forward rule
+      c = {p.wf[(int64_t)(J - o) * p.ntau + (J - t)], 0.0};
+      P = p.mat + (t - o) * E;
+      break;
+    case B_R1: c = {p.w[(int64_t)p.n * p.nt + o], 0.0}; P = kp_blk(p, o, t); break;
+    case B_R2: c = {-p.w[(int64_t)p.n * p.nt + o], 0.0}; P = kp_blk(p, t, o); break;
+    case B_R3: c = {p.w[(int64_t)p.n * p.nt + o], 0.0}; P = tv_blk(p, o, t); break;
     case B_L:
-      c0 = {p.w[(int64_t)t * p.nt + o], 0.0};
-      P0 = t > o ? kp_blk(p, t, o) : p.rdiag + o * E;
-      return 1;
-    case B_T1: c0 = {0.0, p.wtau[o]}; P0 = tv_blk(p, t, J - o); return 1;
-    case G_MAT: {  // l = t, k = o: pairs with j - l = J - k (l <= k) or l - j = k (l >= k)
-      const int l = t, kk = o;
-      const bool va = l <= kk, vb = l >= kk;
-      const int ja = va ? l + J - kk : 0, jb = vb ? l - kk : 0;
-      const cd ca = {va ? -p.wf[(int64_t)ja * p.ntau + l] : 0.0, 0.0};
-      const cd cb = {vb ? p.wf[(int64_t)(J - jb) * p.ntau + (J - l)] : 0.0, 0.0};
-      return two_pieces(va, ca, p.gJ + ja * E, vb, cb, p.gJ + jb * E, c0, P0, c1, P1);
+      c = {p.w[(int64_t)t * p.nt + o], 0.0};
+      P = t > o ? kp_blk(p, t, o) : p.rdiag + o * E;
+      break;
+    case B_T1: c = {0.0, p.wtau[o]}; P = tv_blk(p, t, J - o); break;
+    case B_T2A:  // j = t >= l = o
+      c = {-p.wf[(int64_t)t * p.ntau + o], 0.0};
+      P = p.mat + (J + o - t) * E;
+      break;
+    case B_T2B:  // j = t <= l = o
+      c = {p.wf[(int64_t)(J - t) * p.ntau + (J - o)], 0.0};
+      P = p.mat + (o - t) * E;
+      break;
+    case G_MAT1: {  // l = t <= k = o, j = l + J - k
+      const int j = t + J - o;
+      c = {-p.wf[(int64_t)j * p.ntau + t], 0.0};
+      P = p.gJ + j * E;
+      break;
+    }
+    case G_MAT2: {  // l = t >= k = o, j = l - k
+      const int j = t - o;
+      c = {p.wf[(int64_t)(J - j) * p.ntau + (J - t)], 0.0};
+      P = p.gJ + j * E;
+      break;
     }
   }
-  return 0;
 }
 
 __device__ __forceinline__ void range_rt(int cls, const Params &p, int o, int &lo, int &hi) {
   switch (cls) {
-    case C_IRC: cls_range<C_IRC>(p, o, lo, hi); break;
-    case C_IRR: cls_range<C_IRR>(p, o, lo, hi); break;
-    case C_IL: cls_range<C_IL>(p, o, lo, hi); break;
-    case C_ITV: cls_range<C_ITV>(p, o, lo, hi); break;
-    case C_JR: cls_range<C_JR>(p, o, lo, hi); break;
-    case C_JM: cls_range<C_JM>(p, o, lo, hi); break;
-    case B_R1: cls_range<B_R1>(p, o, lo, hi); break;
-    case B_R2: cls_range<B_R2>(p, o, lo, hi); break;
-    case B_R3: cls_range<B_R3>(p, o, lo, hi); break;
-    case B_L: cls_range<B_L>(p, o, lo, hi); break;
-    case B_T1: cls_range<B_T1>(p, o, lo, hi); break;
-    case B_T2: cls_range<B_T2>(p, o, lo, hi); break;
-    case G_MAT: cls_range<G_MAT>(p, o, lo, hi); break;
+#define KBE_CASE(C) \
+  case C: cls_range<C>(p, o, lo, hi); break;
+    KBE_CASE(C_IRC) KBE_CASE(C_IRR) KBE_CASE(C_IL) KBE_CASE(C_ITV) KBE_CASE(C_JR) KBE_CASE(C_JM1)
+    KBE_CASE(C_JM2) KBE_CASE(B_R1) KBE_CASE(B_R2) KBE_CASE(B_R3) KBE_CASE(B_L) KBE_CASE(B_T1)
+    KBE_CASE(B_T2A) KBE_CASE(B_T2B) KBE_CASE(G_MAT1) KBE_CASE(G_MAT2)
+#undef KBE_CASE
     default: lo = hi = 0;
   }
 }
@@ -187,25 +181,22 @@ __device__ __forceinline__ void task_generic(const Params &p, int o, int t0, int
   if (g < Gs) {
     for (int t = t0 + g; t < t1; t += Gs) {
       const kbe_c128 *Q = cls_Q<CLS>(p, t);
-      cd c0, c1;
-      const kbe_c128 *P0, *P1;
-      const int np = cls_P<CLS>(p, o, t, c0, P0, c1, P1);
+      cd c;
+      const kbe_c128 *P;
+      cls_P<CLS>(p, o, t, c, P);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         if (r >= R) break;
         const int e = E <= 64 ? lane % E : lane + 64 * r;
         if (e >= E) break;
         const int i = e / N, j = e % N;
-        for (int u = 0; u < np; ++u) {
-          const kbe_c128 *Pu = u == 0 ? P0 : P1;
-          cd s = czero();
-          for (int k = 0; k < N; ++k) {
-            if (OP == OP_N) s = s + ld(Q + i * N + k) * ld(Pu + k * N + j);
-            else if (OP == OP_H) s = s + ld(Q + i * N + k) * cj(ld(Pu + j * N + k));
-            else s = s + cj(ld(Q + k * N + i)) * ld(Pu + k * N + j);
-          }
-          acc[r] = acc[r] + (u == 0 ? c0 : c1) * s;
+        cd s = czero();
+        for (int k = 0; k < N; ++k) {
+          if (OP == OP_N) s = s + ld(Q + i * N + k) * ld(P + k * N + j);
+          else if (OP == OP_H) s = s + ld(Q + i * N + k) * cj(ld(P + j * N + k));
+          else s = s + cj(ld(Q + k * N + i)) * ld(P + k * N + j);
         }
+        acc[r] = acc[r] + c * s;
       }
     }
   }
@@ -228,170 +219,292 @@ __device__ __forceinline__ void task_generic(const Params &p, int o, int t0, int
 
 // ------------------------------------------------------------------------------------------
 // FP64 MFMA task (N = 16): outputs o0..o0+no-1 (no <= MO), terms t in [t0, t1).
-// The weight goes on the streamed block: P' = c P (OP_N, OP_HN) or conj(c) P (OP_H), so that
-//   OP_N : out = sum Q P'        A = Q  (row segments),  B = P' (row slices)
-//   OP_H : out = (sum P' Q^dag)^dag   A = P' (row segments), B = Q^dag (Q row segments)
-//   OP_HN: out = sum Q^dag P'    A = Q^dag (Q row slices),   B = P' (row slices)
-// With (ar, ai) / (br, bi) the parts of the A / B operands and x' = -x for the part that
-// enters with a minus sign, each output keeps  re += ar br - ai bi,  im += ar bi + ai br.
-// D layout of v_mfma_f64_16x16x4 (checked on gfx950): lane l, register r holds element
-// (l/16 + 4*r, l%16).
+//
+// Matrix cores: v_mfma_f64_4x4x4 (four independent 4x4x4 blocks per instruction; on gfx950 it
+// sustains about 1.5x the FP64 rate of the 16x16x4 form).  Lane layout (checked with an
+// in-bounds probe on gfx950): A[b][i][k] at lane 4b+i+16k, B[b][k][j] at lane 4b+j+16k,
+// D[b][i][j] at lane 4b+j+16i.  A 16x16x16 product D = A B is cut into tile rows ti and
+// k-chunks kc (4 each); one instruction computes the four tiles (ti, tj = b) of a tile row:
+//   lane l supplies A[4ti + l%4][4kc + l/16] (a 4x4 tile, the same for every b) and
+//   B[4kc + l/16][l%16] (rows 4kc..4kc+3 of B: a contiguous 1 KiB slab of a row-major block),
+// and accumulator ti of lane l holds D[4ti + l/16][l%16].
+//
+// The small operand Q is always A and the streamed block is always B, so the streamed block is
+// read as whole slabs (OP_N, OP_HN) or as 64-byte row segments (OP_H, which needs its columns):
+//   OP_N : A = Q,       B = P'
+//   OP_H : A = Q,       B = P'^dagger,  P' = conj(c) P   (then Q P'^dag = c Q P^dag)
+//   OP_HN: A = Q^dagger, B = P'
+// with P' = c P for OP_N and OP_HN.  Per output: re += ar br - ai bi, im += ar bi + ai br,
+// the needed negated parts of Q being prepared once per term and shared by all outputs.
 // ------------------------------------------------------------------------------------------
-typedef double v4d __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ double mfma4(double a, double b, double c) {
+  return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+}
 
-__device__ __forceinline__ v4d mfma(double a, double b, v4d c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+// Workgroup task on the MFMA path: the 4 waves of a workgroup handle 4 groups of MO = 4
+// consecutive outputs over the same chunk of terms, so they share every Q block.  Each term's
+// Q block is staged once per workgroup in LDS (double-buffered, rows padded to 20 complex
+// numbers so the 4x4 A-tile reads are free of bank conflicts) while every wave prefetches its
+// outputs' streamed slabs for the next term into registers; one barrier per term.
+constexpr int MO_MFMA = 2;
+constexpr int QLD = 20;  // LDS row stride of a staged 16x16 block, in complex numbers
+
+template <int MO>
+struct TermOps {
+  const kbe_c128 *P[MO];
+  cd c[MO];
+  bool on[MO];
+};
+
+template <int MO>
+struct TermP {
+  cd v[4][MO];  // slab value for k-chunk kc of output u
+};
+
+template <int CLS, int MO>
+__device__ __forceinline__ void term_setup(const Params &p, int o0, int t, const int *lo,
+                                           const int *hi, int no, TermOps<MO> &ts) {
+  constexpr int OP = cls_op<CLS>();
+#pragma unroll
+  for (int u = 0; u < MO; ++u) {
+    ts.on[u] = u < no && t >= lo[u] && t < hi[u];
+    ts.c[u] = czero();
+    ts.P[u] = p.rdiag;  // any valid address; not read when the output is off
+    if (ts.on[u]) {
+      cls_P<CLS>(p, o0 + u, t, ts.c[u], ts.P[u]);
+      if (OP == OP_H) ts.c[u] = cj(ts.c[u]);
+    }
+  }
 }
 
 template <int CLS, int MO>
-__device__ __forceinline__ void task_mfma16(const Params &p, int o0, int no, int t0, int t1,
-                                            kbe_c128 *const *out, int lane) {
+__device__ __forceinline__ void term_loadP(const TermOps<MO> &ts, int lk, int lc, TermP<MO> &tp) {
   constexpr int OP = cls_op<CLS>();
-  const int row = lane & 15, q = lane >> 4;
-  const int offA = row * 16 + q;  // element (row, 4*slice + q): + 4*slice
-  const int offB = q * 16 + row;  // element (4*slice + q, row): + 64*slice
-  v4d are[MO], aim[MO];
-  int lo[MO], hi[MO];
 #pragma unroll
-  for (int u = 0; u < MO; ++u) {
-    are[u] = v4d{0, 0, 0, 0};
-    aim[u] = are[u];
-    lo[u] = 0;
-    hi[u] = 0;
-    if (u < no) cls_range<CLS>(p, o0 + u, lo[u], hi[u]);
+  for (int kc = 0; kc < 4; ++kc) {
+    const int pidx = OP == OP_H ? lc * 16 + 4 * kc + lk : (4 * kc + lk) * 16 + lc;
+#pragma unroll
+    for (int u = 0; u < MO; ++u)
+      if (ts.on[u]) tp.v[kc][u] = ld(ts.P[u] + pidx);
   }
-  for (int t = t0; t < t1; ++t) {
-    const kbe_c128 *Q = cls_Q<CLS>(p, t);
-    double qr[4], qi[4], nqi[4];
+}
+
+// Matrix-core work of one term for the wave's outputs; Q is read from the LDS tile qs.
+template <int CLS, int MO>
+__device__ __forceinline__ void term_compute(const TermOps<MO> &ts, const TermP<MO> &tp,
+                                             const cd *qs, int lr, int lk,
+                                             double (&are)[MO][4], double (&aim)[MO][4]) {
+  constexpr int OP = cls_op<CLS>();
 #pragma unroll
-    for (int sl = 0; sl < 4; ++sl) {
-      const cd v = ld(Q + (OP == OP_HN ? offB + 64 * sl : offA + 4 * sl));
-      qr[sl] = v.re;
-      qi[sl] = v.im;
-      nqi[sl] = -v.im;
+  for (int kc = 0; kc < 4; ++kc) {
+    double ar[4], ai[4], an[4];
+#pragma unroll
+    for (int ti = 0; ti < 4; ++ti) {
+      const cd v = OP == OP_HN ? qs[(4 * kc + lk) * QLD + 4 * ti + lr]
+                               : qs[(4 * ti + lr) * QLD + 4 * kc + lk];
+      ar[ti] = v.re;
+      ai[ti] = v.im;
+      an[ti] = OP == OP_H ? -v.re : -v.im;
     }
+    cd pv[MO];
 #pragma unroll
-    for (int u = 0; u < MO; ++u) {
-      if (u >= no || t < lo[u] || t >= hi[u]) continue;  // wave-uniform
-      cd c0, c1;
-      const kbe_c128 *P0, *P1;
-      const int np = cls_P<CLS>(p, o0 + u, t, c0, P0, c1, P1);
-      if (OP == OP_H) {
-        c0 = cj(c0);
-        c1 = cj(c1);
-      }
-      cd pv[4];
+    for (int u = 0; u < MO; ++u) pv[u] = ts.c[u] * tp.v[kc][u];
+    // Four passes over (output, tile row): the two updates of an accumulator are 2*4*MO
+    // instructions apart (back-to-back dependent 4x4x4 updates stall the short pipeline).
+    // re gets (A.re B.re) and (-A.im B.im), im gets (A.re B.im) and (A.im B.re), signs per op.
 #pragma unroll
-      for (int sl = 0; sl < 4; ++sl) {
-        const int off = OP == OP_H ? offA + 4 * sl : offB + 64 * sl;
-        pv[sl] = c0 * ld(P0 + off);
-        if (np > 1) pv[sl] = pv[sl] + c1 * ld(P1 + off);
-      }
+    for (int pass = 0; pass < 4; ++pass) {
 #pragma unroll
-      for (int sl = 0; sl < 4; ++sl) {
-        if (OP == OP_N) {  // A = Q, B = P'
-          are[u] = mfma(qr[sl], pv[sl].re, are[u]);
-          are[u] = mfma(nqi[sl], pv[sl].im, are[u]);
-          aim[u] = mfma(qr[sl], pv[sl].im, aim[u]);
-          aim[u] = mfma(qi[sl], pv[sl].re, aim[u]);
-        } else if (OP == OP_H) {  // A = P', B = Q^dag: br = qr, bi = -qi
-          are[u] = mfma(pv[sl].re, qr[sl], are[u]);
-          are[u] = mfma(pv[sl].im, qi[sl], are[u]);
-          aim[u] = mfma(pv[sl].re, nqi[sl], aim[u]);
-          aim[u] = mfma(pv[sl].im, qr[sl], aim[u]);
-        } else {  // A = Q^dag: ar = qr, ai = -qi; B = P'
-          are[u] = mfma(qr[sl], pv[sl].re, are[u]);
-          are[u] = mfma(qi[sl], pv[sl].im, are[u]);
-          aim[u] = mfma(qr[sl], pv[sl].im, aim[u]);
-          aim[u] = mfma(nqi[sl], pv[sl].re, aim[u]);
+      for (int u = 0; u < MO; ++u) {
+        if (!ts.on[u]) continue;  // wave-uniform
+#pragma unroll
+        for (int ti = 0; ti < 4; ++ti) {
+          if (OP == OP_N) {  // A = Q, B = P'
+            if (pass == 0) are[u][ti] = mfma4(ar[ti], pv[u].re, are[u][ti]);
+            if (pass == 1) aim[u][ti] = mfma4(ar[ti], pv[u].im, aim[u][ti]);
+            if (pass == 2) are[u][ti] = mfma4(an[ti], pv[u].im, are[u][ti]);
+            if (pass == 3) aim[u][ti] = mfma4(ai[ti], pv[u].re, aim[u][ti]);
+          } else if (OP == OP_H) {  // A = Q, B = conj(P'^T): br = pv.re, bi = -pv.im
+            if (pass == 0) are[u][ti] = mfma4(ar[ti], pv[u].re, are[u][ti]);
+            if (pass == 1) aim[u][ti] = mfma4(an[ti], pv[u].im, aim[u][ti]);
+            if (pass == 2) are[u][ti] = mfma4(ai[ti], pv[u].im, are[u][ti]);
+            if (pass == 3) aim[u][ti] = mfma4(ai[ti], pv[u].re, aim[u][ti]);
+          } else {  // A = conj(Q^T): a = (qr, -qi), B = P'
+            if (pass == 0) are[u][ti] = mfma4(ar[ti], pv[u].re, are[u][ti]);
+            if (pass == 1) aim[u][ti] = mfma4(ar[ti], pv[u].im, aim[u][ti]);
+            if (pass == 2) are[u][ti] = mfma4(ai[ti], pv[u].im, are[u][ti]);
+            if (pass == 3) aim[u][ti] = mfma4(an[ti], pv[u].re, aim[u][ti]);
+          }
         }
       }
-    }
-  }
-#pragma unroll
-  for (int u = 0; u < MO; ++u) {
-    if (u >= no || hi[u] <= t0 || lo[u] >= t1) continue;  // no term of this chunk: not written
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = q + 4 * r;
-      if (OP == OP_H) st(out[u] + row * 16 + i, cd{are[u][r], -aim[u][r]});
-      else st(out[u] + i * 16 + row, cd{are[u][r], aim[u][r]});
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
 }
 
-// One launch covers every class of a call.  Class k owns workgroups [first_wg[k],
-// first_wg[k+1]) (a multiple of 8 apart); local workgroup lb handles chunk lb % nchunk and
-// output groups 4*(lb / nchunk) + wave, each of MO outputs.
+// One workgroup = chunk ch x output groups 4*gb .. 4*gb+3.  qbuf: 2 x 16 x QLD complex in LDS.
+// All 256 threads reach every barrier: the term range is uniform over the workgroup.
+template <int CLS>
+__device__ __forceinline__ void wg_task_mfma16(const Params &p, int nout, int ngroup, int ch,
+                                               int gb, int SC, kbe_c128 *base, cd *qbuf,
+                                               int *rng) {
+  constexpr int MO = MO_MFMA;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 3, lk = lane >> 4, lc = lane & 15;
+  const int g = gb * 4 + wave;
+  const int o0 = g * MO;
+  const int no = g < ngroup ? (nout - o0 < MO ? nout - o0 : MO) : 0;
+  int lo[MO], hi[MO];
+  int wlo = 1 << 30, whi = 0;
+#pragma unroll
+  for (int u = 0; u < MO; ++u) {
+    lo[u] = 0;
+    hi[u] = 0;
+    if (u < no) {
+      cls_range<CLS>(p, o0 + u, lo[u], hi[u]);
+      wlo = lo[u] < wlo ? lo[u] : wlo;
+      whi = hi[u] > whi ? hi[u] : whi;
+    }
+  }
+  // workgroup union of the term ranges, clipped to the chunk
+  if (lane == 0) {
+    rng[2 * wave] = wlo;
+    rng[2 * wave + 1] = whi;
+  }
+  __syncthreads();
+  int T0 = 1 << 30, T1 = 0;
+  for (int w = 0; w < 4; ++w) {
+    T0 = rng[2 * w] < T0 ? rng[2 * w] : T0;
+    T1 = rng[2 * w + 1] > T1 ? rng[2 * w + 1] : T1;
+  }
+  T0 = T0 > ch * SC ? T0 : ch * SC;
+  T1 = T1 < (ch + 1) * SC ? T1 : (ch + 1) * SC;
+  double are[MO][4], aim[MO][4];
+#pragma unroll
+  for (int u = 0; u < MO; ++u)
+#pragma unroll
+    for (int ti = 0; ti < 4; ++ti) are[u][ti] = aim[u][ti] = 0.0;
+  if (T0 < T1) {
+    const int qrow = tid >> 4, qcol = tid & 15;  // this thread stages element (qrow, qcol)
+    TermOps<MO> ta, tb;
+    TermP<MO> pa, pb;
+    // prologue: Q(T0) into buffer 0, slabs of T0 into pa
+    qbuf[qrow * QLD + qcol] = ld(cls_Q<CLS>(p, T0) + tid);
+    term_setup<CLS, MO>(p, o0, T0, lo, hi, no, ta);
+    term_loadP<CLS, MO>(ta, lk, lc, pa);
+    for (int t = T0; t < T1; t += 2) {
+      // even term t: compute from (ta, pa, buffer 0); prefetch t+1 into (tb, pb, buffer 1)
+      cd qn = czero();
+      const bool m1 = t + 1 < T1;
+      if (m1) {
+        qn = ld(cls_Q<CLS>(p, t + 1) + tid);
+        term_setup<CLS, MO>(p, o0, t + 1, lo, hi, no, tb);
+        term_loadP<CLS, MO>(tb, lk, lc, pb);
+      }
+      __syncthreads();
+      __builtin_amdgcn_sched_barrier(0);
+      term_compute<CLS, MO>(ta, pa, qbuf, lr, lk, are, aim);
+      if (m1) qbuf[16 * QLD + qrow * QLD + qcol] = qn;
+      if (!m1) break;
+      // odd term t+1: compute from (tb, pb, buffer 1); prefetch t+2 into (ta, pa, buffer 0)
+      const bool m2 = t + 2 < T1;
+      if (m2) {
+        qn = ld(cls_Q<CLS>(p, t + 2) + tid);
+        term_setup<CLS, MO>(p, o0, t + 2, lo, hi, no, ta);
+        term_loadP<CLS, MO>(ta, lk, lc, pa);
+      }
+      __syncthreads();
+      __builtin_amdgcn_sched_barrier(0);
+      term_compute<CLS, MO>(tb, pb, qbuf + 16 * QLD, lr, lk, are, aim);
+      if (m2) qbuf[qrow * QLD + qcol] = qn;
+    }
+  }
+  const int64_t E = bsz(p);
+#pragma unroll
+  for (int u = 0; u < MO; ++u) {
+    if (u >= no || hi[u] <= ch * SC || lo[u] >= (ch + 1) * SC) continue;  // no term: not written
+    kbe_c128 *out = base + ((int64_t)ch * nout + o0 + u) * E;
+#pragma unroll
+    for (int ti = 0; ti < 4; ++ti) st(out + (4 * ti + lk) * 16 + lc, cd{are[u][ti], aim[u][ti]});
+  }
+}
+
+// One persistent launch covers every class of a call.  A task is (class k, chunk ch, output
+// group block gb) with local index lb = gb * nchunk + ch; class k owns task indices
+// [first[k], first[k+1]) (a multiple of 8 apart).  Task i belongs to queue i % 8; workgroup b
+// serves queue b % 8 first (its XCD under round-robin placement, so the tasks of a chunk share
+// one L2) and then steals from the other queues.  Queue heads live in the workspace and are
+// zeroed by a fill kernel before each launch.
 struct FusedPlan {
   int ncls, SC, MO;
-  int cls[8], nout[8], nchunk[8], ngroup[8];
-  int64_t first_wg[9];
-  int64_t off[8];  // byte offset of each class's partials [nchunk][nout][N*N] in the workspace
+  int cls[10], nout[10], nchunk[10], ngroup[10];
+  int64_t first[11];
+  int64_t off[10];  // byte offset of each class's partials [nchunk][nout][N*N] in the workspace
+  int64_t qoff;     // byte offset of the 8 queue heads
 };
 
 template <bool MFMA, int CLS>
 __device__ __forceinline__ void run_task(const Params &p, const FusedPlan &pl, int k, int64_t lb,
-                                         char *ws, int lane, int wave) {
+                                         char *ws, int lane, int wave, cd *qbuf, int *rng) {
   const int nch = pl.nchunk[k];
   const int ch = (int)(lb % nch);
-  const int g = (int)(lb / nch) * 4 + wave;
-  if (g >= pl.ngroup[k]) return;
-  const int t0 = ch * pl.SC, t1 = t0 + pl.SC;
+  const int gb = (int)(lb / nch);
   kbe_c128 *base = (kbe_c128 *)(ws + pl.off[k]);
-  const int64_t E = bsz(p);
   if (MFMA) {
-    constexpr int MO = 4;
-    const int o0 = g * MO;
-    const int no = pl.nout[k] - o0 < MO ? pl.nout[k] - o0 : MO;
-    int lo = 1 << 30, hi = 0;  // union of the outputs' ranges, clipped to the chunk
-    kbe_c128 *out[MO];
-#pragma unroll
-    for (int u = 0; u < MO; ++u) {
-      out[u] = base + ((int64_t)ch * pl.nout[k] + o0 + (u < no ? u : 0)) * E;
-      if (u < no) {
-        int a, b;
-        cls_range<CLS>(p, o0 + u, a, b);
-        lo = a < lo ? a : lo;
-        hi = b > hi ? b : hi;
-      }
-    }
-    const int a = t0 > lo ? t0 : lo, b = t1 < hi ? t1 : hi;
-    if (a >= b) return;
-    task_mfma16<CLS, MO>(p, o0, no, a, b, out, lane);
+    wg_task_mfma16<CLS>(p, pl.nout[k], pl.ngroup[k], ch, gb, pl.SC, base, qbuf, rng);
   } else {
+    const int g = gb * 4 + wave;
+    if (g >= pl.ngroup[k]) return;
+    const int t0 = ch * pl.SC, t1 = t0 + pl.SC;
     const int o = g;
     int lo, hi;
     cls_range<CLS>(p, o, lo, hi);
     const int a = t0 > lo ? t0 : lo, b = t1 < hi ? t1 : hi;
     if (a >= b) return;
-    task_generic<CLS>(p, o, a, b, base + ((int64_t)ch * pl.nout[k] + o) * E, lane);
+    task_generic<CLS>(p, o, a, b, base + ((int64_t)ch * pl.nout[k] + o) * bsz(p), lane);
   }
 }
 
 template <bool MFMA>
 __global__ void __launch_bounds__(256) stream_fused(Params p, FusedPlan pl, char *ws) {
+  __shared__ cd qbuf[MFMA ? 2 * 16 * QLD : 1];
+  __shared__ int rng[8];
+  __shared__ long long s_task;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t b = blockIdx.x;
-  if (b >= pl.first_wg[pl.ncls]) return;  // no block-level barriers anywhere below
-  int k = 0;
-  while (b >= pl.first_wg[k + 1]) ++k;
-  const int64_t lb = b - pl.first_wg[k];
-  switch (pl.cls[k]) {
-    case C_IRC: run_task<MFMA, C_IRC>(p, pl, k, lb, ws, lane, wave); break;
-    case C_IRR: run_task<MFMA, C_IRR>(p, pl, k, lb, ws, lane, wave); break;
-    case C_IL: run_task<MFMA, C_IL>(p, pl, k, lb, ws, lane, wave); break;
-    case C_ITV: run_task<MFMA, C_ITV>(p, pl, k, lb, ws, lane, wave); break;
-    case C_JR: run_task<MFMA, C_JR>(p, pl, k, lb, ws, lane, wave); break;
-    case C_JM: run_task<MFMA, C_JM>(p, pl, k, lb, ws, lane, wave); break;
-    case B_R1: run_task<MFMA, B_R1>(p, pl, k, lb, ws, lane, wave); break;
-    case B_R2: run_task<MFMA, B_R2>(p, pl, k, lb, ws, lane, wave); break;
-    case B_R3: run_task<MFMA, B_R3>(p, pl, k, lb, ws, lane, wave); break;
-    case B_L: run_task<MFMA, B_L>(p, pl, k, lb, ws, lane, wave); break;
-    case B_T1: run_task<MFMA, B_T1>(p, pl, k, lb, ws, lane, wave); break;
-    case B_T2: run_task<MFMA, B_T2>(p, pl, k, lb, ws, lane, wave); break;
-    case G_MAT: run_task<MFMA, G_MAT>(p, pl, k, lb, ws, lane, wave); break;
+  unsigned int *heads = (unsigned int *)(ws + pl.qoff);
+  const int64_t ntask = pl.first[pl.ncls];
+  const int64_t per_q = (ntask + 7) / 8;
+  const int home = blockIdx.x & 7;
+  for (int qi = 0; qi < 8; ++qi) {
+    const int q = (home + qi) & 7;
+    for (;;) {
+      if (threadIdx.x == 0) {
+        const unsigned int j = atomicAdd(heads + q, 1u);
+        s_task = j < per_q ? (long long)j * 8 + q : -1;
+      }
+      __syncthreads();
+      const int64_t task = s_task;
+      __syncthreads();
+      if (task < 0 || task >= ntask) break;  // uniform over the workgroup
+      int k = 0;
+      while (task >= pl.first[k + 1]) ++k;
+      const int64_t lb = task - pl.first[k];
+      switch (pl.cls[k]) {
+#define KBE_CASE(C) \
+  case C: run_task<MFMA, C>(p, pl, k, lb, ws, lane, wave, qbuf, rng); break;
+        KBE_CASE(C_IRC) KBE_CASE(C_IRR) KBE_CASE(C_IL) KBE_CASE(C_ITV) KBE_CASE(C_JR)
+        KBE_CASE(C_JM1) KBE_CASE(C_JM2) KBE_CASE(B_R1) KBE_CASE(B_R2) KBE_CASE(B_R3)
+        KBE_CASE(B_L) KBE_CASE(B_T1) KBE_CASE(B_T2A) KBE_CASE(B_T2B) KBE_CASE(G_MAT1)
+        KBE_CASE(G_MAT2)
+#undef KBE_CASE
+      }
+      __syncthreads();  // LDS tiles and range scratch are reused by the next task
+    }
   }
+}
+
+__global__ void zero_heads(unsigned int *heads) {
+  if (threadIdx.x < 8) heads[threadIdx.x] = 0u;
 }
 
 // out[x] (=|+=) the sum, in increasing chunk order, of the chunks of up to three classes'
@@ -513,6 +626,9 @@ __global__ void __launch_bounds__(256) grad_generic(Params p, int64_t nblk) {
   st(dst + e, s);
 }
 
+// MFMA version (N = 16): one wave per gradient block; each term c X^dag Y is an OP_HN product
+// (A = conj(X'^T) with X' = conj(c) X, B = Y slabs) on v_mfma_f64_4x4x4, laid out as in
+// task_mfma16.
 __global__ void __launch_bounds__(256) grad_mfma16(Params p, int64_t nblk) {
   const int lane = threadIdx.x & 63;
   const int64_t blk = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -523,29 +639,35 @@ __global__ void __launch_bounds__(256) grad_mfma16(Params p, int64_t nblk) {
   kbe_c128 *dst;
   const int nt = grad_terms(p, kind, a, b, t0, t1, dst);
   if (nt == 0) return;
-  const int row = lane & 15, q = lane >> 4;
-  const int offB = q * 16 + row;
-  v4d rr = {0, 0, 0, 0}, ii = rr, ri = rr, ir = rr;
+  const int lr = lane & 3, lk = lane >> 4, lc = lane & 15;
+  double are[4] = {0, 0, 0, 0}, aim[4] = {0, 0, 0, 0};
   for (int u = 0; u < nt; ++u) {
     const GT &tu = u == 0 ? t0 : t1;
-    cd xa[4], yb[4];
+    const cd cx = cj(tu.c);
 #pragma unroll
-    for (int sl = 0; sl < 4; ++sl) {
-      xa[sl] = cj(tu.c) * ld(tu.X + offB + 64 * sl);
-      yb[sl] = ld(tu.Y + offB + 64 * sl);
-    }
+    for (int kc = 0; kc < 4; ++kc) {
+      const cd y = ld(tu.Y + (4 * kc + lk) * 16 + lc);
+      cd x[4];
 #pragma unroll
-    for (int sl = 0; sl < 4; ++sl) {
-      rr = mfma(xa[sl].re, yb[sl].re, rr);
-      ii = mfma(xa[sl].im, yb[sl].im, ii);
-      ri = mfma(xa[sl].re, yb[sl].im, ri);
-      ir = mfma(xa[sl].im, yb[sl].re, ir);
+      for (int ti = 0; ti < 4; ++ti) x[ti] = cx * ld(tu.X + (4 * kc + lk) * 16 + 4 * ti + lr);
+      // dependent updates of an accumulator kept 8 instructions apart
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int ti = 0; ti < 4; ++ti) are[ti] = mfma4(x[ti].re, y.re, are[ti]);
+#pragma unroll
+      for (int ti = 0; ti < 4; ++ti) aim[ti] = mfma4(x[ti].re, y.im, aim[ti]);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int ti = 0; ti < 4; ++ti) are[ti] = mfma4(x[ti].im, y.im, are[ti]);
+#pragma unroll
+      for (int ti = 0; ti < 4; ++ti) aim[ti] = mfma4(-x[ti].im, y.re, aim[ti]);
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    kbe_c128 *d = dst + (q + 4 * r) * 16 + row;
-    cd v{rr[r] + ii[r], ri[r] - ir[r]};
+  for (int ti = 0; ti < 4; ++ti) {
+    kbe_c128 *d = dst + (4 * ti + lk) * 16 + lc;
+    cd v{are[ti], aim[ti]};
     if (!p.overwrite) v = v + ld(d);
     st(d, v);
   }
@@ -571,15 +693,15 @@ static void plan_add(FusedPlan &pl, int cls, int nout, int tmax, int E, size_t &
   pl.nchunk[k] = (tmax + pl.SC - 1) / pl.SC;
   pl.ngroup[k] = (nout + pl.MO - 1) / pl.MO;
   pl.off[k] = (int64_t)off;
-  const int64_t wgs = (int64_t)pl.nchunk[k] * ((pl.ngroup[k] + 3) / 4);
-  pl.first_wg[k + 1] = pl.first_wg[k] + (wgs + 7) / 8 * 8;
+  const int64_t tasks = (int64_t)pl.nchunk[k] * ((pl.ngroup[k] + 3) / 4);
+  pl.first[k + 1] = pl.first[k] + (tasks + 7) / 8 * 8;
   off += al256(sizeof(kbe_c128) * (size_t)pl.nchunk[k] * nout * E);
 }
 
 static FusedPlan plan_init(int N, bool mfma) {
   FusedPlan pl{};
   pl.SC = chunk_terms(N, mfma);
-  pl.MO = mfma ? 4 : 1;
+  pl.MO = mfma ? MO_MFMA : 1;
   return pl;
 }
 
@@ -597,9 +719,11 @@ static size_t plan_forward(int N, int ntau, int n, int m0, int m1, unsigned flag
   if ((flags & KBE_OUT_ITV) && th) plan_add(pl, C_ITV, M, ntau, E, off);
   if ((flags & KBE_OUT_JTV) && th) {
     plan_add(pl, C_JR, ntau, n + 1, E, off);
-    plan_add(pl, C_JM, ntau, ntau, E, off);
+    plan_add(pl, C_JM1, ntau, ntau, E, off);
+    plan_add(pl, C_JM2, ntau, ntau, E, off);
   }
-  return off;
+  pl.qoff = (int64_t)off;
+  return off + 256;
 }
 
 static size_t plan_adjoint(int N, int ntau, int n, int m0, int m1, unsigned flags, bool mfma,
@@ -617,10 +741,13 @@ static size_t plan_adjoint(int N, int ntau, int n, int m0, int m1, unsigned flag
   if ((flags & KBE_OUT_IL) && M) plan_add(pl, B_L, n + 1, m1, E, off);
   if (fITV && M) plan_add(pl, B_T1, ntau, m1, E, off);
   if (fJTV) {
-    plan_add(pl, B_T2, ntau, ntau, E, off);
-    plan_add(pl, G_MAT, ntau, ntau, E, off);
+    plan_add(pl, B_T2A, ntau, ntau, E, off);
+    plan_add(pl, B_T2B, ntau, ntau, E, off);
+    plan_add(pl, G_MAT1, ntau, ntau, E, off);
+    plan_add(pl, G_MAT2, ntau, ntau, E, off);
   }
-  return off;
+  pl.qoff = (int64_t)off;
+  return off + 256;
 }
 
 size_t collision_ws_bytes(int N, int nt, int ntau, int n, int m0, int m1, unsigned flags) {
@@ -637,13 +764,34 @@ size_t collision_vjp_ws_bytes(int N, int nt, int ntau, int n, int m0, int m1, un
   return plan_adjoint(N, ntau, n, m0, m1, flags, mfma, pl);
 }
 
+// Resident workgroups of the persistent kernel on the current device (queried once per
+// device and kernel variant).
+static int persistent_grid(bool mfma) {
+  static int cached[64][2];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 1024;
+  int &c = cached[dev][mfma ? 1 : 0];
+  if (c == 0) {
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
+    hipError_t e = mfma ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stream_fused<true>, 256, 0)
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stream_fused<false>, 256, 0);
+    if (e != hipSuccess || per_cu < 1) per_cu = 1;
+    c = cus * per_cu;
+  }
+  return c;
+}
+
 static void launch_fused(const Params &p, const FusedPlan &pl, bool mfma, char *ws,
                          hipStream_t st) {
-  const int64_t wgs = pl.first_wg[pl.ncls];
-  if (wgs == 0) return;
-  const dim3 grid((unsigned)wgs), block(256);
-  if (mfma) hipLaunchKernelGGL(stream_fused<true>, grid, block, 0, st, p, pl, ws);
-  else hipLaunchKernelGGL(stream_fused<false>, grid, block, 0, st, p, pl, ws);
+  const int64_t ntask = pl.first[pl.ncls];
+  if (ntask == 0) return;
+  hipLaunchKernelGGL(zero_heads, dim3(1), dim3(64), 0, st, (unsigned int *)(ws + pl.qoff));
+  int64_t grid = persistent_grid(mfma);
+  if (grid > ntask) grid = ntask;
+  const dim3 g((unsigned)grid), block(256);
+  if (mfma) hipLaunchKernelGGL(stream_fused<true>, g, block, 0, st, p, pl, ws);
+  else hipLaunchKernelGGL(stream_fused<false>, g, block, 0, st, p, pl, ws);
 }
 
 // Reduce the listed classes (those present in the plan) into out[nout][E].
@@ -676,7 +824,7 @@ hipError_t launch_collision(const Params &p, unsigned flags, kbe_c128 *IR, kbe_c
   if (flags & KBE_OUT_IR) reduce_into(p, pl, {C_IRC, C_IRR}, w, M, IR, false, st);
   if (flags & KBE_OUT_IL) reduce_into(p, pl, {C_IL}, w, M, IL, false, st);
   if (flags & KBE_OUT_ITV) reduce_into(p, pl, {C_ITV}, w, M, Itv, false, st);
-  if ((flags & KBE_OUT_JTV) && p.ntau > 0) reduce_into(p, pl, {C_JR, C_JM}, w, p.ntau, Jtv, false, st);
+  if ((flags & KBE_OUT_JTV) && p.ntau > 0) reduce_into(p, pl, {C_JR, C_JM1, C_JM2}, w, p.ntau, Jtv, false, st);
   return hipGetLastError();
 }
 
@@ -690,7 +838,7 @@ hipError_t launch_collision_vjp(const Params &p, unsigned flags, kbe_c128 *gmat,
   // self-energy gradients: overwritten
   reduce_into(p, pl, {B_R1, B_R2, B_R3}, w, p.n + 1, gS->ret, false, st);
   reduce_into(p, pl, {B_L}, w, p.n + 1, gS->les, false, st);
-  if (p.ntau > 0) reduce_into(p, pl, {B_T1, B_T2}, w, p.ntau, gS->tv, false, st);
+  if (p.ntau > 0) reduce_into(p, pl, {B_T1, B_T2A, B_T2B}, w, p.ntau, gS->tv, false, st);
   // Green's-function gradients
   const int64_t n1 = p.n + 1;
   const int64_t nblk = n1 * n1 + n1 + (p.ntau > 0 ? n1 * p.ntau : 0);
@@ -700,7 +848,7 @@ hipError_t launch_collision_vjp(const Params &p, unsigned flags, kbe_c128 *gmat,
     const int64_t th = nblk * p.N * p.N;
     hipLaunchKernelGGL(grad_generic, dim3((unsigned)((th + 255) / 256)), dim3(256), 0, st, p, nblk);
   }
-  if (p.fJTV) reduce_into(p, pl, {G_MAT}, w, p.ntau, gmat, !p.overwrite, st);
+  if (p.fJTV) reduce_into(p, pl, {G_MAT1, G_MAT2}, w, p.ntau, gmat, !p.overwrite, st);
   return hipGetLastError();
 }
 
