@@ -99,57 +99,79 @@ __device__ __forceinline__ const kbe_c128 *cls_Q(const Params &p, int t) {
   return nullptr;
 }
 
-// Weight c and streamed block P of term t of output o (t inside o's range).
+// Every term weight is a real quadrature weight times a class constant f in {1, -1, i, -i}.
 template <int CLS>
-__device__ __forceinline__ void cls_P(const Params &p, int o, int t, cd &c, const kbe_c128 *&P) {
+__host__ __device__ constexpr int cls_fre() {
+  return (CLS == C_IRR || CLS == C_JM1 || CLS == B_R2 || CLS == B_T2A || CLS == G_MAT1) ? -1
+         : (CLS == C_ITV || CLS == B_T1)                                                 ? 0
+                                                                                         : 1;
+}
+template <int CLS>
+__host__ __device__ constexpr int cls_fim() {
+  return CLS == C_ITV ? -1 : (CLS == B_T1 ? 1 : 0);
+}
+
+// Real weight w (the term weight is f w) and streamed block P of term t of output o (t inside
+// o's range).
+template <int CLS>
+__device__ __forceinline__ void cls_wP(const Params &p, int o, int t, double &w,
+                                       const kbe_c128 *&P) {
   const int64_t E = bsz(p);
   const int J = p.J, m = p.m0 + o;
   switch (CLS) {
-    case C_IRC: c = {p.w[(int64_t)p.n * p.nt + t], 0.0}; P = kp_blk(p, t, m); break;
-    case C_IRR: c = {-p.w[(int64_t)p.n * p.nt + t], 0.0}; P = kp_blk(p, m, t); break;
+    case C_IRC: w = p.w[(int64_t)p.n * p.nt + t]; P = kp_blk(p, t, m); break;
+    case C_IRR: w = p.w[(int64_t)p.n * p.nt + t]; P = kp_blk(p, m, t); break;
     case C_IL:
-      c = {p.w[(int64_t)m * p.nt + t], 0.0};
+      w = p.w[(int64_t)m * p.nt + t];
       P = t < m ? kp_blk(p, m, t) : p.rdiag + m * E;
       break;
-    case C_ITV: c = {0.0, -p.wtau[t]}; P = tv_blk(p, m, J - t); break;
-    case C_JR: c = {p.w[(int64_t)p.n * p.nt + t], 0.0}; P = tv_blk(p, t, o); break;
+    case C_ITV: w = p.wtau[t]; P = tv_blk(p, m, J - t); break;
+    case C_JR: w = p.w[(int64_t)p.n * p.nt + t]; P = tv_blk(p, t, o); break;
     case C_JM1:  // l = t <= j = o
-      c = {-p.wf[(int64_t)o * p.ntau + t], 0.0};
+      w = p.wf[(int64_t)o * p.ntau + t];
       P = p.mat + (J + t - o) * E;
       break;
     case C_JM2:  // l = t >= j = o; the rule over [tau_j, beta] is the mirrored forward rule
-      c = {p.wf[(int64_t)(J - o) * p.ntau + (J - t)], 0.0};
+      w = p.wf[(int64_t)(J - o) * p.ntau + (J - t)];
       P = p.mat + (t - o) * E;
       break;
-    case B_R1: c = {p.w[(int64_t)p.n * p.nt + o], 0.0}; P = kp_blk(p, o, t); break;
-    case B_R2: c = {-p.w[(int64_t)p.n * p.nt + o], 0.0}; P = kp_blk(p, t, o); break;
-    case B_R3: c = {p.w[(int64_t)p.n * p.nt + o], 0.0}; P = tv_blk(p, o, t); break;
+    case B_R1: w = p.w[(int64_t)p.n * p.nt + o]; P = kp_blk(p, o, t); break;
+    case B_R2: w = p.w[(int64_t)p.n * p.nt + o]; P = kp_blk(p, t, o); break;
+    case B_R3: w = p.w[(int64_t)p.n * p.nt + o]; P = tv_blk(p, o, t); break;
     case B_L:
-      c = {p.w[(int64_t)t * p.nt + o], 0.0};
+      w = p.w[(int64_t)t * p.nt + o];
       P = t > o ? kp_blk(p, t, o) : p.rdiag + o * E;
       break;
-    case B_T1: c = {0.0, p.wtau[o]}; P = tv_blk(p, t, J - o); break;
+    case B_T1: w = p.wtau[o]; P = tv_blk(p, t, J - o); break;
     case B_T2A:  // j = t >= l = o
-      c = {-p.wf[(int64_t)t * p.ntau + o], 0.0};
+      w = p.wf[(int64_t)t * p.ntau + o];
       P = p.mat + (J + o - t) * E;
       break;
     case B_T2B:  // j = t <= l = o
-      c = {p.wf[(int64_t)(J - t) * p.ntau + (J - o)], 0.0};
+      w = p.wf[(int64_t)(J - t) * p.ntau + (J - o)];
       P = p.mat + (o - t) * E;
       break;
     case G_MAT1: {  // l = t <= k = o, j = l + J - k
       const int j = t + J - o;
-      c = {-p.wf[(int64_t)j * p.ntau + t], 0.0};
+      w = p.wf[(int64_t)j * p.ntau + t];
       P = p.gJ + j * E;
       break;
     }
     case G_MAT2: {  // l = t >= k = o, j = l - k
       const int j = t - o;
-      c = {p.wf[(int64_t)(J - j) * p.ntau + (J - t)], 0.0};
+      w = p.wf[(int64_t)(J - j) * p.ntau + (J - t)];
       P = p.gJ + j * E;
       break;
     }
   }
+}
+
+// Complex weight c = f w and block P of term t of output o.
+template <int CLS>
+__device__ __forceinline__ void cls_P(const Params &p, int o, int t, cd &c, const kbe_c128 *&P) {
+  double w;
+  cls_wP<CLS>(p, o, t, w, P);
+  c = {cls_fre<CLS>() * w, cls_fim<CLS>() * w};
 }
 
 __device__ __forceinline__ void range_rt(int cls, const Params &p, int o, int &lo, int &hi) {
@@ -252,8 +274,7 @@ constexpr int QLD = 20;  // LDS row stride of a staged 16x16 block, in complex n
 template <int MO>
 struct TermOps {
   const kbe_c128 *P[MO];
-  cd c[MO];
-  bool on[MO];
+  double w[MO];  // real weight; 0 when the output has no such term
 };
 
 template <int MO>
@@ -261,19 +282,18 @@ struct TermP {
   cd v[4][MO];  // slab value for k-chunk kc of output u
 };
 
+// Weights and block addresses of term t for the wave's outputs.  Everything here is wave-uniform
+// (scalar control flow); an output without this term gets weight 0 and a valid dummy block,
+// so loads and products below run unconditionally.  Nothing is computed from the loaded weights
+// here: they are prefetches, first used by term_compute one term later.
 template <int CLS, int MO>
 __device__ __forceinline__ void term_setup(const Params &p, int o0, int t, const int *lo,
                                            const int *hi, int no, TermOps<MO> &ts) {
-  constexpr int OP = cls_op<CLS>();
 #pragma unroll
   for (int u = 0; u < MO; ++u) {
-    ts.on[u] = u < no && t >= lo[u] && t < hi[u];
-    ts.c[u] = czero();
-    ts.P[u] = p.rdiag;  // any valid address; not read when the output is off
-    if (ts.on[u]) {
-      cls_P<CLS>(p, o0 + u, t, ts.c[u], ts.P[u]);
-      if (OP == OP_H) ts.c[u] = cj(ts.c[u]);
-    }
+    ts.w[u] = 0.0;
+    ts.P[u] = p.rdiag;
+    if (u < no && t >= lo[u] && t < hi[u]) cls_wP<CLS>(p, o0 + u, t, ts.w[u], ts.P[u]);
   }
 }
 
@@ -284,9 +304,13 @@ __device__ __forceinline__ void term_loadP(const TermOps<MO> &ts, int lk, int lc
   for (int kc = 0; kc < 4; ++kc) {
     const int pidx = OP == OP_H ? lc * 16 + 4 * kc + lk : (4 * kc + lk) * 16 + lc;
 #pragma unroll
-    for (int u = 0; u < MO; ++u)
-      if (ts.on[u]) tp.v[kc][u] = ld(ts.P[u] + pidx);
+    for (int u = 0; u < MO; ++u) tp.v[kc][u] = ld(ts.P[u] + pidx);
   }
+}
+
+// MFMA with the A operand negated (the f64 forms take negate modifiers).
+__device__ __forceinline__ double mfma4na(double a, double b, double c) {
+  return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 1);
 }
 
 // Matrix-core work of one term for the wave's outputs; Q is read from the LDS tile qs.
@@ -295,20 +319,30 @@ __device__ __forceinline__ void term_compute(const TermOps<MO> &ts, const TermP<
                                              const cd *qs, int lr, int lk,
                                              double (&are)[MO][4], double (&aim)[MO][4]) {
   constexpr int OP = cls_op<CLS>();
+  // B scale: c for OP_N / OP_HN, conj(c) for OP_H, with c = f w, f in {1, -1, i, -i}
+  constexpr int FR = cls_fre<CLS>(), FI = OP == OP_H ? -cls_fim<CLS>() : cls_fim<CLS>();
 #pragma unroll
   for (int kc = 0; kc < 4; ++kc) {
-    double ar[4], ai[4], an[4];
+    double ar[4], ai[4];
 #pragma unroll
     for (int ti = 0; ti < 4; ++ti) {
       const cd v = OP == OP_HN ? qs[(4 * kc + lk) * QLD + 4 * ti + lr]
                                : qs[(4 * ti + lr) * QLD + 4 * kc + lk];
       ar[ti] = v.re;
       ai[ti] = v.im;
-      an[ti] = OP == OP_H ? -v.re : -v.im;
     }
     cd pv[MO];
 #pragma unroll
-    for (int u = 0; u < MO; ++u) pv[u] = ts.c[u] * tp.v[kc][u];
+    for (int u = 0; u < MO; ++u) {
+      const cd x = tp.v[kc][u];
+      if (FI == 0) {
+        const double s = FR * ts.w[u];
+        pv[u] = {s * x.re, s * x.im};
+      } else {  // (FI i) w x
+        const double s = FI * ts.w[u];
+        pv[u] = {-s * x.im, s * x.re};
+      }
+    }
     // Four passes over (output, tile row): the two updates of an accumulator are 2*4*MO
     // instructions apart (back-to-back dependent 4x4x4 updates stall the short pipeline).
     // re gets (A.re B.re) and (-A.im B.im), im gets (A.re B.im) and (A.im B.re), signs per op.
@@ -316,24 +350,23 @@ __device__ __forceinline__ void term_compute(const TermOps<MO> &ts, const TermP<
     for (int pass = 0; pass < 4; ++pass) {
 #pragma unroll
       for (int u = 0; u < MO; ++u) {
-        if (!ts.on[u]) continue;  // wave-uniform
 #pragma unroll
         for (int ti = 0; ti < 4; ++ti) {
           if (OP == OP_N) {  // A = Q, B = P'
             if (pass == 0) are[u][ti] = mfma4(ar[ti], pv[u].re, are[u][ti]);
             if (pass == 1) aim[u][ti] = mfma4(ar[ti], pv[u].im, aim[u][ti]);
-            if (pass == 2) are[u][ti] = mfma4(an[ti], pv[u].im, are[u][ti]);
+            if (pass == 2) are[u][ti] = mfma4na(ai[ti], pv[u].im, are[u][ti]);
             if (pass == 3) aim[u][ti] = mfma4(ai[ti], pv[u].re, aim[u][ti]);
           } else if (OP == OP_H) {  // A = Q, B = conj(P'^T): br = pv.re, bi = -pv.im
             if (pass == 0) are[u][ti] = mfma4(ar[ti], pv[u].re, are[u][ti]);
-            if (pass == 1) aim[u][ti] = mfma4(an[ti], pv[u].im, aim[u][ti]);
+            if (pass == 1) aim[u][ti] = mfma4na(ar[ti], pv[u].im, aim[u][ti]);
             if (pass == 2) are[u][ti] = mfma4(ai[ti], pv[u].im, are[u][ti]);
             if (pass == 3) aim[u][ti] = mfma4(ai[ti], pv[u].re, aim[u][ti]);
           } else {  // A = conj(Q^T): a = (qr, -qi), B = P'
             if (pass == 0) are[u][ti] = mfma4(ar[ti], pv[u].re, are[u][ti]);
             if (pass == 1) aim[u][ti] = mfma4(ar[ti], pv[u].im, aim[u][ti]);
             if (pass == 2) are[u][ti] = mfma4(ai[ti], pv[u].im, are[u][ti]);
-            if (pass == 3) aim[u][ti] = mfma4(an[ti], pv[u].re, aim[u][ti]);
+            if (pass == 3) aim[u][ti] = mfma4na(ai[ti], pv[u].re, aim[u][ti]);
           }
         }
       }
@@ -343,13 +376,16 @@ __device__ __forceinline__ void term_compute(const TermOps<MO> &ts, const TermP<
 }
 
 // One workgroup = chunk ch x output groups 4*gb .. 4*gb+3.  qbuf: 2 x 16 x QLD complex in LDS.
-// All 256 threads reach every barrier: the term range is uniform over the workgroup.
+// All 256 threads reach every barrier: the term range is uniform over the workgroup.  The
+// barriers order LDS only, so the global prefetches of the next term stay in flight across
+// them.
 template <int CLS>
 __device__ __forceinline__ void wg_task_mfma16(const Params &p, int nout, int ngroup, int ch,
                                                int gb, int SC, kbe_c128 *base, cd *qbuf,
                                                int *rng) {
   constexpr int MO = MO_MFMA;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lr = lane & 3, lk = lane >> 4, lc = lane & 15;
   const int g = gb * 4 + wave;
   const int o0 = g * MO;
@@ -371,14 +407,14 @@ __device__ __forceinline__ void wg_task_mfma16(const Params &p, int nout, int ng
     rng[2 * wave] = wlo;
     rng[2 * wave + 1] = whi;
   }
-  __syncthreads();
+  lds_barrier();
   int T0 = 1 << 30, T1 = 0;
   for (int w = 0; w < 4; ++w) {
     T0 = rng[2 * w] < T0 ? rng[2 * w] : T0;
     T1 = rng[2 * w + 1] > T1 ? rng[2 * w + 1] : T1;
   }
-  T0 = T0 > ch * SC ? T0 : ch * SC;
-  T1 = T1 < (ch + 1) * SC ? T1 : (ch + 1) * SC;
+  T0 = __builtin_amdgcn_readfirstlane(T0 > ch * SC ? T0 : ch * SC);
+  T1 = __builtin_amdgcn_readfirstlane(T1 < (ch + 1) * SC ? T1 : (ch + 1) * SC);
   double are[MO][4], aim[MO][4];
 #pragma unroll
   for (int u = 0; u < MO; ++u)
@@ -393,30 +429,26 @@ __device__ __forceinline__ void wg_task_mfma16(const Params &p, int nout, int ng
     term_setup<CLS, MO>(p, o0, T0, lo, hi, no, ta);
     term_loadP<CLS, MO>(ta, lk, lc, pa);
     for (int t = T0; t < T1; t += 2) {
-      // even term t: compute from (ta, pa, buffer 0); prefetch t+1 into (tb, pb, buffer 1)
-      cd qn = czero();
-      const bool m1 = t + 1 < T1;
-      if (m1) {
-        qn = ld(cls_Q<CLS>(p, t + 1) + tid);
-        term_setup<CLS, MO>(p, o0, t + 1, lo, hi, no, tb);
-        term_loadP<CLS, MO>(tb, lk, lc, pb);
-      }
-      __syncthreads();
+      // even term t: compute from (ta, pa, buffer 0); prefetch t+1 into (tb, pb, buffer 1).
+      // The prefetch is unconditional: past the range it re-reads the last term (unused).
+      const int t1 = t + 1 < T1 ? t + 1 : T1 - 1;
+      cd qn = ld(cls_Q<CLS>(p, t1) + tid);
+      term_setup<CLS, MO>(p, o0, t1, lo, hi, no, tb);
+      term_loadP<CLS, MO>(tb, lk, lc, pb);
+      lds_barrier();
       __builtin_amdgcn_sched_barrier(0);
       term_compute<CLS, MO>(ta, pa, qbuf, lr, lk, are, aim);
-      if (m1) qbuf[16 * QLD + qrow * QLD + qcol] = qn;
-      if (!m1) break;
+      qbuf[16 * QLD + qrow * QLD + qcol] = qn;
+      if (t + 1 >= T1) break;
       // odd term t+1: compute from (tb, pb, buffer 1); prefetch t+2 into (ta, pa, buffer 0)
-      const bool m2 = t + 2 < T1;
-      if (m2) {
-        qn = ld(cls_Q<CLS>(p, t + 2) + tid);
-        term_setup<CLS, MO>(p, o0, t + 2, lo, hi, no, ta);
-        term_loadP<CLS, MO>(ta, lk, lc, pa);
-      }
-      __syncthreads();
+      const int t2 = t + 2 < T1 ? t + 2 : T1 - 1;
+      qn = ld(cls_Q<CLS>(p, t2) + tid);
+      term_setup<CLS, MO>(p, o0, t2, lo, hi, no, ta);
+      term_loadP<CLS, MO>(ta, lk, lc, pa);
+      lds_barrier();
       __builtin_amdgcn_sched_barrier(0);
       term_compute<CLS, MO>(tb, pb, qbuf + 16 * QLD, lr, lk, are, aim);
-      if (m2) qbuf[qrow * QLD + qcol] = qn;
+      qbuf[qrow * QLD + qcol] = qn;
     }
   }
   const int64_t E = bsz(p);
@@ -482,9 +514,9 @@ __global__ void __launch_bounds__(256) stream_fused(Params p, FusedPlan pl, char
         const unsigned int j = atomicAdd(heads + q, 1u);
         s_task = j < per_q ? (long long)j * 8 + q : -1;
       }
-      __syncthreads();
+      lds_barrier();
       const int64_t task = s_task;
-      __syncthreads();
+      lds_barrier();
       if (task < 0 || task >= ntask) break;  // uniform over the workgroup
       int k = 0;
       while (task >= pl.first[k + 1]) ++k;
@@ -498,7 +530,7 @@ __global__ void __launch_bounds__(256) stream_fused(Params p, FusedPlan pl, char
         KBE_CASE(G_MAT2)
 #undef KBE_CASE
       }
-      __syncthreads();  // LDS tiles and range scratch are reused by the next task
+      lds_barrier();  // LDS tiles and range scratch are reused by the next task
     }
   }
 }
@@ -626,50 +658,204 @@ __global__ void __launch_bounds__(256) grad_generic(Params p, int64_t nblk) {
   st(dst + e, s);
 }
 
-// MFMA version (N = 16): one wave per gradient block; each term c X^dag Y is an OP_HN product
-// (A = conj(X'^T) with X' = conj(c) X, B = Y slabs) on v_mfma_f64_4x4x4, laid out as in
-// task_mfma16.
-__global__ void __launch_bounds__(256) grad_mfma16(Params p, int64_t nblk) {
-  const int lane = threadIdx.x & 63;
-  const int64_t blk = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (blk >= nblk) return;
-  int kind, a, b;
-  grad_block_index(p, blk, kind, a, b);
-  GT t0, t1;
+// MFMA version (N = 16).  A workgroup owns a segment of one storage row a (the kp row a, then
+// the tv row a, then rdiag[a]).  Every term of that row has the form X^dag (c Y) with X one of
+// four per-row blocks -- Sigma^R(a), gIR(a), gIL(a), gItv(a) -- which are staged once in LDS;
+// the scalar is folded into the streamed Y.  The terms of the segment's blocks (operands,
+// scalars, destination) are resolved once into LDS records.  Each wave walks every fourth block
+// of the segment with the next block's Y prefetched, keeps one accumulator pair per term (so no
+// update depends on the other term's) and uses v_mfma_f64_4x4x4 as in the collision tasks
+// (A = X^dag read from LDS, B = Y slabs).
+constexpr int GSEG = 64;  // blocks per workgroup segment
+
+struct GradTerm {
+  int xid;           // which staged X (0..3); -1: no term
+  cd c;
+  const kbe_c128 *Y;
+};
+
+// Terms of block j of row a: j < n+1 -> kp[a][j]; j < n+1+ntau -> tv[a][j-n-1]; else rdiag[a].
+__device__ __forceinline__ int grad_row_terms(const Params &p, int a, int j, GradTerm &t0,
+                                              GradTerm &t1, kbe_c128 *&dst) {
+  const int64_t E = bsz(p);
+  const int n1 = p.n + 1;
+  const bool ina = a >= p.m0 && a < p.m1;
+  t0.xid = t1.xid = -1;
+  t0.Y = t1.Y = p.ret;
+  t0.c = t1.c = czero();
+  int nt = 0;
+  auto push = [&](int xid, cd c, const kbe_c128 *Y) {
+    if (nt == 0) t0 = GradTerm{xid, c, Y};
+    else t1 = GradTerm{xid, c, Y};
+    ++nt;
+  };
+  if (j < n1) {
+    const int b = j;
+    const bool inb = b >= p.m0 && b < p.m1;
+    dst = p.gkp + ((int64_t)a * p.ldt + b) * E;
+    if (a <= b) {
+      if (p.fIR && inb) push(0, cd{p.w[(int64_t)p.n * p.nt + a], 0.0}, p.gIR + (b - p.m0) * E);
+      if (p.fIR && ina && a < b) push(1, cd{-p.w[(int64_t)p.n * p.nt + b], 0.0}, p.ret + b * E);
+    } else if (p.fIL && ina) {
+      push(2, cd{p.w[(int64_t)a * p.nt + b], 0.0}, p.les + b * E);
+    }
+  } else if (j < n1 + p.ntau) {
+    const int k = j - n1;
+    dst = p.gtv + ((int64_t)a * p.ntau + k) * E;
+    if (p.fJTV) push(0, cd{p.w[(int64_t)p.n * p.nt + a], 0.0}, p.gJ + k * E);
+    if (p.fITV && ina) push(3, cd{0.0, -p.wtau[p.J - k]}, p.stv + (p.J - k) * E);
+  } else {
+    dst = p.grdiag + a * E;
+    if (p.fIL && ina) push(2, cd{p.w[(int64_t)a * p.nt + a], 0.0}, p.les + a * E);
+  }
+  return nt;
+}
+
+// Per-block term record of a segment, built once per workgroup in LDS.
+struct GradRec {
+  const kbe_c128 *y0, *y1;  // Y of term 0 and term 1 (term 0's Y again when there is one term)
   kbe_c128 *dst;
-  const int nt = grad_terms(p, kind, a, b, t0, t1, dst);
-  if (nt == 0) return;
+  double c0r, c0i, c1r, c1i;  // scalars (term 1's are 0 when there is one term)
+  int x0, x1, nt, pad;
+};
+
+__device__ __forceinline__ const kbe_c128 *uniform_ptr(const kbe_c128 *q) {
+  const uint64_t v = (uint64_t)q;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (const kbe_c128 *)(((uint64_t)hi << 32) | lo);
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+grad_mfma16(Params p, int row_len, int nseg) {
+  __shared__ cd xs[4][16 * QLD];
+  __shared__ GradRec rec[GSEG];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 3, lk = lane >> 4, lc = lane & 15;
-  double are[4] = {0, 0, 0, 0}, aim[4] = {0, 0, 0, 0};
-  for (int u = 0; u < nt; ++u) {
-    const GT &tu = u == 0 ? t0 : t1;
-    const cd cx = cj(tu.c);
+  // Workgroups are dealt round-robin to the 8 XCDs; XCD x walks the segment-major range
+  // [x per_xcd, (x+1) per_xcd) of (segment, row) pairs, so the column operands (Y) its L2 holds
+  // belong to about one segment at a time.  The results bypass the caches (streaming stores) so
+  // that they do not evict those operands.
+  const int per_xcd = (int)((gridDim.x + 7) / 8);
+  const int L = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (L >= (p.n + 1) * nseg) return;  // whole workgroup: before any barrier
+  const int seg = L / (p.n + 1), a = L % (p.n + 1);
+  const int64_t E = bsz(p);
+  const bool ina = a >= p.m0 && a < p.m1;
+  {  // stage the row's X blocks: Sigma^R(a), gIR(a), gIL(a), gItv(a) (zeros when absent)
+    const int r = tid >> 4, c = tid & 15;
+    xs[0][r * QLD + c] = ld(p.ret + a * E + tid);
+    xs[1][r * QLD + c] = (p.fIR && ina) ? ld(p.gIR + (a - p.m0) * E + tid) : czero();
+    xs[2][r * QLD + c] = (p.fIL && ina) ? ld(p.gIL + (a - p.m0) * E + tid) : czero();
+    xs[3][r * QLD + c] = (p.fITV && ina) ? ld(p.gItv + (a - p.m0) * E + tid) : czero();
+  }
+  const int j0 = seg * GSEG, len = (j0 + GSEG < row_len ? j0 + GSEG : row_len) - j0;
+  if (tid < GSEG) {
+    GradTerm t0{-1, czero(), p.ret}, t1 = t0;
+    kbe_c128 *d = p.gkp;
+    const int nt = tid < len ? grad_row_terms(p, a, j0 + tid, t0, t1, d) : 0;
+    GradRec &g = rec[tid];
+    g.y0 = t0.Y;
+    g.y1 = nt > 1 ? t1.Y : t0.Y;
+    g.dst = d;
+    g.c0r = t0.c.re;
+    g.c0i = t0.c.im;
+    g.c1r = nt > 1 ? t1.c.re : 0.0;
+    g.c1i = nt > 1 ? t1.c.im : 0.0;
+    g.x0 = t0.xid < 0 ? 0 : t0.xid;
+    g.x1 = nt > 1 ? t1.xid : 0;
+    g.nt = nt;
+  }
+  __syncthreads();
+  cd yn0[4], yn1[4];  // raw Y slabs of the block after the current one
+  // Every record's Y pointers are valid (a block without terms points at Sigma^R(0)), so the
+  // prefetch is unconditional; past the end of the segment it re-reads the last record.
+  auto fetch = [&](int q) {
+    const kbe_c128 *Y0 = uniform_ptr(rec[q].y0), *Y1 = uniform_ptr(rec[q].y1);
 #pragma unroll
     for (int kc = 0; kc < 4; ++kc) {
-      const cd y = ld(tu.Y + (4 * kc + lk) * 16 + lc);
-      cd x[4];
+      yn0[kc] = ldg(Y0 + (4 * kc + lk) * 16 + lc);
+      yn1[kc] = ldg(Y1 + (4 * kc + lk) * 16 + lc);
+    }
+  };
+  // A block's result is held for one iteration and written one 16 x 4 slab per inner step of
+  // the next block, so each wave's stores spread over its products instead of a burst.
+  cd prev[4];
+  kbe_c128 *pdst = nullptr;
+  auto put = [&](int ti) {
+    kbe_c128 *d = pdst + (4 * ti + lk) * 16 + lc;
+    cd v = prev[ti];
+    if (!p.overwrite) v = v + ldg(d);
+    dvec2 w;
+    w.x = v.re;
+    w.y = v.im;
+    __builtin_nontemporal_store(w, (g_dvec2 *)(void *)d);
+  };
+  int q = __builtin_amdgcn_readfirstlane(wave);
+  if (q < len) fetch(q);
+  for (; q < len; q += 4) {
+    const int cnt = __builtin_amdgcn_readfirstlane(rec[q].nt);
+    kbe_c128 *const cdst = (kbe_c128 *)uniform_ptr(rec[q].dst);
+    const cd c0{rec[q].c0r, rec[q].c0i}, c1{rec[q].c1r, rec[q].c1i};
+    const cd *x0 = xs[__builtin_amdgcn_readfirstlane(rec[q].x0)];
+    const cd *x1 = xs[__builtin_amdgcn_readfirstlane(rec[q].x1)];
+    cd y0[4], y1[4];
 #pragma unroll
-      for (int ti = 0; ti < 4; ++ti) x[ti] = cx * ld(tu.X + (4 * kc + lk) * 16 + 4 * ti + lr);
-      // dependent updates of an accumulator kept 8 instructions apart
+    for (int kc = 0; kc < 4; ++kc) {
+      y0[kc] = c0 * yn0[kc];
+      y1[kc] = c1 * yn1[kc];
+    }
+    // issue the next block's loads before this block's products and stores
+    fetch(q + 4 < len ? q + 4 : len - 1);
+    if (cnt == 0) continue;
+    double r0[4] = {0, 0, 0, 0}, i0[4] = {0, 0, 0, 0}, r1[4] = {0, 0, 0, 0}, i1[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) {
+      double ar0[4], ai0[4], ar1[4], ai1[4];
+#pragma unroll
+      for (int ti = 0; ti < 4; ++ti) {  // A = X^dag: A[i][k] = conj(X[k][i])
+        const cd u0 = x0[(4 * kc + lk) * QLD + 4 * ti + lr];
+        const cd u1 = x1[(4 * kc + lk) * QLD + 4 * ti + lr];
+        ar0[ti] = u0.re;
+        ai0[ti] = u0.im;
+        ar1[ti] = u1.re;
+        ai1[ti] = u1.im;
+      }
+      // re += xr yr + xi yi; im += xr yi + xi (-yr) (A = conj(x)); terms keep separate sums
+      const double nr0 = -y0[kc].re, nr1 = -y1[kc].re;
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int ti = 0; ti < 4; ++ti) are[ti] = mfma4(x[ti].re, y.re, are[ti]);
+      for (int ti = 0; ti < 4; ++ti) r0[ti] = mfma4(ar0[ti], y0[kc].re, r0[ti]);
 #pragma unroll
-      for (int ti = 0; ti < 4; ++ti) aim[ti] = mfma4(x[ti].re, y.im, aim[ti]);
+      for (int ti = 0; ti < 4; ++ti) i0[ti] = mfma4(ar0[ti], y0[kc].im, i0[ti]);
+      if (cnt > 1) {
+#pragma unroll
+        for (int ti = 0; ti < 4; ++ti) r1[ti] = mfma4(ar1[ti], y1[kc].re, r1[ti]);
+#pragma unroll
+        for (int ti = 0; ti < 4; ++ti) i1[ti] = mfma4(ar1[ti], y1[kc].im, i1[ti]);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      if (pdst) put(kc);
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int ti = 0; ti < 4; ++ti) are[ti] = mfma4(x[ti].im, y.im, are[ti]);
+      for (int ti = 0; ti < 4; ++ti) r0[ti] = mfma4(ai0[ti], y0[kc].im, r0[ti]);
 #pragma unroll
-      for (int ti = 0; ti < 4; ++ti) aim[ti] = mfma4(-x[ti].im, y.re, aim[ti]);
+      for (int ti = 0; ti < 4; ++ti) i0[ti] = mfma4(ai0[ti], nr0, i0[ti]);
+      if (cnt > 1) {
+#pragma unroll
+        for (int ti = 0; ti < 4; ++ti) r1[ti] = mfma4(ai1[ti], y1[kc].im, r1[ti]);
+#pragma unroll
+        for (int ti = 0; ti < 4; ++ti) i1[ti] = mfma4(ai1[ti], nr1, i1[ti]);
+      }
       __builtin_amdgcn_sched_barrier(0);
     }
-  }
 #pragma unroll
-  for (int ti = 0; ti < 4; ++ti) {
-    kbe_c128 *d = dst + (4 * ti + lk) * 16 + lc;
-    cd v{are[ti], aim[ti]};
-    if (!p.overwrite) v = v + ld(d);
-    st(d, v);
+    for (int ti = 0; ti < 4; ++ti) prev[ti] = cd{r0[ti] + r1[ti], i0[ti] + i1[ti]};
+    pdst = cdst;
+  }
+  if (pdst) {
+#pragma unroll
+    for (int ti = 0; ti < 4; ++ti) put(ti);
   }
 }
 
@@ -843,7 +1029,11 @@ hipError_t launch_collision_vjp(const Params &p, unsigned flags, kbe_c128 *gmat,
   const int64_t n1 = p.n + 1;
   const int64_t nblk = n1 * n1 + n1 + (p.ntau > 0 ? n1 * p.ntau : 0);
   if (mfma) {
-    hipLaunchKernelGGL(grad_mfma16, dim3((unsigned)((nblk + 3) / 4)), dim3(256), 0, st, p, nblk);
+    const int row_len = p.n + 2 + p.ntau;  // kp row, tv row, rdiag
+    const int nseg = (row_len + GSEG - 1) / GSEG;
+    const int64_t tasks = (int64_t)(p.n + 1) * nseg;
+    hipLaunchKernelGGL(grad_mfma16, dim3((unsigned)(8 * ((tasks + 7) / 8))), dim3(256), 0, st,
+                       p, row_len, nseg);
   } else {
     const int64_t th = nblk * p.N * p.N;
     hipLaunchKernelGGL(grad_generic, dim3((unsigned)((th + 255) / 256)), dim3(256), 0, st, p, nblk);

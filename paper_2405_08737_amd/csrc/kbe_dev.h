@@ -20,6 +20,21 @@ __device__ __forceinline__ cd ld(const kbe_c128 *p) {
 __device__ __forceinline__ void st(kbe_c128 *p, cd v) {
   *reinterpret_cast<double2 *>(p) = make_double2(v.re, v.im);
 }
+// The same through a pointer known to address global memory (for pointers rebuilt from integers,
+// e.g. after readfirstlane, whose address space the compiler can no longer infer; a generic
+// pointer would turn the access into a flat one that also counts against the LDS wait counter).
+typedef double __attribute__((ext_vector_type(2))) dvec2;
+typedef __attribute__((address_space(1))) dvec2 g_dvec2;
+__device__ __forceinline__ cd ldg(const kbe_c128 *p) {
+  const dvec2 v = *(const g_dvec2 *)(const void *)p;
+  return {v.x, v.y};
+}
+__device__ __forceinline__ void stg(kbe_c128 *p, cd v) {
+  dvec2 w;
+  w.x = v.re;
+  w.y = v.im;
+  *(g_dvec2 *)(void *)p = w;
+}
 __device__ __forceinline__ cd operator+(cd a, cd b) { return {a.re + b.re, a.im + b.im}; }
 __device__ __forceinline__ cd operator-(cd a, cd b) { return {a.re - b.re, a.im - b.im}; }
 __device__ __forceinline__ cd operator-(cd a) { return {-a.re, -a.im}; }
@@ -29,6 +44,14 @@ __device__ __forceinline__ cd operator*(cd a, cd b) {
 __device__ __forceinline__ cd operator*(double s, cd a) { return {s * a.re, s * a.im}; }
 __device__ __forceinline__ cd cj(cd a) { return {a.re, -a.im}; }
 __device__ __forceinline__ cd czero() { return {0.0, 0.0}; }
+
+// Workgroup barrier that orders LDS accesses only.  __syncthreads() also orders global memory,
+// which makes every wave wait for all of its outstanding global loads (prefetches included).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 
 // Every pointer/size a collision-type kernel can need.  Passed by value.
 struct Params {
