@@ -497,7 +497,9 @@ __device__ __forceinline__ void run_task(const Params &p, const FusedPlan &pl, i
   }
 }
 
-template <bool MFMA>
+// ADJ selects the adjoint classes (B_*, G_MAT*) instead of the forward ones, so the two calls
+// run separate, smaller kernels.
+template <bool MFMA, bool ADJ>
 __global__ void __launch_bounds__(256) stream_fused(Params p, FusedPlan pl, char *ws) {
   __shared__ cd qbuf[MFMA ? 2 * 16 * QLD : 1];
   __shared__ int rng[8];
@@ -521,15 +523,20 @@ __global__ void __launch_bounds__(256) stream_fused(Params p, FusedPlan pl, char
       int k = 0;
       while (task >= pl.first[k + 1]) ++k;
       const int64_t lb = task - pl.first[k];
-      switch (pl.cls[k]) {
 #define KBE_CASE(C) \
   case C: run_task<MFMA, C>(p, pl, k, lb, ws, lane, wave, qbuf, rng); break;
-        KBE_CASE(C_IRC) KBE_CASE(C_IRR) KBE_CASE(C_IL) KBE_CASE(C_ITV) KBE_CASE(C_JR)
-        KBE_CASE(C_JM1) KBE_CASE(C_JM2) KBE_CASE(B_R1) KBE_CASE(B_R2) KBE_CASE(B_R3)
-        KBE_CASE(B_L) KBE_CASE(B_T1) KBE_CASE(B_T2A) KBE_CASE(B_T2B) KBE_CASE(G_MAT1)
-        KBE_CASE(G_MAT2)
-#undef KBE_CASE
+      if (!ADJ) {
+        switch (pl.cls[k]) {
+          KBE_CASE(C_IRC) KBE_CASE(C_IRR) KBE_CASE(C_IL) KBE_CASE(C_ITV) KBE_CASE(C_JR)
+          KBE_CASE(C_JM1) KBE_CASE(C_JM2)
+        }
+      } else {
+        switch (pl.cls[k]) {
+          KBE_CASE(B_R1) KBE_CASE(B_R2) KBE_CASE(B_R3) KBE_CASE(B_L) KBE_CASE(B_T1)
+          KBE_CASE(B_T2A) KBE_CASE(B_T2B) KBE_CASE(G_MAT1) KBE_CASE(G_MAT2)
+        }
       }
+#undef KBE_CASE
       lds_barrier();  // LDS tiles and range scratch are reused by the next task
     }
   }
@@ -952,32 +959,31 @@ size_t collision_vjp_ws_bytes(int N, int nt, int ntau, int n, int m0, int m1, un
 
 // Resident workgroups of the persistent kernel on the current device (queried once per
 // device and kernel variant).
-static int persistent_grid(bool mfma) {
-  static int cached[64][2];
+template <bool MFMA, bool ADJ>
+static int persistent_grid() {
+  static int cached[64];
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 1024;
-  int &c = cached[dev][mfma ? 1 : 0];
+  int &c = cached[dev];
   if (c == 0) {
     int cus = 0, per_cu = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
-    hipError_t e = mfma ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stream_fused<true>, 256, 0)
-                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stream_fused<false>, 256, 0);
+    const hipError_t e =
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stream_fused<MFMA, ADJ>, 256, 0);
     if (e != hipSuccess || per_cu < 1) per_cu = 1;
     c = cus * per_cu;
   }
   return c;
 }
 
-static void launch_fused(const Params &p, const FusedPlan &pl, bool mfma, char *ws,
-                         hipStream_t st) {
+template <bool MFMA, bool ADJ>
+static void launch_fused(const Params &p, const FusedPlan &pl, char *ws, hipStream_t st) {
   const int64_t ntask = pl.first[pl.ncls];
   if (ntask == 0) return;
   hipLaunchKernelGGL(zero_heads, dim3(1), dim3(64), 0, st, (unsigned int *)(ws + pl.qoff));
-  int64_t grid = persistent_grid(mfma);
+  int64_t grid = persistent_grid<MFMA, ADJ>();
   if (grid > ntask) grid = ntask;
-  const dim3 g((unsigned)grid), block(256);
-  if (mfma) hipLaunchKernelGGL(stream_fused<true>, g, block, 0, st, p, pl, ws);
-  else hipLaunchKernelGGL(stream_fused<false>, g, block, 0, st, p, pl, ws);
+  hipLaunchKernelGGL((stream_fused<MFMA, ADJ>), dim3((unsigned)grid), dim3(256), 0, st, p, pl, ws);
 }
 
 // Reduce the listed classes (those present in the plan) into out[nout][E].
@@ -1005,7 +1011,8 @@ hipError_t launch_collision(const Params &p, unsigned flags, kbe_c128 *IR, kbe_c
   FusedPlan pl;
   plan_forward(p.N, p.ntau, p.n, p.m0, p.m1, flags, mfma, pl);
   char *w = (char *)ws;
-  launch_fused(p, pl, mfma, w, st);
+  if (mfma) launch_fused<true, false>(p, pl, w, st);
+  else launch_fused<false, false>(p, pl, w, st);
   const int M = p.m1 - p.m0;
   if (flags & KBE_OUT_IR) reduce_into(p, pl, {C_IRC, C_IRR}, w, M, IR, false, st);
   if (flags & KBE_OUT_IL) reduce_into(p, pl, {C_IL}, w, M, IL, false, st);
@@ -1020,7 +1027,8 @@ hipError_t launch_collision_vjp(const Params &p, unsigned flags, kbe_c128 *gmat,
   FusedPlan pl;
   plan_adjoint(p.N, p.ntau, p.n, p.m0, p.m1, flags, mfma, pl);
   char *w = (char *)ws;
-  launch_fused(p, pl, mfma, w, st);
+  if (mfma) launch_fused<true, true>(p, pl, w, st);
+  else launch_fused<false, true>(p, pl, w, st);
   // self-energy gradients: overwritten
   reduce_into(p, pl, {B_R1, B_R2, B_R3}, w, p.n + 1, gS->ret, false, st);
   reduce_into(p, pl, {B_L}, w, p.n + 1, gS->les, false, st);
