@@ -18,9 +18,9 @@
 // holds that chunk's Q blocks.
 //
 // Implementations of a task:
-//   * task_mfma16 (N = 16): FP64 matrix cores (v_mfma_f64_4x4x4, layout below); two
-//     accumulators per output (real and imaginary part), the negated parts of Q prepared once
-//     per term.  Operands go from global memory straight into the MFMA register layouts.
+//   * wg_task_mfma16 (N = 16): FP64 matrix cores (v_mfma_f64_4x4x4, layout below), three real
+//     products per complex one (three accumulators per output); Q staged in LDS per term,
+//     the streamed blocks prefetched into registers a term ahead.
 //   * task_generic (any N <= 16): vector ALU, one output per wave, one output element per lane,
 //     several terms per wave for small N summed across lanes at the end.
 #include "kbe_dev.h"
@@ -256,8 +256,8 @@ __device__ __forceinline__ void task_generic(const Params &p, int o, int t0, int
 //   OP_N : A = Q,       B = P'
 //   OP_H : A = Q,       B = P'^dagger,  P' = conj(c) P   (then Q P'^dag = c Q P^dag)
 //   OP_HN: A = Q^dagger, B = P'
-// with P' = c P for OP_N and OP_HN.  Per output: re += ar br - ai bi, im += ar bi + ai br,
-// the needed negated parts of Q being prepared once per term and shared by all outputs.
+// with P' = c P for OP_N and OP_HN.  Each complex product is three real ones (see
+// term_compute); the sums of Q's parts are formed once per term and shared by all outputs.
 // ------------------------------------------------------------------------------------------
 __device__ __forceinline__ double mfma4(double a, double b, double c) {
   return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
@@ -316,57 +316,55 @@ __device__ __forceinline__ double mfma4na(double a, double b, double c) {
 // Matrix-core work of one term for the wave's outputs; Q is read from the LDS tile qs.
 template <int CLS, int MO>
 __device__ __forceinline__ void term_compute(const TermOps<MO> &ts, const TermP<MO> &tp,
-                                             const cd *qs, int lr, int lk,
-                                             double (&are)[MO][4], double (&aim)[MO][4]) {
+                                             const cd *qs, int lr, int lk, double (&k1)[MO][4],
+                                             double (&k2)[MO][4], double (&k3)[MO][4]) {
   constexpr int OP = cls_op<CLS>();
   // B scale: c for OP_N / OP_HN, conj(c) for OP_H, with c = f w, f in {1, -1, i, -i}
   constexpr int FR = cls_fre<CLS>(), FI = OP == OP_H ? -cls_fim<CLS>() : cls_fim<CLS>();
 #pragma unroll
   for (int kc = 0; kc < 4; ++kc) {
-    double ar[4], ai[4];
+    // operands a = (ar, sa ai), b = (br, sb bi): sa = -1 for OP_HN (A = Q^dag), sb = -1 for
+    // OP_H (B = P^dag); the product takes three real MFMA products (Gauss):
+    //   k1 += (ar + sa ai) br,  k2 += ar (sb bi - br),  k3 += (sa ai) (br + sb bi),
+    //   Re = k1 - k3, Im = k1 + k2.
+    double ar[4], ai[4], as[4];
 #pragma unroll
     for (int ti = 0; ti < 4; ++ti) {
       const cd v = OP == OP_HN ? qs[(4 * kc + lk) * QLD + 4 * ti + lr]
                                : qs[(4 * ti + lr) * QLD + 4 * kc + lk];
       ar[ti] = v.re;
       ai[ti] = v.im;
+      as[ti] = OP == OP_HN ? v.re - v.im : v.re + v.im;
     }
-    cd pv[MO];
+    double br[MO], bd[MO], bp[MO];
 #pragma unroll
     for (int u = 0; u < MO; ++u) {
       const cd x = tp.v[kc][u];
+      cd pv;
       if (FI == 0) {
         const double s = FR * ts.w[u];
-        pv[u] = {s * x.re, s * x.im};
+        pv = {s * x.re, s * x.im};
       } else {  // (FI i) w x
         const double s = FI * ts.w[u];
-        pv[u] = {-s * x.im, s * x.re};
+        pv = {-s * x.im, s * x.re};
       }
+      const double bi = OP == OP_H ? -pv.im : pv.im;
+      br[u] = pv.re;
+      bd[u] = bi - pv.re;
+      bp[u] = pv.re + bi;
     }
-    // Four passes over (output, tile row): the two updates of an accumulator are 2*4*MO
-    // instructions apart (back-to-back dependent 4x4x4 updates stall the short pipeline).
-    // re gets (A.re B.re) and (-A.im B.im), im gets (A.re B.im) and (A.im B.re), signs per op.
+    // three passes over (output, tile row): an accumulator's updates are 4*MO instructions apart
 #pragma unroll
-    for (int pass = 0; pass < 4; ++pass) {
+    for (int pass = 0; pass < 3; ++pass) {
 #pragma unroll
       for (int u = 0; u < MO; ++u) {
 #pragma unroll
         for (int ti = 0; ti < 4; ++ti) {
-          if (OP == OP_N) {  // A = Q, B = P'
-            if (pass == 0) are[u][ti] = mfma4(ar[ti], pv[u].re, are[u][ti]);
-            if (pass == 1) aim[u][ti] = mfma4(ar[ti], pv[u].im, aim[u][ti]);
-            if (pass == 2) are[u][ti] = mfma4na(ai[ti], pv[u].im, are[u][ti]);
-            if (pass == 3) aim[u][ti] = mfma4(ai[ti], pv[u].re, aim[u][ti]);
-          } else if (OP == OP_H) {  // A = Q, B = conj(P'^T): br = pv.re, bi = -pv.im
-            if (pass == 0) are[u][ti] = mfma4(ar[ti], pv[u].re, are[u][ti]);
-            if (pass == 1) aim[u][ti] = mfma4na(ar[ti], pv[u].im, aim[u][ti]);
-            if (pass == 2) are[u][ti] = mfma4(ai[ti], pv[u].im, are[u][ti]);
-            if (pass == 3) aim[u][ti] = mfma4(ai[ti], pv[u].re, aim[u][ti]);
-          } else {  // A = conj(Q^T): a = (qr, -qi), B = P'
-            if (pass == 0) are[u][ti] = mfma4(ar[ti], pv[u].re, are[u][ti]);
-            if (pass == 1) aim[u][ti] = mfma4(ar[ti], pv[u].im, aim[u][ti]);
-            if (pass == 2) are[u][ti] = mfma4(ai[ti], pv[u].im, are[u][ti]);
-            if (pass == 3) aim[u][ti] = mfma4na(ai[ti], pv[u].re, aim[u][ti]);
+          if (pass == 0) k1[u][ti] = mfma4(as[ti], br[u], k1[u][ti]);
+          if (pass == 1) k2[u][ti] = mfma4(ar[ti], bd[u], k2[u][ti]);
+          if (pass == 2) {
+            if (OP == OP_HN) k3[u][ti] = mfma4na(ai[ti], bp[u], k3[u][ti]);
+            else k3[u][ti] = mfma4(ai[ti], bp[u], k3[u][ti]);
           }
         }
       }
@@ -415,11 +413,11 @@ __device__ __forceinline__ void wg_task_mfma16(const Params &p, int nout, int ng
   }
   T0 = __builtin_amdgcn_readfirstlane(T0 > ch * SC ? T0 : ch * SC);
   T1 = __builtin_amdgcn_readfirstlane(T1 < (ch + 1) * SC ? T1 : (ch + 1) * SC);
-  double are[MO][4], aim[MO][4];
+  double k1[MO][4], k2[MO][4], k3[MO][4];
 #pragma unroll
   for (int u = 0; u < MO; ++u)
 #pragma unroll
-    for (int ti = 0; ti < 4; ++ti) are[u][ti] = aim[u][ti] = 0.0;
+    for (int ti = 0; ti < 4; ++ti) k1[u][ti] = k2[u][ti] = k3[u][ti] = 0.0;
   if (T0 < T1) {
     const int qrow = tid >> 4, qcol = tid & 15;  // this thread stages element (qrow, qcol)
     TermOps<MO> ta, tb;
@@ -437,7 +435,7 @@ __device__ __forceinline__ void wg_task_mfma16(const Params &p, int nout, int ng
       term_loadP<CLS, MO>(tb, lk, lc, pb);
       lds_barrier();
       __builtin_amdgcn_sched_barrier(0);
-      term_compute<CLS, MO>(ta, pa, qbuf, lr, lk, are, aim);
+      term_compute<CLS, MO>(ta, pa, qbuf, lr, lk, k1, k2, k3);
       qbuf[16 * QLD + qrow * QLD + qcol] = qn;
       if (t + 1 >= T1) break;
       // odd term t+1: compute from (tb, pb, buffer 1); prefetch t+2 into (ta, pa, buffer 0)
@@ -447,7 +445,7 @@ __device__ __forceinline__ void wg_task_mfma16(const Params &p, int nout, int ng
       term_loadP<CLS, MO>(ta, lk, lc, pa);
       lds_barrier();
       __builtin_amdgcn_sched_barrier(0);
-      term_compute<CLS, MO>(tb, pb, qbuf + 16 * QLD, lr, lk, are, aim);
+      term_compute<CLS, MO>(tb, pb, qbuf + 16 * QLD, lr, lk, k1, k2, k3);
       qbuf[qrow * QLD + qcol] = qn;
     }
   }
@@ -457,7 +455,8 @@ __device__ __forceinline__ void wg_task_mfma16(const Params &p, int nout, int ng
     if (u >= no || hi[u] <= ch * SC || lo[u] >= (ch + 1) * SC) continue;  // no term: not written
     kbe_c128 *out = base + ((int64_t)ch * nout + o0 + u) * E;
 #pragma unroll
-    for (int ti = 0; ti < 4; ++ti) st(out + (4 * ti + lk) * 16 + lc, cd{are[u][ti], aim[u][ti]});
+    for (int ti = 0; ti < 4; ++ti)
+      st(out + (4 * ti + lk) * 16 + lc, cd{k1[u][ti] - k3[u][ti], k1[u][ti] + k2[u][ti]});
   }
 }
 
@@ -672,7 +671,7 @@ __global__ void __launch_bounds__(256) grad_generic(Params p, int64_t nblk) {
 // scalars, destination) are resolved once into LDS records.  Each wave walks every fourth block
 // of the segment with the next block's Y prefetched, keeps one accumulator pair per term (so no
 // update depends on the other term's) and uses v_mfma_f64_4x4x4 as in the collision tasks
-// (A = X^dag read from LDS, B = Y slabs).
+// (A = X^dag read from LDS, B = Y slabs), three real products per complex one.
 constexpr int GSEG = 64;  // blocks per workgroup segment
 
 struct GradTerm {
@@ -815,49 +814,40 @@ grad_mfma16(Params p, int row_len, int nseg) {
     // issue the next block's loads before this block's products and stores
     fetch(q + 4 < len ? q + 4 : len - 1);
     if (cnt == 0) continue;
-    double r0[4] = {0, 0, 0, 0}, i0[4] = {0, 0, 0, 0}, r1[4] = {0, 0, 0, 0}, i1[4] = {0, 0, 0, 0};
+    // Three real products per complex one (Gauss): with A = conj(X), for each k-chunk
+    //   K1 += (xr - xi) yr,   K2 += xr (yi - yr),   K3 += xi (yr + yi);
+    // then Re = K1 + K3 and Im = K1 + K2.  Both terms of the block share the accumulators.
+    double k1[4] = {0, 0, 0, 0}, k2[4] = {0, 0, 0, 0}, k3[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int kc = 0; kc < 4; ++kc) {
-      double ar0[4], ai0[4], ar1[4], ai1[4];
 #pragma unroll
-      for (int ti = 0; ti < 4; ++ti) {  // A = X^dag: A[i][k] = conj(X[k][i])
-        const cd u0 = x0[(4 * kc + lk) * QLD + 4 * ti + lr];
-        const cd u1 = x1[(4 * kc + lk) * QLD + 4 * ti + lr];
-        ar0[ti] = u0.re;
-        ai0[ti] = u0.im;
-        ar1[ti] = u1.re;
-        ai1[ti] = u1.im;
+      for (int term = 0; term < 2; ++term) {
+        if (term == 1 && cnt < 2) break;  // wave-uniform
+        const cd *x = term == 0 ? x0 : x1;
+        const cd y = term == 0 ? y0[kc] : y1[kc];
+        double xr[4], xi[4], xd[4];
+#pragma unroll
+        for (int ti = 0; ti < 4; ++ti) {  // A = X^dag: A[i][k] = conj(X[k][i])
+          const cd u = x[(4 * kc + lk) * QLD + 4 * ti + lr];
+          xr[ti] = u.re;
+          xi[ti] = u.im;
+          xd[ti] = u.re - u.im;
+        }
+        const double ys = y.im - y.re, yp = y.re + y.im;
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int ti = 0; ti < 4; ++ti) k1[ti] = mfma4(xd[ti], y.re, k1[ti]);
+#pragma unroll
+        for (int ti = 0; ti < 4; ++ti) k2[ti] = mfma4(xr[ti], ys, k2[ti]);
+#pragma unroll
+        for (int ti = 0; ti < 4; ++ti) k3[ti] = mfma4(xi[ti], yp, k3[ti]);
+        __builtin_amdgcn_sched_barrier(0);
       }
-      // re += xr yr + xi yi; im += xr yi + xi (-yr) (A = conj(x)); terms keep separate sums
-      const double nr0 = -y0[kc].re, nr1 = -y1[kc].re;
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int ti = 0; ti < 4; ++ti) r0[ti] = mfma4(ar0[ti], y0[kc].re, r0[ti]);
-#pragma unroll
-      for (int ti = 0; ti < 4; ++ti) i0[ti] = mfma4(ar0[ti], y0[kc].im, i0[ti]);
-      if (cnt > 1) {
-#pragma unroll
-        for (int ti = 0; ti < 4; ++ti) r1[ti] = mfma4(ar1[ti], y1[kc].re, r1[ti]);
-#pragma unroll
-        for (int ti = 0; ti < 4; ++ti) i1[ti] = mfma4(ar1[ti], y1[kc].im, i1[ti]);
-      }
-      __builtin_amdgcn_sched_barrier(0);
       if (pdst) put(kc);
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int ti = 0; ti < 4; ++ti) r0[ti] = mfma4(ai0[ti], y0[kc].im, r0[ti]);
-#pragma unroll
-      for (int ti = 0; ti < 4; ++ti) i0[ti] = mfma4(ai0[ti], nr0, i0[ti]);
-      if (cnt > 1) {
-#pragma unroll
-        for (int ti = 0; ti < 4; ++ti) r1[ti] = mfma4(ai1[ti], y1[kc].im, r1[ti]);
-#pragma unroll
-        for (int ti = 0; ti < 4; ++ti) i1[ti] = mfma4(ai1[ti], nr1, i1[ti]);
-      }
       __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
-    for (int ti = 0; ti < 4; ++ti) prev[ti] = cd{r0[ti] + r1[ti], i0[ti] + i1[ti]};
+    for (int ti = 0; ti < 4; ++ti) prev[ti] = cd{k1[ti] + k3[ti], k1[ti] + k2[ti]};
     pdst = cdst;
   }
   if (pdst) {
