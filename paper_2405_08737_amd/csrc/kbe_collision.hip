@@ -27,6 +27,7 @@
 #include "kbe_internal.h"
 
 #include <initializer_list>
+#include <utility>
 
 namespace kbe {
 
@@ -236,6 +237,178 @@ __device__ __forceinline__ void task_generic(const Params &p, int o, int t0, int
       const int e = lane + 64 * r;
       if (r < R && e < E) st(out + e, acc[r]);
     }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Small-block task (N <= 8): vector ALU, workgroup-tiled like the MFMA task.
+//
+// A wave holds GS = 64 / (N*N) blocks side by side ("slots", lane = slot * N*N + element) and
+// every slot carries ML outputs, so a wave covers MO = GS * ML consecutive outputs and one load
+// instruction streams GS blocks.  Lane (a, b) of a slot holds element (a, b) of its outputs'
+// streamed blocks and accumulates that element's share of every output row i (a k-split):
+//   OP_N : element (k, j) of P adds Q[i][k] c P[k][j]           to out[i][j]
+//   OP_H : element (j, k) of P adds Q[i][k] c conj(P[j][k])     to out[i][j]
+//   OP_HN: element (k, j) of P adds conj(Q[k][i]) c P[k][j]      to out[i][j]
+// so the lane reads one column of Q (one row for OP_HN) per term, from an LDS copy shared by
+// the workgroup (staged TB terms at a time, double-buffered, one barrier per TB terms), and
+// the streamed blocks of the next term are in flight while a term is computed.  The sum over
+// k is taken once per task, through LDS, in a fixed order.
+// ------------------------------------------------------------------------------------------
+template <int N>
+struct SmallCfg {
+  static constexpr int E = N * N;
+  static constexpr int GS = 64 / E;                         // slots per wave
+  static constexpr int ML = N >= 3 ? 4 : (N == 2 ? 2 : 1);  // outputs per slot
+  static constexpr int MO = GS * ML;                        // outputs per wave
+  static constexpr int TB = 256 / E;                        // terms per staged Q batch
+  static constexpr int LQ = N == 1 ? 1 : N + 1;             // LDS row stride (complex)
+  static constexpr int QB = TB * N * LQ;                    // complex numbers per batch
+  static constexpr int RS = 65;                             // reduction row stride (complex)
+  static constexpr int RED = 4 * N * RS;                    // reduction scratch, 4 waves
+  static constexpr int LDS = 2 * QB > RED ? 2 * QB : RED;
+};
+
+template <int N, int CLS>
+__device__ __forceinline__ void wg_task_small(const Params &p, int nout, int ngroup, int ch,
+                                              int gb, int SC, kbe_c128 *base, cd *smem,
+                                              int *rng) {
+  using C = SmallCfg<N>;
+  constexpr int E = C::E, GS = C::GS, ML = C::ML, MO = C::MO, TB = C::TB, LQ = C::LQ;
+  constexpr int OP = cls_op<CLS>();
+  constexpr int FR = cls_fre<CLS>(), FI = cls_fim<CLS>();  // term weight c = (FR + i FI) w
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int g = gb * 4 + wave;
+  const int o0 = g * MO;
+  // lane -> (slot, element); the lanes past GS*E (N = 3, 5, 6, 7) are idle: they read a valid
+  // element and store nothing
+  const bool act = lane < GS * E;
+  const int slot = GS == 1 ? 0 : (act ? lane / E : 0);
+  const int e = act ? lane - slot * E : 0;
+  const int a = e / N, b = e - (e / N) * N;
+  int lo[ML], hi[ML];
+  bool val[ML];
+#pragma unroll
+  for (int u = 0; u < ML; ++u) {
+    const int o = o0 + slot * ML + u;
+    val[u] = act && g < ngroup && o < nout;
+    lo[u] = hi[u] = 0;
+    if (val[u]) cls_range<CLS>(p, o, lo[u], hi[u]);
+  }
+  // workgroup union of the term ranges (wave-uniform loop over the wave's outputs)
+  int wlo = 1 << 30, whi = 0;
+  if (g < ngroup) {
+    for (int v = 0; v < MO; ++v) {
+      if (o0 + v >= nout) break;
+      int l, h;
+      cls_range<CLS>(p, o0 + v, l, h);
+      wlo = l < wlo ? l : wlo;
+      whi = h > whi ? h : whi;
+    }
+  }
+  if (lane == 0) {
+    rng[2 * wave] = wlo;
+    rng[2 * wave + 1] = whi;
+  }
+  lds_barrier();
+  int T0 = 1 << 30, T1 = 0;
+  for (int w = 0; w < 4; ++w) {
+    T0 = rng[2 * w] < T0 ? rng[2 * w] : T0;
+    T1 = rng[2 * w + 1] > T1 ? rng[2 * w + 1] : T1;
+  }
+  T0 = __builtin_amdgcn_readfirstlane(T0 > ch * SC ? T0 : ch * SC);
+  T1 = __builtin_amdgcn_readfirstlane(T1 < (ch + 1) * SC ? T1 : (ch + 1) * SC);
+  cd acc[ML][N];
+#pragma unroll
+  for (int u = 0; u < ML; ++u)
+#pragma unroll
+    for (int i = 0; i < N; ++i) acc[u][i] = czero();
+  if (T0 < T1) {
+    // staging: thread tid < TB*E copies element r = (qi, qk) of Q(T + tq)
+    const bool stager = tid < TB * E;
+    const int tq = stager ? tid / E : 0, r = tid - tq * E;
+    const int qi = r / N, qk = r - (r / N) * N;
+    const int qdst = tq * N * LQ + (OP == OP_HN ? qi * LQ + qk : qk * LQ + qi);
+    auto stage_ld = [&](int T) -> cd {
+      int t = T + tq;
+      t = t < T1 ? t : T1 - 1;
+      return ld(cls_Q<CLS>(p, t) + r);
+    };
+    auto setup = [&](int t, double (&w)[ML], cd (&x)[ML]) {
+#pragma unroll
+      for (int u = 0; u < ML; ++u) {
+        const kbe_c128 *P = p.rdiag;
+        w[u] = 0.0;
+        if (t >= lo[u] && t < hi[u]) cls_wP<CLS>(p, o0 + slot * ML + u, t, w[u], P);
+        x[u] = ld(P + e);
+      }
+    };
+    const int R = OP == OP_H ? b : a;
+    auto compute = [&](const cd *qs, const double (&w)[ML], const cd (&x)[ML]) {
+      cd y[ML];
+#pragma unroll
+      for (int u = 0; u < ML; ++u) {
+        const cd xx = OP == OP_H ? cj(x[u]) : x[u];
+        if (FI == 0) y[u] = (FR * w[u]) * xx;
+        else y[u] = cd{-(FI * w[u]) * xx.im, (FI * w[u]) * xx.re};
+      }
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        cd q = qs[R * LQ + i];
+        if (OP == OP_HN) q = cj(q);
+#pragma unroll
+        for (int u = 0; u < ML; ++u) acc[u][i] = acc[u][i] + q * y[u];
+      }
+    };
+    double wc[ML], wn[ML];
+    cd xc[ML], xn[ML];
+    if (stager) smem[qdst] = stage_ld(T0);
+    setup(T0, wc, xc);
+    lds_barrier();
+    int buf = 0;
+    for (int T = T0; T < T1; T += TB) {
+      cd qn = czero();
+      if (stager) qn = stage_ld(T + TB < T1 ? T + TB : T);
+      const cd *qb = smem + buf * C::QB;
+#pragma unroll 2
+      for (int tt = 0; tt < TB; ++tt) {
+        const int t = T + tt;
+        if (t >= T1) break;  // uniform
+        setup(t + 1 < T1 ? t + 1 : t, wn, xn);  // next term's blocks, in flight during compute
+        compute(qb + tt * N * LQ, wc, xc);
+#pragma unroll
+        for (int u = 0; u < ML; ++u) {
+          wc[u] = wn[u];
+          xc[u] = xn[u];
+        }
+      }
+      buf ^= 1;
+      if (stager) smem[buf * C::QB + qdst] = qn;
+      lds_barrier();
+    }
+  }
+  // sum over k: rows of red are output rows i, columns are lanes
+  cd *red = smem + wave * N * C::RS;
+  const int oi = e / N, oj = e - (e / N) * N;  // this lane's output element (oi, oj)
+#pragma unroll
+  for (int u = 0; u < ML; ++u) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) red[i * C::RS + lane] = acc[u][i];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const bool has = val[u] && hi[u] > ch * SC && lo[u] < (ch + 1) * SC;
+    cd s = czero();
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      const int src = slot * E + (OP == OP_H ? oj * N + k : k * N + oj);
+      s = s + red[oi * C::RS + src];
+    }
+    if (has) st(base + ((int64_t)ch * nout + o0 + slot * ML + u) * E + e, s);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
@@ -474,15 +647,28 @@ struct FusedPlan {
   int64_t qoff;     // byte offset of the 8 queue heads
 };
 
-template <bool MFMA, int CLS>
+// Kernel variants ("kind"): 16 = FP64 MFMA (N = 16), 1..8 = small-block task for that N,
+// 0 = generic vector-ALU task (any N).
+constexpr int KIND_GENERIC = 0, KIND_MFMA = 16;
+
+template <int KIND>
+__host__ __device__ constexpr int kind_lds() {  // complex numbers of LDS per workgroup
+  if constexpr (KIND == KIND_MFMA) return 2 * 16 * QLD;
+  else if constexpr (KIND >= 1 && KIND <= 8) return SmallCfg<KIND>::LDS;
+  else return 1;
+}
+
+template <int KIND, int CLS>
 __device__ __forceinline__ void run_task(const Params &p, const FusedPlan &pl, int k, int64_t lb,
                                          char *ws, int lane, int wave, cd *qbuf, int *rng) {
   const int nch = pl.nchunk[k];
   const int ch = (int)(lb % nch);
   const int gb = (int)(lb / nch);
   kbe_c128 *base = (kbe_c128 *)(ws + pl.off[k]);
-  if (MFMA) {
+  if constexpr (KIND == KIND_MFMA) {
     wg_task_mfma16<CLS>(p, pl.nout[k], pl.ngroup[k], ch, gb, pl.SC, base, qbuf, rng);
+  } else if constexpr (KIND >= 1 && KIND <= 8) {
+    wg_task_small<KIND, CLS>(p, pl.nout[k], pl.ngroup[k], ch, gb, pl.SC, base, qbuf, rng);
   } else {
     const int g = gb * 4 + wave;
     if (g >= pl.ngroup[k]) return;
@@ -498,9 +684,9 @@ __device__ __forceinline__ void run_task(const Params &p, const FusedPlan &pl, i
 
 // ADJ selects the adjoint classes (B_*, G_MAT*) instead of the forward ones, so the two calls
 // run separate, smaller kernels.
-template <bool MFMA, bool ADJ>
+template <int KIND, bool ADJ>
 __global__ void __launch_bounds__(256) stream_fused(Params p, FusedPlan pl, char *ws) {
-  __shared__ cd qbuf[MFMA ? 2 * 16 * QLD : 1];
+  __shared__ cd qbuf[kind_lds<KIND>()];
   __shared__ int rng[8];
   __shared__ long long s_task;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -523,7 +709,7 @@ __global__ void __launch_bounds__(256) stream_fused(Params p, FusedPlan pl, char
       while (task >= pl.first[k + 1]) ++k;
       const int64_t lb = task - pl.first[k];
 #define KBE_CASE(C) \
-  case C: run_task<MFMA, C>(p, pl, k, lb, ws, lane, wave, qbuf, rng); break;
+  case C: run_task<KIND, C>(p, pl, k, lb, ws, lane, wave, qbuf, rng); break;
       if (!ADJ) {
         switch (pl.cls[k]) {
           KBE_CASE(C_IRC) KBE_CASE(C_IRR) KBE_CASE(C_IL) KBE_CASE(C_ITV) KBE_CASE(C_JR)
@@ -861,10 +1047,30 @@ grad_mfma16(Params p, int row_len, int nseg) {
 // ------------------------------------------------------------------------------------------
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static int chunk_terms(int N, bool mfma) {
-  if (mfma) return 256;
+static int path_kind(int N, unsigned flags) {
+  if (flags & KBE_FORCE_GENERIC) return KIND_GENERIC;
+  if (N == 16) return KIND_MFMA;
+  return N <= 8 ? N : KIND_GENERIC;
+}
+
+static int chunk_terms(int N, int kind) {
+  if (kind == KIND_MFMA) return 256;
+  if (kind != KIND_GENERIC) return N >= 5 ? 128 : (N >= 3 ? 256 : 1024);
   const int E = N * N;
   return E >= 64 ? 256 : (E >= 16 ? 1024 : 4096);
+}
+
+template <int... Ns>
+static int small_mo(int N, std::integer_sequence<int, Ns...>) {
+  int mo = 1;
+  ((mo = (N == Ns + 1 ? SmallCfg<Ns + 1>::MO : mo)), ...);
+  return mo;
+}
+
+static int outputs_per_wave(int N, int kind) {
+  if (kind == KIND_MFMA) return MO_MFMA;
+  if (kind == KIND_GENERIC) return 1;
+  return small_mo(N, std::make_integer_sequence<int, 8>{});
 }
 
 // Add class cls with nout outputs whose term indices lie below tmax (skipped when empty).
@@ -881,16 +1087,16 @@ static void plan_add(FusedPlan &pl, int cls, int nout, int tmax, int E, size_t &
   off += al256(sizeof(kbe_c128) * (size_t)pl.nchunk[k] * nout * E);
 }
 
-static FusedPlan plan_init(int N, bool mfma) {
+static FusedPlan plan_init(int N, int kind) {
   FusedPlan pl{};
-  pl.SC = chunk_terms(N, mfma);
-  pl.MO = mfma ? MO_MFMA : 1;
+  pl.SC = chunk_terms(N, kind);
+  pl.MO = outputs_per_wave(N, kind);
   return pl;
 }
 
-static size_t plan_forward(int N, int ntau, int n, int m0, int m1, unsigned flags, bool mfma,
+static size_t plan_forward(int N, int ntau, int n, int m0, int m1, unsigned flags, int kind,
                            FusedPlan &pl) {
-  pl = plan_init(N, mfma);
+  pl = plan_init(N, kind);
   const int E = N * N, M = m1 - m0;
   size_t off = 0;
   const bool th = ntau > 0;
@@ -909,9 +1115,9 @@ static size_t plan_forward(int N, int ntau, int n, int m0, int m1, unsigned flag
   return off + 256;
 }
 
-static size_t plan_adjoint(int N, int ntau, int n, int m0, int m1, unsigned flags, bool mfma,
+static size_t plan_adjoint(int N, int ntau, int n, int m0, int m1, unsigned flags, int kind,
                            FusedPlan &pl) {
-  pl = plan_init(N, mfma);
+  pl = plan_init(N, kind);
   const int E = N * N;
   size_t off = 0;
   const bool th = ntau > 0, M = m1 > m0;
@@ -936,20 +1142,18 @@ static size_t plan_adjoint(int N, int ntau, int n, int m0, int m1, unsigned flag
 size_t collision_ws_bytes(int N, int nt, int ntau, int n, int m0, int m1, unsigned flags) {
   (void)nt;
   FusedPlan pl;
-  const bool mfma = N == 16 && !(flags & KBE_FORCE_GENERIC);
-  return plan_forward(N, ntau, n, m0, m1, flags, mfma, pl);
+  return plan_forward(N, ntau, n, m0, m1, flags, path_kind(N, flags), pl);
 }
 
 size_t collision_vjp_ws_bytes(int N, int nt, int ntau, int n, int m0, int m1, unsigned flags) {
   (void)nt;
   FusedPlan pl;
-  const bool mfma = N == 16 && !(flags & KBE_FORCE_GENERIC);
-  return plan_adjoint(N, ntau, n, m0, m1, flags, mfma, pl);
+  return plan_adjoint(N, ntau, n, m0, m1, flags, path_kind(N, flags), pl);
 }
 
 // Resident workgroups of the persistent kernel on the current device (queried once per
 // device and kernel variant).
-template <bool MFMA, bool ADJ>
+template <int KIND, bool ADJ>
 static int persistent_grid() {
   static int cached[64];
   int dev = 0;
@@ -959,21 +1163,37 @@ static int persistent_grid() {
     int cus = 0, per_cu = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
     const hipError_t e =
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stream_fused<MFMA, ADJ>, 256, 0);
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stream_fused<KIND, ADJ>, 256, 0);
     if (e != hipSuccess || per_cu < 1) per_cu = 1;
     c = cus * per_cu;
   }
   return c;
 }
 
-template <bool MFMA, bool ADJ>
+template <int KIND, bool ADJ>
 static void launch_fused(const Params &p, const FusedPlan &pl, char *ws, hipStream_t st) {
   const int64_t ntask = pl.first[pl.ncls];
   if (ntask == 0) return;
   hipLaunchKernelGGL(zero_heads, dim3(1), dim3(64), 0, st, (unsigned int *)(ws + pl.qoff));
-  int64_t grid = persistent_grid<MFMA, ADJ>();
+  int64_t grid = persistent_grid<KIND, ADJ>();
   if (grid > ntask) grid = ntask;
-  hipLaunchKernelGGL((stream_fused<MFMA, ADJ>), dim3((unsigned)grid), dim3(256), 0, st, p, pl, ws);
+  hipLaunchKernelGGL((stream_fused<KIND, ADJ>), dim3((unsigned)grid), dim3(256), 0, st, p, pl, ws);
+}
+
+template <bool ADJ>
+static void launch_kind(int kind, const Params &p, const FusedPlan &pl, char *ws, hipStream_t st) {
+  switch (kind) {
+    case KIND_MFMA: launch_fused<KIND_MFMA, ADJ>(p, pl, ws, st); break;
+    case 1: launch_fused<1, ADJ>(p, pl, ws, st); break;
+    case 2: launch_fused<2, ADJ>(p, pl, ws, st); break;
+    case 3: launch_fused<3, ADJ>(p, pl, ws, st); break;
+    case 4: launch_fused<4, ADJ>(p, pl, ws, st); break;
+    case 5: launch_fused<5, ADJ>(p, pl, ws, st); break;
+    case 6: launch_fused<6, ADJ>(p, pl, ws, st); break;
+    case 7: launch_fused<7, ADJ>(p, pl, ws, st); break;
+    case 8: launch_fused<8, ADJ>(p, pl, ws, st); break;
+    default: launch_fused<KIND_GENERIC, ADJ>(p, pl, ws, st); break;
+  }
 }
 
 // Reduce the listed classes (those present in the plan) into out[nout][E].
@@ -997,12 +1217,11 @@ static void reduce_into(const Params &p, const FusedPlan &pl, std::initializer_l
 
 hipError_t launch_collision(const Params &p, unsigned flags, kbe_c128 *IR, kbe_c128 *IL,
                             kbe_c128 *Itv, kbe_c128 *Jtv, void *ws, hipStream_t st) {
-  const bool mfma = p.N == 16 && !(flags & KBE_FORCE_GENERIC);
+  const int kind = path_kind(p.N, flags);
   FusedPlan pl;
-  plan_forward(p.N, p.ntau, p.n, p.m0, p.m1, flags, mfma, pl);
+  plan_forward(p.N, p.ntau, p.n, p.m0, p.m1, flags, kind, pl);
   char *w = (char *)ws;
-  if (mfma) launch_fused<true, false>(p, pl, w, st);
-  else launch_fused<false, false>(p, pl, w, st);
+  launch_kind<false>(kind, p, pl, w, st);
   const int M = p.m1 - p.m0;
   if (flags & KBE_OUT_IR) reduce_into(p, pl, {C_IRC, C_IRR}, w, M, IR, false, st);
   if (flags & KBE_OUT_IL) reduce_into(p, pl, {C_IL}, w, M, IL, false, st);
@@ -1013,12 +1232,12 @@ hipError_t launch_collision(const Params &p, unsigned flags, kbe_c128 *IR, kbe_c
 
 hipError_t launch_collision_vjp(const Params &p, unsigned flags, kbe_c128 *gmat,
                                 const kbe_sigma_row *gS, void *ws, hipStream_t st) {
-  const bool mfma = p.N == 16 && !(flags & KBE_FORCE_GENERIC);
+  const int kind = path_kind(p.N, flags);
+  const bool mfma = kind == KIND_MFMA;
   FusedPlan pl;
-  plan_adjoint(p.N, p.ntau, p.n, p.m0, p.m1, flags, mfma, pl);
+  plan_adjoint(p.N, p.ntau, p.n, p.m0, p.m1, flags, kind, pl);
   char *w = (char *)ws;
-  if (mfma) launch_fused<true, true>(p, pl, w, st);
-  else launch_fused<false, true>(p, pl, w, st);
+  launch_kind<true>(kind, p, pl, w, st);
   // self-energy gradients: overwritten
   reduce_into(p, pl, {B_R1, B_R2, B_R3}, w, p.n + 1, gS->ret, false, st);
   reduce_into(p, pl, {B_L}, w, p.n + 1, gS->les, false, st);

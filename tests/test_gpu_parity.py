@@ -132,6 +132,34 @@ def test_collision_orbital_counts(gpu, N):
     check_all(*run_collision(kbe, case))
 
 
+@pytest.mark.parametrize("N,nt,ntau", [(8, 300, 140), (6, 290, 20), (4, 600, 300), (3, 530, 300),
+                                        (2, 2100, 30), (1, 2200, 10)])
+def test_collision_small_blocks_several_chunks(gpu, N, nt, ntau):
+    """Small-block path (N <= 8) over several term chunks with ragged tails (chunks of 128 terms
+    for N >= 5, 256 for N = 3, 4 and 1024 below), real-time and Matsubara classes."""
+    kbe = gpu
+    _print("small blocks", N, nt, ntau)
+    case = Case(N=N, nt=nt, ntau=ntau, beta=3.0, seed=200 + N)
+    check_all(*run_collision(kbe, case))
+
+
+@pytest.mark.parametrize("N", [2, 5, 8])
+def test_small_block_path_agrees_with_generic(gpu, N):
+    """The small-block task and the generic one-output-per-wave task sum the same terms in
+    different orders: they agree to rounding."""
+    kbe = gpu
+    case = Case(N=N, nt=260, ntau=150, beta=3.0, seed=300 + N)
+    t, order, kp, rd, tv, mat = case.host()
+    W = device_weights(oracle.Weights.build(t, order, case.beta, case.ntau))
+    Gd = device_green(kp, rd, tv, mat)
+    sig = tuple(to_dev(x) for x in synth.sigma_row(case.seed, N, 259, case.ntau, t))
+    a = kbe.collision(Gd, sig, W, 259)
+    b = kbe.collision(Gd, sig, W, 259, flags=kbe.OUT_ALL | kbe.FORCE_GENERIC)
+    for x, y in zip(a, b):
+        x, y = to_host(x), to_host(y)
+        assert np.linalg.norm((x - y).ravel()) <= 1e-13 * np.linalg.norm(y.ravel())
+
+
 def test_collision_ragged_ranges_and_edges(gpu):
     kbe = gpu
     case = Case(N=4, nt=50, ntau=10, beta=2.0, seed=5)

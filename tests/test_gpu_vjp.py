@@ -46,6 +46,11 @@ def vjp_case(kbe, case: Case, m0, m1, flags, extra=0, seed_cot=5):
     (16, 150, 12, 33, 101, oracle.F_ALL, False),
     (16, 60, 8, 0, 60, oracle.F_IR | oracle.F_JTV, False),
     (5, 40, 0, 0, 40, oracle.F_IR | oracle.F_IL, False),
+    (8, 300, 140, 0, 300, oracle.F_ALL, False),
+    (8, 300, 140, 0, 300, oracle.F_ALL, True),
+    (4, 600, 40, 100, 480, oracle.F_ALL, False),
+    (3, 530, 260, 0, 530, oracle.F_ALL, False),
+    (1, 1500, 300, 0, 1500, oracle.F_ALL, False),
 ])
 def test_collision_vjp_matches_oracle(gpu, N, nt, ntau, m0, m1, flags, generic):
     kbe = gpu
