@@ -112,59 +112,67 @@ __host__ __device__ constexpr int cls_fim() {
   return CLS == C_ITV ? -1 : (CLS == B_T1 ? 1 : 0);
 }
 
-// Real weight w (the term weight is f w) and streamed block P of term t of output o (t inside
-// o's range).
+// Addresses of the real weight (the term weight is f w) and of the streamed block P of term t of
+// output o.  Only address arithmetic: they are valid to read when t lies in o's range.
 template <int CLS>
-__device__ __forceinline__ void cls_wP(const Params &p, int o, int t, double &w,
-                                       const kbe_c128 *&P) {
+__device__ __forceinline__ void cls_wpP(const Params &p, int o, int t, const double *&w,
+                                        const kbe_c128 *&P) {
   const int64_t E = bsz(p);
   const int J = p.J, m = p.m0 + o;
   switch (CLS) {
-    case C_IRC: w = p.w[(int64_t)p.n * p.nt + t]; P = kp_blk(p, t, m); break;
-    case C_IRR: w = p.w[(int64_t)p.n * p.nt + t]; P = kp_blk(p, m, t); break;
+    case C_IRC: w = p.w + ((int64_t)p.n * p.nt + t); P = kp_blk(p, t, m); break;
+    case C_IRR: w = p.w + ((int64_t)p.n * p.nt + t); P = kp_blk(p, m, t); break;
     case C_IL:
-      w = p.w[(int64_t)m * p.nt + t];
+      w = p.w + ((int64_t)m * p.nt + t);
       P = t < m ? kp_blk(p, m, t) : p.rdiag + m * E;
       break;
-    case C_ITV: w = p.wtau[t]; P = tv_blk(p, m, J - t); break;
-    case C_JR: w = p.w[(int64_t)p.n * p.nt + t]; P = tv_blk(p, t, o); break;
+    case C_ITV: w = p.wtau + t; P = tv_blk(p, m, J - t); break;
+    case C_JR: w = p.w + ((int64_t)p.n * p.nt + t); P = tv_blk(p, t, o); break;
     case C_JM1:  // l = t <= j = o
-      w = p.wf[(int64_t)o * p.ntau + t];
+      w = p.wf + ((int64_t)o * p.ntau + t);
       P = p.mat + (J + t - o) * E;
       break;
     case C_JM2:  // l = t >= j = o; the rule over [tau_j, beta] is the mirrored forward rule
-      w = p.wf[(int64_t)(J - o) * p.ntau + (J - t)];
+      w = p.wf + ((int64_t)(J - o) * p.ntau + (J - t));
       P = p.mat + (t - o) * E;
       break;
-    case B_R1: w = p.w[(int64_t)p.n * p.nt + o]; P = kp_blk(p, o, t); break;
-    case B_R2: w = p.w[(int64_t)p.n * p.nt + o]; P = kp_blk(p, t, o); break;
-    case B_R3: w = p.w[(int64_t)p.n * p.nt + o]; P = tv_blk(p, o, t); break;
+    case B_R1: w = p.w + ((int64_t)p.n * p.nt + o); P = kp_blk(p, o, t); break;
+    case B_R2: w = p.w + ((int64_t)p.n * p.nt + o); P = kp_blk(p, t, o); break;
+    case B_R3: w = p.w + ((int64_t)p.n * p.nt + o); P = tv_blk(p, o, t); break;
     case B_L:
-      w = p.w[(int64_t)t * p.nt + o];
+      w = p.w + ((int64_t)t * p.nt + o);
       P = t > o ? kp_blk(p, t, o) : p.rdiag + o * E;
       break;
-    case B_T1: w = p.wtau[o]; P = tv_blk(p, t, J - o); break;
+    case B_T1: w = p.wtau + o; P = tv_blk(p, t, J - o); break;
     case B_T2A:  // j = t >= l = o
-      w = p.wf[(int64_t)t * p.ntau + o];
+      w = p.wf + ((int64_t)t * p.ntau + o);
       P = p.mat + (J + o - t) * E;
       break;
     case B_T2B:  // j = t <= l = o
-      w = p.wf[(int64_t)(J - t) * p.ntau + (J - o)];
+      w = p.wf + ((int64_t)(J - t) * p.ntau + (J - o));
       P = p.mat + (o - t) * E;
       break;
     case G_MAT1: {  // l = t <= k = o, j = l + J - k
       const int j = t + J - o;
-      w = p.wf[(int64_t)j * p.ntau + t];
+      w = p.wf + ((int64_t)j * p.ntau + t);
       P = p.gJ + j * E;
       break;
     }
     case G_MAT2: {  // l = t >= k = o, j = l - k
       const int j = t - o;
-      w = p.wf[(int64_t)(J - j) * p.ntau + (J - t)];
+      w = p.wf + ((int64_t)(J - j) * p.ntau + (J - t));
       P = p.gJ + j * E;
       break;
     }
   }
+}
+
+template <int CLS>
+__device__ __forceinline__ void cls_wP(const Params &p, int o, int t, double &w,
+                                       const kbe_c128 *&P) {
+  const double *wp;
+  cls_wpP<CLS>(p, o, t, wp, P);
+  w = *wp;
 }
 
 // Complex weight c = f w and block P of term t of output o.
@@ -335,58 +343,80 @@ __device__ __forceinline__ void wg_task_small(const Params &p, int nout, int ngr
       t = t < T1 ? t : T1 - 1;
       return ld(cls_Q<CLS>(p, t) + r);
     };
-    auto setup = [&](int t, double (&w)[ML], cd (&x)[ML]) {
+    // The loads are unconditional (an output without term t reads a valid dummy and gets
+    // weight 0), so the number of loads in flight is fixed and the wait for term t does not
+    // wait for the prefetches of term t + 1.
+    // The weight of an absent term is zeroed when the term is computed, not here, so that
+    // nothing waits for a prefetch before its use.
+    struct Term {
+      double w[ML];
+      bool in[ML];
+      cd x[ML];
+    };
+    auto setup = [&](int t, Term &tm) {
 #pragma unroll
       for (int u = 0; u < ML; ++u) {
-        const kbe_c128 *P = p.rdiag;
-        w[u] = 0.0;
-        if (t >= lo[u] && t < hi[u]) cls_wP<CLS>(p, o0 + slot * ML + u, t, w[u], P);
-        x[u] = ld(P + e);
+        const double *wp;
+        const kbe_c128 *P;
+        cls_wpP<CLS>(p, o0 + slot * ML + u, t, wp, P);
+        tm.in[u] = t >= lo[u] && t < hi[u];
+        wp = tm.in[u] ? wp : p.w;
+        P = tm.in[u] ? P : p.rdiag;
+        tm.w[u] = *wp;
+        tm.x[u] = ld(P + e);
       }
     };
     const int R = OP == OP_H ? b : a;
-    auto compute = [&](const cd *qs, const double (&w)[ML], const cd (&x)[ML]) {
+    auto compute = [&](const cd *qs, const Term &tm) {
       cd y[ML];
 #pragma unroll
       for (int u = 0; u < ML; ++u) {
-        const cd xx = OP == OP_H ? cj(x[u]) : x[u];
-        if (FI == 0) y[u] = (FR * w[u]) * xx;
-        else y[u] = cd{-(FI * w[u]) * xx.im, (FI * w[u]) * xx.re};
+        const cd xx = OP == OP_H ? cj(tm.x[u]) : tm.x[u];
+        const double wu = tm.in[u] ? tm.w[u] : 0.0;
+        if (FI == 0) y[u] = (FR * wu) * xx;
+        else y[u] = cd{-(FI * wu) * xx.im, (FI * wu) * xx.re};
       }
 #pragma unroll
       for (int i = 0; i < N; ++i) {
-        cd q = qs[R * LQ + i];
-        if (OP == OP_HN) q = cj(q);
+        const cd q = qs[R * LQ + i];
+        const double qi = OP == OP_HN ? -q.im : q.im;
 #pragma unroll
-        for (int u = 0; u < ML; ++u) acc[u][i] = acc[u][i] + q * y[u];
-      }
-    };
-    double wc[ML], wn[ML];
-    cd xc[ML], xn[ML];
-    if (stager) smem[qdst] = stage_ld(T0);
-    setup(T0, wc, xc);
-    lds_barrier();
-    int buf = 0;
-    for (int T = T0; T < T1; T += TB) {
-      cd qn = czero();
-      if (stager) qn = stage_ld(T + TB < T1 ? T + TB : T);
-      const cd *qb = smem + buf * C::QB;
-#pragma unroll 2
-      for (int tt = 0; tt < TB; ++tt) {
-        const int t = T + tt;
-        if (t >= T1) break;  // uniform
-        setup(t + 1 < T1 ? t + 1 : t, wn, xn);  // next term's blocks, in flight during compute
-        compute(qb + tt * N * LQ, wc, xc);
-#pragma unroll
-        for (int u = 0; u < ML; ++u) {
-          wc[u] = wn[u];
-          xc[u] = xn[u];
+        for (int u = 0; u < ML; ++u) {  // four fused multiply-adds per complex one
+          acc[u][i].re = __builtin_fma(q.re, y[u].re, acc[u][i].re);
+          acc[u][i].re = __builtin_fma(-qi, y[u].im, acc[u][i].re);
+          acc[u][i].im = __builtin_fma(q.re, y[u].im, acc[u][i].im);
+          acc[u][i].im = __builtin_fma(qi, y[u].re, acc[u][i].im);
         }
       }
-      buf ^= 1;
-      if (stager) smem[buf * C::QB + qdst] = qn;
-      lds_barrier();
+    };
+    // Batch b of Q (terms T0 + b TB ...) lives in staging buffer b % 2: written at the start of
+    // batch b (loaded a batch earlier), then one barrier.  Terms ping-pong between two
+    // register sets, so no prefetched value is copied (a copy would wait for its load).
+    Term A, B;
+    cd qn;
+    if (stager) smem[qdst] = stage_ld(T0);
+    setup(T0, A);
+    if (stager) qn = stage_ld(T0 + TB);
+    lds_barrier();
+    auto step = [&](int t, const Term &cu, Term &nx) {
+      const int rel = t - T0, bt = rel / TB, tt = rel - bt * TB;
+      if (tt == 0 && rel > 0) {  // uniform: a new batch starts at term t
+        if (stager) smem[(bt & 1) * C::QB + qdst] = qn;
+        lds_barrier();
+        if (stager) qn = stage_ld(t + TB);
+      }
+      setup(t + 1 < T1 ? t + 1 : t, nx);  // next term, in flight during compute
+      // keep the loads of term t + 1 after those of term t (the load counter retires in order)
+      __builtin_amdgcn_sched_barrier(0);
+      compute(smem + (bt & 1) * C::QB + tt * N * LQ, cu);
+      __builtin_amdgcn_sched_barrier(0);
+    };
+    for (int t = T0; t < T1; t += 2) {
+      step(t, A, B);
+      if (t + 1 >= T1) break;
+      step(t + 1, B, A);
     }
+    lds_barrier();  // the reduction below reuses the staging buffers
   }
   // sum over k: rows of red are output rows i, columns are lanes
   cd *red = smem + wave * N * C::RS;
@@ -1042,6 +1072,118 @@ grad_mfma16(Params p, int row_len, int nseg) {
   }
 }
 
+// MFMA version for 5 <= N <= 8.  Blocks are zero-padded to 8 x 8 and one v_mfma_f64_4x4x4
+// instruction computes all four 4 x 4 tiles (ti, tj) of an 8 x 8 product (instruction block
+// b = 2 ti + tj), so a block costs two k-chunks of three real products per term.  Lane roles:
+//   A[b][i][k] = conj(X[4 kc + k][4 ti + i])  at lane 4b + i + 16k   (read from LDS),
+//   B[b][k][j] = c Y[4 kc + k][4 tj + j]      at lane 4b + j + 16k   (loaded from the cache),
+//   D[b][i][j] = out[4 ti + i][4 tj + j]      at lane 4b + j + 16i,
+// so lanes 8r .. 8r+7 of a store hold a whole row of the block (128 contiguous bytes at N = 8).
+// Work split, records, prefetch and streaming stores as in grad_mfma16.
+constexpr int GSEG8 = 128;  // blocks per workgroup segment
+constexpr int XLD8 = 9;     // LDS row stride of a staged 8x8 block, in complex numbers
+
+__global__ void __launch_bounds__(256) grad_mfma8(Params p, int row_len, int nseg) {
+  __shared__ cd xs[4][8 * XLD8];
+  __shared__ GradRec rec[GSEG8];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int N = p.N;
+  const int per_xcd = (int)((gridDim.x + 7) / 8);
+  const int L = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (L >= (p.n + 1) * nseg) return;  // whole workgroup: before any barrier
+  const int seg = L / (p.n + 1), a = L % (p.n + 1);
+  const int64_t E = bsz(p);
+  const bool ina = a >= p.m0 && a < p.m1;
+  {  // stage the row's X blocks (Sigma^R(a), gIR(a), gIL(a), gItv(a)), zero-padded to 8 x 8
+    const int x = tid >> 6, r = (tid >> 3) & 7, c = tid & 7;
+    const bool present = x == 0 || (x == 1 && p.fIR && ina) || (x == 2 && p.fIL && ina) ||
+                         (x == 3 && p.fITV && ina);
+    const kbe_c128 *X = x == 0 ? p.ret + a * E
+                        : x == 1 ? p.gIR + (a - p.m0) * E
+                        : x == 2 ? p.gIL + (a - p.m0) * E
+                                 : p.gItv + (a - p.m0) * E;
+    xs[x][r * XLD8 + c] = (present && r < N && c < N) ? ld(X + r * N + c) : czero();
+  }
+  const int j0 = seg * GSEG8, len = (j0 + GSEG8 < row_len ? j0 + GSEG8 : row_len) - j0;
+  if (tid < GSEG8) {
+    GradTerm t0{-1, czero(), p.ret}, t1 = t0;
+    kbe_c128 *d = p.gkp;
+    const int nt = tid < len ? grad_row_terms(p, a, j0 + tid, t0, t1, d) : 0;
+    GradRec &g = rec[tid];
+    g.y0 = t0.Y;
+    g.y1 = nt > 1 ? t1.Y : t0.Y;
+    g.dst = d;
+    g.c0r = t0.c.re;
+    g.c0i = t0.c.im;
+    g.c1r = nt > 1 ? t1.c.re : 0.0;
+    g.c1i = nt > 1 ? t1.c.im : 0.0;
+    g.x0 = t0.xid < 0 ? 0 : t0.xid;
+    g.x1 = nt > 1 ? t1.xid : 0;
+    g.nt = nt;
+  }
+  __syncthreads();
+  const int lj = lane & 3, lb = (lane >> 2) & 3, lk = lane >> 4;
+  const int ti = lb >> 1, tj = lb & 1;
+  // B element of k-chunk kc: row 4 kc + lk, column 4 tj + lj (zero outside N x N)
+  const int bc = 4 * tj + lj;
+  const bool bv0 = lk < N && bc < N, bv1 = 4 + lk < N && bc < N;
+  const int bo0 = bv0 ? lk * N + bc : 0, bo1 = bv1 ? (4 + lk) * N + bc : 0;
+  // D element: row 4 ti + lk, column 4 tj + lj
+  const bool dv = 4 * ti + lk < N && bc < N;
+  const int dof = dv ? (4 * ti + lk) * N + bc : 0;
+  cd yn[2][2];  // raw Y of [term][kc] of the block after the current one
+  auto fetch = [&](int q) {
+    const kbe_c128 *Y0 = uniform_ptr(rec[q].y0), *Y1 = uniform_ptr(rec[q].y1);
+    yn[0][0] = ldg(Y0 + bo0);
+    yn[0][1] = ldg(Y0 + bo1);
+    yn[1][0] = ldg(Y1 + bo0);
+    yn[1][1] = ldg(Y1 + bo1);
+  };
+  int q = __builtin_amdgcn_readfirstlane(wave);
+  if (q < len) fetch(q);
+  for (; q < len; q += 4) {
+    const int cnt = __builtin_amdgcn_readfirstlane(rec[q].nt);
+    kbe_c128 *const cdst = (kbe_c128 *)uniform_ptr(rec[q].dst);
+    const cd c0{rec[q].c0r, rec[q].c0i}, c1{rec[q].c1r, rec[q].c1i};
+    const cd *x0 = xs[__builtin_amdgcn_readfirstlane(rec[q].x0)];
+    const cd *x1 = xs[__builtin_amdgcn_readfirstlane(rec[q].x1)];
+    cd y[2][2];
+    y[0][0] = c0 * (bv0 ? yn[0][0] : czero());
+    y[0][1] = c0 * (bv1 ? yn[0][1] : czero());
+    y[1][0] = c1 * (bv0 ? yn[1][0] : czero());
+    y[1][1] = c1 * (bv1 ? yn[1][1] : czero());
+    fetch(q + 4 < len ? q + 4 : len - 1);  // next block's loads before this block's work
+    if (cnt == 0) continue;
+    __builtin_amdgcn_sched_barrier(0);
+    // three real products per complex one, A = conj(X) (see grad_mfma16):
+    //   K1 += (xr - xi) yr,  K2 += xr (yi - yr),  K3 += xi (yr + yi);  Re = K1 + K3, Im = K1 + K2
+    double k1 = 0.0, k2 = 0.0, k3 = 0.0;
+#pragma unroll
+    for (int term = 0; term < 2; ++term) {
+      if (term == 1 && cnt < 2) break;  // wave-uniform
+      const cd *x = term == 0 ? x0 : x1;
+#pragma unroll
+      for (int kc = 0; kc < 2; ++kc) {
+        const cd u = x[(4 * kc + lk) * XLD8 + 4 * ti + lj];
+        const cd v = y[term][kc];
+        k1 = mfma4(u.re - u.im, v.re, k1);
+        k2 = mfma4(u.re, v.im - v.re, k2);
+        k3 = mfma4(u.im, v.re + v.im, k3);
+      }
+    }
+    cd r{k1 + k3, k1 + k2};
+    if (dv) {
+      kbe_c128 *d = cdst + dof;
+      if (!p.overwrite) r = r + ldg(d);
+      dvec2 w;
+      w.x = r.re;
+      w.y = r.im;
+      __builtin_nontemporal_store(w, (g_dvec2 *)(void *)d);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
 // ------------------------------------------------------------------------------------------
 // Host side: chunking, workspace layout and launches.
 // ------------------------------------------------------------------------------------------
@@ -1245,11 +1387,16 @@ hipError_t launch_collision_vjp(const Params &p, unsigned flags, kbe_c128 *gmat,
   // Green's-function gradients
   const int64_t n1 = p.n + 1;
   const int64_t nblk = n1 * n1 + n1 + (p.ntau > 0 ? n1 * p.ntau : 0);
+  const int row_len = p.n + 2 + p.ntau;  // kp row, tv row, rdiag
   if (mfma) {
-    const int row_len = p.n + 2 + p.ntau;  // kp row, tv row, rdiag
     const int nseg = (row_len + GSEG - 1) / GSEG;
     const int64_t tasks = (int64_t)(p.n + 1) * nseg;
     hipLaunchKernelGGL(grad_mfma16, dim3((unsigned)(8 * ((tasks + 7) / 8))), dim3(256), 0, st,
+                       p, row_len, nseg);
+  } else if (kind >= 5 && kind <= 8) {
+    const int nseg = (row_len + GSEG8 - 1) / GSEG8;
+    const int64_t tasks = (int64_t)(p.n + 1) * nseg;
+    hipLaunchKernelGGL(grad_mfma8, dim3((unsigned)(8 * ((tasks + 7) / 8))), dim3(256), 0, st,
                        p, row_len, nseg);
   } else {
     const int64_t th = nblk * p.N * p.N;

@@ -51,6 +51,9 @@ def vjp_case(kbe, case: Case, m0, m1, flags, extra=0, seed_cot=5):
     (4, 600, 40, 100, 480, oracle.F_ALL, False),
     (3, 530, 260, 0, 530, oracle.F_ALL, False),
     (1, 1500, 300, 0, 1500, oracle.F_ALL, False),
+    (6, 140, 30, 20, 120, oracle.F_ALL, False),
+    (7, 100, 50, 0, 100, oracle.F_IR | oracle.F_JTV, False),
+    (7, 100, 50, 10, 90, oracle.F_IL | oracle.F_ITV, False),
 ])
 def test_collision_vjp_matches_oracle(gpu, N, nt, ntau, m0, m1, flags, generic):
     kbe = gpu
@@ -74,18 +77,20 @@ def test_collision_vjp_overwrite_mode(gpu):
     # accumulate-mode reference minus the initial content = the overwrite result
     for g, r, b in zip([gG.kp, gG.rdiag, gG.tv, gG.mat], ref[:4], base):
         assert rel(to_host(g), r - b) < RTOL
-    # a partial range: blocks nobody reads keep their initial values
-    case2 = Case(N=4, nt=30, ntau=6, beta=2.0, seed=4)
-    ref2, (gG2, _), base2 = vjp_case(kbe, case2, 10, 20, oracle.F_IR | oracle.F_IL,
-                                     kbe.GRAD_OVERWRITE)
-    kp = to_host(gG2.kp)
-    read = np.zeros((30, 30), bool)
-    for m in range(10, 20):
-        read[: m + 1, m] = True   # IR column part
-        read[m, m + 1:] = True    # IR row part
-        read[m, :m] = True        # IL
-    assert np.array_equal(kp[~read], base2[0][~read])
-    assert rel(kp[read], (ref2[0] - base2[0])[read]) < RTOL
+    # a partial range: blocks nobody reads keep their initial values (generic gradient kernel
+    # at N = 4, the padded MFMA one at N = 8)
+    for N in (4, 8):
+        case2 = Case(N=N, nt=30, ntau=6, beta=2.0, seed=4)
+        ref2, (gG2, _), base2 = vjp_case(kbe, case2, 10, 20, oracle.F_IR | oracle.F_IL,
+                                         kbe.GRAD_OVERWRITE)
+        kp = to_host(gG2.kp)
+        read = np.zeros((30, 30), bool)
+        for m in range(10, 20):
+            read[: m + 1, m] = True   # IR column part
+            read[m, m + 1:] = True    # IR row part
+            read[m, :m] = True        # IL
+        assert np.array_equal(kp[~read], base2[0][~read])
+        assert rel(kp[read], (ref2[0] - base2[0])[read]) < RTOL
 
 
 @pytest.mark.parametrize("N,n", [(2, 63), (3, 0), (16, 45), (16, 0)])
