@@ -3,8 +3,10 @@
 One step = the whole path over the 16-orbital, 2048-point workload (n_tau = 512):
   kbe_weights -> kbe_sigma_2b (row n = 2047) -> kbe_collision (all m <= n, all four integrals)
   -> kbe_collision_vjp (all cotangents) -> kbe_sigma_2b_vjp,
-all through the C ABI of libkbe.so.  Inputs are seeded synthetic arrays (see the input recipe in
-the design doc), resident in HBM before timing starts.  Prints one JSON line.
+all through the C ABI of libkbe.so.  Inputs are seeded synthetic arrays, resident in HBM before
+timing starts.  After the timed steps, the forward and adjoint collision calls are also timed on
+the 8-orbital differentiation shape (nt = 1024, n_tau = 256: the small-block path, bound by HBM
+bandwidth) and reported beside the step.  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
   python bench.py --copy-calibration   # 3 plain 1 GiB device copies (PMC byte-counter scale)
@@ -59,10 +61,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per forward call from the committed rocprofv3 counter summary, or None when
-    the kernel source changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "traffic_collision_N16_nt2048.json")
+def measured_traffic(name="traffic_collision_N16_nt2048.json"):
+    """HBM bytes per forward stream launch from a committed rocprofv3 counter summary, or None
+    when the kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
@@ -108,6 +110,52 @@ def cpu_baseline(w, host, target_s=30.0):
             "kind": "oracle",
             "sample": f"rows m in [{m0},{m1}) of row n={n}: I^R, I^<, I^] "
                       f"({fl / 1e9:.1f} GFLOP in {dt:.1f} s)"}
+
+
+def small_orbital_shape(kbe, torch, dev, reps=5):
+    """Forward and adjoint collision calls on the 8-orbital differentiation workload (row
+    n = nt - 1, all m), timed with HIP events on the library's stream, after two warm-up calls."""
+    import synth
+    w = synth.DIFFERENTIATION
+    N, nt, ntau, n = w.N, w.nt, w.ntau, w.nt - 1
+    t, order = synth.grid(w.seed, nt, w.hmin, w.hmax, w.omin, w.omax)
+    G = kbe.Green(torch.from_numpy(synth.kp(w.seed, N, t)).to(dev),
+                  torch.from_numpy(synth.rdiag(N, nt)).to(dev),
+                  torch.from_numpy(synth.tv(w.seed, N, ntau, t)).to(dev),
+                  torch.from_numpy(synth.mat(w.seed, N, ntau)).to(dev))
+    gG = G.zeros_like()
+    u = torch.full((N,), w.U, dtype=torch.float64, device=dev)
+    cot = tuple(torch.from_numpy(synth.normal(7, k, (nt if k < 3 else ntau, N, N))).to(dev)
+                for k in range(4))
+    W = kbe.weights(t, order, ntau, w.beta, w.tau_order, device=dev)
+    sig = kbe.sigma_2b(G, u, n)
+    flags = kbe.OUT_ALL | kbe.GRAD_OVERWRITE
+    for _ in range(2):
+        kbe.collision(G, sig, W, n)
+        kbe.collision_vjp(G, sig, W, n, 0, n + 1, cot, flags, gG)
+    torch.cuda.synchronize()
+    tf, tb = [], []
+    for _ in range(reps):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record()
+        kbe.collision(G, sig, W, n)
+        e[1].record()
+        kbe.collision_vjp(G, sig, W, n, 0, n + 1, cot, flags, gG)
+        e[2].record()
+        torch.cuda.synchronize()
+        tf.append(e[0].elapsed_time(e[1]))
+        tb.append(e[1].elapsed_time(e[2]))
+    c = counts(N, nt, ntau, n)
+    f_ms, b_ms = float(np.mean(tf)), float(np.mean(tb))
+    return {"workload": w.name, "N_orb": N, "nt": nt, "n": n, "ntau": ntau, "U": w.U,
+            "seed": w.seed, "calls": reps,
+            "collision_ms": f_ms, "collision_vjp_ms": b_ms, "adjoint_over_forward": b_ms / f_ms,
+            "collision_gflops": c["fwd_flop"] / f_ms / 1e6,
+            "collision_gbps": c["fwd_bytes"] / f_ms / 1e6,
+            "collision_hbm_frac": c["fwd_bytes"] / f_ms / 1e6 / HBM_PEAK_GBS,
+            "collision_vjp_gbps": c["adj_bytes"] / b_ms / 1e6,
+            "algorithmic_bytes": c["fwd_bytes"], "algorithmic_flop": c["fwd_flop"],
+            "traffic": measured_traffic("traffic_collision_N8_nt1024.json")}
 
 
 def main():
@@ -239,8 +287,9 @@ def main():
         "adjoint_over_forward": adj_ms / fwd_ms,
         "hbm_gbps": (c["fwd_bytes"] + c["adj_bytes"]) / (ms_step / 1e3) / 1e9,
         "roofline": {
-            "kernel": "kbe_collision forward call: stream_fused<MFMA, forward> (about 99% of it) "
-                      "+ zero_heads + chunk reduces, timed with HIP events around the call",
+            "kernel": "kbe_collision forward call: stream_fused<16, false> (the MFMA task, about "
+                      "99% of it) + zero_heads + chunk reduces, timed with HIP events around the "
+                      "call",
             "bound": "mfma" if c["fwd_flop"] / c["fwd_bytes"] > RIDGE else "hbm",
             "achieved": achieved, "peak": MFMA_F64_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / MFMA_F64_PEAK_TFLOPS,
@@ -249,9 +298,12 @@ def main():
             "intensity_flop_per_byte": c["fwd_flop"] / c["fwd_bytes"],
             "hbm_frac": c["fwd_bytes"] / coll_s / 1e9 / HBM_PEAK_GBS},
     }
+    del gG, kp, tvd, G
+    torch.cuda.empty_cache()
+    log("8-orbital differentiation shape")
+    result["small_orbital"] = small_orbital_shape(kbe, torch, dev)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample)")
-        del gG, kp, tvd
         result["cpu_baseline"] = cpu_baseline(w, (t, order, kp_h, rd_h, tv_h, mat_h))
     print(json.dumps(result), flush=True)
 
