@@ -761,32 +761,43 @@ __global__ void zero_heads(unsigned int *heads) {
   if (threadIdx.x < 8) heads[threadIdx.x] = 0u;
 }
 
-// out[x] (=|+=) the sum, in increasing chunk order, of the chunks of up to three classes'
-// partial arrays that intersect output o's term range.
-struct RedIn {
+// Chunk reduction, all outputs of a call in one launch.  Job j writes out_j[x] (=|+=) the sum,
+// in increasing chunk order, of the chunks of up to three classes' partial arrays that
+// intersect output o's term range; the jobs' elements are laid end to end over the grid.
+struct RedJob {
   const kbe_c128 *a[3];
   int cls[3], nchunk[3];
-  int nparts, SC;
+  int nparts, nout, accumulate;
+  kbe_c128 *out;
+  int64_t start;  // first grid element of this job
 };
-__global__ void __launch_bounds__(256) reduce_kernel(Params p, RedIn in, int nout,
-                                                     kbe_c128 *out, int accumulate) {
+struct RedAll {
+  RedJob j[4];
+  int njob, SC;
+  int64_t total;
+};
+__global__ void __launch_bounds__(256) reduce_kernel(Params p, RedAll r) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= r.total) return;
+  int jb = 0;
+  while (jb + 1 < r.njob && g >= r.j[jb + 1].start) ++jb;
+  const RedJob &in = r.j[jb];
   const int64_t E = bsz(p);
-  const int64_t nel = (int64_t)nout * E;
-  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= nel) return;
+  const int64_t nel = (int64_t)in.nout * E;
+  const int64_t x = g - in.start;
   const int o = (int)(x / E);
   cd s = czero();
   for (int k = 0; k < in.nparts; ++k) {
     int lo, hi;
     range_rt(in.cls[k], p, o, lo, hi);
     if (hi <= lo) continue;
-    const int c0 = lo / in.SC;
-    int c1 = (hi - 1) / in.SC;
+    const int c0 = lo / r.SC;
+    int c1 = (hi - 1) / r.SC;
     if (c1 > in.nchunk[k] - 1) c1 = in.nchunk[k] - 1;
     for (int c = c0; c <= c1; ++c) s = s + ld(in.a[k] + (int64_t)c * nel + x);
   }
-  if (accumulate) s = s + ld(out + x);
-  st(out + x, s);
+  if (in.accumulate) s = s + ld(in.out + x);
+  st(in.out + x, s);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1339,10 +1350,13 @@ static void launch_kind(int kind, const Params &p, const FusedPlan &pl, char *ws
 }
 
 // Reduce the listed classes (those present in the plan) into out[nout][E].
+// Queue a reduction of the listed classes (those present in the plan) into out[nout][E].
 static void reduce_into(const Params &p, const FusedPlan &pl, std::initializer_list<int> classes,
-                        char *ws, int nout, kbe_c128 *out, bool accumulate, hipStream_t st) {
-  RedIn in{};
-  in.SC = pl.SC;
+                        char *ws, int nout, kbe_c128 *out, bool accumulate, RedAll &r) {
+  const int64_t nel = (int64_t)nout * p.N * p.N;
+  if (nel == 0 || r.njob >= 4) return;
+  RedJob &in = r.j[r.njob++];
+  in = RedJob{};
   for (int c : classes)
     for (int k = 0; k < pl.ncls; ++k)
       if (pl.cls[k] == c && in.nparts < 3) {
@@ -1351,10 +1365,17 @@ static void reduce_into(const Params &p, const FusedPlan &pl, std::initializer_l
         in.nchunk[in.nparts] = pl.nchunk[k];
         ++in.nparts;
       }
-  const int64_t nel = (int64_t)nout * p.N * p.N;
-  if (nel == 0) return;
-  hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)((nel + 255) / 256)), dim3(256), 0, st, p, in,
-                     nout, out, accumulate ? 1 : 0);
+  in.nout = nout;
+  in.accumulate = accumulate ? 1 : 0;
+  in.out = out;
+  in.start = r.total;
+  r.total += nel;
+}
+
+static void reduce_launch(const Params &p, const RedAll &r, hipStream_t st) {
+  if (r.total == 0) return;
+  hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)((r.total + 255) / 256)), dim3(256), 0, st, p,
+                     r);
 }
 
 hipError_t launch_collision(const Params &p, unsigned flags, kbe_c128 *IR, kbe_c128 *IL,
@@ -1365,10 +1386,13 @@ hipError_t launch_collision(const Params &p, unsigned flags, kbe_c128 *IR, kbe_c
   char *w = (char *)ws;
   launch_kind<false>(kind, p, pl, w, st);
   const int M = p.m1 - p.m0;
-  if (flags & KBE_OUT_IR) reduce_into(p, pl, {C_IRC, C_IRR}, w, M, IR, false, st);
-  if (flags & KBE_OUT_IL) reduce_into(p, pl, {C_IL}, w, M, IL, false, st);
-  if (flags & KBE_OUT_ITV) reduce_into(p, pl, {C_ITV}, w, M, Itv, false, st);
-  if ((flags & KBE_OUT_JTV) && p.ntau > 0) reduce_into(p, pl, {C_JR, C_JM1, C_JM2}, w, p.ntau, Jtv, false, st);
+  RedAll r{};
+  r.SC = pl.SC;
+  if (flags & KBE_OUT_IR) reduce_into(p, pl, {C_IRC, C_IRR}, w, M, IR, false, r);
+  if (flags & KBE_OUT_IL) reduce_into(p, pl, {C_IL}, w, M, IL, false, r);
+  if (flags & KBE_OUT_ITV) reduce_into(p, pl, {C_ITV}, w, M, Itv, false, r);
+  if ((flags & KBE_OUT_JTV) && p.ntau > 0) reduce_into(p, pl, {C_JR, C_JM1, C_JM2}, w, p.ntau, Jtv, false, r);
+  reduce_launch(p, r, st);
   return hipGetLastError();
 }
 
@@ -1381,9 +1405,13 @@ hipError_t launch_collision_vjp(const Params &p, unsigned flags, kbe_c128 *gmat,
   char *w = (char *)ws;
   launch_kind<true>(kind, p, pl, w, st);
   // self-energy gradients: overwritten
-  reduce_into(p, pl, {B_R1, B_R2, B_R3}, w, p.n + 1, gS->ret, false, st);
-  reduce_into(p, pl, {B_L}, w, p.n + 1, gS->les, false, st);
-  if (p.ntau > 0) reduce_into(p, pl, {B_T1, B_T2A, B_T2B}, w, p.ntau, gS->tv, false, st);
+  RedAll r{};
+  r.SC = pl.SC;
+  reduce_into(p, pl, {B_R1, B_R2, B_R3}, w, p.n + 1, gS->ret, false, r);
+  reduce_into(p, pl, {B_L}, w, p.n + 1, gS->les, false, r);
+  if (p.ntau > 0) reduce_into(p, pl, {B_T1, B_T2A, B_T2B}, w, p.ntau, gS->tv, false, r);
+  if (p.fJTV) reduce_into(p, pl, {G_MAT1, G_MAT2}, w, p.ntau, gmat, !p.overwrite, r);
+  reduce_launch(p, r, st);
   // Green's-function gradients
   const int64_t n1 = p.n + 1;
   const int64_t nblk = n1 * n1 + n1 + (p.ntau > 0 ? n1 * p.ntau : 0);
@@ -1402,7 +1430,6 @@ hipError_t launch_collision_vjp(const Params &p, unsigned flags, kbe_c128 *gmat,
     const int64_t th = nblk * p.N * p.N;
     hipLaunchKernelGGL(grad_generic, dim3((unsigned)((th + 255) / 256)), dim3(256), 0, st, p, nblk);
   }
-  if (p.fJTV) reduce_into(p, pl, {G_MAT1, G_MAT2}, w, p.ntau, gmat, !p.overwrite, st);
   return hipGetLastError();
 }
 
