@@ -143,6 +143,20 @@ def test_collision_small_blocks_several_chunks(gpu, N, nt, ntau):
     check_all(*run_collision(kbe, case))
 
 
+@pytest.mark.parametrize("flags", [oracle.F_IR, oracle.F_ITV | oracle.F_JTV,
+                                   oracle.F_IR | oracle.F_IL, oracle.F_ALL])
+def test_collision_small_blocks_output_subsets(gpu, flags):
+    """N = 8 over the full m range with output subsets (I^R alone, the two tau integrals alone,
+    I^R with I^<, all four), at the last row and with row n in the middle of the stored history
+    (the tasks stop short of the arrays' ends) and at n = 0."""
+    kbe = gpu
+    case = Case(N=8, nt=90, ntau=21, beta=2.0, seed=31)
+    for n in (89, 40, 0):
+        _print("output subsets", flags, n)
+        out = run_collision(kbe, case, n=n, flags=flags)
+        check_all(*out, flags=flags)
+
+
 @pytest.mark.parametrize("N", [2, 5, 8])
 def test_small_block_path_agrees_with_generic(gpu, N):
     """The small-block task and the generic one-output-per-wave task sum the same terms in
