@@ -250,6 +250,72 @@ kbe_status kbe_sigma_2b_vjp(const kbe_green *G, const double *u, int32_t n,
                             const kbe_sigma_row *gS, const kbe_green *gG, double *gu, void *ws,
                             size_t ws_bytes, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Batches of history rows (a project addition: many independent rows of
+ * different systems, orbital counts and lengths in one launch).
+ *
+ * An item is one row (t_n, t_m) of one system, given by the blocks that row
+ * reads (its "cross" storage), all device memory with the item's own N:
+ *   sig_ret, sig_les [n+1]  Sigma^R(t_n,t_s), Sigma^<(t_n,t_s), s = 0..n
+ *   sig_tv  [ntau]          Sigma^](t_n,tau_j)
+ *   col     [m+1]           kp[s][m] = G^<(t_s,t_m), s = 0..m
+ *   row     [n+1]           kp[m][s]: G^R(t_m,t_s) for s < m, G^<(t_m,t_s) for s >= m
+ *   rdiag   [1]             G^R(t_m,t_m)
+ *   tv      [ntau]          G^](t_m,tau_j)
+ *   wn [n+1], wm [m+1]      weight rows w[n][.] and w[m][.]; wtau [ntau]
+ * and it asks for the integrals of kbe_collision at that single (n, m):
+ *   IR  = sum_{s<=m} wn[s] sig_ret[s] col[s] - sum_{s>m} wn[s] sig_ret[s] row[s]^dagger
+ *   IL  = sum_{s<m} wm[s] sig_les[s] row[s]^dagger + wm[m] sig_les[m] rdiag^dagger
+ *   Itv = -i sum_j wtau[j] sig_tv[j] tv[J-j]^dagger
+ * (G^<(t_s,t_m) = -kp[m][s]^dagger for s > m; these are a3-a5 of kbe_collision
+ * with the row's blocks passed directly).  Outputs are one N x N block each.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t N;     /* orbitals, 1..KBE_NMAX */
+  int32_t n, m;  /* row and column, 0 <= m <= n */
+  int32_t ntau;  /* imaginary-time points: 0 or >= 2 */
+  uint32_t flags; /* KBE_OUT_IR | KBE_OUT_IL | KBE_OUT_ITV (J^] is not a per-row output) */
+  int32_t pad_;
+  const kbe_c128 *sig_ret, *sig_les, *sig_tv;
+  const kbe_c128 *col, *row, *rdiag, *tv;
+  const double *wn, *wm, *wtau;
+  kbe_c128 *IR, *IL, *Itv; /* one block each; NULL when its flag is off */
+} kbe_batch_item;
+
+#define KBE_BATCH_MAX 65536 /* most items per call */
+
+/* ---------------------------------------------------------------------------
+ * kbe_collision_batch — the items' integrals in one persistent launch.
+ *
+ * items: host array of count items (validated here); items_dev: the same array
+ * copied by the caller into device memory (what the kernels read; its content
+ * must equal items when the work runs).  chunk: terms per work unit, one of
+ * 32, 64, 128, 256, or 0 for the library default (see kbe_collision_batch_tune).
+ * ws: kbe_collision_batch_workspace(items, count, chunk) bytes.  Nothing is
+ * copied from host memory and nothing is allocated, so the call can be
+ * captured in a HIP graph and replayed.
+ * Errors: KBE_EINVAL (NULL pointers, N out of range, bad flags, chunk not
+ * allowed), KBE_ERANGE (m > n, negative sizes, count > KBE_BATCH_MAX),
+ * KBE_ENOMEM (workspace too small).
+ * ------------------------------------------------------------------------- */
+size_t kbe_collision_batch_workspace(const kbe_batch_item *items, int32_t count, int32_t chunk);
+kbe_status kbe_collision_batch(const kbe_batch_item *items, const kbe_batch_item *items_dev,
+                               int32_t count, int32_t chunk, void *ws, size_t ws_bytes,
+                               void *stream);
+
+/* ---------------------------------------------------------------------------
+ * kbe_collision_batch_tune — the autotuner: runs kbe_collision_batch on the
+ * given batch once per allowed chunk size (after one warm-up call each), times
+ * each with HIP events on the stream, and returns the fastest in *best_chunk
+ * (and, if times_ms is not NULL, the four times in the order 32, 64, 128,
+ * 256).  It synchronises the stream.  ws must hold the workspace of the
+ * largest requirement (chunk = 32).  Errors: as kbe_collision_batch, plus
+ * KBE_EHIP.
+ * ------------------------------------------------------------------------- */
+kbe_status kbe_collision_batch_tune(const kbe_batch_item *items, const kbe_batch_item *items_dev,
+                                    int32_t count, void *ws, size_t ws_bytes, void *stream,
+                                    int32_t *best_chunk, float *times_ms);
+
 /* Human-readable name of a status code (static string). */
 const char *kbe_status_string(kbe_status s);
 /* Detail of the last error on the calling thread ("" if none). */

@@ -56,6 +56,8 @@ def _load():
         lib.orc_sigma_row.argtypes = [I32, I32, I32, I64, P, P, P, P, I32, P, P, P]
         lib.orc_collision.argtypes = [I32, I32, I32, I64, P, P, P, P, P, P, P, P, P, P, P, I32, I32,
                                       I32, I32, I32, I32, P, P, P, P]
+        lib.orc_collision_row.argtypes = [I32, I32, I32, I32, P, P, P, P, P, P, P, P, P, P, I32,
+                                          P, P, P]
         lib.orc_collision_vjp.argtypes = [I32, I32, I32, I64, P, P, P, P, P, P, P, P, P, P, P, I32,
                                           I32, I32, I32, P, P, P, P, P, P, P, P, P, P, P]
         lib.orc_sigma_row_vjp.argtypes = [I32, I32, I32, I64, P, P, P, P, I32, P, P, P, P, P, P, P]
@@ -184,6 +186,23 @@ def collision(G: Green, sig, W: Weights, n: int, m0: int = 0, m1: int | None = N
                           _p(stv), _p(W.w), _p(W.wfull), _p(W.wf), _p(W.wb), n, m0, m1, j0, j1,
                           flags, _p(IR), _p(IL), _p(Itv), _p(Jtv))
     return IR, IL, Itv, Jtv
+
+
+def collision_row(N: int, ntau: int, n: int, m: int, sig, col, row, rdg, tvm, wn, wm, wfull,
+                  flags: int = F_IR | F_IL | F_ITV):
+    """(IR, IL, Itv) blocks at one (t_n, t_m) from the row's own blocks (see orc_collision_row):
+    sig = (ret [n+1], les [n+1], stv [ntau]); col [m+1] = kp[:m+1, m]; row [n+1] = kp[m, :n+1];
+    rdg = rdiag[m]; tvm [ntau] = tv[m]; wn [n+1], wm [m+1] weight rows; wfull [ntau]."""
+    ret, les, stv = (_c(x) for x in sig)
+    args = [_c(col), _c(row), _c(rdg), _c(tvm) if ntau > 0 else np.zeros((1, N, N), np.complex128),
+            _c(wn, np.float64), _c(wm, np.float64),
+            _c(wfull, np.float64) if ntau > 0 else np.zeros(1)]
+    if ntau == 0:
+        stv = np.zeros((1, N, N), np.complex128)
+    out = [np.zeros((N, N), np.complex128) for _ in range(3)]
+    _load().orc_collision_row(N, ntau, n, m, _p(ret), _p(les), _p(stv), *(_p(a) for a in args),
+                              flags, *(_p(o) for o in out))
+    return tuple(out)
 
 
 def collision_vjp(G: Green, sig, W: Weights, n: int, m0: int, m1: int, cot, flags: int = F_ALL,

@@ -395,6 +395,42 @@ void orc_collision(int N, int nt, int ntau, int64_t ldt, const cplx *kp, const c
   }
 }
 
+/* The integrals of orc_collision (IR, IL, Itv) at one point (t_n, t_m), from the
+ * blocks that row reads (its "cross"): col[s] = kp[s][m] for s <= m, row[s] =
+ * kp[m][s] for s <= n, rdg = G^R(t_m,t_m), tvm[j] = G^](t_m,tau_j); weight rows
+ * wn = w[n][.] and wm = w[m][.]; wfull the full-range tau rule.  By the lesser
+ * symmetry G^<(t_s,t_m) = col[s] for s <= m and -row[s]^dagger for s > m; G^R(t_m,t_s)
+ * is row[s] for s < m and rdg at s = m.  Same sums, same order as orc_collision. */
+void orc_collision_row(int N, int ntau, int n, int m, const cplx *ret, const cplx *les,
+                       const cplx *stv, const cplx *col, const cplx *row, const cplx *rdg,
+                       const cplx *tvm, const double *wn, const double *wm, const double *wfull,
+                       int flags, cplx *IR, cplx *IL, cplx *Itv) {
+  int64_t bs = (int64_t)N * N;
+  cplx blk[256];
+  if (flags & F_IR) {
+    memset(IR, 0, sizeof(cplx) * bs);
+    for (int s = 0; s <= n; ++s) {
+      if (s <= m) {
+        memcpy(blk, col + s * bs, sizeof(cplx) * bs);
+      } else {
+        const cplx *x = row + s * bs;
+        for (int i = 0; i < N; ++i)
+          for (int j = 0; j < N; ++j) blk[i * N + j] = -conj(x[j * N + i]);
+      }
+      mm_acc(N, IR, wn[s], ret + s * bs, blk, 0);
+    }
+  }
+  if (flags & F_IL) {
+    memset(IL, 0, sizeof(cplx) * bs);
+    for (int s = 0; s <= m; ++s) mm_acc(N, IL, wm[s], les + s * bs, s < m ? row + s * bs : rdg, 1);
+  }
+  if (flags & F_ITV) {
+    memset(Itv, 0, sizeof(cplx) * bs);
+    for (int j = 0; j < ntau; ++j)
+      mm_acc(N, Itv, -I * wfull[j], stv + j * bs, tvm + tau_mirror(ntau, j) * bs, 1);
+  }
+}
+
 /* ------------------------------------------------------------------------- */
 /* Adjoint (vector-Jacobian product) of orc_collision.  Complex gradients     */
 /* follow PyTorch's convention: for real loss L and complex z the gradient is */

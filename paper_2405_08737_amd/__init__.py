@@ -52,9 +52,17 @@ class _Wts(ctypes.Structure):
     _fields_ = [("w", ctypes.c_void_p), ("wtau", ctypes.c_void_p), ("wtau_fwd", ctypes.c_void_p)]
 
 
+class _BatchItem(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("n", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("ntau", ctypes.c_int32), ("flags", ctypes.c_uint32), ("pad_", ctypes.c_int32)] + [
+        (name, ctypes.c_void_p) for name in ("sig_ret", "sig_les", "sig_tv", "col", "row", "rdiag",
+                                             "tv", "wn", "wm", "wtau", "IR", "IL", "Itv")]
+
+
 EXPORTS = ("kbe_weights_workspace", "kbe_weights", "kbe_sigma_2b", "kbe_collision_workspace",
            "kbe_collision", "kbe_collision_vjp_workspace", "kbe_collision_vjp",
-           "kbe_sigma_2b_vjp_workspace", "kbe_sigma_2b_vjp", "kbe_status_string",
+           "kbe_sigma_2b_vjp_workspace", "kbe_sigma_2b_vjp", "kbe_collision_batch_workspace",
+           "kbe_collision_batch", "kbe_collision_batch_tune", "kbe_status_string",
            "kbe_last_error", "kbe_version")
 
 
@@ -79,6 +87,9 @@ def lib():
             "kbe_collision_vjp": (I32, [G, R, W, I32, I32, I32, U32, P, P, P, P, G, R, P, SZ, P]),
             "kbe_sigma_2b_vjp_workspace": (SZ, [I32, I32, I32]),
             "kbe_sigma_2b_vjp": (I32, [G, P, I32, R, G, P, P, SZ, P]),
+            "kbe_collision_batch_workspace": (SZ, [P, I32, I32]),
+            "kbe_collision_batch": (I32, [P, P, I32, I32, P, SZ, P]),
+            "kbe_collision_batch_tune": (I32, [P, P, I32, P, SZ, P, P, P]),
             "kbe_status_string": (ctypes.c_char_p, [I32]),
             "kbe_last_error": (ctypes.c_char_p, []),
             "kbe_version": (I32, []),
@@ -303,3 +314,85 @@ class KBECollision(torch.autograd.Function):
         gG, (gret, gles, gstv) = collision_vjp(G, (ret, les, stv), ctx.W, ctx.n, ctx.m0, ctx.m1,
                                                (gIR, gIL, gItv, gJ), ctx.flags)
         return gG.kp, gG.rdiag, gG.tv, gG.mat, gret, gles, gstv, None, None, None, None
+
+
+# ------------------------------------------------------------------------------------------
+# Batches of history rows (kbe_collision_batch).
+# ------------------------------------------------------------------------------------------
+@dataclass
+class BatchItem:
+    """One history row (t_n, t_m) of one system in cross storage (device tensors of that system's
+    N; layout in include/kbe.h): the self-energy row at t_n, kp column m (rows 0..m), kp row m
+    (columns 0..n), G^R(t_m, t_m), tv row m, the weight rows w[n][:n+1] and w[m][:m+1], the tau
+    rule.  flags selects I^R, I^<, I^] (OUT_IR | OUT_IL | OUT_ITV)."""
+    n: int
+    m: int
+    sig_ret: torch.Tensor              # [n+1, N, N]
+    sig_les: torch.Tensor              # [n+1, N, N]
+    col: torch.Tensor                  # [m+1, N, N]
+    row: torch.Tensor                  # [n+1, N, N]
+    rdiag: torch.Tensor                # [N, N]
+    wn: torch.Tensor                   # [n+1] float64
+    wm: torch.Tensor                   # [m+1] float64
+    sig_tv: Optional[torch.Tensor] = None  # [ntau, N, N]
+    tv: Optional[torch.Tensor] = None      # [ntau, N, N]
+    wtau: Optional[torch.Tensor] = None    # [ntau] float64
+    flags: int = OUT_IR | OUT_IL | OUT_ITV
+
+    @property
+    def N(self):
+        return self.rdiag.shape[-1]
+
+    @property
+    def ntau(self):
+        return 0 if self.tv is None else self.tv.shape[0]
+
+
+class Batch:
+    """A fixed batch of rows: the item table (host array and device copy), the outputs and the
+    workspace are allocated once; run() then only enqueues the library call, so it can be
+    captured in a CUDA/HIP graph and replayed.  Outputs: self.IR[i], self.IL[i], self.Itv[i]
+    (N x N blocks; None where the item's flag is off)."""
+
+    def __init__(self, items, device=None):
+        self.items = list(items)
+        self.count = len(self.items)
+        dev = device if device is not None else self.items[0].rdiag.device
+        self.device = dev
+        mk = lambda it, f: (torch.empty((it.N, it.N), dtype=torch.complex128, device=dev)
+                            if it.flags & f else None)
+        self.IR = [mk(it, OUT_IR) for it in self.items]
+        self.IL = [mk(it, OUT_IL) for it in self.items]
+        self.Itv = [mk(it, OUT_ITV) for it in self.items]
+        host = (_BatchItem * max(self.count, 1))()
+        for i, it in enumerate(self.items):
+            host[i] = _BatchItem(it.N, it.n, it.m, it.ntau, it.flags, 0, _ptr(it.sig_ret),
+                                 _ptr(it.sig_les), _ptr(it.sig_tv), _ptr(it.col), _ptr(it.row),
+                                 _ptr(it.rdiag), _ptr(it.tv), _ptr(it.wn), _ptr(it.wm),
+                                 _ptr(it.wtau), _ptr(self.IR[i]), _ptr(self.IL[i]),
+                                 _ptr(self.Itv[i]))
+        self._host = host
+        raw = bytes(host)[:ctypes.sizeof(_BatchItem) * self.count]
+        self._dev = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(dev)
+        L = lib()
+        self.ws_bytes = L.kbe_collision_batch_workspace(host, self.count, 32)  # the largest chunk need
+        if self.count and self.ws_bytes == 0:
+            raise KBEError("kbe_collision_batch_workspace: invalid items")
+        self.ws = _ws(self.ws_bytes, dev)
+
+    def run(self, chunk: int = 0):
+        """Enqueue kbe_collision_batch on the current stream (chunk 0: the library default)."""
+        _check(lib().kbe_collision_batch(self._host, _ptr(self._dev), self.count, chunk,
+                                         _ptr(self.ws), self.ws_bytes, _stream(self.device)),
+               "kbe_collision_batch")
+        return self.IR, self.IL, self.Itv
+
+    def tune(self):
+        """The library's autotuner: (best chunk, {chunk: ms})."""
+        best = ctypes.c_int32(0)
+        times = (ctypes.c_float * 4)()
+        _check(lib().kbe_collision_batch_tune(self._host, _ptr(self._dev), self.count,
+                                              _ptr(self.ws), self.ws_bytes, _stream(self.device),
+                                              ctypes.byref(best), times),
+               "kbe_collision_batch_tune")
+        return best.value, dict(zip((32, 64, 128, 256), list(times)))

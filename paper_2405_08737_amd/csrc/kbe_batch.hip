@@ -1,0 +1,382 @@
+// Batches of history rows (the integrals of Eq. KBE2 at single (t_n, t_m) points of many
+// independent systems), one persistent launch per call.
+//
+// Work unit ("task"): one wave sums one chunk of terms of one term class of one item:
+//   IRC: s in [0, m]      wn[s] sig_ret[s] col[s]                      (Q P)
+//   IRR: s in (m, n]     -wn[s] sig_ret[s] row[s]^dagger               (Q P^dagger)
+//   IL : s in [0, m]      wm[s] sig_les[s] (row[s] | rdiag)^dagger     (Q P^dagger)
+//   ITV: j in [0, ntau)  -i wtau[j] sig_tv[j] tv[J-j]^dagger           (Q P^dagger)
+// Both factors of a term are streamed (nothing is shared between terms), so the work is bound by
+// HBM bandwidth at every N (N/4 FLOP per byte).  Each wave takes tasks from one atomic counter
+// and runs the code path of its item's N: blocks zero-padded to 8 x 8 (N <= 8) or 16 x 16
+// (9 <= N <= 16), multiplied with v_mfma_f64_4x4x4, three real products per complex one:
+//   k1 += (ar + ai) br,  k2 += ar (bi - br),  k3 += ai (br + bi);  Re = k1 - k3, Im = k1 + k2.
+// A task writes its partial sum to the workspace; a reduce adds an item's partials in task
+// order, so results are deterministic.  The task plan (per-item task and partial offsets) is
+// computed on the device from the item array, so a call copies nothing from host memory.
+#include "kbe_dev.h"
+#include "kbe_internal.h"
+
+namespace kbe {
+
+namespace {
+
+constexpr int BQLD = 20;  // LDS row stride of a staged 16 x 16 block, in complex numbers
+
+__device__ __forceinline__ double mfma4b(double a, double b, double c) {
+  return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ int cdivd(int a, int b) { return (a + b - 1) / b; }
+
+// Chunks per term class of an item: IRC, IRR, IL, ITV.
+__host__ __device__ inline void item_chunks(const kbe_batch_item &it, int chunk, int c[4]) {
+  const bool ir = it.flags & KBE_OUT_IR, il = it.flags & KBE_OUT_IL;
+  const bool itv = (it.flags & KBE_OUT_ITV) && it.ntau > 0;
+  c[0] = ir ? (it.m + 1 + chunk - 1) / chunk : 0;
+  c[1] = ir ? (it.n - it.m + chunk - 1) / chunk : 0;
+  c[2] = il ? (it.m + 1 + chunk - 1) / chunk : 0;
+  c[3] = itv ? (it.ntau + chunk - 1) / chunk : 0;
+}
+
+// Term t of class k of an item: real weight w, complex factor (fr + i fi), Q and P blocks.
+struct Term {
+  double w;
+  const kbe_c128 *Q, *P;
+};
+__device__ __forceinline__ Term item_term(const kbe_batch_item &it, int k, int t) {
+  const int64_t E = (int64_t)it.N * it.N;
+  switch (k) {
+    case 0: return {it.wn[t], it.sig_ret + t * E, it.col + t * E};
+    case 1: return {it.wn[t], it.sig_ret + t * E, it.row + t * E};
+    case 2: return {it.wm[t], it.sig_les + t * E, t < it.m ? it.row + t * E : it.rdiag};
+    default: return {it.wtau[t], it.sig_tv + t * E, it.tv + (it.ntau - 1 - t) * E};
+  }
+}
+
+// Term range [lo, hi) of class k.
+__device__ __forceinline__ void item_range(const kbe_batch_item &it, int k, int &lo, int &hi) {
+  switch (k) {
+    case 0: lo = 0; hi = it.m + 1; break;
+    case 1: lo = it.m + 1; hi = it.n + 1; break;
+    case 2: lo = 0; hi = it.m + 1; break;
+    default: lo = 0; hi = it.ntau; break;
+  }
+}
+
+// c = (fr + i fi) w per class: IRC 1, IRR -1, IL 1, ITV -i.
+__device__ __forceinline__ cd class_factor(int k, double w) {
+  return k == 1 ? cd{-w, 0.0} : (k == 3 ? cd{0.0, -w} : cd{w, 0.0});
+}
+
+// ---------------------------------------------------------------------------------------
+// N <= 8: blocks padded to 8 x 8; one instruction computes the four 4 x 4 tiles (ti, tj) of the
+// product (instruction block b = 2 ti + tj).  Lane roles: A element (4ti + lj, 4kc + lk) of
+// c Q, B element (4kc + lk, 4tj + lj) of P, or conj of P's (4tj + lj, 4kc + lk) for P^dagger,
+// D element (4ti + lk, 4tj + lj).  Terms are loaded three ahead of their use.
+// ---------------------------------------------------------------------------------------
+__device__ void task8(const kbe_batch_item &it, int k, int t0, int t1, kbe_c128 *out, int lane) {
+  const int N = it.N;
+  const bool dag = k != 0;
+  const int lj = lane & 3, lk = lane >> 4, tb = (lane >> 2) & 3, ti = tb >> 1, tj = tb & 1;
+  bool av[2], bv[2];
+  int ao[2], bo[2];
+#pragma unroll
+  for (int kc = 0; kc < 2; ++kc) {
+    const int ra = 4 * ti + lj, ca = 4 * kc + lk;
+    av[kc] = ra < N && ca < N;
+    ao[kc] = av[kc] ? ra * N + ca : 0;
+    const int rb = dag ? 4 * tj + lj : 4 * kc + lk, cb = dag ? 4 * kc + lk : 4 * tj + lj;
+    bv[kc] = rb < N && cb < N;
+    bo[kc] = bv[kc] ? rb * N + cb : 0;
+  }
+  struct Buf {
+    double w;
+    cd q[2], x[2];
+  };
+  auto load = [&](int t, Buf &b) {
+    t = t < t1 ? t : t1 - 1;
+    const Term tm = item_term(it, k, t);
+    b.w = tm.w;
+#pragma unroll
+    for (int kc = 0; kc < 2; ++kc) {
+      b.q[kc] = ldg(tm.Q + ao[kc]);
+      b.x[kc] = ldg(tm.P + bo[kc]);
+    }
+  };
+  double k1 = 0.0, k2 = 0.0, k3 = 0.0;
+  auto compute = [&](const Buf &b) {
+    const cd c = class_factor(k, b.w);
+#pragma unroll
+    for (int kc = 0; kc < 2; ++kc) {
+      const cd q = av[kc] ? c * b.q[kc] : czero();
+      cd x = bv[kc] ? b.x[kc] : czero();
+      if (dag) x.im = -x.im;
+      k1 = mfma4b(q.re + q.im, x.re, k1);
+      k2 = mfma4b(q.re, x.im - x.re, k2);
+      k3 = mfma4b(q.im, x.re + x.im, k3);
+    }
+  };
+  Buf bf[4];
+  load(t0, bf[0]);
+  load(t0 + 1, bf[1]);
+  load(t0 + 2, bf[2]);
+  for (int t = t0; t < t1; t += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (t + u >= t1) break;  // wave-uniform
+      load(t + u + 3, bf[(u + 3) & 3]);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(bf[u]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  const int dr = 4 * ti + lk, dc = 4 * tj + lj;
+  if (dr < N && dc < N) stg(out + dr * N + dc, cd{k1 - k3, k1 + k2});
+}
+
+// ---------------------------------------------------------------------------------------
+// 9 <= N <= 16: blocks padded to 16 x 16, the layout of the N = 16 collision task: the wave
+// stages c Q in its own LDS tile (rows padded to BQLD complex numbers), lane l supplies
+// A[4ti + l%4][4kc + l/16] from it and the slab B[4kc + l/16][l%16] of P (or P^dagger), and
+// accumulator ti holds D[4ti + l/16][l%16].  The next term's Q and P are in flight during a
+// term's products.
+// ---------------------------------------------------------------------------------------
+__device__ void task16(const kbe_batch_item &it, int k, int t0, int t1, kbe_c128 *out, int lane,
+                       cd *qs) {
+  const int N = it.N;
+  const bool dag = k != 0;
+  const int lr = lane & 3, lk = lane >> 4, lc = lane & 15;
+  int qo[4], bo[4];
+  bool qv[4], bv[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = lane + 64 * u, r = e >> 4, c = e & 15;  // Q element staged by this lane
+    qv[u] = r < N && c < N;
+    qo[u] = qv[u] ? r * N + c : 0;
+    const int rb = dag ? lc : 4 * u + lk, cb = dag ? 4 * u + lk : lc;  // B slab u element
+    bv[u] = rb < N && cb < N;
+    bo[u] = bv[u] ? rb * N + cb : 0;
+  }
+  struct Buf {
+    double w;
+    cd q[4], x[4];
+  };
+  auto load = [&](int t, Buf &b) {
+    t = t < t1 ? t : t1 - 1;
+    const Term tm = item_term(it, k, t);
+    b.w = tm.w;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      b.q[u] = ldg(tm.Q + qo[u]);
+      b.x[u] = ldg(tm.P + bo[u]);
+    }
+  };
+  double k1[4] = {0, 0, 0, 0}, k2[4] = {0, 0, 0, 0}, k3[4] = {0, 0, 0, 0};
+  auto compute = [&](const Buf &b) {
+    const cd c = class_factor(k, b.w);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = lane + 64 * u;
+      qs[(e >> 4) * BQLD + (e & 15)] = qv[u] ? c * b.q[u] : czero();
+    }
+    // the wave's own LDS writes are complete before its reads (in-order LDS queue); the
+    // compiler keeps the order since the accesses may alias
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) {
+      cd x = bv[kc] ? b.x[kc] : czero();
+      if (dag) x.im = -x.im;
+      const double br = x.re, bd = x.im - x.re, bp = x.re + x.im;
+#pragma unroll
+      for (int ti = 0; ti < 4; ++ti) {
+        const cd a = qs[(4 * ti + lr) * BQLD + 4 * kc + lk];
+        k1[ti] = mfma4b(a.re + a.im, br, k1[ti]);
+        k2[ti] = mfma4b(a.re, bd, k2[ti]);
+        k3[ti] = mfma4b(a.im, bp, k3[ti]);
+      }
+    }
+  };
+  Buf ba, bb;
+  load(t0, ba);
+  for (int t = t0; t < t1; t += 2) {
+    load(t + 1, bb);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(ba);
+    __builtin_amdgcn_sched_barrier(0);
+    if (t + 1 >= t1) break;  // wave-uniform
+    load(t + 2, ba);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(bb);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int ti = 0; ti < 4; ++ti) {
+    const int r = 4 * ti + lk;
+    if (r < N && lc < N) stg(out + r * N + lc, cd{k1[ti] - k3[ti], k1[ti] + k2[ti]});
+  }
+}
+
+}  // namespace
+
+// Plan: per-item task offsets tb[count+1] and partial offsets pb[count+1] (complex numbers),
+// exclusive scans in item order; also zeroes the task counter.  One workgroup of 1024 threads.
+__global__ void __launch_bounds__(1024) batch_plan(const kbe_batch_item *items, int count,
+                                                   int chunk, int64_t *tb, int64_t *pb,
+                                                   unsigned int *head) {
+  __shared__ int64_t st[1024], sp[1024];
+  int64_t carry_t = 0, carry_p = 0;
+  for (int base = 0; base < count; base += 1024) {
+    const int i = base + (int)threadIdx.x;
+    int64_t nt = 0, np = 0;
+    if (i < count) {
+      int c[4];
+      item_chunks(items[i], chunk, c);
+      nt = c[0] + c[1] + c[2] + c[3];
+      np = nt * (int64_t)items[i].N * items[i].N;
+    }
+    st[threadIdx.x] = nt;
+    sp[threadIdx.x] = np;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {  // inclusive scan (Hillis-Steele)
+      const int64_t a = threadIdx.x >= (unsigned)off ? st[threadIdx.x - off] : 0;
+      const int64_t b = threadIdx.x >= (unsigned)off ? sp[threadIdx.x - off] : 0;
+      __syncthreads();
+      st[threadIdx.x] += a;
+      sp[threadIdx.x] += b;
+      __syncthreads();
+    }
+    if (i < count) {
+      tb[i] = carry_t + st[threadIdx.x] - nt;
+      pb[i] = carry_p + sp[threadIdx.x] - np;
+    }
+    carry_t += st[1023];
+    carry_p += sp[1023];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    tb[count] = carry_t;
+    pb[count] = carry_p;
+    head[0] = 0u;
+  }
+}
+
+// Persistent: every wave takes tasks from the counter until none are left.
+__global__ void __launch_bounds__(256) batch_stream(const kbe_batch_item *items, int count,
+                                                    int chunk, const int64_t *tb,
+                                                    const int64_t *pb, kbe_c128 *parts,
+                                                    unsigned int *head) {
+  __shared__ cd qtile[4][16 * BQLD];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t ntask = tb[count];
+  for (;;) {
+    unsigned int v = 0;
+    if (lane == 0) v = atomicAdd(head, 1u);
+    const int64_t task = (int64_t)__builtin_amdgcn_readfirstlane(v);
+    if (task >= ntask) break;  // wave-uniform
+    // item: the last i with tb[i] <= task (binary search over the offsets)
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (tb[mid] <= task) lo = mid;
+      else hi = mid - 1;
+    }
+    const int i = __builtin_amdgcn_readfirstlane(lo);
+    const kbe_batch_item it = items[i];
+    int c[4];
+    item_chunks(it, chunk, c);
+    int local = (int)(task - tb[i]), k = 0;
+    while (local >= c[k]) local -= c[k++];
+    int t0, t1;
+    item_range(it, k, t0, t1);
+    t0 += local * chunk;
+    t1 = t0 + chunk < t1 ? t0 + chunk : t1;
+    kbe_c128 *out = parts + pb[i] + (task - tb[i]) * (int64_t)it.N * it.N;
+    if (it.N <= 8) task8(it, k, t0, t1, out, lane);
+    else task16(it, k, t0, t1, out, lane, qtile[wave]);
+  }
+}
+
+// One workgroup per item: element e of each selected output = its tasks' partials in order.
+__global__ void __launch_bounds__(256) batch_reduce(const kbe_batch_item *items, int chunk,
+                                                    const int64_t *tb, const int64_t *pb,
+                                                    const kbe_c128 *parts) {
+  const kbe_batch_item it = items[blockIdx.x];
+  const int E = it.N * it.N, e = threadIdx.x;
+  if (e >= E) return;
+  int c[4];
+  item_chunks(it, chunk, c);
+  const kbe_c128 *p = parts + pb[blockIdx.x] + e;
+  auto sum = [&](int a, int b) {
+    cd s = czero();
+    for (int L = a; L < b; ++L) s = s + ldg(p + (int64_t)L * E);
+    return s;
+  };
+  const int irb = c[0] + c[1], ilb = irb + c[2], itb = ilb + c[3];
+  if (it.flags & KBE_OUT_IR) stg(it.IR + e, sum(0, irb));
+  if (it.flags & KBE_OUT_IL) stg(it.IL + e, sum(irb, ilb));
+  if (it.flags & KBE_OUT_ITV) stg(it.Itv + e, sum(ilb, itb));
+}
+
+// ---------------------------------------------------------------------------------------
+// Host side.
+// ---------------------------------------------------------------------------------------
+static size_t al256b(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int batch_default_chunk() { return 64; }
+
+size_t batch_ws_bytes(const kbe_batch_item *items, int count, int chunk) {
+  int64_t parts = 0;
+  for (int i = 0; i < count; ++i) {
+    int c[4];
+    item_chunks(items[i], chunk, c);
+    parts += (int64_t)(c[0] + c[1] + c[2] + c[3]) * items[i].N * items[i].N;
+  }
+  return 2 * al256b(sizeof(int64_t) * (size_t)(count + 1)) + 256 +
+         sizeof(kbe_c128) * (size_t)parts;
+}
+
+static int batch_grid() {
+  static int cached[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 1024;
+  int &c = cached[dev];
+  if (c == 0) {
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_stream, 256, 0) != hipSuccess ||
+        per_cu < 1)
+      per_cu = 1;
+    c = cus * per_cu;
+  }
+  return c;
+}
+
+hipError_t launch_batch(const kbe_batch_item *items, const kbe_batch_item *items_dev, int count,
+                        int chunk, void *ws, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  char *w = (char *)ws;
+  int64_t *tb = (int64_t *)w;
+  int64_t *pb = (int64_t *)(w + al256b(sizeof(int64_t) * (size_t)(count + 1)));
+  unsigned int *head = (unsigned int *)(w + 2 * al256b(sizeof(int64_t) * (size_t)(count + 1)));
+  kbe_c128 *parts = (kbe_c128 *)((char *)head + 256);
+  int64_t ntask = 0;
+  for (int i = 0; i < count; ++i) {
+    int c[4];
+    item_chunks(items[i], chunk, c);
+    ntask += c[0] + c[1] + c[2] + c[3];
+  }
+  hipLaunchKernelGGL(batch_plan, dim3(1), dim3(1024), 0, st, items_dev, count, chunk, tb, pb,
+                     head);
+  if (ntask > 0) {
+    int64_t grid = batch_grid();
+    const int64_t need = (ntask + 3) / 4;  // four waves per workgroup
+    if (grid > need) grid = need;
+    hipLaunchKernelGGL(batch_stream, dim3((unsigned)grid), dim3(256), 0, st, items_dev, count,
+                       chunk, tb, pb, parts, head);
+  }
+  hipLaunchKernelGGL(batch_reduce, dim3((unsigned)count), dim3(256), 0, st, items_dev, chunk, tb,
+                     pb, parts);
+  return hipGetLastError();
+}
+
+}  // namespace kbe

@@ -245,4 +245,106 @@ kbe_status kbe_collision_vjp(const kbe_green *G, const kbe_sigma_row *S, const k
                     "kbe_collision_vjp");
 }
 
+// ---------------------------------------------------------------------------------------
+// Batches of history rows.
+// ---------------------------------------------------------------------------------------
+static bool batch_chunk_ok(int32_t chunk) {
+  return chunk == 0 || chunk == 32 || chunk == 64 || chunk == 128 || chunk == 256;
+}
+
+static kbe_status check_batch(const kbe_batch_item *items, const kbe_batch_item *items_dev,
+                              int32_t count, int32_t chunk) {
+  if (count < 0 || count > KBE_BATCH_MAX)
+    return fail(KBE_ERANGE, "count = %d outside [0, %d]", count, KBE_BATCH_MAX);
+  if (!batch_chunk_ok(chunk)) return fail(KBE_EINVAL, "chunk = %d not in {0, 32, 64, 128, 256}", chunk);
+  if (count == 0) return ok();
+  if (!items || !items_dev) return fail(KBE_EINVAL, "items or items_dev is NULL");
+  const unsigned known = KBE_OUT_IR | KBE_OUT_IL | KBE_OUT_ITV;
+  for (int32_t i = 0; i < count; ++i) {
+    const kbe_batch_item &it = items[i];
+    if (it.N < 1 || it.N > KBE_NMAX)
+      return fail(KBE_EINVAL, "item %d: N = %d outside 1..%d", i, it.N, KBE_NMAX);
+    if (it.flags & ~known) return fail(KBE_EINVAL, "item %d: unknown flag bits 0x%x", i, it.flags);
+    if (it.n < 0 || it.m < 0 || it.m > it.n)
+      return fail(KBE_ERANGE, "item %d: (n, m) = (%d, %d) needs 0 <= m <= n", i, it.n, it.m);
+    if (it.ntau < 0 || it.ntau == 1)
+      return fail(KBE_EINVAL, "item %d: ntau = %d (must be 0 or >= 2)", i, it.ntau);
+    if (it.flags & KBE_OUT_IR) {
+      if (!it.IR || !it.sig_ret || !it.col || !it.wn || (it.n > it.m && !it.row))
+        return fail(KBE_EINVAL, "item %d: I^R needs IR, sig_ret, col, wn (and row when n > m)", i);
+    }
+    if (it.flags & KBE_OUT_IL) {
+      if (!it.IL || !it.sig_les || !it.rdiag || !it.wm || (it.m > 0 && !it.row))
+        return fail(KBE_EINVAL, "item %d: I^< needs IL, sig_les, rdiag, wm (and row when m > 0)", i);
+    }
+    if (it.flags & KBE_OUT_ITV) {
+      if (!it.Itv) return fail(KBE_EINVAL, "item %d: Itv is NULL", i);
+      if (it.ntau > 0 && (!it.sig_tv || !it.tv || !it.wtau))
+        return fail(KBE_EINVAL, "item %d: I^] needs sig_tv, tv, wtau with ntau > 0", i);
+    }
+  }
+  return ok();
+}
+
+size_t kbe_collision_batch_workspace(const kbe_batch_item *items, int32_t count, int32_t chunk) {
+  if (count <= 0 || count > KBE_BATCH_MAX || !items || !batch_chunk_ok(chunk)) return 0;
+  for (int32_t i = 0; i < count; ++i)
+    if (items[i].N < 1 || items[i].N > KBE_NMAX || items[i].m < 0 || items[i].m > items[i].n ||
+        items[i].ntau < 0)
+      return 0;
+  return kbe::batch_ws_bytes(items, count, chunk ? chunk : kbe::batch_default_chunk());
+}
+
+kbe_status kbe_collision_batch(const kbe_batch_item *items, const kbe_batch_item *items_dev,
+                               int32_t count, int32_t chunk, void *ws, size_t ws_bytes,
+                               void *stream) {
+  kbe_status s = check_batch(items, items_dev, count, chunk);
+  if (s != KBE_OK || count == 0) return s;
+  const int c = chunk ? chunk : kbe::batch_default_chunk();
+  const size_t need = kbe::batch_ws_bytes(items, count, c);
+  if (!ws || ws_bytes < need) return fail(KBE_ENOMEM, "workspace %zu bytes < %zu", ws_bytes, need);
+  return hip_status(kbe::launch_batch(items, items_dev, count, c, ws, (hipStream_t)stream),
+                    "kbe_collision_batch");
+}
+
+kbe_status kbe_collision_batch_tune(const kbe_batch_item *items, const kbe_batch_item *items_dev,
+                                    int32_t count, void *ws, size_t ws_bytes, void *stream,
+                                    int32_t *best_chunk, float *times_ms) {
+  kbe_status s = check_batch(items, items_dev, count, 0);
+  if (s != KBE_OK) return s;
+  if (!best_chunk) return fail(KBE_EINVAL, "best_chunk is NULL");
+  static const int cand[4] = {32, 64, 128, 256};
+  *best_chunk = kbe::batch_default_chunk();
+  if (count == 0) return ok();
+  const size_t need = kbe::batch_ws_bytes(items, count, 32);  // the largest requirement
+  if (!ws || ws_bytes < need) return fail(KBE_ENOMEM, "workspace %zu bytes < %zu", ws_bytes, need);
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return hip_status(hipGetLastError(), "hipEventCreate");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return hip_status(hipGetLastError(), "hipEventCreate");
+  }
+  float best = -1.0f;
+  hipError_t err = hipSuccess;
+  for (int k = 0; k < 4 && err == hipSuccess; ++k) {
+    err = kbe::launch_batch(items, items_dev, count, cand[k], ws, st);  // warm-up
+    if (err == hipSuccess) err = hipEventRecord(e0, st);
+    if (err == hipSuccess) err = kbe::launch_batch(items, items_dev, count, cand[k], ws, st);
+    if (err == hipSuccess) err = hipEventRecord(e1, st);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    if (err != hipSuccess) break;
+    if (times_ms) times_ms[k] = ms;
+    if (best < 0.0f || ms < best) {
+      best = ms;
+      *best_chunk = cand[k];
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  return hip_status(err, "kbe_collision_batch_tune");
+}
+
 }  // extern "C"

@@ -30,4 +30,10 @@ size_t collision_vjp_ws_bytes(int N, int nt, int ntau, int n, int m0, int m1, un
 hipError_t launch_collision_vjp(const Params &p, unsigned flags, kbe_c128 *gmat,
                                 const kbe_sigma_row *gS, void *ws, hipStream_t st);
 
+// Batches of history rows (kbe_batch.hip).
+int batch_default_chunk();
+size_t batch_ws_bytes(const kbe_batch_item *items, int count, int chunk);
+hipError_t launch_batch(const kbe_batch_item *items, const kbe_batch_item *items_dev, int count,
+                        int chunk, void *ws, hipStream_t st);
+
 }  // namespace kbe

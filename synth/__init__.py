@@ -46,6 +46,8 @@ def _load():
                                    c.c_int32, P, P]
         lib.synth_kp_rows.argtypes = [c.c_uint64, c.c_int32, c.c_int32, c.c_int64, P, c.c_double,
                                       c.c_int32, c.c_int32, P]
+        lib.synth_kp_col.argtypes = [c.c_uint64, c.c_int32, c.c_int32, P, c.c_double, c.c_int32,
+                                     c.c_int32, c.c_int32, P]
         lib.synth_rdiag.argtypes = [c.c_int32, c.c_int32, P]
         lib.synth_tv_rows.argtypes = [c.c_uint64, c.c_int32, c.c_int32, P, c.c_double, c.c_int32,
                                       c.c_int32, P]
@@ -53,7 +55,7 @@ def _load():
         lib.synth_sigma_row.argtypes = [c.c_uint64, c.c_int32, c.c_int32, c.c_int32, P, c.c_double,
                                         P, P, P]
         lib.synth_normal.argtypes = [c.c_uint64, c.c_uint64, c.c_int64, P]
-        for f in (lib.synth_grid, lib.synth_kp_rows, lib.synth_rdiag, lib.synth_tv_rows,
+        for f in (lib.synth_grid, lib.synth_kp_rows, lib.synth_kp_col, lib.synth_rdiag, lib.synth_tv_rows,
                   lib.synth_mat, lib.synth_sigma_row, lib.synth_normal):
             f.restype = None
         _lib = lib
@@ -83,6 +85,15 @@ def kp(seed: int, N: int, t: np.ndarray, decay: float = 0.3, rows=None, ldt: int
         out = np.zeros((a1 - a0, ldt, N, N), np.complex128)
     assert out.shape == (a1 - a0, ldt, N, N) and out.dtype == np.complex128
     _load().synth_kp_rows(seed, N, nt, ldt, _ptr(np.ascontiguousarray(t)), decay, a0, a1, _ptr(out))
+    return out
+
+
+def kp_col(seed: int, N: int, t: np.ndarray, col: int, rows=None, decay: float = 0.3) -> np.ndarray:
+    """Column `col` of the KP array of `kp(seed, N, t)`, rows [a0, a1): shape (a1-a0, N, N)."""
+    nt = len(t)
+    a0, a1 = (0, nt) if rows is None else rows
+    out = np.zeros((a1 - a0, N, N), np.complex128)
+    _load().synth_kp_col(seed, N, nt, _ptr(np.ascontiguousarray(t)), decay, col, a0, a1, _ptr(out))
     return out
 
 
@@ -159,3 +170,47 @@ def green(w: Workload, decay: float = 0.3, ldt: int | None = None):
     t, order = grid(w.seed, w.nt, w.hmin, w.hmax, w.omin, w.omax)
     return dict(t=t, order=order, kp=kp(w.seed, w.N, t, decay, ldt=ldt), rdiag=rdiag(w.N, w.nt),
                 tv=tv(w.seed, w.N, w.ntau, t, decay), mat=mat(w.seed, w.N, w.ntau))
+
+
+@dataclass
+class BatchSpec:
+    """Shape of one history row of a batch: orbitals N, row n, column m, and the seed of the
+    row's own system (grid of n+1 points, KP, tv and self-energy row all drawn from it)."""
+    N: int
+    n: int
+    m: int
+    seed: int
+
+
+# Batching workload: 256 rows, N ~ U{2,4,8,16}, n log-uniform in [128, 4096], m ~ U{0..n},
+# ntau = 256, per-interval orders U{3..6}, steps U[0.005, 0.05], beta = 10.
+BATCH = dict(count=256, Ns=(2, 4, 8, 16), nmin=128, nmax=4096, ntau=256, beta=10.0,
+             hmin=0.005, hmax=0.05, omin=3, omax=6, tau_order=5, seed=1002)
+
+
+def batch_specs(seed: int, count: int, Ns=(2, 4, 8, 16), nmin: int = 128, nmax: int = 4096):
+    """The rows of a batch: N uniform over Ns, n log-uniform in [nmin, nmax], m uniform in
+    0..n.  The uniform draws are the steps of `grid` with steps U[0, 1) on the batch's seed."""
+    u, _ = grid(seed, 3 * count + 1, 0.0, 1.0, 1, 1)  # cumulative sums of U[0,1) draws
+    d = np.diff(u)                                     # the draws themselves
+    out = []
+    for i in range(count):
+        N = Ns[min(int(d[3 * i] * len(Ns)), len(Ns) - 1)]
+        n = int(round(np.exp(np.log(nmin) + (np.log(nmax) - np.log(nmin)) * d[3 * i + 1])))
+        m = min(int(d[3 * i + 2] * (n + 1)), n)
+        out.append(BatchSpec(N, n, m, seed * 100003 + i))
+    return out
+
+
+def batch_cross(spec: BatchSpec, ntau: int, hmin: float, hmax: float, omin: int, omax: int,
+                decay: float = 0.3):
+    """Host arrays of one batch row: its grid (t, order), self-energy row at t_n, KP column m
+    (rows 0..m), KP row m (columns 0..n), G^R(t_m, t_m), tv row m."""
+    N, n, m, s = spec.N, spec.n, spec.m, spec.seed
+    t, order = grid(s, n + 1, hmin, hmax, omin, omax)
+    ret, les, stv = sigma_row(s, N, n, ntau, t, decay)
+    col = kp_col(s, N, t, m, rows=(0, m + 1), decay=decay)
+    row = kp(s, N, t, decay, rows=(m, m + 1))[0]
+    rd = rdiag(N, 1)[0]
+    tvm = tv(s, N, ntau, t, decay, rows=(m, m + 1))[0] if ntau > 0 else np.zeros((0, N, N), np.complex128)
+    return dict(t=t, order=order, ret=ret, les=les, stv=stv, col=col, row=row, rdiag=rd, tv=tvm)

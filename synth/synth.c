@@ -109,6 +109,21 @@ void synth_kp_rows(uint64_t seed, int32_t N, int32_t nt, int64_t ldt, const doub
   }
 }
 
+/* One column b of the same KP array, rows a in [a0, a1): block (a, b) exactly as
+ * synth_kp_rows makes it (out + (a - a0) * N * N * 2 doubles). */
+void synth_kp_col(uint64_t seed, int32_t N, int32_t nt, const double *t, double decay, int32_t b,
+                  int32_t a0, int32_t a1, double *out) {
+  uint64_t key = stream_key(seed, S_KP);
+  int64_t bs = (int64_t)N * N;
+#pragma omp parallel for schedule(static)
+  for (int32_t a = a0; a < a1; ++a) {
+    double *blk = out + 2 * ((int64_t)(a - a0) * bs);
+    double sc = exp(-decay * fabs(t[a] - t[b]));
+    fill_block(key, ((uint64_t)a * (uint64_t)nt + (uint64_t)b) * (uint64_t)bs, N, sc, blk);
+    if (a == b) anti_hermitian(blk, N);
+  }
+}
+
 /* Equal-time retarded values G^R(t,t) = -i * identity for rows [0, nt). */
 void synth_rdiag(int32_t N, int32_t nt, double *out) {
   int64_t bs = (int64_t)N * N;

@@ -108,3 +108,27 @@ def assert_blocks_close(got, ref, scale, name, rtol=RTOL):
     if gn > 0:
         rel = np.linalg.norm((got - ref).ravel()) / gn
         assert rel <= rtol, f"{name}: global relative error {rel:.3e} > {rtol}"
+
+
+def row_scales(N, ntau, n, m, cr, wn, wm, wfull):
+    """Rounding scales of one batch row's three blocks (the bar of R14 for a single output):
+    sum over terms of |weight| * ||Q||_F * ||P||_F."""
+    nrm = lambda x: np.linalg.norm(x.reshape(len(x), -1), axis=1)
+    ret, les, stv = nrm(cr["ret"]), nrm(cr["les"]), nrm(cr["stv"]) if ntau else None
+    col, row = nrm(cr["col"]), nrm(cr["row"])
+    g_ir = np.concatenate([col, row[m + 1:n + 1]])
+    s_ir = np.sum(np.abs(wn[:n + 1]) * ret[:n + 1] * g_ir)
+    g_il = np.concatenate([row[:m], [np.linalg.norm(cr["rdiag"])]])
+    s_il = np.sum(np.abs(wm[:m + 1]) * les[:m + 1] * g_il)
+    s_tv = np.sum(np.abs(wfull) * stv * nrm(cr["tv"])[::-1]) if ntau else 0.0
+    return s_ir, s_il, s_tv
+
+
+def batch_item(kbe, cr, n, m, wn, wm, wfull, flags):
+    """A kbe.BatchItem on the device from host cross arrays (synth.batch_cross's keys)."""
+    c = lambda a: to_dev(np.ascontiguousarray(a))
+    th = cr["stv"].shape[0] > 0
+    return kbe.BatchItem(n=n, m=m, sig_ret=c(cr["ret"]), sig_les=c(cr["les"]), col=c(cr["col"]),
+                         row=c(cr["row"]), rdiag=c(cr["rdiag"]), wn=c(wn), wm=c(wm),
+                         sig_tv=c(cr["stv"]) if th else None, tv=c(cr["tv"]) if th else None,
+                         wtau=c(wfull) if th else None, flags=flags)

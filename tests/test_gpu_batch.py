@@ -1,0 +1,183 @@
+"""Batches of history rows (kbe_collision_batch): many rows of independent systems with mixed
+orbital counts and lengths in one launch, against the oracle to the FP64 bar, at every chunk
+size, run to run, under graph capture and replay, and at the full batching size (sampled)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.cases import RTOL, batch_item, row_scales, to_host
+
+pytestmark = pytest.mark.gpu
+
+F3 = 0x1 | 0x2 | 0x4  # I^R, I^<, I^]
+
+
+def _print(*a):
+    print(*a, flush=True)
+
+
+def _cross_from_system(S, n, m, seed):
+    """A row's cross arrays cut from a full synthetic system (plus its own self-energy row)."""
+    N, ntau, t = S["N"], S["ntau"], S["t"]
+    ret, les, stv = synth.sigma_row(seed, N, n, ntau, t)
+    kp, tv = S["kp"], S["tv"]
+    return dict(ret=ret, les=les, stv=stv, col=kp[:m + 1, m], row=kp[m, :n + 1],
+                rdiag=S["rd"][m], tv=tv[m] if ntau else np.zeros((0, N, N), np.complex128))
+
+
+def _system(N, nt, ntau, seed):
+    t, order = synth.grid(seed, nt, 0.02, 0.08, 3, 6)
+    S = dict(N=N, nt=nt, ntau=ntau, t=t, kp=synth.kp(seed, N, t), rd=synth.rdiag(N, nt),
+             tv=synth.tv(seed, N, ntau, t), mat=synth.mat(seed, N, ntau))
+    S["W"] = oracle.Weights.build(t, order, 3.0 if ntau else None, ntau, 5)
+    S["G"] = oracle.Green(S["kp"], S["rd"], S["tv"], S["mat"])
+    return S
+
+
+@pytest.fixture(scope="module")
+def mixed(gpu):
+    """Rows of seven systems (N = 1, 2, 3, 5, 8, 11, 16; with and without a thermal branch),
+    including m = 0, m = n, n = 0 and output subsets, interleaved in one batch."""
+    kbe = gpu
+    systems = [_system(*a) for a in [(1, 30, 0, 11), (2, 64, 64, 12), (3, 40, 7, 13),
+                                     (5, 50, 0, 14), (8, 90, 20, 15), (11, 45, 9, 16),
+                                     (16, 70, 12, 17)]]
+    rows = []
+    for si, S in enumerate(systems):
+        nt = S["nt"]
+        for k, (n, m, f) in enumerate([(nt - 1, 0, F3), (nt - 1, nt - 1, F3),
+                                       (nt - 1, nt // 2, F3), (nt // 2, nt // 5, 0x1),
+                                       (nt // 3, nt // 3, 0x2 | 0x4), (0, 0, F3)]):
+            rows.append((si, n, m, f, 100 * si + k))
+    order = sorted(range(len(rows)), key=lambda r: (rows[r][4] * 7919) % 101)  # interleave
+    items, refs = [], []
+    for r in order:
+        si, n, m, f, seed = rows[r]
+        S = systems[si]
+        cr = _cross_from_system(S, n, m, seed)
+        W = S["W"]
+        wf = W.wfull if S["ntau"] else None
+        items.append(batch_item(kbe, cr, n, m, W.w[n, :n + 1], W.w[m, :m + 1], wf, f))
+        sig = (cr["ret"], cr["les"], cr["stv"])
+        of = (f & 0x3) | (f & 0x4 if S["ntau"] else 0)
+        IR, IL, Itv, _ = oracle.collision(S["G"], sig, W, n, m, m + 1, of)
+        sc = row_scales(S["N"], S["ntau"], n, m, cr, W.w[n], W.w[m], wf)
+        refs.append(dict(f=f, ref=(IR[0], IL[0], Itv[0]), sc=sc, N=S["N"], nm=(n, m)))
+    return kbe.Batch(items), refs
+
+
+def _check(batch, refs, rtol=RTOL):
+    for i, r in enumerate(refs):
+        for k, (got, name) in enumerate(((batch.IR[i], "IR"), (batch.IL[i], "IL"),
+                                         (batch.Itv[i], "Itv"))):
+            if not r["f"] & (1 << k):
+                assert got is None
+                continue
+            g, want = to_host(got), r["ref"][k]
+            err = np.linalg.norm(g - want)
+            assert err <= rtol * r["sc"][k] + 1e-300, (i, name, r["N"], r["nm"], err, r["sc"][k])
+
+
+@pytest.mark.parametrize("chunk", [0, 32, 128, 256])
+def test_batch_matches_oracle(mixed, chunk):
+    import torch
+    batch, refs = mixed
+    _print("batch chunk", chunk, "items", batch.count)
+    batch.run(chunk)
+    torch.cuda.synchronize()
+    _check(batch, refs)
+
+
+def test_batch_deterministic_and_chunks_agree(mixed):
+    import torch
+    batch, _ = mixed
+    outs = {}
+    for chunk in (32, 64, 32):
+        batch.run(chunk)
+        torch.cuda.synchronize()
+        outs.setdefault(chunk, []).append([to_host(x) for x in batch.IR + batch.IL + batch.Itv
+                                           if x is not None])
+    for a, b in zip(*outs[32]):
+        assert np.array_equal(a, b)  # bitwise run to run
+    for a, b in zip(outs[32][0], outs[64][0]):
+        assert np.linalg.norm(a - b) <= 1e-13 * (np.linalg.norm(b) + 1e-300)
+
+
+def test_batch_graph_capture_replay(mixed):
+    """The call allocates nothing and copies nothing from the host: captured once, every replay
+    (with eager work and synchronisation between replays) reproduces the eager result."""
+    import torch
+    batch, refs = mixed
+    batch.run(64)
+    torch.cuda.synchronize()
+    eager = [to_host(x) for x in batch.IR + batch.IL + batch.Itv if x is not None]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        batch.run(64)  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        batch.run(64)
+    for rep in range(3):
+        for x in batch.IR + batch.IL + batch.Itv:
+            if x is not None:
+                x.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = [to_host(x) for x in batch.IR + batch.IL + batch.Itv if x is not None]
+        for a, b in zip(got, eager):
+            assert np.array_equal(a, b), rep
+    _check(batch, refs)
+
+
+def test_batch_autotuner(mixed):
+    import torch
+    batch, refs = mixed
+    best, times = batch.tune()
+    _print("tuner", best, times)
+    assert best in (32, 64, 128, 256)
+    assert all(v > 0 for v in times.values())
+    batch.run(best)
+    torch.cuda.synchronize()
+    _check(batch, refs)
+
+
+def test_batch_full_size_sampled(gpu):
+    """The batching workload at full size (256 rows, N in {2,4,8,16}, n up to 4096, ntau = 256),
+    oracle weights; sampled rows against the oracle's row function, one launch."""
+    import torch
+    kbe = gpu
+    B = synth.BATCH
+    specs = synth.batch_specs(B["seed"], B["count"], B["Ns"], B["nmin"], B["nmax"])
+    _print("full batch: building", len(specs), "rows")
+    items, keep = [], {}
+    sample = sorted({0, 1, 2, len(specs) - 1} |
+                    {max(range(len(specs)), key=lambda i: specs[i].n * specs[i].N ** 2)} |
+                    {next(i for i, s in enumerate(specs) if s.N == N) for N in B["Ns"]})
+    _, _, wfull = oracle.tau_weights(B["beta"], B["ntau"], B["tau_order"])
+    for i, sp in enumerate(specs):
+        cr = synth.batch_cross(sp, B["ntau"], B["hmin"], B["hmax"], B["omin"], B["omax"])
+        w = oracle.weights(cr["t"], cr["order"])
+        wn, wm = w[sp.n].copy(), w[sp.m, :sp.m + 1].copy()
+        items.append(batch_item(kbe, cr, sp.n, sp.m, wn, wm, wfull, F3))
+        if i in sample:
+            keep[i] = (cr, wn, wm)
+        del w
+    batch = kbe.Batch(items)
+    _print("full batch: run")
+    batch.run()
+    torch.cuda.synchronize()
+    for i in sample:
+        sp = specs[i]
+        cr, wn, wm = keep[i]
+        ref = oracle.collision_row(sp.N, B["ntau"], sp.n, sp.m, (cr["ret"], cr["les"], cr["stv"]),
+                                   cr["col"], cr["row"], cr["rdiag"], cr["tv"], wn, wm, wfull, F3)
+        sc = row_scales(sp.N, B["ntau"], sp.n, sp.m, cr, wn, wm, wfull)
+        _print("row", i, sp)
+        for k, got in enumerate((batch.IR[i], batch.IL[i], batch.Itv[i])):
+            err = np.linalg.norm(to_host(got) - ref[k])
+            assert err <= RTOL * sc[k], (i, k, err, sc[k])

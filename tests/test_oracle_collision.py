@@ -244,3 +244,28 @@ def test_m_range_is_a_slice():
     for a, b in zip(full[:3], part[:3]):
         np.testing.assert_array_equal(a[10:37], b)
     np.testing.assert_array_equal(full[3], part[3])
+
+
+@pytest.mark.parametrize("N,nt,ntau", [(1, 20, 0), (2, 30, 6), (3, 25, 9), (5, 18, 4)])
+def test_row_from_cross_equals_full_system(N, nt, ntau):
+    """oracle.collision_row (one (t_n, t_m) from the blocks that row reads) against
+    oracle.collision on the full system, for rows with m = 0, m = n, n = 0 and interior m: the
+    same sums in the same order, so the blocks agree to the last bit or nearly."""
+    t, order = synth.grid(40 + N, nt, 0.02, 0.08, 3, 6)
+    kp = synth.kp(40 + N, N, t)
+    rd = synth.rdiag(N, nt)
+    tv = synth.tv(40 + N, N, ntau, t)
+    mat = synth.mat(40 + N, N, ntau)
+    G = oracle.Green(kp, rd, tv, mat)
+    W = oracle.Weights.build(t, order, 3.0 if ntau else None, ntau, 5)
+    flags = oracle.F_IR | oracle.F_IL | (oracle.F_ITV if ntau else 0)
+    for n, m in [(0, 0), (nt - 1, 0), (nt - 1, nt - 1), (nt - 1, nt // 2), (nt // 2, 3)]:
+        sig = synth.sigma_row(7 + n, N, n, ntau, t)
+        if not ntau:
+            sig = (sig[0], sig[1], np.zeros((0, N, N), np.complex128))
+        IR, IL, Itv, _ = oracle.collision(G, sig, W, n, m, m + 1, flags)
+        r = oracle.collision_row(N, ntau, n, m, sig, kp[:m + 1, m], kp[m, :n + 1], rd[m],
+                                 tv[m] if ntau else None, W.w[n, :n + 1], W.w[m, :m + 1],
+                                 W.wfull if ntau else None, flags)
+        for got, want in zip(r, (IR[0], IL[0], Itv[0])):
+            assert np.abs(got - want).max() <= 1e-14 * (np.abs(want).max() + 1e-300)
