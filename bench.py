@@ -6,7 +6,9 @@ One step = the whole path over the 16-orbital, 2048-point workload (n_tau = 512)
 all through the C ABI of libkbe.so.  Inputs are seeded synthetic arrays, resident in HBM before
 timing starts.  After the timed steps, the forward and adjoint collision calls are also timed on
 the 8-orbital differentiation shape (nt = 1024, n_tau = 256: the small-block path, bound by HBM
-bandwidth) and reported beside the step.  Prints one JSON line.
+bandwidth), and the batching workload (256 independent rows, N in {2,4,8,16}, n up to 4096) is
+timed as one batched launch, as a graph replay and as 256 separate launches; both are reported
+beside the step.  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
   python bench.py --copy-calibration   # 3 plain 1 GiB device copies (PMC byte-counter scale)
@@ -158,6 +160,69 @@ def small_orbital_shape(kbe, torch, dev, reps=5):
             "traffic": measured_traffic("traffic_collision_N8_nt1024.json")}
 
 
+def batching(kbe, torch, dev, reps=10):
+    """The batching workload: one kbe_collision_batch launch over 256 rows of independent systems
+    (chunk from the library's autotuner), its graph replay, and the same rows as 256 separate
+    launches.  Algorithmic bytes: every block a row reads once, its three outputs written once,
+    its weights; FLOP: 8 N^3 per block product."""
+    import synth
+    B = synth.BATCH
+    specs = synth.batch_specs(B["seed"], B["count"], B["Ns"], B["nmin"], B["nmax"])
+    c = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    items, nbytes, flop = [], 0.0, 0.0
+    wtau = None
+    for sp in specs:
+        cr = synth.batch_cross(sp, B["ntau"], B["hmin"], B["hmax"], B["omin"], B["omax"])
+        W = kbe.weights(cr["t"], cr["order"], B["ntau"], B["beta"], B["tau_order"], device=dev)
+        wtau = W.wtau if wtau is None else wtau
+        items.append(kbe.BatchItem(n=sp.n, m=sp.m, sig_ret=c(cr["ret"]), sig_les=c(cr["les"]),
+                                   col=c(cr["col"]), row=c(cr["row"]), rdiag=c(cr["rdiag"]),
+                                   wn=W.w[sp.n].contiguous(), wm=W.w[sp.m, :sp.m + 1].contiguous(),
+                                   sig_tv=c(cr["stv"]), tv=c(cr["tv"]), wtau=W.wtau))
+        del W
+        N, n, m, nt = sp.N, sp.n, sp.m, B["ntau"]
+        blocks = (n + 1) + (m + 1) + (n - m) + (m + 1) + m + 1 + 2 * nt + 3
+        nbytes += 16.0 * N * N * blocks + 8.0 * ((n + 1) + (m + 1) + nt)
+        flop += 8.0 * N ** 3 * ((n + 1) + (m + 1) + nt)
+    batch = kbe.Batch(items)
+    best, tuned = batch.tune()
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, k):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = ev(), ev()
+        e0.record()
+        for _ in range(k):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    batched_ms = timed(lambda: batch.run(best), reps)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        batch.run(best)
+    torch.cuda.current_stream().wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        batch.run(best)
+    graph_ms = timed(g.replay, reps)
+    singles = [kbe.Batch([it]) for it in items]
+    separate_ms = timed(lambda: [b.run(best) for b in singles], 3)
+    Ns = [sp.N for sp in specs]
+    return {"workload": "256 rows, N in {2,4,8,16}, n log-uniform [128,4096], m uniform, ntau 256",
+            "items": len(specs), "rows_per_N": {str(N): Ns.count(N) for N in B["Ns"]},
+            "chunk": best, "tuner_ms": {str(k): v for k, v in tuned.items()},
+            "batched_ms": batched_ms, "graph_replay_ms": graph_ms,
+            "separate_launches_ms": separate_ms, "speedup_vs_separate": separate_ms / batched_ms,
+            "gbps": nbytes / batched_ms / 1e6, "hbm_frac": nbytes / batched_ms / 1e6 / HBM_PEAK_GBS,
+            "gflops": flop / batched_ms / 1e6, "algorithmic_bytes": nbytes,
+            "algorithmic_flop": flop}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -302,6 +367,9 @@ def main():
     torch.cuda.empty_cache()
     log("8-orbital differentiation shape")
     result["small_orbital"] = small_orbital_shape(kbe, torch, dev)
+    log("batching workload")
+    result["batching"] = batching(kbe, torch, dev)
+    torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample)")
         result["cpu_baseline"] = cpu_baseline(w, (t, order, kp_h, rd_h, tv_h, mat_h))

@@ -13,7 +13,8 @@
 //   k1 += (ar + ai) br,  k2 += ar (bi - br),  k3 += ai (br + bi);  Re = k1 - k3, Im = k1 + k2.
 // A task writes its partial sum to the workspace; a reduce adds an item's partials in task
 // order, so results are deterministic.  The task plan (per-item task and partial offsets) is
-// computed on the device from the item array, so a call copies nothing from host memory.
+// computed on the device from the item array, so a call copies nothing from host memory; it
+// hands out the tasks of the largest blocks first.
 #include "kbe_dev.h"
 #include "kbe_internal.h"
 
@@ -218,42 +219,88 @@ __device__ void task16(const kbe_batch_item &it, int k, int t0, int t1, kbe_c128
 
 }  // namespace
 
-// Plan: per-item task offsets tb[count+1] and partial offsets pb[count+1] (complex numbers),
-// exclusive scans in item order; also zeroes the task counter.  One workgroup of 1024 threads.
+// Plan (one workgroup of 1024 threads):
+//   perm[count]  processing order: items by decreasing N, stable (the heaviest tasks are taken
+//                first, so the launch does not end on a tail of large blocks; results do not
+//                depend on the order, since each item's partials are laid out and summed by
+//                chunk index);
+//   tb[count+1]  task offsets in that order (exclusive scan);
+//   pb[count+1]  partial offsets in item order, in complex numbers (exclusive scan);
+// and zeroes the task counter.
+// Inclusive scan over the 1024 threads of the workgroup (wave shuffles, then the 16 wave totals);
+// every thread calls it; *total receives the sum.  ws: 16 shared slots.
+__device__ __forceinline__ int64_t block_scan(int64_t v, int64_t *ws, int64_t *total) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int64_t y = __shfl_up(v, off, 64);
+    if (lane >= off) v += y;
+  }
+  if (lane == 63) ws[w] = v;
+  __syncthreads();
+  if (w == 0) {
+    int64_t x = lane < 16 ? ws[lane] : 0;
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) {
+      const int64_t y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
+    }
+    if (lane < 16) ws[lane] = x;
+  }
+  __syncthreads();
+  v += w > 0 ? ws[w - 1] : 0;
+  *total = ws[15];
+  __syncthreads();  // ws is reused by the next scan
+  return v;
+}
+
 __global__ void __launch_bounds__(1024) batch_plan(const kbe_batch_item *items, int count,
-                                                   int chunk, int64_t *tb, int64_t *pb,
-                                                   unsigned int *head) {
-  __shared__ int64_t st[1024], sp[1024];
+                                                   int chunk, int *perm, int64_t *tb,
+                                                   int64_t *pb, unsigned int *head) {
+  __shared__ int64_t wsum[16];
+  __shared__ int nbin[KBE_NMAX + 1];
+  const int tid = threadIdx.x;
+  if (tid <= KBE_NMAX) nbin[tid] = 0;
+  __syncthreads();
+  for (int i = tid; i < count; i += 1024) atomicAdd(&nbin[items[i].N], 1);  // integer counts
+  __syncthreads();
+  // stable counting sort, N from KBE_NMAX down to 1 (empty bins skipped)
+  int64_t placed = 0;
+  for (int N = KBE_NMAX; N >= 1; --N) {
+    if (nbin[N] == 0) continue;  // uniform
+    for (int base = 0; base < count; base += 1024) {
+      const int i = base + tid;
+      const int64_t hit = i < count && items[i].N == N;
+      int64_t tot;
+      const int64_t r = block_scan(hit, wsum, &tot);
+      if (hit) perm[placed + r - 1] = i;
+      placed += tot;
+    }
+  }
+  __syncthreads();  // perm (global memory, written by other threads) is read below
+  // task offsets in processing order, partial offsets in item order
   int64_t carry_t = 0, carry_p = 0;
   for (int base = 0; base < count; base += 1024) {
-    const int i = base + (int)threadIdx.x;
+    const int j = base + tid;
     int64_t nt = 0, np = 0;
-    if (i < count) {
+    if (j < count) {
       int c[4];
-      item_chunks(items[i], chunk, c);
+      item_chunks(items[perm[j]], chunk, c);
       nt = c[0] + c[1] + c[2] + c[3];
-      np = nt * (int64_t)items[i].N * items[i].N;
+      item_chunks(items[j], chunk, c);
+      np = (int64_t)(c[0] + c[1] + c[2] + c[3]) * items[j].N * items[j].N;
     }
-    st[threadIdx.x] = nt;
-    sp[threadIdx.x] = np;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {  // inclusive scan (Hillis-Steele)
-      const int64_t a = threadIdx.x >= (unsigned)off ? st[threadIdx.x - off] : 0;
-      const int64_t b = threadIdx.x >= (unsigned)off ? sp[threadIdx.x - off] : 0;
-      __syncthreads();
-      st[threadIdx.x] += a;
-      sp[threadIdx.x] += b;
-      __syncthreads();
+    int64_t tt, tp;
+    const int64_t st = block_scan(nt, wsum, &tt);
+    const int64_t sp = block_scan(np, wsum, &tp);
+    if (j < count) {
+      tb[j] = carry_t + st - nt;
+      pb[j] = carry_p + sp - np;
     }
-    if (i < count) {
-      tb[i] = carry_t + st[threadIdx.x] - nt;
-      pb[i] = carry_p + sp[threadIdx.x] - np;
-    }
-    carry_t += st[1023];
-    carry_p += sp[1023];
-    __syncthreads();
+    carry_t += tt;
+    carry_p += tp;
   }
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
     tb[count] = carry_t;
     pb[count] = carry_p;
     head[0] = 0u;
@@ -262,9 +309,9 @@ __global__ void __launch_bounds__(1024) batch_plan(const kbe_batch_item *items, 
 
 // Persistent: every wave takes tasks from the counter until none are left.
 __global__ void __launch_bounds__(256) batch_stream(const kbe_batch_item *items, int count,
-                                                    int chunk, const int64_t *tb,
-                                                    const int64_t *pb, kbe_c128 *parts,
-                                                    unsigned int *head) {
+                                                    int chunk, const int *perm,
+                                                    const int64_t *tb, const int64_t *pb,
+                                                    kbe_c128 *parts, unsigned int *head) {
   __shared__ cd qtile[4][16 * BQLD];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t ntask = tb[count];
@@ -273,24 +320,26 @@ __global__ void __launch_bounds__(256) batch_stream(const kbe_batch_item *items,
     if (lane == 0) v = atomicAdd(head, 1u);
     const int64_t task = (int64_t)__builtin_amdgcn_readfirstlane(v);
     if (task >= ntask) break;  // wave-uniform
-    // item: the last i with tb[i] <= task (binary search over the offsets)
+    // position in the processing order: the last j with tb[j] <= task (binary search)
     int lo = 0, hi = count - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
       if (tb[mid] <= task) lo = mid;
       else hi = mid - 1;
     }
-    const int i = __builtin_amdgcn_readfirstlane(lo);
+    const int j = __builtin_amdgcn_readfirstlane(lo);
+    const int i = __builtin_amdgcn_readfirstlane(perm[j]);
     const kbe_batch_item it = items[i];
     int c[4];
     item_chunks(it, chunk, c);
-    int local = (int)(task - tb[i]), k = 0;
+    const int64_t ltask = task - tb[j];
+    int local = (int)ltask, k = 0;
     while (local >= c[k]) local -= c[k++];
     int t0, t1;
     item_range(it, k, t0, t1);
     t0 += local * chunk;
     t1 = t0 + chunk < t1 ? t0 + chunk : t1;
-    kbe_c128 *out = parts + pb[i] + (task - tb[i]) * (int64_t)it.N * it.N;
+    kbe_c128 *out = parts + pb[i] + ltask * (int64_t)it.N * it.N;
     if (it.N <= 8) task8(it, k, t0, t1, out, lane);
     else task16(it, k, t0, t1, out, lane, qtile[wave]);
   }
@@ -298,17 +347,23 @@ __global__ void __launch_bounds__(256) batch_stream(const kbe_batch_item *items,
 
 // One workgroup per item: element e of each selected output = its tasks' partials in order.
 __global__ void __launch_bounds__(256) batch_reduce(const kbe_batch_item *items, int chunk,
-                                                    const int64_t *tb, const int64_t *pb,
-                                                    const kbe_c128 *parts) {
+                                                    const int64_t *pb, const kbe_c128 *parts) {
   const kbe_batch_item it = items[blockIdx.x];
   const int E = it.N * it.N, e = threadIdx.x;
   if (e >= E) return;
   int c[4];
   item_chunks(it, chunk, c);
   const kbe_c128 *p = parts + pb[blockIdx.x] + e;
-  auto sum = [&](int a, int b) {
+  auto sum = [&](int a, int b) {  // eight loads in flight; added in chunk order
     cd s = czero();
-    for (int L = a; L < b; ++L) s = s + ldg(p + (int64_t)L * E);
+    for (int L = a; L < b; L += 8) {
+      cd v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = L + u < b ? ldg(p + (int64_t)(L + u) * E) : czero();
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (L + u < b) s = s + v[u];
+    }
     return s;
   };
   const int irb = c[0] + c[1], ilb = irb + c[2], itb = ilb + c[3];
@@ -331,8 +386,8 @@ size_t batch_ws_bytes(const kbe_batch_item *items, int count, int chunk) {
     item_chunks(items[i], chunk, c);
     parts += (int64_t)(c[0] + c[1] + c[2] + c[3]) * items[i].N * items[i].N;
   }
-  return 2 * al256b(sizeof(int64_t) * (size_t)(count + 1)) + 256 +
-         sizeof(kbe_c128) * (size_t)parts;
+  return 2 * al256b(sizeof(int64_t) * (size_t)(count + 1)) + al256b(sizeof(int) * (size_t)count) +
+         256 + sizeof(kbe_c128) * (size_t)parts;
 }
 
 static int batch_grid() {
@@ -355,9 +410,11 @@ hipError_t launch_batch(const kbe_batch_item *items, const kbe_batch_item *items
                         int chunk, void *ws, hipStream_t st) {
   if (count == 0) return hipSuccess;
   char *w = (char *)ws;
+  const size_t tsz = al256b(sizeof(int64_t) * (size_t)(count + 1));
   int64_t *tb = (int64_t *)w;
-  int64_t *pb = (int64_t *)(w + al256b(sizeof(int64_t) * (size_t)(count + 1)));
-  unsigned int *head = (unsigned int *)(w + 2 * al256b(sizeof(int64_t) * (size_t)(count + 1)));
+  int64_t *pb = (int64_t *)(w + tsz);
+  int *perm = (int *)(w + 2 * tsz);
+  unsigned int *head = (unsigned int *)(w + 2 * tsz + al256b(sizeof(int) * (size_t)count));
   kbe_c128 *parts = (kbe_c128 *)((char *)head + 256);
   int64_t ntask = 0;
   for (int i = 0; i < count; ++i) {
@@ -365,17 +422,17 @@ hipError_t launch_batch(const kbe_batch_item *items, const kbe_batch_item *items
     item_chunks(items[i], chunk, c);
     ntask += c[0] + c[1] + c[2] + c[3];
   }
-  hipLaunchKernelGGL(batch_plan, dim3(1), dim3(1024), 0, st, items_dev, count, chunk, tb, pb,
-                     head);
+  hipLaunchKernelGGL(batch_plan, dim3(1), dim3(1024), 0, st, items_dev, count, chunk, perm, tb,
+                     pb, head);
   if (ntask > 0) {
     int64_t grid = batch_grid();
     const int64_t need = (ntask + 3) / 4;  // four waves per workgroup
     if (grid > need) grid = need;
     hipLaunchKernelGGL(batch_stream, dim3((unsigned)grid), dim3(256), 0, st, items_dev, count,
-                       chunk, tb, pb, parts, head);
+                       chunk, perm, tb, pb, parts, head);
   }
-  hipLaunchKernelGGL(batch_reduce, dim3((unsigned)count), dim3(256), 0, st, items_dev, chunk, tb,
-                     pb, parts);
+  hipLaunchKernelGGL(batch_reduce, dim3((unsigned)count), dim3(256), 0, st, items_dev, chunk, pb,
+                     parts);
   return hipGetLastError();
 }
 

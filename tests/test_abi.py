@@ -163,3 +163,56 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(kbe, "_lib", None)
     with pytest.raises(RuntimeError, match="not built"):
         kbe.lib()
+
+
+def batch_item(N=4, n=10, m=3, ntau=6, flags=0x7):
+    f = kbe._BatchItem(N, n, m, ntau, flags, 0, *([FAKE] * 13))
+    return f
+
+
+def batch_call(items, count=None, chunk=0, ws=FAKE, ws_bytes=1 << 40):
+    arr = (kbe._BatchItem * max(len(items), 1))(*items)
+    L = kbe.lib()
+    count = len(items) if count is None else count
+    return L.kbe_collision_batch(arr, FAKE, count, chunk, ws, ws_bytes, None)
+
+
+def test_batch_argument_errors():
+    EINVAL, ERANGE, ENOMEM = 1, 2, 3
+    assert batch_call([]) == 0  # nothing to do
+    assert batch_call([batch_item(N=0)]) == EINVAL
+    assert batch_call([batch_item(N=17)]) == EINVAL
+    assert batch_call([batch_item(n=5, m=6)]) == ERANGE
+    assert batch_call([batch_item(m=-1)]) == ERANGE
+    assert batch_call([batch_item(ntau=1)]) == EINVAL
+    assert batch_call([batch_item(flags=0x8)]) == EINVAL   # J^] is not a per-row output
+    assert batch_call([batch_item()], chunk=48) == EINVAL
+    assert batch_call([batch_item()], count=65537) == ERANGE
+    it = batch_item()
+    it.IR = None
+    assert batch_call([it]) == EINVAL
+    it = batch_item(flags=0x2)
+    it.rdiag = None
+    assert batch_call([it]) == EINVAL
+    it = batch_item(flags=0x4)
+    it.sig_tv = None
+    assert batch_call([it]) == EINVAL
+    assert batch_call([batch_item()], ws_bytes=16) == ENOMEM
+    L = kbe.lib()
+    assert L.kbe_collision_batch(None, FAKE, 1, 0, FAKE, 1 << 40, None) == EINVAL
+    assert L.kbe_collision_batch((kbe._BatchItem * 1)(batch_item()), None, 1, 0, FAKE, 1 << 40,
+                                 None) == EINVAL
+
+
+def test_batch_workspace_counts_chunks():
+    """Workspace = two offset tables, the processing order, the counter, and one N x N partial per
+    (item, class, chunk)."""
+    L = kbe.lib()
+    items = [batch_item(N=4, n=100, m=30, ntau=64), batch_item(N=16, n=7, m=7, ntau=0, flags=0x3)]
+    arr = (kbe._BatchItem * 2)(*items)
+    for chunk in (32, 64, 128, 256):
+        c = lambda k: (k + chunk - 1) // chunk
+        parts = (c(31) + c(70) + c(31) + c(64)) * 16 + (c(8) + c(0) + c(8) + 0) * 256
+        tables = 2 * ((8 * 3 + 255) // 256 * 256) + (4 * 2 + 255) // 256 * 256 + 256
+        assert L.kbe_collision_batch_workspace(arr, 2, chunk) == tables + 16 * parts
+    assert L.kbe_collision_batch_workspace(arr, 2, 48) == 0
