@@ -140,7 +140,7 @@ __device__ void task8(const kbe_batch_item &it, int k, int t0, int t1, kbe_c128 
 // 9 <= N <= 16: blocks padded to 16 x 16, the layout of the N = 16 collision task: the wave
 // stages c Q in its own LDS tile (rows padded to BQLD complex numbers), lane l supplies
 // A[4ti + l%4][4kc + l/16] from it and the slab B[4kc + l/16][l%16] of P (or P^dagger), and
-// accumulator ti holds D[4ti + l/16][l%16].  The next term's Q and P are in flight during a
+// accumulator ti holds D[4ti + l/16][l%16].  The next two terms' Q and P are in flight during a
 // term's products.
 // ---------------------------------------------------------------------------------------
 __device__ void task16(const kbe_batch_item &it, int k, int t0, int t1, kbe_c128 *out, int lane,
@@ -197,17 +197,23 @@ __device__ void task16(const kbe_batch_item &it, int k, int t0, int t1, kbe_c128
       }
     }
   };
-  Buf ba, bb;
-  load(t0, ba);
-  for (int t = t0; t < t1; t += 2) {
-    load(t + 1, bb);
+  Buf b0, b1, b2;  // two terms in flight
+  load(t0, b0);
+  load(t0 + 1, b1);
+  for (int t = t0; t < t1; t += 3) {
+    load(t + 2, b2);
     __builtin_amdgcn_sched_barrier(0);
-    compute(ba);
+    compute(b0);
     __builtin_amdgcn_sched_barrier(0);
     if (t + 1 >= t1) break;  // wave-uniform
-    load(t + 2, ba);
+    load(t + 3, b0);
     __builtin_amdgcn_sched_barrier(0);
-    compute(bb);
+    compute(b1);
+    __builtin_amdgcn_sched_barrier(0);
+    if (t + 2 >= t1) break;
+    load(t + 4, b1);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(b2);
     __builtin_amdgcn_sched_barrier(0);
   }
 #pragma unroll
