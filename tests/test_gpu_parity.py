@@ -237,3 +237,37 @@ def test_conservation_invariant_on_gpu(gpu):
     scale = np.abs(IR[0]).sum() + np.abs(IL[0]).sum()
     assert abs(np.trace(IR[0] + IL[0]).real) < 1e-13 * scale
     assert abs(np.trace(Itv[0]).real) < 1e-13 * np.abs(Itv[0]).sum()
+
+
+@pytest.mark.parametrize("N", [16, 8])
+def test_sigma_and_collision_graph_capture(gpu, N):
+    """[kbe_sigma_2b -> kbe_collision (stream kernels and chunk reduce)] captured once in a graph
+    (no host copies, no allocation inside the library, no memset nodes): every replay, with
+    eager work and synchronisation between replays, reproduces the eager result bitwise."""
+    import torch
+    kbe = gpu
+    case = Case(N=N, nt=120, ntau=16, beta=3.0, seed=60 + N)
+    t, order, kp, rd, tv, mat = case.host()
+    Gd = device_green(kp, rd, tv, mat)
+    Wd = device_weights(oracle.Weights.build(t, order, case.beta, case.ntau))
+    u = to_dev(np.full(N, 1.3))
+    n = case.nt - 1
+    eager = [to_host(x) for x in kbe.collision(Gd, kbe.sigma_2b(Gd, u, n), Wd, n)]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        kbe.collision(Gd, kbe.sigma_2b(Gd, u, n), Wd, n)  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        sig = kbe.sigma_2b(Gd, u, n)
+        out = kbe.collision(Gd, sig, Wd, n)
+    for rep in range(3):
+        for x in out:
+            x.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(out, eager):
+            assert np.array_equal(to_host(a), b), rep
