@@ -56,21 +56,24 @@ def counts(N, nt, ntau, n):
                 adj_flop=adj_terms * blk_flop, adj_bytes=adj_read + adj_write)
 
 
-def kernel_source_hash():
+def kernel_source_hash(files=("kbe_collision.hip", "kbe_dev.h")):
     h = hashlib.sha256()
-    for f in ("kbe_collision.hip", "kbe_dev.h"):
+    for f in files:
         h.update(open(os.path.join(ROOT, "paper_2405_08737_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(name="traffic_collision_N16_nt2048.json"):
-    """HBM bytes per forward stream launch from a committed rocprofv3 counter summary, or None
-    when the kernel source changed since the counters were taken."""
+BATCH_SOURCES = ("kbe_batch.hip", "kbe_dev.h")
+
+
+def measured_traffic(name="traffic_collision_N16_nt2048.json", files=None):
+    """HBM bytes per stream launch from a committed rocprofv3 counter summary, or None when the
+    kernel source changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
-    if d.get("kernel_source_hash") != kernel_source_hash():
+    if d.get("kernel_source_hash") != (kernel_source_hash(files) if files else kernel_source_hash()):
         return None
     return d.get("hbm_bytes_per_call")
 
@@ -220,7 +223,8 @@ def batching(kbe, torch, dev, reps=10):
             "separate_launches_ms": separate_ms, "speedup_vs_separate": separate_ms / batched_ms,
             "gbps": nbytes / batched_ms / 1e6, "hbm_frac": nbytes / batched_ms / 1e6 / HBM_PEAK_GBS,
             "gflops": flop / batched_ms / 1e6, "algorithmic_bytes": nbytes,
-            "algorithmic_flop": flop}
+            "algorithmic_flop": flop,
+            "traffic": measured_traffic("traffic_batch_256rows.json", BATCH_SOURCES)}
 
 
 def main():
