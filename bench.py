@@ -119,7 +119,10 @@ def cpu_baseline(w, host, target_s=30.0):
 
 def small_orbital_shape(kbe, torch, dev, reps=5):
     """Forward and adjoint collision calls on the 8-orbital differentiation workload (row
-    n = nt - 1, all m), timed with HIP events on the library's stream, after two warm-up calls."""
+    n = nt - 1, all m), timed with HIP events on the library's stream, after two warm-up calls.
+    The sustained figures time `reps` calls issued back to back, as a propagation issues them;
+    the isolated figures time single calls after a synchronisation, host launch latency
+    included."""
     import synth
     w = synth.DIFFERENTIATION
     N, nt, ntau, n = w.N, w.nt, w.ntau, w.nt - 1
@@ -139,6 +142,19 @@ def small_orbital_shape(kbe, torch, dev, reps=5):
         kbe.collision(G, sig, W, n)
         kbe.collision_vjp(G, sig, W, n, 0, n + 1, cot, flags, gG)
     torch.cuda.synchronize()
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    def sustained(fn):
+        e0, e1 = ev(), ev()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    f_ms = sustained(lambda: kbe.collision(G, sig, W, n))
+    b_ms = sustained(lambda: kbe.collision_vjp(G, sig, W, n, 0, n + 1, cot, flags, gG))
     tf, tb = [], []
     for _ in range(reps):
         e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
@@ -151,10 +167,11 @@ def small_orbital_shape(kbe, torch, dev, reps=5):
         tf.append(e[0].elapsed_time(e[1]))
         tb.append(e[1].elapsed_time(e[2]))
     c = counts(N, nt, ntau, n)
-    f_ms, b_ms = float(np.mean(tf)), float(np.mean(tb))
     return {"workload": w.name, "N_orb": N, "nt": nt, "n": n, "ntau": ntau, "U": w.U,
             "seed": w.seed, "calls": reps,
             "collision_ms": f_ms, "collision_vjp_ms": b_ms, "adjoint_over_forward": b_ms / f_ms,
+            "collision_ms_isolated": float(np.mean(tf)),
+            "collision_vjp_ms_isolated": float(np.mean(tb)),
             "collision_gflops": c["fwd_flop"] / f_ms / 1e6,
             "collision_gbps": c["fwd_bytes"] / f_ms / 1e6,
             "collision_hbm_frac": c["fwd_bytes"] / f_ms / 1e6 / HBM_PEAK_GBS,
@@ -165,8 +182,8 @@ def small_orbital_shape(kbe, torch, dev, reps=5):
 
 def batching(kbe, torch, dev, reps=10):
     """The batching workload: one kbe_collision_batch launch over 256 rows of independent systems
-    (chunk from the library's autotuner), its graph replay, and the same rows as 256 separate
-    launches.  Algorithmic bytes: every block a row reads once, its three outputs written once,
+    (the best common chunk, then the per-group tile table from the library's autotuners), its
+    graph replay, and the same rows as 256 separate launches.  Algorithmic bytes: every block a row reads once, its three outputs written once,
     its weights; FLOP: 8 N^3 per block product."""
     import synth
     B = synth.BATCH
@@ -189,6 +206,7 @@ def batching(kbe, torch, dev, reps=10):
         flop += 8.0 * N ** 3 * ((n + 1) + (m + 1) + nt)
     batch = kbe.Batch(items)
     best, tuned = batch.tune()
+    table_ms, table = batch.tune_groups()
     ev = lambda: torch.cuda.Event(enable_timing=True)
 
     def timed(fn, k):
@@ -203,23 +221,27 @@ def batching(kbe, torch, dev, reps=10):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / k
 
-    batched_ms = timed(lambda: batch.run(best), reps)
+    common_ms = timed(lambda: batch.run(best), reps)
+    batched_ms = timed(lambda: batch.run(0), reps)  # the tile table
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
-        batch.run(best)
+        batch.run(0)
     torch.cuda.current_stream().wait_stream(s)
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
-        batch.run(best)
+        batch.run(0)
     graph_ms = timed(g.replay, reps)
     singles = [kbe.Batch([it]) for it in items]
-    separate_ms = timed(lambda: [b.run(best) for b in singles], 3)
+    for b in singles:
+        b.apply_table(table)
+    separate_ms = timed(lambda: [b.run(0) for b in singles], 3)
     Ns = [sp.N for sp in specs]
     return {"workload": "256 rows, N in {2,4,8,16}, n log-uniform [128,4096], m uniform, ntau 256",
             "items": len(specs), "rows_per_N": {str(N): Ns.count(N) for N in B["Ns"]},
             "chunk": best, "tuner_ms": {str(k): v for k, v in tuned.items()},
-            "batched_ms": batched_ms, "graph_replay_ms": graph_ms,
+            "common_chunk_ms": common_ms, "tile_table": dict(sorted(table.items())),
+            "tile_table_tuner_ms": table_ms, "batched_ms": batched_ms, "graph_replay_ms": graph_ms,
             "separate_launches_ms": separate_ms, "speedup_vs_separate": separate_ms / batched_ms,
             "gbps": nbytes / batched_ms / 1e6, "hbm_frac": nbytes / batched_ms / 1e6 / HBM_PEAK_GBS,
             "gflops": flop / batched_ms / 1e6, "algorithmic_bytes": nbytes,

@@ -275,7 +275,9 @@ typedef struct {
   int32_t n, m;  /* row and column, 0 <= m <= n */
   int32_t ntau;  /* imaginary-time points: 0 or >= 2 */
   uint32_t flags; /* KBE_OUT_IR | KBE_OUT_IL | KBE_OUT_ITV (J^] is not a per-row output) */
-  int32_t pad_;
+  int32_t chunk;  /* terms per work unit for this item: 0 (the library default, 64) or 32, 64,
+                     128, 256; used when the call's chunk is 0 (kbe_collision_batch_tune_groups
+                     writes it) */
   const kbe_c128 *sig_ret, *sig_les, *sig_tv;
   const kbe_c128 *col, *row, *rdiag, *tv;
   const double *wn, *wm, *wtau;
@@ -289,8 +291,9 @@ typedef struct {
  *
  * items: host array of count items (validated here); items_dev: the same array
  * copied by the caller into device memory (what the kernels read; its content
- * must equal items when the work runs).  chunk: terms per work unit, one of
- * 32, 64, 128, 256, or 0 for the library default (see kbe_collision_batch_tune).
+ * must equal items when the work runs).  chunk: terms per work unit for every
+ * item, one of 32, 64, 128, 256; or 0, when each item's own chunk field applies
+ * (see kbe_collision_batch_tune and kbe_collision_batch_tune_groups).
  * ws: kbe_collision_batch_workspace(items, count, chunk) bytes.  Nothing is
  * copied from host memory and nothing is allocated, so the call can be
  * captured in a HIP graph and replayed.
@@ -315,6 +318,23 @@ kbe_status kbe_collision_batch(const kbe_batch_item *items, const kbe_batch_item
 kbe_status kbe_collision_batch_tune(const kbe_batch_item *items, const kbe_batch_item *items_dev,
                                     int32_t count, void *ws, size_t ws_bytes, void *stream,
                                     int32_t *best_chunk, float *times_ms);
+
+/* ---------------------------------------------------------------------------
+ * kbe_collision_batch_tune_groups — the autotuner's tile table: a chunk size
+ * per group of items, a group being the items of one N and one length bucket
+ * floor(log2(n + 1)).  It starts from the best common chunk, then, for each
+ * group in decreasing order of its bytes, tries the other chunk sizes on that
+ * group's items alone and keeps one only if the whole call (best of three timed
+ * calls after a warm-up) gets faster by more than 1%.  On return every item's
+ * chunk field holds its group's chunk, in items and (copied by this call) in
+ * items_dev, so kbe_collision_batch(..., chunk = 0, ...) runs the table; the
+ * caller may read the fields back to store the table.  *best_ms (if not NULL)
+ * receives the tuned call's time.  It synchronises the stream.  ws: as for
+ * kbe_collision_batch_tune.  Errors: as kbe_collision_batch_tune.
+ * ------------------------------------------------------------------------- */
+kbe_status kbe_collision_batch_tune_groups(kbe_batch_item *items, kbe_batch_item *items_dev,
+                                           int32_t count, void *ws, size_t ws_bytes, void *stream,
+                                           float *best_ms);
 
 /* Human-readable name of a status code (static string). */
 const char *kbe_status_string(kbe_status s);

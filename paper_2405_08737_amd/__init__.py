@@ -11,6 +11,7 @@ Arrays are torch tensors on a ROCm device: complex128 for Green's functions and 
 from __future__ import annotations
 
 import ctypes
+import json
 import os
 from dataclasses import dataclass
 from typing import Optional
@@ -54,7 +55,7 @@ class _Wts(ctypes.Structure):
 
 class _BatchItem(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int32), ("n", ctypes.c_int32), ("m", ctypes.c_int32),
-                ("ntau", ctypes.c_int32), ("flags", ctypes.c_uint32), ("pad_", ctypes.c_int32)] + [
+                ("ntau", ctypes.c_int32), ("flags", ctypes.c_uint32), ("chunk", ctypes.c_int32)] + [
         (name, ctypes.c_void_p) for name in ("sig_ret", "sig_les", "sig_tv", "col", "row", "rdiag",
                                              "tv", "wn", "wm", "wtau", "IR", "IL", "Itv")]
 
@@ -62,7 +63,8 @@ class _BatchItem(ctypes.Structure):
 EXPORTS = ("kbe_weights_workspace", "kbe_weights", "kbe_sigma_2b", "kbe_collision_workspace",
            "kbe_collision", "kbe_collision_vjp_workspace", "kbe_collision_vjp",
            "kbe_sigma_2b_vjp_workspace", "kbe_sigma_2b_vjp", "kbe_collision_batch_workspace",
-           "kbe_collision_batch", "kbe_collision_batch_tune", "kbe_status_string",
+           "kbe_collision_batch", "kbe_collision_batch_tune", "kbe_collision_batch_tune_groups",
+           "kbe_status_string",
            "kbe_last_error", "kbe_version")
 
 
@@ -90,6 +92,7 @@ def lib():
             "kbe_collision_batch_workspace": (SZ, [P, I32, I32]),
             "kbe_collision_batch": (I32, [P, P, I32, I32, P, SZ, P]),
             "kbe_collision_batch_tune": (I32, [P, P, I32, P, SZ, P, P, P]),
+            "kbe_collision_batch_tune_groups": (I32, [P, P, I32, P, SZ, P, P]),
             "kbe_status_string": (ctypes.c_char_p, [I32]),
             "kbe_last_error": (ctypes.c_char_p, []),
             "kbe_version": (I32, []),
@@ -381,7 +384,8 @@ class Batch:
         self.ws = _ws(self.ws_bytes, dev)
 
     def run(self, chunk: int = 0):
-        """Enqueue kbe_collision_batch on the current stream (chunk 0: the library default)."""
+        """Enqueue kbe_collision_batch on the current stream (chunk 0: each item's own chunk from
+        the tile table, or the library default where it has none)."""
         _check(lib().kbe_collision_batch(self._host, _ptr(self._dev), self.count, chunk,
                                          _ptr(self.ws), self.ws_bytes, _stream(self.device)),
                "kbe_collision_batch")
@@ -396,3 +400,45 @@ class Batch:
                                               ctypes.byref(best), times),
                "kbe_collision_batch_tune")
         return best.value, dict(zip((32, 64, 128, 256), list(times)))
+
+    @staticmethod
+    def group(N: int, n: int) -> str:
+        """Tile-table key of a row: its N and length bucket floor(log2(n + 1))."""
+        return f"{N}:{(n + 1).bit_length() - 1}"
+
+    def tune_groups(self):
+        """The library's per-group autotuner (kbe_collision_batch_tune_groups): sets every item's
+        chunk to its group's and returns (ms of the tuned call, tile table {group: chunk})."""
+        ms = ctypes.c_float(0.0)
+        _check(lib().kbe_collision_batch_tune_groups(self._host, _ptr(self._dev), self.count,
+                                                     _ptr(self.ws), self.ws_bytes,
+                                                     _stream(self.device), ctypes.byref(ms)),
+               "kbe_collision_batch_tune_groups")
+        return ms.value, self.table()
+
+    def table(self):
+        """The items' chunks as a tile table {group: chunk} (items of a group share one)."""
+        return {self.group(it.N, it.n): int(self._host[i].chunk)
+                for i, it in enumerate(self.items)}
+
+    def apply_table(self, table):
+        """Set each item's chunk from a tile table (0, the default, for groups it lacks) and copy
+        the item array to the device again."""
+        for i, it in enumerate(self.items):
+            c = int(table.get(self.group(it.N, it.n), 0))
+            if c not in (0, 32, 64, 128, 256):
+                raise KBEError(f"tile table: chunk {c} for group {self.group(it.N, it.n)}")
+            self._host[i].chunk = c
+        raw = bytes(self._host)[:ctypes.sizeof(_BatchItem) * self.count]
+        self._dev.copy_(torch.frombuffer(bytearray(raw), dtype=torch.uint8))
+
+    def save_table(self, path):
+        """Write the tile table as JSON."""
+        with open(path, "w") as f:
+            json.dump({"key": "N:floor(log2(n+1))", "chunk": self.table()}, f, indent=1,
+                      sort_keys=True)
+
+    def load_table(self, path):
+        """Read a tile table written by save_table and apply it."""
+        with open(path) as f:
+            self.apply_table(json.load(f)["chunk"])

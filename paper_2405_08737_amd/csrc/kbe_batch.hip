@@ -30,8 +30,15 @@ __device__ __forceinline__ double mfma4b(double a, double b, double c) {
 
 __device__ __forceinline__ int cdivd(int a, int b) { return (a + b - 1) / b; }
 
+// Terms per work unit of an item: the call's chunk when it is set, else the item's own, else the
+// default.
+__host__ __device__ inline int item_chunk(const kbe_batch_item &it, int chunk) {
+  return chunk > 0 ? chunk : it.chunk > 0 ? it.chunk : 64;
+}
+
 // Chunks per term class of an item: IRC, IRR, IL, ITV.
-__host__ __device__ inline void item_chunks(const kbe_batch_item &it, int chunk, int c[4]) {
+__host__ __device__ inline void item_chunks(const kbe_batch_item &it, int call_chunk, int c[4]) {
+  const int chunk = item_chunk(it, call_chunk);
   const bool ir = it.flags & KBE_OUT_IR, il = it.flags & KBE_OUT_IL;
   const bool itv = (it.flags & KBE_OUT_ITV) && it.ntau > 0;
   c[0] = ir ? (it.m + 1 + chunk - 1) / chunk : 0;
@@ -343,8 +350,9 @@ __global__ void __launch_bounds__(256) batch_stream(const kbe_batch_item *items,
     while (local >= c[k]) local -= c[k++];
     int t0, t1;
     item_range(it, k, t0, t1);
-    t0 += local * chunk;
-    t1 = t0 + chunk < t1 ? t0 + chunk : t1;
+    const int ch = item_chunk(it, chunk);
+    t0 += local * ch;
+    t1 = t0 + ch < t1 ? t0 + ch : t1;
     kbe_c128 *out = parts + pb[i] + ltask * (int64_t)it.N * it.N;
     if (it.N <= 8) task8(it, k, t0, t1, out, lane);
     else task16(it, k, t0, t1, out, lane, qtile[wave]);
@@ -383,7 +391,7 @@ __global__ void __launch_bounds__(256) batch_reduce(const kbe_batch_item *items,
 // ---------------------------------------------------------------------------------------
 static size_t al256b(size_t x) { return (x + 255) & ~(size_t)255; }
 
-int batch_default_chunk() { return 64; }
+int batch_default_chunk() { return item_chunk(kbe_batch_item{}, 0); }
 
 size_t batch_ws_bytes(const kbe_batch_item *items, int count, int chunk) {
   int64_t parts = 0;

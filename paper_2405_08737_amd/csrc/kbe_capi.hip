@@ -3,7 +3,10 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "kbe_dev.h"
 #include "kbe_internal.h"
@@ -269,6 +272,8 @@ static kbe_status check_batch(const kbe_batch_item *items, const kbe_batch_item 
       return fail(KBE_ERANGE, "item %d: (n, m) = (%d, %d) needs 0 <= m <= n", i, it.n, it.m);
     if (it.ntau < 0 || it.ntau == 1)
       return fail(KBE_EINVAL, "item %d: ntau = %d (must be 0 or >= 2)", i, it.ntau);
+    if (!batch_chunk_ok(it.chunk))
+      return fail(KBE_EINVAL, "item %d: chunk = %d not in {0, 32, 64, 128, 256}", i, it.chunk);
     if (it.flags & KBE_OUT_IR) {
       if (!it.IR || !it.sig_ret || !it.col || !it.wn || (it.n > it.m && !it.row))
         return fail(KBE_EINVAL, "item %d: I^R needs IR, sig_ret, col, wn (and row when n > m)", i);
@@ -290,9 +295,9 @@ size_t kbe_collision_batch_workspace(const kbe_batch_item *items, int32_t count,
   if (count <= 0 || count > KBE_BATCH_MAX || !items || !batch_chunk_ok(chunk)) return 0;
   for (int32_t i = 0; i < count; ++i)
     if (items[i].N < 1 || items[i].N > KBE_NMAX || items[i].m < 0 || items[i].m > items[i].n ||
-        items[i].ntau < 0)
+        items[i].ntau < 0 || !batch_chunk_ok(items[i].chunk))
       return 0;
-  return kbe::batch_ws_bytes(items, count, chunk ? chunk : kbe::batch_default_chunk());
+  return kbe::batch_ws_bytes(items, count, chunk);
 }
 
 kbe_status kbe_collision_batch(const kbe_batch_item *items, const kbe_batch_item *items_dev,
@@ -300,12 +305,56 @@ kbe_status kbe_collision_batch(const kbe_batch_item *items, const kbe_batch_item
                                void *stream) {
   kbe_status s = check_batch(items, items_dev, count, chunk);
   if (s != KBE_OK || count == 0) return s;
-  const int c = chunk ? chunk : kbe::batch_default_chunk();
-  const size_t need = kbe::batch_ws_bytes(items, count, c);
+  const size_t need = kbe::batch_ws_bytes(items, count, chunk);
   if (!ws || ws_bytes < need) return fail(KBE_ENOMEM, "workspace %zu bytes < %zu", ws_bytes, need);
-  return hip_status(kbe::launch_batch(items, items_dev, count, c, ws, (hipStream_t)stream),
+  return hip_status(kbe::launch_batch(items, items_dev, count, chunk, ws, (hipStream_t)stream),
                     "kbe_collision_batch");
 }
+
+}  // extern "C"
+
+namespace {
+// Event pair for the tuners, destroyed with the object.
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t init() {
+    hipError_t e = hipEventCreate(&a);
+    return e == hipSuccess ? hipEventCreate(&b) : e;
+  }
+  ~EventPair() {
+    if (a) hipEventDestroy(a);
+    if (b) hipEventDestroy(b);
+  }
+};
+
+// One warm-up call, then `reps` timed calls; *ms = the fastest.
+hipError_t time_batch(const kbe_batch_item *items, const kbe_batch_item *items_dev, int count,
+                      int chunk, void *ws, hipStream_t st, EventPair &ev, int reps, float *ms) {
+  hipError_t err = kbe::launch_batch(items, items_dev, count, chunk, ws, st);
+  *ms = -1.0f;
+  for (int r = 0; r < reps && err == hipSuccess; ++r) {
+    err = hipEventRecord(ev.a, st);
+    if (err == hipSuccess) err = kbe::launch_batch(items, items_dev, count, chunk, ws, st);
+    if (err == hipSuccess) err = hipEventRecord(ev.b, st);
+    if (err == hipSuccess) err = hipEventSynchronize(ev.b);
+    float t = 0.0f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&t, ev.a, ev.b);
+    if (err == hipSuccess && (*ms < 0.0f || t < *ms)) *ms = t;
+  }
+  return err;
+}
+
+int floor_log2(int64_t x) {
+  int b = 0;
+  while (x > 1) {
+    x >>= 1;
+    ++b;
+  }
+  return b;
+}
+}  // namespace
+
+extern "C" {
 
 kbe_status kbe_collision_batch_tune(const kbe_batch_item *items, const kbe_batch_item *items_dev,
                                     int32_t count, void *ws, size_t ws_bytes, void *stream,
@@ -319,22 +368,12 @@ kbe_status kbe_collision_batch_tune(const kbe_batch_item *items, const kbe_batch
   const size_t need = kbe::batch_ws_bytes(items, count, 32);  // the largest requirement
   if (!ws || ws_bytes < need) return fail(KBE_ENOMEM, "workspace %zu bytes < %zu", ws_bytes, need);
   hipStream_t st = (hipStream_t)stream;
-  hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess) return hip_status(hipGetLastError(), "hipEventCreate");
-  if (hipEventCreate(&e1) != hipSuccess) {
-    hipEventDestroy(e0);
-    return hip_status(hipGetLastError(), "hipEventCreate");
-  }
+  EventPair ev;
+  hipError_t err = ev.init();
   float best = -1.0f;
-  hipError_t err = hipSuccess;
   for (int k = 0; k < 4 && err == hipSuccess; ++k) {
-    err = kbe::launch_batch(items, items_dev, count, cand[k], ws, st);  // warm-up
-    if (err == hipSuccess) err = hipEventRecord(e0, st);
-    if (err == hipSuccess) err = kbe::launch_batch(items, items_dev, count, cand[k], ws, st);
-    if (err == hipSuccess) err = hipEventRecord(e1, st);
-    if (err == hipSuccess) err = hipEventSynchronize(e1);
     float ms = 0.0f;
-    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    err = time_batch(items, items_dev, count, cand[k], ws, st, ev, 1, &ms);
     if (err != hipSuccess) break;
     if (times_ms) times_ms[k] = ms;
     if (best < 0.0f || ms < best) {
@@ -342,9 +381,72 @@ kbe_status kbe_collision_batch_tune(const kbe_batch_item *items, const kbe_batch
       *best_chunk = cand[k];
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
   return hip_status(err, "kbe_collision_batch_tune");
+}
+
+kbe_status kbe_collision_batch_tune_groups(kbe_batch_item *items, kbe_batch_item *items_dev,
+                                           int32_t count, void *ws, size_t ws_bytes, void *stream,
+                                           float *best_ms) {
+  int32_t c0 = 0;
+  kbe_status s = kbe_collision_batch_tune(items, items_dev, count, ws, ws_bytes, stream, &c0, nullptr);
+  if (s != KBE_OK) return s;
+  if (best_ms) *best_ms = 0.0f;
+  if (count == 0) return ok();
+  hipStream_t st = (hipStream_t)stream;
+  const size_t isz = sizeof(kbe_batch_item) * (size_t)count;
+  // groups: (N, floor(log2(n + 1))), heaviest first by the blocks their items read
+  std::vector<int64_t> key(count);
+  std::vector<std::pair<double, int64_t>> weight;
+  for (int32_t i = 0; i < count; ++i) {
+    const kbe_batch_item &it = items[i];
+    key[i] = (int64_t)it.N * 64 + floor_log2((int64_t)it.n + 1);
+    const double w = (double)it.N * it.N * (2.0 * it.n + it.m + it.ntau + 4);
+    bool found = false;
+    for (auto &g : weight)
+      if (g.second == key[i]) {
+        g.first += w;
+        found = true;
+      }
+    if (!found) weight.push_back({w, key[i]});
+  }
+  std::sort(weight.begin(), weight.end(),
+            [](const std::pair<double, int64_t> &a, const std::pair<double, int64_t> &b) {
+              return a.first > b.first;
+            });
+  auto set_group = [&](int64_t g, int32_t c) {
+    for (int32_t i = 0; i < count; ++i)
+      if (key[i] == g) items[i].chunk = c;
+  };
+  auto upload = [&]() {
+    hipError_t e = hipMemcpyAsync(items_dev, items, isz, hipMemcpyHostToDevice, st);
+    return e == hipSuccess ? hipStreamSynchronize(st) : e;
+  };
+  EventPair ev;
+  hipError_t err = ev.init();
+  for (int32_t i = 0; i < count; ++i) items[i].chunk = c0;
+  if (err == hipSuccess) err = upload();
+  float cur = 0.0f;
+  if (err == hipSuccess) err = time_batch(items, items_dev, count, 0, ws, st, ev, 3, &cur);
+  static const int cand[4] = {32, 64, 128, 256};
+  for (const auto &g : weight) {
+    if (err != hipSuccess) break;
+    int32_t keep = c0;
+    for (int k = 0; k < 4 && err == hipSuccess; ++k) {
+      if (cand[k] == keep) continue;
+      set_group(g.second, cand[k]);
+      err = upload();
+      float t = 0.0f;
+      if (err == hipSuccess) err = time_batch(items, items_dev, count, 0, ws, st, ev, 3, &t);
+      if (err == hipSuccess && t < 0.99f * cur) {
+        cur = t;
+        keep = cand[k];
+      }
+    }
+    set_group(g.second, keep);
+  }
+  if (err == hipSuccess) err = upload();
+  if (best_ms) *best_ms = cur;
+  return hip_status(err, "kbe_collision_batch_tune_groups");
 }
 
 }  // extern "C"

@@ -165,8 +165,8 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
         kbe.lib()
 
 
-def batch_item(N=4, n=10, m=3, ntau=6, flags=0x7):
-    f = kbe._BatchItem(N, n, m, ntau, flags, 0, *([FAKE] * 13))
+def batch_item(N=4, n=10, m=3, ntau=6, flags=0x7, chunk=0):
+    f = kbe._BatchItem(N, n, m, ntau, flags, chunk, *([FAKE] * 13))
     return f
 
 
@@ -187,6 +187,8 @@ def test_batch_argument_errors():
     assert batch_call([batch_item(ntau=1)]) == EINVAL
     assert batch_call([batch_item(flags=0x8)]) == EINVAL   # J^] is not a per-row output
     assert batch_call([batch_item()], chunk=48) == EINVAL
+    assert batch_call([batch_item(chunk=100)]) == EINVAL   # an item's own chunk is checked too
+    assert batch_call([batch_item(chunk=-32)]) == EINVAL
     assert batch_call([batch_item()], count=65537) == ERANGE
     it = batch_item()
     it.IR = None
@@ -216,3 +218,33 @@ def test_batch_workspace_counts_chunks():
         tables = 2 * ((8 * 3 + 255) // 256 * 256) + (4 * 2 + 255) // 256 * 256 + 256
         assert L.kbe_collision_batch_workspace(arr, 2, chunk) == tables + 16 * parts
     assert L.kbe_collision_batch_workspace(arr, 2, 48) == 0
+
+
+def test_batch_workspace_item_chunks():
+    """Call chunk 0: each item's own chunk, 64 where it has none; a call chunk overrides them."""
+    L = kbe.lib()
+    c = lambda k, ch: (k + ch - 1) // ch
+    items = [batch_item(N=4, n=100, m=30, ntau=64, chunk=32),
+             batch_item(N=2, n=300, m=299, ntau=64, chunk=0)]
+    arr = (kbe._BatchItem * 2)(*items)
+    tables = 2 * ((8 * 3 + 255) // 256 * 256) + (4 * 2 + 255) // 256 * 256 + 256
+    parts = ((c(31, 32) + c(70, 32) + c(31, 32) + c(64, 32)) * 16 +
+             (c(300, 64) + c(1, 64) + c(300, 64) + c(64, 64)) * 4)
+    assert L.kbe_collision_batch_workspace(arr, 2, 0) == tables + 16 * parts
+    parts = ((c(31, 256) + c(70, 256) + c(31, 256) + c(64, 256)) * 16 +
+             (c(300, 256) + c(1, 256) + c(300, 256) + c(64, 256)) * 4)
+    assert L.kbe_collision_batch_workspace(arr, 2, 256) == tables + 16 * parts
+    arr[0].chunk = 48
+    assert L.kbe_collision_batch_workspace(arr, 2, 0) == 0
+
+
+def test_batch_tile_table_keys_and_tuner_errors(tmp_path):
+    """Tile-table keys (N, floor(log2(n + 1))) and the group tuner's argument checks."""
+    assert kbe.Batch.group(16, 0) == "16:0"
+    assert kbe.Batch.group(8, 1) == "8:1" and kbe.Batch.group(8, 2) == "8:1"
+    assert kbe.Batch.group(2, 4095) == "2:12" and kbe.Batch.group(2, 4094) == "2:11"
+    L = kbe.lib()
+    arr = (kbe._BatchItem * 1)(batch_item(N=0))
+    assert L.kbe_collision_batch_tune_groups(arr, FAKE, 1, FAKE, 1 << 40, None, None) == 1
+    arr = (kbe._BatchItem * 1)(batch_item())
+    assert L.kbe_collision_batch_tune_groups(arr, FAKE, 1, FAKE, 16, None, None) == 3

@@ -181,3 +181,35 @@ def test_batch_full_size_sampled(gpu):
         for k, got in enumerate((batch.IR[i], batch.IL[i], batch.Itv[i])):
             err = np.linalg.norm(to_host(got) - ref[k])
             assert err <= RTOL * sc[k], (i, k, err, sc[k])
+
+
+def test_batch_tile_table(mixed, tmp_path):
+    """The per-group autotuner: every item gets its group's chunk (one of the allowed sizes); the
+    table runs through chunk 0 to the oracle bar; a saved and reloaded table gives the same
+    chunks and bitwise the same results."""
+    import torch
+    batch, refs = mixed
+    ms, table = batch.tune_groups()
+    _print("tile table", ms, table)
+    assert ms > 0 and set(table.values()) <= {32, 64, 128, 256}
+    for i, it in enumerate(batch.items):
+        assert batch._host[i].chunk == table[batch.group(it.N, it.n)]
+    batch.run(0)
+    torch.cuda.synchronize()
+    _check(batch, refs)
+    first = [to_host(x) for x in batch.IR + batch.IL + batch.Itv if x is not None]
+    path = tmp_path / "tiles.json"
+    batch.save_table(path)
+    batch.apply_table({})            # every item back to the default chunk
+    assert all(batch._host[i].chunk == 0 for i in range(batch.count))
+    batch.run(0)
+    torch.cuda.synchronize()
+    _check(batch, refs)
+    batch.load_table(path)
+    assert batch.table() == table
+    batch.run(0)
+    torch.cuda.synchronize()
+    again = [to_host(x) for x in batch.IR + batch.IL + batch.Itv if x is not None]
+    for a, b in zip(first, again):
+        assert np.array_equal(a, b)
+    batch.apply_table({})
