@@ -238,3 +238,64 @@ def sigma_row_vjp(G: Green, u, n: int, gsig, grads=None, gu=None):
     _load().orc_sigma_row_vjp(*G.args(), _p(G.kp), _p(G.rdiag), _p(G.tv), _p(u), n, _p(gret),
                               _p(gles), _p(gstv), _p(gkp), _p(grd), _p(gtv), _p(gu))
     return gkp, grd, gtv, gu
+
+
+# ------------------------------------------------------------------------------------------
+# Second-Born self-energy with a general four-index interaction (Eq. SE).
+#
+# Sigma_ij = sum_{f,d,e,a,b,c} U_ifde Uex_jabc A_fb A_ea C_cd, with Uex_jabc = 2 U_jbac - U_jabc,
+# A = G^<>(t,t') and C = G^><(t',t) on the real axis, A = G^](t,tau) and C = G^[(tau,t) on the
+# mixed branch.  The six-fold sum is evaluated as the nested sums it factors into (over c, then b,
+# then a, then f, d, e together); each partial sum is one numpy contraction.  U is real,
+# U[i, f, d, e] = U_ifde.
+# ------------------------------------------------------------------------------------------
+def uex(U):
+    """Exchange tensor of Eq. SE: Uex[j, a, b, c] = 2 U[j, b, a, c] - U[j, a, b, c]."""
+    U = np.asarray(U, np.float64)
+    return 2.0 * np.transpose(U, (0, 2, 1, 3)) - U
+
+
+def gf2_block(U, A, C):
+    """Eq. SE at one time argument pair: sum U_ifde Uex_jabc A_fb A_ea C_cd."""
+    U = np.asarray(U, np.float64)
+    X = uex(U)
+    s1 = np.einsum("jabc,cd->jabd", X, C)      # sum over c
+    s2 = np.einsum("fb,jabd->jfad", A, s1)     # sum over b
+    s3 = np.einsum("ea,jfad->jfed", A, s2)     # sum over a
+    return np.einsum("ifde,jfed->ij", U, s3)   # sum over f, d, e
+
+
+def les_block(G: Green, a: int, b: int):
+    """G^<(t_a, t_b) from the storage: kp[a][b] for a <= b, else -kp[b][a]^dagger."""
+    return G.kp[a, b].copy() if a <= b else -G.kp[b, a].conj().T
+
+
+def gtr_block(G: Green, a: int, b: int):
+    """G^>(t_a, t_b): G^R + G^< for a >= b (G^R in rdiag at a = b), else -G^>(t_b, t_a)^dagger."""
+    if a >= b:
+        ret = G.rdiag[a] if a == b else G.kp[a, b]
+        return ret + les_block(G, a, b)
+    return -gtr_block(G, b, a).conj().T
+
+
+def sigma_gf2_row(G: Green, U, n: int, s_list=None, l_list=None):
+    """(ret[n+1], les[n+1], stv[ntau]) at t_n with a general U: ret = Sigma^> - Sigma^<,
+    les = Sigma^<, stv[l] = Sigma^](t_n, tau_l) with G^[(tau_l, t_n) = G^](t_n, beta - tau_l)^dagger
+    (symmetric tau grid: beta - tau_l = tau_{J-l}).  s_list / l_list restrict the computed
+    entries (the others stay NaN)."""
+    N = G.N
+    ntau = G.ntau
+    ret = np.full((n + 1, N, N), np.nan, np.complex128)
+    les = np.full((n + 1, N, N), np.nan, np.complex128)
+    stv = np.full((ntau, N, N), np.nan, np.complex128)
+    for s in (range(n + 1) if s_list is None else s_list):
+        l_ns, g_ns = les_block(G, n, s), gtr_block(G, n, s)
+        l_sn, g_sn = les_block(G, s, n), gtr_block(G, s, n)
+        sl = gf2_block(U, l_ns, g_sn)
+        sg = gf2_block(U, g_ns, l_sn)
+        les[s] = sl
+        ret[s] = sg - sl
+    J = ntau - 1
+    for l in (range(ntau) if l_list is None else l_list):
+        stv[l] = gf2_block(U, G.tv[n, l], G.tv[n, J - l].conj().T)
+    return ret, les, stv
