@@ -181,6 +181,29 @@ kbe_status kbe_sigma_2b(const kbe_green *G, const double *u, int32_t n, const kb
                         void *stream);
 
 /* ---------------------------------------------------------------------------
+ * kbe_sigma_gf2 — second-Born self-energy row at t_n with a general
+ * four-index interaction (Eq. SE):
+ *   Sigma^<>_ij(t,t') = sum U_ifde Uex_jabc G^<>_fb(t,t') G^<>_ea(t,t') G^><_cd(t',t)
+ *   Sigma^]_ij(t,tau) = sum U_ifde Uex_jabc G^]_fb(t,tau) G^]_ea(t,tau) G^[_cd(tau,t)
+ * summed over f, d, e, a, b, c, with Uex_jabc = 2 U_jbac - U_jabc and
+ * G^[(tau,t) = G^](t,beta-tau)^dagger, for t = t_n, t' = t_s (s = 0..n) and
+ * every tau_l.  Outputs as kbe_sigma_2b: out->ret[s] = Sigma^> - Sigma^<,
+ * out->les[s] = Sigma^<, out->tv[l].  With U_ijkl = u_i d_ij d_jk d_kl the
+ * result is kbe_sigma_2b's.  Cost: 4 N^5 complex multiply-adds per block.
+ *
+ * Arguments: G (device arrays, read as kbe_sigma_2b reads them); U device
+ * [N][N][N][N] real, U[i][f][d][e] = U_ifde (the index order of Eq. SE; the
+ * Hartree-Fock term of Eq. eps pairs its indices as chemists' two-electron
+ * integrals (ij|kl)); 0 <= n < G->nt; out device arrays (overwritten); ws a
+ * device workspace of kbe_sigma_gf2_workspace(N) bytes (zero-padded copies of
+ * U and Uex, rewritten by every call).
+ * Errors: KBE_EINVAL (NULL, bad shape), KBE_ERANGE (n), KBE_ENOMEM (ws).
+ * ------------------------------------------------------------------------- */
+size_t kbe_sigma_gf2_workspace(int32_t N);
+kbe_status kbe_sigma_gf2(const kbe_green *G, const double *U, int32_t n, const kbe_sigma_row *out,
+                         void *ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
  * kbe_collision — history integrals at t = t_n for t' = t_m, m in [m0, m1)
  * (the integrals of Eq. KBE2, lesser form, and of Eq. KBE3):
  *   IR[m-m0]  = sum_{s=0}^{n} w[n][s] Sigma^R(t_n,t_s) G^<(t_s,t_m)

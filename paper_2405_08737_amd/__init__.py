@@ -62,7 +62,8 @@ class _BatchItem(ctypes.Structure):
 
 EXPORTS = ("kbe_weights_workspace", "kbe_weights", "kbe_sigma_2b", "kbe_collision_workspace",
            "kbe_collision", "kbe_collision_vjp_workspace", "kbe_collision_vjp",
-           "kbe_sigma_2b_vjp_workspace", "kbe_sigma_2b_vjp", "kbe_collision_batch_workspace",
+           "kbe_sigma_2b_vjp_workspace", "kbe_sigma_2b_vjp", "kbe_sigma_gf2_workspace",
+           "kbe_sigma_gf2", "kbe_collision_batch_workspace",
            "kbe_collision_batch", "kbe_collision_batch_tune", "kbe_collision_batch_tune_groups",
            "kbe_status_string",
            "kbe_last_error", "kbe_version")
@@ -83,6 +84,8 @@ def lib():
             "kbe_weights_workspace": (SZ, [GR]),
             "kbe_weights": (I32, [GR, P, P, P, P, SZ, P]),
             "kbe_sigma_2b": (I32, [G, P, I32, R, P]),
+            "kbe_sigma_gf2_workspace": (SZ, [I32]),
+            "kbe_sigma_gf2": (I32, [G, P, I32, R, P, SZ, P]),
             "kbe_collision_workspace": (SZ, [I32, I32, I32, I32, I32, I32, U32]),
             "kbe_collision": (I32, [G, R, W, I32, I32, I32, U32, P, P, P, P, P, SZ, P]),
             "kbe_collision_vjp_workspace": (SZ, [I32, I32, I32, I32, I32, I32, U32]),
@@ -200,6 +203,25 @@ def sigma_2b(G: Green, u: torch.Tensor, n: int):
     row = _row(ret, les, stv)
     _check(lib().kbe_sigma_2b(ctypes.byref(G.c()), _ptr(u), n, ctypes.byref(row), _stream(dev)),
            "kbe_sigma_2b")
+    return ret, les, stv
+
+
+def sigma_gf2(G: Green, U: torch.Tensor, n: int):
+    """kbe_sigma_gf2: (ret[n+1], les[n+1], tv[ntau]) second-Born row at t_n with a general
+    four-index interaction U [N, N, N, N] (float64, U[i, f, d, e] = U_ifde of Eq. SE)."""
+    N, dev = G.N, G.device
+    if tuple(U.shape) != (N, N, N, N) or U.dtype != torch.float64 or not U.is_contiguous():
+        raise KBEError(f"U must be a contiguous float64 [{N}]*4 tensor, got {tuple(U.shape)} "
+                       f"{U.dtype}")
+    ret = torch.empty((n + 1, N, N), dtype=torch.complex128, device=dev)
+    les = torch.empty_like(ret)
+    stv = torch.empty((G.ntau, N, N), dtype=torch.complex128, device=dev) if G.ntau else None
+    row = _row(ret, les, stv)
+    L = lib()
+    nb = L.kbe_sigma_gf2_workspace(N)
+    ws = _ws(nb, dev)
+    _check(L.kbe_sigma_gf2(ctypes.byref(G.c()), _ptr(U), n, ctypes.byref(row), _ptr(ws), nb,
+                           _stream(dev)), "kbe_sigma_gf2")
     return ret, les, stv
 
 

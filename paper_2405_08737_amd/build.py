@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(HERE, "_build")
 SO = os.path.join(HERE, "libkbe.so")
-SOURCES = ["kbe_capi.hip", "kbe_weights.hip", "kbe_sigma.hip", "kbe_collision.hip",
+SOURCES = ["kbe_capi.hip", "kbe_weights.hip", "kbe_sigma.hip", "kbe_gf2.hip", "kbe_collision.hip",
            "kbe_batch.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

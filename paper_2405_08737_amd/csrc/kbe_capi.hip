@@ -166,6 +166,24 @@ kbe_status kbe_sigma_2b(const kbe_green *G, const double *u, int32_t n, const kb
   return hip_status(kbe::launch_sigma_row(G, u, n, out, (hipStream_t)stream), "kbe_sigma_2b");
 }
 
+size_t kbe_sigma_gf2_workspace(int32_t N) {
+  if (N < 1 || N > KBE_NMAX) return 0;
+  return kbe::gf2_ws_bytes(N);
+}
+
+kbe_status kbe_sigma_gf2(const kbe_green *G, const double *U, int32_t n, const kbe_sigma_row *out,
+                         void *ws, size_t ws_bytes, void *stream) {
+  kbe_status s = check_green(G, "G");
+  if (s != KBE_OK) return s;
+  if (n < 0 || n >= G->nt) return fail(KBE_ERANGE, "n = %d outside [0, nt = %d)", n, G->nt);
+  if (!U) return fail(KBE_EINVAL, "U is NULL");
+  if (!out || !out->ret || !out->les) return fail(KBE_EINVAL, "output row is NULL");
+  if (G->ntau > 0 && !out->tv) return fail(KBE_EINVAL, "out->tv is NULL with ntau > 0");
+  const size_t need = kbe::gf2_ws_bytes(G->N);
+  if (!ws || ws_bytes < need) return fail(KBE_ENOMEM, "workspace %zu bytes < %zu", ws_bytes, need);
+  return hip_status(kbe::launch_sigma_gf2(G, U, n, out, ws, (hipStream_t)stream), "kbe_sigma_gf2");
+}
+
 size_t kbe_sigma_2b_vjp_workspace(int32_t N, int32_t n, int32_t ntau) {
   if (N < 1 || n < 0 || ntau < 0) return 0;
   return kbe::sigma_vjp_ws_bytes(N, n, ntau);

@@ -22,6 +22,11 @@ hipError_t launch_sigma_row_vjp(const kbe_green *G, const double *u, int n,
                                 const kbe_sigma_row *gS, const kbe_green *gG, double *gu,
                                 void *ws, hipStream_t st);
 
+// Second-Born self-energy with a general four-index interaction (kbe_gf2.hip).
+size_t gf2_ws_bytes(int N);
+hipError_t launch_sigma_gf2(const kbe_green *G, const double *U, int n, const kbe_sigma_row *out,
+                            void *ws, hipStream_t st);
+
 // History integrals and their adjoint (kbe_collision.hip).
 size_t collision_ws_bytes(int N, int nt, int ntau, int n, int m0, int m1, unsigned flags);
 hipError_t launch_collision(const Params &p, unsigned flags, kbe_c128 *IR, kbe_c128 *IL,

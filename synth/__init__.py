@@ -214,3 +214,17 @@ def batch_cross(spec: BatchSpec, ntau: int, hmin: float, hmax: float, omin: int,
     rd = rdiag(N, 1)[0]
     tvm = tv(s, N, ntau, t, decay, rows=(m, m + 1))[0] if ntau > 0 else np.zeros((0, N, N), np.complex128)
     return dict(t=t, order=order, ret=ret, les=les, stv=stv, col=col, row=row, rdiag=rd, tv=tvm)
+
+
+def coulomb(seed: int, N: int, onsite: float = 1.0, spread: float = 0.1) -> np.ndarray:
+    """A real four-index interaction U[i, f, d, e] in chemists' notation (ij|kl): on-site value
+    `onsite` on U[i, i, i, i] plus N(0, spread^2) entries averaged over the eight index
+    permutations (ij|kl) = (ji|kl) = (ij|lk) = (kl|ij) ..., so it has the symmetry of real
+    two-electron integrals.  Stands in for molecular integrals (none are available offline)."""
+    U0 = spread * normal(seed, 99, (N, N, N, N)).real
+    perms = [(0, 1, 2, 3), (1, 0, 2, 3), (0, 1, 3, 2), (1, 0, 3, 2),
+             (2, 3, 0, 1), (3, 2, 0, 1), (2, 3, 1, 0), (3, 2, 1, 0)]
+    U = sum(np.transpose(U0, p) for p in perms) / 8.0
+    for i in range(N):
+        U[i, i, i, i] += onsite
+    return np.ascontiguousarray(U)

@@ -124,6 +124,28 @@ def test_vjp_argument_errors():
     assert st == 1 and "u" in err()
 
 
+def test_sigma_gf2_argument_errors_and_workspace():
+    """kbe_sigma_gf2: zero-padded U and Uex in the workspace (2 NP^4 doubles, NP = 4, 8 or 16)."""
+    L = kbe.lib()
+    for N, NP in ((1, 4), (4, 4), (5, 8), (8, 8), (9, 16), (16, 16)):
+        assert L.kbe_sigma_gf2_workspace(N) == 2 * NP ** 4 * 8
+    assert L.kbe_sigma_gf2_workspace(0) == 0 and L.kbe_sigma_gf2_workspace(17) == 0
+    G = green()
+    ws = L.kbe_sigma_gf2_workspace(G.N)
+    st = L.kbe_sigma_gf2(ctypes.byref(G), FAKE, 8, ctypes.byref(row()), FAKE, ws, None)
+    assert st == 2
+    st = L.kbe_sigma_gf2(ctypes.byref(G), None, 3, ctypes.byref(row()), FAKE, ws, None)
+    assert st == 1 and "U" in err()
+    st = L.kbe_sigma_gf2(ctypes.byref(G), FAKE, 3, ctypes.byref(row()), FAKE, ws - 8, None)
+    assert st == 3 and "workspace" in err()
+    st = L.kbe_sigma_gf2(ctypes.byref(G), FAKE, 3, ctypes.byref(row()), None, ws, None)
+    assert st == 3
+    bad = row()
+    bad.les = None
+    st = L.kbe_sigma_gf2(ctypes.byref(G), FAKE, 3, ctypes.byref(bad), FAKE, ws, None)
+    assert st == 1
+
+
 def grid_call(t, order, ntau=0, beta=1.0, tau_order=5, ws_bytes=1 << 40):
     L = kbe.lib()
     t = np.ascontiguousarray(t, np.float64)
