@@ -180,6 +180,29 @@ def small_orbital_shape(kbe, torch, dev, reps=5):
             "traffic": measured_traffic("traffic_collision_N8_nt1024.json")}
 
 
+def general_u_sigma(kbe, torch, G, n, w, reps=5):
+    """kbe_sigma_gf2 on the headline row (same G, n, ntau) with a synthetic symmetric U, calls
+    back to back.  Algorithmic FLOP per block: 24 N^5 (two real-by-complex and two complex
+    contractions of N^5 multiply-adds); blocks: 2 (n + 1) real-time + ntau mixed."""
+    import synth
+    N = G.N
+    U = torch.from_numpy(synth.coulomb(w.seed, N)).to(G.device)
+    for _ in range(2):
+        kbe.sigma_gf2(G, U, n)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        kbe.sigma_gf2(G, U, n)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    flop = 24.0 * N ** 5 * (2 * (n + 1) + G.ntau)
+    return {"workload": f"N{N}_nt{G.nt}_ntau{G.ntau} row n={n}, U: symmetric (ij|kl), on-site 1",
+            "ms": ms, "algorithmic_flop": flop, "tflops": flop / ms / 1e9,
+            "frac_f64_peak": flop / ms / 1e9 / MFMA_F64_PEAK_TFLOPS}
+
+
 def batching(kbe, torch, dev, reps=10):
     """The batching workload: one kbe_collision_batch launch over 256 rows of independent systems
     (the best common chunk, then the per-group tile table from the library's autotuners), its
@@ -389,6 +412,8 @@ def main():
             "intensity_flop_per_byte": c["fwd_flop"] / c["fwd_bytes"],
             "hbm_frac": c["fwd_bytes"] / coll_s / 1e9 / HBM_PEAK_GBS},
     }
+    log("general four-index self-energy")
+    result["gf2"] = general_u_sigma(kbe, torch, G, n, w)
     del gG, kp, tvd, G
     torch.cuda.empty_cache()
     log("8-orbital differentiation shape")
