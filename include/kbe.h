@@ -345,10 +345,12 @@ kbe_status kbe_collision_batch_tune(const kbe_batch_item *items, const kbe_batch
 /* ---------------------------------------------------------------------------
  * kbe_collision_batch_tune_groups — the autotuner's tile table: a chunk size
  * per group of items, a group being the items of one N and one length bucket
- * floor(log2(n + 1)).  It starts from the best common chunk, then, for each
- * group in decreasing order of its bytes, tries the other chunk sizes on that
- * group's items alone and keeps one only if the whole call (best of three timed
- * calls after a warm-up) gets faster by more than 1%.  On return every item's
+ * floor(log2(n + 1)).  It starts from the best common chunk and makes two
+ * coordinate-descent passes, first over the groups of one N, then over the
+ * groups of one N and one length bucket: for each group in decreasing order of
+ * its bytes it tries the other chunk sizes on that group's items alone and keeps
+ * one only if the whole call (best of three timed calls after a warm-up) gets
+ * faster by more than 1%.  On return every item's
  * chunk field holds its group's chunk, in items and (copied by this call) in
  * items_dev, so kbe_collision_batch(..., chunk = 0, ...) runs the table; the
  * caller may read the fields back to store the table.  *best_ms (if not NULL)

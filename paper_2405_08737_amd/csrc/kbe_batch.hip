@@ -8,8 +8,9 @@
 //   ITV: j in [0, ntau)  -i wtau[j] sig_tv[j] tv[J-j]^dagger           (Q P^dagger)
 // Both factors of a term are streamed (nothing is shared between terms), so the work is bound by
 // HBM bandwidth at every N (N/4 FLOP per byte).  Each wave takes tasks from one atomic counter
-// and runs the code path of its item's N: blocks zero-padded to 8 x 8 (N <= 8) or 16 x 16
-// (9 <= N <= 16), multiplied with v_mfma_f64_4x4x4, three real products per complex one:
+// and runs the code path of its item's N: one lane per term on the vector ALU (N <= 4), or
+// blocks zero-padded to 8 x 8 (5 <= N <= 8) or 16 x 16 (9 <= N <= 16) multiplied with
+// v_mfma_f64_4x4x4, three real products per complex one:
 //   k1 += (ar + ai) br,  k2 += ar (bi - br),  k3 += ai (br + bi);  Re = k1 - k3, Im = k1 + k2.
 // A task writes its partial sum to the workspace; a reduce adds an item's partials in task
 // order, so results are deterministic.  The task plan (per-item task and partial offsets) is
@@ -22,7 +23,8 @@ namespace kbe {
 
 namespace {
 
-constexpr int BQLD = 20;  // LDS row stride of a staged 16 x 16 block, in complex numbers
+constexpr int BQLD = 20;     // LDS row stride of a staged 16 x 16 block, in complex numbers
+constexpr int TB_LDS = 2048;  // task-offset entries kept in LDS (batches of up to 2047 items)
 
 __device__ __forceinline__ double mfma4b(double a, double b, double c) {
   return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
@@ -75,6 +77,69 @@ __device__ __forceinline__ void item_range(const kbe_batch_item &it, int k, int 
 // c = (fr + i fi) w per class: IRC 1, IRR -1, IL 1, ITV -i.
 __device__ __forceinline__ cd class_factor(int k, double w) {
   return k == 1 ? cd{-w, 0.0} : (k == 3 ? cd{0.0, -w} : cd{w, 0.0});
+}
+
+// ---------------------------------------------------------------------------------------
+// N <= 4: one lane per term, 64 terms per pass; the lane adds c Q op(P) into its N x N
+// accumulator (op(P) = P or P^dagger), then the wave's 64 accumulators are summed by a
+// reduce-scatter (the accumulator padded to EP = 1, 4 or 16 entries: halving steps on lane bits
+// 5, 4, ... leave lane l with one entry, whose index is read from those bits, and the remaining
+// lane bits are summed by butterflies).
+// ---------------------------------------------------------------------------------------
+template <int N>
+__device__ void task_tiny(const kbe_batch_item &it, int k, int t0, int t1, kbe_c128 *out,
+                          int lane) {
+  constexpr int E = N * N, EP = E == 1 ? 1 : (E <= 4 ? 4 : 16), LB = EP == 1 ? 0 : (EP == 4 ? 2 : 4);
+  const bool dag = k != 0;
+  cd acc[EP];
+#pragma unroll
+  for (int e = 0; e < EP; ++e) acc[e] = czero();
+  for (int t = t0 + lane; t < t1; t += 64) {
+    const Term tm = item_term(it, k, t);
+    const cd c = class_factor(k, tm.w);
+    cd q[E], p[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      q[e] = ldg(tm.Q + e);
+      p[e] = ldg(tm.P + e);
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int l = 0; l < N; ++l) {
+        const cd cq = c * q[i * N + l];
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          const cd x = dag ? cj(p[j * N + l]) : p[l * N + j];
+          cd &a = acc[i * N + j];
+          a.re = __builtin_fma(cq.re, x.re, a.re);
+          a.re = __builtin_fma(-cq.im, x.im, a.re);
+          a.im = __builtin_fma(cq.re, x.im, a.im);
+          a.im = __builtin_fma(cq.im, x.re, a.im);
+        }
+      }
+  }
+#pragma unroll
+  for (int s = 0; s < LB; ++s) {
+    const int m = 32 >> s, c = EP >> (s + 1);
+    const bool up = lane & m;
+#pragma unroll
+    for (int kk = 0; kk < c; ++kk) {
+      const cd lo = acc[kk], hi = acc[kk + c];
+      const cd send = up ? lo : hi, keep = up ? hi : lo;
+      acc[kk].re = keep.re + __shfl_xor(send.re, m);
+      acc[kk].im = keep.im + __shfl_xor(send.im, m);
+    }
+  }
+#pragma unroll
+  for (int m = 32 >> LB; m >= 1; m >>= 1) {
+    acc[0].re += __shfl_xor(acc[0].re, m);
+    acc[0].im += __shfl_xor(acc[0].im, m);
+  }
+  int e = 0;
+#pragma unroll
+  for (int s = 0; s < LB; ++s) e = (e << 1) | ((lane >> (5 - s)) & 1);
+  if ((lane & ((64 >> LB) - 1)) == 0 && e < E) stg(out + e, acc[0]);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -326,18 +391,24 @@ __global__ void __launch_bounds__(256) batch_stream(const kbe_batch_item *items,
                                                     const int64_t *tb, const int64_t *pb,
                                                     kbe_c128 *parts, unsigned int *head) {
   __shared__ cd qtile[4][16 * BQLD];
+  __shared__ int64_t tbs[TB_LDS];  // the task offsets, when they fit
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const bool cached = count < TB_LDS;  // uniform
+  if (cached)
+    for (int j = threadIdx.x; j <= count; j += blockDim.x) tbs[j] = tb[j];
+  __syncthreads();
   const int64_t ntask = tb[count];
   for (;;) {
     unsigned int v = 0;
     if (lane == 0) v = atomicAdd(head, 1u);
     const int64_t task = (int64_t)__builtin_amdgcn_readfirstlane(v);
     if (task >= ntask) break;  // wave-uniform
-    // position in the processing order: the last j with tb[j] <= task (binary search)
+    // position in the processing order: the last j with tb[j] <= task (binary search, in LDS
+    // when the table fits)
     int lo = 0, hi = count - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (tb[mid] <= task) lo = mid;
+      if ((cached ? tbs[mid] : tb[mid]) <= task) lo = mid;
       else hi = mid - 1;
     }
     const int j = __builtin_amdgcn_readfirstlane(lo);
@@ -345,7 +416,7 @@ __global__ void __launch_bounds__(256) batch_stream(const kbe_batch_item *items,
     const kbe_batch_item it = items[i];
     int c[4];
     item_chunks(it, chunk, c);
-    const int64_t ltask = task - tb[j];
+    const int64_t ltask = task - (cached ? tbs[j] : tb[j]);
     int local = (int)ltask, k = 0;
     while (local >= c[k]) local -= c[k++];
     int t0, t1;
@@ -354,8 +425,15 @@ __global__ void __launch_bounds__(256) batch_stream(const kbe_batch_item *items,
     t0 += local * ch;
     t1 = t0 + ch < t1 ? t0 + ch : t1;
     kbe_c128 *out = parts + pb[i] + ltask * (int64_t)it.N * it.N;
-    if (it.N <= 8) task8(it, k, t0, t1, out, lane);
-    else task16(it, k, t0, t1, out, lane, qtile[wave]);
+    switch (it.N) {  // wave-uniform
+      case 1: task_tiny<1>(it, k, t0, t1, out, lane); break;
+      case 2: task_tiny<2>(it, k, t0, t1, out, lane); break;
+      case 3: task_tiny<3>(it, k, t0, t1, out, lane); break;
+      case 4: task_tiny<4>(it, k, t0, t1, out, lane); break;
+      default:
+        if (it.N <= 8) task8(it, k, t0, t1, out, lane);
+        else task16(it, k, t0, t1, out, lane, qtile[wave]);
+    }
   }
 }
 

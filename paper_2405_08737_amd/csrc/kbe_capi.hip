@@ -412,29 +412,6 @@ kbe_status kbe_collision_batch_tune_groups(kbe_batch_item *items, kbe_batch_item
   if (count == 0) return ok();
   hipStream_t st = (hipStream_t)stream;
   const size_t isz = sizeof(kbe_batch_item) * (size_t)count;
-  // groups: (N, floor(log2(n + 1))), heaviest first by the blocks their items read
-  std::vector<int64_t> key(count);
-  std::vector<std::pair<double, int64_t>> weight;
-  for (int32_t i = 0; i < count; ++i) {
-    const kbe_batch_item &it = items[i];
-    key[i] = (int64_t)it.N * 64 + floor_log2((int64_t)it.n + 1);
-    const double w = (double)it.N * it.N * (2.0 * it.n + it.m + it.ntau + 4);
-    bool found = false;
-    for (auto &g : weight)
-      if (g.second == key[i]) {
-        g.first += w;
-        found = true;
-      }
-    if (!found) weight.push_back({w, key[i]});
-  }
-  std::sort(weight.begin(), weight.end(),
-            [](const std::pair<double, int64_t> &a, const std::pair<double, int64_t> &b) {
-              return a.first > b.first;
-            });
-  auto set_group = [&](int64_t g, int32_t c) {
-    for (int32_t i = 0; i < count; ++i)
-      if (key[i] == g) items[i].chunk = c;
-  };
   auto upload = [&]() {
     hipError_t e = hipMemcpyAsync(items_dev, items, isz, hipMemcpyHostToDevice, st);
     return e == hipSuccess ? hipStreamSynchronize(st) : e;
@@ -446,22 +423,57 @@ kbe_status kbe_collision_batch_tune_groups(kbe_batch_item *items, kbe_batch_item
   float cur = 0.0f;
   if (err == hipSuccess) err = time_batch(items, items_dev, count, 0, ws, st, ev, 3, &cur);
   static const int cand[4] = {32, 64, 128, 256};
-  for (const auto &g : weight) {
-    if (err != hipSuccess) break;
-    int32_t keep = c0;
-    for (int k = 0; k < 4 && err == hipSuccess; ++k) {
-      if (cand[k] == keep) continue;
-      set_group(g.second, cand[k]);
-      err = upload();
-      float t = 0.0f;
-      if (err == hipSuccess) err = time_batch(items, items_dev, count, 0, ws, st, ev, 3, &t);
-      if (err == hipSuccess && t < 0.99f * cur) {
-        cur = t;
-        keep = cand[k];
-      }
+  // One coordinate-descent pass over the groups of a key, heaviest group first (by the blocks
+  // its items read): each other chunk is tried on the group alone and kept if the whole call
+  // gets more than 1% faster.
+  std::vector<int64_t> key(count);
+  auto pass = [&](bool by_length) {
+    std::vector<std::pair<double, int64_t>> weight;
+    for (int32_t i = 0; i < count; ++i) {
+      const kbe_batch_item &it = items[i];
+      key[i] = (int64_t)it.N * 64 + (by_length ? floor_log2((int64_t)it.n + 1) : 0);
+      const double w = (double)it.N * it.N * (2.0 * it.n + it.m + it.ntau + 4);
+      bool found = false;
+      for (auto &g : weight)
+        if (g.second == key[i]) {
+          g.first += w;
+          found = true;
+        }
+      if (!found) weight.push_back({w, key[i]});
     }
-    set_group(g.second, keep);
-  }
+    std::sort(weight.begin(), weight.end(),
+              [](const std::pair<double, int64_t> &a, const std::pair<double, int64_t> &b) {
+                return a.first > b.first;
+              });
+    auto set_group = [&](int64_t g, int32_t c) {
+      for (int32_t i = 0; i < count; ++i)
+        if (key[i] == g) items[i].chunk = c;
+    };
+    for (const auto &g : weight) {
+      if (err != hipSuccess) break;
+      int32_t keep = c0;
+      for (int32_t i = 0; i < count; ++i)
+        if (key[i] == g.second) {
+          keep = items[i].chunk;  // the group's chunk so far (one value per group)
+          break;
+        }
+      const int32_t start = keep;
+      for (int k = 0; k < 4 && err == hipSuccess; ++k) {
+        if (cand[k] == start) continue;
+        set_group(g.second, cand[k]);
+        err = upload();
+        float t = 0.0f;
+        if (err == hipSuccess) err = time_batch(items, items_dev, count, 0, ws, st, ev, 3, &t);
+        if (err == hipSuccess && t < 0.99f * cur) {
+          cur = t;
+          keep = cand[k];
+        }
+      }
+      set_group(g.second, keep);
+    }
+  };
+  pass(false);  // by N
+  pass(true);   // by N and length bucket
   if (err == hipSuccess) err = upload();
   if (best_ms) *best_ms = cur;
   return hip_status(err, "kbe_collision_batch_tune_groups");
