@@ -37,12 +37,14 @@ def _system(N, nt, ntau, seed):
 
 @pytest.fixture(scope="module")
 def mixed(gpu):
-    """Rows of seven systems (N = 1, 2, 3, 5, 8, 11, 16; with and without a thermal branch),
-    including m = 0, m = n, n = 0 and output subsets, interleaved in one batch."""
+    """Rows of eleven systems (N = 1, 2, 3, 4, 5, 6, 8, 9, 11, 13, 16: every code path and
+    padding; with and without a thermal branch), including m = 0, m = n, n = 0, rows longer than
+    one 64-term pass, and output subsets, interleaved in one batch."""
     kbe = gpu
     systems = [_system(*a) for a in [(1, 30, 0, 11), (2, 64, 64, 12), (3, 40, 7, 13),
-                                     (5, 50, 0, 14), (8, 90, 20, 15), (11, 45, 9, 16),
-                                     (16, 70, 12, 17)]]
+                                     (4, 150, 70, 18), (5, 50, 0, 14), (6, 33, 5, 19),
+                                     (8, 90, 20, 15), (9, 21, 3, 20), (11, 45, 9, 16),
+                                     (13, 27, 0, 21), (16, 70, 12, 17)]]
     rows = []
     for si, S in enumerate(systems):
         nt = S["nt"]
