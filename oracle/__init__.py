@@ -299,3 +299,45 @@ def sigma_gf2_row(G: Green, U, n: int, s_list=None, l_list=None):
     for l in (range(ntau) if l_list is None else l_list):
         stv[l] = gf2_block(U, G.tv[n, l], G.tv[n, J - l].conj().T)
     return ret, les, stv
+
+
+# ------------------------------------------------------------------------------------------
+# Adjoint of one row's integrals (the row function above), from its sums term by term.
+#
+# With PyTorch's convention for complex gradients (g = dL/dRe + i dL/dIm), a term c A B adds
+# conj(c) g B^dagger to the gradient of A and conj(c) A^dagger g to that of B, and a term
+# c A B^dagger adds conj(c) g B to A's and c g^dagger A to B's.  Each input block of a row enters
+# exactly one term, so every gradient block is one such product (zero for blocks the selected
+# outputs do not read).
+# ------------------------------------------------------------------------------------------
+def collision_row_vjp(N: int, ntau: int, n: int, m: int, sig, col, row, rdg, tvm, wn, wm, wfull,
+                      cot, flags: int = F_IR | F_IL | F_ITV):
+    """Gradients (g_ret [n+1], g_les [n+1], g_stv [ntau], g_col [m+1], g_row [n+1], g_rdiag,
+    g_tv [ntau]) of a real loss with cotangents cot = (gIR, gIL, gItv) of collision_row."""
+    ret, les, stv = (np.asarray(x, np.complex128) for x in sig)
+    gIR, gIL, gItv = (np.asarray(x, np.complex128) if x is not None else np.zeros((N, N), complex)
+                      for x in cot)
+    H = lambda x: x.conj().T
+    z = lambda k: np.zeros((k, N, N), np.complex128)
+    g_ret, g_les, g_stv, g_col, g_row, g_tv = z(n + 1), z(n + 1), z(ntau), z(m + 1), z(n + 1), z(ntau)
+    g_rdg = np.zeros((N, N), np.complex128)
+    if flags & F_IR:
+        for s in range(m + 1):        # wn[s] ret[s] col[s]
+            g_ret[s] = wn[s] * gIR @ H(col[s])
+            g_col[s] = wn[s] * H(ret[s]) @ gIR
+        for s in range(m + 1, n + 1):  # -wn[s] ret[s] row[s]^dagger
+            g_ret[s] = -wn[s] * gIR @ row[s]
+            g_row[s] = -wn[s] * H(gIR) @ ret[s]
+    if flags & F_IL:
+        for s in range(m):            # wm[s] les[s] row[s]^dagger
+            g_les[s] = wm[s] * gIL @ row[s]
+            g_row[s] = wm[s] * H(gIL) @ les[s]
+        g_les[m] = wm[m] * gIL @ rdg  # wm[m] les[m] rdiag^dagger
+        g_rdg = wm[m] * H(gIL) @ les[m]
+    if (flags & F_ITV) and ntau > 0:
+        J = ntau - 1
+        for j in range(ntau):         # -i wfull[j] stv[j] tv[J-j]^dagger
+            c = -1j * wfull[j]
+            g_stv[j] = np.conj(c) * gItv @ tvm[J - j]
+            g_tv[J - j] = c * H(gItv) @ stv[j]
+    return g_ret, g_les, g_stv, g_col, g_row, g_rdg, g_tv
