@@ -206,8 +206,10 @@ def general_u_sigma(kbe, torch, G, n, w, reps=5):
 def batching(kbe, torch, dev, reps=10):
     """The batching workload: one kbe_collision_batch launch over 256 rows of independent systems
     (the best common chunk, then the per-group tile table from the library's autotuners), its
-    graph replay, and the same rows as 256 separate launches.  Algorithmic bytes: every block a row reads once, its three outputs written once,
-    its weights; FLOP: 8 N^3 per block product."""
+    graph replay, the adjoint of the same rows in one kbe_collision_batch_vjp launch, and the
+    rows as 256 separate launches.  Algorithmic bytes: every block a row reads once, its three
+    outputs written once, its weights (adjoint: the blocks its nonzero gradients read, every
+    gradient block written once, the cotangents); FLOP: 8 N^3 per block product."""
     import synth
     B = synth.BATCH
     specs = synth.batch_specs(B["seed"], B["count"], B["Ns"], B["nmin"], B["nmax"])
@@ -255,6 +257,18 @@ def batching(kbe, torch, dev, reps=10):
     with torch.cuda.graph(g):
         batch.run(0)
     graph_ms = timed(g.replay, reps)
+    # the adjoint of the same rows (one launch), random cotangents
+    cots, vbytes, vflop = [], 0.0, 0.0
+    for r, sp in enumerate(specs):
+        cots.append(tuple(c(synth.normal(900 + r, k, (sp.N, sp.N))) for k in range(3)))
+        N, n, m, nt = sp.N, sp.n, sp.m, B["ntau"]
+        prods = (n + 1) + (m + 1) + (m + 1) + n + 1 + 2 * nt  # nonzero gradient blocks
+        vbytes += 16.0 * N * N * (prods + 3 * (n + 1) + (m + 1) + 1 + 2 * nt + 3)
+        vbytes += 8.0 * ((n + 1) + (m + 1) + nt)
+        vflop += 8.0 * N ** 3 * prods
+    bv = kbe.BatchVJP(items, cots)
+    vjp_ms = timed(bv.run, reps)
+    del bv
     singles = [kbe.Batch([it]) for it in items]
     for b in singles:
         b.apply_table(table)
@@ -269,7 +283,10 @@ def batching(kbe, torch, dev, reps=10):
             "gbps": nbytes / batched_ms / 1e6, "hbm_frac": nbytes / batched_ms / 1e6 / HBM_PEAK_GBS,
             "gflops": flop / batched_ms / 1e6, "algorithmic_bytes": nbytes,
             "algorithmic_flop": flop,
-            "traffic": measured_traffic("traffic_batch_256rows.json", BATCH_SOURCES)}
+            "traffic": measured_traffic("traffic_batch_256rows.json", BATCH_SOURCES),
+            "vjp": {"ms": vjp_ms, "algorithmic_bytes": vbytes, "gbps": vbytes / vjp_ms / 1e6,
+                    "hbm_frac": vbytes / vjp_ms / 1e6 / HBM_PEAK_GBS,
+                    "gflops": vflop / vjp_ms / 1e6, "over_forward": vjp_ms / batched_ms}}
 
 
 def main():

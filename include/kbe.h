@@ -361,6 +361,50 @@ kbe_status kbe_collision_batch_tune_groups(kbe_batch_item *items, kbe_batch_item
                                            int32_t count, void *ws, size_t ws_bytes, void *stream,
                                            float *best_ms);
 
+/* ---------------------------------------------------------------------------
+ * kbe_collision_batch_vjp — the adjoint of kbe_collision_batch (a project
+ * addition, for gradients through batches of rows).
+ *
+ * An item is a row as for kbe_collision_batch (its IR, IL, Itv are not used),
+ * the cotangents of the row's selected outputs, and the gradient arrays of the
+ * row's inputs.  Complex gradients follow PyTorch's convention (dL/dRe + i
+ * dL/dIm).  Each input block of a row enters exactly one term of one output,
+ * c A B or c A B^dagger, which gives it the gradient conj(c) g B^dagger,
+ * conj(c) A^dagger g (for c A B) or conj(c) g B, c g^dagger A (for
+ * c A B^dagger); so, with GR, GL, GT the cotangents of IR, IL, Itv:
+ *   g_sig_ret[s] = wn[s] GR col[s]^dagger (s <= m),  -wn[s] GR row[s] (s > m)
+ *   g_col[s]     = wn[s] sig_ret[s]^dagger GR                    (s <= m)
+ *   g_row[s]     = -wn[s] GR^dagger sig_ret[s] (s > m),  wm[s] GL^dagger sig_les[s] (s < m)
+ *   g_sig_les[s] = wm[s] GL row[s] (s < m),  wm[m] GL rdiag (s = m)
+ *   g_rdiag      = wm[m] GL^dagger sig_les[m]
+ *   g_sig_tv[j]  = i wtau[j] GT tv[J-j],  g_tv[J-j] = -i wtau[j] GT^dagger sig_tv[j]
+ * Every gradient block is overwritten; blocks no selected output reads
+ * (g_sig_les[s > m], g_row[m], and those of unselected outputs) are set to 0.
+ * No reduction is involved, so results do not depend on the schedule.
+ *
+ * items: host array (validated here); items_dev: the same array in device
+ * memory, read by the kernels; ws: kbe_collision_batch_vjp_workspace(count)
+ * bytes.  Nothing is copied from host memory and nothing is allocated, so the
+ * call can be captured in a HIP graph.
+ * Errors: KBE_EINVAL (NULL pointers, N out of range, bad flags), KBE_ERANGE
+ * (m > n, negative sizes, count > KBE_BATCH_MAX), KBE_ENOMEM (workspace).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  kbe_batch_item row;               /* the row, as for kbe_collision_batch */
+  const kbe_c128 *gIR, *gIL, *gItv; /* cotangents, one N x N block each (NULL when the flag is off) */
+  kbe_c128 *g_sig_ret, *g_sig_les;  /* [n+1] each */
+  kbe_c128 *g_sig_tv;               /* [ntau] (may be NULL when ntau == 0) */
+  kbe_c128 *g_col;                  /* [m+1] */
+  kbe_c128 *g_row;                  /* [n+1] */
+  kbe_c128 *g_rdiag;                /* [1] */
+  kbe_c128 *g_tv;                   /* [ntau] (may be NULL when ntau == 0) */
+} kbe_batch_vjp_item;
+
+size_t kbe_collision_batch_vjp_workspace(int32_t count);
+kbe_status kbe_collision_batch_vjp(const kbe_batch_vjp_item *items,
+                                   const kbe_batch_vjp_item *items_dev, int32_t count, void *ws,
+                                   size_t ws_bytes, void *stream);
+
 /* Human-readable name of a status code (static string). */
 const char *kbe_status_string(kbe_status s);
 /* Detail of the last error on the calling thread ("" if none). */

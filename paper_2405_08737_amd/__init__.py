@@ -60,11 +60,18 @@ class _BatchItem(ctypes.Structure):
                                              "tv", "wn", "wm", "wtau", "IR", "IL", "Itv")]
 
 
+class _BatchVjpItem(ctypes.Structure):
+    _fields_ = [("row", _BatchItem)] + [
+        (name, ctypes.c_void_p) for name in ("gIR", "gIL", "gItv", "g_sig_ret", "g_sig_les",
+                                             "g_sig_tv", "g_col", "g_row", "g_rdiag", "g_tv")]
+
+
 EXPORTS = ("kbe_weights_workspace", "kbe_weights", "kbe_sigma_2b", "kbe_collision_workspace",
            "kbe_collision", "kbe_collision_vjp_workspace", "kbe_collision_vjp",
            "kbe_sigma_2b_vjp_workspace", "kbe_sigma_2b_vjp", "kbe_sigma_gf2_workspace",
            "kbe_sigma_gf2", "kbe_collision_batch_workspace",
            "kbe_collision_batch", "kbe_collision_batch_tune", "kbe_collision_batch_tune_groups",
+           "kbe_collision_batch_vjp_workspace", "kbe_collision_batch_vjp",
            "kbe_status_string",
            "kbe_last_error", "kbe_version")
 
@@ -96,6 +103,8 @@ def lib():
             "kbe_collision_batch": (I32, [P, P, I32, I32, P, SZ, P]),
             "kbe_collision_batch_tune": (I32, [P, P, I32, P, SZ, P, P, P]),
             "kbe_collision_batch_tune_groups": (I32, [P, P, I32, P, SZ, P, P]),
+            "kbe_collision_batch_vjp_workspace": (SZ, [I32]),
+            "kbe_collision_batch_vjp": (I32, [P, P, I32, P, SZ, P]),
             "kbe_status_string": (ctypes.c_char_p, [I32]),
             "kbe_last_error": (ctypes.c_char_p, []),
             "kbe_version": (I32, []),
@@ -464,3 +473,47 @@ class Batch:
         """Read a tile table written by save_table and apply it."""
         with open(path) as f:
             self.apply_table(json.load(f)["chunk"])
+
+
+class BatchVJP:
+    """The adjoint of a fixed batch of rows (kbe_collision_batch_vjp): items as for Batch, cot a
+    list of (gIR, gIL, gItv) N x N cotangent tensors per item (None where a flag is off).  The
+    gradient arrays, the item table (host and device copy) and the workspace are allocated once;
+    run() only enqueues the call.  Gradients: self.g[i] = dict(sig_ret, sig_les, sig_tv, col,
+    row, rdiag, tv) of device tensors (sig_tv and tv None without a thermal branch)."""
+
+    def __init__(self, items, cot, device=None):
+        self.items = list(items)
+        self.count = len(self.items)
+        dev = device if device is not None else self.items[0].rdiag.device
+        self.device = dev
+        self.cot = [tuple(c) for c in cot]
+        mk = lambda k, N: torch.empty((k, N, N), dtype=torch.complex128, device=dev)
+        self.g = []
+        host = (_BatchVjpItem * max(self.count, 1))()
+        for i, (it, c) in enumerate(zip(self.items, self.cot)):
+            N, n, m, nt = it.N, it.n, it.m, it.ntau
+            g = dict(sig_ret=mk(n + 1, N), sig_les=mk(n + 1, N), sig_tv=mk(nt, N) if nt else None,
+                     col=mk(m + 1, N), row=mk(n + 1, N),
+                     rdiag=torch.empty((N, N), dtype=torch.complex128, device=dev),
+                     tv=mk(nt, N) if nt else None)
+            self.g.append(g)
+            row = _BatchItem(N, n, m, nt, it.flags, 0, _ptr(it.sig_ret), _ptr(it.sig_les),
+                             _ptr(it.sig_tv), _ptr(it.col), _ptr(it.row), _ptr(it.rdiag),
+                             _ptr(it.tv), _ptr(it.wn), _ptr(it.wm), _ptr(it.wtau), None, None, None)
+            host[i] = _BatchVjpItem(row, _ptr(c[0]), _ptr(c[1]), _ptr(c[2]), _ptr(g["sig_ret"]),
+                                    _ptr(g["sig_les"]), _ptr(g["sig_tv"]), _ptr(g["col"]),
+                                    _ptr(g["row"]), _ptr(g["rdiag"]), _ptr(g["tv"]))
+        self._host = host
+        raw = bytes(host)[:ctypes.sizeof(_BatchVjpItem) * self.count]
+        self._dev = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(dev)
+        L = lib()
+        self.ws_bytes = L.kbe_collision_batch_vjp_workspace(self.count)
+        self.ws = _ws(self.ws_bytes, dev)
+
+    def run(self):
+        """Enqueue kbe_collision_batch_vjp on the current stream."""
+        _check(lib().kbe_collision_batch_vjp(self._host, _ptr(self._dev), self.count,
+                                             _ptr(self.ws), self.ws_bytes,
+                                             _stream(self.device)), "kbe_collision_batch_vjp")
+        return self.g

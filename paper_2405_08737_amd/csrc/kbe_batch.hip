@@ -32,6 +32,24 @@ __device__ __forceinline__ double mfma4b(double a, double b, double c) {
 
 __device__ __forceinline__ int cdivd(int a, int b) { return (a + b - 1) / b; }
 
+// A copy of *p held in scalar registers (p and *p the same for every lane of the wave), so that
+// values and branches derived from it are wave-uniform.
+template <typename T>
+__device__ __forceinline__ T uniform_copy(const T *p) {
+  static_assert(sizeof(T) % 4 == 0, "word-sized struct");
+  T v;
+  const unsigned *src = (const unsigned *)p;
+  unsigned *dst = (unsigned *)&v;
+#pragma unroll
+  for (int w = 0; w < (int)(sizeof(T) / 4); ++w) dst[w] = __builtin_amdgcn_readfirstlane(src[w]);
+  return v;
+}
+
+// A double through a pointer known to address global memory (not a flat access).
+__device__ __forceinline__ double ldgd(const double *p) {
+  return *(const __attribute__((address_space(1))) double *)(const void *)p;
+}
+
 // Terms per work unit of an item: the call's chunk when it is set, else the item's own, else the
 // default.
 __host__ __device__ inline int item_chunk(const kbe_batch_item &it, int chunk) {
@@ -71,6 +89,39 @@ __device__ __forceinline__ void item_range(const kbe_batch_item &it, int k, int 
     case 1: lo = it.m + 1; hi = it.n + 1; break;
     case 2: lo = 0; hi = it.m + 1; break;
     default: lo = 0; hi = it.ntau; break;
+  }
+}
+
+// Adjoint classes: the gradient blocks of a row, grouped by the product that gives them.
+//   V0 g_sig_ret[s], s <= m:  wn[s] GR col[s]^dagger          (form GX^dagger)
+//   V1 g_sig_ret[s], s > m : -wn[s] GR row[s]                  (form GX)
+//   V2 g_sig_les[s], s <= m:  wm[s] GL (row[s] | rdiag)        (form GX)
+//   V3 g_sig_les[s], s > m :  0
+//   V4 g_col[s],     s <= m:  wn[s] sig_ret[s]^dagger GR       (form X^dagger G)
+//   V5 g_row[s],     s > m : -wn[s] GR^dagger sig_ret[s]       (form G^dagger X)
+//   V6 g_row[s],     s <= m:  wm[s] GL^dagger sig_les[s] (s < m), 0 (s = m)
+//   V7 g_rdiag:               wm[m] GL^dagger sig_les[m]
+//   V8 g_sig_tv[j]:           i wtau[j] GT tv[J-j]             (form GX)
+//   V9 g_tv[k]:              -i wtau[J-k] GT^dagger sig_tv[J-k]
+constexpr int VJP_CLASSES = 10;
+constexpr int VJP_CHUNK = 64;  // output blocks per adjoint task
+constexpr int VJP_R = 2;       // blocks per thread per step of the adjoint (loads in flight)
+enum VjpForm { F_GXH, F_GX, F_XHG, F_GHX, F_ZERO };
+
+__host__ __device__ inline void vjp_range(const kbe_batch_item &r, int k, int &lo, int &hi) {
+  switch (k) {
+    case 0: case 2: case 4: case 6: lo = 0; hi = r.m + 1; break;
+    case 1: case 3: case 5: lo = r.m + 1; hi = r.n + 1; break;
+    case 7: lo = 0; hi = 1; break;
+    default: lo = 0; hi = r.ntau; break;
+  }
+}
+
+__host__ __device__ inline void vjp_chunks(const kbe_batch_item &r, int c[VJP_CLASSES]) {
+  for (int k = 0; k < VJP_CLASSES; ++k) {
+    int lo, hi;
+    vjp_range(r, k, lo, hi);
+    c[k] = (hi - lo + VJP_CHUNK - 1) / VJP_CHUNK;
   }
 }
 
@@ -332,15 +383,38 @@ __device__ __forceinline__ int64_t block_scan(int64_t v, int64_t *ws, int64_t *t
   return v;
 }
 
-__global__ void __launch_bounds__(1024) batch_plan(const kbe_batch_item *items, int count,
-                                                   int chunk, int *perm, int64_t *tb,
-                                                   int64_t *pb, unsigned int *head) {
+// Per-item task and partial counts of the forward (partials: one N x N block per task) and of
+// the adjoint (tasks of VJP_CHUNK output blocks, no partials).
+__device__ inline const kbe_batch_item &row_of(const kbe_batch_item &x) { return x; }
+__device__ inline const kbe_batch_item &row_of(const kbe_batch_vjp_item &x) { return x.row; }
+__device__ inline int64_t plan_tasks(const kbe_batch_item &it, int chunk) {
+  int c[4];
+  item_chunks(it, chunk, c);
+  return c[0] + c[1] + c[2] + c[3];
+}
+__device__ inline int64_t plan_parts(const kbe_batch_item &it, int chunk) {
+  return plan_tasks(it, chunk) * it.N * it.N;
+}
+__device__ inline int64_t plan_tasks(const kbe_batch_vjp_item &it, int) {
+  int c[VJP_CLASSES];
+  vjp_chunks(it.row, c);
+  int64_t t = 0;
+#pragma unroll
+  for (int k = 0; k < VJP_CLASSES; ++k) t += c[k];
+  return t;
+}
+__device__ inline int64_t plan_parts(const kbe_batch_vjp_item &, int) { return 0; }
+
+template <typename Item>
+__global__ void __launch_bounds__(1024) batch_plan(const Item *items, int count, int chunk,
+                                                   int *perm, int64_t *tb, int64_t *pb,
+                                                   unsigned int *head) {
   __shared__ int64_t wsum[16];
   __shared__ int nbin[KBE_NMAX + 1];
   const int tid = threadIdx.x;
   if (tid <= KBE_NMAX) nbin[tid] = 0;
   __syncthreads();
-  for (int i = tid; i < count; i += 1024) atomicAdd(&nbin[items[i].N], 1);  // integer counts
+  for (int i = tid; i < count; i += 1024) atomicAdd(&nbin[row_of(items[i]).N], 1);  // integer counts
   __syncthreads();
   // stable counting sort, N from KBE_NMAX down to 1 (empty bins skipped)
   int64_t placed = 0;
@@ -348,7 +422,7 @@ __global__ void __launch_bounds__(1024) batch_plan(const kbe_batch_item *items, 
     if (nbin[N] == 0) continue;  // uniform
     for (int base = 0; base < count; base += 1024) {
       const int i = base + tid;
-      const int64_t hit = i < count && items[i].N == N;
+      const int64_t hit = i < count && row_of(items[i]).N == N;
       int64_t tot;
       const int64_t r = block_scan(hit, wsum, &tot);
       if (hit) perm[placed + r - 1] = i;
@@ -362,11 +436,8 @@ __global__ void __launch_bounds__(1024) batch_plan(const kbe_batch_item *items, 
     const int j = base + tid;
     int64_t nt = 0, np = 0;
     if (j < count) {
-      int c[4];
-      item_chunks(items[perm[j]], chunk, c);
-      nt = c[0] + c[1] + c[2] + c[3];
-      item_chunks(items[j], chunk, c);
-      np = (int64_t)(c[0] + c[1] + c[2] + c[3]) * items[j].N * items[j].N;
+      nt = plan_tasks(items[perm[j]], chunk);
+      np = plan_parts(items[j], chunk);
     }
     int64_t tt, tp;
     const int64_t st = block_scan(nt, wsum, &tt);
@@ -464,6 +535,181 @@ __global__ void __launch_bounds__(256) batch_reduce(const kbe_batch_item *items,
   if (it.flags & KBE_OUT_ITV) stg(it.Itv + e, sum(ilb, itb));
 }
 
+// Adjoint: persistent workgroups take tasks (item, class, up to VJP_CHUNK output blocks) from one
+// counter.  Blocks of one class go through in steps of VJP_R * 256 / EP blocks (EP = N^2 rounded
+// up to a power of two); thread (block b, element e = i N + j) computes element (i, j) of its
+// VJP_R output blocks from the cotangent's row or column (in registers for the whole task) and
+// the streamed blocks X (staged in LDS, double-buffered, the next step's elements loaded ahead).
+__global__ void __launch_bounds__(256) batch_vjp_stream(const kbe_batch_vjp_item *items,
+                                                        int count, const int *perm,
+                                                        const int64_t *tb, unsigned int *head) {
+  __shared__ int64_t tbs[TB_LDS];
+  __shared__ cd xs[2][VJP_R * 256];
+  __shared__ int64_t task_s;
+  const int tid = threadIdx.x;
+  const bool cached = count < TB_LDS;
+  if (cached)
+    for (int j = tid; j <= count; j += blockDim.x) tbs[j] = tb[j];
+  __syncthreads();
+  const int64_t ntask = tb[count];
+  for (;;) {
+    if (tid == 0) task_s = (int64_t)atomicAdd(head, 1u);
+    __syncthreads();
+    // (read through LDS; made wave-uniform explicitly so that everything derived from the task
+    // stays in scalar registers and branches on it are uniform)
+    const int64_t task = (int64_t)(unsigned)__builtin_amdgcn_readfirstlane((unsigned)task_s);
+    __syncthreads();  // task_s is rewritten for the next task; the tiles are free again
+    if (task >= ntask) break;  // uniform
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if ((cached ? tbs[mid] : tb[mid]) <= task) lo = mid;
+      else hi = mid - 1;
+    }
+    lo = __builtin_amdgcn_readfirstlane(lo);
+    const int i_item = __builtin_amdgcn_readfirstlane(perm[lo]);
+    const kbe_batch_vjp_item it = uniform_copy(items + i_item);
+    const kbe_batch_item &r = it.row;
+    int c[VJP_CLASSES];
+    vjp_chunks(r, c);
+    int local = __builtin_amdgcn_readfirstlane((int)(task - (cached ? tbs[lo] : tb[lo]))), k = 0;
+    while (local >= c[k]) local -= c[k++];
+    int b0, b1;
+    vjp_range(r, k, b0, b1);
+    b0 += local * VJP_CHUNK;
+    b1 = b0 + VJP_CHUNK < b1 ? b0 + VJP_CHUNK : b1;
+    const int N = r.N, E = N * N, J = r.ntau - 1;
+    const int EP = E <= 1 ? 1 : E <= 4 ? 4 : E <= 16 ? 16 : E <= 32 ? 32 : E <= 64 ? 64 : E <= 128 ? 128 : 256;
+    const int bps = 256 / EP, sub = tid / EP, e = tid % EP, ei = e / N, ej = e % N;
+    const bool valid = e < E;
+    // the class's product, cotangent and output array
+    const bool ir = r.flags & KBE_OUT_IR, il = r.flags & KBE_OUT_IL;
+    const bool itv = (r.flags & KBE_OUT_ITV) && r.ntau > 0;
+    int form = F_ZERO;
+    const kbe_c128 *Gc = nullptr;
+    kbe_c128 *out = nullptr;
+    switch (k) {
+      case 0: form = ir ? F_GXH : F_ZERO; Gc = it.gIR; out = it.g_sig_ret; break;
+      case 1: form = ir ? F_GX : F_ZERO; Gc = it.gIR; out = it.g_sig_ret; break;
+      case 2: form = il ? F_GX : F_ZERO; Gc = it.gIL; out = it.g_sig_les; break;
+      case 3: form = F_ZERO; out = it.g_sig_les; break;
+      case 4: form = ir ? F_XHG : F_ZERO; Gc = it.gIR; out = it.g_col; break;
+      case 5: form = ir ? F_GHX : F_ZERO; Gc = it.gIR; out = it.g_row; break;
+      case 6: form = il ? F_GHX : F_ZERO; Gc = it.gIL; out = it.g_row; break;
+      case 7: form = il ? F_GHX : F_ZERO; Gc = it.gIL; out = it.g_rdiag; break;
+      case 8: form = itv ? F_GX : F_ZERO; Gc = it.gItv; out = it.g_sig_tv; break;
+      default: form = itv ? F_GHX : F_ZERO; Gc = it.gItv; out = it.g_tv; break;
+    }
+    // the cotangent's row ei (G X, G X^dagger), column ej (X^dagger G) or conjugated column ei
+    // (G^dagger X) of this thread's element
+    cd g[16];
+    {
+      // loads at clamped, always valid addresses (the output array stands in for an absent
+      // cotangent), the unwanted values selected away: no divergent branches
+      const kbe_c128 *gp = form == F_ZERO ? out : Gc;
+      const int ec = valid ? e : 0, ci = ec / N, cj_ = ec % N;
+#pragma unroll
+      for (int l = 0; l < 16; ++l) {
+        const int lc = l < N ? l : 0;
+        const int gi = form == F_XHG ? lc * N + cj_ : form == F_GHX ? lc * N + ci : ci * N + lc;
+        cd v = ldg(gp + gi);
+        if (form == F_GHX) v = cj(v);  // uniform
+        g[l] = (form != F_ZERO && valid && l < N) ? v : czero();
+      }
+    }
+    // streamed block of output block s, and its scalar
+    auto xblk = [&](int s) -> const kbe_c128 * {
+      switch (k) {
+        case 0: return r.col + (int64_t)s * E;
+        case 1: return r.row + (int64_t)s * E;
+        case 2: return s < r.m ? r.row + (int64_t)s * E : r.rdiag;
+        case 4: case 5: return r.sig_ret + (int64_t)s * E;
+        case 6: return r.sig_les + (int64_t)s * E;
+        case 7: return r.sig_les + (int64_t)r.m * E;
+        case 8: return r.tv + (int64_t)(J - s) * E;
+        default: return r.sig_tv + (int64_t)(J - s) * E;
+      }
+    };
+    auto scal = [&](int s) -> cd {
+      switch (k) {
+        case 0: case 4: return cd{ldgd(r.wn + s), 0.0};
+        case 1: case 5: return cd{-ldgd(r.wn + s), 0.0};
+        case 2: case 6: return cd{ldgd(r.wm + s), 0.0};
+        case 7: return cd{ldgd(r.wm + r.m), 0.0};
+        case 8: return cd{0.0, ldgd(r.wtau + s)};
+        default: return cd{0.0, -ldgd(r.wtau + (J - s))};
+      }
+    };
+    // steps of VJP_R * bps blocks: thread handles block sub + bps r, r = 0..VJP_R-1, of a step
+    const int per = VJP_R * bps;
+    const int nstep = (b1 - b0 + per - 1) / per;
+    // the step's elements and scalars, loaded a step ahead of their use
+    auto fetch = [&](int q, cd (&x)[VJP_R], cd (&sc)[VJP_R]) {
+#pragma unroll
+      for (int rr = 0; rr < VJP_R; ++rr) {
+        const int s = b0 + q * per + rr * bps + sub;
+        const bool on = form != F_ZERO && valid && q < nstep && s < b1 && !(k == 6 && s == r.m);
+        if (form == F_ZERO) {  // uniform: nothing is read
+          x[rr] = sc[rr] = czero();
+          continue;
+        }
+        const int sv = s < b1 ? s : b1 - 1;  // a block of the class: always readable
+        const cd xv = ldg(xblk(sv) + (valid ? e : 0));
+        const cd cv = scal(sv);
+        x[rr] = on ? xv : czero();
+        sc[rr] = on ? cv : czero();
+      }
+    };
+    cd xn[VJP_R], cn[VJP_R];
+    fetch(0, xn, cn);
+    for (int q = 0; q < nstep; ++q) {
+      cd xc[VJP_R], cc[VJP_R];
+#pragma unroll
+      for (int rr = 0; rr < VJP_R; ++rr) {
+        xc[rr] = xn[rr];
+        cc[rr] = cn[rr];
+      }
+      fetch(q + 1, xn, cn);
+      cd *tile = xs[q & 1];
+      // Staging makes every form one loop, acc = sum_l g[l] tile[l N + col]:
+      //   G X         : X at (l, j)                    col = j
+      //   G^dagger X  : X at (l, j)                    col = j
+      //   G X^dagger  : conj(X) transposed, (l, j) <- conj X[j][l]     col = j
+      //   X^dagger G  : conj(X) at (l, i)              col = i
+      const bool conj_x = form == F_GXH || form == F_XHG;
+      const int slot = sub * EP + (form == F_GXH ? ej * N + ei : e);
+      if (form != F_ZERO)
+#pragma unroll
+        for (int rr = 0; rr < VJP_R; ++rr) {
+          const cd v = conj_x ? cj(xc[rr]) : xc[rr];
+          tile[rr * 256 + (valid ? slot : tid)] = v;
+        }
+      lds_barrier();
+      const int col = form == F_XHG ? ei : ej;
+#pragma unroll
+      for (int rr = 0; rr < VJP_R; ++rr) {
+        const cd *t = tile + rr * 256 + sub * EP + col;
+        cd acc = czero();
+        if (form != F_ZERO) {
+#pragma unroll
+          for (int l = 0; l < 16; ++l) {
+            if (l < N) {  // uniform
+              const cd x = t[l * N];
+              acc.re = __builtin_fma(g[l].re, x.re, acc.re);
+              acc.re = __builtin_fma(-g[l].im, x.im, acc.re);
+              acc.im = __builtin_fma(g[l].re, x.im, acc.im);
+              acc.im = __builtin_fma(g[l].im, x.re, acc.im);
+            }
+          }
+        }
+        acc = cc[rr] * acc;  // cc is 0 where the block is zero (unselected, or g_row[m])
+        const int s = b0 + q * per + rr * bps + sub;
+        if (valid && s < b1) stg(out + (int64_t)s * E + e, acc);
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------------------
@@ -514,7 +760,7 @@ hipError_t launch_batch(const kbe_batch_item *items, const kbe_batch_item *items
     item_chunks(items[i], chunk, c);
     ntask += c[0] + c[1] + c[2] + c[3];
   }
-  hipLaunchKernelGGL(batch_plan, dim3(1), dim3(1024), 0, st, items_dev, count, chunk, perm, tb,
+  hipLaunchKernelGGL(batch_plan<kbe_batch_item>, dim3(1), dim3(1024), 0, st, items_dev, count, chunk, perm, tb,
                      pb, head);
   if (ntask > 0) {
     int64_t grid = batch_grid();
@@ -525,6 +771,44 @@ hipError_t launch_batch(const kbe_batch_item *items, const kbe_batch_item *items
   }
   hipLaunchKernelGGL(batch_reduce, dim3((unsigned)count), dim3(256), 0, st, items_dev, chunk, pb,
                      parts);
+  return hipGetLastError();
+}
+
+size_t batch_vjp_ws_bytes(int count) {
+  return 2 * al256b(sizeof(int64_t) * (size_t)(count + 1)) + al256b(sizeof(int) * (size_t)count) +
+         256;
+}
+
+static int batch_vjp_grid() {
+  static int cached[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 1024;
+  int &c = cached[dev];
+  if (c == 0) {
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_vjp_stream, 256, 0) !=
+            hipSuccess ||
+        per_cu < 1)
+      per_cu = 1;
+    c = cus * per_cu;
+  }
+  return c;
+}
+
+hipError_t launch_batch_vjp(const kbe_batch_vjp_item *items_dev, int count, void *ws,
+                            hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  char *w = (char *)ws;
+  const size_t tsz = al256b(sizeof(int64_t) * (size_t)(count + 1));
+  int64_t *tb = (int64_t *)w;
+  int64_t *pb = (int64_t *)(w + tsz);
+  int *perm = (int *)(w + 2 * tsz);
+  unsigned int *head = (unsigned int *)(w + 2 * tsz + al256b(sizeof(int) * (size_t)count));
+  hipLaunchKernelGGL(batch_plan<kbe_batch_vjp_item>, dim3(1), dim3(1024), 0, st, items_dev, count,
+                     VJP_CHUNK, perm, tb, pb, head);
+  hipLaunchKernelGGL(batch_vjp_stream, dim3((unsigned)batch_vjp_grid()), dim3(256), 0, st,
+                     items_dev, count, perm, tb, head);
   return hipGetLastError();
 }
 

@@ -374,6 +374,58 @@ int floor_log2(int64_t x) {
 
 extern "C" {
 
+static kbe_status check_batch_vjp(const kbe_batch_vjp_item *items,
+                                  const kbe_batch_vjp_item *items_dev, int32_t count) {
+  if (count < 0 || count > KBE_BATCH_MAX)
+    return fail(KBE_ERANGE, "count = %d outside [0, %d]", count, KBE_BATCH_MAX);
+  if (count == 0) return ok();
+  if (!items || !items_dev) return fail(KBE_EINVAL, "items or items_dev is NULL");
+  const unsigned known = KBE_OUT_IR | KBE_OUT_IL | KBE_OUT_ITV;
+  for (int32_t i = 0; i < count; ++i) {
+    const kbe_batch_vjp_item &v = items[i];
+    const kbe_batch_item &it = v.row;
+    if (it.N < 1 || it.N > KBE_NMAX)
+      return fail(KBE_EINVAL, "item %d: N = %d outside 1..%d", i, it.N, KBE_NMAX);
+    if (it.flags & ~known) return fail(KBE_EINVAL, "item %d: unknown flag bits 0x%x", i, it.flags);
+    if (it.n < 0 || it.m < 0 || it.m > it.n)
+      return fail(KBE_ERANGE, "item %d: (n, m) = (%d, %d) needs 0 <= m <= n", i, it.n, it.m);
+    if (it.ntau < 0 || it.ntau == 1)
+      return fail(KBE_EINVAL, "item %d: ntau = %d (must be 0 or >= 2)", i, it.ntau);
+    if (!v.g_sig_ret || !v.g_sig_les || !v.g_col || !v.g_row || !v.g_rdiag ||
+        (it.ntau > 0 && (!v.g_sig_tv || !v.g_tv)))
+      return fail(KBE_EINVAL, "item %d: a gradient array is NULL", i);
+    if (it.flags & KBE_OUT_IR) {
+      if (!v.gIR || !it.sig_ret || !it.col || !it.wn || (it.n > it.m && !it.row))
+        return fail(KBE_EINVAL, "item %d: I^R needs gIR, sig_ret, col, wn (and row when n > m)", i);
+    }
+    if (it.flags & KBE_OUT_IL) {
+      if (!v.gIL || !it.sig_les || !it.rdiag || !it.wm || (it.m > 0 && !it.row))
+        return fail(KBE_EINVAL, "item %d: I^< needs gIL, sig_les, rdiag, wm (and row when m > 0)", i);
+    }
+    if ((it.flags & KBE_OUT_ITV) && it.ntau > 0) {
+      if (!v.gItv || !it.sig_tv || !it.tv || !it.wtau)
+        return fail(KBE_EINVAL, "item %d: I^] needs gItv, sig_tv, tv, wtau with ntau > 0", i);
+    }
+  }
+  return ok();
+}
+
+size_t kbe_collision_batch_vjp_workspace(int32_t count) {
+  if (count < 0 || count > KBE_BATCH_MAX) return 0;
+  return kbe::batch_vjp_ws_bytes(count);
+}
+
+kbe_status kbe_collision_batch_vjp(const kbe_batch_vjp_item *items,
+                                   const kbe_batch_vjp_item *items_dev, int32_t count, void *ws,
+                                   size_t ws_bytes, void *stream) {
+  kbe_status s = check_batch_vjp(items, items_dev, count);
+  if (s != KBE_OK || count == 0) return s;
+  const size_t need = kbe::batch_vjp_ws_bytes(count);
+  if (!ws || ws_bytes < need) return fail(KBE_ENOMEM, "workspace %zu bytes < %zu", ws_bytes, need);
+  return hip_status(kbe::launch_batch_vjp(items_dev, count, ws, (hipStream_t)stream),
+                    "kbe_collision_batch_vjp");
+}
+
 kbe_status kbe_collision_batch_tune(const kbe_batch_item *items, const kbe_batch_item *items_dev,
                                     int32_t count, void *ws, size_t ws_bytes, void *stream,
                                     int32_t *best_chunk, float *times_ms) {

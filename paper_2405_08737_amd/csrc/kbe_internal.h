@@ -40,5 +40,8 @@ int batch_default_chunk();
 size_t batch_ws_bytes(const kbe_batch_item *items, int count, int chunk);
 hipError_t launch_batch(const kbe_batch_item *items, const kbe_batch_item *items_dev, int count,
                         int chunk, void *ws, hipStream_t st);
+size_t batch_vjp_ws_bytes(int count);
+hipError_t launch_batch_vjp(const kbe_batch_vjp_item *items_dev, int count, void *ws,
+                            hipStream_t st);
 
 }  // namespace kbe

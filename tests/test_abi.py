@@ -270,3 +270,39 @@ def test_batch_tile_table_keys_and_tuner_errors(tmp_path):
     assert L.kbe_collision_batch_tune_groups(arr, FAKE, 1, FAKE, 1 << 40, None, None) == 1
     arr = (kbe._BatchItem * 1)(batch_item())
     assert L.kbe_collision_batch_tune_groups(arr, FAKE, 1, FAKE, 16, None, None) == 3
+
+
+def test_batch_vjp_argument_errors_and_workspace():
+    EINVAL, ERANGE, ENOMEM = 1, 2, 3
+    L = kbe.lib()
+    tables = lambda c: 2 * ((8 * (c + 1) + 255) // 256 * 256) + (4 * c + 255) // 256 * 256 + 256
+    assert L.kbe_collision_batch_vjp_workspace(3) == tables(3)
+    assert L.kbe_collision_batch_vjp_workspace(-1) == 0
+
+    def item(**kw):
+        v = kbe._BatchVjpItem(batch_item(**kw), *([FAKE] * 10))
+        return v
+
+    def call(items, count=None, ws_bytes=1 << 40):
+        arr = (kbe._BatchVjpItem * max(len(items), 1))(*items)
+        count = len(items) if count is None else count
+        return L.kbe_collision_batch_vjp(arr, FAKE, count, FAKE, ws_bytes, None)
+
+    assert call([]) == 0
+    assert call([item(N=0)]) == EINVAL
+    assert call([item(n=3, m=4)]) == ERANGE
+    assert call([item(flags=0x8)]) == EINVAL
+    assert call([item()], count=65537) == ERANGE
+    v = item()
+    v.gIR = None
+    assert call([v]) == EINVAL
+    v = item(flags=0x2)
+    v.gIR = None  # not needed without I^R
+    v.g_col = None  # every gradient array is written
+    assert call([v]) == EINVAL
+    v = item(ntau=0, flags=0x3)
+    v.g_tv = None
+    v.g_sig_tv = None
+    v.row.sig_tv = None
+    assert call([v], ws_bytes=16) == ENOMEM
+    assert L.kbe_collision_batch_vjp(None, FAKE, 1, FAKE, 1 << 40, None) == EINVAL
