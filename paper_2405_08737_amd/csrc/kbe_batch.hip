@@ -487,7 +487,9 @@ __global__ void __launch_bounds__(256) batch_stream(const kbe_batch_item *items,
     const kbe_batch_item it = items[i];
     int c[4];
     item_chunks(it, chunk, c);
-    const int64_t ltask = task - (cached ? tbs[j] : tb[j]);
+    // (an LDS read: made wave-uniform explicitly, so that the task's ranges and loops are)
+    const int64_t ltask =
+        (int64_t)__builtin_amdgcn_readfirstlane((int)(task - (cached ? tbs[j] : tb[j])));
     int local = (int)ltask, k = 0;
     while (local >= c[k]) local -= c[k++];
     int t0, t1;
