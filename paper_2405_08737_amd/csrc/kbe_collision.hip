@@ -896,9 +896,9 @@ __global__ void __launch_bounds__(256) grad_generic(Params p, int64_t nblk) {
 // four per-row blocks -- Sigma^R(a), gIR(a), gIL(a), gItv(a) -- which are staged once in LDS;
 // the scalar is folded into the streamed Y.  The terms of the segment's blocks (operands,
 // scalars, destination) are resolved once into LDS records.  Each wave walks every fourth block
-// of the segment with the next block's Y prefetched, keeps one accumulator pair per term (so no
-// update depends on the other term's) and uses v_mfma_f64_4x4x4 as in the collision tasks
-// (A = X^dag read from LDS, B = Y slabs), three real products per complex one.
+// of the segment with the next block's Y prefetched and multiplies on v_mfma_f64_16x16x4
+// (A = X^dag, one element per lane per k-chunk read from LDS; B = Y slabs straight from the
+// cache), three real products per complex one, both terms into the same accumulators.
 constexpr int GSEG = 64;  // blocks per workgroup segment
 
 struct GradTerm {
@@ -959,12 +959,17 @@ __device__ __forceinline__ const kbe_c128 *uniform_ptr(const kbe_c128 *q) {
   return (const kbe_c128 *)(((uint64_t)hi << 32) | lo);
 }
 
+typedef double __attribute__((ext_vector_type(4))) d4g;
+__device__ __forceinline__ d4g mfma16f(double a, double b, d4g c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 grad_mfma16(Params p, int row_len, int nseg) {
   __shared__ cd xs[4][16 * QLD];
   __shared__ GradRec rec[GSEG];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int lr = lane & 3, lk = lane >> 4, lc = lane & 15;
+  const int lk = lane >> 4, lc = lane & 15;
   // Workgroups are dealt round-robin to the 8 XCDs; XCD x walks the segment-major range
   // [x per_xcd, (x+1) per_xcd) of (segment, row) pairs, so the column operands (Y) its L2 holds
   // belong to about one segment at a time.  The results bypass the caches (streaming stores) so
@@ -1015,9 +1020,9 @@ grad_mfma16(Params p, int row_len, int nseg) {
   // the next block, so each wave's stores spread over its products instead of a burst.
   cd prev[4];
   kbe_c128 *pdst = nullptr;
-  auto put = [&](int ti) {
-    kbe_c128 *d = pdst + (4 * ti + lk) * 16 + lc;
-    cd v = prev[ti];
+  auto put = [&](int r) {  // rows l/16 + 4 r of the held result
+    kbe_c128 *d = pdst + (lk + 4 * r) * 16 + lc;
+    cd v = prev[r];
     if (!p.overwrite) v = v + ldg(d);
     dvec2 w;
     w.x = v.re;
@@ -1044,7 +1049,9 @@ grad_mfma16(Params p, int row_len, int nseg) {
     // Three real products per complex one (Gauss): with A = conj(X), for each k-chunk
     //   K1 += (xr - xi) yr,   K2 += xr (yi - yr),   K3 += xi (yr + yi);
     // then Re = K1 + K3 and Im = K1 + K2.  Both terms of the block share the accumulators.
-    double k1[4] = {0, 0, 0, 0}, k2[4] = {0, 0, 0, 0}, k3[4] = {0, 0, 0, 0};
+    // v_mfma_f64_16x16x4: lane l supplies A[l%16][4 kc + l/16] = conj(X[4 kc + l/16][l%16]) and
+    // B[4 kc + l/16][l%16] = c Y[..], and holds D[l/16 + 4 r][l%16].
+    d4g k1 = {0, 0, 0, 0}, k2 = {0, 0, 0, 0}, k3 = {0, 0, 0, 0};
 #pragma unroll
     for (int kc = 0; kc < 4; ++kc) {
 #pragma unroll
@@ -1052,34 +1059,24 @@ grad_mfma16(Params p, int row_len, int nseg) {
         if (term == 1 && cnt < 2) break;  // wave-uniform
         const cd *x = term == 0 ? x0 : x1;
         const cd y = term == 0 ? y0[kc] : y1[kc];
-        double xr[4], xi[4], xd[4];
-#pragma unroll
-        for (int ti = 0; ti < 4; ++ti) {  // A = X^dag: A[i][k] = conj(X[k][i])
-          const cd u = x[(4 * kc + lk) * QLD + 4 * ti + lr];
-          xr[ti] = u.re;
-          xi[ti] = u.im;
-          xd[ti] = u.re - u.im;
-        }
+        const cd u = x[(4 * kc + lk) * QLD + lc];
         const double ys = y.im - y.re, yp = y.re + y.im;
         __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int ti = 0; ti < 4; ++ti) k1[ti] = mfma4(xd[ti], y.re, k1[ti]);
-#pragma unroll
-        for (int ti = 0; ti < 4; ++ti) k2[ti] = mfma4(xr[ti], ys, k2[ti]);
-#pragma unroll
-        for (int ti = 0; ti < 4; ++ti) k3[ti] = mfma4(xi[ti], yp, k3[ti]);
+        k1 = mfma16f(u.re - u.im, y.re, k1);
+        k2 = mfma16f(u.re, ys, k2);
+        k3 = mfma16f(u.im, yp, k3);
         __builtin_amdgcn_sched_barrier(0);
       }
       if (pdst) put(kc);
       __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
-    for (int ti = 0; ti < 4; ++ti) prev[ti] = cd{k1[ti] + k3[ti], k1[ti] + k2[ti]};
+    for (int r = 0; r < 4; ++r) prev[r] = cd{k1[r] + k3[r], k1[r] + k2[r]};
     pdst = cdst;
   }
   if (pdst) {
 #pragma unroll
-    for (int ti = 0; ti < 4; ++ti) put(ti);
+    for (int r = 0; r < 4; ++r) put(r);
   }
 }
 
