@@ -181,6 +181,23 @@ kbe_status kbe_sigma_2b(const kbe_green *G, const double *u, int32_t n, const kb
                         void *stream);
 
 /* ---------------------------------------------------------------------------
+ * kbe_sigma_2b_full — the second-Born self-energy of kbe_sigma_2b (local U,
+ * Eq. SE) for every time pair, in the KP storage of G ("full mode", for tests
+ * and for callers that want the whole Sigma rather than one row):
+ *   S->kp[a][b] = Sigma^<(t_a,t_b) (a <= b),  Sigma^>(t_a,t_b) - Sigma^<(t_a,t_b) (a > b)
+ *   S->rdiag[a] = Sigma^>(t_a,t_a) - Sigma^<(t_a,t_a)   (the one-sided Sigma^R(t,t))
+ *   S->tv[a][l] = Sigma^](t_a,tau_l)
+ * for a, b < G->nt; every value from the formula at its own arguments (no
+ * symmetry of Sigma is assumed).  S->mat is not written (Eq. SE gives no
+ * Matsubara component).
+ *
+ * Arguments: G and S device arrays with the same N, nt and ntau (S->ldt >= nt
+ * may differ from G's); u device [N].  Errors: KBE_EINVAL (NULL, shapes).
+ * ------------------------------------------------------------------------- */
+kbe_status kbe_sigma_2b_full(const kbe_green *G, const double *u, const kbe_green *S,
+                             void *stream);
+
+/* ---------------------------------------------------------------------------
  * kbe_sigma_gf2 — second-Born self-energy row at t_n with a general
  * four-index interaction (Eq. SE):
  *   Sigma^<>_ij(t,t') = sum U_ifde Uex_jabc G^<>_fb(t,t') G^<>_ea(t,t') G^><_cd(t',t)

@@ -341,3 +341,27 @@ def collision_row_vjp(N: int, ntau: int, n: int, m: int, sig, col, row, rdg, tvm
             g_stv[j] = np.conj(c) * gItv @ tvm[J - j]
             g_tv[J - j] = c * H(gItv) @ stv[j]
     return g_ret, g_les, g_stv, g_col, g_row, g_rdg, g_tv
+
+
+def sigma_full(G: Green, u):
+    """Second-Born self-energy (local U) for every time pair, in KP storage like G:
+    kp[a][b] = Sigma^<(t_a,t_b) for a <= b and Sigma^R(t_a,t_b) = Sigma^> - Sigma^< for a > b,
+    rdiag[a] = Sigma^>(t_a,t_a) - Sigma^<(t_a,t_a), tv[a][l] = Sigma^](t_a,tau_l) (each entry from
+    sigma_pair / sigma_row at its own arguments).  The Matsubara component is not produced (Eq. SE
+    gives none)."""
+    nt, N, ntau = G.nt, G.N, G.ntau
+    kp = np.zeros((nt, nt, N, N), np.complex128)
+    rd = np.zeros((nt, N, N), np.complex128)
+    tv = np.zeros((nt, ntau, N, N), np.complex128)
+    for a in range(nt):
+        for b in range(nt):
+            les, gtr = sigma_pair(G, u, a, b)
+            if a <= b:
+                kp[a, b] = les
+            else:
+                kp[a, b] = gtr - les
+            if a == b:
+                rd[a] = gtr - les
+        if ntau:
+            tv[a] = sigma_row(G, u, a)[2]
+    return kp, rd, tv

@@ -68,7 +68,8 @@ class _BatchVjpItem(ctypes.Structure):
 
 EXPORTS = ("kbe_weights_workspace", "kbe_weights", "kbe_sigma_2b", "kbe_collision_workspace",
            "kbe_collision", "kbe_collision_vjp_workspace", "kbe_collision_vjp",
-           "kbe_sigma_2b_vjp_workspace", "kbe_sigma_2b_vjp", "kbe_sigma_gf2_workspace",
+           "kbe_sigma_2b_vjp_workspace", "kbe_sigma_2b_vjp", "kbe_sigma_2b_full",
+           "kbe_sigma_gf2_workspace",
            "kbe_sigma_gf2", "kbe_collision_batch_workspace",
            "kbe_collision_batch", "kbe_collision_batch_tune", "kbe_collision_batch_tune_groups",
            "kbe_collision_batch_vjp_workspace", "kbe_collision_batch_vjp",
@@ -91,6 +92,7 @@ def lib():
             "kbe_weights_workspace": (SZ, [GR]),
             "kbe_weights": (I32, [GR, P, P, P, P, SZ, P]),
             "kbe_sigma_2b": (I32, [G, P, I32, R, P]),
+            "kbe_sigma_2b_full": (I32, [G, P, G, P]),
             "kbe_sigma_gf2_workspace": (SZ, [I32]),
             "kbe_sigma_gf2": (I32, [G, P, I32, R, P, SZ, P]),
             "kbe_collision_workspace": (SZ, [I32, I32, I32, I32, I32, I32, U32]),
@@ -213,6 +215,16 @@ def sigma_2b(G: Green, u: torch.Tensor, n: int):
     _check(lib().kbe_sigma_2b(ctypes.byref(G.c()), _ptr(u), n, ctypes.byref(row), _stream(dev)),
            "kbe_sigma_2b")
     return ret, les, stv
+
+
+def sigma_2b_full(G: Green, u: torch.Tensor, S: Optional[Green] = None):
+    """kbe_sigma_2b_full: Sigma for every time pair in KP storage (a Green with G's shapes;
+    its mat is left as allocated)."""
+    if S is None:
+        S = G.zeros_like()
+    _check(lib().kbe_sigma_2b_full(ctypes.byref(G.c()), _ptr(u), ctypes.byref(S.c()),
+                                   _stream(G.device)), "kbe_sigma_2b_full")
+    return S
 
 
 def sigma_gf2(G: Green, U: torch.Tensor, n: int):

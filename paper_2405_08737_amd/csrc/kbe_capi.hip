@@ -166,6 +166,19 @@ kbe_status kbe_sigma_2b(const kbe_green *G, const double *u, int32_t n, const kb
   return hip_status(kbe::launch_sigma_row(G, u, n, out, (hipStream_t)stream), "kbe_sigma_2b");
 }
 
+kbe_status kbe_sigma_2b_full(const kbe_green *G, const double *u, const kbe_green *S,
+                             void *stream) {
+  kbe_status s = check_green(G, "G");
+  if (s != KBE_OK) return s;
+  if (!u) return fail(KBE_EINVAL, "u is NULL");
+  if (!S || !S->kp || !S->rdiag) return fail(KBE_EINVAL, "S, S->kp or S->rdiag is NULL");
+  if (S->N != G->N || S->nt != G->nt || S->ntau != G->ntau || S->ldt < S->nt)
+    return fail(KBE_EINVAL, "S shape (N %d, nt %d, ntau %d, ldt %lld) does not match G", S->N,
+                S->nt, S->ntau, (long long)S->ldt);
+  if (G->ntau > 0 && !S->tv) return fail(KBE_EINVAL, "S->tv is NULL with ntau > 0");
+  return hip_status(kbe::launch_sigma_full(G, u, S, (hipStream_t)stream), "kbe_sigma_2b_full");
+}
+
 size_t kbe_sigma_gf2_workspace(int32_t N) {
   if (N < 1 || N > KBE_NMAX) return 0;
   return kbe::gf2_ws_bytes(N);

@@ -17,6 +17,8 @@ hipError_t launch_weights(const kbe_grid *g, double *w, double *wtau, double *wf
 // Self-energy and its adjoint (kbe_sigma.hip).
 hipError_t launch_sigma_row(const kbe_green *G, const double *u, int n, const kbe_sigma_row *out,
                             hipStream_t st);
+hipError_t launch_sigma_full(const kbe_green *G, const double *u, const kbe_green *S,
+                             hipStream_t st);
 size_t sigma_vjp_ws_bytes(int N, int n, int ntau);
 hipError_t launch_sigma_row_vjp(const kbe_green *G, const double *u, int n,
                                 const kbe_sigma_row *gS, const kbe_green *gG, double *gu,

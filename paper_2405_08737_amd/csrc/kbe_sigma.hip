@@ -67,6 +67,77 @@ hipError_t launch_sigma_row(const kbe_green *G, const double *u, int n, const kb
 }
 
 // ---------------------------------------------------------------------------------------------
+// Full mode: Sigma for every time pair, in KP storage like G (Sigma^< on and above the diagonal,
+// Sigma^R = Sigma^> - Sigma^< below it, the one-sided Sigma^R(t,t) in rdiag, Sigma^] in tv).  One
+// thread per stored element; every value comes from the formula at its own arguments, with G
+// read through the storage symmetries:
+//   G^<(a,b) = kp[a][b] (a <= b), -kp[b][a]^dagger (a > b)
+//   G^>(a,b) = G^R(a,b) + G^<(a,b) (a >= b; G^R from kp[a][b], or rdiag[a] at a = b),
+//              -G^>(b,a)^dagger (a < b).
+// ---------------------------------------------------------------------------------------------
+struct FullArgs {
+  SigArgs a;
+  int nt;
+  int64_t sldt;
+  kbe_c128 *skp, *srd, *stv;
+};
+
+__device__ __forceinline__ cd g_les(const SigArgs &a, int x, int y, int i, int j) {
+  const int64_t E = (int64_t)a.N * a.N;
+  return x <= y ? ld(a.kp + ((int64_t)x * a.ldt + y) * E + i * a.N + j)
+                : -cj(ld(a.kp + ((int64_t)y * a.ldt + x) * E + j * a.N + i));
+}
+__device__ __forceinline__ cd g_gtr(const SigArgs &a, int x, int y, int i, int j) {
+  const int64_t E = (int64_t)a.N * a.N;
+  if (x < y) {
+    const cd r = ld(a.kp + ((int64_t)y * a.ldt + x) * E + j * a.N + i);  // G^R(y,x)_ji
+    return -cj(r + g_les(a, y, x, j, i));
+  }
+  const cd r = x == y ? ld(a.rdiag + (int64_t)x * E + i * a.N + j)
+                      : ld(a.kp + ((int64_t)x * a.ldt + y) * E + i * a.N + j);
+  return r + g_les(a, x, y, i, j);
+}
+
+__global__ void __launch_bounds__(256) sigma_full_kernel(FullArgs f) {
+  const SigArgs &a = f.a;
+  const int N = a.N;
+  const int64_t E = (int64_t)N * N;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nkp = (int64_t)f.nt * f.nt * E, nrd = (int64_t)f.nt * E;
+  if (idx < nkp + nrd) {
+    const bool diag = idx >= nkp;
+    const int64_t k = diag ? idx - nkp : idx;
+    const int x = diag ? (int)(k / E) : (int)(k / E / f.nt);
+    const int y = diag ? x : (int)(k / E % f.nt);
+    const int e = (int)(k % E), i = e / N, j = e % N;
+    const double U = a.u[i] * a.u[j];
+    const cd lxy = g_les(a, x, y, i, j), gxy = g_gtr(a, x, y, i, j);
+    const cd lyx = g_les(a, y, x, j, i), gyx = g_gtr(a, y, x, j, i);
+    const cd sl = U * (lxy * lxy * gyx), sg = U * (gxy * gxy * lyx);
+    if (diag) st(f.srd + (int64_t)x * E + e, sg - sl);
+    else st(f.skp + ((int64_t)x * f.sldt + y) * E + e, x <= y ? sl : sg - sl);
+  } else if (idx < nkp + nrd + (int64_t)f.nt * a.ntau * E) {
+    const int64_t k = idx - nkp - nrd;
+    const int x = (int)(k / E / a.ntau), l = (int)(k / E % a.ntau), e = (int)(k % E);
+    const int i = e / N, j = e % N;
+    const double U = a.u[i] * a.u[j];
+    const cd v = ld(a.tv + ((int64_t)x * a.ntau + l) * E + e);
+    const cd w = ld(a.tv + ((int64_t)x * a.ntau + (a.J - l)) * E + e);
+    st(f.stv + ((int64_t)x * a.ntau + l) * E + e, U * (v * v * cj(w)));
+  }
+}
+
+hipError_t launch_sigma_full(const kbe_green *G, const double *u, const kbe_green *S,
+                             hipStream_t st) {
+  FullArgs f{{G->N, G->ntau, G->ntau - 1, 0, G->ldt, G->kp, G->rdiag, G->tv, u}, G->nt, S->ldt,
+             S->kp, S->rdiag, S->tv};
+  const int64_t E = (int64_t)G->N * G->N;
+  const int64_t tot = ((int64_t)G->nt * G->nt + G->nt + (int64_t)G->nt * G->ntau) * E;
+  hipLaunchKernelGGL(sigma_full_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, f);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
 // Adjoint.  Complex gradients follow PyTorch's convention (dL/dRe + i dL/dIm); for W(z, conj z)
 // the gradient is  conj(gW) dW/dconj(z) + gW conj(dW/dz).  With G1 = gret and G2 = gles - gret
 // (Sigma^> enters ret with +, Sigma^< enters les with + and ret with -), for s < n:

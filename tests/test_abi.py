@@ -306,3 +306,17 @@ def test_batch_vjp_argument_errors_and_workspace():
     v.row.sig_tv = None
     assert call([v], ws_bytes=16) == ENOMEM
     assert L.kbe_collision_batch_vjp(None, FAKE, 1, FAKE, 1 << 40, None) == EINVAL
+
+
+def test_sigma_full_argument_errors():
+    L = kbe.lib()
+    G = green()
+    st = L.kbe_sigma_2b_full(ctypes.byref(G), None, ctypes.byref(green()), None)
+    assert st == 1 and "u" in err()
+    st = L.kbe_sigma_2b_full(ctypes.byref(G), FAKE, ctypes.byref(green(N=3)), None)
+    assert st == 1 and "shape" in err()
+    st = L.kbe_sigma_2b_full(ctypes.byref(G), FAKE, ctypes.byref(green(ldt=5)), None)
+    assert st == 1
+    S = green()
+    S.rdiag = None
+    assert L.kbe_sigma_2b_full(ctypes.byref(G), FAKE, ctypes.byref(S), None) == 1

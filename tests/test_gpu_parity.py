@@ -271,3 +271,28 @@ def test_sigma_and_collision_graph_capture(gpu, N):
         torch.cuda.synchronize()
         for a, b in zip(out, eager):
             assert np.array_equal(to_host(a), b), rep
+
+
+@pytest.mark.parametrize("N,nt,ntau,sldt", [(1, 9, 5, 9), (3, 12, 0, 12), (8, 10, 6, 13),
+                                            (16, 7, 4, 7)])
+def test_sigma_full_mode_matches_oracle(gpu, N, nt, ntau, sldt):
+    """kbe_sigma_2b_full: every stored block of Sigma (KP triangle pair, rdiag, tv) against the
+    oracle, including a Sigma whose row stride exceeds G's."""
+    import torch
+    kbe = gpu
+    case = Case(N=N, nt=nt, ntau=ntau, beta=4.0, seed=700 + N)
+    t, order, kp, rd, tv, mat = case.host()
+    Gd = device_green(kp, rd, tv, mat)
+    u = np.linspace(0.6, 1.4, N)
+    dev = torch.device("cuda:0")
+    S = kbe.Green(torch.full((nt, sldt, N, N), float("nan"), dtype=torch.complex128, device=dev),
+                  torch.full((nt, N, N), float("nan"), dtype=torch.complex128, device=dev),
+                  torch.full((nt, ntau, N, N), float("nan"), dtype=torch.complex128, device=dev),
+                  torch.zeros((ntau, N, N), dtype=torch.complex128, device=dev))
+    kbe.sigma_2b_full(Gd, to_dev(u), S)
+    G = oracle.Green(kp, rd, tv if ntau else None, mat if ntau else None)
+    rkp, rrd, rtv = oracle.sigma_full(G, u)
+    got = to_host(S.kp)[:, :nt]
+    for name, g, r in (("kp", got, rkp), ("rdiag", to_host(S.rdiag), rrd), ("tv", to_host(S.tv), rtv)):
+        assert np.all(np.isfinite(g)), name
+        assert np.all(bnorm(g - r) <= 1e-13 * (bnorm(r) + 1e-300)), name

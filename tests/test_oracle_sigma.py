@@ -124,3 +124,24 @@ def test_hand_calculation_one_orbital():
     assert abs(les[0, 0] - complex(*e["sigma_les_10"])) < 1e-14
     assert abs(gtr[0, 0] - complex(*e["sigma_gtr_10"])) < 1e-14
     assert abs(ret[0, 0, 0] - complex(*e["sigma_ret_10"])) < 1e-14
+
+
+def test_full_mode_agrees_with_rows_and_symmetry():
+    """oracle.sigma_full against the pinned row function at every row (lower triangle, rdiag, tv)
+    and, above the diagonal, against the inherited symmetry Sigma^<(t,t') = -Sigma^<(t',t)^dagger
+    of the row values (which holds for inputs with G's symmetry)."""
+    rng = np.random.default_rng(21)
+    N, nt, ntau = 2, 6, 4
+    les, gtr = random_symmetric_full(rng, N, nt)
+    tv = rng.normal(size=(nt, ntau, N, N)) + 1j * rng.normal(size=(nt, ntau, N, N))
+    G = _green_from_full(les, gtr, tv)
+    u = np.array([0.8, 1.3])
+    kp, rd, stv = oracle.sigma_full(G, u)
+    for n in range(nt):
+        ret, les_row, tv_row = oracle.sigma_row(G, u, n)
+        for s in range(n):
+            np.testing.assert_array_equal(kp[n, s], ret[s])
+            np.testing.assert_allclose(kp[s, n], -les_row[s].conj().T, rtol=1e-13, atol=1e-13)
+        np.testing.assert_array_equal(kp[n, n], les_row[n])
+        np.testing.assert_array_equal(rd[n], ret[n])
+        np.testing.assert_array_equal(stv[n], tv_row)
