@@ -29,6 +29,7 @@ _lib = None
 
 F_IR, F_IL, F_ITV, F_JTV = 1, 2, 4, 8
 F_ALL = F_IR | F_IL | F_ITV | F_JTV
+F_GREATER = 1024  # the greater form of Eq. KBE2 (see orc_collision)
 
 
 def build() -> str:

@@ -322,7 +322,9 @@ static void mm_acc_hn(int N, cplx *out, cplx c, const cplx *A, const cplx *B) {
     }
 }
 
-enum { F_IR = 1, F_IL = 2, F_ITV = 4, F_JTV = 8 };
+/* F_GREATER: the greater form of Eq. KBE2, G^>(t_s,t_m) in I^R and Sigma^> = Sigma^R + Sigma^<
+ * (the same self-energy row) in I^<; I^] and J^] do not depend on the form. */
+enum { F_IR = 1, F_IL = 2, F_ITV = 4, F_JTV = 8, F_GREATER = 1024 };
 
 /* Index of the tau point beta - tau_j (the grid is symmetric). */
 static int tau_mirror(int ntau, int j) { return ntau - 1 - j; }
@@ -356,16 +358,23 @@ void orc_collision(int N, int nt, int ntau, int64_t ldt, const cplx *kp, const c
       cplx *o = IR + (m - m0) * bs;
       memset(o, 0, sizeof(cplx) * bs);
       for (int s = 0; s <= n; ++s) {
-        get_les(&g, s, m, blk);
+        if (flags & F_GREATER) get_gtr(&g, s, m, blk);
+        else get_les(&g, s, m, blk);
         mm_acc(N, o, w[(int64_t)n * nt + s], ret + s * bs, blk, 0);
       }
     }
     if (flags & F_IL) {
       cplx *o = IL + (m - m0) * bs;
+      cplx sg[256];
       memset(o, 0, sizeof(cplx) * bs);
       for (int s = 0; s <= m; ++s) {
         get_ret(&g, m, s, blk);
-        mm_acc(N, o, w[(int64_t)m * nt + s], les + s * bs, blk, 1);
+        const cplx *sx = les + s * bs;
+        if (flags & F_GREATER) { /* Sigma^>(t_n,t_s) = Sigma^R + Sigma^< for s <= n */
+          for (int e = 0; e < bs; ++e) sg[e] = ret[s * bs + e] + les[s * bs + e];
+          sx = sg;
+        }
+        mm_acc(N, o, w[(int64_t)m * nt + s], sx, blk, 1);
       }
     }
     if ((flags & F_ITV) && ntau > 0) {

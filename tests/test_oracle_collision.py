@@ -269,3 +269,36 @@ def test_row_from_cross_equals_full_system(N, nt, ntau):
                                  W.wfull if ntau else None, flags)
         for got, want in zip(r, (IR[0], IL[0], Itv[0])):
             assert np.abs(got - want).max() <= 1e-14 * (np.abs(want).max() + 1e-300)
+
+
+def test_greater_form_from_full_matrices():
+    """F_GREATER against direct sums over the full G^< and G^> matrices (no KP storage logic):
+    I^R(n, :) = [w_ns Sigma^R(n,s)]_s @ [G^>(s,m)]_{s,m} and
+    I^<(n,m) = sum_{s<=m} w_ms (Sigma^R + Sigma^<)(n,s) G^R(m,s)^dagger, G^R = G^> - G^< below and
+    on the diagonal; the tau outputs are the same in both forms."""
+    rng = np.random.default_rng(12)
+    N, nt, ntau = 2, 14, 6
+    les, gtr = random_symmetric_full(rng, N, nt)
+    kp = pack_kp(les, gtr - les)
+    rdiag = np.array([(gtr - les)[a, a] for a in range(nt)])
+    tv = rng.normal(size=(nt, ntau, N, N)) + 1j * rng.normal(size=(nt, ntau, N, N))
+    mat = rng.normal(size=(ntau, N, N)) + 1j * rng.normal(size=(ntau, N, N))
+    G = oracle.Green(kp, rdiag, tv, mat)
+    t, order = synth.grid(12, nt, 0.02, 0.08, 3, 6)
+    W = oracle.Weights.build(t, order, 3.0, ntau, 5)
+    n = nt - 2
+    cm = lambda *s: rng.normal(size=s) + 1j * rng.normal(size=s)
+    sig = (cm(n + 1, N, N), cm(n + 1, N, N), cm(ntau, N, N))
+    ret, sles, _ = sig
+    IRg, ILg, Itvg, Jg = oracle.collision(G, sig, W, n, flags=oracle.F_ALL | oracle.F_GREATER)
+    IRl, ILl, Itvl, Jl = oracle.collision(G, sig, W, n, flags=oracle.F_ALL)
+    left = np.concatenate([W.w[n, s] * ret[s] for s in range(n + 1)], axis=1)
+    big = np.block([[gtr[s, m] for m in range(n + 1)] for s in range(n + 1)])
+    ref = left @ big
+    for m in range(n + 1):
+        assert relerr(IRg[m], ref[:, m * N:(m + 1) * N]) < 1e-13
+        want = sum(W.w[m, s] * (ret[s] + sles[s]) @ (gtr[m, s] - les[m, s]).conj().T
+                   for s in range(m + 1))
+        assert relerr(ILg[m], want) < 1e-13
+    assert np.array_equal(Itvg, Itvl) and np.array_equal(Jg, Jl)
+    assert relerr(IRg[3], IRl[3]) > 1e-3  # the forms differ where G^R is nonzero
