@@ -93,6 +93,13 @@ typedef enum {
                                      kernels exist (N = 16); results agree to rounding */
 #define KBE_GRAD_OVERWRITE 0x200u /* VJP: overwrite the Green's-function gradient blocks the
                                      forward call reads instead of adding to them */
+#define KBE_GREATER 0x400u        /* kbe_collision: the greater form of Eq. KBE2 (the paper's
+                                     choice below the diagonal): I^R with G^>(t_s,t_m) in place
+                                     of G^<(t_s,t_m), assembled from both triangles, and I^< with
+                                     Sigma^> = Sigma^R + Sigma^< (from the same self-energy row)
+                                     in place of Sigma^<; I^] and J^] are the same in both forms.
+                                     Runs on the vector-ALU kernels.  kbe_collision_vjp and the
+                                     batch calls reject it (KBE_ENOTSUP / KBE_EINVAL). */
 
 /* One Keldysh function on the grid (G, or a gradient with the same shape). */
 typedef struct {

@@ -25,6 +25,7 @@ OUT_IR, OUT_IL, OUT_ITV, OUT_JTV = 0x1, 0x2, 0x4, 0x8
 OUT_ALL = 0xF
 FORCE_GENERIC = 0x100
 GRAD_OVERWRITE = 0x200
+GREATER = 0x400  # kbe_collision: the greater form of Eq. KBE2
 NMAX, KMAX = 16, 20
 
 _lib = None

@@ -58,7 +58,7 @@ kbe_status check_common(const kbe_green *G, const kbe_sigma_row *S, const kbe_wt
                         int m0, int m1, unsigned flags) {
   kbe_status s = check_green(G, "G");
   if (s != KBE_OK) return s;
-  if (flags & ~(KBE_OUT_ALL | KBE_FORCE_GENERIC | KBE_GRAD_OVERWRITE))
+  if (flags & ~(KBE_OUT_ALL | KBE_FORCE_GENERIC | KBE_GRAD_OVERWRITE | KBE_GREATER))
     return fail(KBE_EINVAL, "unknown flag bits 0x%x", flags);
   if (n < 0 || n >= G->nt) return fail(KBE_ERANGE, "n = %d outside [0, nt = %d)", n, G->nt);
   if (m0 < 0 || m0 > m1 || m1 > n + 1)
@@ -66,7 +66,8 @@ kbe_status check_common(const kbe_green *G, const kbe_sigma_row *S, const kbe_wt
   if (!S) return fail(KBE_EINVAL, "S is NULL");
   if (!W) return fail(KBE_EINVAL, "W is NULL");
   const bool th = G->ntau > 0;
-  if ((flags & (KBE_OUT_IR | KBE_OUT_JTV)) && !S->ret) return fail(KBE_EINVAL, "S->ret is NULL");
+  const unsigned need_ret = KBE_OUT_IR | KBE_OUT_JTV | ((flags & KBE_GREATER) ? KBE_OUT_IL : 0u);
+  if ((flags & need_ret) && !S->ret) return fail(KBE_EINVAL, "S->ret is NULL");
   if ((flags & KBE_OUT_IL) && !S->les) return fail(KBE_EINVAL, "S->les is NULL");
   if (th && (flags & (KBE_OUT_ITV | KBE_OUT_JTV)) && !S->tv) return fail(KBE_EINVAL, "S->tv is NULL");
   if ((flags & (KBE_OUT_IR | KBE_OUT_IL | KBE_OUT_JTV)) && !W->w) return fail(KBE_EINVAL, "W->w is NULL");
@@ -253,6 +254,7 @@ kbe_status kbe_collision_vjp(const kbe_green *G, const kbe_sigma_row *S, const k
                              const kbe_c128 *gIR, const kbe_c128 *gIL, const kbe_c128 *gItv,
                              const kbe_c128 *gJtv, const kbe_green *gG, const kbe_sigma_row *gS,
                              void *ws, size_t ws_bytes, void *stream) {
+  if (flags & KBE_GREATER) return fail(KBE_ENOTSUP, "the adjoint of the greater form is not built");
   kbe_status s = check_common(G, S, W, n, m0, m1, flags);
   if (s != KBE_OK) return s;
   if ((s = check_same_shape(G, gG, "gG")) != KBE_OK) return s;

@@ -48,6 +48,12 @@ enum Cls {
   B_T2B,   // adjoint: gSigma^](l) from C_JM2 terms
   G_MAT1,  // adjoint: gG^M(k) from C_JM1 terms
   G_MAT2,  // adjoint: gG^M(k) from C_JM2 terms
+  // the greater form (KBE_GREATER): G^>(s,m) = G^<(s,m) + D(s,m) in I^R, with D(s,m) = G^R(s,m)
+  // for s > m, G^R(m,m) at s = m and -G^R(m,s)^dagger for s < m; Sigma^> = Sigma^R + Sigma^< in I^<
+  C_GRL,   // I^R, s > m :  w[n][s] Sigma^R(s) kp[s][m]
+  C_GRD,   // I^R, s = m :  w[n][m] Sigma^R(m) rdiag[m]
+  C_GRU,   // I^R, s < m : -w[n][s] Sigma^R(s) kp[m][s]^dagger
+  C_GLR,   // I^<, s <= m:  w[m][s] Sigma^R(s) G^R(m,s)^dagger
   NCLS
 };
 enum Op { OP_N = 0, OP_H = 1, OP_HN = 2 };
@@ -55,7 +61,7 @@ enum Op { OP_N = 0, OP_H = 1, OP_HN = 2 };
 template <int CLS>
 __host__ __device__ constexpr int cls_op() {
   return (CLS == C_IRR || CLS == C_IL || CLS == C_ITV || CLS == B_R1 || CLS == B_R3 ||
-          CLS == B_T2A || CLS == B_T2B)
+          CLS == B_T2A || CLS == B_T2B || CLS == C_GRU || CLS == C_GLR)
              ? OP_H
              : ((CLS == G_MAT1 || CLS == G_MAT2) ? OP_HN : OP_N);
 }
@@ -68,6 +74,10 @@ __device__ __forceinline__ void cls_range(const Params &p, int o, int &lo, int &
     case C_IRC: lo = 0; hi = m + 1; break;
     case C_IRR: lo = m + 1; hi = p.n + 1; break;
     case C_IL: lo = 0; hi = m + 1; break;
+    case C_GRL: lo = m + 1; hi = p.n + 1; break;
+    case C_GRD: lo = m; hi = m + 1; break;
+    case C_GRU: lo = 0; hi = m; break;
+    case C_GLR: lo = 0; hi = m + 1; break;
     case C_ITV: lo = 0; hi = p.ntau; break;
     case C_JR: lo = 0; hi = p.n + 1; break;
     case C_JM1: lo = 0; hi = o + 1; break;        // l <= j
@@ -89,7 +99,8 @@ template <int CLS>
 __device__ __forceinline__ const kbe_c128 *cls_Q(const Params &p, int t) {
   const int64_t E = bsz(p);
   switch (CLS) {
-    case C_IRC: case C_IRR: case C_JR: return p.ret + t * E;
+    case C_IRC: case C_IRR: case C_JR: case C_GRL: case C_GRD: case C_GRU: case C_GLR:
+      return p.ret + t * E;
     case C_IL: return p.les + t * E;
     case C_ITV: case C_JM1: case C_JM2: case G_MAT1: case G_MAT2: return p.stv + t * E;
     case B_R1: case B_R2: return p.gIR + (t - p.m0) * E;
@@ -103,7 +114,9 @@ __device__ __forceinline__ const kbe_c128 *cls_Q(const Params &p, int t) {
 // Every term weight is a real quadrature weight times a class constant f in {1, -1, i, -i}.
 template <int CLS>
 __host__ __device__ constexpr int cls_fre() {
-  return (CLS == C_IRR || CLS == C_JM1 || CLS == B_R2 || CLS == B_T2A || CLS == G_MAT1) ? -1
+  return (CLS == C_IRR || CLS == C_JM1 || CLS == B_R2 || CLS == B_T2A || CLS == G_MAT1 ||
+          CLS == C_GRU)
+             ? -1
          : (CLS == C_ITV || CLS == B_T1)                                                 ? 0
                                                                                          : 1;
 }
@@ -127,6 +140,13 @@ __device__ __forceinline__ void cls_wpP(const Params &p, int o, int t, const dou
       P = t < m ? kp_blk(p, m, t) : p.rdiag + m * E;
       break;
     case C_ITV: w = p.wtau + t; P = tv_blk(p, m, J - t); break;
+    case C_GRL: w = p.w + ((int64_t)p.n * p.nt + t); P = kp_blk(p, t, m); break;
+    case C_GRD: w = p.w + ((int64_t)p.n * p.nt + t); P = p.rdiag + m * E; break;
+    case C_GRU: w = p.w + ((int64_t)p.n * p.nt + t); P = kp_blk(p, m, t); break;
+    case C_GLR:
+      w = p.w + ((int64_t)m * p.nt + t);
+      P = t < m ? kp_blk(p, m, t) : p.rdiag + m * E;
+      break;
     case C_JR: w = p.w + ((int64_t)p.n * p.nt + t); P = tv_blk(p, t, o); break;
     case C_JM1:  // l = t <= j = o
       w = p.wf + ((int64_t)o * p.ntau + t);
@@ -189,7 +209,8 @@ __device__ __forceinline__ void range_rt(int cls, const Params &p, int o, int &l
   case C: cls_range<C>(p, o, lo, hi); break;
     KBE_CASE(C_IRC) KBE_CASE(C_IRR) KBE_CASE(C_IL) KBE_CASE(C_ITV) KBE_CASE(C_JR) KBE_CASE(C_JM1)
     KBE_CASE(C_JM2) KBE_CASE(B_R1) KBE_CASE(B_R2) KBE_CASE(B_R3) KBE_CASE(B_L) KBE_CASE(B_T1)
-    KBE_CASE(B_T2A) KBE_CASE(B_T2B) KBE_CASE(G_MAT1) KBE_CASE(G_MAT2)
+    KBE_CASE(B_T2A) KBE_CASE(B_T2B) KBE_CASE(G_MAT1) KBE_CASE(G_MAT2) KBE_CASE(C_GRL)
+    KBE_CASE(C_GRD) KBE_CASE(C_GRU) KBE_CASE(C_GLR)
 #undef KBE_CASE
     default: lo = hi = 0;
   }
@@ -671,9 +692,9 @@ __device__ __forceinline__ void wg_task_mfma16(const Params &p, int nout, int ng
 // zeroed by a fill kernel before each launch.
 struct FusedPlan {
   int ncls, SC, MO;
-  int cls[10], nout[10], nchunk[10], ngroup[10];
-  int64_t first[11];
-  int64_t off[10];  // byte offset of each class's partials [nchunk][nout][N*N] in the workspace
+  int cls[12], nout[12], nchunk[12], ngroup[12];
+  int64_t first[13];
+  int64_t off[12];  // byte offset of each class's partials [nchunk][nout][N*N] in the workspace
   int64_t qoff;     // byte offset of the 8 queue heads
 };
 
@@ -745,6 +766,9 @@ __global__ void __launch_bounds__(256) stream_fused(Params p, FusedPlan pl, char
           KBE_CASE(C_IRC) KBE_CASE(C_IRR) KBE_CASE(C_IL) KBE_CASE(C_ITV) KBE_CASE(C_JR)
           KBE_CASE(C_JM1) KBE_CASE(C_JM2)
         }
+        if constexpr (KIND == KIND_GENERIC) {  // the greater form runs on the generic path only
+          switch (pl.cls[k]) { KBE_CASE(C_GRL) KBE_CASE(C_GRD) KBE_CASE(C_GRU) KBE_CASE(C_GLR) }
+        }
       } else {
         switch (pl.cls[k]) {
           KBE_CASE(B_R1) KBE_CASE(B_R2) KBE_CASE(B_R3) KBE_CASE(B_L) KBE_CASE(B_T1)
@@ -764,9 +788,10 @@ __global__ void zero_heads(unsigned int *heads) {
 // Chunk reduction, all outputs of a call in one launch.  Job j writes out_j[x] (=|+=) the sum,
 // in increasing chunk order, of the chunks of up to three classes' partial arrays that
 // intersect output o's term range; the jobs' elements are laid end to end over the grid.
+constexpr int RED_PARTS = 5;  // classes summed into one output array, at most
 struct RedJob {
-  const kbe_c128 *a[3];
-  int cls[3], nchunk[3];
+  const kbe_c128 *a[RED_PARTS];
+  int cls[RED_PARTS], nchunk[RED_PARTS];
   int nparts, nout, accumulate;
   kbe_c128 *out;
   int64_t start;  // first grid element of this job
@@ -1198,7 +1223,7 @@ __global__ void __launch_bounds__(256) grad_mfma8(Params p, int row_len, int nse
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 static int path_kind(int N, unsigned flags) {
-  if (flags & KBE_FORCE_GENERIC) return KIND_GENERIC;
+  if (flags & (KBE_FORCE_GENERIC | KBE_GREATER)) return KIND_GENERIC;
   if (N == 16) return KIND_MFMA;
   return N <= 8 ? N : KIND_GENERIC;
 }
@@ -1250,11 +1275,20 @@ static size_t plan_forward(int N, int ntau, int n, int m0, int m1, unsigned flag
   const int E = N * N, M = m1 - m0;
   size_t off = 0;
   const bool th = ntau > 0;
+  const bool gr = flags & KBE_GREATER;
   if (flags & KBE_OUT_IR) {
     plan_add(pl, C_IRC, M, m1, E, off);
     if (n > m0) plan_add(pl, C_IRR, M, n + 1, E, off);
+    if (gr) {
+      if (n > m0) plan_add(pl, C_GRL, M, n + 1, E, off);
+      plan_add(pl, C_GRD, M, m1, E, off);
+      if (m1 > 1) plan_add(pl, C_GRU, M, m1 - 1, E, off);
+    }
   }
-  if (flags & KBE_OUT_IL) plan_add(pl, C_IL, M, m1, E, off);
+  if (flags & KBE_OUT_IL) {
+    plan_add(pl, C_IL, M, m1, E, off);
+    if (gr) plan_add(pl, C_GLR, M, m1, E, off);
+  }
   if ((flags & KBE_OUT_ITV) && th) plan_add(pl, C_ITV, M, ntau, E, off);
   if ((flags & KBE_OUT_JTV) && th) {
     plan_add(pl, C_JR, ntau, n + 1, E, off);
@@ -1356,7 +1390,7 @@ static void reduce_into(const Params &p, const FusedPlan &pl, std::initializer_l
   in = RedJob{};
   for (int c : classes)
     for (int k = 0; k < pl.ncls; ++k)
-      if (pl.cls[k] == c && in.nparts < 3) {
+      if (pl.cls[k] == c && in.nparts < RED_PARTS) {
         in.a[in.nparts] = (const kbe_c128 *)(ws + pl.off[k]);
         in.cls[in.nparts] = c;
         in.nchunk[in.nparts] = pl.nchunk[k];
@@ -1385,8 +1419,8 @@ hipError_t launch_collision(const Params &p, unsigned flags, kbe_c128 *IR, kbe_c
   const int M = p.m1 - p.m0;
   RedAll r{};
   r.SC = pl.SC;
-  if (flags & KBE_OUT_IR) reduce_into(p, pl, {C_IRC, C_IRR}, w, M, IR, false, r);
-  if (flags & KBE_OUT_IL) reduce_into(p, pl, {C_IL}, w, M, IL, false, r);
+  if (flags & KBE_OUT_IR) reduce_into(p, pl, {C_IRC, C_IRR, C_GRL, C_GRD, C_GRU}, w, M, IR, false, r);
+  if (flags & KBE_OUT_IL) reduce_into(p, pl, {C_IL, C_GLR}, w, M, IL, false, r);
   if (flags & KBE_OUT_ITV) reduce_into(p, pl, {C_ITV}, w, M, Itv, false, r);
   if ((flags & KBE_OUT_JTV) && p.ntau > 0) reduce_into(p, pl, {C_JR, C_JM1, C_JM2}, w, p.ntau, Jtv, false, r);
   reduce_launch(p, r, st);

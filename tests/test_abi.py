@@ -320,3 +320,17 @@ def test_sigma_full_argument_errors():
     S = green()
     S.rdiag = None
     assert L.kbe_sigma_2b_full(ctypes.byref(G), FAKE, ctypes.byref(S), None) == 1
+
+
+def test_greater_form_flag():
+    """KBE_GREATER is a known kbe_collision flag (its workspace differs) and the adjoint rejects it
+    with KBE_ENOTSUP."""
+    L = kbe.lib()
+    a = L.kbe_collision_workspace(2, 8, 4, 7, 0, 8, kbe.OUT_ALL)
+    b = L.kbe_collision_workspace(2, 8, 4, 7, 0, 8, kbe.OUT_ALL | kbe.GREATER)
+    assert b > a > 0
+    G, S, W = green(), row(), wts()
+    st = L.kbe_collision_vjp(ctypes.byref(G), ctypes.byref(S), ctypes.byref(W), 7, 0, 8,
+                             kbe.OUT_ALL | kbe.GREATER, FAKE, FAKE, FAKE, FAKE,
+                             ctypes.byref(green()), ctypes.byref(row()), FAKE, 1 << 40, None)
+    assert st == 5 and "greater" in err()

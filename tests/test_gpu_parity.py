@@ -296,3 +296,29 @@ def test_sigma_full_mode_matches_oracle(gpu, N, nt, ntau, sldt):
     for name, g, r in (("kp", got, rkp), ("rdiag", to_host(S.rdiag), rrd), ("tv", to_host(S.tv), rtv)):
         assert np.all(np.isfinite(g)), name
         assert np.all(bnorm(g - r) <= 1e-13 * (bnorm(r) + 1e-300)), name
+
+
+@pytest.mark.parametrize("N,nt,ntau,mr", [(1, 20, 6, None), (3, 25, 0, (4, 17)), (8, 18, 5, None),
+                                          (16, 14, 4, (0, 9))])
+def test_greater_form_matches_oracle(gpu, N, nt, ntau, mr):
+    """kbe_collision with KBE_GREATER (generic kernels) against the oracle's greater form, all
+    outputs, whole and partial m-ranges."""
+    kbe = gpu
+    case = Case(N=N, nt=nt, ntau=ntau, beta=4.0, seed=800 + N)
+    t, order, kp, rd, tv, mat = case.host()
+    G = oracle.Green(kp, rd, tv if ntau else None, mat if ntau else None)
+    W = oracle.Weights.build(t, order, case.beta if ntau else None, ntau, case.tau_order)
+    n = nt - 1
+    sig = synth.sigma_row(case.seed + 5, N, n, ntau, t)
+    m0, m1 = mr if mr else (0, n + 1)
+    Gd = device_green(kp, rd, tv, mat)
+    Wd = device_weights(W)
+    out = kbe.collision(Gd, tuple(to_dev(x) for x in sig), Wd, n, m0, m1,
+                        kbe.OUT_ALL | kbe.GREATER)
+    ref = oracle.collision(G, sig, W, n, m0, m1, oracle.F_ALL | oracle.F_GREATER)
+    for name, g, r in zip(("IR", "IL", "Itv", "Jtv"), out, ref):
+        if g is None:
+            assert r.size == 0 or not ntau
+            continue
+        g = to_host(g)
+        assert np.all(bnorm(g - r) <= 1e-12 * (bnorm(r).max() + 1e-300)), name
