@@ -31,6 +31,10 @@ METRIC = "collision-integral FP64 GFLOP/s + HBM GB/s, N_orb=16 n=2048; adjoint/f
 HBM_PEAK_GBS = 8000.0
 MFMA_F64_PEAK_TFLOPS = 78.6
 RIDGE = MFMA_F64_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+# Ceilings measured on this GPU with microbenchmarks (a dependent-chain-free stream of
+# v_mfma_f64_4x4x4 products; a read-only stream of the HBM): the achievable, not the spec, peaks.
+MEASURED_MFMA_F64_TFLOPS = 70.0
+MEASURED_HBM_READ_GBS = 6400.0
 
 
 def log(*a):
@@ -178,6 +182,39 @@ def small_orbital_shape(kbe, torch, dev, reps=5):
             "collision_vjp_gbps": c["adj_bytes"] / b_ms / 1e6,
             "algorithmic_bytes": c["fwd_bytes"], "algorithmic_flop": c["fwd_flop"],
             "traffic": measured_traffic("traffic_collision_N8_nt1024.json")}
+
+
+def graph_pair(kbe, torch, G, u, n, t, order, w, reps=10):
+    """[kbe_sigma_2b -> kbe_collision] captured once as a HIP graph and replayed (no host work
+    between the kernels), against the same pair issued eagerly; weights computed beforehand."""
+    W = kbe.weights(t, order, G.ntau, w.beta, w.tau_order, device=G.device)
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = ev(), ev()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    eager = timed(lambda: kbe.collision(G, kbe.sigma_2b(G, u, n), W, n))
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        kbe.collision(G, kbe.sigma_2b(G, u, n), W, n)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        kbe.collision(G, kbe.sigma_2b(G, u, n), W, n)
+    replay = timed(g.replay)
+    del g
+    return {"eager_ms": eager, "graph_replay_ms": replay}
 
 
 def general_u_sigma(kbe, torch, G, n, w, reps=5):
@@ -427,8 +464,17 @@ def main():
             "traffic": traffic,
             "algorithmic_flop": c["fwd_flop"], "algorithmic_bytes": c["fwd_bytes"],
             "intensity_flop_per_byte": c["fwd_flop"] / c["fwd_bytes"],
-            "hbm_frac": c["fwd_bytes"] / coll_s / 1e9 / HBM_PEAK_GBS},
+            "hbm_frac": c["fwd_bytes"] / coll_s / 1e9 / HBM_PEAK_GBS,
+            "frac_of_measured_mfma_ceiling": achieved / MEASURED_MFMA_F64_TFLOPS,
+            "measured_read_gbps": (traffic / coll_s / 1e9) if traffic else None,
+            "measured_read_frac_of_ceiling":
+                (traffic / coll_s / 1e9 / MEASURED_HBM_READ_GBS) if traffic else None},
+        "per_call_ms": {name: {"median": float(np.median(ph[:, i])), "min": float(ph[:, i].min())}
+                        for i, name in enumerate(("weights", "sigma_2b", "collision",
+                                                  "collision_vjp", "sigma_2b_vjp"))},
     }
+    log("sigma row -> collision as a graph")
+    result["sigma_collision_graph"] = graph_pair(kbe, torch, G, u, n, t, order, w)
     log("general four-index self-energy")
     result["gf2"] = general_u_sigma(kbe, torch, G, n, w)
     del gG, kp, tvd, G
