@@ -125,6 +125,27 @@ def test_collision_parity_n16_several_chunks(gpu, generic):
     check_all(*out)
 
 
+@pytest.mark.parametrize("nt,ntau,n,flags", [
+    (9, 3, None, oracle.F_ALL),
+    (2, 2, None, oracle.F_ALL),
+    (257, 9, None, oracle.F_ALL),
+    (300, 17, 170, oracle.F_ALL),
+    (300, 17, None, oracle.F_ITV | oracle.F_JTV),
+    (300, 17, None, oracle.F_IR),
+    (300, 17, None, oracle.F_ITV),
+    (300, 17, None, oracle.F_JTV),
+    (130, 2, None, oracle.F_ALL),
+])
+def test_collision_n16_sizes_and_subsets(gpu, nt, ntau, n, flags):
+    """N = 16 (MFMA path) over the whole output range at small, ragged and two-chunk sizes (chunks
+    of 256 terms, groups of 8 outputs), every output alone or with the others, at the last row
+    and with row n inside the stored history."""
+    kbe = gpu
+    _print("n16 sizes", nt, ntau, n, flags)
+    case = Case(N=16, nt=nt, ntau=ntau, beta=2.5, seed=300 + nt)
+    check_all(*run_collision(kbe, case, n=n, flags=flags), flags)
+
+
 @pytest.mark.parametrize("N", [1, 3, 4, 5, 7, 8, 9, 13, 16])
 def test_collision_orbital_counts(gpu, N):
     kbe = gpu

@@ -45,6 +45,11 @@ def vjp_case(kbe, case: Case, m0, m1, flags, extra=0, seed_cot=5):
     (16, 170, 17, 0, 170, oracle.F_ALL, True),
     (16, 150, 12, 33, 101, oracle.F_ALL, False),
     (16, 60, 8, 0, 60, oracle.F_IR | oracle.F_JTV, False),
+    (16, 300, 40, 0, 300, oracle.F_ALL, False),
+    (16, 9, 3, 0, 9, oracle.F_ALL, False),
+    (16, 60, 8, 0, 60, oracle.F_ITV | oracle.F_JTV, False),
+    (16, 60, 8, 0, 60, oracle.F_IR, False),
+    (16, 260, 2, 0, 260, oracle.F_ALL, False),
     (5, 40, 0, 0, 40, oracle.F_IR | oracle.F_IL, False),
     (8, 300, 140, 0, 300, oracle.F_ALL, False),
     (8, 300, 140, 0, 300, oracle.F_ALL, True),
