@@ -50,6 +50,11 @@ __device__ __forceinline__ double ldgd(const double *p) {
   return *(const __attribute__((address_space(1))) double *)(const void *)p;
 }
 
+typedef double __attribute__((ext_vector_type(4))) d4b;
+__device__ __forceinline__ d4b mfma16b(double a, double b, d4b c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
 // Terms per work unit of an item: the call's chunk when it is set, else the item's own, else the
 // default.
 __host__ __device__ inline int item_chunk(const kbe_batch_item &it, int chunk) {
@@ -542,7 +547,7 @@ __global__ void __launch_bounds__(256) batch_reduce(const kbe_batch_item *items,
 // up to a power of two); thread (block b, element e = i N + j) computes element (i, j) of its
 // VJP_R output blocks from the cotangent's row or column (in registers for the whole task) and
 // the streamed blocks X (staged in LDS, double-buffered, the next step's elements loaded ahead).
-__global__ void __launch_bounds__(256) batch_vjp_stream(const kbe_batch_vjp_item *items,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) batch_vjp_stream(const kbe_batch_vjp_item *items,
                                                         int count, const int *perm,
                                                         const int64_t *tb, unsigned int *head) {
   __shared__ int64_t tbs[TB_LDS];
@@ -602,23 +607,6 @@ __global__ void __launch_bounds__(256) batch_vjp_stream(const kbe_batch_vjp_item
       case 8: form = itv ? F_GX : F_ZERO; Gc = it.gItv; out = it.g_sig_tv; break;
       default: form = itv ? F_GHX : F_ZERO; Gc = it.gItv; out = it.g_tv; break;
     }
-    // the cotangent's row ei (G X, G X^dagger), column ej (X^dagger G) or conjugated column ei
-    // (G^dagger X) of this thread's element
-    cd g[16];
-    {
-      // loads at clamped, always valid addresses (the output array stands in for an absent
-      // cotangent), the unwanted values selected away: no divergent branches
-      const kbe_c128 *gp = form == F_ZERO ? out : Gc;
-      const int ec = valid ? e : 0, ci = ec / N, cj_ = ec % N;
-#pragma unroll
-      for (int l = 0; l < 16; ++l) {
-        const int lc = l < N ? l : 0;
-        const int gi = form == F_XHG ? lc * N + cj_ : form == F_GHX ? lc * N + ci : ci * N + lc;
-        cd v = ldg(gp + gi);
-        if (form == F_GHX) v = cj(v);  // uniform
-        g[l] = (form != F_ZERO && valid && l < N) ? v : czero();
-      }
-    }
     // streamed block of output block s, and its scalar
     auto xblk = [&](int s) -> const kbe_c128 * {
       switch (k) {
@@ -642,6 +630,78 @@ __global__ void __launch_bounds__(256) batch_vjp_stream(const kbe_batch_vjp_item
         default: return cd{0.0, -ldgd(r.wtau + (J - s))};
       }
     };
+    if (N == 16) {
+      // One v_mfma_f64_16x16x4 product per block (lane l supplies A[l%16][4kc + l/16] and
+      // B[4kc + l/16][l%16] and holds D[l/16 + 4r][l%16]), three real products per complex
+      // one as in the small tasks.  The cotangent operand is formed once per task:
+      //   G X, G X^dagger: A = G;   G^dagger X: A = G^dagger;   X^dagger G: B = G;
+      // the streamed operand is loaded straight into its layout, scaled by the block's scalar:
+      //   G X, G^dagger X: B = X;   G X^dagger: B = X^dagger;   X^dagger G: A = X^dagger.
+      // Wave w takes the blocks b0 + w, b0 + w + 4, ..., each loaded a block ahead.  No LDS.
+      const int lane = tid & 63, lk = lane >> 4, lc = lane & 15;
+      const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+      const bool zero = form == F_ZERO;  // nothing is read
+      const bool xa = form == F_XHG;     // the streamed operand is A
+      const bool xt = form == F_GXH;     // it is read at the transposed position
+      const bool xc = form == F_GXH || form == F_XHG;  // and conjugated
+      cd gv[4];
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) {
+        gv[kc] = czero();
+        if (!zero) {
+          gv[kc] = ldg(Gc + (form == F_GHX || xa ? (4 * kc + lk) * 16 + lc : lc * 16 + 4 * kc + lk));
+          if (form == F_GHX) gv[kc] = cj(gv[kc]);
+        }
+      }
+      cd xn[4] = {czero(), czero(), czero(), czero()}, cn = czero();
+      auto fetch16 = [&](int sb) {
+        const kbe_c128 *X = xblk(sb);
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc)
+          xn[kc] = ldg(X + (xt ? lc * 16 + 4 * kc + lk : (4 * kc + lk) * 16 + lc));
+        cn = scal(sb);
+      };
+      int s = b0 + wave;
+      if (!zero && s < b1) fetch16(s);
+      for (; s < b1; s += 4) {
+        cd x[4];
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) x[kc] = xn[kc];
+        cd cs = cn;
+        if (!zero) fetch16(s + 4 < b1 ? s + 4 : b1 - 1);
+        if (zero || (k == 6 && s == r.m)) cs = czero();  // zero blocks (g_row[m], unselected)
+        d4b k1 = {0, 0, 0, 0}, k2 = {0, 0, 0, 0}, k3 = {0, 0, 0, 0};
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) {
+          const cd v = cs * (xc ? cj(x[kc]) : x[kc]);
+          const cd a = xa ? v : gv[kc], bb = xa ? gv[kc] : v;
+          k1 = mfma16b(a.re + a.im, bb.re, k1);
+          k2 = mfma16b(a.re, bb.im - bb.re, k2);
+          k3 = mfma16b(a.im, bb.re + bb.im, k3);
+        }
+        kbe_c128 *d = out + (int64_t)s * E;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) stg(d + (lk + 4 * q) * 16 + lc, cd{k1[q] - k3[q], k1[q] + k2[q]});
+      }
+      continue;  // the whole workgroup: no barrier inside this branch
+    }
+    // the cotangent's row ei (G X, G X^dagger), column ej (X^dagger G) or conjugated column ei
+    // (G^dagger X) of this thread's element
+    cd g[16];
+    {
+      // loads at clamped, always valid addresses (the output array stands in for an absent
+      // cotangent), the unwanted values selected away: no divergent branches
+      const kbe_c128 *gp = form == F_ZERO ? out : Gc;
+      const int ec = valid ? e : 0, ci = ec / N, cj_ = ec % N;
+#pragma unroll
+      for (int l = 0; l < 16; ++l) {
+        const int lc = l < N ? l : 0;
+        const int gi = form == F_XHG ? lc * N + cj_ : form == F_GHX ? lc * N + ci : ci * N + lc;
+        cd v = ldg(gp + gi);
+        if (form == F_GHX) v = cj(v);  // uniform
+        g[l] = (form != F_ZERO && valid && l < N) ? v : czero();
+      }
+    }
     // steps of VJP_R * bps blocks: thread handles block sub + bps r, r = 0..VJP_R-1, of a step
     const int per = VJP_R * bps;
     const int nstep = (b1 - b0 + per - 1) / per;
