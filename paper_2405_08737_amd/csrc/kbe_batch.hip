@@ -109,7 +109,9 @@ __device__ __forceinline__ void item_range(const kbe_batch_item &it, int k, int 
 //   V8 g_sig_tv[j]:           i wtau[j] GT tv[J-j]             (form GX)
 //   V9 g_tv[k]:              -i wtau[J-k] GT^dagger sig_tv[J-k]
 constexpr int VJP_CLASSES = 10;
-constexpr int VJP_CHUNK = 64;  // output blocks per adjoint task
+// Output blocks per adjoint task: 64 at N > 4; more for smaller blocks, so that a task is a few
+// steps of the vector-ALU loop rather than one (8 steps at N = 2, 4 and 8).
+__host__ __device__ inline int vjp_chunk(int N) { return N <= 2 ? 1024 : (N <= 4 ? 256 : 64); }
 constexpr int VJP_R = 2;       // blocks per thread per step of the adjoint (loads in flight)
 enum VjpForm { F_GXH, F_GX, F_XHG, F_GHX, F_ZERO };
 
@@ -126,7 +128,8 @@ __host__ __device__ inline void vjp_chunks(const kbe_batch_item &r, int c[VJP_CL
   for (int k = 0; k < VJP_CLASSES; ++k) {
     int lo, hi;
     vjp_range(r, k, lo, hi);
-    c[k] = (hi - lo + VJP_CHUNK - 1) / VJP_CHUNK;
+    const int ch = vjp_chunk(r.N);
+    c[k] = (hi - lo + ch - 1) / ch;
   }
 }
 
@@ -389,7 +392,7 @@ __device__ __forceinline__ int64_t block_scan(int64_t v, int64_t *ws, int64_t *t
 }
 
 // Per-item task and partial counts of the forward (partials: one N x N block per task) and of
-// the adjoint (tasks of VJP_CHUNK output blocks, no partials).
+// the adjoint (tasks of vjp_chunk(N) output blocks, no partials).
 __device__ inline const kbe_batch_item &row_of(const kbe_batch_item &x) { return x; }
 __device__ inline const kbe_batch_item &row_of(const kbe_batch_vjp_item &x) { return x.row; }
 __device__ inline int64_t plan_tasks(const kbe_batch_item &it, int chunk) {
@@ -542,7 +545,7 @@ __global__ void __launch_bounds__(256) batch_reduce(const kbe_batch_item *items,
   if (it.flags & KBE_OUT_ITV) stg(it.Itv + e, sum(ilb, itb));
 }
 
-// Adjoint: persistent workgroups take tasks (item, class, up to VJP_CHUNK output blocks) from one
+// Adjoint: persistent workgroups take tasks (item, class, up to vjp_chunk(N) output blocks) from one
 // counter.  Blocks of one class go through in steps of VJP_R * 256 / EP blocks (EP = N^2 rounded
 // up to a power of two); thread (block b, element e = i N + j) computes element (i, j) of its
 // VJP_R output blocks from the cotangent's row or column (in registers for the whole task) and
@@ -583,8 +586,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) b
     while (local >= c[k]) local -= c[k++];
     int b0, b1;
     vjp_range(r, k, b0, b1);
-    b0 += local * VJP_CHUNK;
-    b1 = b0 + VJP_CHUNK < b1 ? b0 + VJP_CHUNK : b1;
+    const int vch = vjp_chunk(r.N);
+    b0 += local * vch;
+    b1 = b0 + vch < b1 ? b0 + vch : b1;
     const int N = r.N, E = N * N, J = r.ntau - 1;
     const int EP = E <= 1 ? 1 : E <= 4 ? 4 : E <= 16 ? 16 : E <= 32 ? 32 : E <= 64 ? 64 : E <= 128 ? 128 : 256;
     const int bps = 256 / EP, sub = tid / EP, e = tid % EP, ei = e / N, ej = e % N;
@@ -630,6 +634,59 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) b
         default: return cd{0.0, -ldgd(r.wtau + (J - s))};
       }
     };
+    if (N == 8) {
+      // One v_mfma_f64_4x4x4 product per k-chunk and block: the instruction's four 4x4 blocks
+      // b = 2 ti + tj are the four tiles of the 8 x 8 product, so lane l supplies
+      // A[4ti + l%4][4kc + l/16] and B[4kc + l/16][4tj + l%4] and holds D[4ti + l/16][4tj + l%4]
+      // (ti = (l/8)%2, tj = (l/4)%2).  Operand roles, scaling and the work split as at N = 16
+      // below; a wave covers one whole block.
+      const int lane = tid & 63, lj = lane & 3, lb = (lane >> 2) & 3, lk = lane >> 4;
+      const int ti = lb >> 1, tj = lb & 1;
+      const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+      const bool zero = form == F_ZERO;
+      const bool xa = form == F_XHG, xt = form == F_GXH, xc = form == F_GXH || form == F_XHG;
+      cd gv[2];
+#pragma unroll
+      for (int kc = 0; kc < 2; ++kc) {
+        gv[kc] = czero();
+        if (!zero) {
+          const int gi = xa ? (4 * kc + lk) * 8 + 4 * tj + lj
+                         : (form == F_GHX ? (4 * kc + lk) * 8 + 4 * ti + lj
+                                          : (4 * ti + lj) * 8 + 4 * kc + lk);
+          gv[kc] = ldg(Gc + gi);
+          if (form == F_GHX) gv[kc] = cj(gv[kc]);
+        }
+      }
+      const int xo0 = xa ? lk * 8 + 4 * ti + lj : (xt ? (4 * tj + lj) * 8 + lk : lk * 8 + 4 * tj + lj);
+      const int xo1 = xa ? (4 + lk) * 8 + 4 * ti + lj : (xt ? (4 * tj + lj) * 8 + 4 + lk : (4 + lk) * 8 + 4 * tj + lj);
+      cd xn[2] = {czero(), czero()}, cn = czero();
+      auto fetch8 = [&](int sb) {
+        const kbe_c128 *X = xblk(sb);
+        xn[0] = ldg(X + xo0);
+        xn[1] = ldg(X + xo1);
+        cn = scal(sb);
+      };
+      int s = b0 + wave;
+      if (!zero && s < b1) fetch8(s);
+      for (; s < b1; s += 4) {
+        const cd x0 = xn[0], x1 = xn[1];
+        cd cs = cn;
+        if (!zero) fetch8(s + 4 < b1 ? s + 4 : b1 - 1);
+        if (zero || (k == 6 && s == r.m)) cs = czero();
+        double k1 = 0.0, k2 = 0.0, k3 = 0.0;
+#pragma unroll
+        for (int kc = 0; kc < 2; ++kc) {
+          const cd xv = kc == 0 ? x0 : x1;
+          const cd v = cs * (xc ? cj(xv) : xv);
+          const cd a = xa ? v : gv[kc], bb = xa ? gv[kc] : v;
+          k1 = mfma4b(a.re + a.im, bb.re, k1);
+          k2 = mfma4b(a.re, bb.im - bb.re, k2);
+          k3 = mfma4b(a.im, bb.re + bb.im, k3);
+        }
+        stg(out + (int64_t)s * 64 + (4 * ti + lk) * 8 + 4 * tj + lj, cd{k1 - k3, k1 + k2});
+      }
+      continue;  // the whole workgroup: no barrier inside this branch
+    }
     if (N == 16) {
       // One v_mfma_f64_16x16x4 product per block (lane l supplies A[l%16][4kc + l/16] and
       // B[4kc + l/16][l%16] and holds D[l/16 + 4r][l%16]), three real products per complex
@@ -868,7 +925,7 @@ hipError_t launch_batch_vjp(const kbe_batch_vjp_item *items_dev, int count, void
   int *perm = (int *)(w + 2 * tsz);
   unsigned int *head = (unsigned int *)(w + 2 * tsz + al256b(sizeof(int) * (size_t)count));
   hipLaunchKernelGGL(batch_plan<kbe_batch_vjp_item>, dim3(1), dim3(1024), 0, st, items_dev, count,
-                     VJP_CHUNK, perm, tb, pb, head);
+                     0, perm, tb, pb, head);
   hipLaunchKernelGGL(batch_vjp_stream, dim3((unsigned)batch_vjp_grid()), dim3(256), 0, st,
                      items_dev, count, perm, tb, head);
   return hipGetLastError();
