@@ -483,13 +483,18 @@ void orc_collision_vjp(int N, int nt, int ntau, int64_t ldt, const cplx *kp, con
   for (int m = m0; m < m1; ++m) {
     if (flags & F_IR)
       for (int s = 0; s <= n; ++s) {
-        get_les(&g, s, m, blk); /* IR term: w[n][s] ret[s] G^<(s,m) */
+        /* IR term: w[n][s] ret[s] G^<(s,m)  (greater form: G^>(s,m)) */
+        if (flags & F_GREATER) get_gtr(&g, s, m, blk);
+        else get_les(&g, s, m, blk);
         mm_acc(N, gret + s * bs, w[(int64_t)n * nt + s], gIR + (m - m0) * bs, blk, 1);
       }
     if (flags & F_IL)
       for (int s = 0; s <= m; ++s) {
         get_ret(&g, m, s, blk); /* IL term: w[m][s] les[s] G^R(m,s)^dagger */
         mm_acc(N, gles + s * bs, w[(int64_t)m * nt + s], gIL + (m - m0) * bs, blk, 0);
+        /* greater form: the factor is Sigma^> = ret + les, so ret gets the same gradient */
+        if (flags & F_GREATER)
+          mm_acc(N, gret + s * bs, w[(int64_t)m * nt + s], gIL + (m - m0) * bs, blk, 0);
       }
     if ((flags & F_ITV) && ntau > 0)
       for (int j = 0; j < ntau; ++j) { /* Itv term: (-i wfull[j]) stv[j] tv[m][J-j]^dagger */
@@ -514,11 +519,32 @@ void orc_collision_vjp(int N, int nt, int ntau, int64_t ldt, const cplx *kp, con
         memset(tmp, 0, sizeof(cplx) * bs);
         mm_acc_hn(N, tmp, w[(int64_t)n * nt + s], ret + s * bs, gIR + (m - m0) * bs);
         add_les_grad(&g, gkp, s, m, tmp);
+        if (flags & F_GREATER) {
+          /* B = G^>(s,m) = G^<(s,m) + D(s,m): D = G^R(s,m) stored at kp[s][m] (s > m), at
+           * rdiag[m] (s = m), and D = -G^R(m,s)^dagger with G^R(m,s) at kp[m][s] (s < m) */
+          if (s > m) {
+            cplx *x = gkp + ((int64_t)s * ldt + m) * bs;
+            for (int e = 0; e < bs; ++e) x[e] += tmp[e];
+          } else if (s == m) {
+            cplx *x = grdiag + (int64_t)m * bs;
+            for (int e = 0; e < bs; ++e) x[e] += tmp[e];
+          } else {
+            cplx *x = gkp + ((int64_t)m * ldt + s) * bs;
+            for (int i = 0; i < N; ++i)
+              for (int j = 0; j < N; ++j) x[j * N + i] += -conj(tmp[i * N + j]);
+          }
+        }
       }
     if (flags & F_IL)
       for (int s = 0; s <= m; ++s) { /* B = G^R(m,s) used as B^dagger: gB = c gC^dagger A */
+        cplx sg[256];
+        const cplx *sa = les + s * bs;
+        if (flags & F_GREATER) { /* A = Sigma^>(t_n,t_s) = ret + les */
+          for (int e = 0; e < bs; ++e) sg[e] = ret[s * bs + e] + les[s * bs + e];
+          sa = sg;
+        }
         memset(tmp, 0, sizeof(cplx) * bs);
-        mm_acc_hn(N, tmp, w[(int64_t)m * nt + s], gIL + (m - m0) * bs, les + s * bs);
+        mm_acc_hn(N, tmp, w[(int64_t)m * nt + s], gIL + (m - m0) * bs, sa);
         cplx *x = (s == m) ? grdiag + (int64_t)m * bs : gkp + ((int64_t)m * ldt + s) * bs;
         for (int e = 0; e < bs; ++e) x[e] += tmp[e];
       }

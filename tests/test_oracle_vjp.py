@@ -24,8 +24,15 @@ def setup(N=2, nt=12, ntau=9, seed=0):
 
 
 @pytest.mark.parametrize("m0,m1,flags", [(0, 12, oracle.F_ALL), (3, 9, oracle.F_ALL),
-                                         (5, 6, oracle.F_IR), (0, 7, oracle.F_IL | oracle.F_JTV)])
+                                         (5, 6, oracle.F_IR), (0, 7, oracle.F_IL | oracle.F_JTV),
+                                         (0, 12, oracle.F_ALL | oracle.F_GREATER),
+                                         (3, 9, oracle.F_IR | oracle.F_IL | oracle.F_GREATER),
+                                         (5, 6, oracle.F_IR | oracle.F_GREATER),
+                                         (0, 7, oracle.F_IL | oracle.F_GREATER)])
 def test_collision_adjoint_dot_product(m0, m1, flags):
+    """Exact adjoint: Re<cot, I(dG)> = Re<gG, dG> and Re<cot, I(dSigma)> = Re<gSigma, dSigma>
+    (the integrals are real-linear in G for fixed Sigma and in Sigma for fixed G), for the lesser
+    and the greater form of Eq. KBE2, with the forward oracle pinned on its own."""
     rng, rnd, G, W = setup()
     N, nt, ntau = G.N, G.nt, G.ntau
     n = nt - 1
