@@ -332,12 +332,16 @@ class KBESigma2B(torch.autograd.Function):
 
 
 class KBECollision(torch.autograd.Function):
-    """(kp, rdiag, tv, mat, ret, les, stv) -> (IR, IL, Itv, Jtv); backward via kbe_collision_vjp."""
+    """(kp, rdiag, tv, mat, ret, les, stv) -> (IR, IL, Itv, Jtv); backward via kbe_collision_vjp.
+    greater=True takes the greater form of Eq. KBE2 (KBE_GREATER) in both directions."""
 
     @staticmethod
-    def forward(ctx, kp, rdiag, tv, mat, ret, les, stv, W: Weights, n: int, m0: int, m1: int):
+    def forward(ctx, kp, rdiag, tv, mat, ret, les, stv, W: Weights, n: int, m0: int, m1: int,
+                greater: bool = False):
         G = Green(kp, rdiag, tv, mat)
         flags = OUT_ALL if tv is not None else (OUT_IR | OUT_IL)
+        if greater:
+            flags |= GREATER
         IR, IL, Itv, Jtv = collision(G, (ret, les, stv), W, n, m0, m1, flags)
         ctx.save_for_backward(kp, rdiag, tv, mat, ret, les, stv)
         ctx.W, ctx.n, ctx.m0, ctx.m1, ctx.flags = W, n, m0, m1, flags
@@ -360,7 +364,7 @@ class KBECollision(torch.autograd.Function):
             gJ = g[3] if g[3] is not None else zeros(G.ntau)
         gG, (gret, gles, gstv) = collision_vjp(G, (ret, les, stv), ctx.W, ctx.n, ctx.m0, ctx.m1,
                                                (gIR, gIL, gItv, gJ), ctx.flags)
-        return gG.kp, gG.rdiag, gG.tv, gG.mat, gret, gles, gstv, None, None, None, None
+        return gG.kp, gG.rdiag, gG.tv, gG.mat, gret, gles, gstv, None, None, None, None, None
 
 
 # ------------------------------------------------------------------------------------------

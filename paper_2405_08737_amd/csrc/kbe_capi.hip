@@ -254,7 +254,6 @@ kbe_status kbe_collision_vjp(const kbe_green *G, const kbe_sigma_row *S, const k
                              const kbe_c128 *gIR, const kbe_c128 *gIL, const kbe_c128 *gItv,
                              const kbe_c128 *gJtv, const kbe_green *gG, const kbe_sigma_row *gS,
                              void *ws, size_t ws_bytes, void *stream) {
-  if (flags & KBE_GREATER) return fail(KBE_ENOTSUP, "the adjoint of the greater form is not built");
   kbe_status s = check_common(G, S, W, n, m0, m1, flags);
   if (s != KBE_OK) return s;
   if ((s = check_same_shape(G, gG, "gG")) != KBE_OK) return s;

@@ -54,6 +54,10 @@ enum Cls {
   C_GRD,   // I^R, s = m :  w[n][m] Sigma^R(m) rdiag[m]
   C_GRU,   // I^R, s < m : -w[n][s] Sigma^R(s) kp[m][s]^dagger
   C_GLR,   // I^<, s <= m:  w[m][s] Sigma^R(s) G^R(m,s)^dagger
+  // adjoint of the greater form: gSigma^R(s) from the D parts of C_GRL, C_GRD, C_GRU
+  B_GRL,   // s > m:  w[n][s] gIR(m) kp[s][m]^dagger
+  B_GRD,   // s = m:  w[n][s] gIR(s) rdiag[s]^dagger
+  B_GRU,   // s < m: -w[n][s] gIR(m) kp[m][s]
   NCLS
 };
 enum Op { OP_N = 0, OP_H = 1, OP_HN = 2 };
@@ -61,7 +65,8 @@ enum Op { OP_N = 0, OP_H = 1, OP_HN = 2 };
 template <int CLS>
 __host__ __device__ constexpr int cls_op() {
   return (CLS == C_IRR || CLS == C_IL || CLS == C_ITV || CLS == B_R1 || CLS == B_R3 ||
-          CLS == B_T2A || CLS == B_T2B || CLS == C_GRU || CLS == C_GLR)
+          CLS == B_T2A || CLS == B_T2B || CLS == C_GRU || CLS == C_GLR || CLS == B_GRL ||
+          CLS == B_GRD)
              ? OP_H
              : ((CLS == G_MAT1 || CLS == G_MAT2) ? OP_HN : OP_N);
 }
@@ -91,6 +96,9 @@ __device__ __forceinline__ void cls_range(const Params &p, int o, int &lo, int &
     case B_T2B: lo = 0; hi = o + 1; break;        // output l, terms j <= l
     case G_MAT1: lo = 0; hi = o + 1; break;       // output k, terms l <= k
     case G_MAT2: lo = o; hi = p.ntau; break;      // output k, terms l >= k
+    case B_GRL: lo = p.m0; hi = o < p.m1 ? o : p.m1; break;            // terms m < s
+    case B_GRD: lo = o; hi = (o >= p.m0 && o < p.m1) ? o + 1 : o; break;  // m = s
+    case B_GRU: lo = o + 1 > p.m0 ? o + 1 : p.m0; hi = p.m1; break;     // terms m > s
   }
 }
 
@@ -103,7 +111,7 @@ __device__ __forceinline__ const kbe_c128 *cls_Q(const Params &p, int t) {
       return p.ret + t * E;
     case C_IL: return p.les + t * E;
     case C_ITV: case C_JM1: case C_JM2: case G_MAT1: case G_MAT2: return p.stv + t * E;
-    case B_R1: case B_R2: return p.gIR + (t - p.m0) * E;
+    case B_R1: case B_R2: case B_GRL: case B_GRD: case B_GRU: return p.gIR + (t - p.m0) * E;
     case B_L: return p.gIL + (t - p.m0) * E;
     case B_T1: return p.gItv + (t - p.m0) * E;
     case B_R3: case B_T2A: case B_T2B: return p.gJ + t * E;
@@ -115,7 +123,7 @@ __device__ __forceinline__ const kbe_c128 *cls_Q(const Params &p, int t) {
 template <int CLS>
 __host__ __device__ constexpr int cls_fre() {
   return (CLS == C_IRR || CLS == C_JM1 || CLS == B_R2 || CLS == B_T2A || CLS == G_MAT1 ||
-          CLS == C_GRU)
+          CLS == C_GRU || CLS == B_GRU)
              ? -1
          : (CLS == C_ITV || CLS == B_T1)                                                 ? 0
                                                                                          : 1;
@@ -159,6 +167,9 @@ __device__ __forceinline__ void cls_wpP(const Params &p, int o, int t, const dou
     case B_R1: w = p.w + ((int64_t)p.n * p.nt + o); P = kp_blk(p, o, t); break;
     case B_R2: w = p.w + ((int64_t)p.n * p.nt + o); P = kp_blk(p, t, o); break;
     case B_R3: w = p.w + ((int64_t)p.n * p.nt + o); P = tv_blk(p, o, t); break;
+    case B_GRL: w = p.w + ((int64_t)p.n * p.nt + o); P = kp_blk(p, o, t); break;
+    case B_GRD: w = p.w + ((int64_t)p.n * p.nt + o); P = p.rdiag + o * E; break;
+    case B_GRU: w = p.w + ((int64_t)p.n * p.nt + o); P = kp_blk(p, t, o); break;
     case B_L:
       w = p.w + ((int64_t)t * p.nt + o);
       P = t > o ? kp_blk(p, t, o) : p.rdiag + o * E;
@@ -210,7 +221,8 @@ __device__ __forceinline__ void range_rt(int cls, const Params &p, int o, int &l
     KBE_CASE(C_IRC) KBE_CASE(C_IRR) KBE_CASE(C_IL) KBE_CASE(C_ITV) KBE_CASE(C_JR) KBE_CASE(C_JM1)
     KBE_CASE(C_JM2) KBE_CASE(B_R1) KBE_CASE(B_R2) KBE_CASE(B_R3) KBE_CASE(B_L) KBE_CASE(B_T1)
     KBE_CASE(B_T2A) KBE_CASE(B_T2B) KBE_CASE(G_MAT1) KBE_CASE(G_MAT2) KBE_CASE(C_GRL)
-    KBE_CASE(C_GRD) KBE_CASE(C_GRU) KBE_CASE(C_GLR)
+    KBE_CASE(C_GRD) KBE_CASE(C_GRU) KBE_CASE(C_GLR) KBE_CASE(B_GRL) KBE_CASE(B_GRD)
+    KBE_CASE(B_GRU)
 #undef KBE_CASE
     default: lo = hi = 0;
   }
@@ -774,6 +786,9 @@ __global__ void __launch_bounds__(256) stream_fused(Params p, FusedPlan pl, char
           KBE_CASE(B_R1) KBE_CASE(B_R2) KBE_CASE(B_R3) KBE_CASE(B_L) KBE_CASE(B_T1)
           KBE_CASE(B_T2A) KBE_CASE(B_T2B) KBE_CASE(G_MAT1) KBE_CASE(G_MAT2)
         }
+        if constexpr (KIND == KIND_GENERIC) {  // the greater form runs on the generic path only
+          switch (pl.cls[k]) { KBE_CASE(B_GRL) KBE_CASE(B_GRD) KBE_CASE(B_GRU) }
+        }
       }
 #undef KBE_CASE
       lds_barrier();  // LDS tiles and range scratch are reused by the next task
@@ -788,7 +803,7 @@ __global__ void zero_heads(unsigned int *heads) {
 // Chunk reduction, all outputs of a call in one launch.  Job j writes out_j[x] (=|+=) the sum,
 // in increasing chunk order, of the chunks of up to three classes' partial arrays that
 // intersect output o's term range; the jobs' elements are laid end to end over the grid.
-constexpr int RED_PARTS = 5;  // classes summed into one output array, at most
+constexpr int RED_PARTS = 8;  // classes summed into one output array, at most
 struct RedJob {
   const kbe_c128 *a[RED_PARTS];
   int cls[RED_PARTS], nchunk[RED_PARTS];
@@ -913,6 +928,50 @@ __global__ void __launch_bounds__(256) grad_generic(Params p, int64_t nblk) {
     s = s + tq.c * x;
   }
   if (!p.overwrite) s = s + ld(dst + e);
+  st(dst + e, s);
+}
+
+// The greater form of Eq. KBE2 reads G^R in I^R (through G^> = G^< + D) and Sigma^R in I^<
+// (through Sigma^> = Sigma^R + Sigma^<), which adds to the lower triangle of kp and to rdiag:
+//   kp[a][b], a > b:  w[a][b] gIL(a)^dag Sigma^R(b)     (a in range; I^<)
+//                    + w[n][a] Sigma^R(a)^dag gIR(b)     (b in range; D = G^R(s,m), s > m)
+//                    - w[n][b] gIR(a)^dag Sigma^R(b)     (a in range; D = -G^R(m,s)^dag, s < m)
+//   rdiag[a]       :  w[a][a] gIL(a)^dag Sigma^R(a)     (a in range; I^<)
+//                    + w[n][a] Sigma^R(a)^dag gIR(a)     (a in range; D = G^R(m,m))
+// These run after grad_generic has written the lesser-form terms of the same blocks; a block
+// that pass left unwritten (no lesser-form term, overwrite mode) is written here instead.
+// Blocks 0 .. (n+1)^2 - 1 are kp (a, b), then rdiag[a].
+__global__ void __launch_bounds__(256) grad_greater(Params p, int64_t nblk) {
+  const int E = p.N * p.N;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t blk = gid / E;
+  if (blk >= nblk) return;
+  const int e = (int)(gid % E), i = e / p.N, j = e % p.N;
+  int kind, a, b;
+  grad_block_index(p, blk, kind, a, b);
+  if (kind == 0 && a <= b) return;  // the upper triangle holds G^<: no new term
+  const int64_t En = bsz(p), wn = (int64_t)p.n * p.nt;
+  const bool ina = a >= p.m0 && a < p.m1, inb = b >= p.m0 && b < p.m1;
+  GT t[3];
+  int nt = 0;
+  if (p.fIL && ina) t[nt++] = GT{{p.w[(int64_t)a * p.nt + b], 0.0}, p.gIL + (a - p.m0) * En, p.ret + b * En};
+  if (kind == 0) {
+    if (p.fIR && inb) t[nt++] = GT{{p.w[wn + a], 0.0}, p.ret + a * En, p.gIR + (b - p.m0) * En};
+    if (p.fIR && ina) t[nt++] = GT{{-p.w[wn + b], 0.0}, p.gIR + (a - p.m0) * En, p.ret + b * En};
+  } else if (p.fIR && ina) {
+    t[nt++] = GT{{p.w[wn + a], 0.0}, p.ret + a * En, p.gIR + (a - p.m0) * En};
+  }
+  if (nt == 0) return;
+  cd s = czero();
+  for (int q = 0; q < nt; ++q) {
+    cd x = czero();
+    for (int k = 0; k < p.N; ++k) x = x + cj(ld(t[q].X + k * p.N + i)) * ld(t[q].Y + k * p.N + j);
+    s = s + t[q].c * x;
+  }
+  GT u0, u1;
+  kbe_c128 *dst;
+  const int before = grad_terms(p, kind, a, b, u0, u1, dst);
+  if (!p.overwrite || before > 0) s = s + ld(dst + e);
   st(dst + e, s);
 }
 
@@ -1309,6 +1368,11 @@ static size_t plan_adjoint(int N, int ntau, int n, int m0, int m1, unsigned flag
   if ((flags & KBE_OUT_IR) && M) {
     plan_add(pl, B_R1, n + 1, m1, E, off);
     plan_add(pl, B_R2, n + 1, m1, E, off);
+    if (flags & KBE_GREATER) {
+      plan_add(pl, B_GRL, n + 1, m1, E, off);
+      plan_add(pl, B_GRD, n + 1, m1, E, off);
+      plan_add(pl, B_GRU, n + 1, m1, E, off);
+    }
   }
   if (fJTV) plan_add(pl, B_R3, n + 1, ntau, E, off);
   if ((flags & KBE_OUT_IL) && M) plan_add(pl, B_L, n + 1, m1, E, off);
@@ -1438,7 +1502,10 @@ hipError_t launch_collision_vjp(const Params &p, unsigned flags, kbe_c128 *gmat,
   // self-energy gradients: overwritten
   RedAll r{};
   r.SC = pl.SC;
-  reduce_into(p, pl, {B_R1, B_R2, B_R3}, w, p.n + 1, gS->ret, false, r);
+  if (flags & KBE_GREATER)  // Sigma^> = Sigma^R + Sigma^< in I^<: its terms also reach gSigma^R
+    reduce_into(p, pl, {B_R1, B_R2, B_R3, B_GRL, B_GRD, B_GRU, B_L}, w, p.n + 1, gS->ret, false, r);
+  else
+    reduce_into(p, pl, {B_R1, B_R2, B_R3}, w, p.n + 1, gS->ret, false, r);
   reduce_into(p, pl, {B_L}, w, p.n + 1, gS->les, false, r);
   if (p.ntau > 0) reduce_into(p, pl, {B_T1, B_T2A, B_T2B}, w, p.ntau, gS->tv, false, r);
   if (p.fJTV) reduce_into(p, pl, {G_MAT1, G_MAT2}, w, p.ntau, gmat, !p.overwrite, r);
@@ -1460,6 +1527,10 @@ hipError_t launch_collision_vjp(const Params &p, unsigned flags, kbe_c128 *gmat,
   } else {
     const int64_t th = nblk * p.N * p.N;
     hipLaunchKernelGGL(grad_generic, dim3((unsigned)((th + 255) / 256)), dim3(256), 0, st, p, nblk);
+    if (flags & KBE_GREATER) {
+      const int64_t nk = n1 * n1 + n1, tk = nk * p.N * p.N;  // kp and rdiag blocks
+      hipLaunchKernelGGL(grad_greater, dim3((unsigned)((tk + 255) / 256)), dim3(256), 0, st, p, nk);
+    }
   }
   return hipGetLastError();
 }

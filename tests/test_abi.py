@@ -323,14 +323,19 @@ def test_sigma_full_argument_errors():
 
 
 def test_greater_form_flag():
-    """KBE_GREATER is a known kbe_collision flag (its workspace differs) and the adjoint rejects it
-    with KBE_ENOTSUP."""
+    """KBE_GREATER is a known flag of kbe_collision and of its adjoint: both size their
+    workspaces for it (extra classes), and both validate the arguments it needs (the Sigma^R row
+    for I^< too)."""
     L = kbe.lib()
     a = L.kbe_collision_workspace(2, 8, 4, 7, 0, 8, kbe.OUT_ALL)
     b = L.kbe_collision_workspace(2, 8, 4, 7, 0, 8, kbe.OUT_ALL | kbe.GREATER)
     assert b > a > 0
-    G, S, W = green(), row(), wts()
+    a = L.kbe_collision_vjp_workspace(2, 8, 4, 7, 0, 8, kbe.OUT_ALL)
+    b = L.kbe_collision_vjp_workspace(2, 8, 4, 7, 0, 8, kbe.OUT_ALL | kbe.GREATER)
+    assert b > a > 0
+    G, W = green(), wts()
+    S = kbe._Row(None, FAKE, FAKE)  # no Sigma^R row: the greater form's I^< needs it
     st = L.kbe_collision_vjp(ctypes.byref(G), ctypes.byref(S), ctypes.byref(W), 7, 0, 8,
-                             kbe.OUT_ALL | kbe.GREATER, FAKE, FAKE, FAKE, FAKE,
+                             kbe.OUT_IL | kbe.GREATER, FAKE, FAKE, FAKE, FAKE,
                              ctypes.byref(green()), ctypes.byref(row()), FAKE, 1 << 40, None)
-    assert st == 5 and "greater" in err()
+    assert st == 1 and "ret" in err()

@@ -73,6 +73,50 @@ def test_collision_vjp_matches_oracle(gpu, N, nt, ntau, m0, m1, flags, generic):
         assert rel(to_host(g), r) < RTOL, name
 
 
+@pytest.mark.parametrize("N,nt,ntau,m0,m1,flags", [
+    (3, 40, 8, 0, 40, oracle.F_ALL),
+    (16, 60, 8, 10, 50, oracle.F_ALL),
+    (8, 50, 6, 0, 50, oracle.F_IR | oracle.F_IL),
+    (5, 30, 0, 4, 25, oracle.F_IR),
+    (2, 30, 6, 0, 30, oracle.F_IL | oracle.F_ITV),
+    (1, 70, 4, 7, 64, oracle.F_ALL),
+])
+def test_greater_form_vjp_matches_oracle(gpu, N, nt, ntau, m0, m1, flags):
+    """kbe_collision_vjp with KBE_GREATER (vector-ALU kernels) against the oracle's adjoint of
+    the greater form, every gradient array, accumulate mode."""
+    kbe = gpu
+    print("greater vjp", N, nt, ntau, m0, m1, flags, flush=True)
+    case = Case(N=N, nt=nt, ntau=ntau, beta=3.0 if ntau else 0.0, seed=60 + N)
+    ref, (gG, gs), _ = vjp_case(kbe, case, m0, m1, flags | oracle.F_GREATER)
+    names = ["gkp", "grdiag", "gtv", "gmat", "gret", "gles", "gstv"]
+    got = [gG.kp, gG.rdiag, gG.tv, gG.mat, gs[0], gs[1], gs[2]]
+    for name, g, r in zip(names, got, ref):
+        if r.size == 0:
+            continue
+        assert rel(to_host(g), r) < RTOL, name
+
+
+@pytest.mark.parametrize("N", [4, 16])
+def test_greater_form_vjp_overwrite_mode(gpu, N):
+    """Overwrite mode with KBE_GREATER and I^R alone: the forward reads row m and column m of kp
+    and rdiag[m] for m in the range (G^> assembled from both triangles); exactly those blocks are
+    overwritten, including the lower-triangle ones that only the greater form's terms reach."""
+    kbe = gpu
+    nt, m0, m1 = 30, 10, 20
+    case = Case(N=N, nt=nt, ntau=6, beta=2.0, seed=9)
+    flags = oracle.F_IR | oracle.F_GREATER
+    ref, (gG, _), base = vjp_case(kbe, case, m0, m1, flags, kbe.GRAD_OVERWRITE)
+    read = np.zeros((nt, nt), bool)
+    read[:, m0:m1] = True
+    read[m0:m1, :] = True
+    rd_read = np.zeros(nt, bool)
+    rd_read[m0:m1] = True
+    want_kp = np.where(read[:, :, None, None], ref[0] - base[0], base[0])
+    want_rd = np.where(rd_read[:, None, None], ref[1] - base[1], base[1])
+    assert rel(to_host(gG.kp), want_kp) < RTOL
+    assert rel(to_host(gG.rdiag), want_rd) < RTOL
+
+
 def test_collision_vjp_overwrite_mode(gpu):
     """KBE_GRAD_OVERWRITE writes exactly the blocks the forward reads (here: all of [0,n]^2 and
     tv rows 0..n) and leaves the rest of the arrays as they were."""
@@ -119,10 +163,11 @@ def test_sigma_vjp_matches_oracle(gpu, N, n):
     assert rel(to_host(gu), ru) < 1e-12
 
 
-def test_autograd_wrappers_and_finite_differences(gpu):
+@pytest.mark.parametrize("greater", [False, True])
+def test_autograd_wrappers_and_finite_differences(gpu, greater):
     """Loss = Re sum c * (IR + IL + Itv) at the last rows, through Sigma = second Born(G, U):
     torch autograd over the two Functions equals the oracle's chained adjoint, and dL/dU agrees
-    with a central finite difference (h = 1e-6) of the GPU forward."""
+    with a central finite difference (h = 1e-6) of the GPU forward; lesser and greater form."""
     import torch
     kbe = gpu
     case = Case(N=8, nt=60, ntau=12, beta=3.0, seed=70)
@@ -137,7 +182,7 @@ def test_autograd_wrappers_and_finite_differences(gpu):
         u = U * torch.ones(8, dtype=torch.float64, device="cuda")
         ret, les, stv = kbe.KBESigma2B.apply(kp_t, to_dev(rd), to_dev(tv), to_dev(mat), u, n)
         outs = kbe.KBECollision.apply(kp_t, to_dev(rd), to_dev(tv), to_dev(mat), ret, les, stv,
-                                      Wd, n, m0, m1)
+                                      Wd, n, m0, m1, greater)
         return sum(torch.real(torch.sum(torch.conj(c) * o)) for c, o in zip(ct, outs))
 
     U = torch.tensor(1.7, dtype=torch.float64, device="cuda", requires_grad=True)
@@ -148,8 +193,9 @@ def test_autograd_wrappers_and_finite_differences(gpu):
     Go = oracle.Green(kp, rd, tv, mat)
     u = np.full(8, 1.7)
     sig = oracle.sigma_row(Go, u, n)
-    gk, _, _, _, gret, gles, gstv = oracle.collision_vjp(Go, sig, W, n, m0, m1, cot)
-    gk2, _, _, gu = oracle.sigma_row_vjp(Go, u, n, (gret, gles, gstv), grads=(gk, np.zeros_like(rd),
+    flags = oracle.F_ALL | (oracle.F_GREATER if greater else 0)
+    gk, grd, _, _, gret, gles, gstv = oracle.collision_vjp(Go, sig, W, n, m0, m1, cot, flags)
+    gk2, _, _, gu = oracle.sigma_row_vjp(Go, u, n, (gret, gles, gstv), grads=(gk, grd.copy(),
                                                                              np.zeros_like(tv)))
     assert rel(to_host(kp_t.grad), gk2) < 1e-12
     assert abs(U.grad.item() - gu.sum()) < 1e-12 * abs(gu.sum())
