@@ -1172,7 +1172,7 @@ grad_mfma16(Params p, int row_len, int nseg) {
 //   D[b][i][j] = out[4 ti + i][4 tj + j]      at lane 4b + j + 16i,
 // so lanes 8r .. 8r+7 of a store hold a whole row of the block (128 contiguous bytes at N = 8).
 // Work split, records, prefetch and streaming stores as in grad_mfma16.
-constexpr int GSEG8 = 128;  // blocks per workgroup segment
+constexpr int GSEG8 = 64;   // blocks per workgroup segment (64 beat 32, 128 and 256)
 constexpr int XLD8 = 9;     // LDS row stride of a staged 8x8 block, in complex numbers
 
 __global__ void __launch_bounds__(256) grad_mfma8(Params p, int row_len, int nseg) {
