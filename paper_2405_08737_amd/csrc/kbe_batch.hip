@@ -268,6 +268,66 @@ __device__ void task8(const kbe_batch_item &it, int k, int t0, int t1, kbe_c128 
 }
 
 // ---------------------------------------------------------------------------------------
+// N = 16: v_mfma_f64_16x16x4 with both operands loaded straight into their lane layouts, no
+// LDS: lane l supplies A[l%16][4kc + l/16] = c Q[l%16][4kc + l/16] and B[4kc + l/16][l%16], which
+// is P[4kc + l/16][l%16] (Q P) or conj P[l%16][4kc + l/16] (Q P^dagger), and holds
+// D[l/16 + 4r][l%16].  Three real products per complex one; three terms in flight.
+// ---------------------------------------------------------------------------------------
+__device__ void task16d(const kbe_batch_item &it, int k, int t0, int t1, kbe_c128 *out,
+                        int lane) {
+  const bool dag = k != 0;
+  const int lk = lane >> 4, lc = lane & 15;
+  struct Buf {
+    double w;
+    cd q[4], x[4];
+  };
+  auto load = [&](int t, Buf &b) {
+    t = t < t1 ? t : t1 - 1;
+    const Term tm = item_term(it, k, t);
+    b.w = tm.w;
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) {
+      b.q[kc] = ldg(tm.Q + lc * 16 + 4 * kc + lk);
+      b.x[kc] = ldg(tm.P + (dag ? lc * 16 + 4 * kc + lk : (4 * kc + lk) * 16 + lc));
+    }
+  };
+  d4b k1 = {0, 0, 0, 0}, k2 = {0, 0, 0, 0}, k3 = {0, 0, 0, 0};
+  auto compute = [&](const Buf &b) {
+    const cd c = class_factor(k, b.w);
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) {
+      const cd a = c * b.q[kc];
+      cd x = b.x[kc];
+      if (dag) x.im = -x.im;
+      k1 = mfma16b(a.re + a.im, x.re, k1);
+      k2 = mfma16b(a.re, x.im - x.re, k2);
+      k3 = mfma16b(a.im, x.re + x.im, k3);
+    }
+  };
+  Buf b0, b1, b2;
+  load(t0, b0);
+  load(t0 + 1, b1);
+  for (int t = t0; t < t1; t += 3) {
+    load(t + 2, b2);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(b0);
+    __builtin_amdgcn_sched_barrier(0);
+    if (t + 1 >= t1) break;  // wave-uniform
+    load(t + 3, b0);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(b1);
+    __builtin_amdgcn_sched_barrier(0);
+    if (t + 2 >= t1) break;
+    load(t + 4, b1);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(b2);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) stg(out + (lk + 4 * r) * 16 + lc, cd{k1[r] - k3[r], k1[r] + k2[r]});
+}
+
+// ---------------------------------------------------------------------------------------
 // 9 <= N <= 16: blocks padded to 16 x 16, the layout of the N = 16 collision task: the wave
 // stages c Q in its own LDS tile (rows padded to BQLD complex numbers), lane l supplies
 // A[4ti + l%4][4kc + l/16] from it and the slab B[4kc + l/16][l%16] of P (or P^dagger), and
@@ -465,7 +525,7 @@ __global__ void __launch_bounds__(1024) batch_plan(const Item *items, int count,
 }
 
 // Persistent: every wave takes tasks from the counter until none are left.
-__global__ void __launch_bounds__(256) batch_stream(const kbe_batch_item *items, int count,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) batch_stream(const kbe_batch_item *items, int count,
                                                     int chunk, const int *perm,
                                                     const int64_t *tb, const int64_t *pb,
                                                     kbe_c128 *parts, unsigned int *head) {
@@ -513,6 +573,7 @@ __global__ void __launch_bounds__(256) batch_stream(const kbe_batch_item *items,
       case 4: task_tiny<4>(it, k, t0, t1, out, lane); break;
       default:
         if (it.N <= 8) task8(it, k, t0, t1, out, lane);
+        else if (it.N == 16) task16d(it, k, t0, t1, out, lane);
         else task16(it, k, t0, t1, out, lane, qtile[wave]);
     }
   }
