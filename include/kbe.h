@@ -98,10 +98,11 @@ typedef enum {
                                      of G^<(t_s,t_m), assembled from both triangles, and I^< with
                                      Sigma^> = Sigma^R + Sigma^< (from the same self-energy row)
                                      in place of Sigma^<; I^] and J^] are the same in both forms.
-                                     Runs on the vector-ALU kernels, in kbe_collision and in its
-                                     adjoint kbe_collision_vjp (whose gradients then also reach
-                                     G^R through G^> and Sigma^R through Sigma^>).  The batch
-                                     calls reject it (KBE_EINVAL). */
+                                     Supported by kbe_collision and its adjoint
+                                     kbe_collision_vjp (whose gradients then also reach G^R
+                                     through G^> and Sigma^R through Sigma^>), on the same kernels
+                                     as the lesser form plus extra term classes.  The batch calls
+                                     reject it (KBE_EINVAL). */
 
 /* One Keldysh function on the grid (G, or a gradient with the same shape). */
 typedef struct {

@@ -71,7 +71,9 @@ __host__ __device__ constexpr int cls_op() {
              : ((CLS == G_MAT1 || CLS == G_MAT2) ? OP_HN : OP_N);
 }
 
-// Term-index range [lo, hi) of output o.
+// Term-index range [lo, hi) of output o.  Empty ranges too stay inside the indices for which the
+// class's shared operand exists: the workgroup tasks stage that operand for every term of the
+// union of their outputs' ranges.
 template <int CLS>
 __device__ __forceinline__ void cls_range(const Params &p, int o, int &lo, int &hi) {
   const int m = p.m0 + o;
@@ -97,7 +99,10 @@ __device__ __forceinline__ void cls_range(const Params &p, int o, int &lo, int &
     case G_MAT1: lo = 0; hi = o + 1; break;       // output k, terms l <= k
     case G_MAT2: lo = o; hi = p.ntau; break;      // output k, terms l >= k
     case B_GRL: lo = p.m0; hi = o < p.m1 ? o : p.m1; break;            // terms m < s
-    case B_GRD: lo = o; hi = (o >= p.m0 && o < p.m1) ? o + 1 : o; break;  // m = s
+    case B_GRD:  // m = s; an empty range stays inside [m0, m1), where the shared operand exists
+      lo = (o >= p.m0 && o < p.m1) ? o : p.m0;
+      hi = (o >= p.m0 && o < p.m1) ? o + 1 : p.m0;
+      break;
     case B_GRU: lo = o + 1 > p.m0 ? o + 1 : p.m0; hi = p.m1; break;     // terms m > s
   }
 }
@@ -778,17 +783,13 @@ __global__ void __launch_bounds__(256) stream_fused(Params p, FusedPlan pl, char
           KBE_CASE(C_IRC) KBE_CASE(C_IRR) KBE_CASE(C_IL) KBE_CASE(C_ITV) KBE_CASE(C_JR)
           KBE_CASE(C_JM1) KBE_CASE(C_JM2)
         }
-        if constexpr (KIND == KIND_GENERIC) {  // the greater form runs on the generic path only
-          switch (pl.cls[k]) { KBE_CASE(C_GRL) KBE_CASE(C_GRD) KBE_CASE(C_GRU) KBE_CASE(C_GLR) }
-        }
+        switch (pl.cls[k]) { KBE_CASE(C_GRL) KBE_CASE(C_GRD) KBE_CASE(C_GRU) KBE_CASE(C_GLR) }
       } else {
         switch (pl.cls[k]) {
           KBE_CASE(B_R1) KBE_CASE(B_R2) KBE_CASE(B_R3) KBE_CASE(B_L) KBE_CASE(B_T1)
           KBE_CASE(B_T2A) KBE_CASE(B_T2B) KBE_CASE(G_MAT1) KBE_CASE(G_MAT2)
         }
-        if constexpr (KIND == KIND_GENERIC) {  // the greater form runs on the generic path only
-          switch (pl.cls[k]) { KBE_CASE(B_GRL) KBE_CASE(B_GRD) KBE_CASE(B_GRU) }
-        }
+        switch (pl.cls[k]) { KBE_CASE(B_GRL) KBE_CASE(B_GRD) KBE_CASE(B_GRU) }
       }
 #undef KBE_CASE
       lds_barrier();  // LDS tiles and range scratch are reused by the next task
@@ -1282,7 +1283,7 @@ __global__ void __launch_bounds__(256) grad_mfma8(Params p, int row_len, int nse
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 static int path_kind(int N, unsigned flags) {
-  if (flags & (KBE_FORCE_GENERIC | KBE_GREATER)) return KIND_GENERIC;
+  if (flags & KBE_FORCE_GENERIC) return KIND_GENERIC;
   if (N == 16) return KIND_MFMA;
   return N <= 8 ? N : KIND_GENERIC;
 }
@@ -1527,10 +1528,10 @@ hipError_t launch_collision_vjp(const Params &p, unsigned flags, kbe_c128 *gmat,
   } else {
     const int64_t th = nblk * p.N * p.N;
     hipLaunchKernelGGL(grad_generic, dim3((unsigned)((th + 255) / 256)), dim3(256), 0, st, p, nblk);
-    if (flags & KBE_GREATER) {
-      const int64_t nk = n1 * n1 + n1, tk = nk * p.N * p.N;  // kp and rdiag blocks
-      hipLaunchKernelGGL(grad_greater, dim3((unsigned)((tk + 255) / 256)), dim3(256), 0, st, p, nk);
-    }
+  }
+  if (flags & KBE_GREATER) {  // after any of the three: it adds to what they wrote
+    const int64_t nk = n1 * n1 + n1, tk = nk * p.N * p.N;  // kp and rdiag blocks
+    hipLaunchKernelGGL(grad_greater, dim3((unsigned)((tk + 255) / 256)), dim3(256), 0, st, p, nk);
   }
   return hipGetLastError();
 }
