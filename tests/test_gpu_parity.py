@@ -320,10 +320,13 @@ def test_sigma_full_mode_matches_oracle(gpu, N, nt, ntau, sldt):
 
 
 @pytest.mark.parametrize("N,nt,ntau,mr", [(1, 20, 6, None), (3, 25, 0, (4, 17)), (8, 18, 5, None),
-                                          (16, 14, 4, (0, 9))])
+                                          (16, 14, 4, (0, 9)), (16, 300, 17, None),
+                                          (16, 280, 9, (30, 270)), (8, 300, 20, (7, 290)),
+                                          (5, 140, 6, None)])
 def test_greater_form_matches_oracle(gpu, N, nt, ntau, mr):
-    """kbe_collision with KBE_GREATER (generic kernels) against the oracle's greater form, all
-    outputs, whole and partial m-ranges."""
+    """kbe_collision with KBE_GREATER against the oracle's greater form, all outputs, whole and
+    partial m-ranges, on the lesser form's kernels (MFMA task at N = 16, small-block tasks at
+    N <= 8, generic otherwise) over one and several 256-term chunks."""
     kbe = gpu
     case = Case(N=N, nt=nt, ntau=ntau, beta=4.0, seed=800 + N)
     t, order, kp, rd, tv, mat = case.host()

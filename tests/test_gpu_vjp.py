@@ -80,6 +80,9 @@ def test_collision_vjp_matches_oracle(gpu, N, nt, ntau, m0, m1, flags, generic):
     (5, 30, 0, 4, 25, oracle.F_IR),
     (2, 30, 6, 0, 30, oracle.F_IL | oracle.F_ITV),
     (1, 70, 4, 7, 64, oracle.F_ALL),
+    (16, 300, 17, 0, 300, oracle.F_ALL),
+    (16, 280, 9, 30, 270, oracle.F_ALL),
+    (8, 300, 20, 7, 290, oracle.F_ALL),
 ])
 def test_greater_form_vjp_matches_oracle(gpu, N, nt, ntau, m0, m1, flags):
     """kbe_collision_vjp with KBE_GREATER (vector-ALU kernels) against the oracle's adjoint of
