@@ -1029,12 +1029,58 @@ __device__ __forceinline__ int grad_row_terms(const Params &p, int a, int j, Gra
   return nt;
 }
 
+// The greater form's extra terms (those grad_greater adds on the generic path), in two sets of
+// at most two terms, for grad_mfma16<1> and grad_mfma16<2>; X ids as above (0 Sigma^R(a), 1
+// gIR(a), 2 gIL(a)):
+//   set 1, kp[a][b] a > b:  w[a][b] gIL(a)^dag Sigma^R(b),   w[n][a] Sigma^R(a)^dag gIR(b)
+//          rdiag[a]      :  w[a][a] gIL(a)^dag Sigma^R(a),   w[n][a] Sigma^R(a)^dag gIR(a)
+//   set 2, kp[a][b] a > b: -w[n][b] gIR(a)^dag Sigma^R(b)
+template <int TS>
+__device__ __forceinline__ int grad_row_terms_gr(const Params &p, int a, int j, GradTerm &t0,
+                                                 GradTerm &t1, kbe_c128 *&dst) {
+  const int64_t E = bsz(p);
+  const int n1 = p.n + 1;
+  const bool ina = a >= p.m0 && a < p.m1;
+  const int64_t wn = (int64_t)p.n * p.nt;
+  t0.xid = t1.xid = -1;
+  t0.Y = t1.Y = p.ret;
+  t0.c = t1.c = czero();
+  int nt = 0;
+  auto push = [&](int xid, cd c, const kbe_c128 *Y) {
+    if (nt == 0) t0 = GradTerm{xid, c, Y};
+    else t1 = GradTerm{xid, c, Y};
+    ++nt;
+  };
+  dst = p.gkp;
+  if (j < n1) {
+    const int b = j;
+    const bool inb = b >= p.m0 && b < p.m1;
+    dst = p.gkp + ((int64_t)a * p.ldt + b) * E;
+    if (a > b) {
+      if (TS == 1) {
+        if (p.fIL && ina) push(2, cd{p.w[(int64_t)a * p.nt + b], 0.0}, p.ret + b * E);
+        if (p.fIR && inb) push(0, cd{p.w[wn + a], 0.0}, p.gIR + (b - p.m0) * E);
+      } else if (p.fIR && ina) {
+        push(1, cd{-p.w[wn + b], 0.0}, p.ret + b * E);
+      }
+    }
+  } else if (j >= n1 + p.ntau) {
+    dst = p.grdiag + a * E;
+    if (TS == 1) {
+      if (p.fIL && ina) push(2, cd{p.w[(int64_t)a * p.nt + a], 0.0}, p.ret + a * E);
+      if (p.fIR && ina) push(0, cd{p.w[wn + a], 0.0}, p.gIR + (a - p.m0) * E);
+    }
+  }
+  return nt;
+}
+
 // Per-block term record of a segment, built once per workgroup in LDS.
 struct GradRec {
   const kbe_c128 *y0, *y1;  // Y of term 0 and term 1 (term 0's Y again when there is one term)
   kbe_c128 *dst;
   double c0r, c0i, c1r, c1i;  // scalars (term 1's are 0 when there is one term)
-  int x0, x1, nt, pad;
+  int x0, x1, nt;
+  int acc;  // add the block's current value (accumulate mode, or a block an earlier pass wrote)
 };
 
 __device__ __forceinline__ const kbe_c128 *uniform_ptr(const kbe_c128 *q) {
@@ -1049,6 +1095,9 @@ __device__ __forceinline__ d4g mfma16f(double a, double b, d4g c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// TS = 0: the terms of both forms' common part (grad_row_terms); TS = 1, 2: the greater form's
+// extra terms (grad_row_terms_gr), run after TS = 0 and adding to what earlier passes wrote.
+template <int TS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 grad_mfma16(Params p, int row_len, int nseg) {
   __shared__ cd xs[4][16 * QLD];
@@ -1076,7 +1125,19 @@ grad_mfma16(Params p, int row_len, int nseg) {
   if (tid < GSEG) {
     GradTerm t0{-1, czero(), p.ret}, t1 = t0;
     kbe_c128 *d = p.gkp;
-    const int nt = tid < len ? grad_row_terms(p, a, j0 + tid, t0, t1, d) : 0;
+    int nt = 0, acc = !p.overwrite;
+    if (tid < len) {
+      if constexpr (TS == 0) {
+        nt = grad_row_terms(p, a, j0 + tid, t0, t1, d);
+      } else {
+        nt = grad_row_terms_gr<TS>(p, a, j0 + tid, t0, t1, d);
+        GradTerm u0, u1;
+        kbe_c128 *dd;
+        int before = grad_row_terms(p, a, j0 + tid, u0, u1, dd);
+        if (TS == 2) before += grad_row_terms_gr<1>(p, a, j0 + tid, u0, u1, dd);
+        acc = acc || before > 0;
+      }
+    }
     GradRec &g = rec[tid];
     g.y0 = t0.Y;
     g.y1 = nt > 1 ? t1.Y : t0.Y;
@@ -1088,6 +1149,7 @@ grad_mfma16(Params p, int row_len, int nseg) {
     g.x0 = t0.xid < 0 ? 0 : t0.xid;
     g.x1 = nt > 1 ? t1.xid : 0;
     g.nt = nt;
+    g.acc = acc;
   }
   __syncthreads();
   cd yn0[4], yn1[4];  // raw Y slabs of the block after the current one
@@ -1105,10 +1167,15 @@ grad_mfma16(Params p, int row_len, int nseg) {
   // the next block, so each wave's stores spread over its products instead of a burst.
   cd prev[4];
   kbe_c128 *pdst = nullptr;
+  int pacc = 0;
   auto put = [&](int r) {  // rows l/16 + 4 r of the held result
     kbe_c128 *d = pdst + (lk + 4 * r) * 16 + lc;
     cd v = prev[r];
-    if (!p.overwrite) v = v + ldg(d);
+    if constexpr (TS == 0) {
+      if (!p.overwrite) v = v + ldg(d);
+    } else if (pacc) {
+      v = v + ldg(d);
+    }
     dvec2 w;
     w.x = v.re;
     w.y = v.im;
@@ -1158,6 +1225,7 @@ grad_mfma16(Params p, int row_len, int nseg) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) prev[r] = cd{k1[r] + k3[r], k1[r] + k2[r]};
     pdst = cdst;
+    if constexpr (TS != 0) pacc = __builtin_amdgcn_readfirstlane(rec[q].acc);
   }
   if (pdst) {
 #pragma unroll
@@ -1518,8 +1586,14 @@ hipError_t launch_collision_vjp(const Params &p, unsigned flags, kbe_c128 *gmat,
   if (mfma) {
     const int nseg = (row_len + GSEG - 1) / GSEG;
     const int64_t tasks = (int64_t)(p.n + 1) * nseg;
-    hipLaunchKernelGGL(grad_mfma16, dim3((unsigned)(8 * ((tasks + 7) / 8))), dim3(256), 0, st,
+    hipLaunchKernelGGL(grad_mfma16<0>, dim3((unsigned)(8 * ((tasks + 7) / 8))), dim3(256), 0, st,
                        p, row_len, nseg);
+    if (flags & KBE_GREATER) {  // the greater form's extra terms, in two more passes
+      hipLaunchKernelGGL(grad_mfma16<1>, dim3((unsigned)(8 * ((tasks + 7) / 8))), dim3(256), 0,
+                         st, p, row_len, nseg);
+      hipLaunchKernelGGL(grad_mfma16<2>, dim3((unsigned)(8 * ((tasks + 7) / 8))), dim3(256), 0,
+                         st, p, row_len, nseg);
+    }
   } else if (kind >= 5 && kind <= 8) {
     const int nseg = (row_len + GSEG8 - 1) / GSEG8;
     const int64_t tasks = (int64_t)(p.n + 1) * nseg;
@@ -1529,7 +1603,7 @@ hipError_t launch_collision_vjp(const Params &p, unsigned flags, kbe_c128 *gmat,
     const int64_t th = nblk * p.N * p.N;
     hipLaunchKernelGGL(grad_generic, dim3((unsigned)((th + 255) / 256)), dim3(256), 0, st, p, nblk);
   }
-  if (flags & KBE_GREATER) {  // after any of the three: it adds to what they wrote
+  if ((flags & KBE_GREATER) && !mfma) {  // after the gradient kernel: adds to what it wrote
     const int64_t nk = n1 * n1 + n1, tk = nk * p.N * p.N;  // kp and rdiag blocks
     hipLaunchKernelGGL(grad_greater, dim3((unsigned)((tk + 255) / 256)), dim3(256), 0, st, p, nk);
   }
