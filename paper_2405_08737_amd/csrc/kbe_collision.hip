@@ -1244,6 +1244,8 @@ grad_mfma16(Params p, int row_len, int nseg) {
 constexpr int GSEG8 = 64;   // blocks per workgroup segment (64 beat 32, 128 and 256)
 constexpr int XLD8 = 9;     // LDS row stride of a staged 8x8 block, in complex numbers
 
+// TS as in grad_mfma16: 0 the common terms, 1 and 2 the greater form's extra terms.
+template <int TS>
 __global__ void __launch_bounds__(256) grad_mfma8(Params p, int row_len, int nseg) {
   __shared__ cd xs[4][8 * XLD8];
   __shared__ GradRec rec[GSEG8];
@@ -1269,7 +1271,19 @@ __global__ void __launch_bounds__(256) grad_mfma8(Params p, int row_len, int nse
   if (tid < GSEG8) {
     GradTerm t0{-1, czero(), p.ret}, t1 = t0;
     kbe_c128 *d = p.gkp;
-    const int nt = tid < len ? grad_row_terms(p, a, j0 + tid, t0, t1, d) : 0;
+    int nt = 0, acc = !p.overwrite;
+    if (tid < len) {
+      if constexpr (TS == 0) {
+        nt = grad_row_terms(p, a, j0 + tid, t0, t1, d);
+      } else {
+        nt = grad_row_terms_gr<TS>(p, a, j0 + tid, t0, t1, d);
+        GradTerm u0, u1;
+        kbe_c128 *dd;
+        int before = grad_row_terms(p, a, j0 + tid, u0, u1, dd);
+        if (TS == 2) before += grad_row_terms_gr<1>(p, a, j0 + tid, u0, u1, dd);
+        acc = acc || before > 0;
+      }
+    }
     GradRec &g = rec[tid];
     g.y0 = t0.Y;
     g.y1 = nt > 1 ? t1.Y : t0.Y;
@@ -1281,6 +1295,7 @@ __global__ void __launch_bounds__(256) grad_mfma8(Params p, int row_len, int nse
     g.x0 = t0.xid < 0 ? 0 : t0.xid;
     g.x1 = nt > 1 ? t1.xid : 0;
     g.nt = nt;
+    g.acc = acc;
   }
   __syncthreads();
   const int lj = lane & 3, lb = (lane >> 2) & 3, lk = lane >> 4;
@@ -1335,7 +1350,11 @@ __global__ void __launch_bounds__(256) grad_mfma8(Params p, int row_len, int nse
     cd r{k1 + k3, k1 + k2};
     if (dv) {
       kbe_c128 *d = cdst + dof;
-      if (!p.overwrite) r = r + ldg(d);
+      if constexpr (TS == 0) {
+        if (!p.overwrite) r = r + ldg(d);
+      } else if (__builtin_amdgcn_readfirstlane(rec[q].acc)) {
+        r = r + ldg(d);
+      }
       dvec2 w;
       w.x = r.re;
       w.y = r.im;
@@ -1597,13 +1616,19 @@ hipError_t launch_collision_vjp(const Params &p, unsigned flags, kbe_c128 *gmat,
   } else if (kind >= 5 && kind <= 8) {
     const int nseg = (row_len + GSEG8 - 1) / GSEG8;
     const int64_t tasks = (int64_t)(p.n + 1) * nseg;
-    hipLaunchKernelGGL(grad_mfma8, dim3((unsigned)(8 * ((tasks + 7) / 8))), dim3(256), 0, st,
+    hipLaunchKernelGGL(grad_mfma8<0>, dim3((unsigned)(8 * ((tasks + 7) / 8))), dim3(256), 0, st,
                        p, row_len, nseg);
+    if (flags & KBE_GREATER) {  // the greater form's extra terms, in two more passes
+      hipLaunchKernelGGL(grad_mfma8<1>, dim3((unsigned)(8 * ((tasks + 7) / 8))), dim3(256), 0,
+                         st, p, row_len, nseg);
+      hipLaunchKernelGGL(grad_mfma8<2>, dim3((unsigned)(8 * ((tasks + 7) / 8))), dim3(256), 0,
+                         st, p, row_len, nseg);
+    }
   } else {
     const int64_t th = nblk * p.N * p.N;
     hipLaunchKernelGGL(grad_generic, dim3((unsigned)((th + 255) / 256)), dim3(256), 0, st, p, nblk);
   }
-  if ((flags & KBE_GREATER) && !mfma) {  // after the gradient kernel: adds to what it wrote
+  if ((flags & KBE_GREATER) && !mfma && !(kind >= 5 && kind <= 8)) {  // adds to what it wrote
     const int64_t nk = n1 * n1 + n1, tk = nk * p.N * p.N;  // kp and rdiag blocks
     hipLaunchKernelGGL(grad_greater, dim3((unsigned)((tk + 255) / 256)), dim3(256), 0, st, p, nk);
   }
