@@ -49,11 +49,11 @@ enum Cls {
   G_MAT1,  // adjoint: gG^M(k) from C_JM1 terms
   G_MAT2,  // adjoint: gG^M(k) from C_JM2 terms
   // the greater form (KBE_GREATER): G^>(s,m) = G^<(s,m) + D(s,m) in I^R, with D(s,m) = G^R(s,m)
-  // for s > m, G^R(m,m) at s = m and -G^R(m,s)^dagger for s < m; Sigma^> = Sigma^R + Sigma^< in I^<
+  // for s > m, G^R(m,m) at s = m and -G^R(m,s)^dagger for s < m; in I^<, C_IL reads a
+  // Sigma^> = Sigma^R + Sigma^< row formed once in the workspace
   C_GRL,   // I^R, s > m :  w[n][s] Sigma^R(s) kp[s][m]
   C_GRD,   // I^R, s = m :  w[n][m] Sigma^R(m) rdiag[m]
   C_GRU,   // I^R, s < m : -w[n][s] Sigma^R(s) kp[m][s]^dagger
-  C_GLR,   // I^<, s <= m:  w[m][s] Sigma^R(s) G^R(m,s)^dagger
   // adjoint of the greater form: gSigma^R(s) from the D parts of C_GRL, C_GRD, C_GRU
   B_GRL,   // s > m:  w[n][s] gIR(m) kp[s][m]^dagger
   B_GRD,   // s = m:  w[n][s] gIR(s) rdiag[s]^dagger
@@ -65,7 +65,7 @@ enum Op { OP_N = 0, OP_H = 1, OP_HN = 2 };
 template <int CLS>
 __host__ __device__ constexpr int cls_op() {
   return (CLS == C_IRR || CLS == C_IL || CLS == C_ITV || CLS == B_R1 || CLS == B_R3 ||
-          CLS == B_T2A || CLS == B_T2B || CLS == C_GRU || CLS == C_GLR || CLS == B_GRL ||
+          CLS == B_T2A || CLS == B_T2B || CLS == C_GRU || CLS == B_GRL ||
           CLS == B_GRD)
              ? OP_H
              : ((CLS == G_MAT1 || CLS == G_MAT2) ? OP_HN : OP_N);
@@ -84,7 +84,6 @@ __device__ __forceinline__ void cls_range(const Params &p, int o, int &lo, int &
     case C_GRL: lo = m + 1; hi = p.n + 1; break;
     case C_GRD: lo = m; hi = m + 1; break;
     case C_GRU: lo = 0; hi = m; break;
-    case C_GLR: lo = 0; hi = m + 1; break;
     case C_ITV: lo = 0; hi = p.ntau; break;
     case C_JR: lo = 0; hi = p.n + 1; break;
     case C_JM1: lo = 0; hi = o + 1; break;        // l <= j
@@ -112,7 +111,7 @@ template <int CLS>
 __device__ __forceinline__ const kbe_c128 *cls_Q(const Params &p, int t) {
   const int64_t E = bsz(p);
   switch (CLS) {
-    case C_IRC: case C_IRR: case C_JR: case C_GRL: case C_GRD: case C_GRU: case C_GLR:
+    case C_IRC: case C_IRR: case C_JR: case C_GRL: case C_GRD: case C_GRU:
       return p.ret + t * E;
     case C_IL: return p.les + t * E;
     case C_ITV: case C_JM1: case C_JM2: case G_MAT1: case G_MAT2: return p.stv + t * E;
@@ -156,10 +155,6 @@ __device__ __forceinline__ void cls_wpP(const Params &p, int o, int t, const dou
     case C_GRL: w = p.w + ((int64_t)p.n * p.nt + t); P = kp_blk(p, t, m); break;
     case C_GRD: w = p.w + ((int64_t)p.n * p.nt + t); P = p.rdiag + m * E; break;
     case C_GRU: w = p.w + ((int64_t)p.n * p.nt + t); P = kp_blk(p, m, t); break;
-    case C_GLR:
-      w = p.w + ((int64_t)m * p.nt + t);
-      P = t < m ? kp_blk(p, m, t) : p.rdiag + m * E;
-      break;
     case C_JR: w = p.w + ((int64_t)p.n * p.nt + t); P = tv_blk(p, t, o); break;
     case C_JM1:  // l = t <= j = o
       w = p.wf + ((int64_t)o * p.ntau + t);
@@ -226,7 +221,7 @@ __device__ __forceinline__ void range_rt(int cls, const Params &p, int o, int &l
     KBE_CASE(C_IRC) KBE_CASE(C_IRR) KBE_CASE(C_IL) KBE_CASE(C_ITV) KBE_CASE(C_JR) KBE_CASE(C_JM1)
     KBE_CASE(C_JM2) KBE_CASE(B_R1) KBE_CASE(B_R2) KBE_CASE(B_R3) KBE_CASE(B_L) KBE_CASE(B_T1)
     KBE_CASE(B_T2A) KBE_CASE(B_T2B) KBE_CASE(G_MAT1) KBE_CASE(G_MAT2) KBE_CASE(C_GRL)
-    KBE_CASE(C_GRD) KBE_CASE(C_GRU) KBE_CASE(C_GLR) KBE_CASE(B_GRL) KBE_CASE(B_GRD)
+    KBE_CASE(C_GRD) KBE_CASE(C_GRU) KBE_CASE(B_GRL) KBE_CASE(B_GRD)
     KBE_CASE(B_GRU)
 #undef KBE_CASE
     default: lo = hi = 0;
@@ -713,6 +708,7 @@ struct FusedPlan {
   int64_t first[13];
   int64_t off[12];  // byte offset of each class's partials [nchunk][nout][N*N] in the workspace
   int64_t qoff;     // byte offset of the 8 queue heads
+  int64_t sgoff;    // greater form with I^<: byte offset of the Sigma^> row (-1: none)
 };
 
 // Kernel variants ("kind"): 16 = FP64 MFMA (N = 16), 1..8 = small-block task for that N,
@@ -783,7 +779,7 @@ __global__ void __launch_bounds__(256) stream_fused(Params p, FusedPlan pl, char
           KBE_CASE(C_IRC) KBE_CASE(C_IRR) KBE_CASE(C_IL) KBE_CASE(C_ITV) KBE_CASE(C_JR)
           KBE_CASE(C_JM1) KBE_CASE(C_JM2)
         }
-        switch (pl.cls[k]) { KBE_CASE(C_GRL) KBE_CASE(C_GRD) KBE_CASE(C_GRU) KBE_CASE(C_GLR) }
+        switch (pl.cls[k]) { KBE_CASE(C_GRL) KBE_CASE(C_GRD) KBE_CASE(C_GRU) }
       } else {
         switch (pl.cls[k]) {
           KBE_CASE(B_R1) KBE_CASE(B_R2) KBE_CASE(B_R3) KBE_CASE(B_L) KBE_CASE(B_T1)
@@ -799,6 +795,13 @@ __global__ void __launch_bounds__(256) stream_fused(Params p, FusedPlan pl, char
 
 __global__ void zero_heads(unsigned int *heads) {
   if (threadIdx.x < 8) heads[threadIdx.x] = 0u;
+}
+
+// out[x] = a[x] + b[x] over count complex numbers (the Sigma^> row of the greater form).
+__global__ void __launch_bounds__(256) add_rows(const kbe_c128 *a, const kbe_c128 *b,
+                                                kbe_c128 *out, int64_t count) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x < count) st(out + x, ld(a + x) + ld(b + x));
 }
 
 // Chunk reduction, all outputs of a call in one launch.  Job j writes out_j[x] (=|+=) the sum,
@@ -1432,10 +1435,7 @@ static size_t plan_forward(int N, int ntau, int n, int m0, int m1, unsigned flag
       if (m1 > 1) plan_add(pl, C_GRU, M, m1 - 1, E, off);
     }
   }
-  if (flags & KBE_OUT_IL) {
-    plan_add(pl, C_IL, M, m1, E, off);
-    if (gr) plan_add(pl, C_GLR, M, m1, E, off);
-  }
+  if (flags & KBE_OUT_IL) plan_add(pl, C_IL, M, m1, E, off);  // greater form: Q = Sigma^> row
   if ((flags & KBE_OUT_ITV) && th) plan_add(pl, C_ITV, M, ntau, E, off);
   if ((flags & KBE_OUT_JTV) && th) {
     plan_add(pl, C_JR, ntau, n + 1, E, off);
@@ -1443,7 +1443,13 @@ static size_t plan_forward(int N, int ntau, int n, int m0, int m1, unsigned flag
     plan_add(pl, C_JM2, ntau, ntau, E, off);
   }
   pl.qoff = (int64_t)off;
-  return off + 256;
+  off += 256;
+  pl.sgoff = -1;
+  if (gr && (flags & KBE_OUT_IL) && m1 > 0) {  // Sigma^> = Sigma^R + Sigma^< at t_s, s < m1
+    pl.sgoff = (int64_t)off;
+    off += al256(sizeof(kbe_c128) * (size_t)m1 * E);
+  }
+  return off;
 }
 
 static size_t plan_adjoint(int N, int ntau, int n, int m0, int m1, unsigned flags, int kind,
@@ -1567,12 +1573,22 @@ hipError_t launch_collision(const Params &p, unsigned flags, kbe_c128 *IR, kbe_c
   FusedPlan pl;
   plan_forward(p.N, p.ntau, p.n, p.m0, p.m1, flags, kind, pl);
   char *w = (char *)ws;
-  launch_kind<false>(kind, p, pl, w, st);
+  if (pl.sgoff >= 0) {  // greater form: I^< reads Sigma^> = Sigma^R + Sigma^< through C_IL
+    kbe_c128 *sg = (kbe_c128 *)(w + pl.sgoff);
+    const int64_t cnt = (int64_t)p.m1 * p.N * p.N;
+    hipLaunchKernelGGL(add_rows, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, p.ret,
+                       p.les, sg, cnt);
+    Params pg = p;
+    pg.les = sg;
+    launch_kind<false>(kind, pg, pl, w, st);
+  } else {
+    launch_kind<false>(kind, p, pl, w, st);
+  }
   const int M = p.m1 - p.m0;
   RedAll r{};
   r.SC = pl.SC;
   if (flags & KBE_OUT_IR) reduce_into(p, pl, {C_IRC, C_IRR, C_GRL, C_GRD, C_GRU}, w, M, IR, false, r);
-  if (flags & KBE_OUT_IL) reduce_into(p, pl, {C_IL, C_GLR}, w, M, IL, false, r);
+  if (flags & KBE_OUT_IL) reduce_into(p, pl, {C_IL}, w, M, IL, false, r);
   if (flags & KBE_OUT_ITV) reduce_into(p, pl, {C_ITV}, w, M, Itv, false, r);
   if ((flags & KBE_OUT_JTV) && p.ntau > 0) reduce_into(p, pl, {C_JR, C_JM1, C_JM2}, w, p.ntau, Jtv, false, r);
   reduce_launch(p, r, st);
