@@ -20,11 +20,13 @@ def free_setup(N=3, nt=24, ntau=17, beta=2.0, seed=1):
     return fs, t, taus, W
 
 
-def test_free_closed_forms_real_time():
+@pytest.mark.parametrize("N,nt,seed", [(3, 24, 1), (1, 9, 2), (4, 40, 3), (6, 17, 4)])
+def test_free_closed_forms_real_time(N, nt, seed):
     """Sigma^R := G^R_h, G^< := G^<_h  =>  I^R(n,m) = t_n e^{-iht_n} rho e^{iht_m};
     Sigma^< := G^<_h, G^R := G^R_h  =>  I^<(n,m) = -t_m e^{-iht_n} rho e^{iht_m}
-    (the integrand is constant in s; only the weight sums enter)."""
-    fs, t, taus, W = free_setup()
+    (the integrand is constant in s; only the weight sums enter).  Several orbital counts,
+    grids and per-interval orders."""
+    fs, t, taus, W = free_setup(N=N, nt=nt, seed=seed)
     nt = len(t)
     n = nt - 1
     G = oracle.Green(fs.kp(t), fs.rdiag(nt))
@@ -38,13 +40,14 @@ def test_free_closed_forms_real_time():
         assert relerr(IL[m], -t[m] * core) < 1e-12
 
 
-def test_free_closed_forms_thermal():
+@pytest.mark.parametrize("N,nt,ntau,seed", [(3, 24, 17, 1), (2, 12, 9, 5), (5, 30, 25, 6)])
+def test_free_closed_forms_thermal(N, nt, ntau, seed):
     """With the free mixed and Matsubara components:
     I^](n,m) = -i beta e^{-iht_n} f e^{beta h} f e^{iht_m};
     J^] real-time part (Sigma^R := G^R_h) = t_n e^{-iht_n} f e^{h tau_j};
     J^] Matsubara part (Sigma^] := G^]_h) = i e^{-iht_n} f e^{h tau_j} [tau_j f - (beta-tau_j)(1-f)]
     (constant integrand on each side of the jump of G^M)."""
-    fs, t, taus, W = free_setup()
+    fs, t, taus, W = free_setup(N=N, nt=nt, ntau=ntau, seed=seed)
     nt, ntau, N = len(t), len(taus), fs.N
     n, beta = nt - 1, fs.beta
     tv = fs.tv(t, taus)
