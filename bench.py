@@ -217,6 +217,35 @@ def graph_pair(kbe, torch, G, u, n, t, order, w, reps=10):
     return {"eager_ms": eager, "graph_replay_ms": replay}
 
 
+def greater_form(kbe, torch, G, u, n, t, order, w, cot, gG, reps=3):
+    """The greater form of Eq. KBE2 (KBE_GREATER) on the headline row: kbe_collision and
+    kbe_collision_vjp (overwrite mode) back to back, against the lesser form in the same run."""
+    W = kbe.weights(t, order, G.ntau, w.beta, w.tau_order, device=G.device)
+    sig = kbe.sigma_2b(G, u, n)
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    out = {}
+    for name, fl in (("lesser", kbe.OUT_ALL), ("greater", kbe.OUT_ALL | kbe.GREATER)):
+        f = lambda: kbe.collision(G, sig, W, n, flags=fl)
+        b = lambda: kbe.collision_vjp(G, sig, W, n, 0, n + 1, cot, fl | kbe.GRAD_OVERWRITE, gG)
+        f()
+        b()
+        torch.cuda.synchronize()
+        e = [ev() for _ in range(3)]
+        e[0].record()
+        for _ in range(reps):
+            f()
+        e[1].record()
+        for _ in range(reps):
+            b()
+        e[2].record()
+        torch.cuda.synchronize()
+        out[name] = {"collision_ms": e[0].elapsed_time(e[1]) / reps,
+                     "collision_vjp_ms": e[1].elapsed_time(e[2]) / reps}
+    out["greater_over_lesser"] = {k: out["greater"][k] / out["lesser"][k]
+                                  for k in ("collision_ms", "collision_vjp_ms")}
+    return out
+
+
 def general_u_sigma(kbe, torch, G, n, w, reps=5):
     """kbe_sigma_gf2 on the headline row (same G, n, ntau) with a synthetic symmetric U, calls
     back to back.  Algorithmic FLOP per block: 24 N^5 (two real-by-complex and two complex
@@ -475,6 +504,8 @@ def main():
     }
     log("sigma row -> collision as a graph")
     result["sigma_collision_graph"] = graph_pair(kbe, torch, G, u, n, t, order, w)
+    log("greater form")
+    result["greater_form"] = greater_form(kbe, torch, G, u, n, t, order, w, cot, gG)
     log("general four-index self-energy")
     result["gf2"] = general_u_sigma(kbe, torch, G, n, w)
     del gG, kp, tvd, G
