@@ -62,9 +62,10 @@ def _load():
         lib.orc_collision_vjp.argtypes = [I32, I32, I32, I64, P, P, P, P, P, P, P, P, P, P, P, I32,
                                           I32, I32, I32, P, P, P, P, P, P, P, P, P, P, P]
         lib.orc_sigma_row_vjp.argtypes = [I32, I32, I32, I64, P, P, P, P, I32, P, P, P, P, P, P, P]
+        lib.orc_gf2_block.argtypes = [I32, P, P, P, P]
         for name in ("orc_gauss_legendre", "orc_local_weights", "orc_weights", "orc_tau_weights",
                      "orc_sigma_pair", "orc_sigma_row", "orc_collision", "orc_collision_vjp",
-                     "orc_sigma_row_vjp"):
+                     "orc_sigma_row_vjp", "orc_gf2_block"):
             getattr(lib, name).restype = None
         _lib = lib
     return _lib
@@ -246,8 +247,9 @@ def sigma_row_vjp(G: Green, u, n: int, gsig, grads=None, gu=None):
 #
 # Sigma_ij = sum_{f,d,e,a,b,c} U_ifde Uex_jabc A_fb A_ea C_cd, with Uex_jabc = 2 U_jbac - U_jabc,
 # A = G^<>(t,t') and C = G^><(t',t) on the real axis, A = G^](t,tau) and C = G^[(tau,t) on the
-# mixed branch.  The six-fold sum is evaluated as the nested sums it factors into (over c, then b,
-# then a, then f, d, e together); each partial sum is one numpy contraction.  U is real,
+# mixed branch.  The sum is handed to numpy as the printed expression itself, one einsum over all
+# six summed indices; numpy picks the order in which it contracts them (a library step).  The
+# plain six-fold loop in C (orc_gf2_block) pins it at the full orbital count.  U is real,
 # U[i, f, d, e] = U_ifde.
 # ------------------------------------------------------------------------------------------
 def uex(U):
@@ -259,11 +261,18 @@ def uex(U):
 def gf2_block(U, A, C):
     """Eq. SE at one time argument pair: sum U_ifde Uex_jabc A_fb A_ea C_cd."""
     U = np.asarray(U, np.float64)
-    X = uex(U)
-    s1 = np.einsum("jabc,cd->jabd", X, C)      # sum over c
-    s2 = np.einsum("fb,jabd->jfad", A, s1)     # sum over b
-    s3 = np.einsum("ea,jfad->jfed", A, s2)     # sum over a
-    return np.einsum("ifde,jfed->ij", U, s3)   # sum over f, d, e
+    return np.einsum("ifde,jabc,fb,ea,cd->ij", U, uex(U), A, A, C, optimize="optimal")
+
+
+def gf2_block_loops(U, A, C):
+    """Eq. SE at one time argument pair as the plain six-fold loop of orc_gf2_block (C, OpenMP
+    over the output entries): the exchange tensor is formed inside the loop from U."""
+    U = _c(U, np.float64)
+    A, C = _c(A), _c(C)
+    N = A.shape[0]
+    out = np.empty((N, N), np.complex128)
+    _load().orc_gf2_block(N, _p(U), _p(A), _p(C), _p(out))
+    return out
 
 
 def les_block(G: Green, a: int, b: int):

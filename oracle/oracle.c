@@ -662,3 +662,32 @@ void orc_sigma_row_vjp(int N, int nt, int ntau, int64_t ldt, const cplx *kp, con
         gu[j] += u[i] * cu;
       }
 }
+
+/* ------------------------------------------------------------------------- */
+/* Second-Born self-energy with a general four-index interaction (Eq. SE), at  */
+/* one pair of time arguments:                                                */
+/*   out_ij = sum_{f,d,e,a,b,c} U_ifde Uex_jabc A_fb A_ea C_cd,               */
+/*   Uex_jabc = 2 U_jbac - U_jabc,                                            */
+/* with A = G^<>(t,t') and C = G^><(t',t) (or the mixed-branch pair).  U is   */
+/* real, U[i][f][d][e] = U_ifde.  Six nested sums per output entry, in the    */
+/* printed order of the indices; OpenMP over the output entries only.         */
+/* ------------------------------------------------------------------------- */
+void orc_gf2_block(int N, const double *U, const cplx *A, const cplx *C, cplx *out) {
+#define U4(i, f, d, e) U[(((int64_t)(i) * N + (f)) * N + (d)) * N + (e)]
+#pragma omp parallel for collapse(2) schedule(dynamic)
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      cplx acc = 0.0;
+      for (int f = 0; f < N; ++f)
+        for (int d = 0; d < N; ++d)
+          for (int e = 0; e < N; ++e)
+            for (int a = 0; a < N; ++a)
+              for (int b = 0; b < N; ++b)
+                for (int c = 0; c < N; ++c) {
+                  double ex = 2.0 * U4(j, b, a, c) - U4(j, a, b, c);
+                  acc += U4(i, f, d, e) * ex * A[f * N + b] * A[e * N + a] * C[c * N + d];
+                }
+      out[i * N + j] = acc;
+    }
+#undef U4
+}

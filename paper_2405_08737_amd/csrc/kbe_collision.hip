@@ -10,8 +10,9 @@
 // (c, P) pairs, which are combined before the product.
 //
 // Work decomposition: the term index is cut into chunks of SC terms; a wavefront computes the
-// partial sums of MO consecutive outputs over one chunk (MO = 4 on the MFMA path, so each Q
-// load serves four P blocks) and writes them to the workspace; a reduce kernel adds the chunks
+// partial sums of MO consecutive outputs over one chunk (on the MFMA path a workgroup of 4 waves
+// x MO = 2 outputs shares each staged Q block between 8 P blocks) and writes them to the
+// workspace; a reduce kernel adds the chunks
 // of every output in a fixed order, so results are deterministic (no floating-point atomics).
 // Workgroups are laid out chunk-fastest and every class starts on a multiple of 8 workgroups:
 // with round-robin dispatch over the 8 XCDs, all tasks of a chunk land on one XCD and its L2
@@ -75,7 +76,7 @@ __host__ __device__ constexpr int cls_op() {
 // class's shared operand exists: the workgroup tasks stage that operand for every term of the
 // union of their outputs' ranges.
 template <int CLS>
-__device__ __forceinline__ void cls_range(const Params &p, int o, int &lo, int &hi) {
+__host__ __device__ __forceinline__ void cls_range(const Params &p, int o, int &lo, int &hi) {
   const int m = p.m0 + o;
   switch (CLS) {
     case C_IRC: lo = 0; hi = m + 1; break;
@@ -108,7 +109,7 @@ __device__ __forceinline__ void cls_range(const Params &p, int o, int &lo, int &
 
 // Shared operand of term t.
 template <int CLS>
-__device__ __forceinline__ const kbe_c128 *cls_Q(const Params &p, int t) {
+__host__ __device__ __forceinline__ const kbe_c128 *cls_Q(const Params &p, int t) {
   const int64_t E = bsz(p);
   switch (CLS) {
     case C_IRC: case C_IRR: case C_JR: case C_GRL: case C_GRD: case C_GRU:
@@ -140,8 +141,8 @@ __host__ __device__ constexpr int cls_fim() {
 // Addresses of the real weight (the term weight is f w) and of the streamed block P of term t of
 // output o.  Only address arithmetic: they are valid to read when t lies in o's range.
 template <int CLS>
-__device__ __forceinline__ void cls_wpP(const Params &p, int o, int t, const double *&w,
-                                        const kbe_c128 *&P) {
+__host__ __device__ __forceinline__ void cls_wpP(const Params &p, int o, int t, const double *&w,
+                                                 const kbe_c128 *&P) {
   const int64_t E = bsz(p);
   const int J = p.J, m = p.m0 + o;
   switch (CLS) {
@@ -499,7 +500,7 @@ __device__ __forceinline__ double mfma4(double a, double b, double c) {
   return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
 }
 
-// Workgroup task on the MFMA path: the 4 waves of a workgroup handle 4 groups of MO = 4
+// Workgroup task on the MFMA path: the 4 waves of a workgroup handle 4 groups of MO = 2
 // consecutive outputs over the same chunk of terms, so they share every Q block.  Each term's
 // Q block is staged once per workgroup in LDS (double-buffered, rows padded to 20 complex
 // numbers so the 4x4 A-tile reads are free of bank conflicts) while every wave prefetches its
@@ -1651,4 +1652,152 @@ hipError_t launch_collision_vjp(const Params &p, unsigned flags, kbe_c128 *gmat,
   return hipGetLastError();
 }
 
+
+// ------------------------------------------------------------------------------------------
+// Host-side audit of the work decomposition (a self-check, run on the CPU by the test-suite).
+// For the plan a call would launch, it walks every task of every class the way the kernels do:
+// the workgroup union of its outputs' term ranges clipped to the task's chunk (MFMA and
+// small-block tasks, which stage the shared operand Q for every term of that union), or one
+// output's range (generic tasks).  It checks that every staged Q block, and every weight and
+// streamed block P of a term inside its output's own range, lies inside the array it is taken
+// from.  Addresses are formed from distinct dummy base addresses and never dereferenced.
+// ------------------------------------------------------------------------------------------
+namespace {
+struct AuditArr {
+  uintptr_t base;
+  int64_t count;  // elements
+  int64_t esize;  // bytes per element
+  bool in(const void *q) const {
+    const uintptr_t a = (uintptr_t)q;
+    if (a < base) return false;
+    const uintptr_t d = a - base;
+    return d % (uintptr_t)esize == 0 && (int64_t)(d / (uintptr_t)esize) < count;
+  }
+};
+
+template <int CLS>
+void audit_class(const Params &p, const FusedPlan &pl, int k, int kind, const AuditArr *qa,
+                 const AuditArr *const *pa, int npa, const AuditArr *wa, int nwa,
+                 int64_t &bad, int64_t &checked) {
+  const int nch = pl.nchunk[k], nout = pl.nout[k], ngroup = pl.ngroup[k];
+  const int64_t ntask = (int64_t)nch * ((ngroup + 3) / 4);
+  for (int64_t lb = 0; lb < ntask; ++lb) {
+    const int ch = (int)(lb % nch), gb = (int)(lb / nch);
+    const int c0 = ch * pl.SC, c1 = c0 + pl.SC;
+    int T0 = 1 << 30, T1 = 0;
+    for (int wave = 0; wave < 4; ++wave) {
+      const int g = gb * 4 + wave;
+      if (g >= ngroup) continue;
+      const int o0 = kind == KIND_GENERIC ? g : g * pl.MO;
+      const int o1 = kind == KIND_GENERIC ? g + 1 : (o0 + pl.MO < nout ? o0 + pl.MO : nout);
+      for (int o = o0; o < o1; ++o) {
+        int lo, hi;
+        cls_range<CLS>(p, o, lo, hi);
+        if (kind == KIND_GENERIC) {  // one output per wave: only its own terms in this chunk
+          const int a = lo > c0 ? lo : c0, b = hi < c1 ? hi : c1;
+          for (int t = a; t < b; ++t) {
+            ++checked;
+            bad += !qa->in(cls_Q<CLS>(p, t));
+          }
+        } else {
+          T0 = lo < T0 ? lo : T0;
+          T1 = hi > T1 ? hi : T1;
+        }
+        const int a = lo > c0 ? lo : c0, b = hi < c1 ? hi : c1;
+        for (int t = a; t < b; ++t) {  // weight and streamed block of each own term
+          const double *w;
+          const kbe_c128 *P;
+          cls_wpP<CLS>(p, o, t, w, P);
+          bool okP = false, okW = false;
+          for (int i = 0; i < npa; ++i) okP = okP || pa[i]->in(P);
+          for (int i = 0; i < nwa; ++i) okW = okW || wa[i].in(w);
+          ++checked;
+          bad += !(okP && okW);
+        }
+      }
+    }
+    if (kind != KIND_GENERIC) {  // the workgroup stages Q for every term of the union
+      const int a = T0 > c0 ? T0 : c0, b = T1 < c1 ? T1 : c1;
+      for (int t = a; t < b; ++t) {
+        ++checked;
+        bad += !qa->in(cls_Q<CLS>(p, t));
+      }
+    }
+  }
+}
+}  // namespace
+
 }  // namespace kbe
+
+// Declared in kbe_internal.h.
+extern "C" int64_t kbe_internal_audit_tasks(int32_t N, int32_t nt, int32_t ntau, int64_t ldt,
+                                            int32_t n, int32_t m0, int32_t m1, uint32_t flags,
+                                            int32_t adjoint, int64_t *terms_checked) {
+  using namespace kbe;
+  const int kind = path_kind(N, flags);
+  FusedPlan pl;
+  if (adjoint) plan_adjoint(N, ntau, n, m0, m1, flags, kind, pl);
+  else plan_forward(N, ntau, n, m0, m1, flags, kind, pl);
+  const int64_t E = (int64_t)N * N, cs = sizeof(kbe_c128), ds = sizeof(double);
+  const int M = m1 - m0;
+  uintptr_t next = (uintptr_t)1 << 44;
+  auto arr = [&](int64_t count, int64_t esize) {
+    AuditArr a{next, count, esize};
+    next += (uintptr_t)1 << 42;
+    return a;
+  };
+  // the greater form's I^< reads a Sigma^> row of m1 blocks from the workspace
+  const bool sg = !adjoint && pl.sgoff >= 0;
+  AuditArr kp = arr((int64_t)nt * ldt * E, cs), rdiag = arr((int64_t)nt * E, cs),
+           tv = arr((int64_t)nt * ntau * E, cs), mat = arr((int64_t)ntau * E, cs),
+           ret = arr((int64_t)(n + 1) * E, cs), les = arr((int64_t)(sg ? m1 : n + 1) * E, cs),
+           stv = arr((int64_t)ntau * E, cs), w = arr((int64_t)nt * nt, ds),
+           wtau = arr(ntau, ds), wf = arr((int64_t)ntau * ntau, ds),
+           gIR = arr((int64_t)M * E, cs), gIL = arr((int64_t)M * E, cs),
+           gItv = arr((int64_t)M * E, cs), gJ = arr((int64_t)ntau * E, cs);
+  // element-granular checks: kp and tv blocks are whole blocks, so count blocks as elements of
+  // E complex numbers where a block start is what is formed
+  AuditArr kpb{kp.base, (int64_t)nt * ldt, E * cs}, rdb{rdiag.base, nt, E * cs},
+      tvb{tv.base, (int64_t)nt * ntau, E * cs}, matb{mat.base, ntau, E * cs},
+      retb{ret.base, n + 1, E * cs}, lesb{les.base, sg ? m1 : n + 1, E * cs},
+      stvb{stv.base, ntau, E * cs}, gIRb{gIR.base, M, E * cs}, gILb{gIL.base, M, E * cs},
+      gItvb{gItv.base, M, E * cs}, gJb{gJ.base, ntau, E * cs};
+  Params p{};
+  p.N = N; p.nt = nt; p.ntau = ntau; p.J = ntau - 1; p.n = n; p.m0 = m0; p.m1 = m1; p.ldt = ldt;
+  p.kp = (const kbe_c128 *)kp.base; p.rdiag = (const kbe_c128 *)rdiag.base;
+  p.tv = (const kbe_c128 *)tv.base; p.mat = (const kbe_c128 *)mat.base;
+  p.ret = (const kbe_c128 *)ret.base; p.les = (const kbe_c128 *)les.base;
+  p.stv = (const kbe_c128 *)stv.base;
+  p.w = (const double *)w.base; p.wtau = (const double *)wtau.base; p.wf = (const double *)wf.base;
+  p.gIR = (const kbe_c128 *)gIR.base; p.gIL = (const kbe_c128 *)gIL.base;
+  p.gItv = (const kbe_c128 *)gItv.base; p.gJ = (const kbe_c128 *)gJ.base;
+  const AuditArr *Pall[] = {&kpb, &rdb, &tvb, &matb, &gJb};
+  const AuditArr Wall[] = {w, wtau, wf};
+  int64_t bad = 0, checked = 0;
+  for (int k = 0; k < pl.ncls; ++k) {
+    const AuditArr *q = nullptr;
+    switch (pl.cls[k]) {
+      case C_IRC: case C_IRR: case C_JR: case C_GRL: case C_GRD: case C_GRU: q = &retb; break;
+      case C_IL: q = &lesb; break;
+      case C_ITV: case C_JM1: case C_JM2: case G_MAT1: case G_MAT2: q = &stvb; break;
+      case B_R1: case B_R2: case B_GRL: case B_GRD: case B_GRU: q = &gIRb; break;
+      case B_L: q = &gILb; break;
+      case B_T1: q = &gItvb; break;
+      default: q = &gJb; break;  // B_R3, B_T2A, B_T2B
+    }
+    switch (pl.cls[k]) {
+#define KBE_CASE(C) \
+  case C: audit_class<C>(p, pl, k, kind, q, Pall, 5, Wall, 3, bad, checked); break;
+      KBE_CASE(C_IRC) KBE_CASE(C_IRR) KBE_CASE(C_IL) KBE_CASE(C_ITV) KBE_CASE(C_JR)
+      KBE_CASE(C_JM1) KBE_CASE(C_JM2) KBE_CASE(B_R1) KBE_CASE(B_R2) KBE_CASE(B_R3) KBE_CASE(B_L)
+      KBE_CASE(B_T1) KBE_CASE(B_T2A) KBE_CASE(B_T2B) KBE_CASE(G_MAT1) KBE_CASE(G_MAT2)
+      KBE_CASE(C_GRL) KBE_CASE(C_GRD) KBE_CASE(C_GRU) KBE_CASE(B_GRL) KBE_CASE(B_GRD)
+      KBE_CASE(B_GRU)
+#undef KBE_CASE
+      default: ++bad;
+    }
+  }
+  (void)gItv;
+  if (terms_checked) *terms_checked = checked;
+  return bad;
+}

@@ -66,11 +66,11 @@ struct Params {
   int fIR, fIL, fITV, fJTV;                    // selected outputs
 };
 
-__device__ __forceinline__ int64_t bsz(const Params &p) { return (int64_t)p.N * p.N; }
-__device__ __forceinline__ const kbe_c128 *kp_blk(const Params &p, int a, int b) {
+__host__ __device__ __forceinline__ int64_t bsz(const Params &p) { return (int64_t)p.N * p.N; }
+__host__ __device__ __forceinline__ const kbe_c128 *kp_blk(const Params &p, int a, int b) {
   return p.kp + ((int64_t)a * p.ldt + b) * bsz(p);
 }
-__device__ __forceinline__ const kbe_c128 *tv_blk(const Params &p, int m, int j) {
+__host__ __device__ __forceinline__ const kbe_c128 *tv_blk(const Params &p, int m, int j) {
   return p.tv + ((int64_t)m * p.ntau + j) * bsz(p);
 }
 

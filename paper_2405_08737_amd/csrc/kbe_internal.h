@@ -47,3 +47,13 @@ hipError_t launch_batch_vjp(const kbe_batch_vjp_item *items_dev, int count, void
                             hipStream_t st);
 
 }  // namespace kbe
+
+// Host-side self-check of the collision kernels' work decomposition (no GPU needed): for the
+// plan kbe_collision (adjoint = 0) or kbe_collision_vjp (adjoint = 1) would launch with these
+// sizes and flags, walks every task as the kernels do and returns how many of the addresses they
+// form (staged operand blocks over the workgroup's union of term ranges, weights and streamed
+// blocks of each output's own terms) fall outside their arrays; *terms_checked receives the
+// number of addresses examined.  Not part of the public ABI (used by the test-suite).
+extern "C" int64_t kbe_internal_audit_tasks(int32_t N, int32_t nt, int32_t ntau, int64_t ldt,
+                                            int32_t n, int32_t m0, int32_t m1, uint32_t flags,
+                                            int32_t adjoint, int64_t *terms_checked);

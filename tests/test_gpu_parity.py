@@ -74,10 +74,17 @@ def test_weights_match_oracle(gpu):
 
 
 def test_weights_high_order(gpu):
-    """Orders up to KBE_KMAX = 20 (the paper's maximum history order K): the Vandermonde route
-    is ill-conditioned there, so the bar is the polynomial exactness both routes guarantee."""
+    """Orders up to KBE_KMAX = 20 (the paper's maximum history order K).  The moment system is
+    ill-conditioned there (on this grid the local rules reach sum |lambda| / h of about 4e5), so the
+    bar is what both routes guarantee, interval by interval: the local weights of every interval,
+    lambda = w[p] - w[p-1] on its nodes, integrate every polynomial of degree < k exactly, to
+    rounding of the sum of |lambda| (Legendre polynomials in the variable scaled to the node
+    window, so |P| <= 1 there).  The weights themselves agree with the oracle's (a different
+    route: Gauss-Legendre integration of the Lagrange basis) only to the conditioning of the
+    moment system, about 1e6 at order 20 in that basis, hence 1e-9 of the sum of |lambda|."""
+    from numpy.polynomial import legendre as L
     kbe = gpu
-    t, order = synth.grid(3, 120, 0.01, 0.05, 14, 20)
+    t, order = synth.grid(3, 120, 0.01, 0.05, 13, 20)
     w = to_host(kbe.weights(t, order).w)
     W = oracle.weights(t, order)
     assert np.abs(w - W).max() < 1e-9 * np.abs(W).max()
@@ -85,6 +92,26 @@ def test_weights_high_order(gpu):
     for d in range(2):  # start-up intervals limit the whole-range exactness to degree 1
         # high-order weights alternate in sign; rounding scales with sum |w|
         assert abs(w[n] @ (t / t[n]) ** d - t[n] / (d + 1)) < 1e-14 * np.abs(w[n]).sum()
+    checked = 0
+    for p in range(1, 120):
+        k = min(int(order[p]), p + 1)
+        nodes = np.arange(p - k + 1, p + 1)
+        lam = w[p, nodes] - w[p - 1, nodes]
+        sc = np.abs(w[p, nodes]).sum() + np.abs(w[p - 1, nodes]).sum()
+        lam_o = oracle.local_weights(t, p, k)
+        assert np.abs(lam - lam_o).max() <= 1e-9 * sc, p
+        a, b = t[p - k + 1], t[p]
+        x = lambda y: (2.0 * y - a - b) / (b - a) if k > 1 else 0.0 * y
+        for deg in range(k):
+            c = np.zeros(deg + 1)
+            c[deg] = 1.0
+            P = L.legval(x(t[nodes]), c)
+            ci = L.legint(c)
+            exact = 0.5 * (b - a) * (L.legval(x(t[p]), ci) - L.legval(x(t[p - 1]), ci)) \
+                if k > 1 else (t[p] - t[p - 1]) * (deg == 0)
+            assert abs(lam @ P - exact) <= 1e-13 * sc, (p, k, deg)
+            checked += 1
+    assert checked > 1500
 
 
 @pytest.mark.parametrize("N,n", [(1, 5), (2, 0), (2, 63), (3, 17), (16, 0), (16, 39)])
@@ -340,9 +367,10 @@ def test_greater_form_matches_oracle(gpu, N, nt, ntau, mr):
     out = kbe.collision(Gd, tuple(to_dev(x) for x in sig), Wd, n, m0, m1,
                         kbe.OUT_ALL | kbe.GREATER)
     ref = oracle.collision(G, sig, W, n, m0, m1, oracle.F_ALL | oracle.F_GREATER)
+    sc = scales(kp, rd, tv if ntau else None, mat, sig, W, n, range(m0, m1), range(ntau),
+                greater=True)
     for name, g, r in zip(("IR", "IL", "Itv", "Jtv"), out, ref):
-        if g is None:
-            assert r.size == 0 or not ntau
+        if g is None or (not ntau and name in ("Itv", "Jtv")):
+            assert g is None or not np.any(to_host(g)), name  # no thermal branch: zero
             continue
-        g = to_host(g)
-        assert np.all(bnorm(g - r) <= 1e-12 * (bnorm(r).max() + 1e-300)), name
+        assert_blocks_close(to_host(g), r, sc[name], name)

@@ -4,11 +4,13 @@ import pytest
 
 import oracle
 import synth
-from tests.cases import Case, bnorm, device_green, device_weights, to_dev, to_host
+from tests.cases import (Case, assert_blocks_close, bnorm, device_green, device_weights, to_dev,
+                         sigma_vjp_scales, to_host, vjp_scales)
 
 pytestmark = pytest.mark.gpu
 
 RTOL = 1e-12
+NAMES = ["kp", "rdiag", "tv", "mat", "ret", "les", "stv"]
 
 
 def rel(a, b):
@@ -17,7 +19,10 @@ def rel(a, b):
     return np.linalg.norm((a - b).ravel()) / (nb if nb > 0 else 1.0)
 
 
-def vjp_case(kbe, case: Case, m0, m1, flags, extra=0, seed_cot=5):
+def vjp_case(kbe, case: Case, m0, m1, flags, extra=0, seed_cot=5, base="zero"):
+    """The GPU adjoint and the oracle's pure gradient (accumulated into zeros).  The GPU's
+    Green's-function gradient arrays start from `base`: zeros (the accumulated result is then the
+    pure gradient) or random N(0,1) values (to check that accumulation keeps them)."""
     t, order, kp, rd, tv, mat = case.host()
     n = case.nt - 1
     W = oracle.Weights.build(t, order, case.beta, case.ntau, case.tau_order)
@@ -25,16 +30,44 @@ def vjp_case(kbe, case: Case, m0, m1, flags, extra=0, seed_cot=5):
     M, N = m1 - m0, case.N
     cot = (synth.normal(seed_cot, 0, (M, N, N)), synth.normal(seed_cot, 1, (M, N, N)),
            synth.normal(seed_cot, 2, (M, N, N)), synth.normal(seed_cot, 3, (case.ntau, N, N)))
-    base = (synth.normal(seed_cot, 4, kp.shape), synth.normal(seed_cot, 5, rd.shape),
-            synth.normal(seed_cot, 6, tv.shape), synth.normal(seed_cot, 7, mat.shape))
-    ref = oracle.collision_vjp(oracle.Green(kp, rd, tv, mat), sig, W, n, m0, m1, cot, flags,
-                               grads=tuple(b.copy() for b in base))
+    shapes = (kp.shape, rd.shape, tv.shape, mat.shape)
+    if base == "zero":
+        b0 = tuple(np.zeros(s, np.complex128) for s in shapes)
+    else:
+        b0 = tuple(synth.normal(seed_cot, 4 + k, s) for k, s in enumerate(shapes))
+    ref = oracle.collision_vjp(oracle.Green(kp, rd, tv, mat), sig, W, n, m0, m1, cot, flags)
     Gd = device_green(kp, rd, tv, mat)
-    gG = device_green(*base)
+    gG = device_green(*b0)
     sel = lambda k, x: to_dev(x) if flags & (1 << k) else None
     gG, gs = kbe.collision_vjp(Gd, tuple(to_dev(x) for x in sig), device_weights(W), n, m0, m1,
                                tuple(sel(k, c) for k, c in enumerate(cot)), flags | extra, gG)
-    return ref, (gG, gs), base
+    scale = vjp_scales(kp, rd, tv, mat, sig, W, n, m0, m1,
+                       tuple(c if flags & (1 << k) else None for k, c in enumerate(cot)), flags)
+    return ref, (gG, gs), b0, scale
+
+
+def check_gradients(ref, got, base, scale):
+    """Accumulate mode: every gradient array against base + the oracle's pure gradient (the
+    self-energy gradients are overwritten), each block within RTOL of its rounding scale (R14
+    applied to the adjoint; the final addition to the base adds the base's norm to the scale)
+    and globally within RTOL.  With a zero base this is the bar on the pure gradient itself."""
+    gG, gs = got
+    arrays = [gG.kp, gG.rdiag, gG.tv, gG.mat, gs[0], gs[1], gs[2]]
+    for k, (name, g, r) in enumerate(zip(NAMES, arrays, ref)):
+        if r.size == 0:
+            continue
+        g = to_host(g)
+        sc = scale[name]
+        if k < 4:
+            r = r + base[k]
+            if name == "kp":
+                nt = sc.shape[0]
+                g, r, b = g[:, :nt], r[:, :nt], base[0][:, :nt]
+            else:
+                b = base[k]
+            sc = sc + bnorm(b)
+        assert_blocks_close(g.reshape(-1, *g.shape[-2:]), r.reshape(-1, *r.shape[-2:]),
+                            sc.ravel(), "g" + name)
 
 
 @pytest.mark.parametrize("N,nt,ntau,m0,m1,flags,generic", [
@@ -64,13 +97,9 @@ def test_collision_vjp_matches_oracle(gpu, N, nt, ntau, m0, m1, flags, generic):
     kbe = gpu
     print("vjp", N, nt, ntau, m0, m1, flags, generic, flush=True)
     case = Case(N=N, nt=nt, ntau=ntau, beta=3.0 if ntau else 0.0, seed=40 + N)
-    ref, (gG, gs), _ = vjp_case(kbe, case, m0, m1, flags, kbe.FORCE_GENERIC if generic else 0)
-    names = ["gkp", "grdiag", "gtv", "gmat", "gret", "gles", "gstv"]
-    got = [gG.kp, gG.rdiag, gG.tv, gG.mat, gs[0], gs[1], gs[2]]
-    for name, g, r in zip(names, got, ref):
-        if r.size == 0:
-            continue
-        assert rel(to_host(g), r) < RTOL, name
+    ref, got, base, scale = vjp_case(kbe, case, m0, m1, flags,
+                                     kbe.FORCE_GENERIC if generic else 0)
+    check_gradients(ref, got, base, scale)
 
 
 @pytest.mark.parametrize("N,nt,ntau,m0,m1,flags", [
@@ -90,34 +119,57 @@ def test_greater_form_vjp_matches_oracle(gpu, N, nt, ntau, m0, m1, flags):
     kbe = gpu
     print("greater vjp", N, nt, ntau, m0, m1, flags, flush=True)
     case = Case(N=N, nt=nt, ntau=ntau, beta=3.0 if ntau else 0.0, seed=60 + N)
-    ref, (gG, gs), _ = vjp_case(kbe, case, m0, m1, flags | oracle.F_GREATER)
-    names = ["gkp", "grdiag", "gtv", "gmat", "gret", "gles", "gstv"]
-    got = [gG.kp, gG.rdiag, gG.tv, gG.mat, gs[0], gs[1], gs[2]]
-    for name, g, r in zip(names, got, ref):
-        if r.size == 0:
-            continue
-        assert rel(to_host(g), r) < RTOL, name
+    ref, got, base, scale = vjp_case(kbe, case, m0, m1, flags | oracle.F_GREATER)
+    check_gradients(ref, got, base, scale)
 
 
-@pytest.mark.parametrize("N", [4, 16])
-def test_greater_form_vjp_overwrite_mode(gpu, N):
-    """Overwrite mode with KBE_GREATER and I^R alone: the forward reads row m and column m of kp
-    and rdiag[m] for m in the range (G^> assembled from both triangles); exactly those blocks are
-    overwritten, including the lower-triangle ones that only the greater form's terms reach."""
+@pytest.mark.parametrize("N,nt,ntau,m0,m1,greater", [(16, 120, 10, 0, 120, False),
+                                                   (8, 90, 12, 5, 80, True),
+                                                   (3, 70, 6, 0, 70, False)])
+def test_collision_vjp_accumulates_onto_existing_values(gpu, N, nt, ntau, m0, m1, greater):
+    """Accumulate mode on random N(0,1) initial gradient arrays: the result is the initial
+    values plus the pure gradient, to the bar of the final addition."""
+    kbe = gpu
+    case = Case(N=N, nt=nt, ntau=ntau, beta=3.0, seed=90 + N)
+    flags = oracle.F_ALL | (oracle.F_GREATER if greater else 0)
+    ref, got, base, scale = vjp_case(kbe, case, m0, m1, flags, base="random")
+    check_gradients(ref, got, base, scale)
+
+
+def check_overwrite(ref, gG, base, scale, read_kp, read_rd):
+    """Overwrite mode: blocks the forward reads hold the pure gradient (the oracle's, accumulated
+    into zeros) to the R14 bar; every other block keeps its initial value bit for bit."""
+    nt = read_kp.shape[0]
+    kp, rd = to_host(gG.kp)[:, :nt], to_host(gG.rdiag)
+    want_kp, want_rd = ref[0][:, :nt], ref[1]
+    assert np.array_equal(kp[~read_kp], base[0][:, :nt][~read_kp])
+    assert np.array_equal(rd[~read_rd], base[1][~read_rd])
+    assert_blocks_close(kp[read_kp], want_kp[read_kp], scale["kp"][read_kp], "gkp")
+    assert_blocks_close(rd[read_rd], want_rd[read_rd], scale["rdiag"][read_rd], "grdiag")
+
+
+@pytest.mark.parametrize("N,flags", [(4, oracle.F_IR), (6, oracle.F_IR), (8, oracle.F_IR),
+                                     (16, oracle.F_IR), (6, oracle.F_IR | oracle.F_IL),
+                                     (8, oracle.F_IR | oracle.F_IL),
+                                     (16, oracle.F_IR | oracle.F_IL)])
+def test_greater_form_vjp_overwrite_mode(gpu, N, flags):
+    """Overwrite mode with KBE_GREATER: the forward reads row m and column m of kp and rdiag[m]
+    for m in the range (G^> assembled from both triangles; I^< reads the left part of row m);
+    exactly those blocks are overwritten, including the lower-triangle ones that only the greater
+    form's terms reach, on the generic (N = 4), padded 8x8 (N = 6, 8) and 16x16 gradient
+    kernels."""
     kbe = gpu
     nt, m0, m1 = 30, 10, 20
+    print("greater overwrite", N, flags, flush=True)
     case = Case(N=N, nt=nt, ntau=6, beta=2.0, seed=9)
-    flags = oracle.F_IR | oracle.F_GREATER
-    ref, (gG, _), base = vjp_case(kbe, case, m0, m1, flags, kbe.GRAD_OVERWRITE)
+    ref, (gG, _), base, scale = vjp_case(kbe, case, m0, m1, flags | oracle.F_GREATER,
+                                         kbe.GRAD_OVERWRITE, base="random")
     read = np.zeros((nt, nt), bool)
     read[:, m0:m1] = True
     read[m0:m1, :] = True
     rd_read = np.zeros(nt, bool)
     rd_read[m0:m1] = True
-    want_kp = np.where(read[:, :, None, None], ref[0] - base[0], base[0])
-    want_rd = np.where(rd_read[:, None, None], ref[1] - base[1], base[1])
-    assert rel(to_host(gG.kp), want_kp) < RTOL
-    assert rel(to_host(gG.rdiag), want_rd) < RTOL
+    check_overwrite(ref, gG, base, scale, read, rd_read)
 
 
 def test_collision_vjp_overwrite_mode(gpu):
@@ -125,24 +177,24 @@ def test_collision_vjp_overwrite_mode(gpu):
     tv rows 0..n) and leaves the rest of the arrays as they were."""
     kbe = gpu
     case = Case(N=16, nt=80, ntau=10, beta=2.0, seed=3)
-    ref, (gG, gs), base = vjp_case(kbe, case, 0, 80, oracle.F_ALL, kbe.GRAD_OVERWRITE)
-    # accumulate-mode reference minus the initial content = the overwrite result
-    for g, r, b in zip([gG.kp, gG.rdiag, gG.tv, gG.mat], ref[:4], base):
-        assert rel(to_host(g), r - b) < RTOL
+    ref, (gG, gs), base, scale = vjp_case(kbe, case, 0, 80, oracle.F_ALL, kbe.GRAD_OVERWRITE,
+                                          base="random")
+    # every block is read: the arrays hold the pure gradient
+    check_gradients(ref, (gG, gs), tuple(np.zeros_like(b) for b in base), scale)
     # a partial range: blocks nobody reads keep their initial values (generic gradient kernel
-    # at N = 4, the padded MFMA one at N = 8)
-    for N in (4, 8):
+    # at N = 4, the padded MFMA one at N = 6 and 8)
+    for N in (4, 6, 8):
         case2 = Case(N=N, nt=30, ntau=6, beta=2.0, seed=4)
-        ref2, (gG2, _), base2 = vjp_case(kbe, case2, 10, 20, oracle.F_IR | oracle.F_IL,
-                                         kbe.GRAD_OVERWRITE)
-        kp = to_host(gG2.kp)
+        ref2, (gG2, _), base2, scale2 = vjp_case(kbe, case2, 10, 20, oracle.F_IR | oracle.F_IL,
+                                                 kbe.GRAD_OVERWRITE, base="random")
         read = np.zeros((30, 30), bool)
         for m in range(10, 20):
             read[: m + 1, m] = True   # IR column part
             read[m, m + 1:] = True    # IR row part
             read[m, :m] = True        # IL
-        assert np.array_equal(kp[~read], base2[0][~read])
-        assert rel(kp[read], (ref2[0] - base2[0])[read]) < RTOL
+        rd_read = np.zeros(30, bool)
+        rd_read[10:20] = True
+        check_overwrite(ref2, gG2, base2, scale2, read, rd_read)
 
 
 @pytest.mark.parametrize("N,n", [(2, 63), (3, 0), (16, 45), (16, 0)])
@@ -153,16 +205,23 @@ def test_sigma_vjp_matches_oracle(gpu, N, n):
     u = np.linspace(0.7, 1.3, N)
     gsig = (synth.normal(9, 0, (n + 1, N, N)), synth.normal(9, 1, (n + 1, N, N)),
             synth.normal(9, 2, (case.ntau, N, N)))
-    base = (synth.normal(9, 3, kp.shape), synth.normal(9, 4, rd.shape), synth.normal(9, 5, tv.shape))
-    gu0 = np.arange(N, dtype=np.float64)
+    base = (np.zeros(kp.shape, np.complex128), np.zeros(rd.shape, np.complex128),
+            np.zeros(tv.shape, np.complex128))
+    gu0 = np.zeros(N)
     rk, rr, rt, ru = oracle.sigma_row_vjp(oracle.Green(kp, rd, tv, mat), u, n, gsig,
                                          grads=tuple(b.copy() for b in base), gu=gu0.copy())
     gG = device_green(base[0], base[1], base[2], mat)
     gG, gu = kbe.sigma_2b_vjp(device_green(kp, rd, tv, mat), to_dev(u), n,
                               tuple(to_dev(x) for x in gsig), gG, to_dev(gu0.copy()))
-    assert rel(to_host(gG.kp), rk) < RTOL
-    assert rel(to_host(gG.rdiag), rr) < RTOL
-    assert rel(to_host(gG.tv), rt) < RTOL
+    # pure gradients (zero initial arrays): the blocks of row and column n, rdiag[n] and tv row n
+    # that the row reads, each to its rounding scale; nothing else is written
+    S_kp, S_rd, S_tv = sigma_vjp_scales(kp, rd, tv, u, n, gsig)
+    touched = S_kp > 0
+    kpg, rdg, tvg = to_host(gG.kp), to_host(gG.rdiag), to_host(gG.tv)
+    assert_blocks_close(kpg[touched], rk[touched], S_kp[touched], "gkp")
+    assert np.array_equal(kpg[~touched], base[0][~touched])
+    assert_blocks_close(rdg[n:n + 1], rr[n:n + 1], S_rd[n:n + 1], "grdiag")
+    assert_blocks_close(tvg[n], rt[n], S_tv[n], "gtv")
     assert rel(to_host(gu), ru) < 1e-12
 
 

@@ -1,7 +1,9 @@
 """Pins for the oracle's second-Born self-energy with a general four-index interaction (Eq. SE).
 
-Each pin is fixed independently of the oracle's staged contractions:
+Each pin is fixed independently of the order in which the oracle's einsum contracts the indices:
   * a six-fold loop over the indices, written out in plain Python (tiny N, general U);
+  * the same six-fold loop in plain C (oracle.c, orc_gf2_block) at 8 and 16 orbitals, the sizes
+    the GPU kernels run, general U and an eight-fold symmetric one;
   * a rank-one U, for which the sum collapses to products of bilinear forms (closed form);
   * a local U, where Eq. SE reduces to the local second-Born formula of the C oracle, which has
     its own pins (hand calculation, brute force);
@@ -50,6 +52,32 @@ def test_matches_six_fold_loops(N):
     A, C = _cmat(rng, N), _cmat(rng, N)
     np.testing.assert_allclose(oracle.gf2_block(U, A, C), _loops(U, A, C), rtol=1e-13,
                                atol=1e-13 * np.abs(_loops(U, A, C)).max())
+
+
+@pytest.mark.parametrize("N,sym", [(8, False), (16, False), (16, True)])
+def test_matches_six_fold_loops_in_c(N, sym):
+    """At full size: each entry within 1e-13 of its rounding scale, the six-fold sum of the
+    magnitudes of its terms."""
+    rng = np.random.default_rng(150 + N + sym)
+    U = sym8(rng, N) if sym else rng.normal(size=(N,) * 4)
+    A, C = _cmat(rng, N), _cmat(rng, N)
+    got = oracle.gf2_block(U, A, C)
+    ref = oracle.gf2_block_loops(U, A, C)
+    scale = np.einsum("ifde,jabc,fb,ea,cd->ij", np.abs(U), np.abs(oracle.uex(U)), np.abs(A),
+                      np.abs(A), np.abs(C), optimize="optimal")
+    assert np.all(np.abs(got - ref) <= 1e-13 * scale)
+    assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_c_loops_match_python_loops():
+    """The C six-fold loop against the Python one (tiny N, general U): the same sum written twice,
+    so a transposed index in either shows."""
+    rng = np.random.default_rng(160)
+    U = rng.normal(size=(3,) * 4)
+    A, C = _cmat(rng, 3), _cmat(rng, 3)
+    ref = _loops(U, A, C)
+    np.testing.assert_allclose(oracle.gf2_block_loops(U, A, C), ref, rtol=1e-13,
+                               atol=1e-13 * np.abs(ref).max())
 
 
 def test_uex_definition():

@@ -149,3 +149,49 @@ def test_end_to_end_density_gradient_wrt_u():
     h = 0.25
     d5 = (8 * (L(1 + h) - L(1 - h)) - (L(1 + 2 * h) - L(1 - 2 * h))) / (12 * h)
     assert abs(d5 - dLdU) < 1e-11 * max(1.0, abs(d5))
+
+
+@pytest.mark.parametrize("N,nt,ntau,m0,m1,flags", [
+    (2, 12, 5, 0, 12, oracle.F_ALL),
+    (3, 10, 4, 2, 8, oracle.F_ALL),
+    (2, 9, 0, 1, 9, oracle.F_IR | oracle.F_IL),
+    (3, 10, 4, 0, 10, oracle.F_ALL | oracle.F_GREATER),
+    (2, 11, 6, 3, 9, oracle.F_IR | oracle.F_IL | oracle.F_GREATER),
+    (1, 8, 5, 0, 8, oracle.F_ITV | oracle.F_JTV),
+])
+def test_gradient_rounding_scales_bound_the_gradients(N, nt, ntau, m0, m1, flags):
+    """The per-block rounding scales the GPU adjoint tests use (sum over the terms that read a
+    block of |c| and the norms of the other two factors) bound the norm of every gradient block
+    of the oracle: a term the scales leave out would show as a block above its scale."""
+    from tests.cases import Case, bnorm, vjp_scales
+    case = Case(N=N, nt=nt, ntau=ntau, beta=2.0 if ntau else 0.0, seed=30 + N)
+    t, order, kp, rd, tv, mat = case.host()
+    n = nt - 1
+    W = oracle.Weights.build(t, order, case.beta, ntau, case.tau_order)
+    sig = synth.sigma_row(case.seed, N, n, ntau, t)
+    M = m1 - m0
+    cot = [synth.normal(3, k, (M, N, N)) for k in range(3)] + [synth.normal(3, 3, (ntau, N, N))]
+    cot = [c if flags & (1 << k) else None for k, c in enumerate(cot)]
+    full = [c if c is not None else np.zeros_like(z) for c, z in
+            zip(cot, [np.zeros((M, N, N))] * 3 + [np.zeros((ntau, N, N))])]
+    ref = oracle.collision_vjp(oracle.Green(kp, rd, tv, mat), sig, W, n, m0, m1, full, flags)
+    S = vjp_scales(kp, rd, tv, mat, sig, W, n, m0, m1, cot, flags)
+    for name, g in zip(["kp", "rdiag", "tv", "mat", "ret", "les", "stv"], ref):
+        if g.size == 0:
+            continue
+        assert np.all(bnorm(g) <= S[name] * (1 + 1e-9) + 1e-300), name
+
+
+@pytest.mark.parametrize("N,n", [(2, 7), (3, 0), (1, 5)])
+def test_sigma_gradient_rounding_scales_bound_the_gradients(N, n):
+    from tests.cases import Case, bnorm, sigma_vjp_scales
+    case = Case(N=N, nt=9, ntau=6, beta=2.0, seed=50 + N)
+    t, order, kp, rd, tv, mat = case.host()
+    u = np.linspace(0.7, 1.3, N)
+    gsig = (synth.normal(4, 0, (n + 1, N, N)), synth.normal(4, 1, (n + 1, N, N)),
+            synth.normal(4, 2, (6, N, N)))
+    gk, gr, gt, _ = oracle.sigma_row_vjp(oracle.Green(kp, rd, tv, mat), u, n, gsig)
+    S_kp, S_rd, S_tv = sigma_vjp_scales(kp, rd, tv, u, n, gsig)
+    assert np.all(bnorm(gk) <= S_kp * (1 + 1e-9) + 1e-300)
+    assert np.all(bnorm(gr) <= S_rd * (1 + 1e-9) + 1e-300)
+    assert np.all(bnorm(gt) <= S_tv * (1 + 1e-9) + 1e-300)
