@@ -44,7 +44,9 @@
  *
  * Ownership.  The caller owns every buffer.  The library allocates nothing:
  * scratch memory is a caller-supplied device workspace whose size the
- * matching *_workspace() query returns.
+ * matching *_workspace() query returns.  The one exception is the fixed
+ * scratch array behind kbe_collision_noalloc (KBE_NOALLOC_SCRATCH_BYTES per
+ * device, part of the library's device code, held until the process ends).
  *
  * Streams.  `stream` is a hipStream_t (NULL = the default stream).  All device
  * work is enqueued asynchronously on it; no entry point synchronises the host
@@ -257,6 +259,31 @@ size_t kbe_collision_workspace(int32_t N, int32_t nt, int32_t ntau, int32_t n, i
 kbe_status kbe_collision(const kbe_green *G, const kbe_sigma_row *S, const kbe_wts *W, int32_t n,
                          int32_t m0, int32_t m1, uint32_t flags, kbe_c128 *IR, kbe_c128 *IL,
                          kbe_c128 *Itv, kbe_c128 *Jtv, void *ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * kbe_collision_noalloc — kbe_collision for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same integrals, arguments and errors as
+ * kbe_collision, without the workspace arguments.  The workspace lives in a
+ * fixed device array of KBE_NOALLOC_SCRATCH_BYTES inside the library; every
+ * device the library runs on holds its own copy until the process ends.  The
+ * call allocates nothing: it enqueues the same kernels as kbe_collision on
+ * `stream`, using that device's array.
+ *
+ * All calls on one device share its array and every call overwrites it (what
+ * must start at zero is cleared by the call itself, on the stream), so calls
+ * that may overlap on one device race: issue them on one stream, or order them.
+ * The first call on a device looks up the array's device address (a host-side
+ * query, no allocation).
+ * Errors: as kbe_collision, plus KBE_ENOMEM when the call would need more than
+ * KBE_NOALLOC_SCRATCH_BYTES of workspace (kbe_collision_workspace() tells; the
+ * 8-orbital history of 1024 points with 256 tau points needs 29 MiB, the
+ * 16-orbital one of 2048 points needs 232 MiB and is rejected).
+ * ------------------------------------------------------------------------- */
+#define KBE_NOALLOC_SCRATCH_BYTES (64u << 20) /* 64 MiB per device */
+kbe_status kbe_collision_noalloc(const kbe_green *G, const kbe_sigma_row *S, const kbe_wts *W,
+                                 int32_t n, int32_t m0, int32_t m1, uint32_t flags, kbe_c128 *IR,
+                                 kbe_c128 *IL, kbe_c128 *Itv, kbe_c128 *Jtv, void *stream);
 
 /* ---------------------------------------------------------------------------
  * kbe_collision_vjp — adjoint of kbe_collision (a project addition to the

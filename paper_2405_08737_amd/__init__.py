@@ -68,7 +68,8 @@ class _BatchVjpItem(ctypes.Structure):
 
 
 EXPORTS = ("kbe_weights_workspace", "kbe_weights", "kbe_sigma_2b", "kbe_collision_workspace",
-           "kbe_collision", "kbe_collision_vjp_workspace", "kbe_collision_vjp",
+           "kbe_collision", "kbe_collision_noalloc", "kbe_collision_vjp_workspace",
+           "kbe_collision_vjp",
            "kbe_sigma_2b_vjp_workspace", "kbe_sigma_2b_vjp", "kbe_sigma_2b_full",
            "kbe_sigma_gf2_workspace",
            "kbe_sigma_gf2", "kbe_collision_batch_workspace",
@@ -98,6 +99,7 @@ def lib():
             "kbe_sigma_gf2": (I32, [G, P, I32, R, P, SZ, P]),
             "kbe_collision_workspace": (SZ, [I32, I32, I32, I32, I32, I32, U32]),
             "kbe_collision": (I32, [G, R, W, I32, I32, I32, U32, P, P, P, P, P, SZ, P]),
+            "kbe_collision_noalloc": (I32, [G, R, W, I32, I32, I32, U32, P, P, P, P, P]),
             "kbe_collision_vjp_workspace": (SZ, [I32, I32, I32, I32, I32, I32, U32]),
             "kbe_collision_vjp": (I32, [G, R, W, I32, I32, I32, U32, P, P, P, P, G, R, P, SZ, P]),
             "kbe_sigma_2b_vjp_workspace": (SZ, [I32, I32, I32]),
@@ -264,6 +266,25 @@ def collision(G: Green, sig, W: Weights, n: int, m0: int = 0, m1: Optional[int] 
     _check(L.kbe_collision(ctypes.byref(G.c()), ctypes.byref(row), ctypes.byref(W.c()), n, m0, m1,
                            flags, _ptr(IR), _ptr(IL), _ptr(Itv), _ptr(Jtv), _ptr(ws), nb,
                            _stream(dev)), "kbe_collision")
+    return IR, IL, Itv, Jtv
+
+
+def collision_noalloc(G: Green, sig, W: Weights, n: int, m0: int = 0, m1: Optional[int] = None,
+                      flags: int = OUT_ALL, out=None):
+    """kbe_collision_noalloc: kbe_collision with the library's fixed scratch array as workspace.
+    out: optional preallocated (IR, IL, Itv, Jtv) (created here when None)."""
+    m1 = n + 1 if m1 is None else m1
+    N, dev, M = G.N, G.device, m1 - m0
+    if out is None:
+        mk = lambda k: torch.empty((k, N, N), dtype=torch.complex128, device=dev)
+        out = (mk(M) if flags & OUT_IR else None, mk(M) if flags & OUT_IL else None,
+               mk(M) if flags & OUT_ITV else None,
+               mk(G.ntau) if (flags & OUT_JTV) and G.ntau else None)
+    IR, IL, Itv, Jtv = out
+    _check(lib().kbe_collision_noalloc(ctypes.byref(G.c()), ctypes.byref(_row(*sig)),
+                                       ctypes.byref(W.c()), n, m0, m1, flags, _ptr(IR), _ptr(IL),
+                                       _ptr(Itv), _ptr(Jtv), _stream(dev)),
+           "kbe_collision_noalloc")
     return IR, IL, Itv, Jtv
 
 

@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -241,6 +242,71 @@ kbe_status kbe_collision(const kbe_green *G, const kbe_sigma_row *S, const kbe_w
   kbe::Params p = make_params(G, S, W, n, m0, m1, flags);
   return hip_status(kbe::launch_collision(p, flags, IR, IL, Itv, Jtv, ws, (hipStream_t)stream),
                     "kbe_collision");
+}
+
+// ---------------------------------------------------------------------------------------
+// kbe_collision_noalloc: kbe_collision with its workspace in a fixed device array.
+//
+// `scratch` is the array; each device the library runs on holds its own copy from the time
+// the library's code object is loaded there until the process ends.  In host code the name is
+// only a host-side stand-in: the device address comes from hipGetSymbolAddress, taken once per
+// device with that device current and kept in g_scratch_dev, and only that address is handed to
+// the kernels.
+// ---------------------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[KBE_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices];
+
+// Device address of `scratch` on the device that owns `stream` (the current device for the
+// NULL stream).
+kbe_status scratch_address(hipStream_t stream, void **out) {
+  int cur = 0, dev = 0;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return hip_status(e, "hipGetDevice");
+  dev = cur;
+  if (stream) {
+    e = hipStreamGetDevice(stream, &dev);
+    if (e != hipSuccess) return hip_status(e, "hipStreamGetDevice");
+  }
+  if (dev < 0 || dev >= kMaxDevices) return fail(KBE_ENOTSUP, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    if (dev != cur && (e = hipSetDevice(dev)) != hipSuccess) return hip_status(e, "hipSetDevice");
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    const hipError_t r = dev != cur ? hipSetDevice(cur) : hipSuccess;
+    if (e != hipSuccess) return hip_status(e, "hipGetSymbolAddress(scratch)");
+    if (r != hipSuccess) return hip_status(r, "hipSetDevice");
+    if (!ptr) return fail(KBE_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_dev[dev] = ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return KBE_OK;
+}
+}  // namespace
+
+kbe_status kbe_collision_noalloc(const kbe_green *G, const kbe_sigma_row *S, const kbe_wts *W,
+                                 int32_t n, int32_t m0, int32_t m1, uint32_t flags, kbe_c128 *IR,
+                                 kbe_c128 *IL, kbe_c128 *Itv, kbe_c128 *Jtv, void *stream) {
+  kbe_status s = check_common(G, S, W, n, m0, m1, flags);
+  if (s != KBE_OK) return s;
+  const bool M = m1 > m0;
+  if ((flags & KBE_OUT_IR) && M && !IR) return fail(KBE_EINVAL, "IR is NULL");
+  if ((flags & KBE_OUT_IL) && M && !IL) return fail(KBE_EINVAL, "IL is NULL");
+  if ((flags & KBE_OUT_ITV) && M && !Itv) return fail(KBE_EINVAL, "Itv is NULL");
+  if ((flags & KBE_OUT_JTV) && G->ntau > 0 && !Jtv) return fail(KBE_EINVAL, "Jtv is NULL");
+  const size_t need = kbe_collision_workspace(G->N, G->nt, G->ntau, n, m0, m1, flags);
+  if (need > (size_t)KBE_NOALLOC_SCRATCH_BYTES)
+    return fail(KBE_ENOMEM, "this call needs %zu bytes of scratch, more than the fixed %zu",
+                need, (size_t)KBE_NOALLOC_SCRATCH_BYTES);
+  void *ws = nullptr;
+  if ((s = scratch_address((hipStream_t)stream, &ws)) != KBE_OK) return s;
+  kbe::Params p = make_params(G, S, W, n, m0, m1, flags);
+  return hip_status(kbe::launch_collision(p, flags, IR, IL, Itv, Jtv, ws, (hipStream_t)stream),
+                    "kbe_collision_noalloc");
 }
 
 size_t kbe_collision_vjp_workspace(int32_t N, int32_t nt, int32_t ntau, int32_t n, int32_t m0,
