@@ -165,11 +165,51 @@ typedef struct {
  * bytes.  The host arrays may be released when the call returns.
  * Errors: KBE_EINVAL for NULL pointers, nt < 1, t[0] != 0, t not strictly
  * increasing, ntau == 1, beta <= 0; KBE_ERANGE for an order outside
- * 1..KBE_KMAX; KBE_ENOMEM for a short workspace.
+ * 1..KBE_KMAX; KBE_ENOMEM for a short workspace; KBE_ENOTSUP when `stream` is
+ * being captured into a HIP graph (the call copies host memory: use
+ * kbe_weights_dev there).
  * ------------------------------------------------------------------------- */
 size_t kbe_weights_workspace(const kbe_grid *g);
 kbe_status kbe_weights(const kbe_grid *g, double *w, double *wtau, double *wtau_fwd, void *ws,
                        size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * kbe_weights_dev — kbe_weights for a grid already in device memory: the same
+ * weights, with no host copy and no synchronisation, so the call can be
+ * captured in a HIP graph (with the calls that use the weights).
+ *
+ * Arguments: t device [nt], order device [nt] (as in kbe_grid); ntau, beta,
+ * tau_order as in kbe_grid; w, wtau, wtau_fwd device outputs as for
+ * kbe_weights; status: optional device int32 (NULL: no check) that receives 0
+ * for a valid grid, KBE_EINVAL if t[0] != 0 or t is not strictly increasing,
+ * KBE_ERANGE for an order outside 1..KBE_KMAX (the weights of such a grid are
+ * computed with the orders clamped into range and are not meaningful); ws a
+ * device workspace of kbe_weights_dev_workspace(nt, ntau) bytes.
+ * Errors (returned, nothing enqueued): KBE_EINVAL for NULL pointers, nt < 1,
+ * ntau == 1, beta <= 0 with ntau > 0; KBE_ERANGE for tau_order outside
+ * 1..KBE_KMAX; KBE_ENOMEM for a short workspace.
+ * ------------------------------------------------------------------------- */
+size_t kbe_weights_dev_workspace(int32_t nt, int32_t ntau);
+kbe_status kbe_weights_dev(const double *t, const int32_t *order, int32_t nt, int32_t ntau,
+                           double beta, int32_t tau_order, double *w, double *wtau,
+                           double *wtau_fwd, int32_t *status, void *ws, size_t ws_bytes,
+                           void *stream);
+
+/* ---------------------------------------------------------------------------
+ * kbe_step_weights — the local weights of Eq. weights for every interval and
+ * every node count: lam[p][k-1][i] (i < k) integrates over [t_{p-1}, t_p] the
+ * Lagrange interpolant through the k nodes t_{p-k+1..p}, for
+ * k = 1..min(order[p], p+1); other entries (and row p = 0) are zero.  With
+ * k = min(order[p], p+1) these are the local weights that the history rows of
+ * kbe_weights add up; smaller k are the rules kbe_propagate uses for elements
+ * whose history begins inside the window.
+ *
+ * Arguments: t, order device [nt]; lam device [nt][KBE_KMAX][KBE_KMAX];
+ * status optional, as for kbe_weights_dev.  No workspace.  Capturable.
+ * Errors: KBE_EINVAL for NULL pointers or nt < 1.
+ * ------------------------------------------------------------------------- */
+kbe_status kbe_step_weights(const double *t, const int32_t *order, int32_t nt, double *lam,
+                            int32_t *status, void *stream);
 
 /* ---------------------------------------------------------------------------
  * kbe_sigma_2b — second-Born self-energy row at t_n (Eq. SE).
@@ -458,6 +498,72 @@ size_t kbe_collision_batch_vjp_workspace(int32_t count);
 kbe_status kbe_collision_batch_vjp(const kbe_batch_vjp_item *items,
                                    const kbe_batch_vjp_item *items_dev, int32_t count, void *ws,
                                    size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Fixed-grid propagation of the Kadanoff-Baym equations and its adjoint (a
+ * project addition built on the hot path: gradients of observables with
+ * respect to the interaction and a drive, through a whole propagation).
+ *
+ * The paper propagates G^< above the diagonal (Eq. KBE1), G^> below it
+ * (Eq. KBE2) and G^] (Eq. KBE3) as one growing state vector (Sec. "Adaptive
+ * Time Stepping"); here the grid and the orders are fixed.  The unknowns are
+ * the KP storage of G: at step n the new column kp[m][n] = G^<(t_m,t_n)
+ * (m <= n), the new row kp[n][m] = G^R(t_n,t_m) (m < n) and tv[n][j]; each
+ * block obeys an ODE in t_n whose right side takes the history sums of
+ * kbe_collision in the lesser form (C^< = I^R + I^< + I^]) and the greater
+ * form (C^>), J^] of Eq. KBE3, the second-Born row of kbe_sigma_2b and the
+ * Fock matrix of Eq. eps for a local interaction with a Gaussian pulse:
+ *   eps(t) = h0 + A exp(-(t - t0)^2 / (2 s^2)) e_00 + diag(-i u_i G^<_ii(t,t)),
+ *   d/dt_n kp[m][n] = i (kp[m][n] eps - C^<(n,m)^dagger)                (m < n)
+ *   d/dt_n kp[n][m] = -i (eps kp[n][m] + C^>(n,m) - C^<(n,m))           (m < n)
+ *   d/dt_n kp[n][n] = -i [eps, kp[n][n]] - i (C^<(n,n) + C^<(n,n)^dagger)
+ *   d/dt_n tv[n][j] = -i (eps tv[n][j] + J^](n,j)).
+ * kp[m][.] and kp[.][m] start at t_m from kp[m][m] and -i.  Every block
+ * advances over [t_{n-1}, t_n] by the implicit Adams-Moulton rule in Lagrange
+ * form with the local weights of Eq. weights on min(order[n], n - b + 1)
+ * nodes (b: the step where the block's history begins), solved by `iters`
+ * fixed-point iterations from an explicit Euler predictor; the right sides
+ * kept for later steps are evaluated once more at the accepted values.  The
+ * initial state follows Eq. BC: rdiag = -i 1, and with a thermal branch
+ * tv[0][j] = -i G^M(beta - tau_j) = -i mat[ntau-1-j] and
+ * kp[0][0] = -tv[0][0]^dagger; without one, kp[0][0] = G^<(0,0) = i rho(0)
+ * is read from G.  The observable is the density n_i(t_n) = Re(-i G^<_ii).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t iters;         /* fixed-point iterations per step, >= 1 */
+  const double *h0;      /* device [N][N], real symmetric */
+  const double *u;       /* device [N], local interaction (a scalar U fills every entry) */
+  double pulse_amp;      /* A */
+  double pulse_t0;       /* centre t0 */
+  double pulse_sigma;    /* width s > 0 */
+  const double *t;       /* device [nt], the grid (t[0] = 0) */
+  const int32_t *order;  /* device [nt], nodes per interval (as in kbe_grid) */
+  const double *lam;     /* device [nt][KBE_KMAX][KBE_KMAX], from kbe_step_weights(t, order) */
+} kbe_prop;
+
+/* kbe_propagate: runs the propagation over the whole grid.  G (device, N,
+ * nt, ntau, ldt as for the other calls): mat holds G^M (read); kp, rdiag, tv
+ * are written with the solution (kp[0][0] read first when ntau == 0).  W: the
+ * weights of the same grid (kbe_weights / kbe_weights_dev).  dens: device
+ * [nt][N] output, n_i(t_n).  ws: kbe_propagate_workspace(...) bytes; it keeps
+ * the right-side history and the fixed-point iterates that
+ * kbe_propagate_vjp needs.  Errors: KBE_EINVAL (NULL pointers, bad shapes,
+ * iters < 1, pulse_sigma <= 0), KBE_ENOMEM (workspace). */
+size_t kbe_propagate_workspace(int32_t N, int32_t nt, int32_t ntau, int64_t ldt, int32_t iters);
+kbe_status kbe_propagate(const kbe_prop *P, const kbe_wts *W, const kbe_green *G, double *dens,
+                         void *ws, size_t ws_bytes, void *stream);
+
+/* kbe_propagate_vjp: the adjoint of kbe_propagate.  Given gdens (device
+ * [nt][N], the gradient of a real loss with respect to dens), writes
+ * gu (device [N]) = dL/du_i and gamp (device, one double) = dL/dA, exact
+ * derivatives of the discrete propagation (every self-energy row is
+ * recomputed from the stored iterates; the collision and self-energy adjoints
+ * run on the same kernels as kbe_collision_vjp and kbe_sigma_2b_vjp).  P, W,
+ * G and ws must be those of the kbe_propagate call, unchanged since: G holds
+ * the solution again when the call returns.  Errors: as kbe_propagate. */
+kbe_status kbe_propagate_vjp(const kbe_prop *P, const kbe_wts *W, const kbe_green *G,
+                             const double *gdens, double *gu, double *gamp, void *ws,
+                             size_t ws_bytes, void *stream);
 
 /* Human-readable name of a status code (static string). */
 const char *kbe_status_string(kbe_status s);

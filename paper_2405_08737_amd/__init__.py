@@ -35,6 +35,13 @@ class KBEError(RuntimeError):
     pass
 
 
+class _Prop(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("h0", ctypes.c_void_p), ("u", ctypes.c_void_p),
+                ("pulse_amp", ctypes.c_double), ("pulse_t0", ctypes.c_double),
+                ("pulse_sigma", ctypes.c_double), ("t", ctypes.c_void_p),
+                ("order", ctypes.c_void_p), ("lam", ctypes.c_void_p)]
+
+
 class _Green(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int32), ("nt", ctypes.c_int32), ("ntau", ctypes.c_int32),
                 ("ldt", ctypes.c_int64), ("kp", ctypes.c_void_p), ("rdiag", ctypes.c_void_p),
@@ -75,6 +82,8 @@ EXPORTS = ("kbe_weights_workspace", "kbe_weights", "kbe_sigma_2b", "kbe_collisio
            "kbe_sigma_gf2", "kbe_collision_batch_workspace",
            "kbe_collision_batch", "kbe_collision_batch_tune", "kbe_collision_batch_tune_groups",
            "kbe_collision_batch_vjp_workspace", "kbe_collision_batch_vjp",
+           "kbe_weights_dev_workspace", "kbe_weights_dev", "kbe_step_weights",
+           "kbe_propagate_workspace", "kbe_propagate", "kbe_propagate_vjp",
            "kbe_status_string",
            "kbe_last_error", "kbe_version")
 
@@ -110,6 +119,12 @@ def lib():
             "kbe_collision_batch_tune_groups": (I32, [P, P, I32, P, SZ, P, P]),
             "kbe_collision_batch_vjp_workspace": (SZ, [I32]),
             "kbe_collision_batch_vjp": (I32, [P, P, I32, P, SZ, P]),
+            "kbe_weights_dev_workspace": (SZ, [I32, I32]),
+            "kbe_weights_dev": (I32, [P, P, I32, I32, ctypes.c_double, I32, P, P, P, P, P, SZ, P]),
+            "kbe_step_weights": (I32, [P, P, I32, P, P, P]),
+            "kbe_propagate_workspace": (SZ, [I32, I32, I32, I64, I32]),
+            "kbe_propagate": (I32, [ctypes.POINTER(_Prop), W, G, P, P, SZ, P]),
+            "kbe_propagate_vjp": (I32, [ctypes.POINTER(_Prop), W, G, P, P, P, P, SZ, P]),
             "kbe_status_string": (ctypes.c_char_p, [I32]),
             "kbe_last_error": (ctypes.c_char_p, []),
             "kbe_version": (I32, []),
@@ -167,6 +182,11 @@ class Green:
         return self.kp.device
 
     def c(self) -> _Green:
+        for name in ("kp", "rdiag", "tv", "mat"):
+            x = getattr(self, name)
+            if x is not None and (x.dtype != torch.complex128 or not x.is_contiguous()):
+                raise TypeError(f"Green.{name} must be a contiguous complex128 tensor "
+                                f"(got {x.dtype})")
         return _Green(self.N, self.nt, self.ntau, self.kp.shape[1], _ptr(self.kp),
                       _ptr(self.rdiag), _ptr(self.tv), _ptr(self.mat))
 
@@ -555,3 +575,115 @@ class BatchVJP:
                                              _ptr(self.ws), self.ws_bytes,
                                              _stream(self.device)), "kbe_collision_batch_vjp")
         return self.g
+
+
+# ------------------------------------------------------------------------------------------------
+# Grid on the device; fixed-grid propagation and its adjoint.
+# ------------------------------------------------------------------------------------------------
+KMAX = 20
+
+
+def weights_dev(t: torch.Tensor, order: torch.Tensor, ntau: int = 0, beta: float = 0.0,
+                tau_order: int = 5, check: bool = True) -> Weights:
+    """kbe_weights_dev: the weights of a grid held in device memory (t float64, order int32).
+    With check, the device-side grid status is read back and a bad grid raises."""
+    nt, dev = t.shape[0], t.device
+    w = torch.empty((nt, nt), dtype=torch.float64, device=dev)
+    wtau = torch.empty(ntau, dtype=torch.float64, device=dev) if ntau > 0 else None
+    wf = torch.empty((ntau, ntau), dtype=torch.float64, device=dev) if ntau > 0 else None
+    status = torch.zeros(1, dtype=torch.int32, device=dev) if check else None
+    L = lib()
+    nb = L.kbe_weights_dev_workspace(nt, ntau)
+    ws = _ws(nb, dev)
+    _check(L.kbe_weights_dev(_ptr(t), _ptr(order), nt, ntau, float(beta), int(tau_order), _ptr(w),
+                             _ptr(wtau), _ptr(wf), _ptr(status), _ptr(ws), nb, _stream(dev)),
+           "kbe_weights_dev")
+    if check and int(status.item()) != 0:
+        raise KBEError(f"kbe_weights_dev: grid status {int(status.item())}")
+    return Weights(w, wtau, wf)
+
+
+def step_weights(t: torch.Tensor, order: torch.Tensor) -> torch.Tensor:
+    """kbe_step_weights: lam [nt, KMAX, KMAX] local weights for every interval and node count."""
+    nt, dev = t.shape[0], t.device
+    lam = torch.empty((nt, KMAX, KMAX), dtype=torch.float64, device=dev)
+    _check(lib().kbe_step_weights(_ptr(t), _ptr(order), nt, _ptr(lam), None, _stream(dev)),
+           "kbe_step_weights")
+    return lam
+
+
+class Propagation:
+    """A fixed-grid propagation problem on the device (kbe_propagate / kbe_propagate_vjp).
+
+    t, order: the grid (host arrays); h0 [N, N] real; ntau, beta, tau_order: the thermal branch;
+    mat [ntau, N, N] complex (G^M, the initial state) or, without a thermal branch, rho0 [N, N]
+    (G^<(0,0) = i rho0); iters: fixed-point iterations per step; the pulse is
+    amp * exp(-(t - pulse_t0)^2 / (2 pulse_sigma^2)) on h0[0][0]."""
+
+    def __init__(self, t, order, h0, ntau=0, beta=1.0, tau_order=5, mat=None, rho0=None,
+                 iters=2, pulse_t0=2.0, pulse_sigma=1.0, device="cuda:0"):
+        import numpy as np
+        dev = torch.device(device)
+        self.device = dev
+        h0 = np.ascontiguousarray(h0, np.float64)
+        N, nt = h0.shape[0], len(t)
+        self.N, self.nt, self.ntau, self.iters = N, nt, ntau, int(iters)
+        self.t = torch.tensor(np.asarray(t, np.float64), device=dev)
+        self.order = torch.tensor(np.asarray(order, np.int32), device=dev)
+        self.h0 = torch.tensor(h0, device=dev)
+        self.pulse_t0, self.pulse_sigma = float(pulse_t0), float(pulse_sigma)
+        self.W = weights_dev(self.t, self.order, ntau, beta, tau_order)
+        self.lam = step_weights(self.t, self.order)
+        z = lambda *sh: torch.zeros(sh, dtype=torch.complex128, device=dev)
+        self.G = Green(z(nt, nt, N, N), z(nt, N, N), z(nt, ntau, N, N) if ntau else None,
+                       torch.tensor(np.asarray(mat, np.complex128), device=dev) if ntau else None)
+        if not ntau:
+            self.G.kp[0, 0] = 1j * torch.tensor(np.asarray(rho0, np.complex128), device=dev)
+        self.dens = torch.empty((nt, N), dtype=torch.float64, device=dev)
+        L = lib()
+        self.nb = L.kbe_propagate_workspace(N, nt, ntau, nt, self.iters)
+        self.ws = _ws(self.nb, dev)
+        self._u = None
+        self._amp = None
+
+    def _p(self, u: torch.Tensor, amp: float) -> _Prop:
+        self._u = u
+        return _Prop(self.iters, _ptr(self.h0), _ptr(u), float(amp), self.pulse_t0,
+                     self.pulse_sigma, _ptr(self.t), _ptr(self.order), _ptr(self.lam))
+
+    def run(self, u: torch.Tensor, amp: float) -> torch.Tensor:
+        """kbe_propagate: densities n_i(t_n) [nt, N]; the solution is left in self.G."""
+        u = u.detach().to(device=self.device, dtype=torch.float64).contiguous()
+        self._amp = float(amp)
+        P = self._p(u, amp)
+        _check(lib().kbe_propagate(ctypes.byref(P), ctypes.byref(self.W.c()),
+                                   ctypes.byref(self.G.c()), _ptr(self.dens), _ptr(self.ws),
+                                   self.nb, _stream(self.device)), "kbe_propagate")
+        return self.dens
+
+    def vjp(self, gdens: torch.Tensor):
+        """kbe_propagate_vjp after run(): (dL/du [N], dL/dA) for the cotangent gdens [nt, N]."""
+        gdens = gdens.detach().to(device=self.device, dtype=torch.float64).contiguous()
+        gu = torch.empty(self.N, dtype=torch.float64, device=self.device)
+        ga = torch.empty(1, dtype=torch.float64, device=self.device)
+        P = self._p(self._u, self._amp)
+        _check(lib().kbe_propagate_vjp(ctypes.byref(P), ctypes.byref(self.W.c()),
+                                       ctypes.byref(self.G.c()), _ptr(gdens), _ptr(gu), _ptr(ga),
+                                       _ptr(self.ws), self.nb, _stream(self.device)),
+               "kbe_propagate_vjp")
+        return gu, ga[0]
+
+
+class KBEPropagate(torch.autograd.Function):
+    """dens = KBEPropagate.apply(prop, u, amp): differentiable in u [N] and amp (0-dim tensor)."""
+
+    @staticmethod
+    def forward(ctx, prop: Propagation, u, amp):
+        ctx.prop = prop
+        return prop.run(u, float(amp)).clone()
+
+    @staticmethod
+    def backward(ctx, gdens):
+        gu, ga = ctx.prop.vjp(gdens)
+        return None, gu, ga
+

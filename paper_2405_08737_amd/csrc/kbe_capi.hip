@@ -153,7 +153,13 @@ kbe_status kbe_weights(const kbe_grid *g, double *w, double *wtau, double *wtau_
   }
   const size_t need = kbe_weights_workspace(g);
   if (!ws || ws_bytes < need) return fail(KBE_ENOMEM, "workspace %zu bytes < %zu", ws_bytes, need);
-  hipError_t e = kbe::launch_weights(g, w, wtau, wtau_fwd, ws, (hipStream_t)stream);
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing((hipStream_t)stream, &cap);
+  if (e != hipSuccess) return hip_status(e, "kbe_weights");
+  if (cap != hipStreamCaptureStatusNone)
+    return fail(KBE_ENOTSUP, "kbe_weights copies host memory and cannot be captured: use "
+                             "kbe_weights_dev");
+  e = kbe::launch_weights(g, w, wtau, wtau_fwd, ws, (hipStream_t)stream);
   return hip_status(e, "kbe_weights");
 }
 
@@ -344,6 +350,94 @@ kbe_status kbe_collision_vjp(const kbe_green *G, const kbe_sigma_row *S, const k
   p.gtv = gG->tv;
   return hip_status(kbe::launch_collision_vjp(p, flags, gG->mat, gS, ws, (hipStream_t)stream),
                     "kbe_collision_vjp");
+}
+
+// ---------------------------------------------------------------------------------------
+// Weights from a device-resident grid; step weights; the fixed-grid propagation.
+// ---------------------------------------------------------------------------------------
+size_t kbe_weights_dev_workspace(int32_t nt, int32_t ntau) {
+  if (nt < 1 || ntau < 0) return 0;
+  return kbe::weights_ws_bytes(nt, ntau);
+}
+
+kbe_status kbe_weights_dev(const double *t, const int32_t *order, int32_t nt, int32_t ntau,
+                           double beta, int32_t tau_order, double *w, double *wtau,
+                           double *wtau_fwd, int32_t *status, void *ws, size_t ws_bytes,
+                           void *stream) {
+  if (!t || !order || !w) return fail(KBE_EINVAL, "t, order or w is NULL");
+  if (nt < 1) return fail(KBE_EINVAL, "nt = %d < 1", nt);
+  if (ntau < 0 || ntau == 1) return fail(KBE_EINVAL, "ntau = %d (must be 0 or >= 2)", ntau);
+  if (ntau > 0) {
+    if (!(beta > 0)) return fail(KBE_EINVAL, "beta = %g <= 0", beta);
+    if (tau_order < 1 || tau_order > KBE_KMAX)
+      return fail(KBE_ERANGE, "tau_order = %d outside 1..%d", tau_order, KBE_KMAX);
+    if (!wtau || !wtau_fwd) return fail(KBE_EINVAL, "wtau or wtau_fwd is NULL with ntau > 0");
+  }
+  const size_t need = kbe_weights_dev_workspace(nt, ntau);
+  if (!ws || ws_bytes < need) return fail(KBE_ENOMEM, "workspace %zu bytes < %zu", ws_bytes, need);
+  hipStream_t st = (hipStream_t)stream;
+  if (status) {
+    hipError_t e = kbe::launch_grid_check(t, order, nt, status, st);
+    if (e != hipSuccess) return hip_status(e, "kbe_weights_dev");
+  }
+  return hip_status(kbe::launch_weights_dev(t, order, nt, ntau, beta, tau_order, w, wtau,
+                                            wtau_fwd, ws, st),
+                    "kbe_weights_dev");
+}
+
+kbe_status kbe_step_weights(const double *t, const int32_t *order, int32_t nt, double *lam,
+                            int32_t *status, void *stream) {
+  if (!t || !order || !lam) return fail(KBE_EINVAL, "t, order or lam is NULL");
+  if (nt < 1) return fail(KBE_EINVAL, "nt = %d < 1", nt);
+  hipStream_t st = (hipStream_t)stream;
+  if (status) {
+    hipError_t e = kbe::launch_grid_check(t, order, nt, status, st);
+    if (e != hipSuccess) return hip_status(e, "kbe_step_weights");
+  }
+  return hip_status(kbe::launch_step_weights(t, order, nt, lam, st), "kbe_step_weights");
+}
+
+size_t kbe_propagate_workspace(int32_t N, int32_t nt, int32_t ntau, int64_t ldt, int32_t iters) {
+  if (N < 1 || N > KBE_NMAX || nt < 1 || ntau < 0 || ntau == 1 || ldt < nt || iters < 1) return 0;
+  return kbe::prop_ws_bytes(N, nt, ntau, ldt, iters);
+}
+
+namespace {
+kbe_status check_prop(const kbe_prop *P, const kbe_wts *W, const kbe_green *G, size_t ws_bytes,
+                      const void *ws) {
+  kbe_status s = check_green(G, "G");
+  if (s != KBE_OK) return s;
+  if (!P || !W) return fail(KBE_EINVAL, "P or W is NULL");
+  if (P->iters < 1) return fail(KBE_EINVAL, "iters = %d < 1", P->iters);
+  if (!P->h0 || !P->u || !P->t || !P->order || !P->lam)
+    return fail(KBE_EINVAL, "P->h0, u, t, order or lam is NULL");
+  if (!(P->pulse_sigma > 0)) return fail(KBE_EINVAL, "pulse_sigma = %g <= 0", P->pulse_sigma);
+  if (!W->w) return fail(KBE_EINVAL, "W->w is NULL");
+  if (G->ntau > 0 && (!W->wtau || !W->wtau_fwd))
+    return fail(KBE_EINVAL, "tau weights are NULL with ntau > 0");
+  const size_t need = kbe_propagate_workspace(G->N, G->nt, G->ntau, G->ldt, P->iters);
+  if (!ws || ws_bytes < need) return fail(KBE_ENOMEM, "workspace %zu bytes < %zu", ws_bytes, need);
+  return KBE_OK;
+}
+}  // namespace
+
+kbe_status kbe_propagate(const kbe_prop *P, const kbe_wts *W, const kbe_green *G, double *dens,
+                         void *ws, size_t ws_bytes, void *stream) {
+  kbe_status s = check_prop(P, W, G, ws_bytes, ws);
+  if (s != KBE_OK) return s;
+  if (!dens) return fail(KBE_EINVAL, "dens is NULL");
+  return hip_status(kbe::launch_propagate(P, W, G, dens, ws, (hipStream_t)stream),
+                    "kbe_propagate");
+}
+
+kbe_status kbe_propagate_vjp(const kbe_prop *P, const kbe_wts *W, const kbe_green *G,
+                             const double *gdens, double *gu, double *gamp, void *ws,
+                             size_t ws_bytes, void *stream) {
+  kbe_status s = check_prop(P, W, G, ws_bytes, ws);
+  if (s != KBE_OK) return s;
+  if (!gdens || !gu || !gamp) return fail(KBE_EINVAL, "gdens, gu or gamp is NULL");
+  return hip_status(kbe::launch_propagate_vjp(P, W, G, gdens, gu, gamp, ws, (hipStream_t)stream),
+                    "kbe_propagate_vjp");
 }
 
 // ---------------------------------------------------------------------------------------

@@ -13,6 +13,13 @@ struct Params;
 size_t weights_ws_bytes(int nt, int ntau);
 hipError_t launch_weights(const kbe_grid *g, double *w, double *wtau, double *wf, void *ws,
                           hipStream_t st);
+hipError_t launch_weights_dev(const double *t_d, const int32_t *o_d, int nt, int ntau,
+                              double beta, int tau_order, double *w, double *wtau, double *wf,
+                              void *ws, hipStream_t st);
+hipError_t launch_grid_check(const double *t, const int32_t *order, int nt, int32_t *status,
+                             hipStream_t st);
+hipError_t launch_step_weights(const double *t, const int32_t *order, int nt, double *lam,
+                               hipStream_t st);
 
 // Self-energy and its adjoint (kbe_sigma.hip).
 hipError_t launch_sigma_row(const kbe_green *G, const double *u, int n, const kbe_sigma_row *out,
@@ -45,6 +52,14 @@ hipError_t launch_batch(const kbe_batch_item *items, const kbe_batch_item *items
 size_t batch_vjp_ws_bytes(int count);
 hipError_t launch_batch_vjp(const kbe_batch_vjp_item *items_dev, int count, void *ws,
                             hipStream_t st);
+
+// Fixed-grid propagation and its adjoint (kbe_prop.hip).
+size_t prop_ws_bytes(int N, int nt, int ntau, int64_t ldt, int K);
+hipError_t launch_propagate(const kbe_prop *P, const kbe_wts *W, const kbe_green *G,
+                            double *dens, void *ws, hipStream_t st);
+hipError_t launch_propagate_vjp(const kbe_prop *P, const kbe_wts *W, const kbe_green *G,
+                                const double *gdens, double *gu, double *gamp, void *ws,
+                                hipStream_t st);
 
 }  // namespace kbe
 

@@ -1,0 +1,825 @@
+// Fixed-grid propagation of the Kadanoff-Baym equations and its adjoint, on gfx950.
+//
+// arXiv:2405.08737 propagates G^< above the t = t' diagonal (Eq. KBE1) and G^> below it
+// (Eq. KBE2), with G^] (Eq. KBE3), stacked as one state vector in a single time variable: the
+// values of the newest row and column.  Here the grid and the orders are fixed, and the
+// unknowns are the library's KP storage (kp[m][n] = G^<(t_m,t_n) for m <= n, kp[n][m] =
+// G^R(t_n,t_m) = G^> - G^< for m < n, rdiag = G^R(t,t) = -i, tv[n][j] = G^](t_n,tau_j)).  The
+// state of step n consists of these elements, each an N x N block obeying an ODE in t~ = t_n:
+//   U_m  kp[m][n]  f = i (kp[m][n] eps - C^<(n,m)^dagger)                  (Eq. KBE1 at (t_m,t~))
+//   R_m  kp[n][m]  f = -i (eps kp[n][m] + C^>(n,m) - C^<(n,m))             (Eq. KBE2, G^> - G^<)
+//   D    kp[n][n]  f = -i [eps, kp[n][n]] - i (C^<(n,n) + C^<(n,n)^dagger) (both derivatives)
+//   T_j  tv[n][j]  f = -i (eps tv[n][j] + J^](n,j))                        (Eq. KBE3)
+// C^< = I^R + I^< + I^] is the lesser-form history sum of kbe_collision at (t_n,t_m), C^> the
+// greater-form one (KBE_GREATER), J^] the Eq. KBE3 history terms, all on the self-energy row of
+// kbe_sigma_2b, and eps the Fock matrix of Eq. eps for a local interaction with a Gaussian
+// pulse on h_00:  eps = h0 + A exp(-(t-t0)^2 / (2 s^2)) e_00 + diag(-i u_i G^<_ii(t,t)).
+// U_m and R_m are born at t_m (values kp[m][m] and -i; their derivatives there, "birth
+// derivatives", come from the step that created them).
+//
+// Each element advances over [t_{n-1}, t_n] by the implicit Adams-Moulton rule in Lagrange form,
+// y_n = y_{n-1} + sum_i lam_i f(t_{n-k+1+i}), with the local weights of Eq. weights on the nodes
+// t_{n-k+1..n} (kbe_step_weights: the history integrals' rule of interval n) and k =
+// min(order[n], n - b + 1) for an element born at t_b.  The implicit equation is solved by K
+// fixed-point iterations from the explicit Euler predictor; the f values kept for later steps are
+// evaluated once more at the accepted values (P (EC)^K E).
+//
+// Every step runs on the library's kernels: kbe_sigma_2b's row kernel, the collision kernels
+// (lesser and greater form) and the small kernels below; the host only sequences launches on
+// one stream.  The adjoint runs the steps backwards, recomputing the self-energy rows from the
+// stored iterates and calling the collision and self-energy adjoints (kbe_collision_vjp,
+// kbe_sigma_2b_vjp), so that d(loss)/du and d(loss)/dA of a loss on the densities
+// n_i(t_n) = Re(-i G^<_ii(t_n,t_n)) are exact derivatives of the discrete map above.
+#include "kbe_dev.h"
+#include "kbe_internal.h"
+
+namespace kbe {
+namespace {
+
+constexpr int KM = KBE_KMAX;
+
+// Element kinds of a step (index e in [0, 2n+1+ntau), then the two birth derivatives).
+enum { EU = 0, ED = 1, ER = 2, ET = 3, EBU = 4, EBR = 5 };
+
+struct PA {                       // everything the small kernels read, passed by value
+  int N, nt, ntau, K;
+  int64_t ldt;                    // row stride of the solution's kp (blocks)
+  kbe_c128 *kp, *rdiag, *tv;      // the solution
+  const kbe_c128 *mat;
+  const double *h0, *u, *t, *lam;
+  const int32_t *order;
+  double amp, t0, sig;
+  kbe_c128 *fkp, *fbu, *fbr, *ftv;  // f history (compact, row stride nt)
+  kbe_c128 *ykp, *ytv;              // iterates y^(0..K) of each step's elements
+  kbe_c128 *eps;                    // [E]
+  kbe_c128 *IRl, *ILl, *Itv, *Jtv, *IRg, *ILg;  // history sums of the current evaluation
+  kbe_c128 *base, *ynext;           // [elements][E]
+  // adjoint
+  kbe_c128 *gkp, *gtv;              // gradient of the solution (same layout as kp, tv)
+  kbe_c128 *gfkp, *gfbu, *gfbr, *gftv;  // gradient of the f history
+  kbe_c128 *ybar, *bbar, *fbar, *epart;  // [elements][E]
+  kbe_c128 *CbL, *CbG, *CbT, *Jbar;      // cotangents of the history sums
+  kbe_c128 *gretL, *glesL, *gretG, *glesG;
+};
+
+__device__ __forceinline__ int64_t E_(const PA &a) { return (int64_t)a.N * a.N; }
+__device__ __forceinline__ int nelem(const PA &a, int n) { return 2 * n + 1 + a.ntau; }
+
+__device__ __forceinline__ void elem_of(const PA &a, int n, int e, int &kind, int &idx) {
+  const int ne = nelem(a, n);
+  if (e < n) { kind = EU; idx = e; }
+  else if (e == n) { kind = ED; idx = n; }
+  else if (e <= 2 * n) { kind = ER; idx = e - n - 1; }
+  else if (e < ne) { kind = ET; idx = e - 2 * n - 1; }
+  else if (e == ne) { kind = EBU; idx = n; }
+  else { kind = EBR; idx = n; }
+}
+
+__device__ __forceinline__ int birth(int kind, int idx) {
+  return (kind == EU || kind == ER) ? idx : 0;
+}
+
+// Nodes of the rule of interval n for an element born at t_b.
+__device__ __forceinline__ int nodes(const PA &a, int n, int b) {
+  int k = a.order[n];
+  k = k < 1 ? 1 : (k > KM ? KM : k);
+  return k < n - b + 1 ? k : n - b + 1;
+}
+__device__ __forceinline__ const double *lamrow(const PA &a, int n, int k) {
+  return a.lam + ((int64_t)n * KM + (k - 1)) * KM;
+}
+
+// The element's value at step n in the solution / in a gradient of the same layout.
+__device__ __forceinline__ int64_t val_off(const PA &a, int n, int kind, int idx, bool tvarr) {
+  (void)tvarr;
+  switch (kind) {
+    case EU: return ((int64_t)idx * a.ldt + n) * E_(a);
+    case ED: return ((int64_t)n * a.ldt + n) * E_(a);
+    case ER: return ((int64_t)n * a.ldt + idx) * E_(a);
+    default: return ((int64_t)n * a.ntau + idx) * E_(a);  // ET: in tv
+  }
+}
+__device__ __forceinline__ kbe_c128 *val_ptr(const PA &a, kbe_c128 *kp, kbe_c128 *tv, int n,
+                                             int kind, int idx) {
+  return (kind == ET ? tv : kp) + val_off(a, n, kind, idx, kind == ET);
+}
+// The element's iterate slot (compact layout, row stride nt).
+__device__ __forceinline__ kbe_c128 *slot_ptr(const PA &a, int slot, int n, int kind, int idx) {
+  const int64_t E = E_(a), nt = a.nt;
+  if (kind == ET) return a.ytv + (((int64_t)slot * nt + n) * a.ntau + idx) * E;
+  const int64_t base = (int64_t)slot * nt * nt;
+  switch (kind) {
+    case EU: return a.ykp + (base + (int64_t)idx * nt + n) * E;
+    case ED: return a.ykp + (base + (int64_t)n * nt + n) * E;
+    default: return a.ykp + (base + (int64_t)n * nt + idx) * E;  // ER
+  }
+}
+// f of the element at step j (j >= its birth); the same layout for the f history and its
+// gradient (pass the matching arrays).
+__device__ __forceinline__ kbe_c128 *f_ptr(const PA &a, kbe_c128 *fkp, kbe_c128 *fbu,
+                                           kbe_c128 *fbr, kbe_c128 *ftv, int j, int kind,
+                                           int idx) {
+  const int64_t E = E_(a), nt = a.nt;
+  switch (kind) {
+    case EU: return j == idx ? fbu + idx * E : fkp + ((int64_t)idx * nt + j) * E;
+    case ER: return j == idx ? fbr + idx * E : fkp + ((int64_t)j * nt + idx) * E;
+    case ED: return fkp + ((int64_t)j * nt + j) * E;
+    case ET: return ftv + ((int64_t)j * a.ntau + idx) * E;
+    case EBU: return fbu + (int64_t)j * E;
+    default: return fbr + (int64_t)j * E;  // EBR
+  }
+}
+// The element's value at t_{n-1} (its birth value for an element born there); nullptr for the
+// constant -i (R_{n-1}, born on the diagonal).
+__device__ __forceinline__ kbe_c128 *prev_ptr(const PA &a, kbe_c128 *kp, kbe_c128 *tv, int n,
+                                              int kind, int idx) {
+  const int64_t E = E_(a);
+  switch (kind) {
+    case EU: return kp + ((int64_t)idx * a.ldt + (n - 1)) * E;
+    case ED: return kp + ((int64_t)(n - 1) * a.ldt + (n - 1)) * E;
+    case ER: return idx < n - 1 ? kp + ((int64_t)(n - 1) * a.ldt + idx) * E : nullptr;
+    default: return tv + ((int64_t)(n - 1) * a.ntau + idx) * E;
+  }
+}
+
+__device__ __forceinline__ cd mul_i(cd z) { return {-z.im, z.re}; }    // i z
+__device__ __forceinline__ cd mul_mi(cd z) { return {z.im, -z.re}; }   // -i z
+
+__device__ __forceinline__ double pulse(const PA &a, int n) {
+  const double d = a.t[n] - a.t0;
+  return exp(-d * d / (2.0 * a.sig * a.sig));
+}
+
+// ---------------------------------------------------------------------------------------------
+// Forward kernels
+// ---------------------------------------------------------------------------------------------
+
+// Initial state (Eq. BC): rdiag = -i 1 at every t; with a thermal branch
+// G^](0,tau_j) = -i G^M(beta - tau_j) = -i mat[J-j] and G^<(0,0) = -G^](0,0)^dagger; without one
+// kp[0][0] = G^<(0,0) is the caller's.
+__global__ void prop_init(PA a) {
+  const int64_t E = E_(a);
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nrd = (int64_t)a.nt * E;
+  if (gid < nrd) {
+    const int q = (int)(gid % E), r = q / a.N, c = q % a.N;
+    st(a.rdiag + gid, {0.0, r == c ? -1.0 : 0.0});
+    return;
+  }
+  if (a.ntau == 0) return;
+  const int64_t g2 = gid - nrd;
+  const int J = a.ntau - 1;
+  if (g2 < (int64_t)a.ntau * E) {
+    const int j = (int)(g2 / E), q = (int)(g2 % E);
+    st(a.tv + g2, mul_mi(ld(a.mat + (int64_t)(J - j) * E + q)));
+    if (j == 0) {  // kp[0][0][r][c] = -conj(tv[0][0][c][r]) = -i conj(mat[J][c][r])
+      const int r = q / a.N, c = q % a.N;
+      st(a.kp + (int64_t)r * a.N + c, mul_mi(cj(ld(a.mat + (int64_t)J * E + c * a.N + r))));
+    }
+  }
+}
+
+// eps(t_n) from the current G^<(t_n,t_n).
+__global__ void prop_eps(PA a, int n) {
+  const int q = threadIdx.x;
+  const int64_t E = E_(a);
+  if (q >= E) return;
+  const int r = q / a.N, c = q % a.N;
+  cd e = {a.h0[q], 0.0};
+  if (r == 0 && c == 0) e.re += a.amp * pulse(a, n);
+  if (r == c) {
+    const cd d = ld(a.kp + ((int64_t)n * a.ldt + n) * E + (int64_t)r * a.N + r);
+    e = e + a.u[r] * mul_mi(d);
+  }
+  st(a.eps + q, e);
+}
+
+// Adams-Moulton base sums and explicit Euler predictors of step n; the predictor becomes the
+// current value of row/column n and iterate 0.
+__global__ void prop_predict(PA a, int n) {
+  const int64_t E = E_(a);
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)nelem(a, n) * E) return;
+  const int e = (int)(gid / E), q = (int)(gid % E);
+  int kind, idx;
+  elem_of(a, n, e, kind, idx);
+  const int b = birth(kind, idx), k = nodes(a, n, b);
+  const double *L = lamrow(a, n, k);
+  const double h = a.t[n] - a.t[n - 1];
+  const kbe_c128 *pp = prev_ptr(a, a.kp, a.tv, n, kind, idx);
+  const int r = q / a.N, c = q % a.N;
+  const cd prev = pp ? ld(pp + q) : cd{0.0, r == c ? -1.0 : 0.0};
+  cd base = prev;
+  for (int i = 0; i + 1 < k; ++i)
+    base = base + L[i] * ld(f_ptr(a, a.fkp, a.fbu, a.fbr, a.ftv, n - k + 1 + i, kind, idx) + q);
+  const cd pred = prev + h * ld(f_ptr(a, a.fkp, a.fbu, a.fbr, a.ftv, n - 1, kind, idx) + q);
+  st(a.base + gid, base);
+  st(val_ptr(a, a.kp, a.tv, n, kind, idx) + q, pred);
+  st(slot_ptr(a, 0, n, kind, idx) + q, pred);
+}
+
+// f of every element of step n at the current values.  mode 0: the next iterate base +
+// lam_last f into ynext; mode 1: the f history at t_n, birth derivatives included.
+__global__ void prop_rhs(PA a, int n, int mode) {
+  const int64_t E = E_(a);
+  const int N = a.N;
+  const int ne = nelem(a, n) + (mode ? 2 : 0);
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)ne * E) return;
+  const int e = (int)(gid / E), q = (int)(gid % E), r = q / N, c = q % N;
+  int kind, idx;
+  elem_of(a, n, e, kind, idx);
+  const bool th = a.ntau > 0;
+  auto Cl = [&](int m, int rr, int cc) {
+    const int64_t o = (int64_t)m * E + rr * N + cc;
+    cd s = ld(a.IRl + o) + ld(a.ILl + o);
+    return th ? s + ld(a.Itv + o) : s;
+  };
+  auto Cg = [&](int m, int rr, int cc) {
+    const int64_t o = (int64_t)m * E + rr * N + cc;
+    cd s = ld(a.IRg + o) + ld(a.ILg + o);
+    return th ? s + ld(a.Itv + o) : s;
+  };
+  const kbe_c128 *ep = a.eps;
+  cd f = czero();
+  if (kind == EU || kind == EBU) {  // i (X eps - C^<(n,m)^dagger)
+    const int m = kind == EU ? idx : n;
+    const kbe_c128 *X = a.kp + ((int64_t)m * a.ldt + n) * E;
+    cd s = czero();
+    for (int k = 0; k < N; ++k) s = s + ld(X + r * N + k) * ld(ep + k * N + c);
+    f = mul_i(s - cj(Cl(m, c, r)));
+  } else if (kind == ER) {  // -i (eps X + C^> - C^<)
+    const kbe_c128 *X = a.kp + ((int64_t)n * a.ldt + idx) * E;
+    cd s = czero();
+    for (int k = 0; k < N; ++k) s = s + ld(ep + r * N + k) * ld(X + k * N + c);
+    f = mul_mi(s + Cg(idx, r, c) - Cl(idx, r, c));
+  } else if (kind == EBR) {  // -i (eps (-i 1) + C^>(n,n) - C^<(n,n))
+    f = mul_mi(mul_mi(ld(ep + q)) + Cg(n, r, c) - Cl(n, r, c));
+  } else if (kind == ED) {  // -i [eps, D] - i (C + C^dagger)
+    const kbe_c128 *X = a.kp + ((int64_t)n * a.ldt + n) * E;
+    cd s = czero();
+    for (int k = 0; k < N; ++k)
+      s = s + ld(ep + r * N + k) * ld(X + k * N + c) - ld(X + r * N + k) * ld(ep + k * N + c);
+    f = mul_mi(s + Cl(n, r, c) + cj(Cl(n, c, r)));
+  } else {  // ET: -i (eps X + J)
+    const kbe_c128 *X = a.tv + ((int64_t)n * a.ntau + idx) * E;
+    cd s = czero();
+    for (int k = 0; k < N; ++k) s = s + ld(ep + r * N + k) * ld(X + k * N + c);
+    f = mul_mi(s + ld(a.Jtv + (int64_t)idx * E + q));
+  }
+  if (mode == 0) {
+    const int k = nodes(a, n, birth(kind, idx));
+    st(a.ynext + gid, ld(a.base + gid) + lamrow(a, n, k)[k - 1] * f);
+  } else {
+    st(f_ptr(a, a.fkp, a.fbu, a.fbr, a.ftv, n, kind, idx) + q, f);
+  }
+}
+
+// The next iterate becomes the current value of row/column n and iterate `slot`.
+__global__ void prop_commit(PA a, int n, int slot) {
+  const int64_t E = E_(a);
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)nelem(a, n) * E) return;
+  const int e = (int)(gid / E), q = (int)(gid % E);
+  int kind, idx;
+  elem_of(a, n, e, kind, idx);
+  const cd y = ld(a.ynext + gid);
+  st(val_ptr(a, a.kp, a.tv, n, kind, idx) + q, y);
+  st(slot_ptr(a, slot, n, kind, idx) + q, y);
+}
+
+// Row/column n from iterate `slot` (adjoint: the values an evaluation saw).
+__global__ void prop_restore(PA a, int n, int slot) {
+  const int64_t E = E_(a);
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)nelem(a, n) * E) return;
+  const int e = (int)(gid / E), q = (int)(gid % E);
+  int kind, idx;
+  elem_of(a, n, e, kind, idx);
+  st(val_ptr(a, a.kp, a.tv, n, kind, idx) + q, ld(slot_ptr(a, slot, n, kind, idx) + q));
+}
+
+__global__ void prop_dens(PA a, int n, double *dens) {
+  const int r = threadIdx.x;
+  if (r >= a.N) return;
+  const cd d = ld(a.kp + ((int64_t)n * a.ldt + n) * E_(a) + (int64_t)r * a.N + r);
+  dens[(int64_t)n * a.N + r] = d.im;  // Re(-i d)
+}
+
+// ---------------------------------------------------------------------------------------------
+// Adjoint kernels (PyTorch's complex convention: a real loss L has the gradient dL/dRe + i dL/dIm;
+// for y = a X b the cotangents are conj(a)^T ybar b^dagger ... written out per term below)
+// ---------------------------------------------------------------------------------------------
+
+template <typename T>
+__global__ void fill_zero(T *p, int64_t count) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid < count) p[gid] = T{};
+}
+
+// The loss's cotangent: d n_i(t_n) / d G^<_ii(t_n,t_n) pairs with i gdens[n][i].
+__global__ void prop_seed(PA a, const double *gdens) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)a.nt * a.N) return;
+  const int n = (int)(gid / a.N), r = (int)(gid % a.N);
+  kbe_c128 *g = a.gkp + ((int64_t)n * a.ldt + n) * E_(a) + (int64_t)r * a.N + r;
+  st(g, ld(g) + cd{0.0, gdens[gid]});
+}
+
+// fbar of the final evaluation of step n: the gradient of the stored f history at t_n.
+__global__ void prop_gather_final(PA a, int n) {
+  const int64_t E = E_(a);
+  const int ne = nelem(a, n) + 2;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)ne * E) return;
+  const int e = (int)(gid / E), q = (int)(gid % E);
+  int kind, idx;
+  elem_of(a, n, e, kind, idx);
+  st(a.fbar + gid, ld(f_ptr(a, a.gfkp, a.gfbu, a.gfbr, a.gftv, n, kind, idx) + q));
+}
+
+// Cotangents of the history sums from fbar: C^<(m), C^>(m) (m <= n), I^] (both forms), J^](j).
+__global__ void prop_cot(PA a, int n, int mode) {
+  const int64_t E = E_(a);
+  const int N = a.N;
+  const int ne = nelem(a, n);
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nm = (int64_t)(n + 1) * E;
+  if (gid >= nm + (int64_t)a.ntau * E) return;
+  const int q = (int)(gid % E), r = q / N, c = q % N;
+  const int tq = c * N + r;  // transposed entry
+  if (gid < nm) {
+    const int m = (int)(gid / E);
+    cd cl, cg;
+    if (m < n) {
+      const kbe_c128 *fu = a.fbar + (int64_t)m * E, *fr = a.fbar + (int64_t)(n + 1 + m) * E;
+      cl = mul_mi(cj(ld(fu + tq))) + mul_mi(ld(fr + q));
+      cg = mul_i(ld(fr + q));
+    } else {
+      const kbe_c128 *fd = a.fbar + (int64_t)n * E;
+      cl = mul_i(ld(fd + q)) + mul_mi(cj(ld(fd + tq)));
+      cg = czero();
+      if (mode) {
+        const kbe_c128 *fbu = a.fbar + (int64_t)ne * E, *fbr = a.fbar + (int64_t)(ne + 1) * E;
+        cl = cl + mul_mi(cj(ld(fbu + tq))) + mul_mi(ld(fbr + q));
+        cg = mul_i(ld(fbr + q));
+      }
+    }
+    st(a.CbL + gid, cl);
+    st(a.CbG + gid, cg);
+    st(a.CbT + gid, cl + cg);
+  } else {
+    const int64_t g2 = gid - nm;
+    const int j = (int)(g2 / E);
+    st(a.Jbar + g2, mul_i(ld(a.fbar + (int64_t)(2 * n + 1 + j) * E + q)));
+  }
+}
+
+// The terms of f that multiply the element itself or eps: their gradient into the solution's
+// gradient (row/column n) and each element's share of the gradient of eps (epart[e]).
+__global__ void prop_direct(PA a, int n, int mode) {
+  const int64_t E = E_(a);
+  const int N = a.N;
+  const int ne = nelem(a, n);
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)ne * E) return;
+  const int e = (int)(gid / E), q = (int)(gid % E), r = q / N, c = q % N;
+  int kind, idx;
+  elem_of(a, n, e, kind, idx);
+  const kbe_c128 *ep = a.eps;
+  const kbe_c128 *fb = a.fbar + (int64_t)e * E;
+  const kbe_c128 *X = val_ptr(a, a.kp, a.tv, n, kind, idx);
+  kbe_c128 *gX = val_ptr(a, a.gkp, a.gtv, n, kind, idx);
+  cd gx = czero(), ge = czero();
+  if (kind == EU) {  // y = i X eps: Xbar += -i ybar eps^H, epsbar += -i X^H ybar
+    for (int k = 0; k < N; ++k) {
+      gx = gx + ld(fb + r * N + k) * cj(ld(ep + c * N + k));
+      ge = ge + cj(ld(X + k * N + r)) * ld(fb + k * N + c);
+    }
+    gx = mul_mi(gx);
+    ge = mul_mi(ge);
+  } else if (kind == ER || kind == ET) {  // y = -i eps X: Xbar += i eps^H ybar, epsbar += i ybar X^H
+    for (int k = 0; k < N; ++k) {
+      gx = gx + cj(ld(ep + k * N + r)) * ld(fb + k * N + c);
+      ge = ge + ld(fb + r * N + k) * cj(ld(X + c * N + k));
+    }
+    gx = mul_i(gx);
+    ge = mul_i(ge);
+  } else {  // ED: y = -i eps D + i D eps (+ birth of U_n: i D eps; of R_n: -eps)
+    cd a1 = czero(), a2 = czero(), b1 = czero(), b2 = czero();
+    for (int k = 0; k < N; ++k) {
+      a1 = a1 + cj(ld(ep + k * N + r)) * ld(fb + k * N + c);  // eps^H ybar
+      a2 = a2 + ld(fb + r * N + k) * cj(ld(ep + c * N + k));  // ybar eps^H
+      b1 = b1 + ld(fb + r * N + k) * cj(ld(X + c * N + k));   // ybar D^H
+      b2 = b2 + cj(ld(X + k * N + r)) * ld(fb + k * N + c);   // D^H ybar
+    }
+    gx = mul_i(a1) + mul_mi(a2);
+    ge = mul_i(b1) + mul_mi(b2);
+    if (mode) {
+      const kbe_c128 *fu = a.fbar + (int64_t)ne * E, *fr = a.fbar + (int64_t)(ne + 1) * E;
+      cd a3 = czero(), b3 = czero();
+      for (int k = 0; k < N; ++k) {
+        a3 = a3 + ld(fu + r * N + k) * cj(ld(ep + c * N + k));  // ybar_bu eps^H
+        b3 = b3 + cj(ld(X + k * N + r)) * ld(fu + k * N + c);   // D^H ybar_bu
+      }
+      gx = gx + mul_mi(a3);
+      ge = ge + mul_mi(b3) - ld(fr + q);
+    }
+  }
+  st(gX + q, ld(gX + q) + gx);
+  st(a.epart + gid, ge);
+}
+
+// epsbar = sum of the element shares (fixed order), then through eps: the Fock term into
+// G^<(t_n,t_n) and u, the pulse into its amplitude.
+__global__ void prop_eps_vjp(PA a, int n, double *gu, double *gamp) {
+  const int64_t E = E_(a);
+  const int q = threadIdx.x;
+  if (q >= E) return;
+  const int ne = nelem(a, n);
+  cd s = czero();
+  for (int e = 0; e < ne; ++e) s = s + ld(a.epart + (int64_t)e * E + q);
+  const int r = q / a.N, c = q % a.N;
+  if (r == c) {  // eps_rr += -i u_r D_rr
+    kbe_c128 *g = a.gkp + ((int64_t)n * a.ldt + n) * E + q;
+    const cd d = ld(a.kp + ((int64_t)n * a.ldt + n) * E + q);
+    st(g, ld(g) + a.u[r] * mul_i(s));
+    const cd w = mul_mi(d);  // d eps_rr / d u_r
+    gu[r] += w.re * s.re + w.im * s.im;
+  }
+  if (q == 0) gamp[0] += pulse(a, n) * s.re;
+}
+
+// gS = gS(lesser) + gS(greater) over the real-time row.
+__global__ void prop_gs_add(PA a, int n) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)(n + 1) * E_(a)) return;
+  st(a.gretL + gid, ld(a.gretL + gid) + ld(a.gretG + gid));
+  st(a.glesL + gid, ld(a.glesL + gid) + ld(a.glesG + gid));
+}
+
+// ybar of iterate `it` (the gradient accumulated in row/column n), reset for the next; the
+// base's gradient accumulates it, and fbar = lam_last ybar feeds the evaluation that made it.
+__global__ void prop_take(PA a, int n, int first) {
+  const int64_t E = E_(a);
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)nelem(a, n) * E) return;
+  const int e = (int)(gid / E), q = (int)(gid % E);
+  int kind, idx;
+  elem_of(a, n, e, kind, idx);
+  kbe_c128 *g = val_ptr(a, a.gkp, a.gtv, n, kind, idx) + q;
+  const cd y = ld(g);
+  st(g, czero());
+  st(a.bbar + gid, first ? y : ld(a.bbar + gid) + y);
+  const int k = nodes(a, n, birth(kind, idx));
+  st(a.fbar + gid, lamrow(a, n, k)[k - 1] * y);
+}
+
+// Predictor and base sums of step n, backwards: the gradient of iterate 0 (left in row/column
+// n) and of the base reach the values at t_{n-1} and the f history of the rule's nodes.
+__global__ void prop_predict_vjp(PA a, int n) {
+  const int64_t E = E_(a);
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)nelem(a, n) * E) return;
+  const int e = (int)(gid / E), q = (int)(gid % E);
+  int kind, idx;
+  elem_of(a, n, e, kind, idx);
+  const cd y0 = ld(val_ptr(a, a.gkp, a.gtv, n, kind, idx) + q);
+  const cd bb = ld(a.bbar + gid);
+  const double h = a.t[n] - a.t[n - 1];
+  // values at t_{n-1}; U_{n-1}'s is G^<(t_{n-1},t_{n-1}), D's too: D's thread adds both
+  if (!(kind == EU && idx == n - 1)) {
+    kbe_c128 *gp = prev_ptr(a, a.gkp, a.gtv, n, kind, idx);
+    if (gp) {
+      cd add = y0 + bb;
+      if (kind == ED && n - 1 >= 0) {
+        const int64_t eu = (int64_t)(n - 1) * E + q;  // element U_{n-1}
+        add = add + ld(val_ptr(a, a.gkp, a.gtv, n, EU, n - 1) + q) + ld(a.bbar + eu);
+      }
+      st(gp + q, ld(gp + q) + add);
+    }
+  }
+  const int b = birth(kind, idx), k = nodes(a, n, b);
+  const double *L = lamrow(a, n, k);
+  for (int i = 0; i + 1 < k; ++i) {
+    const int j = n - k + 1 + i;
+    kbe_c128 *gf = f_ptr(a, a.gfkp, a.gfbu, a.gfbr, a.gftv, j, kind, idx) + q;
+    cd add = L[i] * bb;
+    if (j == n - 1) add = add + h * y0;
+    st(gf, ld(gf) + add);
+  }
+  if (k == 1) {  // the rule has no history node: the predictor's f at t_{n-1} only
+    kbe_c128 *gf = f_ptr(a, a.gfkp, a.gfbu, a.gfbr, a.gftv, n - 1, kind, idx) + q;
+    st(gf, ld(gf) + h * y0);
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------------------------
+size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+  size_t fkp, fbu, fbr, ftv, ykp, ytv, eps, sig_ret, sig_les, sig_tv, IRl, ILl, Itv, Jtv, IRg,
+      ILg, base, ynext, cws;                                  // forward
+  size_t gkp, grd, gtv, gmat, gfkp, gfbu, gfbr, gftv, ybar, bbar, fbar, epart, CbL, CbG, CbT,
+      Jbar, gretL, glesL, gstvL, gretG, glesG, gstvG, vws, sws;  // adjoint
+  size_t total;
+};
+
+Layout layout(int N, int nt, int ntau, int64_t ldt, int K) {
+  const size_t E = (size_t)N * N * sizeof(kbe_c128);
+  const size_t nt2 = (size_t)nt * nt, ne = (size_t)(2 * nt + 1 + ntau + 2);
+  const int n = nt - 1;
+  Layout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) { const size_t r = o; o += al(bytes); return r; };
+  L.fkp = take(nt2 * E);
+  L.fbu = take(nt * E);
+  L.fbr = take(nt * E);
+  L.ftv = take((size_t)nt * ntau * E);
+  L.ykp = take((size_t)(K + 1) * nt2 * E);
+  L.ytv = take((size_t)(K + 1) * nt * ntau * E);
+  L.eps = take(E);
+  L.sig_ret = take(nt * E);
+  L.sig_les = take(nt * E);
+  L.sig_tv = take(ntau * E);
+  L.IRl = take(nt * E);
+  L.ILl = take(nt * E);
+  L.Itv = take(nt * E);
+  L.Jtv = take(ntau * E);
+  L.IRg = take(nt * E);
+  L.ILg = take(nt * E);
+  L.base = take(ne * E);
+  L.ynext = take(ne * E);
+  const unsigned gfl = KBE_OUT_IR | KBE_OUT_IL | KBE_GREATER;
+  size_t cw = collision_ws_bytes(N, nt, ntau, n, 0, n + 1, KBE_OUT_ALL);
+  const size_t cw2 = collision_ws_bytes(N, nt, ntau, n, 0, n + 1, gfl);
+  L.cws = take(cw > cw2 ? cw : cw2);
+  L.gkp = take((size_t)nt * ldt * E);
+  L.grd = take(nt * E);
+  L.gtv = take((size_t)nt * ntau * E);
+  L.gmat = take(ntau * E);
+  L.gfkp = take(nt2 * E);
+  L.gfbu = take(nt * E);
+  L.gfbr = take(nt * E);
+  L.gftv = take((size_t)nt * ntau * E);
+  L.ybar = take(ne * E);
+  L.bbar = take(ne * E);
+  L.fbar = take(ne * E);
+  L.epart = take(ne * E);
+  L.CbL = take(nt * E);
+  L.CbG = take(nt * E);
+  L.CbT = take(nt * E);
+  L.Jbar = take(ntau * E);
+  L.gretL = take(nt * E);
+  L.glesL = take(nt * E);
+  L.gstvL = take(ntau * E);
+  L.gretG = take(nt * E);
+  L.glesG = take(nt * E);
+  L.gstvG = take(ntau * E);
+  size_t vw = collision_vjp_ws_bytes(N, nt, ntau, n, 0, n + 1, KBE_OUT_ALL);
+  const size_t vw2 = collision_vjp_ws_bytes(N, nt, ntau, n, 0, n + 1, gfl);
+  L.vws = take(vw > vw2 ? vw : vw2);
+  L.sws = take(sigma_vjp_ws_bytes(N, n, ntau));
+  L.total = o;
+  return L;
+}
+
+struct Ctx {
+  PA a;
+  Layout L;
+  char *ws;
+  const kbe_green *G;
+  const kbe_wts *W;
+  kbe_green Gc;          // the solution as a kbe_green (for the Sigma and collision calls)
+  kbe_green gG;          // its gradient (adjoint)
+  kbe_sigma_row sig, gSL, gSG;
+  hipStream_t st;
+};
+
+unsigned blocks(int64_t count) { return (unsigned)((count + 255) / 256); }
+
+Params coll_params(const Ctx &x, int n) {
+  Params p{};
+  p.N = x.a.N;
+  p.nt = x.a.nt;
+  p.ntau = x.a.ntau;
+  p.J = x.a.ntau - 1;
+  p.n = n;
+  p.m0 = 0;
+  p.m1 = n + 1;
+  p.ldt = x.a.ldt;
+  p.kp = x.a.kp;
+  p.rdiag = x.a.rdiag;
+  p.tv = x.a.tv;
+  p.mat = x.a.mat;
+  p.ret = x.sig.ret;
+  p.les = x.sig.les;
+  p.stv = x.sig.tv;
+  p.w = x.W->w;
+  p.wtau = x.W->wtau;
+  p.wf = x.W->wtau_fwd;
+  return p;
+}
+
+void set_flags(Params &p, unsigned flags, bool th) {
+  p.fIR = (flags & KBE_OUT_IR) != 0;
+  p.fIL = (flags & KBE_OUT_IL) != 0;
+  p.fITV = (flags & KBE_OUT_ITV) && th;
+  p.fJTV = (flags & KBE_OUT_JTV) && th;
+  p.overwrite = 0;
+}
+
+constexpr unsigned FL = KBE_OUT_ALL;
+constexpr unsigned FG = KBE_OUT_IR | KBE_OUT_IL | KBE_GREATER;
+
+// Self-energy row and both history sums of step n at the current values, then eps.
+hipError_t evaluate(Ctx &x, int n) {
+  hipError_t e = launch_sigma_row(&x.Gc, x.a.u, n, &x.sig, x.st);
+  if (e != hipSuccess) return e;
+  const bool th = x.a.ntau > 0;
+  Params p = coll_params(x, n);
+  set_flags(p, FL, th);
+  e = launch_collision(p, FL, x.a.IRl, x.a.ILl, x.a.Itv, x.a.Jtv, x.ws + x.L.cws, x.st);
+  if (e != hipSuccess) return e;
+  set_flags(p, FG, th);
+  e = launch_collision(p, FG, x.a.IRg, x.a.ILg, nullptr, nullptr, x.ws + x.L.cws, x.st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(prop_eps, dim3(1), dim3(256), 0, x.st, x.a, n);
+  return hipGetLastError();
+}
+
+// The adjoint of one evaluation at the current values, given fbar: eps, sums and Sigma row.
+hipError_t evaluate_vjp(Ctx &x, int n, int mode, double *gu, double *gamp) {
+  hipError_t e = launch_sigma_row(&x.Gc, x.a.u, n, &x.sig, x.st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(prop_eps, dim3(1), dim3(256), 0, x.st, x.a, n);
+  const int64_t E = (int64_t)x.a.N * x.a.N;
+  const int ne = 2 * n + 1 + x.a.ntau;
+  hipLaunchKernelGGL(prop_cot, dim3(blocks((int64_t)(n + 1 + x.a.ntau) * E)), dim3(256), 0, x.st,
+                     x.a, n, mode);
+  hipLaunchKernelGGL(prop_direct, dim3(blocks((int64_t)ne * E)), dim3(256), 0, x.st, x.a, n, mode);
+  hipLaunchKernelGGL(prop_eps_vjp, dim3(1), dim3(256), 0, x.st, x.a, n, gu, gamp);
+  const bool th = x.a.ntau > 0;
+  Params p = coll_params(x, n);
+  p.gkp = x.gG.kp;
+  p.grdiag = x.gG.rdiag;
+  p.gtv = x.gG.tv;
+  set_flags(p, FL, th);
+  p.gIR = x.a.CbL;
+  p.gIL = x.a.CbL;
+  p.gItv = x.a.CbT;
+  p.gJ = x.a.Jbar;
+  e = launch_collision_vjp(p, FL, x.gG.mat, &x.gSL, x.ws + x.L.vws, x.st);
+  if (e != hipSuccess) return e;
+  set_flags(p, FG, th);
+  p.gIR = x.a.CbG;
+  p.gIL = x.a.CbG;
+  p.gItv = nullptr;
+  p.gJ = nullptr;
+  e = launch_collision_vjp(p, FG, x.gG.mat, &x.gSG, x.ws + x.L.vws, x.st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(prop_gs_add, dim3(blocks((int64_t)(n + 1) * E)), dim3(256), 0, x.st, x.a, n);
+  return launch_sigma_row_vjp(&x.Gc, x.a.u, n, &x.gSL, &x.gG, gu, x.ws + x.L.sws, x.st);
+}
+
+Ctx make_ctx(const kbe_prop *P, const kbe_wts *W, const kbe_green *G, void *ws, hipStream_t st) {
+  Ctx x{};
+  x.L = layout(G->N, G->nt, G->ntau, G->ldt, P->iters);
+  x.ws = (char *)ws;
+  x.G = G;
+  x.W = W;
+  x.st = st;
+  x.Gc = *G;
+  PA &a = x.a;
+  a.N = G->N;
+  a.nt = G->nt;
+  a.ntau = G->ntau;
+  a.K = P->iters;
+  a.ldt = G->ldt;
+  a.kp = G->kp;
+  a.rdiag = G->rdiag;
+  a.tv = G->tv;
+  a.mat = G->mat;
+  a.h0 = P->h0;
+  a.u = P->u;
+  a.t = P->t;
+  a.lam = P->lam;
+  a.order = P->order;
+  a.amp = P->pulse_amp;
+  a.t0 = P->pulse_t0;
+  a.sig = P->pulse_sigma;
+  auto c = [&](size_t off) { return (kbe_c128 *)(x.ws + off); };
+  a.fkp = c(x.L.fkp);
+  a.fbu = c(x.L.fbu);
+  a.fbr = c(x.L.fbr);
+  a.ftv = c(x.L.ftv);
+  a.ykp = c(x.L.ykp);
+  a.ytv = c(x.L.ytv);
+  a.eps = c(x.L.eps);
+  a.IRl = c(x.L.IRl);
+  a.ILl = c(x.L.ILl);
+  a.Itv = c(x.L.Itv);
+  a.Jtv = c(x.L.Jtv);
+  a.IRg = c(x.L.IRg);
+  a.ILg = c(x.L.ILg);
+  a.base = c(x.L.base);
+  a.ynext = c(x.L.ynext);
+  a.gkp = c(x.L.gkp);
+  a.gtv = c(x.L.gtv);
+  a.gfkp = c(x.L.gfkp);
+  a.gfbu = c(x.L.gfbu);
+  a.gfbr = c(x.L.gfbr);
+  a.gftv = c(x.L.gftv);
+  a.ybar = c(x.L.ybar);
+  a.bbar = c(x.L.bbar);
+  a.fbar = c(x.L.fbar);
+  a.epart = c(x.L.epart);
+  a.CbL = c(x.L.CbL);
+  a.CbG = c(x.L.CbG);
+  a.CbT = c(x.L.CbT);
+  a.Jbar = c(x.L.Jbar);
+  a.gretL = c(x.L.gretL);
+  a.glesL = c(x.L.glesL);
+  a.gretG = c(x.L.gretG);
+  a.glesG = c(x.L.glesG);
+  x.sig = {c(x.L.sig_ret), c(x.L.sig_les), a.ntau ? c(x.L.sig_tv) : nullptr};
+  x.gSL = {a.gretL, a.glesL, a.ntau ? c(x.L.gstvL) : nullptr};
+  x.gSG = {a.gretG, a.glesG, a.ntau ? c(x.L.gstvG) : nullptr};
+  x.gG = *G;
+  x.gG.kp = a.gkp;
+  x.gG.rdiag = c(x.L.grd);
+  x.gG.tv = a.ntau ? a.gtv : nullptr;
+  x.gG.mat = a.ntau ? c(x.L.gmat) : nullptr;
+  return x;
+}
+
+}  // namespace
+
+size_t prop_ws_bytes(int N, int nt, int ntau, int64_t ldt, int K) {
+  return layout(N, nt, ntau, ldt, K).total;
+}
+
+hipError_t launch_propagate(const kbe_prop *P, const kbe_wts *W, const kbe_green *G,
+                            double *dens, void *ws, hipStream_t st) {
+  Ctx x = make_ctx(P, W, G, ws, st);
+  PA &a = x.a;
+  const int64_t E = (int64_t)a.N * a.N;
+  hipLaunchKernelGGL(prop_init, dim3(blocks((int64_t)(a.nt + a.ntau) * E)), dim3(256), 0, st, a);
+  hipError_t e = evaluate(x, 0);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(prop_rhs, dim3(blocks((int64_t)(a.ntau + 3) * E)), dim3(256), 0, st, a, 0, 1);
+  hipLaunchKernelGGL(prop_dens, dim3(1), dim3(64), 0, st, a, 0, dens);
+  for (int n = 1; n < a.nt; ++n) {
+    const int64_t ne = 2 * n + 1 + a.ntau;
+    hipLaunchKernelGGL(prop_predict, dim3(blocks(ne * E)), dim3(256), 0, st, a, n);
+    for (int it = 1; it <= a.K; ++it) {
+      if ((e = evaluate(x, n)) != hipSuccess) return e;
+      hipLaunchKernelGGL(prop_rhs, dim3(blocks(ne * E)), dim3(256), 0, st, a, n, 0);
+      hipLaunchKernelGGL(prop_commit, dim3(blocks(ne * E)), dim3(256), 0, st, a, n, it);
+    }
+    if ((e = evaluate(x, n)) != hipSuccess) return e;
+    hipLaunchKernelGGL(prop_rhs, dim3(blocks((ne + 2) * E)), dim3(256), 0, st, a, n, 1);
+    hipLaunchKernelGGL(prop_dens, dim3(1), dim3(64), 0, st, a, n, dens);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_propagate_vjp(const kbe_prop *P, const kbe_wts *W, const kbe_green *G,
+                                const double *gdens, double *gu, double *gamp, void *ws,
+                                hipStream_t st) {
+  Ctx x = make_ctx(P, W, G, ws, st);
+  PA &a = x.a;
+  const int64_t E = (int64_t)a.N * a.N;
+  const Layout &L = x.L;
+  // zero the gradient arrays (fill kernels: no memset nodes if the caller captures the call)
+  const size_t zb = L.gfkp - L.gkp, zf = L.ybar - L.gfkp;
+  hipLaunchKernelGGL(fill_zero<double>, dim3(blocks((int64_t)(zb / 8))), dim3(256), 0, st,
+                     (double *)(x.ws + L.gkp), (int64_t)(zb / 8));
+  hipLaunchKernelGGL(fill_zero<double>, dim3(blocks((int64_t)(zf / 8))), dim3(256), 0, st,
+                     (double *)(x.ws + L.gfkp), (int64_t)(zf / 8));
+  hipLaunchKernelGGL(fill_zero<double>, dim3(1), dim3(64), 0, st, gu, (int64_t)a.N);
+  hipLaunchKernelGGL(fill_zero<double>, dim3(1), dim3(64), 0, st, gamp, (int64_t)1);
+  hipLaunchKernelGGL(prop_seed, dim3(blocks((int64_t)a.nt * a.N)), dim3(256), 0, st, a, gdens);
+  hipError_t e;
+  for (int n = a.nt - 1; n >= 1; --n) {
+    const int64_t ne = 2 * n + 1 + a.ntau;
+    // the final evaluation (row/column n holds the accepted values)
+    hipLaunchKernelGGL(prop_gather_final, dim3(blocks((ne + 2) * E)), dim3(256), 0, st, a, n);
+    if ((e = evaluate_vjp(x, n, 1, gu, gamp)) != hipSuccess) return e;
+    for (int it = a.K; it >= 1; --it) {
+      hipLaunchKernelGGL(prop_take, dim3(blocks(ne * E)), dim3(256), 0, st, a, n, it == a.K);
+      hipLaunchKernelGGL(prop_restore, dim3(blocks(ne * E)), dim3(256), 0, st, a, n, it - 1);
+      if ((e = evaluate_vjp(x, n, 0, gu, gamp)) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(prop_predict_vjp, dim3(blocks(ne * E)), dim3(256), 0, st, a, n);
+    hipLaunchKernelGGL(prop_restore, dim3(blocks(ne * E)), dim3(256), 0, st, a, n, a.K);
+  }
+  hipLaunchKernelGGL(prop_gather_final, dim3(blocks((int64_t)(a.ntau + 3) * E)), dim3(256), 0, st,
+                     a, 0);
+  if ((e = evaluate_vjp(x, 0, 1, gu, gamp)) != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+}  // namespace kbe

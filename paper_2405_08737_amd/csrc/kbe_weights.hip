@@ -132,7 +132,8 @@ __global__ void __launch_bounds__(64) local_weights_kernel(const double *t, cons
   __shared__ double l[KBE_KMAX];
   const int p = blockIdx.x + 1;
   if (p >= nt) return;
-  const int k = order[p] < p + 1 ? order[p] : p + 1;
+  int k = order[p] < 1 ? 1 : (order[p] > KBE_KMAX ? KBE_KMAX : order[p]);  // in range when valid
+  k = k < p + 1 ? k : p + 1;
   if (threadIdx.x == 0) kk[p] = k;
   wave_solve(t + (p - k + 1), k, t[p - 1], t[p], l, S);
   __syncthreads();
@@ -204,6 +205,43 @@ __global__ void tau_full_kernel(const double *wf, int ntau, double *wtau) {
   wtau[l] = 0.5 * (wf[(int64_t)J * ntau + l] + wf[(int64_t)J * ntau + (J - l)]);
 }
 
+// Local weights of interval p for every node count k = 1..min(order[p], p+1) (the time-stepping
+// rules of elements whose history starts inside the interval's window): lam[p][k-1][i] for the
+// nodes t[p-k+1+i]; zero elsewhere.  One 64-thread workgroup per (p, k).
+__global__ void __launch_bounds__(64) step_weights_kernel(const double *t, const int32_t *order,
+                                                          int nt, double *lam) {
+  __shared__ SolveLds S;
+  __shared__ double l[KBE_KMAX];
+  const int p = blockIdx.x / KBE_KMAX, k = blockIdx.x % KBE_KMAX + 1;
+  double *out = lam + ((int64_t)p * KBE_KMAX + (k - 1)) * KBE_KMAX;
+  if (threadIdx.x < KBE_KMAX) out[threadIdx.x] = 0.0;
+  if (p < 1 || p >= nt) return;  // uniform per workgroup
+  int kp = order[p] < 1 ? 1 : (order[p] > KBE_KMAX ? KBE_KMAX : order[p]);
+  kp = kp < p + 1 ? kp : p + 1;
+  if (k > kp) return;
+  wave_solve(t + (p - k + 1), k, t[p - 1], t[p], l, S);
+  __syncthreads();
+  if ((int)threadIdx.x < k) out[threadIdx.x] = l[threadIdx.x];
+}
+
+// Grid check on the device: status = 0, or KBE_EINVAL (t[0] != 0 or t not increasing), or
+// KBE_ERANGE (an order outside 1..KBE_KMAX).  One workgroup; a fixed-order reduction.
+__global__ void __launch_bounds__(256) grid_check_kernel(const double *t, const int32_t *order,
+                                                         int nt, int32_t *status) {
+  __shared__ int bad_t, bad_o;
+  if (threadIdx.x == 0) {
+    bad_t = t[0] != 0.0;
+    bad_o = 0;
+  }
+  __syncthreads();
+  for (int p = 1 + threadIdx.x; p < nt; p += blockDim.x) {
+    if (!(t[p] > t[p - 1])) atomicOr(&bad_t, 1);
+    if (order[p] < 1 || order[p] > KBE_KMAX) atomicOr(&bad_o, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) status[0] = bad_t ? (int32_t)KBE_EINVAL : (bad_o ? (int32_t)KBE_ERANGE : 0);
+}
+
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 size_t weights_ws_bytes(int nt, int ntau) {
@@ -216,38 +254,58 @@ size_t weights_ws_bytes(int nt, int ntau) {
   return b;
 }
 
-hipError_t launch_weights(const kbe_grid *g, double *w, double *wtau, double *wf, void *ws,
-                          hipStream_t st) {
+// Weights from a grid already in device memory (t_d, o_d); ws holds the rest of the layout of
+// weights_ws_bytes (its first two slots, for a host copy of the grid, stay unused).
+hipError_t launch_weights_dev(const double *t_d, const int32_t *o_d, int nt, int ntau,
+                              double beta, int tau_order, double *w, double *wtau, double *wf,
+                              void *ws, hipStream_t st) {
   char *base = (char *)ws;
-  int nt = g->nt;
-  double *t_d = (double *)base;
   base += align256(sizeof(double) * nt);
-  int32_t *o_d = (int32_t *)base;
   base += align256(sizeof(int32_t) * nt);
   double *lam = (double *)base;
   base += align256(sizeof(double) * (size_t)nt * KBE_KMAX);
   int32_t *kk = (int32_t *)base;
   base += align256(sizeof(int32_t) * nt);
   double *tab = (double *)base;
-  hipError_t e = hipMemcpyAsync(t_d, g->t, sizeof(double) * nt, hipMemcpyHostToDevice, st);
-  if (e != hipSuccess) return e;
-  e = hipMemcpyAsync(o_d, g->order, sizeof(int32_t) * nt, hipMemcpyHostToDevice, st);
-  if (e != hipSuccess) return e;
   if (nt > 1)
     hipLaunchKernelGGL(local_weights_kernel, dim3(nt - 1), dim3(64), 0, st, t_d, o_d, nt, lam, kk);
   int64_t tot = (int64_t)nt * nt;
   hipLaunchKernelGGL(composite_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, lam,
                      kk, nt, w);
-  if (g->ntau > 0) {
-    int ntau = g->ntau;
+  if (ntau > 0) {
     hipLaunchKernelGGL(tau_table_kernel, dim3(KBE_KMAX * KBE_KMAX), dim3(64), 0, st, tab,
-                       g->tau_order);
+                       tau_order);
     int64_t tt = (int64_t)ntau * ntau;
     hipLaunchKernelGGL(tau_fwd_kernel, dim3((unsigned)((tt + 255) / 256)), dim3(256), 0, st, tab,
-                       ntau, g->tau_order, g->beta / (ntau - 1), wf);
+                       ntau, tau_order, beta / (ntau - 1), wf);
     hipLaunchKernelGGL(tau_full_kernel, dim3((ntau + 255) / 256), dim3(256), 0, st, wf, ntau,
                        wtau);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_weights(const kbe_grid *g, double *w, double *wtau, double *wf, void *ws,
+                          hipStream_t st) {
+  const int nt = g->nt;
+  double *t_d = (double *)ws;
+  int32_t *o_d = (int32_t *)((char *)ws + align256(sizeof(double) * nt));
+  hipError_t e = hipMemcpyAsync(t_d, g->t, sizeof(double) * nt, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(o_d, g->order, sizeof(int32_t) * nt, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return e;
+  return launch_weights_dev(t_d, o_d, nt, g->ntau, g->beta, g->tau_order, w, wtau, wf, ws, st);
+}
+
+hipError_t launch_grid_check(const double *t, const int32_t *order, int nt, int32_t *status,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(grid_check_kernel, dim3(1), dim3(256), 0, st, t, order, nt, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_weights(const double *t, const int32_t *order, int nt, double *lam,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(step_weights_kernel, dim3((unsigned)nt * KBE_KMAX), dim3(64), 0, st, t, order,
+                     nt, lam);
   return hipGetLastError();
 }
 
