@@ -7,11 +7,14 @@ all through the C ABI of libkbe.so.  Inputs are seeded synthetic arrays, residen
 timing starts.  After the timed steps, the forward and adjoint collision calls are also timed on
 the 8-orbital differentiation shape (nt = 1024, n_tau = 256: the small-block path, bound by HBM
 bandwidth), and the batching workload (256 independent rows, N in {2,4,8,16}, n up to 4096) is
-timed as one batched launch, as a graph replay and as 256 separate launches; both are reported
-beside the step.  Prints one JSON line.
+timed as one batched launch, as a graph replay and as 256 separate launches; the end-to-end
+gradient of a propagation (kbe_propagate and its adjoint on the 8-orbital grid) is timed too;
+all are reported beside the step, with the FP64 matrix-core and HBM ceilings measured live by
+the library's microbenchmarks.  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
   python bench.py --copy-calibration   # 3 plain 1 GiB device copies (PMC byte-counter scale)
+  python bench.py --ceilings           # the ceiling microbenchmarks -> profiles/ceilings.json
 """
 from __future__ import annotations
 
@@ -31,14 +34,55 @@ METRIC = "collision-integral FP64 GFLOP/s + HBM GB/s, N_orb=16 n=2048; adjoint/f
 HBM_PEAK_GBS = 8000.0
 MFMA_F64_PEAK_TFLOPS = 78.6
 RIDGE = MFMA_F64_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
-# Ceilings measured on this GPU with microbenchmarks (a dependent-chain-free stream of
-# v_mfma_f64_4x4x4 products; a read-only stream of the HBM): the achievable, not the spec, peaks.
-MEASURED_MFMA_F64_TFLOPS = 70.0
-MEASURED_HBM_READ_GBS = 6400.0
+CEILING_SOURCES = ("kbe_ceilings.hip",)
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def ceilings(kbe, torch, reps=5):
+    """The library's ceiling microbenchmarks (kbe_ceilings.hip), timed with HIP events on the
+    stream they run on: independent chains of v_mfma_f64_4x4x4 and v_mfma_f64_16x16x4 products
+    over the whole chip, and a 4 GiB HBM read and copy.  Median of `reps` launches after two
+    warm-up launches."""
+    import ctypes
+    L = kbe.lib()
+    L.kbe_internal_ceiling_run.restype = ctypes.c_int32
+    L.kbe_internal_ceiling_run.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_int64, ctypes.c_void_p, ctypes.c_int32,
+                                           ctypes.c_void_p]
+    L.kbe_internal_ceiling_counts.restype = ctypes.c_double
+    L.kbe_internal_ceiling_counts.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32]
+    L.kbe_internal_ceiling_out_count.restype = ctypes.c_int64
+    dev = torch.device("cuda:0")
+    out = torch.empty(L.kbe_internal_ceiling_out_count(), dtype=torch.float64, device=dev)
+    nbytes = 4 << 30
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    st = torch.cuda.current_stream(dev).cuda_stream
+    res = {}
+    for kind, name, iters, unit in ((0, "mfma_f64_4x4x4", 2000, 1e12),
+                                    (1, "mfma_f64_16x16x4", 500, 1e12),
+                                    (2, "hbm_read", 0, 1e9), (3, "hbm_copy", 0, 1e9)):
+        run = lambda: L.kbe_internal_ceiling_run(kind, src.data_ptr(), dst.data_ptr(), nbytes,
+                                                 out.data_ptr(), iters, st)
+        for _ in range(2):
+            assert run() == 0
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            assert run() == 0
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) / 1e3)
+        rate = L.kbe_internal_ceiling_counts(kind, nbytes, iters) / float(np.median(ts)) / unit
+        res[name + ("_tflops" if kind < 2 else "_gbs")] = rate
+    del src, dst
+    torch.cuda.empty_cache()
+    res["source_hash"] = kernel_source_hash(CEILING_SOURCES)
+    return res
 
 
 def counts(N, nt, ntau, n):
@@ -82,43 +126,77 @@ def measured_traffic(name="traffic_collision_N16_nt2048.json", files=None):
     return d.get("hbm_bytes_per_call")
 
 
-def cpu_baseline(w, host, target_s=30.0):
-    """The oracle, as it stands, timed on the host cores: the whole forward row of the same
-    workload (I^R, I^<, I^] for every m and J^] for every tau point) when a calibration says it
-    fits in about target_s seconds, else a contiguous band of rows m around the middle."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, host, target_s=6.0):
+    """The oracle, as it stands, timed on the host cores (median of 3 runs each): the small parity
+    workload (N = 2, nt = 64, ntau = 64: the whole row) and the headline workload, at one thread
+    and at all the threads the process may use.  On the headline the whole forward row (all m, all
+    four integrals) is run when a calibration says it takes at most target_s seconds at that
+    thread count, else a band of rows m around the middle sized to about target_s (I^R, I^<, I^]).
+    `value` is the headline figure at all threads."""
     import oracle
-    t, order, kp, rd, tv, mat = host
-    n = w.nt - 1
-    N = w.N
-    G = oracle.Green(kp, rd, tv, mat)
-    W = oracle.Weights.build(t, order, w.beta, w.ntau, w.tau_order)
-    sig = oracle.sigma_row(G, np.full(N, w.U), n)
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    blk_flop = 8.0 * N ** 3
-    rows_flop = lambda m0, m1: sum((n + 1) + (m + 1) + w.ntau for m in range(m0, m1)) * blk_flop
-    mid = n // 2
-    t0 = time.perf_counter()
-    oracle.collision(G, sig, W, n, mid, mid + threads, oracle.F_IR | oracle.F_IL | oracle.F_ITV)
-    rate = rows_flop(mid, mid + threads) / max(time.perf_counter() - t0, 1e-9)
-    full = rows_flop(0, n + 1) + w.ntau * ((n + 1) + (w.ntau + 1)) * blk_flop
-    if full / rate <= target_s:
+    import synth
+    threads_all = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+    def forward_row(wk, hostk):
+        t, order, kp, rd, tv, mat = hostk
+        n = wk.nt - 1
+        G = oracle.Green(kp, rd, tv, mat)
+        W = oracle.Weights.build(t, order, wk.beta, wk.ntau, wk.tau_order)
+        sig = oracle.sigma_row(G, np.full(wk.N, wk.U), n)
+        return G, W, sig, n
+
+    def measure(wk, hostk, threads):
+        oracle.set_threads(threads)
+        G, W, sig, n = forward_row(wk, hostk)
+        N = wk.N
+        blk_flop = 8.0 * N ** 3
+        rows_flop = lambda m0, m1: sum((n + 1) + (m + 1) + wk.ntau for m in range(m0, m1)) * blk_flop
+        full = rows_flop(0, n + 1) + wk.ntau * ((n + 1) + (wk.ntau + 1)) * blk_flop
+        mid = n // 2
         t0 = time.perf_counter()
-        oracle.collision(G, sig, W, n)
-        dt = time.perf_counter() - t0
-        return {"value": full / dt / 1e9, "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
-                "sample": f"the whole forward row n={n} (all m, all four integrals; "
-                          f"{full / 1e9:.1f} GFLOP in {dt:.1f} s)"}
-    rows = max(threads, int(target_s * rate / rows_flop(mid, mid + 1)) // threads * threads)
-    m0 = max(0, mid - rows // 2)
-    m1 = min(n + 1, m0 + rows)
-    t0 = time.perf_counter()
-    oracle.collision(G, sig, W, n, m0, m1, oracle.F_IR | oracle.F_IL | oracle.F_ITV)
-    dt = time.perf_counter() - t0
-    fl = rows_flop(m0, m1)
-    return {"value": fl / dt / 1e9, "unit": "GFLOP/s", "cores": min(threads, m1 - m0),
-            "kind": "oracle",
-            "sample": f"rows m in [{m0},{m1}) of row n={n}: I^R, I^<, I^] "
-                      f"({fl / 1e9:.1f} GFLOP in {dt:.1f} s)"}
+        oracle.collision(G, sig, W, n, mid, min(n + 1, mid + threads),
+                         oracle.F_IR | oracle.F_IL | oracle.F_ITV)
+        rate = rows_flop(mid, min(n + 1, mid + threads)) / max(time.perf_counter() - t0, 1e-9)
+        if full / rate <= target_s:
+            run = lambda: oracle.collision(G, sig, W, n)
+            fl, what = full, f"the whole forward row n={n} (all m, all four integrals)"
+        else:
+            rows = max(threads, int(target_s * rate / rows_flop(mid, mid + 1)) // threads * threads)
+            m0 = max(0, mid - rows // 2)
+            m1 = min(n + 1, m0 + rows)
+            run = lambda: oracle.collision(G, sig, W, n, m0, m1,
+                                           oracle.F_IR | oracle.F_IL | oracle.F_ITV)
+            fl, what = rows_flop(m0, m1), f"rows m in [{m0},{m1}) of row n={n}: I^R, I^<, I^]"
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            run()
+            ts.append(time.perf_counter() - t0)
+        dt = float(np.median(ts))
+        return {"gflops": fl / dt / 1e9, "threads": threads, "median_s": dt, "runs_s": ts,
+                "gflop": fl / 1e9, "sample": what}
+
+    small = synth.PARITY_SMALL
+    t0_, o0_ = synth.grid(small.seed, small.nt, small.hmin, small.hmax, small.omin, small.omax)
+    host0 = (t0_, o0_, synth.kp(small.seed, small.N, t0_), synth.rdiag(small.N, small.nt),
+             synth.tv(small.seed, small.N, small.ntau, t0_), synth.mat(small.seed, small.N, small.ntau))
+    res = {"parity_small": {f"threads_{k}": measure(small, host0, k) for k in (1, threads_all)},
+           "headline": {f"threads_{k}": measure(w, host, k) for k in (1, threads_all)}}
+    oracle.set_threads(threads_all)
+    top = res["headline"][f"threads_{threads_all}"]
+    return {"value": top["gflops"], "unit": "GFLOP/s", "cores": threads_all, "kind": "oracle",
+            "sample": top["sample"] + f" ({top['gflop']:.1f} GFLOP, median of 3 runs)",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(), "runs": res}
 
 
 def small_orbital_shape(kbe, torch, dev, reps=5):
@@ -355,12 +433,60 @@ def batching(kbe, torch, dev, reps=10):
                     "gflops": vflop / vjp_ms / 1e6, "over_forward": vjp_ms / batched_ms}}
 
 
+def propagation(kbe, torch, dev):
+    """End-to-end gradients through a propagation (kbe_propagate, kbe_propagate_vjp) on the
+    8-orbital differentiation grid (1024 points): the forward sweep and the adjoint sweep timed
+    with HIP events after one warm-up run, with the loss, its gradients and the drift of the
+    particle number (conserved by the method)."""
+    import synth
+    P = synth.PROPAGATION
+    N, nt, last = P["N"], P["nt"], P["last"]
+    t, order = synth.grid(P["seed"], nt, P["hmin"], P["hmax"], P["omin"], P["omax"])
+    h0 = synth.tight_binding(N)
+    out = []
+    for U, ntau in P["cases"]:
+        mat, rho = synth.free_thermal(h0, P["beta"], ntau)
+        pr = kbe.Propagation(t, order, h0, ntau=ntau, beta=P["beta"], mat=mat,
+                             rho0=None if ntau else rho, iters=P["iters"],
+                             pulse_t0=P["pulse_t0"], pulse_sigma=P["pulse_sigma"], device=dev)
+        u = torch.full((N,), U, dtype=torch.float64, device=dev)
+        gd = torch.zeros((nt, N), dtype=torch.float64, device=dev)
+        gd[-last:, 0] = 1.0
+        pr.run(u, P["pulse_amp"])
+        pr.vjp(gd)
+        torch.cuda.synchronize()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record()
+        d = pr.run(u, P["pulse_amp"])
+        e[1].record()
+        gu, ga = pr.vjp(gd)
+        e[2].record()
+        torch.cuda.synchronize()
+        fwd, adj = e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2])
+        dh = d.cpu().numpy()
+        tr = dh.sum(axis=1)
+        out.append({"U": U, "ntau": ntau, "forward_ms": fwd, "adjoint_ms": adj,
+                    "adjoint_over_forward": adj / fwd, "ms_per_step_forward": fwd / nt,
+                    "loss": float(dh[-last:, 0].sum()), "dL_dU": float(gu.sum()),
+                    "dL_dA": float(ga), "particle_number_drift": float(np.abs(tr - tr[0]).max()),
+                    "workspace_gb": pr.nb / 1e9})
+        del pr
+        torch.cuda.empty_cache()
+    return {"workload": f"N{N}_nt{nt} propagation, steps U[{P['hmin']},{P['hmax']}], orders "
+                        f"{P['omin']}..{P['omax']}, beta {P['beta']}, pulse A={P['pulse_amp']} "
+                        f"at t={P['pulse_t0']} width {P['pulse_sigma']}, loss n_0 over the last "
+                        f"{last} steps, {P['iters']} fixed-point iterations",
+            "cases": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--ceilings", action="store_true",
+                    help="only run the ceiling microbenchmarks and write profiles/ceilings.json")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three plain 1 GiB device-to-device copies: the reference "
                          "reading that scales FETCH_SIZE / WRITE_SIZE to bytes")
@@ -386,7 +512,19 @@ def main():
     import synth
 
     kbe.lib()
+    if args.ceilings:
+        c = ceilings(kbe, torch)
+        c["command"] = "python bench.py --ceilings"
+        c["gpu"] = torch.cuda.get_device_name(0)
+        path = os.path.join(ROOT, "profiles", "ceilings.json")
+        with open(path, "w") as f:
+            json.dump(c, f, indent=1)
+            f.write("\n")
+        print(json.dumps(c), flush=True)
+        return
     dev = torch.device("cuda:0")
+    log("ceiling microbenchmarks")
+    ceil = ceilings(kbe, torch)
     w = synth.HEADLINE
     N, nt, ntau, n = w.N, w.nt, w.ntau, w.nt - 1
     log(f"generating {w.name} inputs on the host")
@@ -494,10 +632,11 @@ def main():
             "algorithmic_flop": c["fwd_flop"], "algorithmic_bytes": c["fwd_bytes"],
             "intensity_flop_per_byte": c["fwd_flop"] / c["fwd_bytes"],
             "hbm_frac": c["fwd_bytes"] / coll_s / 1e9 / HBM_PEAK_GBS,
-            "frac_of_measured_mfma_ceiling": achieved / MEASURED_MFMA_F64_TFLOPS,
+            "frac_of_measured_mfma_ceiling": achieved / ceil["mfma_f64_4x4x4_tflops"],
             "measured_read_gbps": (traffic / coll_s / 1e9) if traffic else None,
             "measured_read_frac_of_ceiling":
-                (traffic / coll_s / 1e9 / MEASURED_HBM_READ_GBS) if traffic else None},
+                (traffic / coll_s / 1e9 / ceil["hbm_read_gbs"]) if traffic else None},
+        "ceilings": ceil,
         "per_call_ms": {name: {"median": float(np.median(ph[:, i])), "min": float(ph[:, i].min())}
                         for i, name in enumerate(("weights", "sigma_2b", "collision",
                                                   "collision_vjp", "sigma_2b_vjp"))},
@@ -515,6 +654,8 @@ def main():
     log("batching workload")
     result["batching"] = batching(kbe, torch, dev)
     torch.cuda.empty_cache()
+    log("end-to-end gradients through a propagation")
+    result["propagation"] = propagation(kbe, torch, dev)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample)")
         result["cpu_baseline"] = cpu_baseline(w, (t, order, kp_h, rd_h, tv_h, mat_h))

@@ -63,9 +63,10 @@ def _load():
                                           I32, I32, I32, P, P, P, P, P, P, P, P, P, P, P]
         lib.orc_sigma_row_vjp.argtypes = [I32, I32, I32, I64, P, P, P, P, I32, P, P, P, P, P, P, P]
         lib.orc_gf2_block.argtypes = [I32, P, P, P, P]
+        lib.orc_set_threads.argtypes = [I32]
         for name in ("orc_gauss_legendre", "orc_local_weights", "orc_weights", "orc_tau_weights",
                      "orc_sigma_pair", "orc_sigma_row", "orc_collision", "orc_collision_vjp",
-                     "orc_sigma_row_vjp", "orc_gf2_block"):
+                     "orc_sigma_row_vjp", "orc_gf2_block", "orc_set_threads"):
             getattr(lib, name).restype = None
         _lib = lib
     return _lib
@@ -80,6 +81,11 @@ def _p(a):
 
 def _c(a, dtype=np.complex128):
     return np.ascontiguousarray(a, dtype=dtype)
+
+
+def set_threads(k: int) -> None:
+    """Thread count of the oracle's OpenMP loops (results do not depend on it)."""
+    _load().orc_set_threads(int(k))
 
 
 def gauss_legendre(m: int):

@@ -27,6 +27,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef double complex cplx;
 
@@ -691,3 +694,14 @@ void orc_gf2_block(int N, const double *U, const cplx *A, const cplx *C, cplx *o
     }
 #undef U4
 }
+
+/* Thread count of the OpenMP loops above (timing of the oracle as a CPU baseline; the results
+ * do not depend on it: every output is summed by one thread in a fixed order). */
+void orc_set_threads(int k) {
+#ifdef _OPENMP
+  omp_set_num_threads(k);
+#else
+  (void)k;
+#endif
+}
+

@@ -72,3 +72,15 @@ hipError_t launch_propagate_vjp(const kbe_prop *P, const kbe_wts *W, const kbe_g
 extern "C" int64_t kbe_internal_audit_tasks(int32_t N, int32_t nt, int32_t ntau, int64_t ldt,
                                             int32_t n, int32_t m0, int32_t m1, uint32_t flags,
                                             int32_t adjoint, int64_t *terms_checked);
+
+// Ceiling microbenchmarks (kbe_ceilings.hip; used by the benchmark's --ceilings mode).
+// kind 0: FP64 MFMA 4x4x4 stream, 1: FP64 MFMA 16x16x4 stream, 2: HBM read of `bytes` from src,
+// 3: copy of `bytes` from src to dst.  out: device doubles, kbe_internal_ceiling_out_count() of
+// them.  Returns 0, or 1 for a bad kind, 4 for a launch failure.
+extern "C" int32_t kbe_internal_ceiling_run(int32_t kind, const void *src, void *dst,
+                                            int64_t bytes, double *out, int32_t iters,
+                                            void *stream);
+// FLOP (kinds 0, 1) or HBM bytes (kinds 2, 3) of one launch.
+extern "C" double kbe_internal_ceiling_counts(int32_t kind, int64_t bytes, int32_t iters);
+extern "C" int64_t kbe_internal_ceiling_out_count(void);
+

@@ -164,6 +164,39 @@ PARITY_SMALL = Workload("N2_nt64_ntau64", 2, 64, 64, 10.0, 0.02, 0.08, 5, 5, 5, 
 HEADLINE = Workload("N16_nt2048_ntau512", 16, 2048, 512, 20.0, 0.005, 0.05, 3, 6, 5, 1.0, 1001)
 DIFFERENTIATION = Workload("N8_nt1024_ntau256", 8, 1024, 256, 10.0, 0.005, 0.05, 3, 6, 5, 2.0, 1003)
 
+# The propagation (end-to-end gradients) on the differentiation grid: 8-site open tight-binding
+# chain (hopping -1), initial state the free thermal state at beta (G^M with a thermal branch, its
+# density matrix without one), Gaussian pulse of amplitude 1 at t = 2 with width 1 on h_00, loss
+# n_0 summed over the last 32 steps, two fixed-point iterations per step.  Thermal branch at
+# U = 1; U = 2 without it (the free G^M is not an equilibrium of the U = 2 mixed branch).
+PROPAGATION = dict(N=8, nt=1024, beta=10.0, hmin=0.005, hmax=0.05, omin=3, omax=6, seed=1003,
+                   pulse_amp=1.0, pulse_t0=2.0, pulse_sigma=1.0, last=32, iters=2,
+                   cases=((1.0, 256), (2.0, 0)))
+
+
+def tight_binding(N: int, hop: float = -1.0) -> np.ndarray:
+    """Open chain: h[i][i+1] = h[i+1][i] = hop, on-site 0."""
+    h = np.zeros((N, N))
+    for i in range(N - 1):
+        h[i, i + 1] = h[i + 1, i] = hop
+    return h
+
+
+def free_thermal(h: np.ndarray, beta: float, ntau: int):
+    """Initial state of a propagation: the free thermal state of the real symmetric h at beta, as
+    (G^M(tau_j) for tau_j = j beta / (ntau - 1), complex128 [ntau][N][N], or None when ntau == 0;
+    the density matrix f(h) [N][N]).  G^M(tau) = -exp(-h tau)(1 - f(h)) with its endpoints the
+    one-sided limits 0+ and beta-, evaluated in the eigenbasis of h so the large and small
+    exponentials never meet in a matrix product."""
+    e, v = np.linalg.eigh(h)
+    f = 1.0 / (np.exp(beta * e) + 1.0)
+    rho = (v * f) @ v.T
+    if ntau == 0:
+        return None, rho
+    taus = np.linspace(0.0, beta, ntau)
+    mat = np.array([(v * (-np.exp(-e * x) * (1.0 - f))) @ v.T for x in taus])
+    return mat.astype(np.complex128), rho
+
 
 def green(w: Workload, decay: float = 0.3, ldt: int | None = None):
     """Full random Green's function of a workload: dict with t, order, kp, rdiag, tv, mat."""
