@@ -321,6 +321,50 @@ def test_sigma_and_collision_graph_capture(gpu, N):
             assert np.array_equal(to_host(a), b), rep
 
 
+@pytest.mark.parametrize("N", [4, 16])
+def test_weights_sigma_collision_graph_capture(gpu, N):
+    """The whole forward step [kbe_weights_dev -> kbe_sigma_2b -> kbe_collision] captured in one
+    graph (the grid in device memory): every replay, with eager work between replays, reproduces
+    the eager result bitwise, weights included; kbe_weights (host grid) refuses the capturing
+    stream with KBE_ENOTSUP."""
+    import torch
+    kbe = gpu
+    case = Case(N=N, nt=150, ntau=20, beta=3.0, seed=80 + N)
+    t, order, kp, rd, tv, mat = case.host()
+    Gd = device_green(kp, rd, tv, mat)
+    u = to_dev(np.full(N, 1.1))
+    n = case.nt - 1
+    td, od = to_dev(t), to_dev(np.asarray(order, np.int32))
+
+    def step():
+        W = kbe.weights_dev(td, od, case.ntau, case.beta, case.tau_order, check=False)
+        return (W.w, W.wtau, W.wtau_fwd) + kbe.collision(Gd, kbe.sigma_2b(Gd, u, n), W, n)
+
+    eager = [to_host(x) for x in step()]
+    Wo = oracle.Weights.build(t, order, case.beta, case.ntau, case.tau_order)
+    assert np.abs(eager[0] - Wo.w).max() < 1e-12 * np.abs(Wo.w).max()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        out = step()
+        with pytest.raises(kbe.KBEError, match="KBE_ENOTSUP"):
+            kbe.weights(t, order, case.ntau, case.beta, case.tau_order)
+    for rep in range(3):
+        for x in out:
+            x.fill_(float("nan"))
+        kbe.collision(Gd, kbe.sigma_2b(Gd, u, n), device_weights(Wo), n)  # eager work between
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(out, eager):
+            assert np.array_equal(to_host(a), b), rep
+
+
 @pytest.mark.parametrize("N,nt,ntau,sldt", [(1, 9, 5, 9), (3, 12, 0, 12), (8, 10, 6, 13),
                                             (16, 7, 4, 7)])
 def test_sigma_full_mode_matches_oracle(gpu, N, nt, ntau, sldt):
