@@ -197,15 +197,18 @@ class State:
         return KP, TV
 
 
-def rhs(P: Problem, S: State, n, col_n, row_n, tv_n, u, A, mat):
+def rhs(P: Problem, S: State, n, col_n, row_n, tv_n, u, A, mat, W=None, tn=None, choose=None):
     """f of every element of step n at the given row/column n: (fU [n] for m < n, fR [n],
-    fD, fT [ntau], fbu, fbr) with fbu / fbr the derivatives at birth of U_n and R_n."""
+    fD, fT [ntau], fbu, fbr) with fbu / fbr the derivatives at birth of U_n and R_n.
+    W (default P.weights()) holds the history weights; tn (default P.t[n]) the time; choose, when
+    given, is called with (GL, GR, Sigma row) before the history sums and may set W's row n (the
+    adaptive history order)."""
     N = P.N
-    W = P.weights()
+    W = P.weights() if W is None else W
     KP, TV = S.dense(n, col_n, row_n, tv_n)
     GL, GR, GG = views(KP, N)
     D = col_n[n]
-    tn = float(P.t[n])
+    tn = float(P.t[n]) if tn is None else float(tn)
     pulse = torch.exp(torch.tensor(-(tn - P.pulse_t0) ** 2 / (2 * P.pulse_sigma ** 2),
                                    dtype=torch.float64))
     e00 = torch.zeros((N, N), dtype=CT)
@@ -213,6 +216,8 @@ def rhs(P: Problem, S: State, n, col_n, row_n, tv_n, u, A, mat):
     eps = torch.tensor(P.h0, dtype=CT) + (A * pulse).to(CT) * e00 + \
         torch.diag(-1j * u.to(CT) * torch.diagonal(D))
     sig = sigma_row(GL, GG, tv_n, u, n)
+    if choose is not None:
+        choose(GL, GR, sig)
     IRl, ILl, Itv, Jtv = collision(GL, GR, GG, TV, mat, sig, W, n, greater=False)
     IRg, ILg, _, _ = collision(GL, GR, GG, TV, mat, sig, W, n, greater=True)
     Cl = IRl + ILl + Itv
