@@ -288,6 +288,8 @@ class Adaptive:
                     h, q = replay[n]["t"] - self.t[-1], replay[n]["q"]
                 else:
                     h = min(h, c.t_end - self.t[-1])
+                    if not h > 1e-13 * max(1.0, self.t[-1]):
+                        raise FloatingPointError(f"step size underflow at t = {self.t[-1]}")
                 q = min(q, n)
                 tn = self.t[-1] + h
                 tg = np.array(self.t + [tn])
@@ -313,6 +315,8 @@ class Adaptive:
                     y = ynew
                     if replay is not None:
                         continue
+                    if not math.isfinite(d):
+                        break
                     if m > 1:
                         R = max(0.3 * R, d / dprev) if dprev > 0 else 0.0
                     if min(1.0, R) * d * C < 0.1:
@@ -322,7 +326,7 @@ class Adaptive:
                         break
                     dprev = d
                 E = self._wrms([C * (a_ - b_) for a_, b_ in zip(y, pred)], ewt)
-                if replay is None and not conv:
+                if replay is None and (not conv or not math.isfinite(E)):
                     self.t.pop()
                     self.rejected += 1
                     h *= 0.25
@@ -367,6 +371,8 @@ class Adaptive:
                 vals = [coef * divided_difference(ts, [hi[j] for j in range(n - npts + 1, n + 1)])
                         for hi in hist]
                 Eq = self._wrms(vals, ewt)
+                if not math.isfinite(Eq):
+                    continue
                 cand.append((1.0 / ((bias * Eq) ** (1.0 / (qq + 1)) + 1e-6), qq))
         eta, qn = cand[0]
         for e, qq in cand[1:]:
