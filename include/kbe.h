@@ -565,6 +565,77 @@ kbe_status kbe_propagate_vjp(const kbe_prop *P, const kbe_wts *W, const kbe_gree
                              const double *gdens, double *gu, double *gamp, void *ws,
                              size_t ws_bytes, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * kbe_propagate_adaptive — the adaptive propagation (Sec. "Adaptive Time
+ * Stepping" and Sec. "Adaptive History Integration"): the stacked state of
+ * kbe_propagate advanced by variable-step, variable-order Adams methods on a
+ * grid that grows by one point per accepted step.
+ *
+ * Step n (from t_{n-1} by h, order q <= min(qmax, n)) for every block: the
+ * predictor integrates over [t_{n-1}, t_n] the interpolant of the block's right
+ * sides at t_{n-q..n-1}; the corrector is the Adams-Moulton rule of order q
+ * (the local weights of Eq. weights on t_{n-q+1..n}), solved by fixed-point
+ * iteration (at most maxcor corrections; converged when
+ * min(1, R_m) d_m C < 0.1 with d_m the WRMS norm of the last correction,
+ * R_m = max(0.3 R_{m-1}, d_m / d_{m-1}), R_1 = 1, and C the error-estimate
+ * coefficient; a diverging or non-converged iteration retries with h / 4).
+ * Before every evaluation of the right sides the history order is chosen: the
+ * test integral of G^R(t_n,s) Sigma^<(s,t_n) + G^<(t_n,s) Sigma^A(s,t_n) over
+ * [t_{n-1}, t_n] with k = 1..min(kmax, n+1) nodes, k_opt the first minimiser
+ * of ||I^(k) - I^(k-1)||_F over k >= 2, and row n of the history weights is
+ * row n-1 plus the local weights on k_opt nodes.  The local error is
+ * C (y_n - y_pred) with C = |c_AM / (c_AB - c_AM)| from the principal error
+ * coefficients of the corrector and the predictor (Milne's device), measured
+ * in the WRMS norm of Eq. wrms_norm with the weights of Eq. ewt
+ * (1 / (rtol |y_{n-1}| + atol), per complex entry); E > 1 rejects the step
+ * (h times max(0.2, min(0.9, 0.9 E^(-1/(q+1)))); q = 1 and h / 4 after three
+ * rejections).  After an accepted step the right sides are evaluated at the
+ * accepted values, and those of the blocks born at t_n (kp[.][n], kp[n][.])
+ * are reconstructed at the qmax points below the diagonal from the history
+ * sums of Eq. KBE2 at rows j < n (Sec. "Implementation": the equations hold on
+ * both sides of the diagonal), so every block has a history of q points.  The
+ * next step: eta_q = 1 / ((6 E)^(1/(q+1)) + 1e-6) and, once q+1 steps were
+ * taken at order q, eta_{q-1}, eta_{q+1} from the WRMS norms of the
+ * corresponding error coefficients times divided differences of the right
+ * sides (biases 6 and 10); the largest wins (q on ties); below 1.5 nothing
+ * changes, else h grows by at most 10.  The last step ends at t_end.
+ *
+ * Arguments: P as for kbe_propagate (t, order and lam are not used: the grid
+ * is built here); C the controls; W: wtau and wtau_fwd of the tau grid (W->w
+ * is not used: the history weights are built in the workspace); G with
+ * capacity G->nt points (mat read; kp, rdiag, tv written; kp[0][0] read when
+ * ntau == 0); dens device [G->nt][N] (rows 0..trace->nt-1 written); trace:
+ * host arrays of G->nt entries (ks: G->nt x (12 + 2)), filled by the call;
+ * ws: kbe_propagate_adaptive_workspace(N, G->nt, ntau) bytes.  The call
+ * synchronises the stream at every fixed-point iteration (the controller
+ * reads the norms).  Errors: KBE_EINVAL (NULL pointers, bad controls),
+ * KBE_ENOMEM (workspace), KBE_EHIP.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  double t_end;    /* final time > 0 */
+  double rtol;     /* relative tolerance > 0 */
+  double atol;     /* absolute tolerance > 0 */
+  double h0;       /* first step > 0 */
+  int32_t qmax;    /* largest Adams order, 1..12 */
+  int32_t kmax;    /* largest history order K, 2..KBE_KMAX */
+  int32_t maxcor;  /* fixed-point corrections per attempt, 1..12 */
+} kbe_adapt_ctl;
+
+typedef struct {
+  double *t;         /* [capacity] accepted grid */
+  int32_t *q;        /* [capacity] Adams order of step n (q[0] = 0) */
+  int32_t *m;        /* [capacity] fixed-point iterations of step n */
+  int32_t *ks;       /* [capacity][14] history order of each evaluation of step n (m + 1) */
+  double *err;       /* [capacity] error norm E of step n */
+  int32_t nt;        /* out: points of the grid (steps + 1) */
+  int32_t rejected;  /* out: rejected attempts */
+} kbe_adapt_trace;
+
+size_t kbe_propagate_adaptive_workspace(int32_t N, int32_t capacity, int32_t ntau);
+kbe_status kbe_propagate_adaptive(const kbe_prop *P, const kbe_adapt_ctl *C, const kbe_wts *W,
+                                  const kbe_green *G, double *dens, kbe_adapt_trace *trace,
+                                  void *ws, size_t ws_bytes, void *stream);
+
 /* Human-readable name of a status code (static string). */
 const char *kbe_status_string(kbe_status s);
 /* Detail of the last error on the calling thread ("" if none). */

@@ -42,6 +42,18 @@ class _Prop(ctypes.Structure):
                 ("order", ctypes.c_void_p), ("lam", ctypes.c_void_p)]
 
 
+class _AdaptCtl(ctypes.Structure):
+    _fields_ = [("t_end", ctypes.c_double), ("rtol", ctypes.c_double), ("atol", ctypes.c_double),
+                ("h0", ctypes.c_double), ("qmax", ctypes.c_int32), ("kmax", ctypes.c_int32),
+                ("maxcor", ctypes.c_int32)]
+
+
+class _AdaptTrace(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_void_p), ("q", ctypes.c_void_p), ("m", ctypes.c_void_p),
+                ("ks", ctypes.c_void_p), ("err", ctypes.c_void_p), ("nt", ctypes.c_int32),
+                ("rejected", ctypes.c_int32)]
+
+
 class _Green(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int32), ("nt", ctypes.c_int32), ("ntau", ctypes.c_int32),
                 ("ldt", ctypes.c_int64), ("kp", ctypes.c_void_p), ("rdiag", ctypes.c_void_p),
@@ -84,6 +96,7 @@ EXPORTS = ("kbe_weights_workspace", "kbe_weights", "kbe_sigma_2b", "kbe_collisio
            "kbe_collision_batch_vjp_workspace", "kbe_collision_batch_vjp",
            "kbe_weights_dev_workspace", "kbe_weights_dev", "kbe_step_weights",
            "kbe_propagate_workspace", "kbe_propagate", "kbe_propagate_vjp",
+           "kbe_propagate_adaptive_workspace", "kbe_propagate_adaptive",
            "kbe_status_string",
            "kbe_last_error", "kbe_version")
 
@@ -125,6 +138,9 @@ def lib():
             "kbe_propagate_workspace": (SZ, [I32, I32, I32, I64, I32]),
             "kbe_propagate": (I32, [ctypes.POINTER(_Prop), W, G, P, P, SZ, P]),
             "kbe_propagate_vjp": (I32, [ctypes.POINTER(_Prop), W, G, P, P, P, P, SZ, P]),
+            "kbe_propagate_adaptive_workspace": (SZ, [I32, I32, I32]),
+            "kbe_propagate_adaptive": (I32, [ctypes.POINTER(_Prop), ctypes.POINTER(_AdaptCtl), W,
+                                             G, P, ctypes.POINTER(_AdaptTrace), P, SZ, P]),
             "kbe_status_string": (ctypes.c_char_p, [I32]),
             "kbe_last_error": (ctypes.c_char_p, []),
             "kbe_version": (I32, []),
@@ -686,4 +702,57 @@ class KBEPropagate(torch.autograd.Function):
     def backward(ctx, gdens):
         gu, ga = ctx.prop.vjp(gdens)
         return None, gu, ga
+
+
+KS_STRIDE = 14  # history orders recorded per step in the adaptive trace
+
+
+def propagate_adaptive(h0, u, pulse_amp, t_end, *, ntau=0, beta=1.0, tau_order=5, mat=None,
+                       rho0=None, capacity=4096, rtol=1e-6, atol=1e-10, h_first=1e-3, qmax=12,
+                       kmax=10, maxcor=3, pulse_t0=2.0, pulse_sigma=1.0, device="cuda:0"):
+    """kbe_propagate_adaptive: returns a dict with the grid t, the per-step orders q, iteration
+    counts m, history orders ks (one list per step, the iterations and the final evaluation),
+    error norms err, the number of rejected attempts, the densities dens [nt, N] and the solution
+    G (capacity points allocated, the first len(t) used).  The trace has the oracle's replay
+    format in `replay` ([None] + one dict per step)."""
+    import numpy as np
+    dev = torch.device(device)
+    h0 = np.ascontiguousarray(h0, np.float64)
+    N = h0.shape[0]
+    u = torch.as_tensor(np.broadcast_to(np.asarray(u, np.float64), (N,)).copy(), device=dev)
+    zero_t = torch.zeros(1, dtype=torch.float64, device=dev)
+    one_o = torch.ones(1, dtype=torch.int32, device=dev)
+    W = weights_dev(zero_t, one_o, ntau, beta, tau_order)
+    z = lambda *sh: torch.zeros(sh, dtype=torch.complex128, device=dev)
+    G = Green(z(capacity, capacity, N, N), z(capacity, N, N),
+              z(capacity, ntau, N, N) if ntau else None,
+              torch.tensor(np.asarray(mat, np.complex128), device=dev) if ntau else None)
+    if not ntau:
+        G.kp[0, 0] = 1j * torch.tensor(np.asarray(rho0, np.complex128), device=dev)
+    dens = torch.zeros((capacity, N), dtype=torch.float64, device=dev)
+    h0d = torch.tensor(h0, device=dev)
+    P = _Prop(1, _ptr(h0d), _ptr(u), float(pulse_amp), float(pulse_t0), float(pulse_sigma), None,
+              None, None)
+    C = _AdaptCtl(float(t_end), float(rtol), float(atol), float(h_first), int(qmax), int(kmax),
+                  int(maxcor))
+    tt = np.zeros(capacity)
+    qq = np.zeros(capacity, np.int32)
+    mm = np.zeros(capacity, np.int32)
+    kk = np.zeros((capacity, KS_STRIDE), np.int32)
+    ee = np.zeros(capacity)
+    T = _AdaptTrace(tt.ctypes.data, qq.ctypes.data, mm.ctypes.data, kk.ctypes.data,
+                    ee.ctypes.data, 0, 0)
+    L = lib()
+    nb = L.kbe_propagate_adaptive_workspace(N, capacity, ntau)
+    ws = _ws(nb, dev)
+    _check(L.kbe_propagate_adaptive(ctypes.byref(P), ctypes.byref(C), ctypes.byref(W.c()),
+                                    ctypes.byref(G.c()), _ptr(dens), ctypes.byref(T), _ptr(ws), nb,
+                                    _stream(dev)), "kbe_propagate_adaptive")
+    n = T.nt
+    del ws
+    replay = [None] + [{"t": float(tt[i]), "q": int(qq[i]), "m": int(mm[i]),
+                        "ks": [int(x) for x in kk[i, : mm[i] + 1]]} for i in range(1, n)]
+    return {"t": tt[:n].copy(), "q": qq[:n].copy(), "m": mm[:n].copy(),
+            "ks": [r["ks"] for r in replay[1:]], "err": ee[:n].copy(), "rejected": T.rejected,
+            "dens": dens[:n], "G": G, "replay": replay, "workspace_bytes": nb}
 

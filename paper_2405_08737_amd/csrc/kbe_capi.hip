@@ -440,6 +440,37 @@ kbe_status kbe_propagate_vjp(const kbe_prop *P, const kbe_wts *W, const kbe_gree
                     "kbe_propagate_vjp");
 }
 
+size_t kbe_propagate_adaptive_workspace(int32_t N, int32_t capacity, int32_t ntau) {
+  if (N < 1 || N > KBE_NMAX || capacity < 2 || ntau < 0 || ntau == 1) return 0;
+  return kbe::prop_adaptive_ws_bytes(N, capacity, ntau);
+}
+
+kbe_status kbe_propagate_adaptive(const kbe_prop *P, const kbe_adapt_ctl *C, const kbe_wts *W,
+                                  const kbe_green *G, double *dens, kbe_adapt_trace *trace,
+                                  void *ws, size_t ws_bytes, void *stream) {
+  kbe_status s = check_green(G, "G");
+  if (s != KBE_OK) return s;
+  if (!P || !C || !W || !dens || !trace) return fail(KBE_EINVAL, "P, C, W, dens or trace is NULL");
+  if (!P->h0 || !P->u) return fail(KBE_EINVAL, "P->h0 or P->u is NULL");
+  if (!(P->pulse_sigma > 0)) return fail(KBE_EINVAL, "pulse_sigma = %g <= 0", P->pulse_sigma);
+  if (G->nt < 2) return fail(KBE_EINVAL, "capacity nt = %d < 2", G->nt);
+  if (!(C->t_end > 0) || !(C->rtol > 0) || !(C->atol > 0) || !(C->h0 > 0))
+    return fail(KBE_EINVAL, "t_end, rtol, atol and h0 must be > 0");
+  if (C->qmax < 1 || C->qmax > 12) return fail(KBE_EINVAL, "qmax = %d outside 1..12", C->qmax);
+  if (C->kmax < 2 || C->kmax > KBE_KMAX)
+    return fail(KBE_EINVAL, "kmax = %d outside 2..%d", C->kmax, KBE_KMAX);
+  if (C->maxcor < 1 || C->maxcor > 12) return fail(KBE_EINVAL, "maxcor = %d outside 1..12", C->maxcor);
+  if (G->ntau > 0 && (!W->wtau || !W->wtau_fwd))
+    return fail(KBE_EINVAL, "tau weights are NULL with ntau > 0");
+  if (!trace->t || !trace->q || !trace->m || !trace->ks || !trace->err)
+    return fail(KBE_EINVAL, "a trace array is NULL");
+  const size_t need = kbe_propagate_adaptive_workspace(G->N, G->nt, G->ntau);
+  if (!ws || ws_bytes < need) return fail(KBE_ENOMEM, "workspace %zu bytes < %zu", ws_bytes, need);
+  return hip_status(kbe::launch_propagate_adaptive(P, C, W, G, dens, trace, ws,
+                                                   (hipStream_t)stream),
+                    "kbe_propagate_adaptive");
+}
+
 // ---------------------------------------------------------------------------------------
 // Batches of history rows.
 // ---------------------------------------------------------------------------------------

@@ -20,6 +20,8 @@ hipError_t launch_grid_check(const double *t, const int32_t *order, int nt, int3
                              hipStream_t st);
 hipError_t launch_step_weights(const double *t, const int32_t *order, int nt, double *lam,
                                hipStream_t st);
+hipError_t launch_interval_weights(const double *t, int n, int kam, int kab, double *am,
+                                   double *ab, hipStream_t st);
 
 // Self-energy and its adjoint (kbe_sigma.hip).
 hipError_t launch_sigma_row(const kbe_green *G, const double *u, int n, const kbe_sigma_row *out,
@@ -60,6 +62,10 @@ hipError_t launch_propagate(const kbe_prop *P, const kbe_wts *W, const kbe_green
 hipError_t launch_propagate_vjp(const kbe_prop *P, const kbe_wts *W, const kbe_green *G,
                                 const double *gdens, double *gu, double *gamp, void *ws,
                                 hipStream_t st);
+size_t prop_adaptive_ws_bytes(int N, int nt, int ntau);
+hipError_t launch_propagate_adaptive(const kbe_prop *P, const kbe_adapt_ctl *ctl,
+                                     const kbe_wts *W, const kbe_green *G, double *dens,
+                                     kbe_adapt_trace *tr, void *ws, hipStream_t st);
 
 }  // namespace kbe
 

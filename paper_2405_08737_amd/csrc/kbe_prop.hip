@@ -30,6 +30,9 @@
 // stored iterates and calling the collision and self-energy adjoints (kbe_collision_vjp,
 // kbe_sigma_2b_vjp), so that d(loss)/du and d(loss)/dA of a loss on the densities
 // n_i(t_n) = Re(-i G^<_ii(t_n,t_n)) are exact derivatives of the discrete map above.
+#include <cmath>
+#include <vector>
+
 #include "kbe_dev.h"
 #include "kbe_internal.h"
 
@@ -60,7 +63,15 @@ struct PA {                       // everything the small kernels read, passed b
   kbe_c128 *ybar, *bbar, *fbar, *epart;  // [elements][E]
   kbe_c128 *CbL, *CbG, *CbT, *Jbar;      // cotangents of the history sums
   kbe_c128 *gretL, *glesL, *gretG, *glesG;
+  // adaptive propagation: one method order q for every element, rules of the current interval,
+  // right sides of U_m / R_m below their birth (fpu[m][i], fpr[m][i]: at t_{m-1-i}, i < QM)
+  int adaptive, q;
+  const double *amt, *abt;          // [KM][KM]: corrector (k nodes) and predictor (q nodes) rules
+  const double *wtau_;              // [ntau] the full-range tau rule
+  kbe_c128 *fpu, *fpr;
 };
+
+constexpr int QM = 12;  // the largest Adams order of the adaptive propagation
 
 __device__ __forceinline__ int64_t E_(const PA &a) { return (int64_t)a.N * a.N; }
 __device__ __forceinline__ int nelem(const PA &a, int n) { return 2 * n + 1 + a.ntau; }
@@ -79,13 +90,16 @@ __device__ __forceinline__ int birth(int kind, int idx) {
   return (kind == EU || kind == ER) ? idx : 0;
 }
 
-// Nodes of the rule of interval n for an element born at t_b.
+// Nodes of the rule of interval n for an element born at t_b (adaptive: the step's order, every
+// element having a history of that length).
 __device__ __forceinline__ int nodes(const PA &a, int n, int b) {
+  if (a.adaptive) return a.q;
   int k = a.order[n];
   k = k < 1 ? 1 : (k > KM ? KM : k);
   return k < n - b + 1 ? k : n - b + 1;
 }
 __device__ __forceinline__ const double *lamrow(const PA &a, int n, int k) {
+  if (a.adaptive) return a.amt + (int64_t)(k - 1) * KM;
   return a.lam + ((int64_t)n * KM + (k - 1)) * KM;
 }
 
@@ -121,8 +135,12 @@ __device__ __forceinline__ kbe_c128 *f_ptr(const PA &a, kbe_c128 *fkp, kbe_c128 
                                            int idx) {
   const int64_t E = E_(a), nt = a.nt;
   switch (kind) {
-    case EU: return j == idx ? fbu + idx * E : fkp + ((int64_t)idx * nt + j) * E;
-    case ER: return j == idx ? fbr + idx * E : fkp + ((int64_t)j * nt + idx) * E;
+    case EU:
+      if (j < idx) return a.fpu + ((int64_t)idx * QM + (idx - 1 - j)) * E;  // below its birth
+      return j == idx ? fbu + idx * E : fkp + ((int64_t)idx * nt + j) * E;
+    case ER:
+      if (j < idx) return a.fpr + ((int64_t)idx * QM + (idx - 1 - j)) * E;
+      return j == idx ? fbr + idx * E : fkp + ((int64_t)j * nt + idx) * E;
     case ED: return fkp + ((int64_t)j * nt + j) * E;
     case ET: return ftv + ((int64_t)j * a.ntau + idx) * E;
     case EBU: return fbu + (int64_t)j * E;
@@ -285,7 +303,7 @@ __global__ void prop_commit(PA a, int n, int slot) {
   elem_of(a, n, e, kind, idx);
   const cd y = ld(a.ynext + gid);
   st(val_ptr(a, a.kp, a.tv, n, kind, idx) + q, y);
-  st(slot_ptr(a, slot, n, kind, idx) + q, y);
+  if (slot >= 0) st(slot_ptr(a, slot, n, kind, idx) + q, y);
 }
 
 // Row/column n from iterate `slot` (adjoint: the values an evaluation saw).
@@ -755,6 +773,281 @@ Ctx make_ctx(const kbe_prop *P, const kbe_wts *W, const kbe_green *G, void *ws, 
   return x;
 }
 
+// ---------------------------------------------------------------------------------------------
+// Adaptive propagation (Sec. "Adaptive Time Stepping", Sec. "Adaptive History Integration"):
+// the kernels of a step; the controller is host code below.
+// ---------------------------------------------------------------------------------------------
+struct AA {                        // adaptive-only arrays
+  double *t;                       // [nt] the grid (device copy, written point by point)
+  double *w;                       // [nt][nt] history weights, built row by row
+  kbe_c128 *ypred;                 // [elements][E] predictor values
+  kbe_c128 *sret, *sles, *stv;     // Sigma rows of the current evaluation
+  kbe_c128 *Sret, *Sles, *Stv;     // Sigma rows of every accepted step [nt][nt], [nt][ntau]
+  kbe_c128 *epsall;                // [nt][E] eps of every accepted step
+  kbe_c128 *ubuf;                  // [KM][E] test-integrand values
+  kbe_c128 *Cl, *Cg;               // [QM][E] history sums above the diagonal
+  double *part;                    // [NPART] norm partial sums
+  double *res;                     // [8] norm results
+  int32_t *kbuf;                   // [QM + 2] history order of every evaluation of a step
+  double rtol, atol;
+};
+
+constexpr int NPART = 1024;
+
+__global__ void ad_set_t(double *t, int n, double v) {
+  if (threadIdx.x == 0) t[n] = v;
+}
+
+// Adams base sums (corrector history part) and predictors of step n at order a.q; the predictor
+// becomes the current value of row/column n.
+__global__ void ad_predict(PA a, AA b, int n) {
+  const int64_t E = E_(a);
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)nelem(a, n) * E) return;
+  const int e = (int)(gid / E), q = (int)(gid % E);
+  int kind, idx;
+  elem_of(a, n, e, kind, idx);
+  const int k = a.q;
+  const double *L = a.amt + (int64_t)(k - 1) * KM, *B = a.abt + (int64_t)(k - 1) * KM;
+  const kbe_c128 *pp = prev_ptr(a, a.kp, a.tv, n, kind, idx);
+  const int r = q / a.N, c = q % a.N;
+  const cd prev = pp ? ld(pp + q) : cd{0.0, r == c ? -1.0 : 0.0};
+  cd base = prev, pred = prev;
+  for (int i = 0; i + 1 < k; ++i)
+    base = base + L[i] * ld(f_ptr(a, a.fkp, a.fbu, a.fbr, a.ftv, n - k + 1 + i, kind, idx) + q);
+  for (int i = 0; i < k; ++i)
+    pred = pred + B[i] * ld(f_ptr(a, a.fkp, a.fbu, a.fbr, a.ftv, n - k + i, kind, idx) + q);
+  st(a.base + gid, base);
+  st(b.ypred + gid, pred);
+  st(val_ptr(a, a.kp, a.tv, n, kind, idx) + q, pred);
+}
+
+// The history order of interval n (Sec. "Adaptive History Integration"): the test integrand
+// u(t_s) = G^R(t_n,t_s) Sigma^<(t_s,t_n) + G^<(t_n,t_s) Sigma^A(t_s,t_n) at s = n-K+1..n
+// (Sigma^<(t_s,t_n) = -Sigma^<(t_n,t_s)^dagger, Sigma^A(t_s,t_n) = Sigma^R(t_n,t_s)^dagger,
+// G^<(t_n,t_s) = -kp[s][n]^dagger), its integrals I^(k) over the interval with k = 1..K nodes,
+// k_opt = the first minimum of ||I^(k) - I^(k-1)||_F over k = 2..K, and row n of the history
+// weights: row n-1 plus the local weights on k_opt nodes.  One workgroup; fixed-order sums.
+__global__ void __launch_bounds__(256) ad_choose(PA a, AA b, int n, int K, int slot) {
+  const int64_t E = E_(a);
+  const int N = a.N;
+  __shared__ double dk[KM + 1];
+  __shared__ double red[256];
+  __shared__ int kopt;
+  const int tid = threadIdx.x;
+  for (int64_t x = tid; x < (int64_t)K * E; x += 256) {  // u at s = n-K+1+i
+    const int i = (int)(x / E), q = (int)(x % E), r = q / N, c = q % N;
+    const int sidx = n - K + 1 + i;
+    const kbe_c128 *gr = sidx < n ? a.kp + ((int64_t)n * a.ldt + sidx) * E : a.rdiag + n * E;
+    const kbe_c128 *gl = a.kp + ((int64_t)sidx * a.ldt + n) * E;  // G^<(t_n,t_s) = -gl^dagger
+    const kbe_c128 *sl = b.sles + sidx * E, *sr = b.sret + sidx * E;
+    cd acc = czero();
+    for (int k = 0; k < N; ++k) {
+      acc = acc - ld(gr + r * N + k) * cj(ld(sl + c * N + k));   // G^R (-Sigma^<^dagger)
+      // G^<(t_n,t_s): -kp[s][n]^dagger, or kp[n][n] itself on the diagonal
+      const cd g = sidx < n ? -cj(ld(gl + k * N + r)) : ld(gl + r * N + k);
+      acc = acc + g * cj(ld(sr + c * N + k));                      // G^< Sigma^R^dagger
+    }
+    st(b.ubuf + x, acc);
+  }
+  __syncthreads();
+  for (int k = 2; k <= K; ++k) {  // ||I^(k) - I^(k-1)||_F^2, entries summed in a fixed tree
+    double part = 0.0;
+    for (int q = tid; q < E; q += 256) {
+      cd ik = czero(), ik1 = czero();
+      const double *Lk = a.amt + (int64_t)(k - 1) * KM, *Lk1 = a.amt + (int64_t)(k - 2) * KM;
+      for (int i = 0; i < k; ++i) ik = ik + Lk[i] * ld(b.ubuf + (int64_t)(K - k + i) * E + q);
+      for (int i = 0; i < k - 1; ++i) ik1 = ik1 + Lk1[i] * ld(b.ubuf + (int64_t)(K - k + 1 + i) * E + q);
+      const cd d = ik - ik1;
+      part += d.re * d.re + d.im * d.im;
+    }
+    red[tid] = part;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+      if (tid < off) red[tid] += red[tid + off];
+      __syncthreads();
+    }
+    if (tid == 0) dk[k] = sqrt(red[0]);
+    __syncthreads();
+  }
+  if (tid == 0) {
+    int best = 2;
+    for (int k = 3; k <= K; ++k)
+      if (dk[k] < dk[best]) best = k;
+    kopt = best;
+    b.kbuf[slot] = best;
+  }
+  __syncthreads();
+  const int k = kopt, lo = n - k + 1;
+  const double *L = a.amt + (int64_t)(k - 1) * KM;
+  for (int sidx = tid; sidx < a.nt; sidx += 256) {
+    double v = sidx < n ? b.w[(int64_t)(n - 1) * a.nt + sidx] : 0.0;
+    if (sidx >= lo && sidx <= n) v += L[sidx - lo];
+    b.w[(int64_t)n * a.nt + sidx] = v;
+  }
+}
+
+// Weighted root-mean-square norms over the entries of step n's elements (Eq. wrms_norm), with the
+// weights of Eq. ewt from the values at t_{n-1}.  kind 0: ynext - current; 1: C (current -
+// predictor); 2: coef * f[t_{n-npts+1}..t_n] (a divided difference of every element's right
+// sides).  Partial sums per workgroup, then one ordered sum.
+__global__ void __launch_bounds__(256) ad_norm_part(PA a, AA b, int n, int kind, double C,
+                                                    int npts, double coef) {
+  const int64_t E = E_(a);
+  const int64_t tot = (int64_t)nelem(a, n) * E;
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x; gid < tot;
+       gid += (int64_t)gridDim.x * 256) {
+    const int e = (int)(gid / E), q = (int)(gid % E);
+    int kind_e, idx;
+    elem_of(a, n, e, kind_e, idx);
+    const kbe_c128 *pp = prev_ptr(a, a.kp, a.tv, n, kind_e, idx);
+    const int r = q / a.N, c = q % a.N;
+    const cd prev = pp ? ld(pp + q) : cd{0.0, r == c ? -1.0 : 0.0};
+    const double wt = 1.0 / (b.rtol * sqrt(prev.re * prev.re + prev.im * prev.im) + b.atol);
+    cd v;
+    if (kind == 0) {
+      v = ld(a.ynext + gid) - ld(val_ptr(a, a.kp, a.tv, n, kind_e, idx) + q);
+    } else if (kind == 1) {
+      v = C * (ld(val_ptr(a, a.kp, a.tv, n, kind_e, idx) + q) - ld(b.ypred + gid));
+    } else {
+      cd d[QM + 2];
+      double tt[QM + 2];
+      for (int i = 0; i < npts; ++i) {
+        const int j = n - npts + 1 + i;
+        tt[i] = b.t[j];
+        d[i] = ld(f_ptr(a, a.fkp, a.fbu, a.fbr, a.ftv, j, kind_e, idx) + q);
+      }
+      for (int lev = 1; lev < npts; ++lev)
+        for (int i = 0; i + lev < npts; ++i)
+          d[i] = (1.0 / (tt[i + lev] - tt[i])) * (d[i + 1] - d[i]);
+      v = coef * d[0];
+    }
+    const double m = sqrt(v.re * v.re + v.im * v.im) * wt;
+    acc += m * m;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) b.part[blockIdx.x] = red[0];
+}
+
+__global__ void ad_norm_final(AA b, int nparts, int64_t count, int slot) {
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int i = 0; i < nparts; ++i) s += b.part[i];
+  b.res[slot] = sqrt(s / (double)(count > 0 ? count : 1));
+}
+
+// Keep the Sigma row and eps of the accepted step n (the history of later reconstructions).
+__global__ void ad_keep(PA a, AA b, int n) {
+  const int64_t E = E_(a);
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nrow = (int64_t)(n + 1) * E;
+  if (gid < nrow) {
+    st(b.Sret + (int64_t)n * a.nt * E + gid, ld(b.sret + gid));
+    st(b.Sles + (int64_t)n * a.nt * E + gid, ld(b.sles + gid));
+  } else if (gid < nrow + (int64_t)a.ntau * E) {
+    const int64_t g2 = gid - nrow;
+    st(b.Stv + (int64_t)n * a.ntau * E + g2, ld(b.stv + g2));
+  } else if (gid < nrow + (int64_t)a.ntau * E + E) {
+    const int64_t g3 = gid - nrow - (int64_t)a.ntau * E;
+    st(b.epsall + (int64_t)n * E + g3, ld(a.eps + g3));
+  }
+}
+
+// History sums of Eq. KBE2 at row j < n and column n (the lesser form C^< and the greater form
+// C^>), for j = j0..n-1: I^R with upper limit t_j (weights row j), I^< with upper limit t_n
+// (weights row n), Sigma(t_j, t_s) for s > j read from row s through the symmetry
+// Sigma(t_j,t_s) = -Sigma(t_s,t_j)^dagger (Sigma^> = Sigma^R + Sigma^< in the stored rows).
+__global__ void ad_upper(PA a, AA b, int n, int j0) {
+  const int64_t E = E_(a);
+  const int N = a.N;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)(n - j0) * E) return;
+  const int j = j0 + (int)(gid / E), q = (int)(gid % E), r = q / N, c = q % N;
+  const double *wj = b.w + (int64_t)j * a.nt, *wn = b.w + (int64_t)n * a.nt;
+  cd irl = czero(), irg = czero(), ill = czero(), ilg = czero(), itv = czero();
+  for (int s = 0; s <= j; ++s) {  // Sigma^R(t_j,t_s) G^<(t_s,t_n), G^>(t_s,t_n)
+    const kbe_c128 *SR = b.Sret + ((int64_t)j * a.nt + s) * E;
+    const kbe_c128 *GL = a.kp + ((int64_t)s * a.ldt + n) * E;        // G^<(s,n)
+    const kbe_c128 *GRns = a.kp + ((int64_t)n * a.ldt + s) * E;      // G^R(n,s), s < n
+    cd x = czero(), y = czero();
+    for (int k = 0; k < N; ++k) {
+      const cd sr = ld(SR + r * N + k);
+      const cd gl = ld(GL + k * N + c);
+      const cd gg = gl - cj(ld(GRns + c * N + k));  // G^>(s,n) = kp[s][n] - kp[n][s]^dagger
+      x = x + sr * gl;
+      y = y + sr * gg;
+    }
+    irl = irl + wj[s] * x;
+    irg = irg + wj[s] * y;
+  }
+  for (int s = 0; s <= n; ++s) {  // Sigma^<(t_j,t_s), Sigma^>(t_j,t_s) times G^A(t_s,t_n)
+    const kbe_c128 *GA = s < n ? a.kp + ((int64_t)n * a.ldt + s) * E : a.rdiag + n * E;
+    cd x = czero(), y = czero();
+    for (int k = 0; k < N; ++k) {
+      cd sl, sg;
+      if (s <= j) {
+        sl = ld(b.Sles + ((int64_t)j * a.nt + s) * E + r * N + k);
+        sg = sl + ld(b.Sret + ((int64_t)j * a.nt + s) * E + r * N + k);
+      } else {
+        const cd l = ld(b.Sles + ((int64_t)s * a.nt + j) * E + k * N + r);
+        const cd g = l + ld(b.Sret + ((int64_t)s * a.nt + j) * E + k * N + r);
+        sl = -cj(l);
+        sg = -cj(g);
+      }
+      const cd ga = cj(ld(GA + c * N + k));  // G^A(s,n)[k][c] = conj(G^R(n,s)[c][k])
+      x = x + sl * ga;
+      y = y + sg * ga;
+    }
+    ill = ill + wn[s] * x;
+    ilg = ilg + wn[s] * y;
+  }
+  if (a.ntau > 0) {
+    const int J = a.ntau - 1;
+    for (int l = 0; l < a.ntau; ++l) {
+      const kbe_c128 *S = b.Stv + ((int64_t)j * a.ntau + l) * E;
+      const kbe_c128 *T = a.tv + ((int64_t)n * a.ntau + (J - l)) * E;
+      cd x = czero();
+      for (int k = 0; k < N; ++k) x = x + ld(S + r * N + k) * cj(ld(T + c * N + k));
+      itv = itv + a.wtau_[l] * x;
+    }
+    itv = mul_mi(itv);
+  }
+  st(b.Cl + (int64_t)(j - j0) * E + q, irl + ill + itv);
+  st(b.Cg + (int64_t)(j - j0) * E + q, irg + ilg + itv);
+}
+
+// Right sides of the blocks born at t_n below their birth: U_n at t_j, i (G^<(t_n,t_j) eps_j -
+// C^<(j,n)^dagger) with G^<(t_n,t_j) = -kp[j][n]^dagger; R_n (continued: -kp[n][j]^dagger) at
+// t_j, -i (eps_j (-kp[n][j]^dagger) + C^>(j,n) - C^<(j,n)).
+__global__ void ad_recon(PA a, AA b, int n, int j0) {
+  const int64_t E = E_(a);
+  const int N = a.N;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)(n - j0) * E) return;
+  const int jj = (int)(gid / E), j = j0 + jj, q = (int)(gid % E), r = q / N, c = q % N;
+  const kbe_c128 *ep = b.epsall + (int64_t)j * E;
+  const kbe_c128 *U = a.kp + ((int64_t)j * a.ldt + n) * E;   // kp[j][n]
+  const kbe_c128 *R = a.kp + ((int64_t)n * a.ldt + j) * E;   // kp[n][j]
+  const kbe_c128 *Cl = b.Cl + (int64_t)jj * E, *Cg = b.Cg + (int64_t)jj * E;
+  cd fu = czero(), fr = czero();
+  for (int k = 0; k < N; ++k) {
+    fu = fu - cj(ld(U + k * N + r)) * ld(ep + k * N + c);  // (-kp[j][n]^dagger) eps_j
+    fr = fr - ld(ep + r * N + k) * cj(ld(R + c * N + k));  // eps_j (-kp[n][j]^dagger)
+  }
+  fu = mul_i(fu - cj(ld(Cl + c * N + r)));
+  fr = mul_mi(fr + ld(Cg + q) - ld(Cl + q));
+  const int i = n - 1 - j;  // < QM
+  st(a.fpu + ((int64_t)n * QM + i) * E + q, fu);
+  st(a.fpr + ((int64_t)n * QM + i) * E + q, fr);
+}
+
 }  // namespace
 
 size_t prop_ws_bytes(int N, int nt, int ntau, int64_t ldt, int K) {
@@ -783,6 +1076,365 @@ hipError_t launch_propagate(const kbe_prop *P, const kbe_wts *W, const kbe_green
     hipLaunchKernelGGL(prop_rhs, dim3(blocks((ne + 2) * E)), dim3(256), 0, st, a, n, 1);
     hipLaunchKernelGGL(prop_dens, dim3(1), dim3(64), 0, st, a, n, dens);
   }
+  return hipGetLastError();
+}
+
+namespace {
+
+// Host-side helpers of the adaptive controller (the same formulas as the oracle's).
+double poly_integral(const double *x, int k, double a, double b) {  // int_a^b prod (s - x_i) ds
+  // Gauss-Legendre with m >= (k + 1) / 2 points (Newton on the three-term recurrence)
+  const int m = k / 2 + 2;
+  double acc = 0.0;
+  for (int i = 0; i < m; ++i) {
+    double z = cos(M_PI * (i + 0.75) / (m + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int l = 1; l < m; ++l) {
+        const double p2 = ((2.0 * l + 1.0) * z * p1 - l * p0) / (l + 1.0);
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = m * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (fabs(dz) < 1e-16) break;
+    }
+    const double wgt = 2.0 / ((1.0 - z * z) * dp * dp);
+    const double sv = 0.5 * (b - a) * z + 0.5 * (a + b);
+    double pr = 1.0;
+    for (int l = 0; l < k; ++l) pr *= sv - x[l];
+    acc += wgt * pr;
+  }
+  return 0.5 * (b - a) * acc;
+}
+
+double factorial(int q) {
+  double f = 1.0;
+  for (int i = 2; i <= q; ++i) f *= i;
+  return f;
+}
+
+struct ALay {
+  size_t fkp, fbu, fbr, ftv, fpu, fpr, t, w, eps, sret, sles, stv, Sret, Sles, Stv, epsall, IRl,
+      ILl, Itv, Jtv, IRg, ILg, base, ynext, ypred, ubuf, Cl, Cg, amt, abt, part, res, kbuf, cws,
+      total;
+};
+
+ALay alayout(int N, int nt, int ntau) {
+  const size_t E = (size_t)N * N * sizeof(kbe_c128);
+  const size_t nt2 = (size_t)nt * nt, ne = (size_t)(2 * nt + 1 + ntau + 2);
+  ALay L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) { const size_t r = o; o += al(bytes); return r; };
+  L.fkp = take(nt2 * E);
+  L.fbu = take(nt * E);
+  L.fbr = take(nt * E);
+  L.ftv = take((size_t)nt * ntau * E);
+  L.fpu = take((size_t)nt * QM * E);
+  L.fpr = take((size_t)nt * QM * E);
+  L.t = take(nt * sizeof(double));
+  L.w = take(nt2 * sizeof(double));
+  L.eps = take(E);
+  L.sret = take(nt * E);
+  L.sles = take(nt * E);
+  L.stv = take(ntau * E);
+  L.Sret = take(nt2 * E);
+  L.Sles = take(nt2 * E);
+  L.Stv = take((size_t)nt * ntau * E);
+  L.epsall = take(nt * E);
+  L.IRl = take(nt * E);
+  L.ILl = take(nt * E);
+  L.Itv = take(nt * E);
+  L.Jtv = take(ntau * E);
+  L.IRg = take(nt * E);
+  L.ILg = take(nt * E);
+  L.base = take(ne * E);
+  L.ynext = take(ne * E);
+  L.ypred = take(ne * E);
+  L.ubuf = take((size_t)KM * E);
+  L.Cl = take((size_t)QM * E);
+  L.Cg = take((size_t)QM * E);
+  L.amt = take(KM * KM * sizeof(double));
+  L.abt = take(KM * KM * sizeof(double));
+  L.part = take(NPART * sizeof(double));
+  L.res = take(8 * sizeof(double));
+  L.kbuf = take((QM + 4) * sizeof(int32_t));
+  const int n = nt - 1;
+  size_t cw = collision_ws_bytes(N, nt, ntau, n, 0, n + 1, KBE_OUT_ALL);
+  const size_t cw2 = collision_ws_bytes(N, nt, ntau, n, 0, n + 1, FG);
+  L.cws = take(cw > cw2 ? cw : cw2);
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+size_t prop_adaptive_ws_bytes(int N, int nt, int ntau) { return alayout(N, nt, ntau).total; }
+
+hipError_t launch_propagate_adaptive(const kbe_prop *P, const kbe_adapt_ctl *ctl,
+                                     const kbe_wts *W, const kbe_green *G, double *dens,
+                                     kbe_adapt_trace *tr, void *ws, hipStream_t st) {
+  const ALay L = alayout(G->N, G->nt, G->ntau);
+  char *wsb = (char *)ws;
+  auto c = [&](size_t off) { return (kbe_c128 *)(wsb + off); };
+  PA a{};
+  a.N = G->N;
+  a.nt = G->nt;
+  a.ntau = G->ntau;
+  a.K = 0;
+  a.ldt = G->ldt;
+  a.kp = G->kp;
+  a.rdiag = G->rdiag;
+  a.tv = G->tv;
+  a.mat = G->mat;
+  a.h0 = P->h0;
+  a.u = P->u;
+  a.amp = P->pulse_amp;
+  a.t0 = P->pulse_t0;
+  a.sig = P->pulse_sigma;
+  a.fkp = c(L.fkp);
+  a.fbu = c(L.fbu);
+  a.fbr = c(L.fbr);
+  a.ftv = c(L.ftv);
+  a.fpu = c(L.fpu);
+  a.fpr = c(L.fpr);
+  a.eps = c(L.eps);
+  a.IRl = c(L.IRl);
+  a.ILl = c(L.ILl);
+  a.Itv = c(L.Itv);
+  a.Jtv = c(L.Jtv);
+  a.IRg = c(L.IRg);
+  a.ILg = c(L.ILg);
+  a.base = c(L.base);
+  a.ynext = c(L.ynext);
+  a.adaptive = 1;
+  a.q = 1;
+  a.amt = (const double *)(wsb + L.amt);
+  a.abt = (const double *)(wsb + L.abt);
+  a.wtau_ = W->wtau;
+  double *tdev = (double *)(wsb + L.t);
+  double *wdev = (double *)(wsb + L.w);
+  a.t = tdev;
+  AA b{};
+  b.t = tdev;
+  b.w = wdev;
+  b.ypred = c(L.ypred);
+  b.sret = c(L.sret);
+  b.sles = c(L.sles);
+  b.stv = c(L.stv);
+  b.Sret = c(L.Sret);
+  b.Sles = c(L.Sles);
+  b.Stv = c(L.Stv);
+  b.epsall = c(L.epsall);
+  b.ubuf = c(L.ubuf);
+  b.Cl = c(L.Cl);
+  b.Cg = c(L.Cg);
+  b.part = (double *)(wsb + L.part);
+  b.res = (double *)(wsb + L.res);
+  b.kbuf = (int32_t *)(wsb + L.kbuf);
+  b.rtol = ctl->rtol;
+  b.atol = ctl->atol;
+  const int N = a.N, nt = a.nt, ntau = a.ntau;
+  const int64_t E = (int64_t)N * N;
+  kbe_green Gc = *G;
+  kbe_sigma_row sig{b.sret, b.sles, ntau ? b.stv : nullptr};
+  const bool th = ntau > 0;
+  hipError_t e;
+  // history weights: the collision reads rows 0..n of w (row stride nt)
+  kbe_wts Wc{wdev, W->wtau, W->wtau_fwd};
+  auto coll = [&](int n) -> hipError_t {
+    Params p{};
+    p.N = N;
+    p.nt = nt;
+    p.ntau = ntau;
+    p.J = ntau - 1;
+    p.n = n;
+    p.m0 = 0;
+    p.m1 = n + 1;
+    p.ldt = a.ldt;
+    p.kp = a.kp;
+    p.rdiag = a.rdiag;
+    p.tv = a.tv;
+    p.mat = a.mat;
+    p.ret = sig.ret;
+    p.les = sig.les;
+    p.stv = sig.tv;
+    p.w = Wc.w;
+    p.wtau = Wc.wtau;
+    p.wf = Wc.wtau_fwd;
+    set_flags(p, FL, th);
+    hipError_t r = launch_collision(p, FL, a.IRl, a.ILl, a.Itv, a.Jtv, wsb + L.cws, st);
+    if (r != hipSuccess) return r;
+    set_flags(p, FG, th);
+    return launch_collision(p, FG, a.IRg, a.ILg, nullptr, nullptr, wsb + L.cws, st);
+  };
+  // one evaluation of the right sides at the current values of step n; kslot: where the history
+  // order is recorded (n >= 1)
+  auto evaluate = [&](int n, int kslot) -> hipError_t {
+    hipError_t r = launch_sigma_row(&Gc, a.u, n, &sig, st);
+    if (r != hipSuccess) return r;
+    if (n >= 1) {
+      const int K = ctl->kmax < n + 1 ? ctl->kmax : n + 1;
+      hipLaunchKernelGGL(ad_choose, dim3(1), dim3(256), 0, st, a, b, n, K, kslot);
+    }
+    if ((r = coll(n)) != hipSuccess) return r;
+    hipLaunchKernelGGL(prop_eps, dim3(1), dim3(256), 0, st, a, n);
+    return hipGetLastError();
+  };
+  hipError_t nerr = hipSuccess;
+  auto norm = [&](int n, int kind, double C, int npts, double coef, int slot) -> double {
+    const int64_t tot = (int64_t)(2 * n + 1 + ntau) * E;
+    int nb = (int)((tot + 255) / 256);
+    nb = nb < NPART ? nb : NPART;
+    hipLaunchKernelGGL(ad_norm_part, dim3(nb), dim3(256), 0, st, a, b, n, kind, C, npts, coef);
+    hipLaunchKernelGGL(ad_norm_final, dim3(1), dim3(64), 0, st, b, nb, tot, slot);
+    double v = 0.0;
+    hipError_t r = hipMemcpyAsync(&v, b.res + slot, sizeof(double), hipMemcpyDeviceToHost, st);
+    if (r == hipSuccess) r = hipStreamSynchronize(st);
+    if (r != hipSuccess) {
+      nerr = r;
+      return NAN;
+    }
+    return v;
+  };
+  std::vector<double> t(1, 0.0);
+  // t = 0: the initial state, its right sides, the weights row 0 (zero)
+  hipLaunchKernelGGL(fill_zero<double>, dim3(blocks((int64_t)nt * nt)), dim3(256), 0, st, wdev,
+                     (int64_t)nt * nt);
+  hipLaunchKernelGGL(ad_set_t, dim3(1), dim3(64), 0, st, tdev, 0, 0.0);
+  hipLaunchKernelGGL(prop_init, dim3(blocks((int64_t)(nt + ntau) * E)), dim3(256), 0, st, a);
+  if ((e = evaluate(0, 0)) != hipSuccess) return e;
+  hipLaunchKernelGGL(prop_rhs, dim3(blocks((int64_t)(ntau + 3) * E)), dim3(256), 0, st, a, 0, 1);
+  hipLaunchKernelGGL(ad_keep, dim3(blocks((int64_t)(1 + ntau + 1) * E)), dim3(256), 0, st, a, b, 0);
+  hipLaunchKernelGGL(prop_dens, dim3(1), dim3(64), 0, st, a, 0, dens);
+  tr->t[0] = 0.0;
+  tr->q[0] = 0;
+  tr->m[0] = 0;
+  tr->err[0] = 0.0;
+  for (int i = 0; i <= QM + 1; ++i) tr->ks[i] = 0;
+  tr->rejected = 0;
+  double h = ctl->h0;
+  int q = 1, at_q = 0, n = 1;
+  const int ksw = QM + 2;  // trace stride of the history orders
+  while (n < nt && t.back() < ctl->t_end * (1.0 - 1e-14)) {
+    int nfail = 0, m = 0;
+    double E_err = 0.0, tn = 0.0;
+    std::vector<int32_t> ks;
+    for (;;) {
+      h = h < ctl->t_end - t.back() ? h : ctl->t_end - t.back();
+      if (!(h > 1e-13 * (t.back() > 1.0 ? t.back() : 1.0))) {  // step size underflow
+        tr->nt = n;
+        return hipErrorInvalidValue;
+      }
+      q = q < n ? q : n;
+      tn = t.back() + h;
+      hipLaunchKernelGGL(ad_set_t, dim3(1), dim3(64), 0, st, tdev, n, tn);
+      const int kam = (ctl->kmax > q ? ctl->kmax : q);
+      if ((e = launch_interval_weights(tdev, n, kam, q, (double *)(wsb + L.amt),
+                                       (double *)(wsb + L.abt), st)) != hipSuccess)
+        return e;
+      a.q = q;
+      // error-estimate coefficient (Milne's device, the same formula as the oracle's)
+      std::vector<double> tg(t);
+      tg.push_back(tn);
+      const double cam = poly_integral(&tg[n - q + 1], q, tg[n - 1], tg[n]) / factorial(q);
+      const double cab = poly_integral(&tg[n - q], q, tg[n - 1], tg[n]) / factorial(q);
+      const double C = fabs(cam / (cab - cam));
+      const int64_t ne = 2 * n + 1 + ntau;
+      hipLaunchKernelGGL(ad_predict, dim3(blocks(ne * E)), dim3(256), 0, st, a, b, n);
+      bool conv = false;
+      double R = 1.0, dprev = 0.0;
+      m = 0;
+      while (m < ctl->maxcor) {
+        ++m;
+        if ((e = evaluate(n, m - 1)) != hipSuccess) return e;
+        hipLaunchKernelGGL(prop_rhs, dim3(blocks(ne * E)), dim3(256), 0, st, a, n, 0);
+        const double d = norm(n, 0, 0.0, 0, 0.0, 0);
+        if (nerr != hipSuccess) return nerr;
+        hipLaunchKernelGGL(prop_commit, dim3(blocks(ne * E)), dim3(256), 0, st, a, n, -1);
+        if (!std::isfinite(d)) break;  // a non-finite iterate: not converged
+        if (m > 1) R = dprev > 0 ? (0.3 * R > d / dprev ? 0.3 * R : d / dprev) : 0.0;
+        if ((R < 1.0 ? R : 1.0) * d * C < 0.1) {
+          conv = true;
+          break;
+        }
+        if (m > 1 && d > 2.0 * dprev) break;
+        dprev = d;
+      }
+      E_err = norm(n, 1, C, 0, 0.0, 1);
+      if (nerr != hipSuccess) return nerr;
+      if (!conv || !std::isfinite(E_err)) {
+        ++tr->rejected;
+        h *= 0.25;
+        continue;
+      }
+      if (E_err > 1.0) {
+        ++tr->rejected;
+        ++nfail;
+        if (nfail >= 3) {
+          q = 1;
+          at_q = 0;
+          h *= 0.25;
+        } else {
+          const double eta = 0.9 * pow(E_err, -1.0 / (q + 1));
+          h *= eta > 0.9 ? 0.9 : (eta < 0.2 ? 0.2 : eta);
+        }
+        continue;
+      }
+      break;
+    }
+    // accept: the right sides once more at the accepted values, the step's history
+    if ((e = evaluate(n, m)) != hipSuccess) return e;
+    const int64_t ne = 2 * n + 1 + ntau;
+    hipLaunchKernelGGL(prop_rhs, dim3(blocks((ne + 2) * E)), dim3(256), 0, st, a, n, 1);
+    hipLaunchKernelGGL(ad_keep, dim3(blocks((int64_t)(n + 1 + ntau + 1) * E)), dim3(256), 0, st, a,
+                       b, n);
+    hipLaunchKernelGGL(prop_dens, dim3(1), dim3(64), 0, st, a, n, dens);
+    const int j0 = n - ctl->qmax > 0 ? n - ctl->qmax : 0;
+    hipLaunchKernelGGL(ad_upper, dim3(blocks((int64_t)(n - j0) * E)), dim3(256), 0, st, a, b, n,
+                       j0);
+    hipLaunchKernelGGL(ad_recon, dim3(blocks((int64_t)(n - j0) * E)), dim3(256), 0, st, a, b, n,
+                       j0);
+    ks.assign(m + 1, 0);
+    if ((e = hipMemcpyAsync(ks.data(), b.kbuf, sizeof(int32_t) * (m + 1), hipMemcpyDeviceToHost,
+                            st)) != hipSuccess)
+      return e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    t.push_back(tn);
+    tr->t[n] = tn;
+    tr->q[n] = q;
+    tr->m[n] = m;
+    tr->err[n] = E_err;
+    for (int i = 0; i < ksw; ++i) tr->ks[(int64_t)n * ksw + i] = i <= m ? ks[i] : 0;
+    // next step size and order
+    ++at_q;
+    double eta = 1.0 / (pow(6.0 * E_err, 1.0 / (q + 1)) + 1e-6);
+    int qn = q;
+    if (at_q >= q + 1) {
+      for (int dq = -1; dq <= 1; dq += 2) {
+        const int qq = q + dq, npts = qq + 1;
+        if (qq < 1 || qq > ctl->qmax || npts > n + 1) continue;
+        const double coef = poly_integral(&t[n - qq + 1], qq, t[n - 1], t[n]);
+        const double Eq = norm(n, 2, 0.0, npts, coef, 2);
+        if (nerr != hipSuccess) return nerr;
+        if (!std::isfinite(Eq)) continue;
+        const double bias = dq < 0 ? 6.0 : 10.0;
+        const double e2 = 1.0 / (pow(bias * Eq, 1.0 / (qq + 1)) + 1e-6);
+        if (e2 > eta) {
+          eta = e2;
+          qn = qq;
+        }
+      }
+    }
+    if (eta >= 1.5) {
+      if (qn != q) at_q = 0;
+      q = qn;
+      h *= eta < 10.0 ? eta : 10.0;
+    }
+    ++n;
+  }
+  tr->nt = n;
   return hipGetLastError();
 }
 

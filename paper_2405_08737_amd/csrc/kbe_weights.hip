@@ -224,6 +224,25 @@ __global__ void __launch_bounds__(64) step_weights_kernel(const double *t, const
   if ((int)threadIdx.x < k) out[threadIdx.x] = l[threadIdx.x];
 }
 
+// Rules of one interval n = [t_{n-1}, t_n] for an adaptive step: am[k-1][i], the local weights
+// of Eq. weights on the k nodes t_{n-k+1..n} (k = 1..min(kam, n+1)), and ab[q-1][i], the integral
+// over the same interval of the Lagrange basis on the q nodes t_{n-q..n-1} (the predictor,
+// q = 1..min(kab, n)); other entries zero.  One 64-thread workgroup per (table, k).
+__global__ void __launch_bounds__(64) interval_weights_kernel(const double *t, int n, int kam,
+                                                              int kab, double *am, double *ab) {
+  __shared__ SolveLds S;
+  __shared__ double l[KBE_KMAX];
+  const int tab = blockIdx.x / KBE_KMAX, k = blockIdx.x % KBE_KMAX + 1;
+  double *out = (tab == 0 ? am : ab) + (int64_t)(k - 1) * KBE_KMAX;
+  if (threadIdx.x < KBE_KMAX) out[threadIdx.x] = 0.0;
+  const int kmx = tab == 0 ? (kam < n + 1 ? kam : n + 1) : (kab < n ? kab : n);
+  if (n < 1 || k > kmx) return;  // uniform per workgroup
+  const double *x = tab == 0 ? t + (n - k + 1) : t + (n - k);
+  wave_solve(x, k, t[n - 1], t[n], l, S);
+  __syncthreads();
+  if ((int)threadIdx.x < k) out[threadIdx.x] = l[threadIdx.x];
+}
+
 // Grid check on the device: status = 0, or KBE_EINVAL (t[0] != 0 or t not increasing), or
 // KBE_ERANGE (an order outside 1..KBE_KMAX).  One workgroup; a fixed-order reduction.
 __global__ void __launch_bounds__(256) grid_check_kernel(const double *t, const int32_t *order,
@@ -299,6 +318,13 @@ hipError_t launch_weights(const kbe_grid *g, double *w, double *wtau, double *wf
 hipError_t launch_grid_check(const double *t, const int32_t *order, int nt, int32_t *status,
                              hipStream_t st) {
   hipLaunchKernelGGL(grid_check_kernel, dim3(1), dim3(256), 0, st, t, order, nt, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_interval_weights(const double *t, int n, int kam, int kab, double *am,
+                                   double *ab, hipStream_t st) {
+  hipLaunchKernelGGL(interval_weights_kernel, dim3(2 * KBE_KMAX), dim3(64), 0, st, t, n, kam, kab,
+                     am, ab);
   return hipGetLastError();
 }
 
