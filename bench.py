@@ -479,6 +479,105 @@ def propagation(kbe, torch, dev):
             "cases": out}
 
 
+def adaptive(kbe, torch, dev):
+    """The adaptive propagation (kbe_propagate_adaptive): the 8-site chain at U = 1, beta = 10,
+    pulse on site 0, variable step and order at rtol 1e-8, atol 1e-10, with the thermal branch
+    (256 tau points) to t = 30 and without it to t = 40.  Each case: one warm-up run to t = 0.5,
+    then the whole run timed by the host clock (inputs resident, the controller synchronising at
+    every fixed-point iteration), the step and order statistics, the particle-number drift, and
+    the first `prefix` steps run again on their own (to t = t_prefix) for the oracle comparison.
+    Returns the report and, per case, what the oracle needs to replay the prefix."""
+    import synth
+    A = synth.ADAPTIVE
+    N = A["N"]
+    h0 = synth.tight_binding(N)
+    out, replays = [], []
+    for ntau, t_end, prefix in A["cases"]:
+        mat, rho = synth.free_thermal(h0, A["beta"], ntau)
+
+        def run(te, cap):
+            return kbe.propagate_adaptive(
+                h0, A["U"], A["pulse_amp"], te, ntau=ntau, beta=A["beta"], mat=mat,
+                rho0=None if ntau else rho, capacity=cap, rtol=A["rtol"], atol=A["atol"],
+                h_first=A["h_first"], qmax=A["qmax"], kmax=A["kmax"], maxcor=A["maxcor"],
+                pulse_t0=A["pulse_t0"], pulse_sigma=A["pulse_sigma"], device=dev)
+
+        run(0.5, 256)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = run(t_end, A["capacity"])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        t, d = g["t"], g["dens"].cpu().numpy()
+        tr = d.sum(axis=1)
+        steps = len(t) - 1
+        ks = np.concatenate([np.asarray(k) for k in g["ks"]])
+        tp = float(t[prefix])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gp = run(tp, prefix + 8)
+        torch.cuda.synchronize()
+        wall_p = time.perf_counter() - t0
+        same = len(gp["t"]) == prefix + 1 and bool(np.all(gp["q"] == g["q"][: prefix + 1]))
+        out.append({
+            "ntau": ntau, "t_end": t_end, "steps": steps, "rejected": int(g["rejected"]),
+            "wall_s": wall, "ms_per_step": 1e3 * wall / steps,
+            "fixed_point_iterations_mean": float(g["m"][1:].mean()),
+            "h_min": float(np.diff(t).min()), "h_max": float(np.diff(t).max()),
+            "adams_order_histogram": np.bincount(g["q"][1:], minlength=A["qmax"] + 1).tolist(),
+            "history_order_histogram": np.bincount(ks, minlength=A["kmax"] + 1).tolist(),
+            "particle_number": float(tr[0]),
+            "particle_number_drift": float(np.abs(tr - tr[0]).max()),
+            "n0_final": float(d[-1, 0]), "workspace_gb": g["workspace_bytes"] / 1e9,
+            "prefix": {"steps": prefix, "t": tp, "wall_s": wall_p,
+                       "ms_per_step": 1e3 * wall_p / prefix, "same_decisions": same}})
+        replays.append({"ntau": ntau, "mat": mat, "rho": rho, "replay": g["replay"][: prefix + 1],
+                        "dens": d[: prefix + 1],
+                        "kp": g["G"].kp[: prefix + 1, : prefix + 1].cpu().numpy(),
+                        "gpu_ms_per_step": 1e3 * wall_p / prefix})
+        del g, gp
+        torch.cuda.empty_cache()
+    return ({"workload": f"N{N} chain, U={A['U']}, beta={A['beta']}, half filling, pulse "
+                         f"A={A['pulse_amp']} on site 0 at t={A['pulse_t0']} width "
+                         f"{A['pulse_sigma']}; rtol {A['rtol']}, atol {A['atol']}, Adams orders "
+                         f"1..{A['qmax']}, history orders 1..{A['kmax']}, at most {A['maxcor']} "
+                         f"fixed-point corrections; thermal branch (256 tau points) to t=30, "
+                         f"no thermal branch to t=40",
+             "cases": out}, replays)
+
+
+def adaptive_oracle(replays):
+    """The oracle replaying the GPU's first steps of each adaptive case on the same grid (same
+    orders and history orders): its time per step beside the GPU's, and the largest deviations of
+    the densities and of the stored Green's function."""
+    import synth
+    from oracle import adaptive as oad
+    from oracle import propagate as oprop
+    A = synth.ADAPTIVE
+    h0 = synth.tight_binding(A["N"])
+    res = []
+    for r in replays:
+        ntau = r["ntau"]
+        P = oprop.Problem(t=np.zeros(1), order=np.zeros(1, np.int32), h0=h0, ntau=ntau,
+                          beta=A["beta"], mat=r["mat"], rho0=None if ntau else r["rho"],
+                          pulse_t0=A["pulse_t0"], pulse_sigma=A["pulse_sigma"])
+        ctl = oad.Controls(t_end=r["replay"][-1]["t"], rtol=A["rtol"], atol=A["atol"],
+                           h0=A["h_first"], qmax=A["qmax"], kmax=A["kmax"], maxcor=A["maxcor"],
+                           nt_max=len(r["replay"]))
+        o = oad.Adaptive(P, ctl)
+        t0 = time.perf_counter()
+        dens = o.run(A["U"], A["pulse_amp"], replay=r["replay"]).numpy()
+        dt = time.perf_counter() - t0
+        kp, _ = o.storage()
+        steps = len(r["replay"]) - 1
+        res.append({"ntau": ntau, "steps": steps, "oracle_s": dt,
+                    "oracle_ms_per_step": 1e3 * dt / steps,
+                    "gpu_ms_per_step": r["gpu_ms_per_step"],
+                    "dens_max_abs_diff": float(np.abs(dens - r["dens"]).max()),
+                    "kp_rel_diff": float(np.linalg.norm(kp - r["kp"]) / np.linalg.norm(kp))})
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -487,6 +586,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--ceilings", action="store_true",
                     help="only run the ceiling microbenchmarks and write profiles/ceilings.json")
+    ap.add_argument("--adaptive-only", action="store_true",
+                    help="only run the adaptive propagation cases (no oracle leg)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three plain 1 GiB device-to-device copies: the reference "
                          "reading that scales FETCH_SIZE / WRITE_SIZE to bytes")
@@ -523,6 +624,12 @@ def main():
         print(json.dumps(c), flush=True)
         return
     dev = torch.device("cuda:0")
+    if args.adaptive_only:
+        t0 = time.perf_counter()
+        rep, _ = adaptive(kbe, torch, dev)
+        rep["process_wall_s"] = time.perf_counter() - t0
+        print(json.dumps(rep), flush=True)
+        return
     log("ceiling microbenchmarks")
     ceil = ceilings(kbe, torch)
     w = synth.HEADLINE
@@ -656,9 +763,14 @@ def main():
     torch.cuda.empty_cache()
     log("end-to-end gradients through a propagation")
     result["propagation"] = propagation(kbe, torch, dev)
+    torch.cuda.empty_cache()
+    log("adaptive propagation")
+    result["adaptive"], replays = adaptive(kbe, torch, dev)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample)")
         result["cpu_baseline"] = cpu_baseline(w, (t, order, kp_h, rd_h, tv_h, mat_h))
+        log("oracle replaying the adaptive prefixes")
+        result["cpu_baseline"]["adaptive"] = adaptive_oracle(replays)
     print(json.dumps(result), flush=True)
 
 

@@ -78,7 +78,9 @@ typedef enum {
   KBE_ERANGE = 2,  /* n, m-range or order outside the allowed range */
   KBE_ENOMEM = 3,  /* workspace smaller than the *_workspace() query */
   KBE_EHIP = 4,    /* a HIP runtime call or kernel launch failed */
-  KBE_ENOTSUP = 5  /* valid request this build does not support */
+  KBE_ENOTSUP = 5, /* valid request this build does not support */
+  KBE_ESTEP = 6    /* the adaptive controller could not reach t_end (step size underflow or the
+                      grid capacity exhausted); the trace holds the steps accepted until then */
 } kbe_status;
 
 #define KBE_NMAX 16 /* largest orbital count N */
@@ -609,7 +611,9 @@ kbe_status kbe_propagate_vjp(const kbe_prop *P, const kbe_wts *W, const kbe_gree
  * ws: kbe_propagate_adaptive_workspace(N, G->nt, ntau) bytes.  The call
  * synchronises the stream at every fixed-point iteration (the controller
  * reads the norms).  Errors: KBE_EINVAL (NULL pointers, bad controls),
- * KBE_ENOMEM (workspace), KBE_EHIP.
+ * KBE_ENOMEM (workspace), KBE_EHIP, KBE_ESTEP (the step size fell below
+ * 1e-13 max(1, t), or G->nt points were accepted before t_end: trace, dens
+ * and G hold the accepted steps, trace->nt of them).
  * ------------------------------------------------------------------------- */
 typedef struct {
   double t_end;    /* final time > 0 */

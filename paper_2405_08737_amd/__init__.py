@@ -32,7 +32,16 @@ _lib = None
 
 
 class KBEError(RuntimeError):
-    pass
+    """A non-zero kbe_status.  `status` is the code; `partial` holds what a call that stopped
+    part-way produced (kbe_propagate_adaptive's accepted steps on KBE_ESTEP), else None."""
+
+    def __init__(self, msg, status=None, partial=None):
+        super().__init__(msg)
+        self.status = status
+        self.partial = partial
+
+
+KBE_ESTEP = 6
 
 
 class _Prop(ctypes.Structure):
@@ -155,7 +164,8 @@ def lib():
 def _check(st: int, what: str):
     if st != 0:
         L = lib()
-        raise KBEError(f"{what}: {L.kbe_status_string(st).decode()}: {L.kbe_last_error().decode()}")
+        raise KBEError(f"{what}: {L.kbe_status_string(st).decode()}: {L.kbe_last_error().decode()}",
+                       st)
 
 
 def _ptr(x: Optional[torch.Tensor]):
@@ -714,7 +724,8 @@ def propagate_adaptive(h0, u, pulse_amp, t_end, *, ntau=0, beta=1.0, tau_order=5
     counts m, history orders ks (one list per step, the iterations and the final evaluation),
     error norms err, the number of rejected attempts, the densities dens [nt, N] and the solution
     G (capacity points allocated, the first len(t) used).  The trace has the oracle's replay
-    format in `replay` ([None] + one dict per step)."""
+    format in `replay` ([None] + one dict per step).  A run that stops before t_end (step-size
+    underflow, capacity exhausted) raises KBEError with that dict, up to the stop, in `partial`."""
     import numpy as np
     dev = torch.device(device)
     h0 = np.ascontiguousarray(h0, np.float64)
@@ -745,14 +756,20 @@ def propagate_adaptive(h0, u, pulse_amp, t_end, *, ntau=0, beta=1.0, tau_order=5
     L = lib()
     nb = L.kbe_propagate_adaptive_workspace(N, capacity, ntau)
     ws = _ws(nb, dev)
-    _check(L.kbe_propagate_adaptive(ctypes.byref(P), ctypes.byref(C), ctypes.byref(W.c()),
-                                    ctypes.byref(G.c()), _ptr(dens), ctypes.byref(T), _ptr(ws), nb,
-                                    _stream(dev)), "kbe_propagate_adaptive")
-    n = T.nt
+    st = L.kbe_propagate_adaptive(ctypes.byref(P), ctypes.byref(C), ctypes.byref(W.c()),
+                                  ctypes.byref(G.c()), _ptr(dens), ctypes.byref(T), _ptr(ws), nb,
+                                  _stream(dev))
     del ws
+    if st not in (0, KBE_ESTEP):
+        _check(st, "kbe_propagate_adaptive")
+    n = T.nt
     replay = [None] + [{"t": float(tt[i]), "q": int(qq[i]), "m": int(mm[i]),
                         "ks": [int(x) for x in kk[i, : mm[i] + 1]]} for i in range(1, n)]
-    return {"t": tt[:n].copy(), "q": qq[:n].copy(), "m": mm[:n].copy(),
-            "ks": [r["ks"] for r in replay[1:]], "err": ee[:n].copy(), "rejected": T.rejected,
-            "dens": dens[:n], "G": G, "replay": replay, "workspace_bytes": nb}
+    res = {"t": tt[:n].copy(), "q": qq[:n].copy(), "m": mm[:n].copy(),
+           "ks": [r["ks"] for r in replay[1:]], "err": ee[:n].copy(), "rejected": T.rejected,
+           "dens": dens[:n], "G": G, "replay": replay, "workspace_bytes": nb}
+    if st == KBE_ESTEP:
+        raise KBEError(f"kbe_propagate_adaptive: {L.kbe_status_string(st).decode()}: "
+                       f"{L.kbe_last_error().decode()}", st, res)
+    return res
 

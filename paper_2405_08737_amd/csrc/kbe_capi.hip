@@ -118,6 +118,7 @@ const char *kbe_status_string(kbe_status s) {
     case KBE_ENOMEM: return "KBE_ENOMEM: workspace too small";
     case KBE_EHIP: return "KBE_EHIP: HIP runtime error";
     case KBE_ENOTSUP: return "KBE_ENOTSUP: not supported";
+    case KBE_ESTEP: return "KBE_ESTEP: adaptive controller stopped before t_end";
   }
   return "unknown kbe_status";
 }
@@ -466,9 +467,18 @@ kbe_status kbe_propagate_adaptive(const kbe_prop *P, const kbe_adapt_ctl *C, con
     return fail(KBE_EINVAL, "a trace array is NULL");
   const size_t need = kbe_propagate_adaptive_workspace(G->N, G->nt, G->ntau);
   if (!ws || ws_bytes < need) return fail(KBE_ENOMEM, "workspace %zu bytes < %zu", ws_bytes, need);
-  return hip_status(kbe::launch_propagate_adaptive(P, C, W, G, dens, trace, ws,
-                                                   (hipStream_t)stream),
-                    "kbe_propagate_adaptive");
+  int stalled = 0;
+  s = hip_status(kbe::launch_propagate_adaptive(P, C, W, G, dens, trace, ws, (hipStream_t)stream,
+                                                &stalled),
+                 "kbe_propagate_adaptive");
+  if (s != KBE_OK) return s;
+  if (stalled == 1)
+    return fail(KBE_ESTEP, "step size underflow at t = %.17g after %d points",
+                trace->t[trace->nt - 1], trace->nt);
+  if (stalled == 2)
+    return fail(KBE_ESTEP, "capacity of %d points exhausted at t = %.17g < t_end = %g", G->nt,
+                trace->t[trace->nt - 1], C->t_end);
+  return s;
 }
 
 // ---------------------------------------------------------------------------------------

@@ -65,7 +65,8 @@ hipError_t launch_propagate_vjp(const kbe_prop *P, const kbe_wts *W, const kbe_g
 size_t prop_adaptive_ws_bytes(int N, int nt, int ntau);
 hipError_t launch_propagate_adaptive(const kbe_prop *P, const kbe_adapt_ctl *ctl,
                                      const kbe_wts *W, const kbe_green *G, double *dens,
-                                     kbe_adapt_trace *tr, void *ws, hipStream_t st);
+                                     kbe_adapt_trace *tr, void *ws, hipStream_t st,
+                                     int *stalled);
 
 }  // namespace kbe
 

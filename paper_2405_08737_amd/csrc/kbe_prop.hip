@@ -786,6 +786,7 @@ struct AA {                        // adaptive-only arrays
   kbe_c128 *epsall;                // [nt][E] eps of every accepted step
   kbe_c128 *ubuf;                  // [KM][E] test-integrand values
   kbe_c128 *Cl, *Cg;               // [QM][E] history sums above the diagonal
+  kbe_c128 *upart;                 // [chunks][QM][2][E] their partial sums by term chunk
   double *part;                    // [NPART] norm partial sums
   double *res;                     // [8] norm results
   int32_t *kbuf;                   // [QM + 2] history order of every evaluation of a step
@@ -964,63 +965,121 @@ __global__ void ad_keep(PA a, AA b, int n) {
 // C^>), for j = j0..n-1: I^R with upper limit t_j (weights row j), I^< with upper limit t_n
 // (weights row n), Sigma(t_j, t_s) for s > j read from row s through the symmetry
 // Sigma(t_j,t_s) = -Sigma(t_s,t_j)^dagger (Sigma^> = Sigma^R + Sigma^< in the stored rows).
-__global__ void ad_upper(PA a, AA b, int n, int j0) {
+// Upper history sums of step n at rows j0 <= j < n, in two stages.  Stage one: block (c, j - j0)
+// takes terms u in [c UCH, (c + 1) UCH) of row j's three sums, numbered
+//   u <  j + 1                      : w_j[s] Sigma^R(t_j,t_s) G^{<,>}(t_s,t_n), s = u;
+//   u <  j + n + 2                  : w_n[s] Sigma^{<,>}(t_j,t_s) G^A(t_s,t_n), s = u - j - 1;
+//   u <  j + n + 2 + ntau           : -i wtau[l] Sigma^](t_j,tau_l) G^[(tau_l,t_n), l = u - j - n - 2;
+// each thread one element of the block for every lanes-th term, the lanes summed in LDS in a
+// fixed order, and writes its chunk's partial sums of C^< (ret + les + mixed) and C^> (the same
+// with G^>, Sigma^>).  Stage two sums the chunks in order.  The result does not depend on the
+// launch beyond the rounding of the fixed summation order.
+constexpr int UCH = 64;
+
+__host__ __device__ __forceinline__ int upper_terms(int j, int n, int ntau) { return j + n + 2 + ntau; }
+
+__global__ void __launch_bounds__(256) ad_upper_part(PA a, AA b, int n, int j0) {
   const int64_t E = E_(a);
   const int N = a.N;
+  const int jj = blockIdx.y, j = j0 + jj, chunk = blockIdx.x, tid = threadIdx.x;
+  const int lanes = E <= 256 ? 256 / (int)E : 1;
+  const int lane = E <= 256 ? tid / (int)E : 0;
+  const int u0 = chunk * UCH, uend = min(u0 + UCH, upper_terms(j, n, a.ntau));
+  const double *wj = b.w + (int64_t)j * a.nt, *wn = b.w + (int64_t)n * a.nt;
+  __shared__ cd red[2][256];
+  for (int64_t q0 = 0; q0 < E; q0 += 256) {
+    const int64_t q = E <= 256 ? tid % E : q0 + tid;
+    const bool act = lane < lanes && q < E;
+    cd cl = czero(), cg = czero();
+    if (act) {
+      const int r = (int)(q / N), c = (int)(q % N);
+      for (int u = u0 + lane; u < uend; u += lanes) {
+        if (u <= j) {
+          const int s = u;
+          const kbe_c128 *SR = b.Sret + ((int64_t)j * a.nt + s) * E;
+          const kbe_c128 *GL = a.kp + ((int64_t)s * a.ldt + n) * E;    // G^<(s,n)
+          const kbe_c128 *GRns = a.kp + ((int64_t)n * a.ldt + s) * E;  // G^R(n,s), s < n
+          cd x = czero(), y = czero();
+          for (int k = 0; k < N; ++k) {
+            const cd sr = ld(SR + r * N + k);
+            const cd gl = ld(GL + k * N + c);
+            const cd gg = gl - cj(ld(GRns + c * N + k));  // G^>(s,n) = kp[s][n] - kp[n][s]^dagger
+            x = x + sr * gl;
+            y = y + sr * gg;
+          }
+          cl = cl + wj[s] * x;
+          cg = cg + wj[s] * y;
+        } else if (u <= j + n + 1) {
+          const int s = u - j - 1;
+          const kbe_c128 *GA = s < n ? a.kp + ((int64_t)n * a.ldt + s) * E : a.rdiag + n * E;
+          cd x = czero(), y = czero();
+          for (int k = 0; k < N; ++k) {
+            cd sl, sg;
+            if (s <= j) {
+              sl = ld(b.Sles + ((int64_t)j * a.nt + s) * E + r * N + k);
+              sg = sl + ld(b.Sret + ((int64_t)j * a.nt + s) * E + r * N + k);
+            } else {
+              const cd l = ld(b.Sles + ((int64_t)s * a.nt + j) * E + k * N + r);
+              const cd g = l + ld(b.Sret + ((int64_t)s * a.nt + j) * E + k * N + r);
+              sl = -cj(l);
+              sg = -cj(g);
+            }
+            const cd ga = cj(ld(GA + c * N + k));  // G^A(s,n)[k][c] = conj(G^R(n,s)[c][k])
+            x = x + sl * ga;
+            y = y + sg * ga;
+          }
+          cl = cl + wn[s] * x;
+          cg = cg + wn[s] * y;
+        } else {
+          const int l = u - j - n - 2, J = a.ntau - 1;
+          const kbe_c128 *S = b.Stv + ((int64_t)j * a.ntau + l) * E;
+          const kbe_c128 *T = a.tv + ((int64_t)n * a.ntau + (J - l)) * E;
+          cd x = czero();
+          for (int k = 0; k < N; ++k) x = x + ld(S + r * N + k) * cj(ld(T + c * N + k));
+          x = mul_mi(a.wtau_[l] * x);
+          cl = cl + x;
+          cg = cg + x;
+        }
+      }
+    }
+    kbe_c128 *out = b.upart + (((int64_t)chunk * QM + jj) * 2) * E;
+    if (lanes == 1) {
+      if (act) {
+        st(out + q, cl);
+        st(out + E + q, cg);
+      }
+      continue;
+    }
+    red[0][tid] = cl;
+    red[1][tid] = cg;
+    __syncthreads();
+    if (tid < E) {
+      cd sl = red[0][tid], sg = red[1][tid];
+      for (int i = 1; i < lanes; ++i) {
+        sl = sl + red[0][i * E + tid];
+        sg = sg + red[1][i * E + tid];
+      }
+      st(out + tid, sl);
+      st(out + E + tid, sg);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void ad_upper_sum(PA a, AA b, int n, int j0, int nchunk) {
+  const int64_t E = E_(a);
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= (int64_t)(n - j0) * E) return;
-  const int j = j0 + (int)(gid / E), q = (int)(gid % E), r = q / N, c = q % N;
-  const double *wj = b.w + (int64_t)j * a.nt, *wn = b.w + (int64_t)n * a.nt;
-  cd irl = czero(), irg = czero(), ill = czero(), ilg = czero(), itv = czero();
-  for (int s = 0; s <= j; ++s) {  // Sigma^R(t_j,t_s) G^<(t_s,t_n), G^>(t_s,t_n)
-    const kbe_c128 *SR = b.Sret + ((int64_t)j * a.nt + s) * E;
-    const kbe_c128 *GL = a.kp + ((int64_t)s * a.ldt + n) * E;        // G^<(s,n)
-    const kbe_c128 *GRns = a.kp + ((int64_t)n * a.ldt + s) * E;      // G^R(n,s), s < n
-    cd x = czero(), y = czero();
-    for (int k = 0; k < N; ++k) {
-      const cd sr = ld(SR + r * N + k);
-      const cd gl = ld(GL + k * N + c);
-      const cd gg = gl - cj(ld(GRns + c * N + k));  // G^>(s,n) = kp[s][n] - kp[n][s]^dagger
-      x = x + sr * gl;
-      y = y + sr * gg;
-    }
-    irl = irl + wj[s] * x;
-    irg = irg + wj[s] * y;
+  const int jj = (int)(gid / E), q = (int)(gid % E);
+  const int nc = (upper_terms(j0 + jj, n, a.ntau) + UCH - 1) / UCH;  // chunks of row j (<= nchunk)
+  cd cl = czero(), cg = czero();
+  for (int c = 0; c < nc && c < nchunk; ++c) {
+    const kbe_c128 *in = b.upart + (((int64_t)c * QM + jj) * 2) * E;
+    cl = cl + ld(in + q);
+    cg = cg + ld(in + E + q);
   }
-  for (int s = 0; s <= n; ++s) {  // Sigma^<(t_j,t_s), Sigma^>(t_j,t_s) times G^A(t_s,t_n)
-    const kbe_c128 *GA = s < n ? a.kp + ((int64_t)n * a.ldt + s) * E : a.rdiag + n * E;
-    cd x = czero(), y = czero();
-    for (int k = 0; k < N; ++k) {
-      cd sl, sg;
-      if (s <= j) {
-        sl = ld(b.Sles + ((int64_t)j * a.nt + s) * E + r * N + k);
-        sg = sl + ld(b.Sret + ((int64_t)j * a.nt + s) * E + r * N + k);
-      } else {
-        const cd l = ld(b.Sles + ((int64_t)s * a.nt + j) * E + k * N + r);
-        const cd g = l + ld(b.Sret + ((int64_t)s * a.nt + j) * E + k * N + r);
-        sl = -cj(l);
-        sg = -cj(g);
-      }
-      const cd ga = cj(ld(GA + c * N + k));  // G^A(s,n)[k][c] = conj(G^R(n,s)[c][k])
-      x = x + sl * ga;
-      y = y + sg * ga;
-    }
-    ill = ill + wn[s] * x;
-    ilg = ilg + wn[s] * y;
-  }
-  if (a.ntau > 0) {
-    const int J = a.ntau - 1;
-    for (int l = 0; l < a.ntau; ++l) {
-      const kbe_c128 *S = b.Stv + ((int64_t)j * a.ntau + l) * E;
-      const kbe_c128 *T = a.tv + ((int64_t)n * a.ntau + (J - l)) * E;
-      cd x = czero();
-      for (int k = 0; k < N; ++k) x = x + ld(S + r * N + k) * cj(ld(T + c * N + k));
-      itv = itv + a.wtau_[l] * x;
-    }
-    itv = mul_mi(itv);
-  }
-  st(b.Cl + (int64_t)(j - j0) * E + q, irl + ill + itv);
-  st(b.Cg + (int64_t)(j - j0) * E + q, irg + ilg + itv);
+  st(b.Cl + (int64_t)jj * E + q, cl);
+  st(b.Cg + (int64_t)jj * E + q, cg);
 }
 
 // Right sides of the blocks born at t_n below their birth: U_n at t_j, i (G^<(t_n,t_j) eps_j -
@@ -1115,10 +1174,13 @@ double factorial(int q) {
   return f;
 }
 
+// Term chunks of the upper history sums at the last step of a grid of nt points.
+int upper_chunks(int nt, int ntau) { return (2 * nt + ntau + UCH - 1) / UCH; }
+
 struct ALay {
   size_t fkp, fbu, fbr, ftv, fpu, fpr, t, w, eps, sret, sles, stv, Sret, Sles, Stv, epsall, IRl,
-      ILl, Itv, Jtv, IRg, ILg, base, ynext, ypred, ubuf, Cl, Cg, amt, abt, part, res, kbuf, cws,
-      total;
+      ILl, Itv, Jtv, IRg, ILg, base, ynext, ypred, ubuf, Cl, Cg, upart, amt, abt, part, res, kbuf,
+      cws, total;
 };
 
 ALay alayout(int N, int nt, int ntau) {
@@ -1155,6 +1217,7 @@ ALay alayout(int N, int nt, int ntau) {
   L.ubuf = take((size_t)KM * E);
   L.Cl = take((size_t)QM * E);
   L.Cg = take((size_t)QM * E);
+  L.upart = take((size_t)upper_chunks(nt, ntau) * QM * 2 * E);
   L.amt = take(KM * KM * sizeof(double));
   L.abt = take(KM * KM * sizeof(double));
   L.part = take(NPART * sizeof(double));
@@ -1174,7 +1237,9 @@ size_t prop_adaptive_ws_bytes(int N, int nt, int ntau) { return alayout(N, nt, n
 
 hipError_t launch_propagate_adaptive(const kbe_prop *P, const kbe_adapt_ctl *ctl,
                                      const kbe_wts *W, const kbe_green *G, double *dens,
-                                     kbe_adapt_trace *tr, void *ws, hipStream_t st) {
+                                     kbe_adapt_trace *tr, void *ws, hipStream_t st,
+                                     int *stalled) {
+  *stalled = 0;
   const ALay L = alayout(G->N, G->nt, G->ntau);
   char *wsb = (char *)ws;
   auto c = [&](size_t off) { return (kbe_c128 *)(wsb + off); };
@@ -1230,6 +1295,7 @@ hipError_t launch_propagate_adaptive(const kbe_prop *P, const kbe_adapt_ctl *ctl
   b.ubuf = c(L.ubuf);
   b.Cl = c(L.Cl);
   b.Cg = c(L.Cg);
+  b.upart = c(L.upart);
   b.part = (double *)(wsb + L.part);
   b.res = (double *)(wsb + L.res);
   b.kbuf = (int32_t *)(wsb + L.kbuf);
@@ -1325,7 +1391,8 @@ hipError_t launch_propagate_adaptive(const kbe_prop *P, const kbe_adapt_ctl *ctl
       h = h < ctl->t_end - t.back() ? h : ctl->t_end - t.back();
       if (!(h > 1e-13 * (t.back() > 1.0 ? t.back() : 1.0))) {  // step size underflow
         tr->nt = n;
-        return hipErrorInvalidValue;
+        *stalled = 1;
+        return hipGetLastError();
       }
       q = q < n ? q : n;
       tn = t.back() + h;
@@ -1392,8 +1459,10 @@ hipError_t launch_propagate_adaptive(const kbe_prop *P, const kbe_adapt_ctl *ctl
                        b, n);
     hipLaunchKernelGGL(prop_dens, dim3(1), dim3(64), 0, st, a, n, dens);
     const int j0 = n - ctl->qmax > 0 ? n - ctl->qmax : 0;
-    hipLaunchKernelGGL(ad_upper, dim3(blocks((int64_t)(n - j0) * E)), dim3(256), 0, st, a, b, n,
-                       j0);
+    const int nch = (upper_terms(n - 1, n, ntau) + UCH - 1) / UCH;
+    hipLaunchKernelGGL(ad_upper_part, dim3(nch, n - j0), dim3(256), 0, st, a, b, n, j0);
+    hipLaunchKernelGGL(ad_upper_sum, dim3(blocks((int64_t)(n - j0) * E)), dim3(256), 0, st, a, b,
+                       n, j0, nch);
     hipLaunchKernelGGL(ad_recon, dim3(blocks((int64_t)(n - j0) * E)), dim3(256), 0, st, a, b, n,
                        j0);
     ks.assign(m + 1, 0);
@@ -1435,6 +1504,7 @@ hipError_t launch_propagate_adaptive(const kbe_prop *P, const kbe_adapt_ctl *ctl
     ++n;
   }
   tr->nt = n;
+  if (t.back() < ctl->t_end * (1.0 - 1e-14)) *stalled = 2;  // capacity exhausted
   return hipGetLastError();
 }
 
