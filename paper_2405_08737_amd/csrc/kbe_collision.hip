@@ -59,13 +59,16 @@ enum Cls {
   B_GRL,   // s > m:  w[n][s] gIR(m) kp[s][m]^dagger
   B_GRD,   // s = m:  w[n][s] gIR(s) rdiag[s]^dagger
   B_GRU,   // s < m: -w[n][s] gIR(m) kp[m][s]
+  // both forms in one call (the propagations): I^< of the greater form reads the Sigma^> row
+  // through its own class, beside C_IL on the Sigma^< row
+  C_ILX,   // I^<, s <= m:  w[m][s] Sigma^>(s) G^R(m,s)^dagger
   NCLS
 };
 enum Op { OP_N = 0, OP_H = 1, OP_HN = 2 };
 
 template <int CLS>
 __host__ __device__ constexpr int cls_op() {
-  return (CLS == C_IRR || CLS == C_IL || CLS == C_ITV || CLS == B_R1 || CLS == B_R3 ||
+  return (CLS == C_IRR || CLS == C_IL || CLS == C_ILX || CLS == C_ITV || CLS == B_R1 || CLS == B_R3 ||
           CLS == B_T2A || CLS == B_T2B || CLS == C_GRU || CLS == B_GRL ||
           CLS == B_GRD)
              ? OP_H
@@ -81,7 +84,7 @@ __host__ __device__ __forceinline__ void cls_range(const Params &p, int o, int &
   switch (CLS) {
     case C_IRC: lo = 0; hi = m + 1; break;
     case C_IRR: lo = m + 1; hi = p.n + 1; break;
-    case C_IL: lo = 0; hi = m + 1; break;
+    case C_IL: case C_ILX: lo = 0; hi = m + 1; break;
     case C_GRL: lo = m + 1; hi = p.n + 1; break;
     case C_GRD: lo = m; hi = m + 1; break;
     case C_GRU: lo = 0; hi = m; break;
@@ -115,6 +118,7 @@ __host__ __device__ __forceinline__ const kbe_c128 *cls_Q(const Params &p, int t
     case C_IRC: case C_IRR: case C_JR: case C_GRL: case C_GRD: case C_GRU:
       return p.ret + t * E;
     case C_IL: return p.les + t * E;
+    case C_ILX: return p.sgt + t * E;
     case C_ITV: case C_JM1: case C_JM2: case G_MAT1: case G_MAT2: return p.stv + t * E;
     case B_R1: case B_R2: case B_GRL: case B_GRD: case B_GRU: return p.gIR + (t - p.m0) * E;
     case B_L: return p.gIL + (t - p.m0) * E;
@@ -148,7 +152,7 @@ __host__ __device__ __forceinline__ void cls_wpP(const Params &p, int o, int t, 
   switch (CLS) {
     case C_IRC: w = p.w + ((int64_t)p.n * p.nt + t); P = kp_blk(p, t, m); break;
     case C_IRR: w = p.w + ((int64_t)p.n * p.nt + t); P = kp_blk(p, m, t); break;
-    case C_IL:
+    case C_IL: case C_ILX:
       w = p.w + ((int64_t)m * p.nt + t);
       P = t < m ? kp_blk(p, m, t) : p.rdiag + m * E;
       break;
@@ -223,7 +227,7 @@ __device__ __forceinline__ void range_rt(int cls, const Params &p, int o, int &l
     KBE_CASE(C_JM2) KBE_CASE(B_R1) KBE_CASE(B_R2) KBE_CASE(B_R3) KBE_CASE(B_L) KBE_CASE(B_T1)
     KBE_CASE(B_T2A) KBE_CASE(B_T2B) KBE_CASE(G_MAT1) KBE_CASE(G_MAT2) KBE_CASE(C_GRL)
     KBE_CASE(C_GRD) KBE_CASE(C_GRU) KBE_CASE(B_GRL) KBE_CASE(B_GRD)
-    KBE_CASE(B_GRU)
+    KBE_CASE(B_GRU) KBE_CASE(C_ILX)
 #undef KBE_CASE
     default: lo = hi = 0;
   }
@@ -780,7 +784,7 @@ __global__ void __launch_bounds__(256) stream_fused(Params p, FusedPlan pl, char
           KBE_CASE(C_IRC) KBE_CASE(C_IRR) KBE_CASE(C_IL) KBE_CASE(C_ITV) KBE_CASE(C_JR)
           KBE_CASE(C_JM1) KBE_CASE(C_JM2)
         }
-        switch (pl.cls[k]) { KBE_CASE(C_GRL) KBE_CASE(C_GRD) KBE_CASE(C_GRU) }
+        switch (pl.cls[k]) { KBE_CASE(C_GRL) KBE_CASE(C_GRD) KBE_CASE(C_GRU) KBE_CASE(C_ILX) }
       } else {
         switch (pl.cls[k]) {
           KBE_CASE(B_R1) KBE_CASE(B_R2) KBE_CASE(B_R3) KBE_CASE(B_L) KBE_CASE(B_T1)
@@ -816,8 +820,9 @@ struct RedJob {
   kbe_c128 *out;
   int64_t start;  // first grid element of this job
 };
+constexpr int RED_JOBS = 6;  // output arrays per call, at most
 struct RedAll {
-  RedJob j[4];
+  RedJob j[RED_JOBS];
   int njob, SC;
   int64_t total;
 };
@@ -1426,7 +1431,8 @@ static size_t plan_forward(int N, int ntau, int n, int m0, int m1, unsigned flag
   const int E = N * N, M = m1 - m0;
   size_t off = 0;
   const bool th = ntau > 0;
-  const bool gr = flags & KBE_GREATER;
+  const bool both = flags & KBE_INT_BOTH;
+  const bool gr = (flags & KBE_GREATER) || both;
   if (flags & KBE_OUT_IR) {
     plan_add(pl, C_IRC, M, m1, E, off);
     if (n > m0) plan_add(pl, C_IRR, M, n + 1, E, off);
@@ -1437,6 +1443,7 @@ static size_t plan_forward(int N, int ntau, int n, int m0, int m1, unsigned flag
     }
   }
   if (flags & KBE_OUT_IL) plan_add(pl, C_IL, M, m1, E, off);  // greater form: Q = Sigma^> row
+  if (both && (flags & KBE_OUT_IL)) plan_add(pl, C_ILX, M, m1, E, off);
   if ((flags & KBE_OUT_ITV) && th) plan_add(pl, C_ITV, M, ntau, E, off);
   if ((flags & KBE_OUT_JTV) && th) {
     plan_add(pl, C_JR, ntau, n + 1, E, off);
@@ -1544,7 +1551,7 @@ static void launch_kind(int kind, const Params &p, const FusedPlan &pl, char *ws
 static void reduce_into(const Params &p, const FusedPlan &pl, std::initializer_list<int> classes,
                         char *ws, int nout, kbe_c128 *out, bool accumulate, RedAll &r) {
   const int64_t nel = (int64_t)nout * p.N * p.N;
-  if (nel == 0 || r.njob >= 4) return;
+  if (nel == 0 || r.njob >= RED_JOBS) return;
   RedJob &in = r.j[r.njob++];
   in = RedJob{};
   for (int c : classes)
@@ -1592,6 +1599,38 @@ hipError_t launch_collision(const Params &p, unsigned flags, kbe_c128 *IR, kbe_c
   if (flags & KBE_OUT_IL) reduce_into(p, pl, {C_IL}, w, M, IL, false, r);
   if (flags & KBE_OUT_ITV) reduce_into(p, pl, {C_ITV}, w, M, Itv, false, r);
   if ((flags & KBE_OUT_JTV) && p.ntau > 0) reduce_into(p, pl, {C_JR, C_JM1, C_JM2}, w, p.ntau, Jtv, false, r);
+  reduce_launch(p, r, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_collision_both(const Params &p, kbe_c128 *IRl, kbe_c128 *ILl, kbe_c128 *Itv,
+                                 kbe_c128 *Jtv, kbe_c128 *IRg, kbe_c128 *ILg, void *ws,
+                                 hipStream_t st) {
+  const unsigned flags = KBE_OUT_ALL | KBE_INT_BOTH;
+  const int kind = path_kind(p.N, flags);
+  FusedPlan pl;
+  plan_forward(p.N, p.ntau, p.n, p.m0, p.m1, flags, kind, pl);
+  char *w = (char *)ws;
+  Params pg = p;
+  if (pl.sgoff >= 0) {  // C_ILX reads Sigma^> = Sigma^R + Sigma^<, formed once
+    kbe_c128 *sg = (kbe_c128 *)(w + pl.sgoff);
+    const int64_t cnt = (int64_t)p.m1 * p.N * p.N;
+    hipLaunchKernelGGL(add_rows, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, p.ret,
+                       p.les, sg, cnt);
+    pg.sgt = sg;
+  }
+  launch_kind<false>(kind, pg, pl, w, st);
+  const int M = p.m1 - p.m0;
+  RedAll r{};
+  r.SC = pl.SC;
+  reduce_into(p, pl, {C_IRC, C_IRR}, w, M, IRl, false, r);
+  reduce_into(p, pl, {C_IRC, C_IRR, C_GRL, C_GRD, C_GRU}, w, M, IRg, false, r);
+  reduce_into(p, pl, {C_IL}, w, M, ILl, false, r);
+  reduce_into(p, pl, {C_ILX}, w, M, ILg, false, r);
+  if (p.ntau > 0) {
+    reduce_into(p, pl, {C_ITV}, w, M, Itv, false, r);
+    reduce_into(p, pl, {C_JR, C_JM1, C_JM2}, w, p.ntau, Jtv, false, r);
+  }
   reduce_launch(p, r, st);
   return hipGetLastError();
 }
@@ -1747,27 +1786,30 @@ extern "C" int64_t kbe_internal_audit_tasks(int32_t N, int32_t nt, int32_t ntau,
     return a;
   };
   // the greater form's I^< reads a Sigma^> row of m1 blocks from the workspace
-  const bool sg = !adjoint && pl.sgoff >= 0;
+  const bool both = !adjoint && (flags & KBE_INT_BOTH);
+  const bool sg = !adjoint && pl.sgoff >= 0 && !both;
   AuditArr kp = arr((int64_t)nt * ldt * E, cs), rdiag = arr((int64_t)nt * E, cs),
            tv = arr((int64_t)nt * ntau * E, cs), mat = arr((int64_t)ntau * E, cs),
            ret = arr((int64_t)(n + 1) * E, cs), les = arr((int64_t)(sg ? m1 : n + 1) * E, cs),
            stv = arr((int64_t)ntau * E, cs), w = arr((int64_t)nt * nt, ds),
            wtau = arr(ntau, ds), wf = arr((int64_t)ntau * ntau, ds),
            gIR = arr((int64_t)M * E, cs), gIL = arr((int64_t)M * E, cs),
-           gItv = arr((int64_t)M * E, cs), gJ = arr((int64_t)ntau * E, cs);
+           gItv = arr((int64_t)M * E, cs), gJ = arr((int64_t)ntau * E, cs),
+           sgt = arr((int64_t)m1 * E, cs);
   // element-granular checks: kp and tv blocks are whole blocks, so count blocks as elements of
   // E complex numbers where a block start is what is formed
   AuditArr kpb{kp.base, (int64_t)nt * ldt, E * cs}, rdb{rdiag.base, nt, E * cs},
       tvb{tv.base, (int64_t)nt * ntau, E * cs}, matb{mat.base, ntau, E * cs},
       retb{ret.base, n + 1, E * cs}, lesb{les.base, sg ? m1 : n + 1, E * cs},
       stvb{stv.base, ntau, E * cs}, gIRb{gIR.base, M, E * cs}, gILb{gIL.base, M, E * cs},
-      gItvb{gItv.base, M, E * cs}, gJb{gJ.base, ntau, E * cs};
+      gItvb{gItv.base, M, E * cs}, gJb{gJ.base, ntau, E * cs}, sgtb{sgt.base, m1, E * cs};
   Params p{};
   p.N = N; p.nt = nt; p.ntau = ntau; p.J = ntau - 1; p.n = n; p.m0 = m0; p.m1 = m1; p.ldt = ldt;
   p.kp = (const kbe_c128 *)kp.base; p.rdiag = (const kbe_c128 *)rdiag.base;
   p.tv = (const kbe_c128 *)tv.base; p.mat = (const kbe_c128 *)mat.base;
   p.ret = (const kbe_c128 *)ret.base; p.les = (const kbe_c128 *)les.base;
   p.stv = (const kbe_c128 *)stv.base;
+  p.sgt = both ? (const kbe_c128 *)sgt.base : nullptr;
   p.w = (const double *)w.base; p.wtau = (const double *)wtau.base; p.wf = (const double *)wf.base;
   p.gIR = (const kbe_c128 *)gIR.base; p.gIL = (const kbe_c128 *)gIL.base;
   p.gItv = (const kbe_c128 *)gItv.base; p.gJ = (const kbe_c128 *)gJ.base;
@@ -1779,6 +1821,7 @@ extern "C" int64_t kbe_internal_audit_tasks(int32_t N, int32_t nt, int32_t ntau,
     switch (pl.cls[k]) {
       case C_IRC: case C_IRR: case C_JR: case C_GRL: case C_GRD: case C_GRU: q = &retb; break;
       case C_IL: q = &lesb; break;
+      case C_ILX: q = &sgtb; break;
       case C_ITV: case C_JM1: case C_JM2: case G_MAT1: case G_MAT2: q = &stvb; break;
       case B_R1: case B_R2: case B_GRL: case B_GRD: case B_GRU: q = &gIRb; break;
       case B_L: q = &gILb; break;
@@ -1792,7 +1835,7 @@ extern "C" int64_t kbe_internal_audit_tasks(int32_t N, int32_t nt, int32_t ntau,
       KBE_CASE(C_JM1) KBE_CASE(C_JM2) KBE_CASE(B_R1) KBE_CASE(B_R2) KBE_CASE(B_R3) KBE_CASE(B_L)
       KBE_CASE(B_T1) KBE_CASE(B_T2A) KBE_CASE(B_T2B) KBE_CASE(G_MAT1) KBE_CASE(G_MAT2)
       KBE_CASE(C_GRL) KBE_CASE(C_GRD) KBE_CASE(C_GRU) KBE_CASE(B_GRL) KBE_CASE(B_GRD)
-      KBE_CASE(B_GRU)
+      KBE_CASE(B_GRU) KBE_CASE(C_ILX)
 #undef KBE_CASE
       default: ++bad;
     }

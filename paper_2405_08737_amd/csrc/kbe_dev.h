@@ -59,6 +59,7 @@ struct Params {
   int64_t ldt;
   const kbe_c128 *kp, *rdiag, *tv, *mat;       // Green's function
   const kbe_c128 *ret, *les, *stv;             // self-energy row at t_n
+  const kbe_c128 *sgt;                         // Sigma^> row (both forms in one call)
   const double *w, *wtau, *wf;                 // weights
   const kbe_c128 *gIR, *gIL, *gItv, *gJ;       // cotangents (adjoint only)
   kbe_c128 *gkp, *grdiag, *gtv;                // gradient outputs (adjoint only)

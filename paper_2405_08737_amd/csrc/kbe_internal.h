@@ -20,7 +20,7 @@ hipError_t launch_grid_check(const double *t, const int32_t *order, int nt, int3
                              hipStream_t st);
 hipError_t launch_step_weights(const double *t, const int32_t *order, int nt, double *lam,
                                hipStream_t st);
-hipError_t launch_interval_weights(const double *t, int n, int kam, int kab, double *am,
+hipError_t launch_interval_weights(double *t, int n, double tn, int kam, int kab, double *am,
                                    double *ab, hipStream_t st);
 
 // Self-energy and its adjoint (kbe_sigma.hip).
@@ -42,6 +42,13 @@ hipError_t launch_sigma_gf2(const kbe_green *G, const double *U, int n, const kb
 size_t collision_ws_bytes(int N, int nt, int ntau, int n, int m0, int m1, unsigned flags);
 hipError_t launch_collision(const Params &p, unsigned flags, kbe_c128 *IR, kbe_c128 *IL,
                             kbe_c128 *Itv, kbe_c128 *Jtv, void *ws, hipStream_t st);
+// Both forms of Eq. KBE2 in one call (the propagations): the lesser form's four outputs and the
+// greater form's I^R, I^<, sharing the lesser form's I^R terms.  Internal flag (not part of the
+// C ABI, whose flag check rejects it) for the workspace query and the task audit.
+constexpr unsigned KBE_INT_BOTH = 0x10000u;
+hipError_t launch_collision_both(const Params &p, kbe_c128 *IRl, kbe_c128 *ILl, kbe_c128 *Itv,
+                                 kbe_c128 *Jtv, kbe_c128 *IRg, kbe_c128 *ILg, void *ws,
+                                 hipStream_t st);
 size_t collision_vjp_ws_bytes(int N, int nt, int ntau, int n, int m0, int m1, unsigned flags);
 hipError_t launch_collision_vjp(const Params &p, unsigned flags, kbe_c128 *gmat,
                                 const kbe_sigma_row *gS, void *ws, hipStream_t st);

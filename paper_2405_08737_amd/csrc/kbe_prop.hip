@@ -30,7 +30,9 @@
 // stored iterates and calling the collision and self-energy adjoints (kbe_collision_vjp,
 // kbe_sigma_2b_vjp), so that d(loss)/du and d(loss)/dA of a loss on the densities
 // n_i(t_n) = Re(-i G^<_ii(t_n,t_n)) are exact derivatives of the discrete map above.
+#include <atomic>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "kbe_dev.h"
@@ -72,6 +74,10 @@ struct PA {                       // everything the small kernels read, passed b
 };
 
 constexpr int QM = 12;  // the largest Adams order of the adaptive propagation
+constexpr int KSW = QM + 2;  // history orders recorded per step (at most maxcor + 1 evaluations)
+// the collision outputs of the lesser form, and the greater form's I^R, I^< (Eq. KBE2)
+constexpr unsigned FL = KBE_OUT_ALL;
+constexpr unsigned FG = KBE_OUT_IR | KBE_OUT_IL | KBE_GREATER;
 
 __device__ __forceinline__ int64_t E_(const PA &a) { return (int64_t)a.N * a.N; }
 __device__ __forceinline__ int nelem(const PA &a, int n) { return 2 * n + 1 + a.ntau; }
@@ -570,10 +576,7 @@ Layout layout(int N, int nt, int ntau, int64_t ldt, int K) {
   L.ILg = take(nt * E);
   L.base = take(ne * E);
   L.ynext = take(ne * E);
-  const unsigned gfl = KBE_OUT_IR | KBE_OUT_IL | KBE_GREATER;
-  size_t cw = collision_ws_bytes(N, nt, ntau, n, 0, n + 1, KBE_OUT_ALL);
-  const size_t cw2 = collision_ws_bytes(N, nt, ntau, n, 0, n + 1, gfl);
-  L.cws = take(cw > cw2 ? cw : cw2);
+  L.cws = take(collision_ws_bytes(N, nt, ntau, n, 0, n + 1, KBE_OUT_ALL | KBE_INT_BOTH));
   L.gkp = take((size_t)nt * ldt * E);
   L.grd = take(nt * E);
   L.gtv = take((size_t)nt * ntau * E);
@@ -597,7 +600,7 @@ Layout layout(int N, int nt, int ntau, int64_t ldt, int K) {
   L.glesG = take(nt * E);
   L.gstvG = take(ntau * E);
   size_t vw = collision_vjp_ws_bytes(N, nt, ntau, n, 0, n + 1, KBE_OUT_ALL);
-  const size_t vw2 = collision_vjp_ws_bytes(N, nt, ntau, n, 0, n + 1, gfl);
+  const size_t vw2 = collision_vjp_ws_bytes(N, nt, ntau, n, 0, n + 1, FG);
   L.vws = take(vw > vw2 ? vw : vw2);
   L.sws = take(sigma_vjp_ws_bytes(N, n, ntau));
   L.total = o;
@@ -649,8 +652,6 @@ void set_flags(Params &p, unsigned flags, bool th) {
   p.overwrite = 0;
 }
 
-constexpr unsigned FL = KBE_OUT_ALL;
-constexpr unsigned FG = KBE_OUT_IR | KBE_OUT_IL | KBE_GREATER;
 
 // Self-energy row and both history sums of step n at the current values, then eps.
 hipError_t evaluate(Ctx &x, int n) {
@@ -659,10 +660,8 @@ hipError_t evaluate(Ctx &x, int n) {
   const bool th = x.a.ntau > 0;
   Params p = coll_params(x, n);
   set_flags(p, FL, th);
-  e = launch_collision(p, FL, x.a.IRl, x.a.ILl, x.a.Itv, x.a.Jtv, x.ws + x.L.cws, x.st);
-  if (e != hipSuccess) return e;
-  set_flags(p, FG, th);
-  e = launch_collision(p, FG, x.a.IRg, x.a.ILg, nullptr, nullptr, x.ws + x.L.cws, x.st);
+  e = launch_collision_both(p, x.a.IRl, x.a.ILl, x.a.Itv, x.a.Jtv, x.a.IRg, x.a.ILg,
+                            x.ws + x.L.cws, x.st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(prop_eps, dim3(1), dim3(256), 0, x.st, x.a, n);
   return hipGetLastError();
@@ -787,9 +786,11 @@ struct AA {                        // adaptive-only arrays
   kbe_c128 *ubuf;                  // [KM][E] test-integrand values
   kbe_c128 *Cl, *Cg;               // [QM][E] history sums above the diagonal
   kbe_c128 *upart;                 // [chunks][QM][2][E] their partial sums by term chunk
-  double *part;                    // [NPART] norm partial sums
-  double *res;                     // [8] norm results
-  int32_t *kbuf;                   // [QM + 2] history order of every evaluation of a step
+  double *part;                    // [2][NPART] norm partial sums
+  uint32_t *done;                  // workgroups of a norm launch that have stored their partials
+  double *res;                     // [2] norm results, in page-locked host memory
+  volatile uint32_t *flag;         // sequence number of the last norm launch (host memory)
+  int32_t *kbuf;                   // [nt][QM + 2] history order of every evaluation of each step
   double rtol, atol;
 };
 
@@ -829,11 +830,10 @@ __global__ void ad_predict(PA a, AA b, int n) {
 // G^<(t_n,t_s) = -kp[s][n]^dagger), its integrals I^(k) over the interval with k = 1..K nodes,
 // k_opt = the first minimum of ||I^(k) - I^(k-1)||_F over k = 2..K, and row n of the history
 // weights: row n-1 plus the local weights on k_opt nodes.  One workgroup; fixed-order sums.
-__global__ void __launch_bounds__(256) ad_choose(PA a, AA b, int n, int K, int slot) {
+__global__ void __launch_bounds__(256) ad_choose(PA a, AA b, int n, int K, int64_t slot) {
   const int64_t E = E_(a);
   const int N = a.N;
   __shared__ double dk[KM + 1];
-  __shared__ double red[256];
   __shared__ int kopt;
   const int tid = threadIdx.x;
   for (int64_t x = tid; x < (int64_t)K * E; x += 256) {  // u at s = n-K+1+i
@@ -852,25 +852,23 @@ __global__ void __launch_bounds__(256) ad_choose(PA a, AA b, int n, int K, int s
     st(b.ubuf + x, acc);
   }
   __syncthreads();
-  for (int k = 2; k <= K; ++k) {  // ||I^(k) - I^(k-1)||_F^2, entries summed in a fixed tree
+  // ||I^(k) - I^(k-1)||_F for k = 2..K: wave w takes k = 2 + w, 6 + w, ...; each lane sums its
+  // entries q = lane, lane + 64, ... and the wave sums the lanes by a fixed butterfly
+  const int wave = tid / 64, lane = tid % 64;
+  for (int k = 2 + wave; k <= K; k += 4) {
     double part = 0.0;
-    for (int q = tid; q < E; q += 256) {
+    const double *Lk = a.amt + (int64_t)(k - 1) * KM, *Lk1 = a.amt + (int64_t)(k - 2) * KM;
+    for (int64_t q = lane; q < E; q += 64) {
       cd ik = czero(), ik1 = czero();
-      const double *Lk = a.amt + (int64_t)(k - 1) * KM, *Lk1 = a.amt + (int64_t)(k - 2) * KM;
       for (int i = 0; i < k; ++i) ik = ik + Lk[i] * ld(b.ubuf + (int64_t)(K - k + i) * E + q);
       for (int i = 0; i < k - 1; ++i) ik1 = ik1 + Lk1[i] * ld(b.ubuf + (int64_t)(K - k + 1 + i) * E + q);
       const cd d = ik - ik1;
       part += d.re * d.re + d.im * d.im;
     }
-    red[tid] = part;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-      if (tid < off) red[tid] += red[tid + off];
-      __syncthreads();
-    }
-    if (tid == 0) dk[k] = sqrt(red[0]);
-    __syncthreads();
+    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
+    if (lane == 0) dk[k] = sqrt(part);
   }
+  __syncthreads();
   if (tid == 0) {
     int best = 2;
     for (int k = 3; k <= K; ++k)
@@ -881,7 +879,7 @@ __global__ void __launch_bounds__(256) ad_choose(PA a, AA b, int n, int K, int s
   __syncthreads();
   const int k = kopt, lo = n - k + 1;
   const double *L = a.amt + (int64_t)(k - 1) * KM;
-  for (int sidx = tid; sidx < a.nt; sidx += 256) {
+  for (int sidx = tid; sidx <= n; sidx += 256) {  // entries beyond n stay zero
     double v = sidx < n ? b.w[(int64_t)(n - 1) * a.nt + sidx] : 0.0;
     if (sidx >= lo && sidx <= n) v += L[sidx - lo];
     b.w[(int64_t)n * a.nt + sidx] = v;
@@ -889,15 +887,41 @@ __global__ void __launch_bounds__(256) ad_choose(PA a, AA b, int n, int K, int s
 }
 
 // Weighted root-mean-square norms over the entries of step n's elements (Eq. wrms_norm), with the
-// weights of Eq. ewt from the values at t_{n-1}.  kind 0: ynext - current; 1: C (current -
-// predictor); 2: coef * f[t_{n-npts+1}..t_n] (a divided difference of every element's right
-// sides).  Partial sums per workgroup, then one ordered sum.
-__global__ void __launch_bounds__(256) ad_norm_part(PA a, AA b, int n, int kind, double C,
-                                                    int npts, double coef) {
+// weights of Eq. ewt from the values at t_{n-1}.  Up to two norms per launch (job j = 0, 1):
+// kind 0: ynext - current; 1: C (current - predictor); 2: coef * f[t_{n-npts+1}..t_n] (a divided
+// difference of every element's right sides); 3: C (ynext - predictor).  Each workgroup stores
+// its partial sums; the last one to finish (a counter) sums the partials in workgroup order,
+// writes the norms to b.res[j] and then the launch's sequence number to b.flag (page-locked host
+// memory, which the controller polls), and resets the counter for the next launch.
+struct NormJob {
+  int kind, npts;
+  double C, coef;
+};
+
+__device__ __forceinline__ cd norm_term(const PA &a, const AA &b, int n, int e, int q,
+                                        int kind_e, int idx, int64_t gid, const NormJob &j) {
+  if (j.kind == 0) return ld(a.ynext + gid) - ld(val_ptr(a, a.kp, a.tv, n, kind_e, idx) + q);
+  if (j.kind == 1) return j.C * (ld(val_ptr(a, a.kp, a.tv, n, kind_e, idx) + q) - ld(b.ypred + gid));
+  if (j.kind == 3) return j.C * (ld(a.ynext + gid) - ld(b.ypred + gid));
+  cd d[QM + 2];
+  double tt[QM + 2];
+  for (int i = 0; i < j.npts; ++i) {
+    const int jj = n - j.npts + 1 + i;
+    tt[i] = b.t[jj];
+    d[i] = ld(f_ptr(a, a.fkp, a.fbu, a.fbr, a.ftv, jj, kind_e, idx) + q);
+  }
+  for (int lev = 1; lev < j.npts; ++lev)
+    for (int i = 0; i + lev < j.npts; ++i) d[i] = (1.0 / (tt[i + lev] - tt[i])) * (d[i + 1] - d[i]);
+  return j.coef * d[0];
+}
+
+__global__ void __launch_bounds__(256) ad_norm(PA a, AA b, int n, int nj, NormJob j0, NormJob j1,
+                                               uint32_t seq) {
   const int64_t E = E_(a);
   const int64_t tot = (int64_t)nelem(a, n) * E;
-  __shared__ double red[256];
-  double acc = 0.0;
+  __shared__ double red[2][256];
+  __shared__ bool last;
+  double acc[2] = {0.0, 0.0};
   for (int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x; gid < tot;
        gid += (int64_t)gridDim.x * 256) {
     const int e = (int)(gid / E), q = (int)(gid % E);
@@ -907,41 +931,49 @@ __global__ void __launch_bounds__(256) ad_norm_part(PA a, AA b, int n, int kind,
     const int r = q / a.N, c = q % a.N;
     const cd prev = pp ? ld(pp + q) : cd{0.0, r == c ? -1.0 : 0.0};
     const double wt = 1.0 / (b.rtol * sqrt(prev.re * prev.re + prev.im * prev.im) + b.atol);
-    cd v;
-    if (kind == 0) {
-      v = ld(a.ynext + gid) - ld(val_ptr(a, a.kp, a.tv, n, kind_e, idx) + q);
-    } else if (kind == 1) {
-      v = C * (ld(val_ptr(a, a.kp, a.tv, n, kind_e, idx) + q) - ld(b.ypred + gid));
-    } else {
-      cd d[QM + 2];
-      double tt[QM + 2];
-      for (int i = 0; i < npts; ++i) {
-        const int j = n - npts + 1 + i;
-        tt[i] = b.t[j];
-        d[i] = ld(f_ptr(a, a.fkp, a.fbu, a.fbr, a.ftv, j, kind_e, idx) + q);
-      }
-      for (int lev = 1; lev < npts; ++lev)
-        for (int i = 0; i + lev < npts; ++i)
-          d[i] = (1.0 / (tt[i + lev] - tt[i])) * (d[i + 1] - d[i]);
-      v = coef * d[0];
+    for (int jj = 0; jj < nj; ++jj) {
+      const cd v = norm_term(a, b, n, e, q, kind_e, idx, gid, jj == 0 ? j0 : j1);
+      const double m = sqrt(v.re * v.re + v.im * v.im) * wt;
+      acc[jj] += m * m;
     }
-    const double m = sqrt(v.re * v.re + v.im * v.im) * wt;
-    acc += m * m;
   }
-  red[threadIdx.x] = acc;
+  const int tid = threadIdx.x;
+  red[0][tid] = acc[0];
+  red[1][tid] = acc[1];
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    if (tid < off) {
+      red[0][tid] += red[0][tid + off];
+      red[1][tid] += red[1][tid + off];
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) b.part[blockIdx.x] = red[0];
-}
-
-__global__ void ad_norm_final(AA b, int nparts, int64_t count, int slot) {
-  if (threadIdx.x != 0) return;
-  double s = 0.0;
-  for (int i = 0; i < nparts; ++i) s += b.part[i];
-  b.res[slot] = sqrt(s / (double)(count > 0 ? count : 1));
+  if (tid == 0) {
+    b.part[blockIdx.x] = red[0][0];
+    b.part[NPART + blockIdx.x] = red[1][0];
+    __threadfence();
+    last = atomicAdd(b.done, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  for (int jj = 0; jj < nj; ++jj) {
+    double sum = 0.0;
+    for (int i = tid; i < (int)gridDim.x; i += 256) sum += b.part[jj * NPART + i];
+    red[0][tid] = sum;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+      if (tid < off) red[0][tid] += red[0][tid + off];
+      __syncthreads();
+    }
+    if (tid == 0) b.res[jj] = sqrt(red[0][0] / (double)(tot > 0 ? tot : 1));
+    __syncthreads();
+  }
+  if (tid == 0) {
+    *b.done = 0u;
+    __threadfence_system();  // the norms reach host memory before the sequence number
+    *b.flag = seq;
+  }
 }
 
 // Keep the Sigma row and eps of the accepted step n (the history of later reconstructions).
@@ -1179,7 +1211,7 @@ int upper_chunks(int nt, int ntau) { return (2 * nt + ntau + UCH - 1) / UCH; }
 
 struct ALay {
   size_t fkp, fbu, fbr, ftv, fpu, fpr, t, w, eps, sret, sles, stv, Sret, Sles, Stv, epsall, IRl,
-      ILl, Itv, Jtv, IRg, ILg, base, ynext, ypred, ubuf, Cl, Cg, upart, amt, abt, part, res, kbuf,
+      ILl, Itv, Jtv, IRg, ILg, base, ynext, ypred, ubuf, Cl, Cg, upart, amt, abt, part, done, kbuf,
       cws, total;
 };
 
@@ -1220,13 +1252,11 @@ ALay alayout(int N, int nt, int ntau) {
   L.upart = take((size_t)upper_chunks(nt, ntau) * QM * 2 * E);
   L.amt = take(KM * KM * sizeof(double));
   L.abt = take(KM * KM * sizeof(double));
-  L.part = take(NPART * sizeof(double));
-  L.res = take(8 * sizeof(double));
-  L.kbuf = take((QM + 4) * sizeof(int32_t));
+  L.part = take(2 * NPART * sizeof(double));
+  L.done = take(sizeof(uint32_t));
+  L.kbuf = take((size_t)nt * KSW * sizeof(int32_t));
   const int n = nt - 1;
-  size_t cw = collision_ws_bytes(N, nt, ntau, n, 0, n + 1, KBE_OUT_ALL);
-  const size_t cw2 = collision_ws_bytes(N, nt, ntau, n, 0, n + 1, FG);
-  L.cws = take(cw > cw2 ? cw : cw2);
+  L.cws = take(collision_ws_bytes(N, nt, ntau, n, 0, n + 1, KBE_OUT_ALL | KBE_INT_BOTH));
   L.total = o;
   return L;
 }
@@ -1234,6 +1264,28 @@ ALay alayout(int N, int nt, int ntau) {
 }  // namespace
 
 size_t prop_adaptive_ws_bytes(int N, int nt, int ntau) { return alayout(N, nt, ntau).total; }
+
+// Page-locked, coherent host memory for the norms the controller reads, held for one call:
+// res[0..1] and, at byte 64, the sequence number of the last norm launch that wrote them.
+struct HostRes {
+  char *host = nullptr, *dev = nullptr;
+  hipError_t alloc() {
+    hipError_t e = hipHostMalloc((void **)&host, 4096,
+                                 hipHostMallocMapped | hipHostMallocPortable |
+                                     hipHostMallocCoherent);
+    if (e != hipSuccess) {
+      host = nullptr;
+      return e;
+    }
+    std::memset(host, 0, 4096);
+    return hipHostGetDevicePointer((void **)&dev, host, 0);
+  }
+  const volatile double *res() const { return (const volatile double *)host; }
+  const volatile uint32_t *flag() const { return (const volatile uint32_t *)(host + 64); }
+  ~HostRes() {
+    if (host) (void)hipHostFree(host);
+  }
+};
 
 hipError_t launch_propagate_adaptive(const kbe_prop *P, const kbe_adapt_ctl *ctl,
                                      const kbe_wts *W, const kbe_green *G, double *dens,
@@ -1297,8 +1349,16 @@ hipError_t launch_propagate_adaptive(const kbe_prop *P, const kbe_adapt_ctl *ctl
   b.Cg = c(L.Cg);
   b.upart = c(L.upart);
   b.part = (double *)(wsb + L.part);
-  b.res = (double *)(wsb + L.res);
+  b.done = (uint32_t *)(wsb + L.done);
   b.kbuf = (int32_t *)(wsb + L.kbuf);
+  // the norms the controller reads: written by the kernels into page-locked host memory, read
+  // after the stream is synchronised (no copy operations)
+  HostRes hres;
+  hipError_t e = hres.alloc();
+  if (e != hipSuccess) return e;
+  b.res = (double *)hres.dev;
+  b.flag = (volatile uint32_t *)(hres.dev + 64);
+  uint32_t seq = 0;
   b.rtol = ctl->rtol;
   b.atol = ctl->atol;
   const int N = a.N, nt = a.nt, ntau = a.ntau;
@@ -1306,7 +1366,6 @@ hipError_t launch_propagate_adaptive(const kbe_prop *P, const kbe_adapt_ctl *ctl
   kbe_green Gc = *G;
   kbe_sigma_row sig{b.sret, b.sles, ntau ? b.stv : nullptr};
   const bool th = ntau > 0;
-  hipError_t e;
   // history weights: the collision reads rows 0..n of w (row stride nt)
   kbe_wts Wc{wdev, W->wtau, W->wtau_fwd};
   auto coll = [&](int n) -> hipError_t {
@@ -1330,45 +1389,70 @@ hipError_t launch_propagate_adaptive(const kbe_prop *P, const kbe_adapt_ctl *ctl
     p.wtau = Wc.wtau;
     p.wf = Wc.wtau_fwd;
     set_flags(p, FL, th);
-    hipError_t r = launch_collision(p, FL, a.IRl, a.ILl, a.Itv, a.Jtv, wsb + L.cws, st);
-    if (r != hipSuccess) return r;
-    set_flags(p, FG, th);
-    return launch_collision(p, FG, a.IRg, a.ILg, nullptr, nullptr, wsb + L.cws, st);
+    return launch_collision_both(p, a.IRl, a.ILl, a.Itv, a.Jtv, a.IRg, a.ILg, wsb + L.cws, st);
   };
-  // one evaluation of the right sides at the current values of step n; kslot: where the history
-  // order is recorded (n >= 1)
+  // one evaluation of the right sides at the current values of step n; kslot: which evaluation
+  // of the step it is (where its history order is recorded, n >= 1)
   auto evaluate = [&](int n, int kslot) -> hipError_t {
     hipError_t r = launch_sigma_row(&Gc, a.u, n, &sig, st);
     if (r != hipSuccess) return r;
     if (n >= 1) {
       const int K = ctl->kmax < n + 1 ? ctl->kmax : n + 1;
-      hipLaunchKernelGGL(ad_choose, dim3(1), dim3(256), 0, st, a, b, n, K, kslot);
+      hipLaunchKernelGGL(ad_choose, dim3(1), dim3(256), 0, st, a, b, n, K,
+                         (int64_t)n * KSW + kslot);
     }
     if ((r = coll(n)) != hipSuccess) return r;
     hipLaunchKernelGGL(prop_eps, dim3(1), dim3(256), 0, st, a, n);
     return hipGetLastError();
   };
   hipError_t nerr = hipSuccess;
-  auto norm = [&](int n, int kind, double C, int npts, double coef, int slot) -> double {
+  // one or two norms (jobs) of step n: the host polls the launch's sequence number in host
+  // memory; every 256 polls it asks whether the stream has finished or failed, so an error or a
+  // launch that wrote nothing ends the wait
+  auto launch_norms = [&](int n, int nj, NormJob j0, NormJob j1) {
     const int64_t tot = (int64_t)(2 * n + 1 + ntau) * E;
     int nb = (int)((tot + 255) / 256);
     nb = nb < NPART ? nb : NPART;
-    hipLaunchKernelGGL(ad_norm_part, dim3(nb), dim3(256), 0, st, a, b, n, kind, C, npts, coef);
-    hipLaunchKernelGGL(ad_norm_final, dim3(1), dim3(64), 0, st, b, nb, tot, slot);
-    double v = 0.0;
-    hipError_t r = hipMemcpyAsync(&v, b.res + slot, sizeof(double), hipMemcpyDeviceToHost, st);
-    if (r == hipSuccess) r = hipStreamSynchronize(st);
-    if (r != hipSuccess) {
-      nerr = r;
-      return NAN;
+    ++seq;
+    hipLaunchKernelGGL(ad_norm, dim3(nb), dim3(256), 0, st, a, b, n, nj, j0, j1, seq);
+    const hipError_t r = hipGetLastError();
+    if (r != hipSuccess) nerr = r;
+  };
+  auto wait_norms = [&](int nj, double *out) {
+    hipError_t r = nerr;
+    for (uint64_t spin = 1; r == hipSuccess; ++spin) {
+      if (*hres.flag() == seq) break;
+      if ((spin & 255) == 0) {
+        const hipError_t qs = hipStreamQuery(st);
+        if (qs == hipErrorNotReady) continue;
+        if (qs != hipSuccess) r = qs;
+        else if (*hres.flag() != seq) r = hipErrorUnknown;  // the stream is idle: never written
+        break;
+      }
     }
-    return v;
+    std::atomic_thread_fence(std::memory_order_acquire);
+    for (int j = 0; j < nj; ++j) out[j] = r == hipSuccess ? hres.res()[j] : NAN;
+    if (r != hipSuccess) nerr = r;
+  };
+  // the history orders of steps 1..n-1 into the trace (slots beyond a step's evaluations zero)
+  auto finish = [&](int n) -> hipError_t {
+    tr->nt = n;
+    std::vector<int32_t> ks((size_t)n * KSW);
+    hipError_t r = hipMemcpyAsync(ks.data(), b.kbuf, ks.size() * sizeof(int32_t),
+                                  hipMemcpyDeviceToHost, st);
+    if (r == hipSuccess) r = hipStreamSynchronize(st);
+    if (r != hipSuccess) return r;
+    for (int j = 1; j < n; ++j)
+      for (int i = 0; i < KSW; ++i)
+        tr->ks[(int64_t)j * KSW + i] = i <= tr->m[j] ? ks[(size_t)j * KSW + i] : 0;
+    return hipSuccess;
   };
   std::vector<double> t(1, 0.0);
   // t = 0: the initial state, its right sides, the weights row 0 (zero)
   hipLaunchKernelGGL(fill_zero<double>, dim3(blocks((int64_t)nt * nt)), dim3(256), 0, st, wdev,
                      (int64_t)nt * nt);
   hipLaunchKernelGGL(ad_set_t, dim3(1), dim3(64), 0, st, tdev, 0, 0.0);
+  hipLaunchKernelGGL(fill_zero<uint32_t>, dim3(1), dim3(64), 0, st, b.done, (int64_t)1);
   hipLaunchKernelGGL(prop_init, dim3(blocks((int64_t)(nt + ntau) * E)), dim3(256), 0, st, a);
   if ((e = evaluate(0, 0)) != hipSuccess) return e;
   hipLaunchKernelGGL(prop_rhs, dim3(blocks((int64_t)(ntau + 3) * E)), dim3(256), 0, st, a, 0, 1);
@@ -1378,27 +1462,24 @@ hipError_t launch_propagate_adaptive(const kbe_prop *P, const kbe_adapt_ctl *ctl
   tr->q[0] = 0;
   tr->m[0] = 0;
   tr->err[0] = 0.0;
-  for (int i = 0; i <= QM + 1; ++i) tr->ks[i] = 0;
+  for (int i = 0; i < KSW; ++i) tr->ks[i] = 0;
   tr->rejected = 0;
   double h = ctl->h0;
   int q = 1, at_q = 0, n = 1;
-  const int ksw = QM + 2;  // trace stride of the history orders
   while (n < nt && t.back() < ctl->t_end * (1.0 - 1e-14)) {
     int nfail = 0, m = 0;
     double E_err = 0.0, tn = 0.0;
-    std::vector<int32_t> ks;
     for (;;) {
       h = h < ctl->t_end - t.back() ? h : ctl->t_end - t.back();
       if (!(h > 1e-13 * (t.back() > 1.0 ? t.back() : 1.0))) {  // step size underflow
-        tr->nt = n;
         *stalled = 1;
+        if ((e = finish(n)) != hipSuccess) return e;
         return hipGetLastError();
       }
       q = q < n ? q : n;
       tn = t.back() + h;
-      hipLaunchKernelGGL(ad_set_t, dim3(1), dim3(64), 0, st, tdev, n, tn);
-      const int kam = (ctl->kmax > q ? ctl->kmax : q);
-      if ((e = launch_interval_weights(tdev, n, kam, q, (double *)(wsb + L.amt),
+      const int kam = (ctl->kmax > q ? ctl->kmax : q);  // the rules store t_n in t[n] too
+      if ((e = launch_interval_weights(tdev, n, tn, kam, q, (double *)(wsb + L.amt),
                                        (double *)(wsb + L.abt), st)) != hipSuccess)
         return e;
       a.q = q;
@@ -1413,13 +1494,22 @@ hipError_t launch_propagate_adaptive(const kbe_prop *P, const kbe_adapt_ctl *ctl
       bool conv = false;
       double R = 1.0, dprev = 0.0;
       m = 0;
+      if ((e = evaluate(n, 0)) != hipSuccess) return e;
       while (m < ctl->maxcor) {
         ++m;
-        if ((e = evaluate(n, m - 1)) != hipSuccess) return e;
         hipLaunchKernelGGL(prop_rhs, dim3(blocks(ne * E)), dim3(256), 0, st, a, n, 0);
-        const double d = norm(n, 0, 0.0, 0, 0.0, 0);
-        if (nerr != hipSuccess) return nerr;
+        // the correction's norm, and the local error should this iterate be the last one
+        launch_norms(n, 2, NormJob{0, 0, 0.0, 0.0}, NormJob{3, 0, C, 0.0});
         hipLaunchKernelGGL(prop_commit, dim3(blocks(ne * E)), dim3(256), 0, st, a, n, -1);
+        // queued before the decision is known: the next iteration's evaluation and the final
+        // evaluation at the accepted values are the same computation on the committed iterate
+        // (it is only wasted when the step is rejected)
+        if ((e = evaluate(n, m)) != hipSuccess) return e;
+        double dv[2];
+        wait_norms(2, dv);
+        if (nerr != hipSuccess) return nerr;
+        const double d = dv[0];
+        E_err = dv[1];
         if (!std::isfinite(d)) break;  // a non-finite iterate: not converged
         if (m > 1) R = dprev > 0 ? (0.3 * R > d / dprev ? 0.3 * R : d / dprev) : 0.0;
         if ((R < 1.0 ? R : 1.0) * d * C < 0.1) {
@@ -1429,8 +1519,6 @@ hipError_t launch_propagate_adaptive(const kbe_prop *P, const kbe_adapt_ctl *ctl
         if (m > 1 && d > 2.0 * dprev) break;
         dprev = d;
       }
-      E_err = norm(n, 1, C, 0, 0.0, 1);
-      if (nerr != hipSuccess) return nerr;
       if (!conv || !std::isfinite(E_err)) {
         ++tr->rejected;
         h *= 0.25;
@@ -1451,10 +1539,28 @@ hipError_t launch_propagate_adaptive(const kbe_prop *P, const kbe_adapt_ctl *ctl
       }
       break;
     }
-    // accept: the right sides once more at the accepted values, the step's history
-    if ((e = evaluate(n, m)) != hipSuccess) return e;
+    // accept: the right sides at the accepted values (evaluated above), the step's history
     const int64_t ne = 2 * n + 1 + ntau;
     hipLaunchKernelGGL(prop_rhs, dim3(blocks((ne + 2) * E)), dim3(256), 0, st, a, n, 1);
+    t.push_back(tn);
+    tr->t[n] = tn;
+    tr->q[n] = q;
+    tr->m[n] = m;
+    tr->err[n] = E_err;
+    // the error estimates at orders q - 1 and q + 1 (once q + 1 steps were taken at order q), in
+    // one launch ahead of the rest of the step's kernels; read before the next step
+    ++at_q;
+    NormJob jb[2];
+    int dqs[2], nj = 0;
+    if (at_q >= q + 1) {
+      for (int dq = -1; dq <= 1; dq += 2) {
+        const int qq = q + dq, npts = qq + 1;
+        if (qq < 1 || qq > ctl->qmax || npts > n + 1) continue;
+        jb[nj] = NormJob{2, npts, 0.0, poly_integral(&t[n - qq + 1], qq, t[n - 1], t[n])};
+        dqs[nj++] = dq;
+      }
+      if (nj > 0) launch_norms(n, nj, jb[0], nj > 1 ? jb[1] : NormJob{});
+    }
     hipLaunchKernelGGL(ad_keep, dim3(blocks((int64_t)(n + 1 + ntau + 1) * E)), dim3(256), 0, st, a,
                        b, n);
     hipLaunchKernelGGL(prop_dens, dim3(1), dim3(64), 0, st, a, n, dens);
@@ -1465,31 +1571,19 @@ hipError_t launch_propagate_adaptive(const kbe_prop *P, const kbe_adapt_ctl *ctl
                        n, j0, nch);
     hipLaunchKernelGGL(ad_recon, dim3(blocks((int64_t)(n - j0) * E)), dim3(256), 0, st, a, b, n,
                        j0);
-    ks.assign(m + 1, 0);
-    if ((e = hipMemcpyAsync(ks.data(), b.kbuf, sizeof(int32_t) * (m + 1), hipMemcpyDeviceToHost,
-                            st)) != hipSuccess)
-      return e;
-    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-    t.push_back(tn);
-    tr->t[n] = tn;
-    tr->q[n] = q;
-    tr->m[n] = m;
-    tr->err[n] = E_err;
-    for (int i = 0; i < ksw; ++i) tr->ks[(int64_t)n * ksw + i] = i <= m ? ks[i] : 0;
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     // next step size and order
-    ++at_q;
     double eta = 1.0 / (pow(6.0 * E_err, 1.0 / (q + 1)) + 1e-6);
     int qn = q;
-    if (at_q >= q + 1) {
-      for (int dq = -1; dq <= 1; dq += 2) {
-        const int qq = q + dq, npts = qq + 1;
-        if (qq < 1 || qq > ctl->qmax || npts > n + 1) continue;
-        const double coef = poly_integral(&t[n - qq + 1], qq, t[n - 1], t[n]);
-        const double Eq = norm(n, 2, 0.0, npts, coef, 2);
-        if (nerr != hipSuccess) return nerr;
-        if (!std::isfinite(Eq)) continue;
-        const double bias = dq < 0 ? 6.0 : 10.0;
-        const double e2 = 1.0 / (pow(bias * Eq, 1.0 / (qq + 1)) + 1e-6);
+    if (nj > 0) {
+      double Eq[2];
+      wait_norms(nj, Eq);
+      if (nerr != hipSuccess) return nerr;
+      for (int j = 0; j < nj; ++j) {
+        if (!std::isfinite(Eq[j])) continue;
+        const int qq = q + dqs[j];
+        const double bias = dqs[j] < 0 ? 6.0 : 10.0;
+        const double e2 = 1.0 / (pow(bias * Eq[j], 1.0 / (qq + 1)) + 1e-6);
         if (e2 > eta) {
           eta = e2;
           qn = qq;
@@ -1503,7 +1597,7 @@ hipError_t launch_propagate_adaptive(const kbe_prop *P, const kbe_adapt_ctl *ctl
     }
     ++n;
   }
-  tr->nt = n;
+  if ((e = finish(n)) != hipSuccess) return e;
   if (t.back() < ctl->t_end * (1.0 - 1e-14)) *stalled = 2;  // capacity exhausted
   return hipGetLastError();
 }

@@ -224,23 +224,74 @@ __global__ void __launch_bounds__(64) step_weights_kernel(const double *t, const
   if ((int)threadIdx.x < k) out[threadIdx.x] = l[threadIdx.x];
 }
 
-// Rules of one interval n = [t_{n-1}, t_n] for an adaptive step: am[k-1][i], the local weights
+// Rules of one interval n = [t_{n-1}, t_n] for an adaptive step, t_n = tn (also stored in t[n] by
+// workgroup 0; every workgroup takes node n from the argument): am[k-1][i], the local weights
 // of Eq. weights on the k nodes t_{n-k+1..n} (k = 1..min(kam, n+1)), and ab[q-1][i], the integral
 // over the same interval of the Lagrange basis on the q nodes t_{n-q..n-1} (the predictor,
-// q = 1..min(kab, n)); other entries zero.  One 64-thread workgroup per (table, k).
-__global__ void __launch_bounds__(64) interval_weights_kernel(const double *t, int n, int kam,
-                                                              int kab, double *am, double *ab) {
-  __shared__ SolveLds S;
-  __shared__ double l[KBE_KMAX];
+// q = 1..min(kab, n)); other entries zero.  Each weight is the integral of its Lagrange basis
+// polynomial (degree < KBE_KMAX) by a Gauss-Legendre rule with GL_M points, exact for degree
+// < 2 GL_M: the same numbers as the moment equations, without their conditioning at high order.
+// One 64-thread workgroup per (table, k), one thread per weight.
+constexpr int GL_M = 12;
+struct GLRule {
+  double x[GL_M], w[GL_M];  // nodes and weights on [-1, 1]
+};
+static_assert(2 * GL_M > KBE_KMAX - 1, "the rule must integrate degree KBE_KMAX - 1 exactly");
+
+__global__ void __launch_bounds__(64) interval_weights_kernel(double *t, int n, double tn, int kam,
+                                                              int kab, double *am, double *ab,
+                                                              GLRule g) {
   const int tab = blockIdx.x / KBE_KMAX, k = blockIdx.x % KBE_KMAX + 1;
   double *out = (tab == 0 ? am : ab) + (int64_t)(k - 1) * KBE_KMAX;
-  if (threadIdx.x < KBE_KMAX) out[threadIdx.x] = 0.0;
+  const int j = threadIdx.x;
+  if (blockIdx.x == 0 && j == 0) t[n] = tn;
+  if (j >= KBE_KMAX) return;
   const int kmx = tab == 0 ? (kam < n + 1 ? kam : n + 1) : (kab < n ? kab : n);
-  if (n < 1 || k > kmx) return;  // uniform per workgroup
-  const double *x = tab == 0 ? t + (n - k + 1) : t + (n - k);
-  wave_solve(x, k, t[n - 1], t[n], l, S);
-  __syncthreads();
-  if ((int)threadIdx.x < k) out[threadIdx.x] = l[threadIdx.x];
+  if (n < 1 || k > kmx || j >= k) {
+    out[j] = 0.0;
+    return;
+  }
+  const int first = tab == 0 ? n - k + 1 : n - k;  // nodes t[first .. first + k - 1]
+  double x[KBE_KMAX];
+  for (int i = 0; i < k; ++i) x[i] = first + i == n ? tn : t[first + i];
+  const double a = t[n - 1], b = tn, half = 0.5 * (b - a), mid = 0.5 * (a + b);
+  double den = 1.0;
+  for (int i = 0; i < k; ++i)
+    if (i != j) den *= x[j] - x[i];
+  double acc = 0.0;
+  for (int m = 0; m < GL_M; ++m) {
+    const double s = mid + half * g.x[m];
+    double pr = 1.0;
+    for (int i = 0; i < k; ++i)
+      if (i != j) pr *= s - x[i];
+    acc += g.w[m] * pr;
+  }
+  out[j] = half * acc / den;
+}
+
+// The GL_M-point Gauss-Legendre rule on [-1, 1]: Newton's method on the three-term recurrence of
+// the Legendre polynomials from the usual cosine guesses.
+static GLRule gauss_legendre() {
+  GLRule g{};
+  const int m = GL_M;
+  for (int i = 0; i < m; ++i) {
+    double z = cos(M_PI * (i + 0.75) / (m + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int l = 1; l < m; ++l) {
+        const double p2 = ((2.0 * l + 1.0) * z * p1 - l * p0) / (l + 1.0);
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = m * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (fabs(dz) < 1e-16) break;
+    }
+    g.x[i] = z;
+    g.w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+  return g;
 }
 
 // Grid check on the device: status = 0, or KBE_EINVAL (t[0] != 0 or t not increasing), or
@@ -321,10 +372,11 @@ hipError_t launch_grid_check(const double *t, const int32_t *order, int nt, int3
   return hipGetLastError();
 }
 
-hipError_t launch_interval_weights(const double *t, int n, int kam, int kab, double *am,
+hipError_t launch_interval_weights(double *t, int n, double tn, int kam, int kab, double *am,
                                    double *ab, hipStream_t st) {
-  hipLaunchKernelGGL(interval_weights_kernel, dim3(2 * KBE_KMAX), dim3(64), 0, st, t, n, kam, kab,
-                     am, ab);
+  static const GLRule g = gauss_legendre();
+  hipLaunchKernelGGL(interval_weights_kernel, dim3(2 * KBE_KMAX), dim3(64), 0, st, t, n, tn, kam,
+                     kab, am, ab, g);
   return hipGetLastError();
 }
 

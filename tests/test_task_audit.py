@@ -15,6 +15,8 @@ import pytest
 import paper_2405_08737_amd as kbe
 
 OUT_ALL, GREATER, FORCE_GENERIC = 0xF, 0x400, 0x100
+OUT_IR_IL = 0x3
+BOTH = 0x10000  # library-internal: both forms in one call (the propagations), forward only
 
 
 def audit(N, nt, ntau, n, m0, m1, flags, adjoint, ldt=None):
@@ -61,6 +63,20 @@ def test_every_task_stays_inside_its_arrays(N, nt, ntau, n, m0, m1, greater, adj
         return
     bad, checked = audit(N, nt, ntau, n, m0, m1, flags | FORCE_GENERIC, adjoint)
     assert bad == 0
+
+
+@pytest.mark.parametrize("N,nt,ntau,n,m0,m1", CASES)
+def test_both_forms_tasks_stay_inside_their_arrays(N, nt, ntau, n, m0, m1):
+    """The propagations' call that runs the lesser and the greater form together (the greater
+    form's I^< on a Sigma^> row of m1 blocks through its own class)."""
+    for extra in (0, FORCE_GENERIC):
+        bad, checked = audit(N, nt, ntau, n, m0, m1, OUT_ALL | BOTH | extra, 0)
+        assert checked > 0
+        assert bad == 0, f"{bad} of {checked} addresses outside their arrays"
+        lesser = audit(N, nt, ntau, n, m0, m1, OUT_ALL | extra, 0)[1]
+        greater = audit(N, nt, ntau, n, m0, m1, OUT_IR_IL | GREATER | extra, 0)[1]
+        # every address of the lesser form, plus the greater form's minus its shared I^R terms
+        assert lesser < checked < lesser + greater
 
 
 def test_padded_row_stride():
