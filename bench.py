@@ -8,11 +8,13 @@ timing starts.  After the timed steps, the forward and adjoint collision calls a
 the 8-orbital differentiation shape (nt = 1024, n_tau = 256: the small-block path, bound by HBM
 bandwidth), and the batching workload (256 independent rows, N in {2,4,8,16}, n up to 4096) is
 timed as one batched launch, as a graph replay and as 256 separate launches; the end-to-end
-gradient of a propagation (kbe_propagate and its adjoint on the 8-orbital grid) is timed too;
-all are reported beside the step, with the FP64 matrix-core and HBM ceilings measured live by
-the library's microbenchmarks.  Prints one JSON line.
+gradient of a propagation (kbe_propagate and its adjoint on the 8-orbital grid) and the adaptive
+propagation of the 8-site chain (kbe_propagate_adaptive) are timed too; all are reported beside
+the step, with the FP64 matrix-core and HBM ceilings measured live by the library's
+microbenchmarks.  Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-propagation]
+  python bench.py --adaptive-only      # only the adaptive propagation cases
   python bench.py --copy-calibration   # 3 plain 1 GiB device copies (PMC byte-counter scale)
   python bench.py --ceilings           # the ceiling microbenchmarks -> profiles/ceilings.json
 """
@@ -588,6 +590,8 @@ def main():
                     help="only run the ceiling microbenchmarks and write profiles/ceilings.json")
     ap.add_argument("--adaptive-only", action="store_true",
                     help="only run the adaptive propagation cases (no oracle leg)")
+    ap.add_argument("--no-propagation", action="store_true",
+                    help="skip the two propagations (for counter runs over the collision kernels)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three plain 1 GiB device-to-device copies: the reference "
                          "reading that scales FETCH_SIZE / WRITE_SIZE to bytes")
@@ -761,16 +765,19 @@ def main():
     log("batching workload")
     result["batching"] = batching(kbe, torch, dev)
     torch.cuda.empty_cache()
-    log("end-to-end gradients through a propagation")
-    result["propagation"] = propagation(kbe, torch, dev)
-    torch.cuda.empty_cache()
-    log("adaptive propagation")
-    result["adaptive"], replays = adaptive(kbe, torch, dev)
+    replays = []
+    if not args.no_propagation:
+        log("end-to-end gradients through a propagation")
+        result["propagation"] = propagation(kbe, torch, dev)
+        torch.cuda.empty_cache()
+        log("adaptive propagation")
+        result["adaptive"], replays = adaptive(kbe, torch, dev)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample)")
         result["cpu_baseline"] = cpu_baseline(w, (t, order, kp_h, rd_h, tv_h, mat_h))
-        log("oracle replaying the adaptive prefixes")
-        result["cpu_baseline"]["adaptive"] = adaptive_oracle(replays)
+        if replays:
+            log("oracle replaying the adaptive prefixes")
+            result["cpu_baseline"]["adaptive"] = adaptive_oracle(replays)
     print(json.dumps(result), flush=True)
 
 
