@@ -788,13 +788,14 @@ struct AA {                        // adaptive-only arrays
   kbe_c128 *upart;                 // [chunks][QM][2][E] their partial sums by term chunk
   double *part;                    // [2][NPART] norm partial sums
   uint32_t *done;                  // workgroups of a norm launch that have stored their partials
+  uint32_t *cdone;                 // workgroups of an ad_choose launch that have stored their u
   double *res;                     // [2] norm results, in page-locked host memory
   volatile uint32_t *flag;         // sequence number of the last norm launch (host memory)
   int32_t *kbuf;                   // [nt][QM + 2] history order of every evaluation of each step
   double rtol, atol;
 };
 
-constexpr int NPART = 1024;
+constexpr int NPART = 256;  // workgroups of a norm launch, at most (each fences and counts once)
 
 __global__ void ad_set_t(double *t, int n, double v) {
   if (threadIdx.x == 0) t[n] = v;
@@ -829,14 +830,17 @@ __global__ void ad_predict(PA a, AA b, int n) {
 // (Sigma^<(t_s,t_n) = -Sigma^<(t_n,t_s)^dagger, Sigma^A(t_s,t_n) = Sigma^R(t_n,t_s)^dagger,
 // G^<(t_n,t_s) = -kp[s][n]^dagger), its integrals I^(k) over the interval with k = 1..K nodes,
 // k_opt = the first minimum of ||I^(k) - I^(k-1)||_F over k = 2..K, and row n of the history
-// weights: row n-1 plus the local weights on k_opt nodes.  One workgroup; fixed-order sums.
+// weights: row n-1 plus the local weights on k_opt nodes.  The entries of u are spread over
+// workgroups; the last one to finish (a counter it resets) makes the choice; fixed-order sums.
 __global__ void __launch_bounds__(256) ad_choose(PA a, AA b, int n, int K, int64_t slot) {
   const int64_t E = E_(a);
   const int N = a.N;
   __shared__ double dk[KM + 1];
   __shared__ int kopt;
+  __shared__ bool last;
   const int tid = threadIdx.x;
-  for (int64_t x = tid; x < (int64_t)K * E; x += 256) {  // u at s = n-K+1+i
+  // every workgroup computes 256 entries of u; the last one to finish chooses k_opt
+  for (int64_t x = (int64_t)blockIdx.x * 256 + tid; x < (int64_t)K * E; x += (int64_t)gridDim.x * 256) {
     const int i = (int)(x / E), q = (int)(x % E), r = q / N, c = q % N;
     const int sidx = n - K + 1 + i;
     const kbe_c128 *gr = sidx < n ? a.kp + ((int64_t)n * a.ldt + sidx) * E : a.rdiag + n * E;
@@ -852,6 +856,14 @@ __global__ void __launch_bounds__(256) ad_choose(PA a, AA b, int n, int K, int64
     st(b.ubuf + x, acc);
   }
   __syncthreads();
+  if (tid == 0) {
+    __threadfence();
+    last = atomicAdd(b.cdone, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  if (tid == 0) *b.cdone = 0u;
   // ||I^(k) - I^(k-1)||_F for k = 2..K: wave w takes k = 2 + w, 6 + w, ...; each lane sums its
   // entries q = lane, lane + 64, ... and the wave sums the lanes by a fixed butterfly
   const int wave = tid / 64, lane = tid % 64;
@@ -903,15 +915,26 @@ __device__ __forceinline__ cd norm_term(const PA &a, const AA &b, int n, int e, 
   if (j.kind == 0) return ld(a.ynext + gid) - ld(val_ptr(a, a.kp, a.tv, n, kind_e, idx) + q);
   if (j.kind == 1) return j.C * (ld(val_ptr(a, a.kp, a.tv, n, kind_e, idx) + q) - ld(b.ypred + gid));
   if (j.kind == 3) return j.C * (ld(a.ynext + gid) - ld(b.ypred + gid));
+  // Newton's recursion over a fixed bound, predicated on npts, so the arrays stay in registers
   cd d[QM + 2];
   double tt[QM + 2];
-  for (int i = 0; i < j.npts; ++i) {
-    const int jj = n - j.npts + 1 + i;
-    tt[i] = b.t[jj];
-    d[i] = ld(f_ptr(a, a.fkp, a.fbu, a.fbr, a.ftv, jj, kind_e, idx) + q);
+#pragma unroll
+  for (int i = 0; i < QM + 2; ++i) {
+    if (i < j.npts) {
+      const int jj = n - j.npts + 1 + i;
+      tt[i] = b.t[jj];
+      d[i] = ld(f_ptr(a, a.fkp, a.fbu, a.fbr, a.ftv, jj, kind_e, idx) + q);
+    } else {
+      tt[i] = 0.0;
+      d[i] = czero();
+    }
   }
-  for (int lev = 1; lev < j.npts; ++lev)
-    for (int i = 0; i + lev < j.npts; ++i) d[i] = (1.0 / (tt[i + lev] - tt[i])) * (d[i + 1] - d[i]);
+#pragma unroll
+  for (int lev = 1; lev < QM + 2; ++lev) {
+#pragma unroll
+    for (int i = 0; i + lev < QM + 2; ++i)
+      if (i + lev < j.npts) d[i] = (1.0 / (tt[i + lev] - tt[i])) * (d[i + 1] - d[i]);
+  }
   return j.coef * d[0];
 }
 
@@ -1253,7 +1276,7 @@ ALay alayout(int N, int nt, int ntau) {
   L.amt = take(KM * KM * sizeof(double));
   L.abt = take(KM * KM * sizeof(double));
   L.part = take(2 * NPART * sizeof(double));
-  L.done = take(sizeof(uint32_t));
+  L.done = take(2 * sizeof(uint32_t));
   L.kbuf = take((size_t)nt * KSW * sizeof(int32_t));
   const int n = nt - 1;
   L.cws = take(collision_ws_bytes(N, nt, ntau, n, 0, n + 1, KBE_OUT_ALL | KBE_INT_BOTH));
@@ -1350,6 +1373,7 @@ hipError_t launch_propagate_adaptive(const kbe_prop *P, const kbe_adapt_ctl *ctl
   b.upart = c(L.upart);
   b.part = (double *)(wsb + L.part);
   b.done = (uint32_t *)(wsb + L.done);
+  b.cdone = b.done + 1;
   b.kbuf = (int32_t *)(wsb + L.kbuf);
   // the norms the controller reads: written by the kernels into page-locked host memory, read
   // after the stream is synchronised (no copy operations)
@@ -1398,7 +1422,7 @@ hipError_t launch_propagate_adaptive(const kbe_prop *P, const kbe_adapt_ctl *ctl
     if (r != hipSuccess) return r;
     if (n >= 1) {
       const int K = ctl->kmax < n + 1 ? ctl->kmax : n + 1;
-      hipLaunchKernelGGL(ad_choose, dim3(1), dim3(256), 0, st, a, b, n, K,
+      hipLaunchKernelGGL(ad_choose, dim3(blocks((int64_t)K * E)), dim3(256), 0, st, a, b, n, K,
                          (int64_t)n * KSW + kslot);
     }
     if ((r = coll(n)) != hipSuccess) return r;
@@ -1452,7 +1476,7 @@ hipError_t launch_propagate_adaptive(const kbe_prop *P, const kbe_adapt_ctl *ctl
   hipLaunchKernelGGL(fill_zero<double>, dim3(blocks((int64_t)nt * nt)), dim3(256), 0, st, wdev,
                      (int64_t)nt * nt);
   hipLaunchKernelGGL(ad_set_t, dim3(1), dim3(64), 0, st, tdev, 0, 0.0);
-  hipLaunchKernelGGL(fill_zero<uint32_t>, dim3(1), dim3(64), 0, st, b.done, (int64_t)1);
+  hipLaunchKernelGGL(fill_zero<uint32_t>, dim3(1), dim3(64), 0, st, b.done, (int64_t)2);
   hipLaunchKernelGGL(prop_init, dim3(blocks((int64_t)(nt + ntau) * E)), dim3(256), 0, st, a);
   if ((e = evaluate(0, 0)) != hipSuccess) return e;
   hipLaunchKernelGGL(prop_rhs, dim3(blocks((int64_t)(ntau + 3) * E)), dim3(256), 0, st, a, 0, 1);

@@ -244,16 +244,18 @@ __global__ void __launch_bounds__(64) interval_weights_kernel(double *t, int n, 
   const int tab = blockIdx.x / KBE_KMAX, k = blockIdx.x % KBE_KMAX + 1;
   double *out = (tab == 0 ? am : ab) + (int64_t)(k - 1) * KBE_KMAX;
   const int j = threadIdx.x;
-  if (blockIdx.x == 0 && j == 0) t[n] = tn;
-  if (j >= KBE_KMAX) return;
+  __shared__ double x[KBE_KMAX];
   const int kmx = tab == 0 ? (kam < n + 1 ? kam : n + 1) : (kab < n ? kab : n);
-  if (n < 1 || k > kmx || j >= k) {
+  const bool live = n >= 1 && k <= kmx;                 // uniform per workgroup
+  const int first = tab == 0 ? n - k + 1 : n - k;      // nodes t[first .. first + k - 1]
+  if (live && j < k) x[j] = first + j == n ? tn : t[first + j];
+  __syncthreads();
+  if (blockIdx.x == 0 && j == 0) t[n] = tn;  // no workgroup reads t[n]: node n is tn
+  if (j >= KBE_KMAX) return;
+  if (!live || j >= k) {
     out[j] = 0.0;
     return;
   }
-  const int first = tab == 0 ? n - k + 1 : n - k;  // nodes t[first .. first + k - 1]
-  double x[KBE_KMAX];
-  for (int i = 0; i < k; ++i) x[i] = first + i == n ? tn : t[first + i];
   const double a = t[n - 1], b = tn, half = 0.5 * (b - a), mid = 0.5 * (a + b);
   double den = 1.0;
   for (int i = 0; i < k; ++i)
