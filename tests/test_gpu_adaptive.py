@@ -35,10 +35,15 @@ def run_gpu(kbe, P, U, A, **kw):
 
 CASES = [dict(N=2, ntau=6, beta=2.0, U=1.0, A=0.7, t_end=0.8, rtol=1e-5, atol=1e-8),
          dict(N=3, ntau=0, beta=2.0, U=1.5, A=0.5, t_end=0.6, rtol=1e-6, atol=1e-9),
-         dict(N=4, ntau=5, beta=1.0, U=0.8, A=1.0, t_end=0.5, rtol=1e-4, atol=1e-7)]
+         dict(N=4, ntau=5, beta=1.0, U=0.8, A=1.0, t_end=0.5, rtol=1e-4, atol=1e-7),
+         # low orders and at most one fixed-point correction per step (rejections by the
+         # convergence test as well as by the error test)
+         dict(N=3, ntau=4, beta=1.5, U=1.2, A=0.9, t_end=0.5, rtol=1e-4, atol=1e-7, qmax=3,
+              kmax=4, maxcor=1)]
 
 
-@pytest.mark.parametrize("case", CASES, ids=lambda c: f"N{c['N']}_ntau{c['ntau']}")
+@pytest.mark.parametrize("case", CASES,
+                         ids=lambda c: f"N{c['N']}_ntau{c['ntau']}" + ("_q3k4m1" if "qmax" in c else ""))
 def test_adaptive_matches_oracle(gpu, case):
     kbe = gpu
     c = dict(case)
@@ -48,7 +53,8 @@ def test_adaptive_matches_oracle(gpu, case):
     g = run_gpu(kbe, P, U, A, capacity=512, **c)
     _print("  gpu: %d steps, %d rejected, orders %s" % (len(g["t"]) - 1, g["rejected"],
                                                          np.bincount(g["q"][1:])))
-    ctl = ad.Controls(t_end=c["t_end"], rtol=c["rtol"], atol=c["atol"], nt_max=512)
+    ctl = ad.Controls(t_end=c["t_end"], rtol=c["rtol"], atol=c["atol"], nt_max=512,
+                      qmax=c.get("qmax", 12), kmax=c.get("kmax", 10), maxcor=c.get("maxcor", 3))
     orc = ad.Adaptive(P, ctl)
     d_own = orc.run(U, A).numpy()
     own = orc.trace
@@ -128,3 +134,33 @@ def test_adaptive_hubbard_workload_short(gpu):
     kp = g["G"].kp[:7, :7].cpu().numpy()
     assert np.linalg.norm(kp - kp_ref) < 1e-12 * np.linalg.norm(kp_ref)
     assert np.linalg.norm(g["G"].tv[:7].cpu().numpy() - tv_ref) < 1e-12 * np.linalg.norm(tv_ref)
+
+
+def test_adaptive_capacity_exhausted(gpu):
+    """A grid that runs out of points before t_end: KBE_ESTEP with the accepted steps, which are
+    those of a run with room to spare (the same decisions, the same solution bit for bit)."""
+    kbe = gpu
+    h0, mat, P = problem(2, 6, 2.0)
+    full = run_gpu(kbe, P, 1.0, 0.7, capacity=512, t_end=0.8, rtol=1e-5, atol=1e-8)
+    cap = 12
+    assert len(full["t"]) > cap
+    with pytest.raises(kbe.KBEError, match="KBE_ESTEP") as ex:
+        run_gpu(kbe, P, 1.0, 0.7, capacity=cap, t_end=0.8, rtol=1e-5, atol=1e-8)
+    part = ex.value.partial
+    assert ex.value.status == kbe.KBE_ESTEP and part is not None
+    assert len(part["t"]) == cap
+    assert np.array_equal(part["t"], full["t"][:cap])
+    assert np.array_equal(part["q"], full["q"][:cap]) and part["ks"] == full["ks"][:cap - 1]
+    kp_p = part["G"].kp[:cap, :cap].cpu().numpy()
+    kp_f = full["G"].kp[:cap, :cap].cpu().numpy()
+    assert np.array_equal(kp_p, kp_f)
+    assert np.array_equal(part["dens"].cpu().numpy(), full["dens"][:cap].cpu().numpy())
+
+
+def test_adaptive_rejects_bad_controls(gpu):
+    """Argument errors are reported before any launch."""
+    kbe = gpu
+    h0, mat, P = problem(2, 0, 2.0)
+    for bad in (dict(qmax=13), dict(kmax=1), dict(maxcor=0), dict(rtol=0.0), dict(h_first=-1.0)):
+        with pytest.raises(kbe.KBEError, match="KBE_EINVAL"):
+            run_gpu(kbe, P, 1.0, 0.7, capacity=16, t_end=0.5, **bad)
