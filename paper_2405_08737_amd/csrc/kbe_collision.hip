@@ -1467,6 +1467,16 @@ static size_t plan_adjoint(int N, int ntau, int n, int m0, int m1, unsigned flag
   size_t off = 0;
   const bool th = ntau > 0, M = m1 > m0;
   const bool fITV = (flags & KBE_OUT_ITV) && th, fJTV = (flags & KBE_OUT_JTV) && th;
+  if (flags & KBE_INT_GREXTRA) {  // only the greater form's terms beyond the lesser form's
+    if ((flags & KBE_OUT_IR) && M) {
+      plan_add(pl, B_GRL, n + 1, m1, E, off);
+      plan_add(pl, B_GRD, n + 1, m1, E, off);
+      plan_add(pl, B_GRU, n + 1, m1, E, off);
+    }
+    if ((flags & KBE_OUT_IL) && M) plan_add(pl, B_L, n + 1, m1, E, off);
+    pl.qoff = (int64_t)off;
+    return off + 256;
+  }
   if ((flags & KBE_OUT_IR) && M) {
     plan_add(pl, B_R1, n + 1, m1, E, off);
     plan_add(pl, B_R2, n + 1, m1, E, off);
@@ -1646,14 +1656,21 @@ hipError_t launch_collision_vjp(const Params &p, unsigned flags, kbe_c128 *gmat,
   // self-energy gradients: overwritten
   RedAll r{};
   r.SC = pl.SC;
-  if (flags & KBE_GREATER)  // Sigma^> = Sigma^R + Sigma^< in I^<: its terms also reach gSigma^R
+  const bool extra = flags & KBE_INT_GREXTRA;
+  if (extra) {  // the Sigma^R part of Sigma^> in I^< and the G^R terms; nothing reaches Sigma^<
+    reduce_into(p, pl, {B_GRL, B_GRD, B_GRU, B_L}, w, p.n + 1, gS->ret, false, r);
+    reduce_into(p, pl, {}, w, p.n + 1, gS->les, false, r);
+    reduce_launch(p, r, st);
+  } else if (flags & KBE_GREATER)  // Sigma^> = Sigma^R + Sigma^< in I^<: its terms also reach gSigma^R
     reduce_into(p, pl, {B_R1, B_R2, B_R3, B_GRL, B_GRD, B_GRU, B_L}, w, p.n + 1, gS->ret, false, r);
   else
     reduce_into(p, pl, {B_R1, B_R2, B_R3}, w, p.n + 1, gS->ret, false, r);
-  reduce_into(p, pl, {B_L}, w, p.n + 1, gS->les, false, r);
-  if (p.ntau > 0) reduce_into(p, pl, {B_T1, B_T2A, B_T2B}, w, p.ntau, gS->tv, false, r);
-  if (p.fJTV) reduce_into(p, pl, {G_MAT1, G_MAT2}, w, p.ntau, gmat, !p.overwrite, r);
-  reduce_launch(p, r, st);
+  if (!extra) {
+    reduce_into(p, pl, {B_L}, w, p.n + 1, gS->les, false, r);
+    if (p.ntau > 0) reduce_into(p, pl, {B_T1, B_T2A, B_T2B}, w, p.ntau, gS->tv, false, r);
+    if (p.fJTV) reduce_into(p, pl, {G_MAT1, G_MAT2}, w, p.ntau, gmat, !p.overwrite, r);
+    reduce_launch(p, r, st);
+  }
   // Green's-function gradients
   const int64_t n1 = p.n + 1;
   const int64_t nblk = n1 * n1 + n1 + (p.ntau > 0 ? n1 * p.ntau : 0);
@@ -1661,8 +1678,9 @@ hipError_t launch_collision_vjp(const Params &p, unsigned flags, kbe_c128 *gmat,
   if (mfma) {
     const int nseg = (row_len + GSEG - 1) / GSEG;
     const int64_t tasks = (int64_t)(p.n + 1) * nseg;
-    hipLaunchKernelGGL(grad_mfma16<0>, dim3((unsigned)(8 * ((tasks + 7) / 8))), dim3(256), 0, st,
-                       p, row_len, nseg);
+    if (!extra)
+      hipLaunchKernelGGL(grad_mfma16<0>, dim3((unsigned)(8 * ((tasks + 7) / 8))), dim3(256), 0,
+                         st, p, row_len, nseg);
     if (flags & KBE_GREATER) {  // the greater form's extra terms, in two more passes
       hipLaunchKernelGGL(grad_mfma16<1>, dim3((unsigned)(8 * ((tasks + 7) / 8))), dim3(256), 0,
                          st, p, row_len, nseg);
@@ -1672,15 +1690,16 @@ hipError_t launch_collision_vjp(const Params &p, unsigned flags, kbe_c128 *gmat,
   } else if (kind >= 5 && kind <= 8) {
     const int nseg = (row_len + GSEG8 - 1) / GSEG8;
     const int64_t tasks = (int64_t)(p.n + 1) * nseg;
-    hipLaunchKernelGGL(grad_mfma8<0>, dim3((unsigned)(8 * ((tasks + 7) / 8))), dim3(256), 0, st,
-                       p, row_len, nseg);
+    if (!extra)
+      hipLaunchKernelGGL(grad_mfma8<0>, dim3((unsigned)(8 * ((tasks + 7) / 8))), dim3(256), 0,
+                         st, p, row_len, nseg);
     if (flags & KBE_GREATER) {  // the greater form's extra terms, in two more passes
       hipLaunchKernelGGL(grad_mfma8<1>, dim3((unsigned)(8 * ((tasks + 7) / 8))), dim3(256), 0,
                          st, p, row_len, nseg);
       hipLaunchKernelGGL(grad_mfma8<2>, dim3((unsigned)(8 * ((tasks + 7) / 8))), dim3(256), 0,
                          st, p, row_len, nseg);
     }
-  } else {
+  } else if (!extra) {
     const int64_t th = nblk * p.N * p.N;
     hipLaunchKernelGGL(grad_generic, dim3((unsigned)((th + 255) / 256)), dim3(256), 0, st, p, nblk);
   }

@@ -46,6 +46,10 @@ hipError_t launch_collision(const Params &p, unsigned flags, kbe_c128 *IR, kbe_c
 // greater form's I^R, I^<, sharing the lesser form's I^R terms.  Internal flag (not part of the
 // C ABI, whose flag check rejects it) for the workspace query and the task audit.
 constexpr unsigned KBE_INT_BOTH = 0x10000u;
+// Adjoint of the greater form's terms beyond the lesser form's (with KBE_GREATER; accumulate
+// mode only): the G^R terms of I^R and the Sigma^R part of Sigma^> in I^<.  The adjoint of both
+// forms is the lesser form's adjoint on the summed cotangents plus this on the greater form's.
+constexpr unsigned KBE_INT_GREXTRA = 0x20000u;
 hipError_t launch_collision_both(const Params &p, kbe_c128 *IRl, kbe_c128 *ILl, kbe_c128 *Itv,
                                  kbe_c128 *Jtv, kbe_c128 *IRg, kbe_c128 *ILg, void *ws,
                                  hipStream_t st);

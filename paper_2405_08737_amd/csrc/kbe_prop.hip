@@ -63,6 +63,7 @@ struct PA {                       // everything the small kernels read, passed b
   kbe_c128 *gkp, *gtv;              // gradient of the solution (same layout as kp, tv)
   kbe_c128 *gfkp, *gfbu, *gfbr, *gftv;  // gradient of the f history
   kbe_c128 *ybar, *bbar, *fbar, *epart;  // [elements][E]
+  kbe_c128 *epp;                          // [element chunks][E] partial sums of epart
   kbe_c128 *CbL, *CbG, *CbT, *Jbar;      // cotangents of the history sums
   kbe_c128 *gretL, *glesL, *gretG, *glesG;
   // adaptive propagation: one method order q for every element, rules of the current interval,
@@ -456,13 +457,28 @@ __global__ void prop_direct(PA a, int n, int mode) {
 
 // epsbar = sum of the element shares (fixed order), then through eps: the Fock term into
 // G^<(t_n,t_n) and u, the pulse into its amplitude.
+// eps's gradient: the per-element shares summed in a fixed order, in two stages (chunks of
+// EPC elements over many workgroups, then the chunks in order).
+constexpr int EPC = 32;
+__global__ void prop_eps_part(PA a, int n) {
+  const int64_t E = E_(a);
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int ne = nelem(a, n), nch = (ne + EPC - 1) / EPC;
+  if (gid >= (int64_t)nch * E) return;
+  const int ch = (int)(gid / E), q = (int)(gid % E);
+  const int e1 = (ch + 1) * EPC < ne ? (ch + 1) * EPC : ne;
+  cd s = czero();
+  for (int e = ch * EPC; e < e1; ++e) s = s + ld(a.epart + (int64_t)e * E + q);
+  st(a.epp + gid, s);
+}
+
 __global__ void prop_eps_vjp(PA a, int n, double *gu, double *gamp) {
   const int64_t E = E_(a);
   const int q = threadIdx.x;
   if (q >= E) return;
-  const int ne = nelem(a, n);
+  const int nch = (nelem(a, n) + EPC - 1) / EPC;
   cd s = czero();
-  for (int e = 0; e < ne; ++e) s = s + ld(a.epart + (int64_t)e * E + q);
+  for (int ch = 0; ch < nch; ++ch) s = s + ld(a.epp + (int64_t)ch * E + q);
   const int r = q / a.N, c = q % a.N;
   if (r == c) {  // eps_rr += -i u_r D_rr
     kbe_c128 *g = a.gkp + ((int64_t)n * a.ldt + n) * E + q;
@@ -546,7 +562,7 @@ size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Layout {
   size_t fkp, fbu, fbr, ftv, ykp, ytv, eps, sig_ret, sig_les, sig_tv, IRl, ILl, Itv, Jtv, IRg,
       ILg, base, ynext, cws;                                  // forward
-  size_t gkp, grd, gtv, gmat, gfkp, gfbu, gfbr, gftv, ybar, bbar, fbar, epart, CbL, CbG, CbT,
+  size_t gkp, grd, gtv, gmat, gfkp, gfbu, gfbr, gftv, ybar, bbar, fbar, epart, epp, CbL, CbG, CbT,
       Jbar, gretL, glesL, gstvL, gretG, glesG, gstvG, vws, sws;  // adjoint
   size_t total;
 };
@@ -589,6 +605,7 @@ Layout layout(int N, int nt, int ntau, int64_t ldt, int K) {
   L.bbar = take(ne * E);
   L.fbar = take(ne * E);
   L.epart = take(ne * E);
+  L.epp = take(((ne + EPC - 1) / EPC) * E);
   L.CbL = take(nt * E);
   L.CbG = take(nt * E);
   L.CbT = take(nt * E);
@@ -677,15 +694,20 @@ hipError_t evaluate_vjp(Ctx &x, int n, int mode, double *gu, double *gamp) {
   hipLaunchKernelGGL(prop_cot, dim3(blocks((int64_t)(n + 1 + x.a.ntau) * E)), dim3(256), 0, x.st,
                      x.a, n, mode);
   hipLaunchKernelGGL(prop_direct, dim3(blocks((int64_t)ne * E)), dim3(256), 0, x.st, x.a, n, mode);
+  const int64_t nch = (ne + EPC - 1) / EPC;
+  hipLaunchKernelGGL(prop_eps_part, dim3(blocks(nch * E)), dim3(256), 0, x.st, x.a, n);
   hipLaunchKernelGGL(prop_eps_vjp, dim3(1), dim3(256), 0, x.st, x.a, n, gu, gamp);
   const bool th = x.a.ntau > 0;
   Params p = coll_params(x, n);
   p.gkp = x.gG.kp;
   p.grdiag = x.gG.rdiag;
   p.gtv = x.gG.tv;
+  // Both forms by linearity: the lesser form's adjoint with the summed cotangents (the terms
+  // the forms share, I^R's and the Sigma^< part of I^<, enter C^< and C^> alike, as I^] does:
+  // CbT = CbL + CbG), then the greater form's further terms with its own cotangent.
   set_flags(p, FL, th);
-  p.gIR = x.a.CbL;
-  p.gIL = x.a.CbL;
+  p.gIR = x.a.CbT;
+  p.gIL = x.a.CbT;
   p.gItv = x.a.CbT;
   p.gJ = x.a.Jbar;
   e = launch_collision_vjp(p, FL, x.gG.mat, &x.gSL, x.ws + x.L.vws, x.st);
@@ -695,7 +717,7 @@ hipError_t evaluate_vjp(Ctx &x, int n, int mode, double *gu, double *gamp) {
   p.gIL = x.a.CbG;
   p.gItv = nullptr;
   p.gJ = nullptr;
-  e = launch_collision_vjp(p, FG, x.gG.mat, &x.gSG, x.ws + x.L.vws, x.st);
+  e = launch_collision_vjp(p, FG | KBE_INT_GREXTRA, x.gG.mat, &x.gSG, x.ws + x.L.vws, x.st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(prop_gs_add, dim3(blocks((int64_t)(n + 1) * E)), dim3(256), 0, x.st, x.a, n);
   return launch_sigma_row_vjp(&x.Gc, x.a.u, n, &x.gSL, &x.gG, gu, x.ws + x.L.sws, x.st);
@@ -753,6 +775,7 @@ Ctx make_ctx(const kbe_prop *P, const kbe_wts *W, const kbe_green *G, void *ws, 
   a.bbar = c(x.L.bbar);
   a.fbar = c(x.L.fbar);
   a.epart = c(x.L.epart);
+  a.epp = c(x.L.epp);
   a.CbL = c(x.L.CbL);
   a.CbG = c(x.L.CbG);
   a.CbT = c(x.L.CbT);

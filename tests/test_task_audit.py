@@ -17,6 +17,7 @@ import paper_2405_08737_amd as kbe
 OUT_ALL, GREATER, FORCE_GENERIC = 0xF, 0x400, 0x100
 OUT_IR_IL = 0x3
 BOTH = 0x10000  # library-internal: both forms in one call (the propagations), forward only
+GREXTRA = 0x20000  # library-internal: the greater form's adjoint beyond the lesser form's
 
 
 def audit(N, nt, ntau, n, m0, m1, flags, adjoint, ldt=None):
@@ -77,6 +78,17 @@ def test_both_forms_tasks_stay_inside_their_arrays(N, nt, ntau, n, m0, m1):
         greater = audit(N, nt, ntau, n, m0, m1, OUT_IR_IL | GREATER | extra, 0)[1]
         # every address of the lesser form, plus the greater form's minus its shared I^R terms
         assert lesser < checked < lesser + greater
+
+
+@pytest.mark.parametrize("N,nt,ntau,n,m0,m1", CASES)
+def test_greater_extra_adjoint_tasks_stay_inside_their_arrays(N, nt, ntau, n, m0, m1):
+    """The propagations' adjoint of the greater form's further terms alone (library-internal)."""
+    for extra in (0, FORCE_GENERIC):
+        bad, checked = audit(N, nt, ntau, n, m0, m1, OUT_IR_IL | GREATER | GREXTRA | extra, 1)
+        assert checked > 0
+        assert bad == 0, f"{bad} of {checked} addresses outside their arrays"
+        full = audit(N, nt, ntau, n, m0, m1, OUT_IR_IL | GREATER | extra, 1)[1]
+        assert checked < full
 
 
 def test_padded_row_stride():
