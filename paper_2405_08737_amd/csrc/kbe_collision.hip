@@ -24,6 +24,9 @@
 //     the streamed blocks prefetched into registers a term ahead.
 //   * task_generic (any N <= 16): vector ALU, one output per wave, one output element per lane,
 //     several terms per wave for small N summed across lanes at the end.
+#include <map>
+#include <mutex>
+#include <tuple>
 #include "kbe_dev.h"
 #include "kbe_internal.h"
 
@@ -1418,16 +1421,33 @@ static void plan_add(FusedPlan &pl, int cls, int nout, int tmax, int E, size_t &
   off += al256(sizeof(kbe_c128) * (size_t)pl.nchunk[k] * nout * E);
 }
 
-static FusedPlan plan_init(int N, int kind) {
+static FusedPlan plan_init(int N, int kind, int SC) {
   FusedPlan pl{};
-  pl.SC = chunk_terms(N, kind);
+  pl.SC = SC;
   pl.MO = outputs_per_wave(N, kind);
   return pl;
 }
 
-static size_t plan_forward(int N, int ntau, int n, int m0, int m1, unsigned flags, int kind,
-                           FusedPlan &pl) {
-  pl = plan_init(N, kind);
+// Small-block calls with few tasks (the early rows of a propagation) use shorter term chunks, so
+// that the work spreads over more workgroups and no single task sets the length of the call: the
+// chunk is halved, down to 32 terms, while the plan has fewer than MIN_TASKS tasks.  The choice
+// depends only on the call's shape, so the workspace query and the launch agree.
+constexpr int64_t MIN_TASKS = 1024;
+template <typename F>
+static size_t plan_sized(int N, int kind, FusedPlan &pl, F build) {
+  int sc = chunk_terms(N, kind);
+  size_t off = build(sc);
+  if (kind >= 1 && kind <= 8)
+    while (sc > 32 && pl.first[pl.ncls] < MIN_TASKS) {
+      sc /= 2;
+      off = build(sc);
+    }
+  return off;
+}
+
+static size_t plan_forward_sc(int N, int ntau, int n, int m0, int m1, unsigned flags, int kind,
+                              int SC, FusedPlan &pl) {
+  pl = plan_init(N, kind, SC);
   const int E = N * N, M = m1 - m0;
   size_t off = 0;
   const bool th = ntau > 0;
@@ -1460,9 +1480,16 @@ static size_t plan_forward(int N, int ntau, int n, int m0, int m1, unsigned flag
   return off;
 }
 
-static size_t plan_adjoint(int N, int ntau, int n, int m0, int m1, unsigned flags, int kind,
+static size_t plan_forward(int N, int ntau, int n, int m0, int m1, unsigned flags, int kind,
                            FusedPlan &pl) {
-  pl = plan_init(N, kind);
+  return plan_sized(N, kind, pl, [&](int sc) {
+    return plan_forward_sc(N, ntau, n, m0, m1, flags, kind, sc, pl);
+  });
+}
+
+static size_t plan_adjoint_sc(int N, int ntau, int n, int m0, int m1, unsigned flags, int kind,
+                              int SC, FusedPlan &pl) {
+  pl = plan_init(N, kind, SC);
   const int E = N * N;
   size_t off = 0;
   const bool th = ntau > 0, M = m1 > m0;
@@ -1499,6 +1526,13 @@ static size_t plan_adjoint(int N, int ntau, int n, int m0, int m1, unsigned flag
   return off + 256;
 }
 
+static size_t plan_adjoint(int N, int ntau, int n, int m0, int m1, unsigned flags, int kind,
+                           FusedPlan &pl) {
+  return plan_sized(N, kind, pl, [&](int sc) {
+    return plan_adjoint_sc(N, ntau, n, m0, m1, flags, kind, sc, pl);
+  });
+}
+
 size_t collision_ws_bytes(int N, int nt, int ntau, int n, int m0, int m1, unsigned flags) {
   (void)nt;
   FusedPlan pl;
@@ -1509,6 +1543,35 @@ size_t collision_vjp_ws_bytes(int N, int nt, int ntau, int n, int m0, int m1, un
   (void)nt;
   FusedPlan pl;
   return plan_adjoint(N, ntau, n, m0, m1, flags, path_kind(N, flags), pl);
+}
+
+// The most any whole-row call (m in [0, n]) at n < nt needs: what a propagation over nt points
+// reserves for its collision calls.
+// (one plan per row; memoised per shape, since the propagations query it at every call)
+static size_t ws_rows(int N, int nt, int ntau, unsigned flags, bool adjoint) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, int, unsigned, bool>, size_t> memo;
+  const auto key = std::make_tuple(N, nt, ntau, flags, adjoint);
+  {
+    std::lock_guard<std::mutex> g(mu);
+    const auto it = memo.find(key);
+    if (it != memo.end()) return it->second;
+  }
+  size_t b = 0;
+  for (int n = 0; n < nt; ++n) {
+    const size_t x = adjoint ? collision_vjp_ws_bytes(N, nt, ntau, n, 0, n + 1, flags)
+                             : collision_ws_bytes(N, nt, ntau, n, 0, n + 1, flags);
+    b = x > b ? x : b;
+  }
+  std::lock_guard<std::mutex> g(mu);
+  memo[key] = b;
+  return b;
+}
+size_t collision_ws_bytes_rows(int N, int nt, int ntau, unsigned flags) {
+  return ws_rows(N, nt, ntau, flags, false);
+}
+size_t collision_vjp_ws_bytes_rows(int N, int nt, int ntau, unsigned flags) {
+  return ws_rows(N, nt, ntau, flags, true);
 }
 
 // Resident workgroups of the persistent kernel on the current device (queried once per

@@ -54,6 +54,9 @@ hipError_t launch_collision_both(const Params &p, kbe_c128 *IRl, kbe_c128 *ILl, 
                                  kbe_c128 *Jtv, kbe_c128 *IRg, kbe_c128 *ILg, void *ws,
                                  hipStream_t st);
 size_t collision_vjp_ws_bytes(int N, int nt, int ntau, int n, int m0, int m1, unsigned flags);
+// the largest workspace of a whole-row call at any n < nt (what a propagation reserves)
+size_t collision_ws_bytes_rows(int N, int nt, int ntau, unsigned flags);
+size_t collision_vjp_ws_bytes_rows(int N, int nt, int ntau, unsigned flags);
 hipError_t launch_collision_vjp(const Params &p, unsigned flags, kbe_c128 *gmat,
                                 const kbe_sigma_row *gS, void *ws, hipStream_t st);
 

@@ -592,7 +592,7 @@ Layout layout(int N, int nt, int ntau, int64_t ldt, int K) {
   L.ILg = take(nt * E);
   L.base = take(ne * E);
   L.ynext = take(ne * E);
-  L.cws = take(collision_ws_bytes(N, nt, ntau, n, 0, n + 1, KBE_OUT_ALL | KBE_INT_BOTH));
+  L.cws = take(collision_ws_bytes_rows(N, nt, ntau, KBE_OUT_ALL | KBE_INT_BOTH));
   L.gkp = take((size_t)nt * ldt * E);
   L.grd = take(nt * E);
   L.gtv = take((size_t)nt * ntau * E);
@@ -616,8 +616,8 @@ Layout layout(int N, int nt, int ntau, int64_t ldt, int K) {
   L.gretG = take(nt * E);
   L.glesG = take(nt * E);
   L.gstvG = take(ntau * E);
-  size_t vw = collision_vjp_ws_bytes(N, nt, ntau, n, 0, n + 1, KBE_OUT_ALL);
-  const size_t vw2 = collision_vjp_ws_bytes(N, nt, ntau, n, 0, n + 1, FG);
+  size_t vw = collision_vjp_ws_bytes_rows(N, nt, ntau, KBE_OUT_ALL);
+  const size_t vw2 = collision_vjp_ws_bytes_rows(N, nt, ntau, FG | KBE_INT_GREXTRA);
   L.vws = take(vw > vw2 ? vw : vw2);
   L.sws = take(sigma_vjp_ws_bytes(N, n, ntau));
   L.total = o;
@@ -1302,7 +1302,7 @@ ALay alayout(int N, int nt, int ntau) {
   L.done = take(2 * sizeof(uint32_t));
   L.kbuf = take((size_t)nt * KSW * sizeof(int32_t));
   const int n = nt - 1;
-  L.cws = take(collision_ws_bytes(N, nt, ntau, n, 0, n + 1, KBE_OUT_ALL | KBE_INT_BOTH));
+  L.cws = take(collision_ws_bytes_rows(N, nt, ntau, KBE_OUT_ALL | KBE_INT_BOTH));
   L.total = o;
   return L;
 }
