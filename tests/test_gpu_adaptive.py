@@ -164,3 +164,28 @@ def test_adaptive_rejects_bad_controls(gpu):
     for bad in (dict(qmax=13), dict(kmax=1), dict(maxcor=0), dict(rtol=0.0), dict(h_first=-1.0)):
         with pytest.raises(kbe.KBEError, match="KBE_EINVAL"):
             run_gpu(kbe, P, 1.0, 0.7, capacity=16, t_end=0.5, **bad)
+
+
+def test_adaptive_converges_to_a_fine_fixed_grid(gpu):
+    """An interacting system (4-site chain, U = 1, pulse) without the oracle: the adaptive
+    densities at t_end approach those of the fixed-grid propagation (a separate propagator, on a
+    uniform grid of 1500 steps with sixth-order rules and five fixed-point iterations, whose own
+    error is far below the tolerances) as the tolerance tightens."""
+    kbe = gpu
+    N, U, A, T = 4, 1.0, 0.8, 3.0
+    h0 = synth.tight_binding(N)
+    _, rho = synth.free_thermal(h0, 2.0, 0)
+    nt = 1501
+    t = np.linspace(0.0, T, nt)
+    order = np.full(nt, 6, np.int32)
+    ref = kbe.Propagation(t, order, h0, ntau=0, rho0=rho, iters=5)
+    d_ref = ref.run(torch.full((N,), U, dtype=torch.float64, device="cuda:0"), A).cpu().numpy()[-1]
+    errs = []
+    for rtol in (1e-5, 1e-7, 1e-9):
+        g = kbe.propagate_adaptive(h0, U, A, T, rho0=rho, capacity=2048, rtol=rtol,
+                                   atol=rtol * 1e-3)
+        d = g["dens"].cpu().numpy()[-1]
+        errs.append(np.abs(d - d_ref).max())
+        _print("rtol %g: %d steps, |n(T) - n_ref(T)| = %.2e" % (rtol, len(g["t"]) - 1, errs[-1]))
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[0] < 1e-3 and errs[2] < 1e-7
