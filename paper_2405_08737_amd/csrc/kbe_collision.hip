@@ -1041,26 +1041,27 @@ __device__ __forceinline__ int grad_row_terms(const Params &p, int a, int j, Gra
   return nt;
 }
 
-// The greater form's extra terms (those grad_greater adds on the generic path), in two sets of
-// at most two terms, for grad_mfma16<1> and grad_mfma16<2>; X ids as above (0 Sigma^R(a), 1
-// gIR(a), 2 gIL(a)):
-//   set 1, kp[a][b] a > b:  w[a][b] gIL(a)^dag Sigma^R(b),   w[n][a] Sigma^R(a)^dag gIR(b)
-//          rdiag[a]      :  w[a][a] gIL(a)^dag Sigma^R(a),   w[n][a] Sigma^R(a)^dag gIR(a)
-//   set 2, kp[a][b] a > b: -w[n][b] gIR(a)^dag Sigma^R(b)
-template <int TS>
+// The greater form's extra terms (those grad_greater adds on the generic path), at most three
+// per block, for grad_mfma16<1> and grad_mfma8<1>; X ids as above (0 Sigma^R(a), 1 gIR(a),
+// 2 gIL(a)):
+//   kp[a][b] a > b:  w[a][b] gIL(a)^dag Sigma^R(b),  w[n][a] Sigma^R(a)^dag gIR(b),
+//                    -w[n][b] gIR(a)^dag Sigma^R(b)
+//   rdiag[a]      :  w[a][a] gIL(a)^dag Sigma^R(a),  w[n][a] Sigma^R(a)^dag gIR(a)
 __device__ __forceinline__ int grad_row_terms_gr(const Params &p, int a, int j, GradTerm &t0,
-                                                 GradTerm &t1, kbe_c128 *&dst) {
+                                                 GradTerm &t1, GradTerm &t2, kbe_c128 *&dst) {
   const int64_t E = bsz(p);
   const int n1 = p.n + 1;
   const bool ina = a >= p.m0 && a < p.m1;
   const int64_t wn = (int64_t)p.n * p.nt;
-  t0.xid = t1.xid = -1;
-  t0.Y = t1.Y = p.ret;
-  t0.c = t1.c = czero();
+  t0.xid = t1.xid = t2.xid = -1;
+  t0.Y = t1.Y = t2.Y = p.ret;
+  t0.c = t1.c = t2.c = czero();
   int nt = 0;
   auto push = [&](int xid, cd c, const kbe_c128 *Y) {
-    if (nt == 0) t0 = GradTerm{xid, c, Y};
-    else t1 = GradTerm{xid, c, Y};
+    const GradTerm g{xid, c, Y};
+    if (nt == 0) t0 = g;
+    else if (nt == 1) t1 = g;
+    else t2 = g;
     ++nt;
   };
   dst = p.gkp;
@@ -1069,29 +1070,24 @@ __device__ __forceinline__ int grad_row_terms_gr(const Params &p, int a, int j, 
     const bool inb = b >= p.m0 && b < p.m1;
     dst = p.gkp + ((int64_t)a * p.ldt + b) * E;
     if (a > b) {
-      if (TS == 1) {
-        if (p.fIL && ina) push(2, cd{p.w[(int64_t)a * p.nt + b], 0.0}, p.ret + b * E);
-        if (p.fIR && inb) push(0, cd{p.w[wn + a], 0.0}, p.gIR + (b - p.m0) * E);
-      } else if (p.fIR && ina) {
-        push(1, cd{-p.w[wn + b], 0.0}, p.ret + b * E);
-      }
+      if (p.fIL && ina) push(2, cd{p.w[(int64_t)a * p.nt + b], 0.0}, p.ret + b * E);
+      if (p.fIR && inb) push(0, cd{p.w[wn + a], 0.0}, p.gIR + (b - p.m0) * E);
+      if (p.fIR && ina) push(1, cd{-p.w[wn + b], 0.0}, p.ret + b * E);
     }
   } else if (j >= n1 + p.ntau) {
     dst = p.grdiag + a * E;
-    if (TS == 1) {
-      if (p.fIL && ina) push(2, cd{p.w[(int64_t)a * p.nt + a], 0.0}, p.ret + a * E);
-      if (p.fIR && ina) push(0, cd{p.w[wn + a], 0.0}, p.gIR + (a - p.m0) * E);
-    }
+    if (p.fIL && ina) push(2, cd{p.w[(int64_t)a * p.nt + a], 0.0}, p.ret + a * E);
+    if (p.fIR && ina) push(0, cd{p.w[wn + a], 0.0}, p.gIR + (a - p.m0) * E);
   }
   return nt;
 }
 
 // Per-block term record of a segment, built once per workgroup in LDS.
 struct GradRec {
-  const kbe_c128 *y0, *y1;  // Y of term 0 and term 1 (term 0's Y again when there is one term)
+  const kbe_c128 *y0, *y1, *y2;  // Y of terms 0..2 (term 0's Y again for absent terms)
   kbe_c128 *dst;
-  double c0r, c0i, c1r, c1i;  // scalars (term 1's are 0 when there is one term)
-  int x0, x1, nt;
+  double c0r, c0i, c1r, c1i, c2r, c2i;  // scalars (0 for absent terms)
+  int x0, x1, x2, nt;
   int acc;  // add the block's current value (accumulate mode, or a block an earlier pass wrote)
 };
 
@@ -1107,8 +1103,45 @@ __device__ __forceinline__ d4g mfma16f(double a, double b, d4g c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// TS = 0: the terms of both forms' common part (grad_row_terms); TS = 1, 2: the greater form's
-// extra terms (grad_row_terms_gr), run after TS = 0 and adding to what earlier passes wrote.
+// The record of block j0 + tid of row a.  TS = 0: the terms of both forms' common part
+// (grad_row_terms); TS = 1: the greater form's extra terms (grad_row_terms_gr), which add to what
+// the TS = 0 pass wrote (accumulate mode, or a block that pass reached).
+template <int TS>
+__device__ __forceinline__ void fill_grad_rec(const Params &p, int a, int j0, int len, int tid,
+                                              GradRec &g) {
+  GradTerm t0{-1, czero(), p.ret}, t1 = t0, t2 = t0;
+  kbe_c128 *d = p.gkp;
+  int nt = 0, acc = !p.overwrite;
+  if (tid < len) {
+    if constexpr (TS == 0) {
+      nt = grad_row_terms(p, a, j0 + tid, t0, t1, d);
+    } else {
+      nt = grad_row_terms_gr(p, a, j0 + tid, t0, t1, t2, d);
+      GradTerm u0, u1;
+      kbe_c128 *dd;
+      acc = acc || grad_row_terms(p, a, j0 + tid, u0, u1, dd) > 0;
+    }
+  }
+  g.y0 = t0.Y;
+  g.y1 = nt > 1 ? t1.Y : t0.Y;
+  g.y2 = nt > 2 ? t2.Y : t0.Y;
+  g.dst = d;
+  g.c0r = t0.c.re;
+  g.c0i = t0.c.im;
+  g.c1r = nt > 1 ? t1.c.re : 0.0;
+  g.c1i = nt > 1 ? t1.c.im : 0.0;
+  g.c2r = nt > 2 ? t2.c.re : 0.0;
+  g.c2i = nt > 2 ? t2.c.im : 0.0;
+  g.x0 = t0.xid < 0 ? 0 : t0.xid;
+  g.x1 = nt > 1 ? t1.xid : 0;
+  g.x2 = nt > 2 ? t2.xid : 0;
+  g.nt = nt;
+  g.acc = acc;
+}
+
+// TS = 0: the terms of both forms' common part; TS = 1: the greater form's extra terms, run
+// after TS = 0 and adding to what it wrote.  At most two terms per block for TS = 0, three for
+// TS = 1.
 template <int TS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 grad_mfma16(Params p, int row_len, int nseg) {
@@ -1134,46 +1167,19 @@ grad_mfma16(Params p, int row_len, int nseg) {
     xs[3][r * QLD + c] = (p.fITV && ina) ? ld(p.gItv + (a - p.m0) * E + tid) : czero();
   }
   const int j0 = seg * GSEG, len = (j0 + GSEG < row_len ? j0 + GSEG : row_len) - j0;
-  if (tid < GSEG) {
-    GradTerm t0{-1, czero(), p.ret}, t1 = t0;
-    kbe_c128 *d = p.gkp;
-    int nt = 0, acc = !p.overwrite;
-    if (tid < len) {
-      if constexpr (TS == 0) {
-        nt = grad_row_terms(p, a, j0 + tid, t0, t1, d);
-      } else {
-        nt = grad_row_terms_gr<TS>(p, a, j0 + tid, t0, t1, d);
-        GradTerm u0, u1;
-        kbe_c128 *dd;
-        int before = grad_row_terms(p, a, j0 + tid, u0, u1, dd);
-        if (TS == 2) before += grad_row_terms_gr<1>(p, a, j0 + tid, u0, u1, dd);
-        acc = acc || before > 0;
-      }
-    }
-    GradRec &g = rec[tid];
-    g.y0 = t0.Y;
-    g.y1 = nt > 1 ? t1.Y : t0.Y;
-    g.dst = d;
-    g.c0r = t0.c.re;
-    g.c0i = t0.c.im;
-    g.c1r = nt > 1 ? t1.c.re : 0.0;
-    g.c1i = nt > 1 ? t1.c.im : 0.0;
-    g.x0 = t0.xid < 0 ? 0 : t0.xid;
-    g.x1 = nt > 1 ? t1.xid : 0;
-    g.nt = nt;
-    g.acc = acc;
-  }
+  if (tid < GSEG) fill_grad_rec<TS>(p, a, j0, len, tid, rec[tid]);
   __syncthreads();
-  cd yn0[4], yn1[4];  // raw Y slabs of the block after the current one
+  constexpr int NTM = TS == 0 ? 2 : 3;  // terms per block, at most
+  cd yn[NTM][4];  // raw Y slabs of the block after the current one
   // Every record's Y pointers are valid (a block without terms points at Sigma^R(0)), so the
   // prefetch is unconditional; past the end of the segment it re-reads the last record.
   auto fetch = [&](int q) {
-    const kbe_c128 *Y0 = uniform_ptr(rec[q].y0), *Y1 = uniform_ptr(rec[q].y1);
+    const kbe_c128 *Y[3] = {uniform_ptr(rec[q].y0), uniform_ptr(rec[q].y1),
+                            uniform_ptr(rec[q].y2)};
 #pragma unroll
-    for (int kc = 0; kc < 4; ++kc) {
-      yn0[kc] = ldg(Y0 + (4 * kc + lk) * 16 + lc);
-      yn1[kc] = ldg(Y1 + (4 * kc + lk) * 16 + lc);
-    }
+    for (int kc = 0; kc < 4; ++kc)
+#pragma unroll
+      for (int tm = 0; tm < NTM; ++tm) yn[tm][kc] = ldg(Y[tm] + (4 * kc + lk) * 16 + lc);
   };
   // A block's result is held for one iteration and written one 16 x 4 slab per inner step of
   // the next block, so each wave's stores spread over its products instead of a burst.
@@ -1198,15 +1204,16 @@ grad_mfma16(Params p, int row_len, int nseg) {
   for (; q < len; q += 4) {
     const int cnt = __builtin_amdgcn_readfirstlane(rec[q].nt);
     kbe_c128 *const cdst = (kbe_c128 *)uniform_ptr(rec[q].dst);
-    const cd c0{rec[q].c0r, rec[q].c0i}, c1{rec[q].c1r, rec[q].c1i};
-    const cd *x0 = xs[__builtin_amdgcn_readfirstlane(rec[q].x0)];
-    const cd *x1 = xs[__builtin_amdgcn_readfirstlane(rec[q].x1)];
-    cd y0[4], y1[4];
+    const cd cs[3] = {{rec[q].c0r, rec[q].c0i}, {rec[q].c1r, rec[q].c1i},
+                      {rec[q].c2r, rec[q].c2i}};
+    const cd *xt[3] = {xs[__builtin_amdgcn_readfirstlane(rec[q].x0)],
+                       xs[__builtin_amdgcn_readfirstlane(rec[q].x1)],
+                       xs[__builtin_amdgcn_readfirstlane(rec[q].x2)]};
+    cd y[NTM][4];
 #pragma unroll
-    for (int kc = 0; kc < 4; ++kc) {
-      y0[kc] = c0 * yn0[kc];
-      y1[kc] = c1 * yn1[kc];
-    }
+    for (int kc = 0; kc < 4; ++kc)
+#pragma unroll
+      for (int tm = 0; tm < NTM; ++tm) y[tm][kc] = cs[tm] * yn[tm][kc];
     // issue the next block's loads before this block's products and stores
     fetch(q + 4 < len ? q + 4 : len - 1);
     if (cnt == 0) continue;
@@ -1219,14 +1226,14 @@ grad_mfma16(Params p, int row_len, int nseg) {
 #pragma unroll
     for (int kc = 0; kc < 4; ++kc) {
 #pragma unroll
-      for (int term = 0; term < 2; ++term) {
-        if (term == 1 && cnt < 2) break;  // wave-uniform
-        const cd *x = term == 0 ? x0 : x1;
-        const cd y = term == 0 ? y0[kc] : y1[kc];
+      for (int term = 0; term < NTM; ++term) {
+        if (term >= cnt) break;  // wave-uniform
+        const cd *x = xt[term];
+        const cd yv = y[term][kc];
         const cd u = x[(4 * kc + lk) * QLD + lc];
-        const double ys = y.im - y.re, yp = y.re + y.im;
+        const double ys = yv.im - yv.re, yp = yv.re + yv.im;
         __builtin_amdgcn_sched_barrier(0);
-        k1 = mfma16f(u.re - u.im, y.re, k1);
+        k1 = mfma16f(u.re - u.im, yv.re, k1);
         k2 = mfma16f(u.re, ys, k2);
         k3 = mfma16f(u.im, yp, k3);
         __builtin_amdgcn_sched_barrier(0);
@@ -1280,35 +1287,7 @@ __global__ void __launch_bounds__(256) grad_mfma8(Params p, int row_len, int nse
     xs[x][r * XLD8 + c] = (present && r < N && c < N) ? ld(X + r * N + c) : czero();
   }
   const int j0 = seg * GSEG8, len = (j0 + GSEG8 < row_len ? j0 + GSEG8 : row_len) - j0;
-  if (tid < GSEG8) {
-    GradTerm t0{-1, czero(), p.ret}, t1 = t0;
-    kbe_c128 *d = p.gkp;
-    int nt = 0, acc = !p.overwrite;
-    if (tid < len) {
-      if constexpr (TS == 0) {
-        nt = grad_row_terms(p, a, j0 + tid, t0, t1, d);
-      } else {
-        nt = grad_row_terms_gr<TS>(p, a, j0 + tid, t0, t1, d);
-        GradTerm u0, u1;
-        kbe_c128 *dd;
-        int before = grad_row_terms(p, a, j0 + tid, u0, u1, dd);
-        if (TS == 2) before += grad_row_terms_gr<1>(p, a, j0 + tid, u0, u1, dd);
-        acc = acc || before > 0;
-      }
-    }
-    GradRec &g = rec[tid];
-    g.y0 = t0.Y;
-    g.y1 = nt > 1 ? t1.Y : t0.Y;
-    g.dst = d;
-    g.c0r = t0.c.re;
-    g.c0i = t0.c.im;
-    g.c1r = nt > 1 ? t1.c.re : 0.0;
-    g.c1i = nt > 1 ? t1.c.im : 0.0;
-    g.x0 = t0.xid < 0 ? 0 : t0.xid;
-    g.x1 = nt > 1 ? t1.xid : 0;
-    g.nt = nt;
-    g.acc = acc;
-  }
+  if (tid < GSEG8) fill_grad_rec<TS>(p, a, j0, len, tid, rec[tid]);
   __syncthreads();
   const int lj = lane & 3, lb = (lane >> 2) & 3, lk = lane >> 4;
   const int ti = lb >> 1, tj = lb & 1;
@@ -1319,27 +1298,33 @@ __global__ void __launch_bounds__(256) grad_mfma8(Params p, int row_len, int nse
   // D element: row 4 ti + lk, column 4 tj + lj
   const bool dv = 4 * ti + lk < N && bc < N;
   const int dof = dv ? (4 * ti + lk) * N + bc : 0;
-  cd yn[2][2];  // raw Y of [term][kc] of the block after the current one
+  constexpr int NTM = TS == 0 ? 2 : 3;  // terms per block, at most
+  cd yn[NTM][2];  // raw Y of [term][kc] of the block after the current one
   auto fetch = [&](int q) {
-    const kbe_c128 *Y0 = uniform_ptr(rec[q].y0), *Y1 = uniform_ptr(rec[q].y1);
-    yn[0][0] = ldg(Y0 + bo0);
-    yn[0][1] = ldg(Y0 + bo1);
-    yn[1][0] = ldg(Y1 + bo0);
-    yn[1][1] = ldg(Y1 + bo1);
+    const kbe_c128 *Y[3] = {uniform_ptr(rec[q].y0), uniform_ptr(rec[q].y1),
+                            uniform_ptr(rec[q].y2)};
+#pragma unroll
+    for (int tm = 0; tm < NTM; ++tm) {
+      yn[tm][0] = ldg(Y[tm] + bo0);
+      yn[tm][1] = ldg(Y[tm] + bo1);
+    }
   };
   int q = __builtin_amdgcn_readfirstlane(wave);
   if (q < len) fetch(q);
   for (; q < len; q += 4) {
     const int cnt = __builtin_amdgcn_readfirstlane(rec[q].nt);
     kbe_c128 *const cdst = (kbe_c128 *)uniform_ptr(rec[q].dst);
-    const cd c0{rec[q].c0r, rec[q].c0i}, c1{rec[q].c1r, rec[q].c1i};
-    const cd *x0 = xs[__builtin_amdgcn_readfirstlane(rec[q].x0)];
-    const cd *x1 = xs[__builtin_amdgcn_readfirstlane(rec[q].x1)];
-    cd y[2][2];
-    y[0][0] = c0 * (bv0 ? yn[0][0] : czero());
-    y[0][1] = c0 * (bv1 ? yn[0][1] : czero());
-    y[1][0] = c1 * (bv0 ? yn[1][0] : czero());
-    y[1][1] = c1 * (bv1 ? yn[1][1] : czero());
+    const cd cs[3] = {{rec[q].c0r, rec[q].c0i}, {rec[q].c1r, rec[q].c1i},
+                      {rec[q].c2r, rec[q].c2i}};
+    const cd *xt[3] = {xs[__builtin_amdgcn_readfirstlane(rec[q].x0)],
+                       xs[__builtin_amdgcn_readfirstlane(rec[q].x1)],
+                       xs[__builtin_amdgcn_readfirstlane(rec[q].x2)]};
+    cd y[NTM][2];
+#pragma unroll
+    for (int tm = 0; tm < NTM; ++tm) {
+      y[tm][0] = cs[tm] * (bv0 ? yn[tm][0] : czero());
+      y[tm][1] = cs[tm] * (bv1 ? yn[tm][1] : czero());
+    }
     fetch(q + 4 < len ? q + 4 : len - 1);  // next block's loads before this block's work
     if (cnt == 0) continue;
     __builtin_amdgcn_sched_barrier(0);
@@ -1347,9 +1332,9 @@ __global__ void __launch_bounds__(256) grad_mfma8(Params p, int row_len, int nse
     //   K1 += (xr - xi) yr,  K2 += xr (yi - yr),  K3 += xi (yr + yi);  Re = K1 + K3, Im = K1 + K2
     double k1 = 0.0, k2 = 0.0, k3 = 0.0;
 #pragma unroll
-    for (int term = 0; term < 2; ++term) {
-      if (term == 1 && cnt < 2) break;  // wave-uniform
-      const cd *x = term == 0 ? x0 : x1;
+    for (int term = 0; term < NTM; ++term) {
+      if (term >= cnt) break;  // wave-uniform
+      const cd *x = xt[term];
 #pragma unroll
       for (int kc = 0; kc < 2; ++kc) {
         const cd u = x[(4 * kc + lk) * XLD8 + 4 * ti + lj];
@@ -1744,24 +1729,18 @@ hipError_t launch_collision_vjp(const Params &p, unsigned flags, kbe_c128 *gmat,
     if (!extra)
       hipLaunchKernelGGL(grad_mfma16<0>, dim3((unsigned)(8 * ((tasks + 7) / 8))), dim3(256), 0,
                          st, p, row_len, nseg);
-    if (flags & KBE_GREATER) {  // the greater form's extra terms, in two more passes
+    if (flags & KBE_GREATER)  // the greater form's extra terms, in one more pass
       hipLaunchKernelGGL(grad_mfma16<1>, dim3((unsigned)(8 * ((tasks + 7) / 8))), dim3(256), 0,
                          st, p, row_len, nseg);
-      hipLaunchKernelGGL(grad_mfma16<2>, dim3((unsigned)(8 * ((tasks + 7) / 8))), dim3(256), 0,
-                         st, p, row_len, nseg);
-    }
   } else if (kind >= 5 && kind <= 8) {
     const int nseg = (row_len + GSEG8 - 1) / GSEG8;
     const int64_t tasks = (int64_t)(p.n + 1) * nseg;
     if (!extra)
       hipLaunchKernelGGL(grad_mfma8<0>, dim3((unsigned)(8 * ((tasks + 7) / 8))), dim3(256), 0,
                          st, p, row_len, nseg);
-    if (flags & KBE_GREATER) {  // the greater form's extra terms, in two more passes
+    if (flags & KBE_GREATER)  // the greater form's extra terms, in one more pass
       hipLaunchKernelGGL(grad_mfma8<1>, dim3((unsigned)(8 * ((tasks + 7) / 8))), dim3(256), 0,
                          st, p, row_len, nseg);
-      hipLaunchKernelGGL(grad_mfma8<2>, dim3((unsigned)(8 * ((tasks + 7) / 8))), dim3(256), 0,
-                         st, p, row_len, nseg);
-    }
   } else if (!extra) {
     const int64_t th = nblk * p.N * p.N;
     hipLaunchKernelGGL(grad_generic, dim3((unsigned)((th + 255) / 256)), dim3(256), 0, st, p, nblk);
