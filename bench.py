@@ -483,8 +483,9 @@ def propagation(kbe, torch, dev):
 
 def adaptive(kbe, torch, dev):
     """The adaptive propagation (kbe_propagate_adaptive): the 8-site chain at U = 1, beta = 10,
-    pulse on site 0, variable step and order at rtol 1e-8, atol 1e-10, with the thermal branch
-    (256 tau points) to t = 30 and without it to t = 40.  Each case: one warm-up run to t = 0.5,
+    pulse on site 0, variable step and order at rtol 1e-8, atol 1e-10, to t = 40 with the thermal
+    branch (256 tau points, from the interacting equilibrium of kbe_equilibrium, whose solve is
+    timed too) and without it.  Each case: one warm-up run to t = 0.5,
     then the whole run timed by the host clock (inputs resident, the controller synchronising at
     every fixed-point iteration), the step and order statistics, the particle-number drift, and
     the first `prefix` steps run again on their own (to t = t_prefix) for the oracle comparison.
@@ -496,6 +497,18 @@ def adaptive(kbe, torch, dev):
     out, replays = [], []
     for ntau, t_end, prefix in A["cases"]:
         mat, rho = synth.free_thermal(h0, A["beta"], ntau)
+        eqr = None
+        if ntau:
+            # the interacting equilibrium (kbe_equilibrium), timed after a first solve
+            kbe.equilibrium(h0, A["U"], A["mu"], A["beta"], ntau, device=dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            mat, info = kbe.equilibrium(h0, A["U"], A["mu"], A["beta"], ntau, device=dev)
+            torch.cuda.synchronize()
+            we = time.perf_counter() - t0
+            eqr = {"iterations": info["iterations"], "change": info["change"], "wall_s": we,
+                   "ms_per_iteration": 1e3 * we / info["iterations"],
+                   "density_0": float(-mat[-1, 0, 0].real)}
 
         def run(te, cap):
             return kbe.propagate_adaptive(
@@ -531,9 +544,12 @@ def adaptive(kbe, torch, dev):
             "particle_number": float(tr[0]),
             "particle_number_drift": float(np.abs(tr - tr[0]).max()),
             "n0_final": float(d[-1, 0]), "workspace_gb": g["workspace_bytes"] / 1e9,
+            "initial_state": "interacting equilibrium" if ntau else "free thermal density matrix",
+            **({"equilibrium": eqr} if eqr else {}),
             "prefix": {"steps": prefix, "t": tp, "wall_s": wall_p,
                        "ms_per_step": 1e3 * wall_p / prefix, "same_decisions": same}})
-        replays.append({"ntau": ntau, "mat": mat, "rho": rho, "replay": g["replay"][: prefix + 1],
+        replays.append({"ntau": ntau, "mat": mat.cpu().numpy() if ntau else None, "rho": rho,
+                        "replay": g["replay"][: prefix + 1],
                         "dens": d[: prefix + 1],
                         "kp": g["G"].kp[: prefix + 1, : prefix + 1].cpu().numpy(),
                         "gpu_ms_per_step": 1e3 * wall_p / prefix})
@@ -543,8 +559,8 @@ def adaptive(kbe, torch, dev):
                          f"A={A['pulse_amp']} on site 0 at t={A['pulse_t0']} width "
                          f"{A['pulse_sigma']}; rtol {A['rtol']}, atol {A['atol']}, Adams orders "
                          f"1..{A['qmax']}, history orders 1..{A['kmax']}, at most {A['maxcor']} "
-                         f"fixed-point corrections; thermal branch (256 tau points) to t=30, "
-                         f"no thermal branch to t=40",
+                         f"fixed-point corrections; to t=40 with the thermal branch (256 tau "
+                         f"points, interacting equilibrium at mu={A['mu']}) and without it",
              "cases": out}, replays)
 
 
@@ -557,11 +573,20 @@ def adaptive_oracle(replays):
     from oracle import propagate as oprop
     A = synth.ADAPTIVE
     h0 = synth.tight_binding(A["N"])
+    from oracle import equilibrium as oeq
     res = []
     for r in replays:
         ntau = r["ntau"]
+        eqr, mat = {}, None
+        if ntau:
+            # the oracle's own equilibrium (no input of the oracle comes from the GPU)
+            t0 = time.perf_counter()
+            mat, info = oeq.solve(h0, A["U"], A["mu"], A["beta"], ntau)
+            eqr = {"equilibrium_oracle_s": time.perf_counter() - t0,
+                   "equilibrium_oracle_iterations": info["iterations"],
+                   "equilibrium_max_abs_diff": float(np.abs(mat - r["mat"]).max())}
         P = oprop.Problem(t=np.zeros(1), order=np.zeros(1, np.int32), h0=h0, ntau=ntau,
-                          beta=A["beta"], mat=r["mat"], rho0=None if ntau else r["rho"],
+                          beta=A["beta"], mat=mat, rho0=None if ntau else r["rho"],
                           pulse_t0=A["pulse_t0"], pulse_sigma=A["pulse_sigma"])
         ctl = oad.Controls(t_end=r["replay"][-1]["t"], rtol=A["rtol"], atol=A["atol"],
                            h0=A["h_first"], qmax=A["qmax"], kmax=A["kmax"], maxcor=A["maxcor"],
@@ -576,7 +601,8 @@ def adaptive_oracle(replays):
                     "oracle_ms_per_step": 1e3 * dt / steps,
                     "gpu_ms_per_step": r["gpu_ms_per_step"],
                     "dens_max_abs_diff": float(np.abs(dens - r["dens"]).max()),
-                    "kp_rel_diff": float(np.linalg.norm(kp - r["kp"]) / np.linalg.norm(kp))})
+                    "kp_rel_diff": float(np.linalg.norm(kp - r["kp"]) / np.linalg.norm(kp)),
+                    **eqr})
     return res
 
 

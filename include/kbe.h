@@ -80,7 +80,9 @@ typedef enum {
   KBE_EHIP = 4,    /* a HIP runtime call or kernel launch failed */
   KBE_ENOTSUP = 5, /* valid request this build does not support */
   KBE_ESTEP = 6    /* the adaptive controller could not reach t_end (step size underflow or the
-                      grid capacity exhausted); the trace holds the steps accepted until then */
+                      grid capacity exhausted); the trace holds the steps accepted until then */,
+  KBE_ECONV = 7    /* kbe_equilibrium did not converge within its iteration limit (or the
+                      iteration diverged); the output holds the last iterate */
 } kbe_status;
 
 #define KBE_NMAX 16 /* largest orbital count N */
@@ -639,6 +641,53 @@ size_t kbe_propagate_adaptive_workspace(int32_t N, int32_t capacity, int32_t nta
 kbe_status kbe_propagate_adaptive(const kbe_prop *P, const kbe_adapt_ctl *C, const kbe_wts *W,
                                   const kbe_green *G, double *dens, kbe_adapt_trace *trace,
                                   void *ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * kbe_equilibrium — an interacting equilibrium initial state G^M: the
+ * Matsubara Dyson equation of the local-U second-Born approximation (a project
+ * addition: the paper takes G^M as given, Sec. "Kadanoff Baym Equations").
+ *
+ * In equilibrium Eq. KBE3 at t = 0, with the boundary conditions of Eq. BC
+ * (G^](0,tau) = i G^M(-tau), Sigma^](0,tau) = i Sigma^M(-tau)), becomes
+ * -dG^M/dtau = eps G^M + int_0^beta Sigma^M(u) G^M(tau - u) du, antiperiodic in
+ * tau; its integral form G^M = G0 + G0 * Sigma^M * G^M is solved by mixed
+ * fixed-point iteration from the free function of h0 - mu:
+ *   eps = h0 + diag(u_i n_i) - mu with n_i = -G^M_ii(beta-) (the Hartree term
+ *   of Eq. eps), G0(tau) = -exp(-eps tau)(1 - f(eps)) (eigendecomposition of
+ *   eps), Sigma^M_ij(tau) = u_i u_j G^M_ij(tau)^2 G^M_ji(beta - tau) (Eq. SE at
+ *   t = 0), Gn = G0 + G0 * (Sigma^M * G^M), G^M <- (1 - mix) G^M + mix Gn,
+ * until the largest |Gn - G^M| is below tol.  Each * is the integral over
+ * [0, beta] split at u = tau_j: wtau_fwd[j][l] A(tau_{j-l}) B(tau_l) summed over
+ * l <= j, minus wtau_fwd[J-j][J-l] A(tau_{J+j-l}) B(tau_l) summed over l >= j
+ * (the rule over [tau_j, beta] by reflection, the part above tau_j continued
+ * antiperiodically).  A propagation started from the result is stationary up to
+ * its time-stepping error, which the free G^M of an interacting system is not.
+ *
+ * Arguments: N orbitals (1..KBE_NMAX); ntau >= 2 points tau_j = j beta /
+ * (ntau - 1) (tau_0 = 0+, tau_J = beta-), beta > 0; wtau_fwd device
+ * [ntau][ntau] from kbe_weights / kbe_weights_dev for this tau grid; h0 device
+ * [N][N] real symmetric (its symmetric part is used); u device [N]; C: mu, mix
+ * in (0, 1], tol > 0, maxit >= 1 (in), iterations and change (out: the
+ * iterations run and the last largest change); mat device [ntau][N][N]
+ * (written: G^M, real); ws: kbe_equilibrium_workspace(N, ntau) bytes.  The
+ * call synchronises the stream once per iteration (to read the change).
+ * Errors: KBE_EINVAL (NULL pointers, N, ntau, beta or controls out of range),
+ * KBE_ENOMEM (workspace), KBE_EHIP, KBE_ECONV (change still >= tol after maxit
+ * iterations, or not finite: mat holds the last iterate).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  double mu;          /* chemical potential */
+  double mix;         /* weight of the new iterate, 0 < mix <= 1 */
+  double tol;         /* convergence: largest change of an element below tol, > 0 */
+  int32_t maxit;      /* iteration limit, >= 1 */
+  int32_t iterations; /* out: iterations run */
+  double change;      /* out: largest |Gn - G^M| of the last iteration */
+} kbe_eq_ctl;
+
+size_t kbe_equilibrium_workspace(int32_t N, int32_t ntau);
+kbe_status kbe_equilibrium(int32_t N, int32_t ntau, double beta, const double *wtau_fwd,
+                           const double *h0, const double *u, kbe_eq_ctl *C, kbe_c128 *mat,
+                           void *ws, size_t ws_bytes, void *stream);
 
 /* Human-readable name of a status code (static string). */
 const char *kbe_status_string(kbe_status s);

@@ -42,6 +42,7 @@ class KBEError(RuntimeError):
 
 
 KBE_ESTEP = 6
+KBE_ECONV = 7
 
 
 class _Prop(ctypes.Structure):
@@ -61,6 +62,12 @@ class _AdaptTrace(ctypes.Structure):
     _fields_ = [("t", ctypes.c_void_p), ("q", ctypes.c_void_p), ("m", ctypes.c_void_p),
                 ("ks", ctypes.c_void_p), ("err", ctypes.c_void_p), ("nt", ctypes.c_int32),
                 ("rejected", ctypes.c_int32)]
+
+
+class _EqCtl(ctypes.Structure):
+    _fields_ = [("mu", ctypes.c_double), ("mix", ctypes.c_double), ("tol", ctypes.c_double),
+                ("maxit", ctypes.c_int32), ("iterations", ctypes.c_int32),
+                ("change", ctypes.c_double)]
 
 
 class _Green(ctypes.Structure):
@@ -106,6 +113,7 @@ EXPORTS = ("kbe_weights_workspace", "kbe_weights", "kbe_sigma_2b", "kbe_collisio
            "kbe_weights_dev_workspace", "kbe_weights_dev", "kbe_step_weights",
            "kbe_propagate_workspace", "kbe_propagate", "kbe_propagate_vjp",
            "kbe_propagate_adaptive_workspace", "kbe_propagate_adaptive",
+           "kbe_equilibrium_workspace", "kbe_equilibrium",
            "kbe_status_string",
            "kbe_last_error", "kbe_version")
 
@@ -150,6 +158,9 @@ def lib():
             "kbe_propagate_adaptive_workspace": (SZ, [I32, I32, I32]),
             "kbe_propagate_adaptive": (I32, [ctypes.POINTER(_Prop), ctypes.POINTER(_AdaptCtl), W,
                                              G, P, ctypes.POINTER(_AdaptTrace), P, SZ, P]),
+            "kbe_equilibrium_workspace": (SZ, [I32, I32]),
+            "kbe_equilibrium": (I32, [I32, I32, ctypes.c_double, P, P, P,
+                                      ctypes.POINTER(_EqCtl), P, P, SZ, P]),
             "kbe_status_string": (ctypes.c_char_p, [I32]),
             "kbe_last_error": (ctypes.c_char_p, []),
             "kbe_version": (I32, []),
@@ -177,6 +188,15 @@ def _ptr(x: Optional[torch.Tensor]):
 
 def _stream(device) -> int:
     return torch.cuda.current_stream(device).cuda_stream
+
+
+def _as_dev(x, dtype, device) -> torch.Tensor:
+    """A contiguous device copy of x (a tensor on any device, or array-like)."""
+    if isinstance(x, torch.Tensor):
+        return x.to(device=device, dtype=dtype).contiguous()
+    import numpy as np
+    return torch.tensor(np.asarray(x, {torch.complex128: np.complex128,
+                                       torch.float64: np.float64}[dtype]), device=device)
 
 
 def _ws(nbytes: int, device) -> torch.Tensor:
@@ -662,7 +682,7 @@ class Propagation:
         self.lam = step_weights(self.t, self.order)
         z = lambda *sh: torch.zeros(sh, dtype=torch.complex128, device=dev)
         self.G = Green(z(nt, nt, N, N), z(nt, N, N), z(nt, ntau, N, N) if ntau else None,
-                       torch.tensor(np.asarray(mat, np.complex128), device=dev) if ntau else None)
+                       _as_dev(mat, torch.complex128, dev) if ntau else None)
         if not ntau:
             self.G.kp[0, 0] = 1j * torch.tensor(np.asarray(rho0, np.complex128), device=dev)
         self.dens = torch.empty((nt, N), dtype=torch.float64, device=dev)
@@ -714,6 +734,36 @@ class KBEPropagate(torch.autograd.Function):
         return None, gu, ga
 
 
+def equilibrium(h0, u, mu, beta, ntau, *, tau_order=5, wtau_fwd=None, mix=0.5, tol=1e-13,
+                maxit=1000, device="cuda:0"):
+    """kbe_equilibrium: the interacting equilibrium G^M [ntau, N, N] (complex128, real valued) of
+    the local-U second-Born approximation at inverse temperature beta and chemical potential mu,
+    and {"iterations", "change"}.  wtau_fwd: the tau rule (computed here when None).  A run that
+    does not converge raises KBEError with (G^M, info) of the last iterate in `partial`."""
+    import numpy as np
+    dev = torch.device(device)
+    h0 = torch.as_tensor(np.ascontiguousarray(h0, np.float64), device=dev)
+    N = h0.shape[0]
+    ud = torch.as_tensor(np.broadcast_to(np.asarray(u, np.float64), (N,)).copy(), device=dev)
+    if wtau_fwd is None:
+        wtau_fwd = weights_dev(torch.zeros(1, dtype=torch.float64, device=dev),
+                               torch.ones(1, dtype=torch.int32, device=dev), ntau, beta,
+                               tau_order).wtau_fwd
+    mat = torch.empty((ntau, N, N), dtype=torch.complex128, device=dev)
+    C = _EqCtl(float(mu), float(mix), float(tol), int(maxit), 0, 0.0)
+    L = lib()
+    nb = L.kbe_equilibrium_workspace(N, ntau)
+    ws = _ws(nb, dev)
+    st = L.kbe_equilibrium(N, ntau, float(beta), _ptr(wtau_fwd), _ptr(h0), _ptr(ud),
+                           ctypes.byref(C), _ptr(mat), _ptr(ws), nb, _stream(dev))
+    info = {"iterations": C.iterations, "change": C.change}
+    if st == KBE_ECONV:
+        raise KBEError(f"kbe_equilibrium: {L.kbe_status_string(st).decode()}: "
+                       f"{L.kbe_last_error().decode()}", st, (mat, info))
+    _check(st, "kbe_equilibrium")
+    return mat, info
+
+
 KS_STRIDE = 14  # history orders recorded per step in the adaptive trace
 
 
@@ -737,7 +787,7 @@ def propagate_adaptive(h0, u, pulse_amp, t_end, *, ntau=0, beta=1.0, tau_order=5
     z = lambda *sh: torch.zeros(sh, dtype=torch.complex128, device=dev)
     G = Green(z(capacity, capacity, N, N), z(capacity, N, N),
               z(capacity, ntau, N, N) if ntau else None,
-              torch.tensor(np.asarray(mat, np.complex128), device=dev) if ntau else None)
+              _as_dev(mat, torch.complex128, dev) if ntau else None)
     if not ntau:
         G.kp[0, 0] = 1j * torch.tensor(np.asarray(rho0, np.complex128), device=dev)
     dens = torch.zeros((capacity, N), dtype=torch.float64, device=dev)

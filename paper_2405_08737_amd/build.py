@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(HERE, "_build")
 SO = os.path.join(HERE, "libkbe.so")
 SOURCES = ["kbe_capi.hip", "kbe_weights.hip", "kbe_sigma.hip", "kbe_gf2.hip", "kbe_collision.hip",
-           "kbe_batch.hip", "kbe_prop.hip", "kbe_ceilings.hip"]
+           "kbe_batch.hip", "kbe_prop.hip", "kbe_equilibrium.hip", "kbe_ceilings.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -119,6 +119,7 @@ const char *kbe_status_string(kbe_status s) {
     case KBE_EHIP: return "KBE_EHIP: HIP runtime error";
     case KBE_ENOTSUP: return "KBE_ENOTSUP: not supported";
     case KBE_ESTEP: return "KBE_ESTEP: adaptive controller stopped before t_end";
+    case KBE_ECONV: return "KBE_ECONV: equilibrium iteration did not converge";
   }
   return "unknown kbe_status";
 }
@@ -478,6 +479,42 @@ kbe_status kbe_propagate_adaptive(const kbe_prop *P, const kbe_adapt_ctl *C, con
   if (stalled == 2)
     return fail(KBE_ESTEP, "capacity of %d points exhausted at t = %.17g < t_end = %g", G->nt,
                 trace->t[trace->nt - 1], C->t_end);
+  return s;
+}
+
+// ---------------------------------------------------------------------------------------
+// Interacting equilibrium initial state.
+// ---------------------------------------------------------------------------------------
+size_t kbe_equilibrium_workspace(int32_t N, int32_t ntau) {
+  if (N < 1 || N > KBE_NMAX || ntau < 2) return 0;
+  return kbe::equilibrium_ws_bytes(N, ntau);
+}
+
+kbe_status kbe_equilibrium(int32_t N, int32_t ntau, double beta, const double *wtau_fwd,
+                           const double *h0, const double *u, kbe_eq_ctl *C, kbe_c128 *mat,
+                           void *ws, size_t ws_bytes, void *stream) {
+  if (N < 1 || N > KBE_NMAX) return fail(KBE_EINVAL, "N = %d outside 1..%d", N, KBE_NMAX);
+  if (ntau < 2) return fail(KBE_EINVAL, "ntau = %d < 2", ntau);
+  if (!(beta > 0.0) || !std::isfinite(beta)) return fail(KBE_EINVAL, "beta = %g must be > 0", beta);
+  if (!wtau_fwd || !h0 || !u || !C || !mat)
+    return fail(KBE_EINVAL, "wtau_fwd, h0, u, C or mat is NULL");
+  if (!std::isfinite(C->mu)) return fail(KBE_EINVAL, "mu = %g is not finite", C->mu);
+  if (!(C->mix > 0.0 && C->mix <= 1.0)) return fail(KBE_EINVAL, "mix = %g outside (0, 1]", C->mix);
+  if (!(C->tol > 0.0)) return fail(KBE_EINVAL, "tol = %g must be > 0", C->tol);
+  if (C->maxit < 1) return fail(KBE_EINVAL, "maxit = %d < 1", C->maxit);
+  const size_t need = kbe::equilibrium_ws_bytes(N, ntau);
+  if (!ws || ws_bytes < need) return fail(KBE_ENOMEM, "workspace %zu bytes < %zu", ws_bytes, need);
+  int it = 0;
+  double d = 0.0;
+  kbe_status s = hip_status(kbe::launch_equilibrium(N, ntau, beta, wtau_fwd, h0, u, C->mu, C->mix,
+                                                    C->tol, C->maxit, mat, ws,
+                                                    (hipStream_t)stream, &it, &d),
+                            "kbe_equilibrium");
+  C->iterations = it;
+  C->change = d;
+  if (s != KBE_OK) return s;
+  if (!(d < C->tol))
+    return fail(KBE_ECONV, "largest change %.3e >= tol = %.3e after %d iterations", d, C->tol, it);
   return s;
 }
 

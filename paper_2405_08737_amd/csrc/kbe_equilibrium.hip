@@ -1,0 +1,319 @@
+// Interacting equilibrium initial state: the Matsubara Dyson equation of the local-U second-Born
+// approximation on the uniform tau grid tau_j = j beta / J (ntau = J + 1 points, tau_0 = 0+,
+// tau_J = beta-).
+//
+// The propagations take G^M as their initial condition (Sec. "Kadanoff Baym Equations"); a
+// G^M that is an equilibrium of the interacting system is what makes the unperturbed
+// propagation stationary.  In equilibrium Eq. KBE3 at t = 0, with the boundary conditions of
+// Eq. BC, reduces to  -dG^M/dtau = eps G^M + int_0^beta Sigma^M(u) G^M(tau - u) du
+// (antiperiodic in tau), whose integral form is the Dyson equation G^M = G0 + G0 * Sigma^M * G^M
+// with G0 the free Matsubara function of eps.  Per iteration:
+//   eps   = h0 + diag(u_i n_i) - mu, n_i = -G^M_ii(beta-)       (Hartree term of Eq. eps)
+//   G0    = -V exp(-e tau) (1 - f(e)) V^T                        (eigendecomposition of eps)
+//   S     = Sigma^M_ij(tau) = u_i u_j G_ij(tau)^2 G_ji(beta - tau)  (Eq. SE at t = 0)
+//   X     = S * G,  Gn = G0 + G0 * X,  G <- (1 - mix) G + mix Gn
+// where (A * B)(tau_j) = sum_{l<=j} wf[j][l] A(tau_{j-l}) B(tau_l)
+//                      - sum_{l>=j} wb[j][l] A(tau_{J+j-l}) B(tau_l),
+// the integral split at u = tau_j (where A(tau_j - u) jumps), the part above it continued
+// antiperiodically, wf the forward tau rule of the propagation and wb[j][l] = wf[J-j][J-l] its
+// reflection, the rule over [tau_j, beta] on the uniform grid.
+//
+// G^M is real for the real symmetric h0 of the propagations, so the iteration runs in real FP64
+// and writes the complex output once at the end.  Kernels (one launch each per iteration):
+//   eq_eig    one block: parallel (round-robin) Jacobi on eps, N/2 disjoint rotations per round
+//   eq_free   a block per tau point: G0 from (e, V)
+//   eq_sigma  elementwise
+//   eq_conv   a block per tau point, the l-sum split over slices of the block, LDS reduction;
+//             the second convolution also forms Gn, mixes in place and reduces the change
+// The host reads the change (8 bytes) once per iteration to decide convergence.
+#include "kbe_internal.h"
+
+#include <cmath>
+#include <cstring>
+
+namespace kbe {
+namespace {
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+constexpr int EQ_T = 256;          // threads per block (>= KBE_NMAX^2)
+constexpr int EQ_SWEEPS = 40;      // Jacobi sweep limit (5-6 sweeps for N <= 16 in practice)
+static_assert(KBE_NMAX * KBE_NMAX <= EQ_T, "one thread per matrix element");
+
+__device__ __forceinline__ size_t el(int j, int a, int b, int N) {
+  return ((size_t)j * N + a) * N + b;
+}
+
+// Eigendecomposition of eps (hartree != 0: with the Hartree shift of G[J]; else of h0 - mu).
+// Round-robin ordering: in round r player r pairs with M-1 and (r+k) mod (M-1) with
+// (r-k) mod (M-1), k = 1..M/2-1 (M = N rounded up to even; a pair with the dummy player N is
+// idle).  The rotation of pair (p < q) zeroes A[p][q]: theta = (A_qq - A_pp) / (2 A_pq),
+// t = sign(theta) / (|theta| + sqrt(theta^2 + 1)), c = 1 / sqrt(t^2 + 1), s = t c, and with
+// J_pp = J_qq = c, J_pq = s, J_qp = -s the update is A <- J^T A J, V <- V J.  The rotations of
+// one round act on disjoint planes, so they are applied together.  Also clears the change
+// accumulator of the iteration.
+__global__ void __launch_bounds__(EQ_T) eq_eig(const double *h0, const double *u, double mu,
+                                               const double *G, int J, int N, int hartree,
+                                               double *e_out, double *V_out,
+                                               unsigned long long *chg) {
+  __shared__ double A[2][KBE_NMAX][KBE_NMAX + 1], V[2][KBE_NMAX][KBE_NMAX + 1];
+  __shared__ double jd[KBE_NMAX + 1], jo[KBE_NMAX + 1];
+  __shared__ int pt[KBE_NMAX + 1];
+  __shared__ int done;
+  const int tid = threadIdx.x;
+  const bool act = tid < N * N;
+  const int a = act ? tid / N : 0, b = act ? tid % N : 0;
+  if (tid == 0) *chg = 0ull;
+  if (act) {
+    double x = 0.5 * (h0[a * N + b] + h0[b * N + a]);
+    if (a == b) {
+      if (hartree) x += u[a] * -G[el(J, a, a, N)];
+      x -= mu;
+    }
+    A[0][a][b] = x;
+    V[0][a][b] = a == b ? 1.0 : 0.0;
+  }
+  const int M = N + (N & 1);
+  int cur = 0;
+  __syncthreads();
+  for (int sweep = 0; sweep < EQ_SWEEPS; ++sweep) {
+    if (tid == 0) {
+      double off = 0.0, tot = 0.0;
+      for (int i = 0; i < N; ++i)
+        for (int k = 0; k < N; ++k) {
+          const double v = A[cur][i][k] * A[cur][i][k];
+          tot += v;
+          if (i != k) off += v;
+        }
+      done = !(off > 1e-30 * tot);  // off-diagonal Frobenius norm below 1e-15 of the whole
+    }
+    __syncthreads();
+    if (done) break;
+    for (int r = 0; r < M - 1; ++r) {
+      if (tid < M / 2) {
+        int p, q;
+        if (tid == 0) {
+          p = r;
+          q = M - 1;
+        } else {
+          p = (r + tid) % (M - 1);
+          q = (r - tid + M - 1) % (M - 1);
+        }
+        if (p > q) {
+          const int w = p;
+          p = q;
+          q = w;
+        }
+        double c = 1.0, s = 0.0;
+        if (q < N) {
+          const double apq = A[cur][p][q];
+          if (apq != 0.0) {
+            const double th = (A[cur][q][q] - A[cur][p][p]) / (2.0 * apq);
+            const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+            c = 1.0 / sqrt(t * t + 1.0);
+            s = t * c;
+          }
+        }
+        pt[p] = q;
+        pt[q] = p;
+        jd[p] = c;
+        jd[q] = c;
+        jo[p] = -s;  // J[q][p]
+        jo[q] = s;   // J[p][q]
+      }
+      __syncthreads();
+      if (act) {
+        // A'[a][b] = sum over k in {a, pa}, l in {b, pb} of J[k][a] A[k][l] J[l][b]
+        const int pa = pt[a], pb = pt[b];
+        const double da = jd[a], oa = jo[a], db = jd[b], ob = jo[b];
+        double x = da * db * A[cur][a][b];
+        double y = V[cur][a][b] * db;
+        if (pb < N) {
+          x += da * ob * A[cur][a][pb];
+          y += V[cur][a][pb] * ob;
+        }
+        if (pa < N) {
+          x += oa * db * A[cur][pa][b];
+          if (pb < N) x += oa * ob * A[cur][pa][pb];
+        }
+        A[cur ^ 1][a][b] = x;
+        V[cur ^ 1][a][b] = y;
+      }
+      cur ^= 1;
+      __syncthreads();
+    }
+  }
+  if (act) {
+    V_out[a * N + b] = V[cur][a][b];
+    if (a == b) e_out[a] = A[cur][a][a];
+  }
+}
+
+// G0(tau_j) = V diag(x(tau_j)) V^T, x_k = -exp(-e_k tau)(1 - f(e_k)) in the form that does not
+// overflow for either sign of e_k.
+__global__ void __launch_bounds__(EQ_T) eq_free(const double *e, const double *V, double beta,
+                                                int J, int N, double *G0) {
+  __shared__ double x[KBE_NMAX], Vs[KBE_NMAX * KBE_NMAX];
+  const int j = blockIdx.x, tid = threadIdx.x;
+  const double tau = (double)j * beta / J;
+  if (tid < N) {
+    const double ek = e[tid];
+    x[tid] = ek >= 0.0 ? -exp(-ek * tau) / (1.0 + exp(-beta * ek))
+                       : -exp(ek * (beta - tau)) / (1.0 + exp(beta * ek));
+  }
+  if (tid < N * N) Vs[tid] = V[tid];
+  __syncthreads();
+  if (tid < N * N) {
+    const int a = tid / N, b = tid % N;
+    double acc = 0.0;
+    for (int k = 0; k < N; ++k) acc += Vs[a * N + k] * x[k] * Vs[b * N + k];
+    G0[el(j, a, b, N)] = acc;
+  }
+}
+
+// S_ab(tau_j) = u_a u_b G_ab(tau_j)^2 G_ba(tau_{J-j}).
+__global__ void eq_sigma(const double *G, const double *u, int J, int N, double *S) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tot = (int64_t)(J + 1) * N * N;
+  if (idx >= tot) return;
+  const int j = (int)(idx / (N * N)), e = (int)(idx % (N * N)), a = e / N, b = e % N;
+  const double g = G[idx];
+  S[idx] = u[a] * u[b] * (g * g) * G[el(J - j, b, a, N)];
+}
+
+// out = A * B at tau_j (block j).  Thread (slice s, element (a, b)): the terms l = s, s + ns, ...
+// of both parts; the slices are summed in a fixed order.  COMBINE: Gn = G0 + (A * B),
+// G <- (1 - mix) G + mix Gn in place (no block reads G), the block's largest |Gn - G| raised into
+// chg (non-negative doubles order like their bit patterns).
+template <bool COMBINE>
+__global__ void __launch_bounds__(EQ_T) eq_conv(const double *A, const double *B,
+                                                const double *wf, int J, int N, double *out,
+                                                const double *G0, double *G, double mix,
+                                                unsigned long long *chg) {
+  __shared__ double red[EQ_T];
+  const int j = blockIdx.x, tid = threadIdx.x, NN = N * N, ns = EQ_T / NN;
+  const int s = tid / NN, e = tid % NN, a = e / N, b = e % N;
+  const int64_t ld = (int64_t)J + 1;
+  double acc = 0.0;
+  if (s < ns) {
+    for (int l = s; l <= j; l += ns) {
+      const double *Am = A + el(j - l, a, 0, N), *Bl = B + el(l, 0, b, N);
+      double v = 0.0;
+      for (int c = 0; c < N; ++c) v += Am[c] * Bl[(size_t)c * N];
+      acc += wf[j * ld + l] * v;
+    }
+    for (int l = j + s; l <= J; l += ns) {
+      const double *Am = A + el(J + j - l, a, 0, N), *Bl = B + el(l, 0, b, N);
+      double v = 0.0;
+      for (int c = 0; c < N; ++c) v += Am[c] * Bl[(size_t)c * N];
+      acc -= wf[(int64_t)(J - j) * ld + (J - l)] * v;
+    }
+  }
+  red[tid] = acc;
+  __syncthreads();
+  double d = 0.0;
+  if (tid < NN) {
+    double tot = red[tid];
+    for (int k = 1; k < ns; ++k) tot += red[tid + k * NN];
+    const size_t i = el(j, a, b, N);
+    if (COMBINE) {
+      const double gn = G0[i] + tot, g = G[i];
+      d = fabs(gn - g);
+      G[i] = (1.0 - mix) * g + mix * gn;
+    } else {
+      out[i] = tot;
+    }
+  }
+  if (COMBINE) {
+    __syncthreads();
+    red[tid] = d;
+    __syncthreads();
+    if (tid == 0) {
+      double m = 0.0;
+      bool nan = false;
+      for (int k = 0; k < NN; ++k) {
+        nan |= !(red[k] == red[k]);
+        m = red[k] > m ? red[k] : m;
+      }
+      atomicMax(chg, (unsigned long long)__double_as_longlong(nan ? (double)NAN : m));
+    }
+  }
+}
+
+__global__ void eq_out(const double *G, int64_t tot, kbe_c128 *mat) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < tot) mat[idx] = kbe_c128{G[idx], 0.0};
+}
+
+struct EqLayout {
+  double *G, *G0, *S, *X, *e, *V;
+  unsigned long long *chg;
+};
+
+EqLayout eq_layout(void *ws, int N, int ntau) {
+  const size_t blk = align256(sizeof(double) * (size_t)ntau * N * N);
+  char *p = (char *)ws;
+  EqLayout L;
+  L.G = (double *)p;
+  p += blk;
+  L.G0 = (double *)p;
+  p += blk;
+  L.S = (double *)p;
+  p += blk;
+  L.X = (double *)p;
+  p += blk;
+  L.e = (double *)p;
+  p += align256(sizeof(double) * N);
+  L.V = (double *)p;
+  p += align256(sizeof(double) * N * N);
+  L.chg = (unsigned long long *)p;
+  return L;
+}
+
+}  // namespace
+
+size_t equilibrium_ws_bytes(int N, int ntau) {
+  return 4 * align256(sizeof(double) * (size_t)ntau * N * N) + align256(sizeof(double) * N) +
+         align256(sizeof(double) * N * N) + 256;
+}
+
+hipError_t launch_equilibrium(int N, int ntau, double beta, const double *wf, const double *h0,
+                              const double *u, double mu, double mix, double tol, int maxit,
+                              kbe_c128 *mat, void *ws, hipStream_t st, int *iterations,
+                              double *change) {
+  const EqLayout L = eq_layout(ws, N, ntau);
+  const int J = ntau - 1;
+  const int64_t tot = (int64_t)ntau * N * N;
+  const unsigned eb = (unsigned)((tot + 255) / 256);
+  // the starting point: the free function of h0 - mu
+  hipLaunchKernelGGL(eq_eig, dim3(1), dim3(EQ_T), 0, st, h0, u, mu, L.G, J, N, 0, L.e, L.V,
+                     L.chg);
+  hipLaunchKernelGGL(eq_free, dim3(ntau), dim3(EQ_T), 0, st, L.e, L.V, beta, J, N, L.G);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  double d = INFINITY;
+  int it = 0;
+  while (it < maxit) {
+    ++it;
+    hipLaunchKernelGGL(eq_eig, dim3(1), dim3(EQ_T), 0, st, h0, u, mu, L.G, J, N, 1, L.e, L.V,
+                       L.chg);
+    hipLaunchKernelGGL(eq_free, dim3(ntau), dim3(EQ_T), 0, st, L.e, L.V, beta, J, N, L.G0);
+    hipLaunchKernelGGL(eq_sigma, dim3(eb), dim3(256), 0, st, L.G, u, J, N, L.S);
+    hipLaunchKernelGGL(eq_conv<false>, dim3(ntau), dim3(EQ_T), 0, st, L.S, L.G, wf, J, N, L.X,
+                       nullptr, nullptr, 0.0, nullptr);
+    hipLaunchKernelGGL(eq_conv<true>, dim3(ntau), dim3(EQ_T), 0, st, L.G0, L.X, wf, J, N,
+                       nullptr, L.G0, L.G, mix, L.chg);
+    unsigned long long bits = 0;
+    err = hipMemcpyAsync(&bits, L.chg, sizeof bits, hipMemcpyDeviceToHost, st);
+    if (err == hipSuccess) err = hipStreamSynchronize(st);
+    if (err != hipSuccess) return err;
+    memcpy(&d, &bits, sizeof d);
+    if (!std::isfinite(d) || d < tol) break;
+  }
+  hipLaunchKernelGGL(eq_out, dim3(eb), dim3(256), 0, st, L.G, tot, mat);
+  *iterations = it;
+  *change = d;
+  return hipGetLastError();
+}
+
+}  // namespace kbe

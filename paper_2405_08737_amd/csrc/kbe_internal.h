@@ -76,6 +76,11 @@ hipError_t launch_propagate(const kbe_prop *P, const kbe_wts *W, const kbe_green
 hipError_t launch_propagate_vjp(const kbe_prop *P, const kbe_wts *W, const kbe_green *G,
                                 const double *gdens, double *gu, double *gamp, void *ws,
                                 hipStream_t st);
+size_t equilibrium_ws_bytes(int N, int ntau);
+hipError_t launch_equilibrium(int N, int ntau, double beta, const double *wf, const double *h0,
+                              const double *u, double mu, double mix, double tol, int maxit,
+                              kbe_c128 *mat, void *ws, hipStream_t st, int *iterations,
+                              double *change);
 size_t prop_adaptive_ws_bytes(int N, int nt, int ntau);
 hipError_t launch_propagate_adaptive(const kbe_prop *P, const kbe_adapt_ctl *ctl,
                                      const kbe_wts *W, const kbe_green *G, double *dens,

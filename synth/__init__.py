@@ -175,14 +175,15 @@ PROPAGATION = dict(N=8, nt=1024, beta=10.0, hmin=0.005, hmax=0.05, omin=3, omax=
 
 # The adaptive propagation: the same 8-site chain at half filling, U = 1, beta = 10, quenched by
 # the same pulse on site 0, variable step and order with the paper's tightest tolerances
-# (rtol 1e-8, atol 1e-10) and its largest history order K = 20.  Two cases: the thermal branch (256 tau points) up to t = 30 and
-# no thermal branch (initial density matrix the free thermal one) up to t = 40.  With the free
-# G^M the thermal-branch problem has a finite-time singularity at t ~ 32.88 (the same time to
-# 1e-4 at rtol 1e-6 and 1e-8: a property of the equations, not of the step control).  The
-# oracle replays the first `prefix` steps of each case on the same grid.
-ADAPTIVE = dict(N=8, U=1.0, beta=10.0, pulse_amp=1.0, pulse_t0=2.0, pulse_sigma=1.0, rtol=1e-8,
-                atol=1e-10, h_first=1e-3, qmax=12, kmax=20, maxcor=3, capacity=4096,
-                cases=((256, 30.0, 8), (0, 40.0, 48)))
+# (rtol 1e-8, atol 1e-10) and its largest history order K = 20, up to t = 40.  Two cases: the
+# thermal branch (256 tau points) from the interacting equilibrium G^M at mu = U/2 (the
+# self-consistent second-Born Matsubara Dyson solution; with the free G^M instead, this problem
+# runs into a finite-time singularity at t ~ 32.88), and no thermal branch (initial density
+# matrix the free thermal one).  The oracle replays the first `prefix` steps of each case on the
+# same grid.
+ADAPTIVE = dict(N=8, U=1.0, mu=0.5, beta=10.0, pulse_amp=1.0, pulse_t0=2.0, pulse_sigma=1.0,
+                rtol=1e-8, atol=1e-10, h_first=1e-3, qmax=12, kmax=20, maxcor=3, capacity=4096,
+                cases=((256, 40.0, 8), (0, 40.0, 48)))
 
 
 def tight_binding(N: int, hop: float = -1.0) -> np.ndarray:

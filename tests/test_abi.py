@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_status_strings_and_version():
     L = kbe.lib()
-    for code in range(6):
+    for code in range(8):
         assert L.kbe_status_string(code).decode().startswith("KBE_")
     assert L.kbe_version() >= 10000
 
@@ -339,3 +339,33 @@ def test_greater_form_flag():
                              kbe.OUT_IL | kbe.GREATER, FAKE, FAKE, FAKE, FAKE,
                              ctypes.byref(green()), ctypes.byref(row()), FAKE, 1 << 40, None)
     assert st == 1 and "ret" in err()
+
+
+def test_equilibrium_argument_errors_and_workspace():
+    L = kbe.lib()
+    assert L.kbe_equilibrium_workspace(0, 8) == 0 and L.kbe_equilibrium_workspace(2, 1) == 0
+    assert L.kbe_equilibrium_workspace(17, 8) == 0
+    a, b = L.kbe_equilibrium_workspace(4, 33), L.kbe_equilibrium_workspace(4, 65)
+    assert b > a >= 4 * 33 * 16 * 8
+
+    def call(N=4, ntau=33, beta=2.0, wf=FAKE, h0=FAKE, u=FAKE, mat=FAKE, ws_bytes=1 << 40, **c):
+        ctl = dict(mu=0.5, mix=0.5, tol=1e-13, maxit=100)
+        ctl.update(c)
+        C = kbe._EqCtl(ctl["mu"], ctl["mix"], ctl["tol"], ctl["maxit"], 0, 0.0)
+        return L.kbe_equilibrium(N, ntau, beta, wf, h0, u, ctypes.byref(C), mat, FAKE, ws_bytes,
+                                 None)
+
+    assert call(N=0) == 1 and "N" in err()
+    assert call(N=17) == 1
+    assert call(ntau=1) == 1 and "ntau" in err()
+    assert call(beta=0.0) == 1 and "beta" in err()
+    assert call(beta=float("nan")) == 1
+    for k in ("wf", "h0", "u", "mat"):
+        assert call(**{k: None}) == 1 and "NULL" in err()
+    assert call(mu=float("inf")) == 1 and "mu" in err()
+    assert call(mix=0.0) == 1 and "mix" in err()
+    assert call(mix=1.5) == 1
+    assert call(tol=0.0) == 1 and "tol" in err()
+    assert call(maxit=0) == 1 and "maxit" in err()
+    assert call(ws_bytes=16) == 3
+    assert L.kbe_status_string(kbe.KBE_ECONV).decode().startswith("KBE_ECONV")

@@ -11,6 +11,7 @@ from scipy.special import erf
 
 import synth
 from oracle import adaptive as ad
+from oracle import equilibrium as oeq
 from oracle import propagate as op
 
 pytestmark = pytest.mark.gpu
@@ -114,11 +115,13 @@ def test_adaptive_tolerance_proportionality(gpu):
 
 def test_adaptive_hubbard_workload_short(gpu):
     """The adaptive workload's shape over a shortened run: 8-site chain, U = 1, beta = 10, 256 tau
-    points, pulse on site 0, rtol 1e-6: finite, conserving, the order and the steps varying, and
-    the first 6 steps against the oracle replaying them."""
+    points, the interacting equilibrium at half filling as the initial state, pulse on site 0,
+    rtol 1e-6: finite, conserving, the order and the steps varying, and the first 6 steps against
+    the oracle replaying them."""
     kbe = gpu
     N, ntau, beta, U, A = 8, 256, 10.0, 1.0, 1.0
-    h0, mat, P = problem(N, ntau, beta)
+    h0, _, P = problem(N, ntau, beta)
+    P.mat, _ = oeq.solve(h0, U, U / 2, beta, ntau)
     g = run_gpu(kbe, P, U, A, capacity=1024, t_end=3.0, rtol=1e-6, atol=1e-10)
     d = g["dens"].cpu().numpy()
     t = g["t"]
