@@ -23,8 +23,9 @@
 //   eq_eig    one block: parallel (round-robin) Jacobi on eps, N/2 disjoint rotations per round
 //   eq_free   a block per tau point: G0 from (e, V)
 //   eq_sigma  elementwise
-//   eq_conv   a block per tau point, the l-sum split over slices of the block, LDS reduction;
-//             the second convolution also forms Gn, mixes in place and reduces the change
+//   eq_conv4  a block per tau point (N a multiple of 4; eq_conv otherwise), the l-sum split over
+//             slices of the block, 4 x 4 register tiles, LDS reduction; the second convolution
+//             also forms Gn, mixes in place and reduces the change
 // The host reads the change (8 bytes) once per iteration to decide convergence.
 #include "kbe_internal.h"
 
@@ -181,10 +182,41 @@ __global__ void eq_sigma(const double *G, const double *u, int J, int N, double 
   S[idx] = u[a] * u[b] * (g * g) * G[el(J - j, b, a, N)];
 }
 
-// out = A * B at tau_j (block j).  Thread (slice s, element (a, b)): the terms l = s, s + ns, ...
-// of both parts; the slices are summed in a fixed order.  COMBINE: Gn = G0 + (A * B),
-// G <- (1 - mix) G + mix Gn in place (no block reads G), the block's largest |Gn - G| raised into
-// chg (non-negative doubles order like their bit patterns).
+// The end of a convolution block: tot is the element's sum over l.  COMBINE: Gn = G0 + tot,
+// G <- (1 - mix) G + mix Gn in place (no block of the launch reads G), and the block's largest
+// |Gn - G| raised into chg (non-negative doubles order like their bit patterns; a NaN wins);
+// else out = tot.  red: EQ_T doubles of LDS, free on entry.
+template <bool COMBINE>
+__device__ __forceinline__ void conv_store(double tot, bool act, size_t i, double *out,
+                                           const double *G0, double *G, double mix,
+                                           unsigned long long *chg, double *red, int NN) {
+  double d = 0.0;
+  if (act) {
+    if (COMBINE) {
+      const double gn = G0[i] + tot, g = G[i];
+      d = fabs(gn - g);
+      G[i] = (1.0 - mix) * g + mix * gn;
+    } else {
+      out[i] = tot;
+    }
+  }
+  if (COMBINE) {
+    red[threadIdx.x] = d;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double m = 0.0;
+      bool nan = false;
+      for (int k = 0; k < NN; ++k) {
+        nan |= !(red[k] == red[k]);
+        m = red[k] > m ? red[k] : m;
+      }
+      atomicMax(chg, (unsigned long long)__double_as_longlong(nan ? (double)NAN : m));
+    }
+  }
+}
+
+// out = A * B at tau_j (block j), any N.  Thread (slice s, element (a, b)): the terms
+// l = s, s + ns, ... of both parts; the slices are summed in a fixed order.
 template <bool COMBINE>
 __global__ void __launch_bounds__(EQ_T) eq_conv(const double *A, const double *B,
                                                 const double *wf, int J, int N, double *out,
@@ -211,32 +243,112 @@ __global__ void __launch_bounds__(EQ_T) eq_conv(const double *A, const double *B
   }
   red[tid] = acc;
   __syncthreads();
-  double d = 0.0;
+  double tot = 0.0;
   if (tid < NN) {
-    double tot = red[tid];
+    tot = red[tid];
     for (int k = 1; k < ns; ++k) tot += red[tid + k * NN];
-    const size_t i = el(j, a, b, N);
-    if (COMBINE) {
-      const double gn = G0[i] + tot, g = G[i];
-      d = fabs(gn - g);
-      G[i] = (1.0 - mix) * g + mix * gn;
-    } else {
-      out[i] = tot;
-    }
   }
-  if (COMBINE) {
-    __syncthreads();
-    red[tid] = d;
-    __syncthreads();
-    if (tid == 0) {
-      double m = 0.0;
-      bool nan = false;
-      for (int k = 0; k < NN; ++k) {
-        nan |= !(red[k] == red[k]);
-        m = red[k] > m ? red[k] : m;
+  __syncthreads();
+  conv_store<COMBINE>(tot, tid < NN, el(j, a, b, N), out, G0, G, mix, chg, red, NN);
+}
+
+// The same for N = 4 TN: a thread holds a 4 x 4 tile of the output (TN x TN tiles) and walks
+// its slice of the ntau + 1 terms (the forward part l = 0..j, then the backward part l = j..J,
+// as one sequence); per term the product of the tile's 4 rows of A(tau_m) and 4 columns of
+// B(tau_l) in chunks of 4 along the contraction, from 16-byte loads, then one scaled update of
+// the tile.  The slices' tiles meet in LDS and are summed in a fixed order.
+template <bool COMBINE, int TN>
+__global__ void __launch_bounds__(EQ_T) eq_conv4(const double *A, const double *B,
+                                                 const double *wf, int J, double *out,
+                                                 const double *G0, double *G, double mix,
+                                                 unsigned long long *chg) {
+  constexpr int N = 4 * TN, NT = TN * TN, NS = EQ_T / NT;
+  __shared__ double red[NS * NT * 16];
+  const int j = blockIdx.x, tid = threadIdx.x;
+  const int s = tid / NT, tt = tid % NT, r0 = 4 * (tt / TN), q0 = 4 * (tt % TN);
+  const int64_t ld = (int64_t)J + 1;
+  const int nf = j + 1, nterm = J + 2;  // l = 0..j forward, then l = j..J backward
+  double acc[4][4] = {};
+  if (s < NS) {
+    for (int k = s; k < nterm; k += NS) {
+      int l, m;
+      double w;
+      if (k < nf) {
+        l = k;
+        m = j - l;
+        w = wf[j * ld + l];
+      } else {
+        l = j + (k - nf);
+        m = J + j - l;
+        w = -wf[(int64_t)(J - j) * ld + (J - l)];
       }
-      atomicMax(chg, (unsigned long long)__double_as_longlong(nan ? (double)NAN : m));
+      const double *Am = A + (size_t)m * N * N + (size_t)r0 * N;
+      const double *Bl = B + (size_t)l * N * N + q0;
+      double t[4][4] = {};
+#pragma unroll
+      for (int c0 = 0; c0 < N; c0 += 4) {
+        double2 x[4][2], y[4][2];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          x[r][0] = *(const double2 *)(Am + r * N + c0);
+          x[r][1] = *(const double2 *)(Am + r * N + c0 + 2);
+          y[r][0] = *(const double2 *)(Bl + (size_t)(c0 + r) * N);
+          y[r][1] = *(const double2 *)(Bl + (size_t)(c0 + r) * N + 2);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const double xr[4] = {x[r][0].x, x[r][0].y, x[r][1].x, x[r][1].y};
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const double yc[4] = {y[c][0].x, y[c][0].y, y[c][1].x, y[c][1].y};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) t[r][q] += xr[c] * yc[q];
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[r][q] += w * t[r][q];
     }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) red[(s * NT + tt) * 16 + r * 4 + q] = acc[r][q];
+  }
+  __syncthreads();
+  const bool act = tid < N * N;
+  const int a = act ? tid / N : 0, b = act ? tid % N : 0;
+  double tot = 0.0;
+  if (act) {
+    const int o = ((a >> 2) * TN + (b >> 2)) * 16 + (a & 3) * 4 + (b & 3);
+    for (int k = 0; k < NS; ++k) tot += red[k * NT * 16 + o];
+  }
+  __syncthreads();
+  conv_store<COMBINE>(tot, act, el(j, a, b, N), out, G0, G, mix, chg, red, N * N);
+}
+
+// A * B for every tau point (COMBINE: the update of G, see conv_store).
+template <bool COMBINE>
+void launch_conv(const double *A, const double *B, const double *wf, int J, int N, double *out,
+                 const double *G0, double *G, double mix, unsigned long long *chg,
+                 hipStream_t st) {
+  const dim3 g(J + 1), b(EQ_T);
+  switch (N) {
+    case 4:
+      hipLaunchKernelGGL((eq_conv4<COMBINE, 1>), g, b, 0, st, A, B, wf, J, out, G0, G, mix, chg);
+      break;
+    case 8:
+      hipLaunchKernelGGL((eq_conv4<COMBINE, 2>), g, b, 0, st, A, B, wf, J, out, G0, G, mix, chg);
+      break;
+    case 12:
+      hipLaunchKernelGGL((eq_conv4<COMBINE, 3>), g, b, 0, st, A, B, wf, J, out, G0, G, mix, chg);
+      break;
+    case 16:
+      hipLaunchKernelGGL((eq_conv4<COMBINE, 4>), g, b, 0, st, A, B, wf, J, out, G0, G, mix, chg);
+      break;
+    default:
+      hipLaunchKernelGGL(eq_conv<COMBINE>, g, b, 0, st, A, B, wf, J, N, out, G0, G, mix, chg);
   }
 }
 
@@ -299,10 +411,8 @@ hipError_t launch_equilibrium(int N, int ntau, double beta, const double *wf, co
                        L.chg);
     hipLaunchKernelGGL(eq_free, dim3(ntau), dim3(EQ_T), 0, st, L.e, L.V, beta, J, N, L.G0);
     hipLaunchKernelGGL(eq_sigma, dim3(eb), dim3(256), 0, st, L.G, u, J, N, L.S);
-    hipLaunchKernelGGL(eq_conv<false>, dim3(ntau), dim3(EQ_T), 0, st, L.S, L.G, wf, J, N, L.X,
-                       nullptr, nullptr, 0.0, nullptr);
-    hipLaunchKernelGGL(eq_conv<true>, dim3(ntau), dim3(EQ_T), 0, st, L.G0, L.X, wf, J, N,
-                       nullptr, L.G0, L.G, mix, L.chg);
+    launch_conv<false>(L.S, L.G, wf, J, N, L.X, nullptr, nullptr, 0.0, nullptr, st);
+    launch_conv<true>(L.G0, L.X, wf, J, N, nullptr, L.G0, L.G, mix, L.chg, st);
     unsigned long long bits = 0;
     err = hipMemcpyAsync(&bits, L.chg, sizeof bits, hipMemcpyDeviceToHost, st);
     if (err == hipSuccess) err = hipStreamSynchronize(st);

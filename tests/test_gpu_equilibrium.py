@@ -35,8 +35,10 @@ CASES = [
     # an asymmetric chain away from half filling, few tau points, site-dependent u
     dict(h0=chain(3, [0.3, -0.1, 0.2]), u=[1.0, 0.7, 1.2], mu=0.4, beta=2.0, ntau=9),
     dict(h0=chain(5, [0.2, 0.0, -0.3, 0.1, 0.0]), u=1.3, mu=0.2, beta=4.0, ntau=65),
-    # the largest orbital count
+    # the largest orbital count; 4 and 12 (the register-tiled convolution covers multiples of 4)
     dict(h0=chain(16), u=0.8, mu=0.4, beta=3.0, ntau=33),
+    dict(h0=chain(4, [0.1, 0.0, -0.2, 0.3]), u=1.0, mu=0.6, beta=3.0, ntau=20),
+    dict(h0=chain(12), u=[0.5 + 0.05 * i for i in range(12)], mu=0.3, beta=2.5, ntau=17),
     # the propagation workload: 8 sites, U = 1, beta = 10, 256 tau points, half filling
     dict(h0=chain(8), u=1.0, mu=0.5, beta=10.0, ntau=256),
 ]
