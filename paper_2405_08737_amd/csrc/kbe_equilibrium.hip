@@ -60,6 +60,7 @@ __global__ void __launch_bounds__(EQ_T) eq_eig(const double *h0, const double *u
   __shared__ double A[2][KBE_NMAX][KBE_NMAX + 1], V[2][KBE_NMAX][KBE_NMAX + 1];
   __shared__ double jd[KBE_NMAX + 1], jo[KBE_NMAX + 1];
   __shared__ int pt[KBE_NMAX + 1];
+  __shared__ double wo[EQ_T / 64], wt[EQ_T / 64];
   __shared__ int done;
   const int tid = threadIdx.x;
   const bool act = tid < N * N;
@@ -78,14 +79,28 @@ __global__ void __launch_bounds__(EQ_T) eq_eig(const double *h0, const double *u
   int cur = 0;
   __syncthreads();
   for (int sweep = 0; sweep < EQ_SWEEPS; ++sweep) {
+    // squared off-diagonal and total norms: wave sums, then the waves in order
+    double vo = 0.0, vt = 0.0;
+    if (act) {
+      const double x = A[cur][a][b];
+      vt = x * x;
+      vo = a != b ? vt : 0.0;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      vo += __shfl_down(vo, o);
+      vt += __shfl_down(vt, o);
+    }
+    if ((tid & 63) == 0) {
+      wo[tid >> 6] = vo;
+      wt[tid >> 6] = vt;
+    }
+    __syncthreads();
     if (tid == 0) {
       double off = 0.0, tot = 0.0;
-      for (int i = 0; i < N; ++i)
-        for (int k = 0; k < N; ++k) {
-          const double v = A[cur][i][k] * A[cur][i][k];
-          tot += v;
-          if (i != k) off += v;
-        }
+      for (int w = 0; w < EQ_T / 64; ++w) {
+        off += wo[w];
+        tot += wt[w];
+      }
       done = !(off > 1e-30 * tot);  // off-diagonal Frobenius norm below 1e-15 of the whole
     }
     __syncthreads();

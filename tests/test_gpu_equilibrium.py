@@ -111,3 +111,15 @@ def test_propagation_from_the_equilibrium_is_stationary(gpu):
            % (steps_eq, d_eq, steps_free, d_free))
     assert d_eq < 1e-6
     assert d_free > 1e-3
+
+
+def test_strong_coupling_does_not_converge(gpu):
+    """At U = 20 the mixed iteration does not settle (the oracle's change is still 0.7 after 40
+    iterations): KBE_ECONV, with a finite last iterate and its change."""
+    kbe = gpu
+    with pytest.raises(kbe.KBEError) as ex:
+        kbe.equilibrium(chain(4), 20.0, 10.0, 4.0, 33, maxit=40)
+    assert ex.value.status == kbe.KBE_ECONV
+    mat, info = ex.value.partial
+    assert info["iterations"] == 40 and info["change"] > 1e-3
+    assert torch.isfinite(mat.real).all()
