@@ -8,13 +8,14 @@ timing starts.  After the timed steps, the forward and adjoint collision calls a
 the 8-orbital differentiation shape (nt = 1024, n_tau = 256: the small-block path, bound by HBM
 bandwidth), and the batching workload (256 independent rows, N in {2,4,8,16}, n up to 4096) is
 timed as one batched launch, as a graph replay and as 256 separate launches; the end-to-end
-gradient of a propagation (kbe_propagate and its adjoint on the 8-orbital grid) and the adaptive
-propagation of the 8-site chain (kbe_propagate_adaptive) are timed too; all are reported beside
+gradient of a propagation (kbe_propagate and its adjoint on the 8-orbital grid), the adaptive
+propagation of the 8-site chain (kbe_propagate_adaptive) and the interacting equilibrium solve
+that starts it (kbe_equilibrium, at 8 and 16 orbitals) are timed too; all are reported beside
 the step, with the FP64 matrix-core and HBM ceilings measured live by the library's
 microbenchmarks.  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-propagation]
-  python bench.py --adaptive-only      # only the adaptive propagation cases
+  python bench.py --adaptive-only      # only the adaptive propagation and equilibrium cases
   python bench.py --copy-calibration   # 3 plain 1 GiB device copies (PMC byte-counter scale)
   python bench.py --ceilings           # the ceiling microbenchmarks -> profiles/ceilings.json
 """
@@ -35,6 +36,7 @@ sys.path.insert(0, ROOT)
 METRIC = "collision-integral FP64 GFLOP/s + HBM GB/s, N_orb=16 n=2048; adjoint/fwd time"
 HBM_PEAK_GBS = 8000.0
 MFMA_F64_PEAK_TFLOPS = 78.6
+FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CUs x 128 FP64 flop per clock x 2.4 GHz
 RIDGE = MFMA_F64_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
 CEILING_SOURCES = ("kbe_ceilings.hip",)
 
@@ -564,6 +566,34 @@ def adaptive(kbe, torch, dev):
              "cases": out}, replays)
 
 
+def equilibrium(kbe, torch, dev):
+    """The interacting equilibrium solve (kbe_equilibrium) on the adaptive workload's chain (U = 1,
+    beta = 10, half filling) at 8 and 16 orbitals and 256 and 1024 tau points: one solve to warm
+    up, then one timed by the host clock (the call synchronises once per iteration).  The
+    convolutions do 4 ntau^2 N^3 flops per iteration; their rate is given against the FP64
+    vector peak (they run on the vector ALU)."""
+    import synth
+    A = synth.ADAPTIVE
+    out = []
+    for N, ntau in ((8, 256), (16, 256), (8, 1024), (16, 1024)):
+        h0 = synth.tight_binding(N)
+        kbe.equilibrium(h0, A["U"], A["mu"], A["beta"], ntau, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info = kbe.equilibrium(h0, A["U"], A["mu"], A["beta"], ntau, device=dev)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        it = info["iterations"]
+        flop = 4.0 * ntau * ntau * N ** 3
+        out.append({"N": N, "ntau": ntau, "iterations": it, "change": info["change"],
+                    "wall_ms": 1e3 * wall, "ms_per_iteration": 1e3 * wall / it,
+                    "convolution_gflop_per_iteration": flop / 1e9,
+                    "tflops": flop * it / wall / 1e12,
+                    "frac_of_fp64_vector_peak": flop * it / wall / 1e12 / FP64_VECTOR_PEAK_TFLOPS})
+    return {"workload": f"open chain, U={A['U']}, beta={A['beta']}, mu={A['mu']} (half filling), "
+                        f"tol 1e-13, mixing 1/2", "cases": out}
+
+
 def adaptive_oracle(replays):
     """The oracle replaying the GPU's first steps of each adaptive case on the same grid (same
     orders and history orders): its time per step beside the GPU's, and the largest deviations of
@@ -658,6 +688,7 @@ def main():
         t0 = time.perf_counter()
         rep, _ = adaptive(kbe, torch, dev)
         rep["process_wall_s"] = time.perf_counter() - t0
+        rep["equilibrium"] = equilibrium(kbe, torch, dev)
         print(json.dumps(rep), flush=True)
         return
     log("ceiling microbenchmarks")
@@ -798,6 +829,8 @@ def main():
         torch.cuda.empty_cache()
         log("adaptive propagation")
         result["adaptive"], replays = adaptive(kbe, torch, dev)
+        log("equilibrium solve")
+        result["equilibrium"] = equilibrium(kbe, torch, dev)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample)")
         result["cpu_baseline"] = cpu_baseline(w, (t, order, kp_h, rd_h, tv_h, mat_h))

@@ -20,9 +20,9 @@
 //
 // G^M is real for the real symmetric h0 of the propagations, so the iteration runs in real FP64
 // and writes the complex output once at the end.  Kernels (one launch each per iteration):
-//   eq_eig    one block: parallel (round-robin) Jacobi on eps, N/2 disjoint rotations per round
-//   eq_free   a block per tau point: G0 from (e, V)
-//   eq_sigma  elementwise
+//   eq_eig    one block: parallel (round-robin) Jacobi on eps, N/2 disjoint rotations per round,
+//             from the previous iteration's eigenvectors
+//   eq_free   a block per tau point: G0 from (e, V), and the self-energy of the iterate
 //   eq_conv4  a block per tau point (N a multiple of 4; eq_conv otherwise), the l-sum split over
 //             slices of the block, 4 x 4 register tiles, LDS reduction; the second convolution
 //             also forms Gn, mixes in place and reduces the change
@@ -46,6 +46,8 @@ __device__ __forceinline__ size_t el(int j, int a, int b, int N) {
 }
 
 // Eigendecomposition of eps (hartree != 0: with the Hartree shift of G[J]; else of h0 - mu).
+// warm != 0: start from the eigenvectors V_out of the previous call, i.e. diagonalise V^T eps V
+// (nearly diagonal once the densities settle) and accumulate the rotations onto V.
 // Round-robin ordering: in round r player r pairs with M-1 and (r+k) mod (M-1) with
 // (r-k) mod (M-1), k = 1..M/2-1 (M = N rounded up to even; a pair with the dummy player N is
 // idle).  The rotation of pair (p < q) zeroes A[p][q]: theta = (A_qq - A_pp) / (2 A_pq),
@@ -55,7 +57,7 @@ __device__ __forceinline__ size_t el(int j, int a, int b, int N) {
 // accumulator of the iteration.
 __global__ void __launch_bounds__(EQ_T) eq_eig(const double *h0, const double *u, double mu,
                                                const double *G, int J, int N, int hartree,
-                                               double *e_out, double *V_out,
+                                               int warm, double *e_out, double *V_out,
                                                unsigned long long *chg) {
   __shared__ double A[2][KBE_NMAX][KBE_NMAX + 1], V[2][KBE_NMAX][KBE_NMAX + 1];
   __shared__ double jd[KBE_NMAX + 1], jo[KBE_NMAX + 1];
@@ -72,12 +74,26 @@ __global__ void __launch_bounds__(EQ_T) eq_eig(const double *h0, const double *u
       if (hartree) x += u[a] * -G[el(J, a, a, N)];
       x -= mu;
     }
-    A[0][a][b] = x;
-    V[0][a][b] = a == b ? 1.0 : 0.0;
+    A[warm ? 1 : 0][a][b] = x;
+    V[0][a][b] = warm ? V_out[a * N + b] : (a == b ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  if (warm) {  // A[0] = V^T eps V, through V[1] = eps V
+    if (act) {
+      double t = 0.0;
+      for (int k = 0; k < N; ++k) t += A[1][a][k] * V[0][k][b];
+      V[1][a][b] = t;
+    }
+    __syncthreads();
+    if (act) {
+      double t = 0.0;
+      for (int k = 0; k < N; ++k) t += V[0][k][a] * V[1][k][b];
+      A[0][a][b] = t;
+    }
+    __syncthreads();
   }
   const int M = N + (N & 1);
   int cur = 0;
-  __syncthreads();
   for (int sweep = 0; sweep < EQ_SWEEPS; ++sweep) {
     // squared off-diagonal and total norms: wave sums, then the waves in order
     double vo = 0.0, vt = 0.0;
@@ -166,9 +182,11 @@ __global__ void __launch_bounds__(EQ_T) eq_eig(const double *h0, const double *u
 }
 
 // G0(tau_j) = V diag(x(tau_j)) V^T, x_k = -exp(-e_k tau)(1 - f(e_k)) in the form that does not
-// overflow for either sign of e_k.
+// overflow for either sign of e_k; with S, also the self-energy of the current iterate at tau_j:
+// S_ab(tau_j) = u_a u_b G_ab(tau_j)^2 G_ba(tau_{J-j}).
 __global__ void __launch_bounds__(EQ_T) eq_free(const double *e, const double *V, double beta,
-                                                int J, int N, double *G0) {
+                                                int J, int N, double *G0, const double *G,
+                                                const double *u, double *S) {
   __shared__ double x[KBE_NMAX], Vs[KBE_NMAX * KBE_NMAX];
   const int j = blockIdx.x, tid = threadIdx.x;
   const double tau = (double)j * beta / J;
@@ -184,17 +202,11 @@ __global__ void __launch_bounds__(EQ_T) eq_free(const double *e, const double *V
     double acc = 0.0;
     for (int k = 0; k < N; ++k) acc += Vs[a * N + k] * x[k] * Vs[b * N + k];
     G0[el(j, a, b, N)] = acc;
+    if (S) {
+      const double g = G[el(j, a, b, N)];
+      S[el(j, a, b, N)] = u[a] * u[b] * (g * g) * G[el(J - j, b, a, N)];
+    }
   }
-}
-
-// S_ab(tau_j) = u_a u_b G_ab(tau_j)^2 G_ba(tau_{J-j}).
-__global__ void eq_sigma(const double *G, const double *u, int J, int N, double *S) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t tot = (int64_t)(J + 1) * N * N;
-  if (idx >= tot) return;
-  const int j = (int)(idx / (N * N)), e = (int)(idx % (N * N)), a = e / N, b = e % N;
-  const double g = G[idx];
-  S[idx] = u[a] * u[b] * (g * g) * G[el(J - j, b, a, N)];
 }
 
 // The end of a convolution block: tot is the element's sum over l.  COMBINE: Gn = G0 + tot,
@@ -413,19 +425,20 @@ hipError_t launch_equilibrium(int N, int ntau, double beta, const double *wf, co
   const int64_t tot = (int64_t)ntau * N * N;
   const unsigned eb = (unsigned)((tot + 255) / 256);
   // the starting point: the free function of h0 - mu
-  hipLaunchKernelGGL(eq_eig, dim3(1), dim3(EQ_T), 0, st, h0, u, mu, L.G, J, N, 0, L.e, L.V,
+  hipLaunchKernelGGL(eq_eig, dim3(1), dim3(EQ_T), 0, st, h0, u, mu, L.G, J, N, 0, 0, L.e, L.V,
                      L.chg);
-  hipLaunchKernelGGL(eq_free, dim3(ntau), dim3(EQ_T), 0, st, L.e, L.V, beta, J, N, L.G);
+  hipLaunchKernelGGL(eq_free, dim3(ntau), dim3(EQ_T), 0, st, L.e, L.V, beta, J, N, L.G,
+                     nullptr, nullptr, nullptr);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   double d = INFINITY;
   int it = 0;
   while (it < maxit) {
     ++it;
-    hipLaunchKernelGGL(eq_eig, dim3(1), dim3(EQ_T), 0, st, h0, u, mu, L.G, J, N, 1, L.e, L.V,
-                       L.chg);
-    hipLaunchKernelGGL(eq_free, dim3(ntau), dim3(EQ_T), 0, st, L.e, L.V, beta, J, N, L.G0);
-    hipLaunchKernelGGL(eq_sigma, dim3(eb), dim3(256), 0, st, L.G, u, J, N, L.S);
+    hipLaunchKernelGGL(eq_eig, dim3(1), dim3(EQ_T), 0, st, h0, u, mu, L.G, J, N, 1, 1, L.e,
+                       L.V, L.chg);
+    hipLaunchKernelGGL(eq_free, dim3(ntau), dim3(EQ_T), 0, st, L.e, L.V, beta, J, N, L.G0,
+                       L.G, u, L.S);
     launch_conv<false>(L.S, L.G, wf, J, N, L.X, nullptr, nullptr, 0.0, nullptr, st);
     launch_conv<true>(L.G0, L.X, wf, J, N, nullptr, L.G0, L.G, mix, L.chg, st);
     unsigned long long bits = 0;

@@ -62,7 +62,9 @@ def test_no_interaction_is_the_free_function(gpu):
     kbe = gpu
     h0 = chain(6, [0.1, -0.2, 0.0, 0.3, 0.0, -0.1])
     mat, info = kbe.equilibrium(h0, 0.0, 0.3, 5.0, 41)
-    assert info["iterations"] == 1 and info["change"] == 0.0
+    # the first iteration re-diagonalises the same matrix from the starting eigenvectors: the
+    # free function again, to rounding
+    assert info["iterations"] == 1 and info["change"] < 1e-15
     ref = eq.free_matsubara(h0 - 0.3 * np.eye(6), 5.0, 41)
     np.testing.assert_allclose(mat.cpu().numpy().real, ref, atol=1e-14, rtol=0)
 
