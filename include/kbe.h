@@ -42,15 +42,21 @@
  *   les [n+1][N][N]  Sigma^<(t_n,t_s)
  *   tv  [ntau][N][N] Sigma^](t_n,tau_j)
  *
- * Ownership.  The caller owns every buffer.  The library allocates nothing:
- * scratch memory is a caller-supplied device workspace whose size the
- * matching *_workspace() query returns.  The one exception is the fixed
- * scratch array behind kbe_collision_noalloc (KBE_NOALLOC_SCRATCH_BYTES per
- * device, part of the library's device code, held until the process ends).
+ * Ownership.  The caller owns every buffer.  The library allocates no device
+ * memory: scratch memory is a caller-supplied device workspace whose size the
+ * matching *_workspace() query returns (its parts start at 256-byte offsets:
+ * pass it 256-byte aligned, as hipMalloc returns it).  The one exception is the
+ * fixed scratch array behind kbe_collision_noalloc (KBE_NOALLOC_SCRATCH_BYTES
+ * per device, part of the library's device code, held until the process
+ * ends).  kbe_propagate_adaptive holds 4 KiB of page-locked host memory for the
+ * duration of the call (the error norms its controller reads).
  *
  * Streams.  `stream` is a hipStream_t (NULL = the default stream).  All device
  * work is enqueued asynchronously on it; no entry point synchronises the host
- * except kbe_weights, which reads host arrays before returning.
+ * except kbe_weights, which reads host arrays before returning, and the two
+ * iterations driven from the host: kbe_propagate_adaptive (error norms at
+ * every fixed-point iteration) and kbe_equilibrium (the change once per
+ * iteration).
  *
  * Errors.  Every entry point validates its arguments on the host before
  * enqueuing anything and returns a kbe_status; on an error nothing has been
