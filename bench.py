@@ -7,7 +7,8 @@ all through the C ABI of libkbe.so.  Inputs are seeded synthetic arrays, residen
 timing starts.  After the timed steps, the forward and adjoint collision calls are also timed on
 the 8-orbital differentiation shape (nt = 1024, n_tau = 256: the small-block path, bound by HBM
 bandwidth), and the batching workload (256 independent rows, N in {2,4,8,16}, n up to 4096) is
-timed as one batched launch, as a graph replay and as 256 separate launches; the end-to-end
+timed as one batched launch, as a graph replay and as 256 separate launches, and 256 rows of the
+headline system as one batched launch against 256 plain kbe_collision calls; the end-to-end
 gradient of a propagation (kbe_propagate and its adjoint on the 8-orbital grid), the adaptive
 propagation of the 8-site chain (kbe_propagate_adaptive) and the interacting equilibrium solve
 that starts it (kbe_equilibrium, at 8 and 16 orbitals) are timed too; all are reported beside
@@ -349,6 +350,84 @@ def general_u_sigma(kbe, torch, G, n, w, reps=5):
     return {"workload": f"N{N}_nt{G.nt}_ntau{G.ntau} row n={n}, U: symmetric (ij|kl), on-site 1",
             "ms": ms, "algorithmic_flop": flop, "tflops": flop / ms / 1e9,
             "frac_f64_peak": flop / ms / 1e9 / MFMA_F64_PEAK_TFLOPS}
+
+
+def batch_vs_plain(kbe, torch, dev, G, W, u, nrows=256, seed=1004, reps=5):
+    """The same rows run both ways: 256 rows (n, m) of the 16-orbital headline system (n
+    log-uniform in [128, nt - 1], m uniform in 0..n), as one kbe_collision_batch launch (cross
+    storage: each row's kp column gathered, its kp row, tv row and weight rows in place) and as
+    256 plain kbe_collision calls on the system's KP storage (m-range [m, m + 1), I^R, I^<, I^]),
+    with the outputs, workspace and arguments of the plain calls prepared beforehand.  Both read
+    the same algorithmic bytes; the plain calls' outputs are compared with the batch's."""
+    import ctypes
+    rng = np.random.default_rng(seed)
+    nt = G.nt
+    ns = np.minimum(np.exp(rng.uniform(np.log(128), np.log(nt - 1), nrows)).astype(int), nt - 1)
+    ms = np.array([int(rng.integers(0, n + 1)) for n in ns])
+    flags = kbe.OUT_IR | kbe.OUT_IL | kbe.OUT_ITV
+    sigs, items = {}, []
+    for n, m in zip(ns.tolist(), ms.tolist()):
+        if n not in sigs:
+            sigs[n] = kbe.sigma_2b(G, u, n)
+        sr = sigs[n]
+        items.append(kbe.BatchItem(n=n, m=m, sig_ret=sr[0], sig_les=sr[1],
+                                   col=G.kp[:m + 1, m].contiguous(), row=G.kp[m, :n + 1],
+                                   rdiag=G.rdiag[m], wn=W.w[n, :n + 1], wm=W.w[m, :m + 1],
+                                   sig_tv=sr[2], tv=G.tv[m], wtau=W.wtau, flags=flags))
+    batch = kbe.Batch(items)
+    best, _ = batch.tune()
+    L = kbe.lib()
+    N = G.N
+    nb = max(L.kbe_collision_workspace(N, nt, G.ntau, int(n), int(m), int(m) + 1, flags)
+             for n, m in zip(ns, ms))
+    ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev)
+    outs = torch.empty((nrows, 3, N, N), dtype=torch.complex128, device=dev)
+    gc, wc = G.c(), W.c()
+    rows = [kbe._row(*sigs[int(n)]) for n in ns]
+    stream = torch.cuda.current_stream(dev).cuda_stream
+
+    def plain():
+        for i in range(nrows):
+            o = outs[i]
+            st = L.kbe_collision(ctypes.byref(gc), ctypes.byref(rows[i]), ctypes.byref(wc),
+                                 int(ns[i]), int(ms[i]), int(ms[i]) + 1, flags,
+                                 o[0].data_ptr(), o[1].data_ptr(), o[2].data_ptr(), None,
+                                 ws.data_ptr(), nb, stream)
+            if st != 0:
+                raise RuntimeError(f"kbe_collision: status {st}")
+
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, k):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = ev(), ev()
+        e0.record()
+        for _ in range(k):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    batched_ms = timed(lambda: batch.run(best), reps)
+    plain_ms = timed(plain, reps)
+    IR, IL, Itv = batch.run(best)
+    torch.cuda.synchronize()
+    got = torch.stack([torch.stack([IR[i], IL[i], Itv[i]]) for i in range(nrows)])
+    rel = float(((got - outs).abs().amax(dim=(2, 3)) /
+                 outs.abs().amax(dim=(2, 3)).clamp_min(1e-300)).max())
+    nbytes = 0.0
+    for n, m in zip(ns.tolist(), ms.tolist()):
+        blocks = (n + 1) + (m + 1) + (n - m) + (m + 1) + m + 1 + 2 * G.ntau + 3  # as batching()
+        nbytes += 16.0 * N * N * blocks + 8.0 * ((n + 1) + (m + 1) + G.ntau)
+    del batch, ws, outs
+    return {"workload": f"{nrows} rows (n, m) of the N{N}_nt{nt}_ntau{G.ntau} headline system, "
+                        f"n log-uniform in [128, {nt - 1}], m uniform in 0..n; I^R, I^<, I^]",
+            "chunk": best, "batched_ms": batched_ms, "plain_calls_ms": plain_ms,
+            "speedup_vs_plain": plain_ms / batched_ms, "algorithmic_bytes": nbytes,
+            "batched_gbps": nbytes / batched_ms / 1e6, "plain_gbps": nbytes / plain_ms / 1e6,
+            "max_rel_diff_batched_vs_plain": rel}
 
 
 def batching(kbe, torch, dev, reps=10):
@@ -815,12 +894,17 @@ def main():
     result["greater_form"] = greater_form(kbe, torch, G, u, n, t, order, w, cot, gG)
     log("general four-index self-energy")
     result["gf2"] = general_u_sigma(kbe, torch, G, n, w)
-    del gG, kp, tvd, G
+    log("batched against plain per-row calls")
+    Wh = kbe.weights(t, order, ntau, w.beta, w.tau_order, device=dev)
+    plain_rows = batch_vs_plain(kbe, torch, dev, G, Wh, u)
+    del gG, kp, tvd, G, Wh
     torch.cuda.empty_cache()
     log("8-orbital differentiation shape")
     result["small_orbital"] = small_orbital_shape(kbe, torch, dev)
     log("batching workload")
     result["batching"] = batching(kbe, torch, dev)
+    result["batching"]["plain_per_row"] = plain_rows
+    torch.cuda.empty_cache()
     torch.cuda.empty_cache()
     replays = []
     if not args.no_propagation:
