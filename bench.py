@@ -417,17 +417,47 @@ def batch_vs_plain(kbe, torch, dev, G, W, u, nrows=256, seed=1004, reps=5):
     got = torch.stack([torch.stack([IR[i], IL[i], Itv[i]]) for i in range(nrows)])
     rel = float(((got - outs).abs().amax(dim=(2, 3)) /
                  outs.abs().amax(dim=(2, 3)).clamp_min(1e-300)).max())
+    # the whole pipeline [self-energy rows -> column gathers -> batch] eager and as one graph
+    ud = u.contiguous()
+
+    def pipeline():
+        st = torch.cuda.current_stream(dev).cuda_stream
+        for n in sigs:
+            r = kbe._row(*sigs[n])
+            if L.kbe_sigma_2b(ctypes.byref(gc), ud.data_ptr(), int(n), ctypes.byref(r), st):
+                raise RuntimeError("kbe_sigma_2b failed")
+        for it in items:
+            it.col.copy_(G.kp[:it.m + 1, it.m])
+        batch.run(best)
+
+    pipeline_ms = timed(pipeline, reps)
+    side = torch.cuda.Stream(dev)
+    side.wait_stream(torch.cuda.current_stream(dev))
+    with torch.cuda.stream(side):
+        pipeline()
+    torch.cuda.current_stream(dev).wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        pipeline()
+    graph_ms = timed(graph.replay, reps)
+    torch.cuda.synchronize()
+    same = all(torch.equal(torch.stack([IR[i], IL[i], Itv[i]]), got[i]) for i in range(nrows))
     nbytes = 0.0
     for n, m in zip(ns.tolist(), ms.tolist()):
         blocks = (n + 1) + (m + 1) + (n - m) + (m + 1) + m + 1 + 2 * G.ntau + 3  # as batching()
         nbytes += 16.0 * N * N * blocks + 8.0 * ((n + 1) + (m + 1) + G.ntau)
-    del batch, ws, outs
+    del batch, ws, outs, graph
     return {"workload": f"{nrows} rows (n, m) of the N{N}_nt{nt}_ntau{G.ntau} headline system, "
                         f"n log-uniform in [128, {nt - 1}], m uniform in 0..n; I^R, I^<, I^]",
             "chunk": best, "batched_ms": batched_ms, "plain_calls_ms": plain_ms,
             "speedup_vs_plain": plain_ms / batched_ms, "algorithmic_bytes": nbytes,
             "batched_gbps": nbytes / batched_ms / 1e6, "plain_gbps": nbytes / plain_ms / 1e6,
-            "max_rel_diff_batched_vs_plain": rel}
+            "max_rel_diff_batched_vs_plain": rel,
+            "pipeline": {"stages": f"{len(sigs)} kbe_sigma_2b rows -> {nrows} column gathers -> "
+                                   f"kbe_collision_batch",
+                         "eager_ms": pipeline_ms, "graph_replay_ms": graph_ms,
+                         "graph_equals_eager": bool(same)}}
 
 
 def batching(kbe, torch, dev, reps=10):

@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 import synth
-from tests.cases import RTOL, batch_item, row_scales, to_host
+from tests.cases import RTOL, batch_item, device_weights, row_scales, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -134,6 +134,89 @@ def test_batch_graph_capture_replay(mixed):
         for a, b in zip(got, eager):
             assert np.array_equal(a, b), rep
     _check(batch, refs)
+
+
+def test_batch_graph_with_sigma_rows(gpu):
+    """[self-energy rows -> kbe_collision_batch (plan, stream, reduce)] as one captured graph, for
+    rows of two systems held in KP storage on the device (N = 4 and 16): kbe_sigma_2b writes each
+    row's self-energy, the rows' kp columns are gathered, and the batch reads both.  Every replay
+    (outputs and intermediates set to NaN before it, with eager work and synchronisation between
+    replays) equals the eager pipeline bit for bit, and that matches the oracle (its own
+    self-energy rows) to the FP64 bar."""
+    import ctypes
+    import torch
+    kbe = gpu
+    L = kbe.lib()
+    systems = []
+    for N, nt, ntau, seed, uval in [(4, 40, 6, 31, 0.8), (16, 30, 5, 32, 1.1)]:
+        S = _system(N, nt, ntau, seed)
+        S["u"] = np.full(N, uval)
+        S["Gd"] = kbe.Green(to_dev(S["kp"]), to_dev(S["rd"]), to_dev(S["tv"]), to_dev(S["mat"]))
+        S["Wd"] = device_weights(S["W"])
+        S["ud"] = to_dev(S["u"])
+        systems.append(S)
+    rows = [(0, 39, 0), (0, 39, 39), (0, 25, 11), (0, 10, 10), (1, 29, 3), (1, 29, 29),
+            (1, 17, 9), (1, 0, 0)]
+    z = lambda *sh: torch.empty(sh, dtype=torch.complex128, device="cuda")
+    sig_bufs, col_bufs, items, refs = [], [], [], []
+    for si, n, m in rows:
+        S = systems[si]
+        N, ntau, Gd, Wd = S["N"], S["ntau"], S["Gd"], S["Wd"]
+        sb = (z(n + 1, N, N), z(n + 1, N, N), z(ntau, N, N))
+        cb = z(m + 1, N, N)
+        sig_bufs.append((si, n, sb))
+        col_bufs.append((si, m, cb))
+        items.append(kbe.BatchItem(n=n, m=m, sig_ret=sb[0], sig_les=sb[1], col=cb,
+                                   row=Gd.kp[m, :n + 1], rdiag=Gd.rdiag[m], wn=Wd.w[n, :n + 1],
+                                   wm=Wd.w[m, :m + 1], sig_tv=sb[2], tv=Gd.tv[m], wtau=Wd.wtau,
+                                   flags=F3))
+        sig = oracle.sigma_row(S["G"], S["u"], n)
+        IR, IL, Itv, _ = oracle.collision(S["G"], sig, S["W"], n, m, m + 1, F3)
+        cr = dict(ret=sig[0], les=sig[1], stv=sig[2], col=S["kp"][:m + 1, m],
+                  row=S["kp"][m, :n + 1], rdiag=S["rd"][m], tv=S["tv"][m])
+        sc = row_scales(N, ntau, n, m, cr, S["W"].w[n], S["W"].w[m], S["W"].wfull)
+        refs.append(dict(f=F3, ref=(IR[0], IL[0], Itv[0]), sc=sc, N=N, nm=(n, m)))
+    batch = kbe.Batch(items)
+
+    def pipeline():
+        st = torch.cuda.current_stream().cuda_stream
+        for si, n, sb in sig_bufs:
+            S = systems[si]
+            row = kbe._row(*sb)
+            assert L.kbe_sigma_2b(ctypes.byref(S["Gd"].c()), S["ud"].data_ptr(), n,
+                                  ctypes.byref(row), st) == 0
+        for si, m, cb in col_bufs:
+            cb.copy_(systems[si]["Gd"].kp[:m + 1, m])
+        batch.run(64)
+
+    outs = lambda: [to_host(x) for x in batch.IR + batch.IL + batch.Itv]
+    pipeline()
+    torch.cuda.synchronize()
+    eager = outs()
+    _check(batch, refs)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        pipeline()  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        pipeline()
+    nan = float("nan")
+    for rep in range(3):
+        for _, _, sb in sig_bufs:
+            for x in sb:
+                x.fill_(nan)
+        for _, _, cb in col_bufs:
+            cb.fill_(nan)
+        for x in batch.IR + batch.IL + batch.Itv:
+            x.fill_(nan)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(outs(), eager):
+            assert np.array_equal(a, b), rep
 
 
 def test_batch_autotuner(mixed):
