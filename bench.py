@@ -354,27 +354,39 @@ def general_u_sigma(kbe, torch, G, n, w, reps=5):
 
 def batch_vs_plain(kbe, torch, dev, G, W, u, nrows=256, seed=1004, reps=5):
     """The same rows run both ways: 256 rows (n, m) of the 16-orbital headline system (n
-    log-uniform in [128, nt - 1], m uniform in 0..n), as one kbe_collision_batch launch (cross
-    storage: each row's kp column gathered, its kp row, tv row and weight rows in place) and as
-    256 plain kbe_collision calls on the system's KP storage (m-range [m, m + 1), I^R, I^<, I^]),
+    log-uniform in [128, nt - 1], m uniform in 0..n), as one kbe_collision_batch launch (items
+    reading the system's KP storage in place: kp column m with col_ld = ldt, kp row m, tv row m,
+    the weight rows) and as 256 plain kbe_collision calls (m-range [m, m + 1), I^R, I^<, I^]),
     with the outputs, workspace and arguments of the plain calls prepared beforehand.  Both read
-    the same algorithmic bytes; the plain calls' outputs are compared with the batch's."""
+    the same algorithmic bytes; the plain calls' outputs are compared with the batch's.  Then the
+    whole pipeline [self-energy rows -> batch] eager and captured as one graph, with the rows'
+    self-energies by one kbe_sigma_2b call each (and the columns gathered into arrays) or by one
+    kbe_sigma_2b_batch launch (and the columns read in place)."""
     import ctypes
     rng = np.random.default_rng(seed)
     nt = G.nt
     ns = np.minimum(np.exp(rng.uniform(np.log(128), np.log(nt - 1), nrows)).astype(int), nt - 1)
     ms = np.array([int(rng.integers(0, n + 1)) for n in ns])
     flags = kbe.OUT_IR | kbe.OUT_IL | kbe.OUT_ITV
-    sigs, items = {}, []
-    for n, m in zip(ns.tolist(), ms.tolist()):
-        if n not in sigs:
-            sigs[n] = kbe.sigma_2b(G, u, n)
-        sr = sigs[n]
-        items.append(kbe.BatchItem(n=n, m=m, sig_ret=sr[0], sig_les=sr[1],
-                                   col=G.kp[:m + 1, m].contiguous(), row=G.kp[m, :n + 1],
-                                   rdiag=G.rdiag[m], wn=W.w[n, :n + 1], wm=W.w[m, :m + 1],
-                                   sig_tv=sr[2], tv=G.tv[m], wtau=W.wtau, flags=flags))
-    batch = kbe.Batch(items)
+    distinct = sorted(set(ns.tolist()))
+    sigb = kbe.SigmaBatch([(G, u, n) for n in distinct])  # one launch for every row's Sigma
+    sigb.run()
+    sigs = dict(zip(distinct, sigb.rows))
+    ldt = G.kp.shape[1]
+
+    def make_items(in_place):
+        out = []
+        for n, m in zip(ns.tolist(), ms.tolist()):
+            sr = sigs[n]
+            col, cld = (G.kp[0, m], ldt) if in_place else (G.kp[:m + 1, m].contiguous(), 0)
+            out.append(kbe.BatchItem(n=n, m=m, sig_ret=sr[0], sig_les=sr[1], col=col,
+                                     row=G.kp[m, :n + 1], rdiag=G.rdiag[m], wn=W.w[n, :n + 1],
+                                     wm=W.w[m, :m + 1], sig_tv=sr[2], tv=G.tv[m], wtau=W.wtau,
+                                     flags=flags, col_ld=cld))
+        return out
+
+    items_ip, items_ga = make_items(True), make_items(False)
+    batch, batch_ga = kbe.Batch(items_ip), kbe.Batch(items_ga)
     best, _ = batch.tune()
     L = kbe.lib()
     N = G.N
@@ -410,54 +422,66 @@ def batch_vs_plain(kbe, torch, dev, G, W, u, nrows=256, seed=1004, reps=5):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / k
 
+    stack = lambda b: torch.stack([torch.stack([b.IR[i], b.IL[i], b.Itv[i]])
+                                   for i in range(nrows)])
     batched_ms = timed(lambda: batch.run(best), reps)
+    gathered_ms = timed(lambda: batch_ga.run(best), reps)
     plain_ms = timed(plain, reps)
-    IR, IL, Itv = batch.run(best)
     torch.cuda.synchronize()
-    got = torch.stack([torch.stack([IR[i], IL[i], Itv[i]]) for i in range(nrows)])
+    got, got_ga = stack(batch), stack(batch_ga)
     rel = float(((got - outs).abs().amax(dim=(2, 3)) /
                  outs.abs().amax(dim=(2, 3)).clamp_min(1e-300)).max())
-    # the whole pipeline [self-energy rows -> column gathers -> batch] eager and as one graph
     ud = u.contiguous()
 
-    def pipeline():
+    def pipeline(batched_sigma):
         st = torch.cuda.current_stream(dev).cuda_stream
-        for n in sigs:
+        if batched_sigma:
+            sigb.run()
+            batch.run(best)
+            return
+        for n in distinct:
             r = kbe._row(*sigs[n])
             if L.kbe_sigma_2b(ctypes.byref(gc), ud.data_ptr(), int(n), ctypes.byref(r), st):
                 raise RuntimeError("kbe_sigma_2b failed")
-        for it in items:
+        for it in items_ga:
             it.col.copy_(G.kp[:it.m + 1, it.m])
-        batch.run(best)
+        batch_ga.run(best)
 
-    pipeline_ms = timed(pipeline, reps)
-    side = torch.cuda.Stream(dev)
-    side.wait_stream(torch.cuda.current_stream(dev))
-    with torch.cuda.stream(side):
-        pipeline()
-    torch.cuda.current_stream(dev).wait_stream(side)
-    torch.cuda.synchronize()
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph):
-        pipeline()
-    graph_ms = timed(graph.replay, reps)
-    torch.cuda.synchronize()
-    same = all(torch.equal(torch.stack([IR[i], IL[i], Itv[i]]), got[i]) for i in range(nrows))
+    pipe = {}
+    for mode, bs, b, ref in (("sigma_per_row_columns_gathered", False, batch_ga, got_ga),
+                             ("sigma_batched_columns_in_place", True, batch, got)):
+        eager_ms = timed(lambda: pipeline(bs), reps)
+        side = torch.cuda.Stream(dev)
+        side.wait_stream(torch.cuda.current_stream(dev))
+        with torch.cuda.stream(side):
+            pipeline(bs)
+        torch.cuda.current_stream(dev).wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            pipeline(bs)
+        graph_ms = timed(graph.replay, reps)
+        torch.cuda.synchronize()
+        pipe[mode] = {"eager_ms": eager_ms, "graph_replay_ms": graph_ms,
+                      "graph_equals_eager": bool(torch.equal(stack(b), ref))}
+        del graph
+    sig_one_ms = timed(sigb.run, reps)
     nbytes = 0.0
     for n, m in zip(ns.tolist(), ms.tolist()):
         blocks = (n + 1) + (m + 1) + (n - m) + (m + 1) + m + 1 + 2 * G.ntau + 3  # as batching()
         nbytes += 16.0 * N * N * blocks + 8.0 * ((n + 1) + (m + 1) + G.ntau)
-    del batch, ws, outs, graph
+    same_ga = bool(torch.equal(got, got_ga))
+    del batch, batch_ga, ws, outs, sigb
     return {"workload": f"{nrows} rows (n, m) of the N{N}_nt{nt}_ntau{G.ntau} headline system, "
                         f"n log-uniform in [128, {nt - 1}], m uniform in 0..n; I^R, I^<, I^]",
-            "chunk": best, "batched_ms": batched_ms, "plain_calls_ms": plain_ms,
+            "chunk": best, "batched_ms": batched_ms, "batched_gathered_columns_ms": gathered_ms,
+            "in_place_equals_gathered": same_ga, "plain_calls_ms": plain_ms,
             "speedup_vs_plain": plain_ms / batched_ms, "algorithmic_bytes": nbytes,
             "batched_gbps": nbytes / batched_ms / 1e6, "plain_gbps": nbytes / plain_ms / 1e6,
             "max_rel_diff_batched_vs_plain": rel,
-            "pipeline": {"stages": f"{len(sigs)} kbe_sigma_2b rows -> {nrows} column gathers -> "
-                                   f"kbe_collision_batch",
-                         "eager_ms": pipeline_ms, "graph_replay_ms": graph_ms,
-                         "graph_equals_eager": bool(same)}}
+            "pipeline": {"stages": f"{len(distinct)} self-energy rows -> kbe_collision_batch "
+                                   f"over {nrows} rows",
+                         "sigma_batch_launch_ms": sig_one_ms, **pipe}}
 
 
 def batching(kbe, torch, dev, reps=10):

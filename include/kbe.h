@@ -260,6 +260,34 @@ kbe_status kbe_sigma_2b_full(const kbe_green *G, const double *u, const kbe_gree
                              void *stream);
 
 /* ---------------------------------------------------------------------------
+ * kbe_sigma_2b_batch — the rows of kbe_sigma_2b for many systems in one launch
+ * (a project addition, the self-energy stage of batched history rows): item i
+ * is row n of its own system (its own N, grid, storage and u), with the same
+ * formulas and element code as kbe_sigma_2b, so each row equals that call's bit
+ * for bit.
+ *
+ * items: host array of count items (validated here); items_dev: the same array
+ * in device memory (what the kernel reads; it must equal items when the work
+ * runs).  Nothing is copied from host memory and nothing is allocated, so the
+ * call can be captured in a HIP graph (with the kbe_collision_batch call that
+ * reads the rows).  Errors: KBE_EINVAL (NULL pointers, N, nt, ntau or ldt out
+ * of range), KBE_ERANGE (n outside [0, nt), count outside [0, KBE_BATCH_MAX]).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t N;                        /* orbitals, 1..KBE_NMAX */
+  int32_t nt;                       /* real-time points of the system's storage, >= 1 */
+  int32_t ntau;                     /* imaginary-time points: 0 or >= 2 */
+  int32_t n;                        /* the row, 0 <= n < nt */
+  int64_t ldt;                      /* kp row stride in blocks, >= nt */
+  const kbe_c128 *kp, *rdiag, *tv;  /* the system's G, as in kbe_green (tv NULL if ntau == 0) */
+  const double *u;                  /* [N] local interaction */
+  kbe_c128 *ret, *les, *stv;        /* out: [n+1], [n+1], [ntau] (stv NULL if ntau == 0) */
+} kbe_sigma_batch_item;
+
+kbe_status kbe_sigma_2b_batch(const kbe_sigma_batch_item *items,
+                              const kbe_sigma_batch_item *items_dev, int32_t count, void *stream);
+
+/* ---------------------------------------------------------------------------
  * kbe_sigma_gf2 — second-Born self-energy row at t_n with a general
  * four-index interaction (Eq. SE):
  *   Sigma^<>_ij(t,t') = sum U_ifde Uex_jabc G^<>_fb(t,t') G^<>_ea(t,t') G^><_cd(t',t)
@@ -385,7 +413,8 @@ kbe_status kbe_sigma_2b_vjp(const kbe_green *G, const double *u, int32_t n,
  * reads (its "cross" storage), all device memory with the item's own N:
  *   sig_ret, sig_les [n+1]  Sigma^R(t_n,t_s), Sigma^<(t_n,t_s), s = 0..n
  *   sig_tv  [ntau]          Sigma^](t_n,tau_j)
- *   col     [m+1]           kp[s][m] = G^<(t_s,t_m), s = 0..m
+ *   col     [m+1]           kp[s][m] = G^<(t_s,t_m), s = 0..m (block s at
+ *                           col + s * max(col_ld, 1) blocks)
  *   row     [n+1]           kp[m][s]: G^R(t_m,t_s) for s < m, G^<(t_m,t_s) for s >= m
  *   rdiag   [1]             G^R(t_m,t_m)
  *   tv      [ntau]          G^](t_m,tau_j)
@@ -409,6 +438,9 @@ typedef struct {
   const kbe_c128 *col, *row, *rdiag, *tv;
   const double *wn, *wm, *wtau;
   kbe_c128 *IR, *IL, *Itv; /* one block each; NULL when its flag is off */
+  int64_t col_ld;          /* blocks from col[s] to col[s+1]: 0 or 1 for a contiguous array;
+                              the system's ldt to read column m of its KP storage in place
+                              (col = kp + m blocks) */
 } kbe_batch_item;
 
 #define KBE_BATCH_MAX 65536 /* most items per call */

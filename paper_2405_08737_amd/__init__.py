@@ -89,11 +89,18 @@ class _Wts(ctypes.Structure):
     _fields_ = [("w", ctypes.c_void_p), ("wtau", ctypes.c_void_p), ("wtau_fwd", ctypes.c_void_p)]
 
 
+class _SigBatchItem(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("nt", ctypes.c_int32), ("ntau", ctypes.c_int32),
+                ("n", ctypes.c_int32), ("ldt", ctypes.c_int64)] + [
+        (name, ctypes.c_void_p) for name in ("kp", "rdiag", "tv", "u", "ret", "les", "stv")]
+
+
 class _BatchItem(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int32), ("n", ctypes.c_int32), ("m", ctypes.c_int32),
                 ("ntau", ctypes.c_int32), ("flags", ctypes.c_uint32), ("chunk", ctypes.c_int32)] + [
         (name, ctypes.c_void_p) for name in ("sig_ret", "sig_les", "sig_tv", "col", "row", "rdiag",
-                                             "tv", "wn", "wm", "wtau", "IR", "IL", "Itv")]
+                                             "tv", "wn", "wm", "wtau", "IR", "IL", "Itv")] + [
+        ("col_ld", ctypes.c_int64)]
 
 
 class _BatchVjpItem(ctypes.Structure):
@@ -106,6 +113,7 @@ EXPORTS = ("kbe_weights_workspace", "kbe_weights", "kbe_sigma_2b", "kbe_collisio
            "kbe_collision", "kbe_collision_noalloc", "kbe_collision_vjp_workspace",
            "kbe_collision_vjp",
            "kbe_sigma_2b_vjp_workspace", "kbe_sigma_2b_vjp", "kbe_sigma_2b_full",
+           "kbe_sigma_2b_batch",
            "kbe_sigma_gf2_workspace",
            "kbe_sigma_gf2", "kbe_collision_batch_workspace",
            "kbe_collision_batch", "kbe_collision_batch_tune", "kbe_collision_batch_tune_groups",
@@ -134,6 +142,7 @@ def lib():
             "kbe_weights": (I32, [GR, P, P, P, P, SZ, P]),
             "kbe_sigma_2b": (I32, [G, P, I32, R, P]),
             "kbe_sigma_2b_full": (I32, [G, P, G, P]),
+            "kbe_sigma_2b_batch": (I32, [P, P, I32, P]),
             "kbe_sigma_gf2_workspace": (SZ, [I32]),
             "kbe_sigma_gf2": (I32, [G, P, I32, R, P, SZ, P]),
             "kbe_collision_workspace": (SZ, [I32, I32, I32, I32, I32, I32, U32]),
@@ -467,7 +476,7 @@ class BatchItem:
     m: int
     sig_ret: torch.Tensor              # [n+1, N, N]
     sig_les: torch.Tensor              # [n+1, N, N]
-    col: torch.Tensor                  # [m+1, N, N]
+    col: torch.Tensor                  # [m+1, N, N]; or, with col_ld > 1, the first block
     row: torch.Tensor                  # [n+1, N, N]
     rdiag: torch.Tensor                # [N, N]
     wn: torch.Tensor                   # [n+1] float64
@@ -476,6 +485,7 @@ class BatchItem:
     tv: Optional[torch.Tensor] = None      # [ntau, N, N]
     wtau: Optional[torch.Tensor] = None    # [ntau] float64
     flags: int = OUT_IR | OUT_IL | OUT_ITV
+    col_ld: int = 0  # blocks between col[s] and col[s+1] (0: contiguous; a KP column: its ldt)
 
     @property
     def N(self):
@@ -508,7 +518,7 @@ class Batch:
                                  _ptr(it.sig_les), _ptr(it.sig_tv), _ptr(it.col), _ptr(it.row),
                                  _ptr(it.rdiag), _ptr(it.tv), _ptr(it.wn), _ptr(it.wm),
                                  _ptr(it.wtau), _ptr(self.IR[i]), _ptr(self.IL[i]),
-                                 _ptr(self.Itv[i]))
+                                 _ptr(self.Itv[i]), int(it.col_ld))
         self._host = host
         raw = bytes(host)[:ctypes.sizeof(_BatchItem) * self.count]
         self._dev = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(dev)
@@ -579,6 +589,39 @@ class Batch:
             self.apply_table(json.load(f)["chunk"])
 
 
+class SigmaBatch:
+    """Self-energy rows of many systems in one launch (kbe_sigma_2b_batch).  rows: a list of
+    (G, u, n) with G a Green (its own N, storage and grid), u [N] float64 on the device and n the
+    row.  The outputs self.rows[i] = (ret[n+1], les[n+1], stv[ntau] or None), the item table
+    (host and device copy) are allocated once; run() only enqueues the call, so it can be captured
+    in a graph."""
+
+    def __init__(self, rows, device=None):
+        self.specs = list(rows)
+        self.count = len(self.specs)
+        dev = device if device is not None else (self.specs[0][0].device if self.specs else None)
+        self.device = dev
+        host = (_SigBatchItem * max(self.count, 1))()
+        self.rows = []
+        for i, (G, u, n) in enumerate(self.specs):
+            mk = lambda k: torch.empty((k, G.N, G.N), dtype=torch.complex128, device=dev)
+            out = (mk(n + 1), mk(n + 1), mk(G.ntau) if G.ntau else None)
+            self.rows.append(out)
+            host[i] = _SigBatchItem(G.N, G.nt, G.ntau, int(n), G.kp.shape[1], _ptr(G.kp),
+                                    _ptr(G.rdiag), _ptr(G.tv) if G.ntau else None, _ptr(u),
+                                    _ptr(out[0]), _ptr(out[1]), _ptr(out[2]))
+        self._host = host
+        raw = bytes(host)[:ctypes.sizeof(_SigBatchItem) * self.count]
+        self._dev = (torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(dev)
+                     if self.count else None)
+
+    def run(self):
+        _check(lib().kbe_sigma_2b_batch(self._host, _ptr(self._dev), self.count,
+                                        _stream(self.device) if self.count else None),
+               "kbe_sigma_2b_batch")
+        return self.rows
+
+
 class BatchVJP:
     """The adjoint of a fixed batch of rows (kbe_collision_batch_vjp): items as for Batch, cot a
     list of (gIR, gIL, gItv) N x N cotangent tensors per item (None where a flag is off).  The
@@ -604,7 +647,8 @@ class BatchVJP:
             self.g.append(g)
             row = _BatchItem(N, n, m, nt, it.flags, 0, _ptr(it.sig_ret), _ptr(it.sig_les),
                              _ptr(it.sig_tv), _ptr(it.col), _ptr(it.row), _ptr(it.rdiag),
-                             _ptr(it.tv), _ptr(it.wn), _ptr(it.wm), _ptr(it.wtau), None, None, None)
+                             _ptr(it.tv), _ptr(it.wn), _ptr(it.wm), _ptr(it.wtau), None, None, None,
+                             int(it.col_ld))
             host[i] = _BatchVjpItem(row, _ptr(c[0]), _ptr(c[1]), _ptr(c[2]), _ptr(g["sig_ret"]),
                                     _ptr(g["sig_les"]), _ptr(g["sig_tv"]), _ptr(g["col"]),
                                     _ptr(g["row"]), _ptr(g["rdiag"]), _ptr(g["tv"]))

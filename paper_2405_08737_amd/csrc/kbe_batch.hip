@@ -72,6 +72,11 @@ __host__ __device__ inline void item_chunks(const kbe_batch_item &it, int call_c
   c[3] = itv ? (it.ntau + chunk - 1) / chunk : 0;
 }
 
+// Blocks from col[s] to col[s+1] (a contiguous array, or a column of a KP storage read in place).
+__host__ __device__ inline int64_t col_step(const kbe_batch_item &it) {
+  return it.col_ld > 1 ? it.col_ld : 1;
+}
+
 // Term t of class k of an item: real weight w, complex factor (fr + i fi), Q and P blocks.
 struct Term {
   double w;
@@ -80,7 +85,7 @@ struct Term {
 __device__ __forceinline__ Term item_term(const kbe_batch_item &it, int k, int t) {
   const int64_t E = (int64_t)it.N * it.N;
   switch (k) {
-    case 0: return {it.wn[t], it.sig_ret + t * E, it.col + t * E};
+    case 0: return {it.wn[t], it.sig_ret + t * E, it.col + t * col_step(it) * E};
     case 1: return {it.wn[t], it.sig_ret + t * E, it.row + t * E};
     case 2: return {it.wm[t], it.sig_les + t * E, t < it.m ? it.row + t * E : it.rdiag};
     default: return {it.wtau[t], it.sig_tv + t * E, it.tv + (it.ntau - 1 - t) * E};
@@ -675,7 +680,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) b
     // streamed block of output block s, and its scalar
     auto xblk = [&](int s) -> const kbe_c128 * {
       switch (k) {
-        case 0: return r.col + (int64_t)s * E;
+        case 0: return r.col + (int64_t)s * col_step(r) * E;
         case 1: return r.row + (int64_t)s * E;
         case 2: return s < r.m ? r.row + (int64_t)s * E : r.rdiag;
         case 4: case 5: return r.sig_ret + (int64_t)s * E;

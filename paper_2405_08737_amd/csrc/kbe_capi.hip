@@ -189,6 +189,35 @@ kbe_status kbe_sigma_2b_full(const kbe_green *G, const double *u, const kbe_gree
   return hip_status(kbe::launch_sigma_full(G, u, S, (hipStream_t)stream), "kbe_sigma_2b_full");
 }
 
+kbe_status kbe_sigma_2b_batch(const kbe_sigma_batch_item *items,
+                              const kbe_sigma_batch_item *items_dev, int32_t count, void *stream) {
+  if (count < 0 || count > KBE_BATCH_MAX)
+    return fail(KBE_ERANGE, "count = %d outside [0, %d]", count, KBE_BATCH_MAX);
+  if (count == 0) return ok();
+  if (!items || !items_dev) return fail(KBE_EINVAL, "items or items_dev is NULL");
+  int64_t max_elems = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    const kbe_sigma_batch_item &it = items[i];
+    if (it.N < 1 || it.N > KBE_NMAX)
+      return fail(KBE_EINVAL, "item %d: N = %d outside 1..%d", i, it.N, KBE_NMAX);
+    if (it.nt < 1) return fail(KBE_EINVAL, "item %d: nt = %d < 1", i, it.nt);
+    if (it.ntau < 0 || it.ntau == 1)
+      return fail(KBE_EINVAL, "item %d: ntau = %d (must be 0 or >= 2)", i, it.ntau);
+    if (it.ldt < it.nt)
+      return fail(KBE_EINVAL, "item %d: ldt = %lld < nt = %d", i, (long long)it.ldt, it.nt);
+    if (it.n < 0 || it.n >= it.nt)
+      return fail(KBE_ERANGE, "item %d: n = %d outside [0, nt = %d)", i, it.n, it.nt);
+    if (!it.kp || !it.rdiag || !it.u || !it.ret || !it.les)
+      return fail(KBE_EINVAL, "item %d: kp, rdiag, u, ret or les is NULL", i);
+    if (it.ntau > 0 && (!it.tv || !it.stv))
+      return fail(KBE_EINVAL, "item %d: tv or stv is NULL with ntau > 0", i);
+    const int64_t e = (int64_t)(it.n + 1 + it.ntau) * it.N * it.N;
+    max_elems = e > max_elems ? e : max_elems;
+  }
+  return hip_status(kbe::launch_sigma_batch(items_dev, count, max_elems, (hipStream_t)stream),
+                    "kbe_sigma_2b_batch");
+}
+
 size_t kbe_sigma_gf2_workspace(int32_t N) {
   if (N < 1 || N > KBE_NMAX) return 0;
   return kbe::gf2_ws_bytes(N);
@@ -544,6 +573,8 @@ static kbe_status check_batch(const kbe_batch_item *items, const kbe_batch_item 
       return fail(KBE_EINVAL, "item %d: ntau = %d (must be 0 or >= 2)", i, it.ntau);
     if (!batch_chunk_ok(it.chunk))
       return fail(KBE_EINVAL, "item %d: chunk = %d not in {0, 32, 64, 128, 256}", i, it.chunk);
+    if (it.col_ld < 0)
+      return fail(KBE_EINVAL, "item %d: col_ld = %lld < 0", i, (long long)it.col_ld);
     if (it.flags & KBE_OUT_IR) {
       if (!it.IR || !it.sig_ret || !it.col || !it.wn || (it.n > it.m && !it.row))
         return fail(KBE_EINVAL, "item %d: I^R needs IR, sig_ret, col, wn (and row when n > m)", i);
@@ -643,6 +674,8 @@ static kbe_status check_batch_vjp(const kbe_batch_vjp_item *items,
       return fail(KBE_ERANGE, "item %d: (n, m) = (%d, %d) needs 0 <= m <= n", i, it.n, it.m);
     if (it.ntau < 0 || it.ntau == 1)
       return fail(KBE_EINVAL, "item %d: ntau = %d (must be 0 or >= 2)", i, it.ntau);
+    if (it.col_ld < 0)
+      return fail(KBE_EINVAL, "item %d: col_ld = %lld < 0", i, (long long)it.col_ld);
     if (!v.g_sig_ret || !v.g_sig_les || !v.g_col || !v.g_row || !v.g_rdiag ||
         (it.ntau > 0 && (!v.g_sig_tv || !v.g_tv)))
       return fail(KBE_EINVAL, "item %d: a gradient array is NULL", i);

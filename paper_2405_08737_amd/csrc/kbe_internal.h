@@ -26,6 +26,8 @@ hipError_t launch_interval_weights(double *t, int n, double tn, int kam, int kab
 // Self-energy and its adjoint (kbe_sigma.hip).
 hipError_t launch_sigma_row(const kbe_green *G, const double *u, int n, const kbe_sigma_row *out,
                             hipStream_t st);
+hipError_t launch_sigma_batch(const kbe_sigma_batch_item *items_dev, int count, int64_t max_elems,
+                              hipStream_t st);
 hipError_t launch_sigma_full(const kbe_green *G, const double *u, const kbe_green *S,
                              hipStream_t st);
 size_t sigma_vjp_ws_bytes(int N, int n, int ntau);

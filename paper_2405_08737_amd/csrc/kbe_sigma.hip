@@ -21,10 +21,11 @@ struct SigArgs {
   const double *u;
 };
 
-__global__ void __launch_bounds__(256) sigma_row_kernel(SigArgs a, kbe_c128 *ret, kbe_c128 *les,
-                                                        kbe_c128 *stv) {
+// Element idx of the row at t_n: the first (n+1) N^2 are Sigma^R and Sigma^< at (t_n, t_s), the
+// next ntau N^2 are Sigma^](t_n, tau_l).
+__device__ __forceinline__ void sigma_row_elem(const SigArgs &a, int64_t idx, kbe_c128 *ret,
+                                               kbe_c128 *les, kbe_c128 *stv) {
   const int64_t E = (int64_t)a.N * a.N;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nrt = (int64_t)(a.n + 1) * E;
   if (idx < nrt) {
     const int s = (int)(idx / E), e = (int)(idx % E), i = e / a.N, j = e % a.N;
@@ -55,6 +56,35 @@ __global__ void __launch_bounds__(256) sigma_row_kernel(SigArgs a, kbe_c128 *ret
     const cd y = ld(a.tv + ((int64_t)a.n * a.ntau + (a.J - l)) * E + e);
     st(stv + (int64_t)l * E + e, U * (x * x * cj(y)));
   }
+}
+
+__global__ void __launch_bounds__(256) sigma_row_kernel(SigArgs a, kbe_c128 *ret, kbe_c128 *les,
+                                                        kbe_c128 *stv) {
+  sigma_row_elem(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, ret, les, stv);
+}
+
+// Rows of many systems: blockIdx.y is the item; the item's workgroups stride over its elements.
+__global__ void __launch_bounds__(256) sigma_batch_kernel(const kbe_sigma_batch_item *items) {
+  const kbe_sigma_batch_item it = items[blockIdx.y];
+  const SigArgs a{it.N, it.ntau, it.ntau - 1, it.n, it.ldt, it.kp, it.rdiag, it.tv, it.u};
+  const int64_t tot = (int64_t)(it.n + 1 + it.ntau) * it.N * it.N;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < tot; idx += stride)
+    sigma_row_elem(a, idx, it.ret, it.les, it.stv);
+}
+
+hipError_t launch_sigma_batch(const kbe_sigma_batch_item *items_dev, int count, int64_t max_elems,
+                              hipStream_t st) {
+  // workgroups per item: enough for the longest row at four elements per thread, at most 256
+  int64_t per = (max_elems + 4 * 256 - 1) / (4 * 256);
+  per = per < 1 ? 1 : (per > 256 ? 256 : per);
+  constexpr int YMAX = 32768;  // items per launch (grid y)
+  for (int off = 0; off < count; off += YMAX) {
+    const int c = count - off < YMAX ? count - off : YMAX;
+    hipLaunchKernelGGL(sigma_batch_kernel, dim3((unsigned)per, (unsigned)c), dim3(256), 0, st,
+                       items_dev + off);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_sigma_row(const kbe_green *G, const double *u, int n, const kbe_sigma_row *out,

@@ -211,6 +211,9 @@ def test_batch_argument_errors():
     assert batch_call([batch_item()], chunk=48) == EINVAL
     assert batch_call([batch_item(chunk=100)]) == EINVAL   # an item's own chunk is checked too
     assert batch_call([batch_item(chunk=-32)]) == EINVAL
+    it = batch_item()
+    it.col_ld = -1
+    assert batch_call([it]) == EINVAL and "col_ld" in err()
     assert batch_call([batch_item()], count=65537) == ERANGE
     it = batch_item()
     it.IR = None
@@ -369,3 +372,35 @@ def test_equilibrium_argument_errors_and_workspace():
     assert call(maxit=0) == 1 and "maxit" in err()
     assert call(ws_bytes=16) == 3
     assert L.kbe_status_string(kbe.KBE_ECONV).decode().startswith("KBE_ECONV")
+
+
+def test_sigma_batch_argument_errors():
+    L = kbe.lib()
+
+    def item(**kw):
+        d = dict(N=3, nt=10, ntau=4, n=9, ldt=10)
+        d.update(kw)
+        it = kbe._SigBatchItem(d["N"], d["nt"], d["ntau"], d["n"], d["ldt"], FAKE, FAKE, FAKE,
+                               FAKE, FAKE, FAKE, FAKE)
+        for k in ("kp", "rdiag", "tv", "u", "ret", "les", "stv"):
+            if k in kw and kw[k] is None:
+                setattr(it, k, None)
+        return it
+
+    def call(items, count=None, dev=FAKE):
+        arr = (kbe._SigBatchItem * max(len(items), 1))(*items)
+        return L.kbe_sigma_2b_batch(arr, dev, len(items) if count is None else count, None)
+
+    assert call([]) == 0
+    assert call([item()], count=-1) == 2 and "count" in err()
+    assert call([item()], dev=None) == 1
+    assert call([item(N=0)]) == 1 and "N" in err()
+    assert call([item(N=17)]) == 1
+    assert call([item(nt=0)]) == 1
+    assert call([item(ntau=1)]) == 1 and "ntau" in err()
+    assert call([item(ldt=9)]) == 1 and "ldt" in err()
+    assert call([item(n=10)]) == 2 and "n = 10" in err()
+    assert call([item(n=-1)]) == 2
+    for k in ("kp", "rdiag", "u", "ret", "les"):
+        assert call([item(**{k: None})]) == 1 and "NULL" in err()
+    assert call([item(tv=None)]) == 1 and "tv" in err()

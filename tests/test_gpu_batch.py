@@ -136,13 +136,14 @@ def test_batch_graph_capture_replay(mixed):
     _check(batch, refs)
 
 
-def test_batch_graph_with_sigma_rows(gpu):
+@pytest.mark.parametrize("sigma", ["per_row", "batched"])
+def test_batch_graph_with_sigma_rows(gpu, sigma):
     """[self-energy rows -> kbe_collision_batch (plan, stream, reduce)] as one captured graph, for
-    rows of two systems held in KP storage on the device (N = 4 and 16): kbe_sigma_2b writes each
-    row's self-energy, the rows' kp columns are gathered, and the batch reads both.  Every replay
-    (outputs and intermediates set to NaN before it, with eager work and synchronisation between
-    replays) equals the eager pipeline bit for bit, and that matches the oracle (its own
-    self-energy rows) to the FP64 bar."""
+    rows of two systems held in KP storage on the device (N = 4 and 16): the rows' self-energies
+    (kbe_sigma_2b per row, with the rows' kp columns gathered into arrays; or every row in one
+    kbe_sigma_2b_batch launch, with the columns read in place) and the batch reading both.  Every replay (outputs and intermediates set to NaN
+    before it, with eager work and synchronisation between replays) equals the eager pipeline bit
+    for bit, and that matches the oracle (its own self-energy rows) to the FP64 bar."""
     import ctypes
     import torch
     kbe = gpu
@@ -158,18 +159,22 @@ def test_batch_graph_with_sigma_rows(gpu):
     rows = [(0, 39, 0), (0, 39, 39), (0, 25, 11), (0, 10, 10), (1, 29, 3), (1, 29, 29),
             (1, 17, 9), (1, 0, 0)]
     z = lambda *sh: torch.empty(sh, dtype=torch.complex128, device="cuda")
+    sigb = kbe.SigmaBatch([(systems[si]["Gd"], systems[si]["ud"], n) for si, n, _ in rows])
     sig_bufs, col_bufs, items, refs = [], [], [], []
-    for si, n, m in rows:
+    for r, (si, n, m) in enumerate(rows):
         S = systems[si]
         N, ntau, Gd, Wd = S["N"], S["ntau"], S["Gd"], S["Wd"]
-        sb = (z(n + 1, N, N), z(n + 1, N, N), z(ntau, N, N))
-        cb = z(m + 1, N, N)
+        sb = sigb.rows[r]
         sig_bufs.append((si, n, sb))
-        col_bufs.append((si, m, cb))
+        if sigma == "batched":  # kp column m in place: block s at kp + (s ldt + m) blocks
+            cb, cld = Gd.kp[0, m], Gd.kp.shape[1]
+        else:
+            cb, cld = z(m + 1, N, N), 0
+            col_bufs.append((si, m, cb))
         items.append(kbe.BatchItem(n=n, m=m, sig_ret=sb[0], sig_les=sb[1], col=cb,
                                    row=Gd.kp[m, :n + 1], rdiag=Gd.rdiag[m], wn=Wd.w[n, :n + 1],
                                    wm=Wd.w[m, :m + 1], sig_tv=sb[2], tv=Gd.tv[m], wtau=Wd.wtau,
-                                   flags=F3))
+                                   flags=F3, col_ld=cld))
         sig = oracle.sigma_row(S["G"], S["u"], n)
         IR, IL, Itv, _ = oracle.collision(S["G"], sig, S["W"], n, m, m + 1, F3)
         cr = dict(ret=sig[0], les=sig[1], stv=sig[2], col=S["kp"][:m + 1, m],
@@ -180,11 +185,14 @@ def test_batch_graph_with_sigma_rows(gpu):
 
     def pipeline():
         st = torch.cuda.current_stream().cuda_stream
-        for si, n, sb in sig_bufs:
-            S = systems[si]
-            row = kbe._row(*sb)
-            assert L.kbe_sigma_2b(ctypes.byref(S["Gd"].c()), S["ud"].data_ptr(), n,
-                                  ctypes.byref(row), st) == 0
+        if sigma == "batched":
+            sigb.run()
+        else:
+            for si, n, sb in sig_bufs:
+                S = systems[si]
+                row = kbe._row(*sb)
+                assert L.kbe_sigma_2b(ctypes.byref(S["Gd"].c()), S["ud"].data_ptr(), n,
+                                      ctypes.byref(row), st) == 0
         for si, m, cb in col_bufs:
             cb.copy_(systems[si]["Gd"].kp[:m + 1, m])
         batch.run(64)
@@ -217,6 +225,58 @@ def test_batch_graph_with_sigma_rows(gpu):
         torch.cuda.synchronize()
         for a, b in zip(outs(), eager):
             assert np.array_equal(a, b), rep
+
+
+def test_batch_columns_in_place(gpu):
+    """Items that read kp column m of a KP storage in place (col_ld = ldt) give bit for bit the
+    results of the same items over gathered column arrays, forward (kbe_collision_batch) and
+    adjoint (kbe_collision_batch_vjp), for rows of two systems (N = 3 and 16, one with a padded
+    row stride)."""
+    import torch
+    kbe = gpu
+    F = 0x1 | 0x2 | 0x4
+    built = []
+    for N, nt, ntau, seed, pad in [(3, 45, 6, 41, 0), (16, 28, 5, 42, 5)]:
+        S = _system(N, nt, ntau, seed)
+        kp = S["kp"]
+        if pad:
+            kpp = np.zeros((nt, nt + pad, N, N), np.complex128)
+            kpp[:, :nt] = kp
+            kp = kpp
+        Gd = kbe.Green(to_dev(kp), to_dev(S["rd"]), to_dev(S["tv"]), to_dev(S["mat"]))
+        built.append((S, Gd, device_weights(S["W"])))
+    rows = [(0, 44, 0), (0, 44, 44), (0, 30, 12), (0, 0, 0), (1, 27, 27), (1, 27, 4),
+            (1, 15, 15), (1, 9, 2)]
+    both = {}
+    for mode in ("gathered", "in_place"):
+        items, cots = [], []
+        for r, (si, n, m) in enumerate(rows):
+            S, Gd, Wd = built[si]
+            N = S["N"]
+            ret, les, stv = synth.sigma_row(500 + r, N, n, S["ntau"], S["t"])
+            if mode == "in_place":
+                col, cld = Gd.kp[0, m], Gd.kp.shape[1]
+            else:
+                col, cld = Gd.kp[:m + 1, m].contiguous(), 0
+            items.append(kbe.BatchItem(n=n, m=m, sig_ret=to_dev(ret), sig_les=to_dev(les),
+                                       col=col, row=Gd.kp[m, :n + 1], rdiag=Gd.rdiag[m],
+                                       wn=Wd.w[n, :n + 1], wm=Wd.w[m, :m + 1], sig_tv=to_dev(stv),
+                                       tv=Gd.tv[m], wtau=Wd.wtau, flags=F, col_ld=cld))
+            cots.append(tuple(to_dev(synth.normal(600 + r, k, (N, N))) for k in range(3)))
+        b = kbe.Batch(items)
+        b.run(32)
+        v = kbe.BatchVJP(items, cots)
+        v.run()
+        torch.cuda.synchronize()
+        both[mode] = ([to_host(x) for x in b.IR + b.IL + b.Itv],
+                      [{k: to_host(x) for k, x in g.items()} for g in v.g])
+    fa, ga = both["gathered"]
+    fb, gb = both["in_place"]
+    for x, y in zip(fa, fb):
+        assert np.array_equal(x, y)
+    for x, y in zip(ga, gb):
+        for k in x:
+            assert (x[k] is None and y[k] is None) or np.array_equal(x[k], y[k]), k
 
 
 def test_batch_autotuner(mixed):

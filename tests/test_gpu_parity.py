@@ -128,6 +128,46 @@ def test_sigma_row_matches_oracle(gpu, N, n):
         assert np.all(d <= 1e-13 * (bnorm(r) + 1e-300) + 1e-300)
 
 
+def test_sigma_batch_matches_oracle_and_rows(gpu):
+    """kbe_sigma_2b_batch over rows of systems with different N (1, 3, 8, 16), storage (a padded
+    row stride) and thermal branches (none, 12 and 7 tau points): every row against the oracle
+    (as test_sigma_row_matches_oracle) and bit for bit against kbe_sigma_2b on its own."""
+    import torch
+    kbe = gpu
+    specs = [(1, 30, 0, 21, 0), (3, 50, 12, 22, 7), (8, 40, 7, 23, 0), (16, 25, 12, 24, 0)]
+    systems, rows = [], []
+    for N, nt, ntau, seed, pad in specs:
+        case = Case(N=N, nt=nt, ntau=ntau, beta=3.0, seed=seed)
+        t, order, kp, rd, tv, mat = case.host()
+        if pad:
+            kpp = np.zeros((nt, nt + pad, N, N), np.complex128)
+            kpp[:, :nt] = kp
+            kp = kpp
+        u = np.linspace(0.5, 1.3, N)
+        Gd = kbe.Green(to_dev(kp), to_dev(rd), to_dev(tv) if ntau else None,
+                       to_dev(mat) if ntau else None)
+        systems.append(dict(G=oracle.Green(kp[:, :nt] if pad else kp, rd, tv if ntau else None,
+                                           mat if ntau else None), Gd=Gd, u=u, ud=to_dev(u)))
+        for n in sorted({0, nt // 3, nt - 1}):
+            rows.append((len(systems) - 1, n))
+    sb = kbe.SigmaBatch([(systems[si]["Gd"], systems[si]["ud"], n) for si, n in rows])
+    _print("sigma batch", len(rows), "rows")
+    got = sb.run()
+    torch.cuda.synchronize()
+    for (si, n), g in zip(rows, got):
+        S = systems[si]
+        ref = oracle.sigma_row(S["G"], S["u"], n)
+        one = kbe.sigma_2b(S["Gd"], S["ud"], n)
+        for x, r, o in zip(g, ref, one):
+            if x is None:
+                assert r.shape[0] == 0 and o is None
+                continue
+            x = to_host(x)
+            d = bnorm(x - r)
+            assert np.all(d <= 1e-13 * (bnorm(r) + 1e-300) + 1e-300), (si, n)
+            assert np.array_equal(x, to_host(o)), (si, n)
+
+
 def test_collision_parity_small(gpu):
     """N = 2, nt = 64, ntau = 64, beta = 10, order 5: every output for every m."""
     kbe = gpu
