@@ -141,6 +141,61 @@ def cpu_model():
     return "unknown"
 
 
+def cpu_other_rows(w, host, threads):
+    """The oracle, as it stands, on bounded samples of the other benchmarked calls, for the
+    GPU figures beside it: the whole forward row of the 8-orbital differentiation workload
+    (n = 1023, all m, all four integrals), the 32 shortest rows of the batching workload (their
+    own weights, I^R, I^<, I^]), and the general four-index self-energy of the headline row at 64
+    real-time pairs and 32 tau points.  Rates count the same algorithmic FLOP as the GPU objects."""
+    import oracle
+    import synth
+    oracle.set_threads(threads)
+    out = {}
+    d = synth.DIFFERENTIATION
+    t, order = synth.grid(d.seed, d.nt, d.hmin, d.hmax, d.omin, d.omax)
+    G = oracle.Green(synth.kp(d.seed, d.N, t), synth.rdiag(d.N, d.nt),
+                     synth.tv(d.seed, d.N, d.ntau, t), synth.mat(d.seed, d.N, d.ntau))
+    W = oracle.Weights.build(t, order, d.beta, d.ntau, d.tau_order)
+    n = d.nt - 1
+    sig = oracle.sigma_row(G, np.full(d.N, d.U), n)
+    t0 = time.perf_counter()
+    oracle.collision(G, sig, W, n)
+    dt = time.perf_counter() - t0
+    fl = counts(d.N, d.nt, d.ntau, n)["fwd_flop"]
+    out["small_orbital"] = {"sample": f"{d.name}: the whole forward row n={n}", "seconds": dt,
+                            "gflops": fl / dt / 1e9}
+    del G, W, sig
+    B = synth.BATCH
+    specs = sorted(synth.batch_specs(B["seed"], B["count"], B["Ns"], B["nmin"], B["nmax"]),
+                   key=lambda sp: sp.n)[:32]
+    fl, dt = 0.0, 0.0
+    for sp in specs:
+        cr = synth.batch_cross(sp, B["ntau"], B["hmin"], B["hmax"], B["omin"], B["omax"])
+        Wb = oracle.Weights.build(cr["t"], cr["order"], B["beta"], B["ntau"], B["tau_order"])
+        t0 = time.perf_counter()
+        oracle.collision_row(sp.N, B["ntau"], sp.n, sp.m, (cr["ret"], cr["les"], cr["stv"]),
+                             cr["col"], cr["row"], cr["rdiag"], cr["tv"], Wb.w[sp.n],
+                             Wb.w[sp.m, :sp.m + 1], Wb.wfull)
+        dt += time.perf_counter() - t0
+        fl += 8.0 * sp.N ** 3 * ((sp.n + 1) + (sp.m + 1) + B["ntau"])
+    out["batching"] = {"sample": "the 32 shortest rows of the batching workload "
+                                 f"(n {specs[0].n}..{specs[-1].n})",
+                       "seconds": dt, "gflops": fl / dt / 1e9}
+    t, order, kp, rd, tv, mat = host
+    Gh = oracle.Green(kp, rd, tv, mat)
+    U = synth.coulomb(w.seed, w.N)
+    n = w.nt - 1
+    s_list, l_list = list(range(n - 63, n + 1)), list(range(32))
+    t0 = time.perf_counter()
+    oracle.sigma_gf2_row(Gh, U, n, s_list=s_list, l_list=l_list)
+    dt = time.perf_counter() - t0
+    fl = 24.0 * w.N ** 5 * (2 * len(s_list) + len(l_list))
+    out["gf2"] = {"sample": f"{w.name} row n={n}: 64 real-time pairs (both components) and 32 "
+                            "tau points", "seconds": dt, "gflops": fl / dt / 1e9}
+    oracle.set_threads(threads)
+    return out
+
+
 def cpu_baseline(w, host, target_s=6.0):
     """The oracle, as it stands, timed on the host cores (median of 3 runs each): the small parity
     workload (N = 2, nt = 64, ntau = 64: the whole row) and the headline workload, at one thread
@@ -975,6 +1030,15 @@ def main():
         if replays:
             log("oracle replaying the adaptive prefixes")
             result["cpu_baseline"]["adaptive"] = adaptive_oracle(replays)
+        log("oracle on samples of the other calls")
+        other = cpu_other_rows(w, (t, order, kp_h, rd_h, tv_h, mat_h),
+                               result["cpu_baseline"]["cores"])
+        gpu_rates = {"small_orbital": result["small_orbital"]["collision_gflops"],
+                     "batching": result["batching"]["gflops"],
+                     "gf2": result["gf2"]["tflops"] * 1e3}
+        for k, v in other.items():
+            v["gpu_gflops"] = gpu_rates[k]
+        result["cpu_baseline"]["other_calls"] = other
     print(json.dumps(result), flush=True)
 
 
