@@ -357,7 +357,8 @@ def graph_pair(kbe, torch, G, u, n, t, order, w, reps=10):
 
 def greater_form(kbe, torch, G, u, n, t, order, w, cot, gG, reps=3):
     """The greater form of Eq. KBE2 (KBE_GREATER) on the headline row: kbe_collision and
-    kbe_collision_vjp (overwrite mode) back to back, against the lesser form in the same run."""
+    kbe_collision_vjp (overwrite mode) back to back, against the lesser form in the same run;
+    and kbe_collision_both (both forms from one pass) against the lesser form alone."""
     W = kbe.weights(t, order, G.ntau, w.beta, w.tau_order, device=G.device)
     sig = kbe.sigma_2b(G, u, n)
     ev = lambda: torch.cuda.Event(enable_timing=True)
@@ -381,6 +382,21 @@ def greater_form(kbe, torch, G, u, n, t, order, w, cot, gG, reps=3):
                      "collision_vjp_ms": e[1].elapsed_time(e[2]) / reps}
     out["greater_over_lesser"] = {k: out["greater"][k] / out["lesser"][k]
                                   for k in ("collision_ms", "collision_vjp_ms")}
+    # both forms from one pass (kbe_collision_both: the propagations' call), against the lesser
+    # form alone and against the two separate calls
+    kbe.collision_both(G, sig, W, n)
+    torch.cuda.synchronize()
+    e0, e1 = ev(), ev()
+    e0.record()
+    for _ in range(reps):
+        kbe.collision_both(G, sig, W, n)
+    e1.record()
+    torch.cuda.synchronize()
+    both = e0.elapsed_time(e1) / reps
+    out["both_forms"] = {"collision_ms": both,
+                         "over_lesser": both / out["lesser"]["collision_ms"],
+                         "over_separate_calls": both / (out["lesser"]["collision_ms"] +
+                                                        out["greater"]["collision_ms"])}
     return out
 
 

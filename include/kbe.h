@@ -339,6 +339,34 @@ kbe_status kbe_collision(const kbe_green *G, const kbe_sigma_row *S, const kbe_w
                          kbe_c128 *Itv, kbe_c128 *Jtv, void *ws, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * kbe_collision_both — the lesser and the greater form of Eq. KBE2 from one
+ * pass over the history (the call the propagations make at every evaluation:
+ * the paper propagates G^< above the diagonal by the lesser form and G^> below
+ * it by the greater form, Sec. "Kadanoff Baym Equations").
+ *
+ * Outputs IR, IL, Itv, Jtv as kbe_collision's lesser form with KBE_OUT_ALL,
+ * and IRg, ILg as its greater form's I^R and I^< (KBE_GREATER).  The terms the
+ * forms share (I^R's G^< part, I^]) are computed once, the greater form's own
+ * terms (the G^R part of G^>, and Sigma^> = Sigma^R + Sigma^< in I^<) are added
+ * as further term classes of the same persistent launch, so the upper triangle
+ * of kp is read as often as by the lesser form alone.  Each output equals the
+ * separate call's to rounding (the partial sums are grouped differently).
+ *
+ * Arguments: as kbe_collision with flags KBE_OUT_ALL (S needs ret, les and, with
+ * ntau > 0, tv; W needs w and, with ntau > 0, wtau and wtau_fwd); IR, IL, IRg,
+ * ILg device [m1-m0][N][N]; Itv device [m1-m0][N][N] and Jtv device
+ * [ntau][N][N] when ntau > 0 (else ignored); ws device workspace of
+ * kbe_collision_both_workspace(...) bytes.  Always the default kernel path.
+ * Errors: as kbe_collision.
+ * ------------------------------------------------------------------------- */
+size_t kbe_collision_both_workspace(int32_t N, int32_t nt, int32_t ntau, int32_t n, int32_t m0,
+                                    int32_t m1);
+kbe_status kbe_collision_both(const kbe_green *G, const kbe_sigma_row *S, const kbe_wts *W,
+                              int32_t n, int32_t m0, int32_t m1, kbe_c128 *IR, kbe_c128 *IL,
+                              kbe_c128 *Itv, kbe_c128 *Jtv, kbe_c128 *IRg, kbe_c128 *ILg,
+                              void *ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
  * kbe_collision_noalloc — kbe_collision for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc): the same integrals, arguments and errors as

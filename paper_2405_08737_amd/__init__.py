@@ -110,7 +110,8 @@ class _BatchVjpItem(ctypes.Structure):
 
 
 EXPORTS = ("kbe_weights_workspace", "kbe_weights", "kbe_sigma_2b", "kbe_collision_workspace",
-           "kbe_collision", "kbe_collision_noalloc", "kbe_collision_vjp_workspace",
+           "kbe_collision", "kbe_collision_noalloc", "kbe_collision_both_workspace",
+           "kbe_collision_both", "kbe_collision_vjp_workspace",
            "kbe_collision_vjp",
            "kbe_sigma_2b_vjp_workspace", "kbe_sigma_2b_vjp", "kbe_sigma_2b_full",
            "kbe_sigma_2b_batch",
@@ -148,6 +149,8 @@ def lib():
             "kbe_collision_workspace": (SZ, [I32, I32, I32, I32, I32, I32, U32]),
             "kbe_collision": (I32, [G, R, W, I32, I32, I32, U32, P, P, P, P, P, SZ, P]),
             "kbe_collision_noalloc": (I32, [G, R, W, I32, I32, I32, U32, P, P, P, P, P]),
+            "kbe_collision_both_workspace": (SZ, [I32, I32, I32, I32, I32, I32]),
+            "kbe_collision_both": (I32, [G, R, W, I32, I32, I32, P, P, P, P, P, P, P, SZ, P]),
             "kbe_collision_vjp_workspace": (SZ, [I32, I32, I32, I32, I32, I32, U32]),
             "kbe_collision_vjp": (I32, [G, R, W, I32, I32, I32, U32, P, P, P, P, G, R, P, SZ, P]),
             "kbe_sigma_2b_vjp_workspace": (SZ, [I32, I32, I32]),
@@ -342,6 +345,25 @@ def collision(G: Green, sig, W: Weights, n: int, m0: int = 0, m1: Optional[int] 
                            flags, _ptr(IR), _ptr(IL), _ptr(Itv), _ptr(Jtv), _ptr(ws), nb,
                            _stream(dev)), "kbe_collision")
     return IR, IL, Itv, Jtv
+
+
+def collision_both(G: Green, sig, W: Weights, n: int, m0: int = 0, m1: Optional[int] = None):
+    """kbe_collision_both: (IR, IL, Itv, Jtv) of the lesser form and (IRg, ILg) of the greater
+    form from one pass; Itv and Jtv are None without a thermal branch."""
+    m1 = n + 1 if m1 is None else m1
+    N, dev, M = G.N, G.device, m1 - m0
+    mk = lambda k: torch.empty((k, N, N), dtype=torch.complex128, device=dev)
+    IR, IL, IRg, ILg = mk(M), mk(M), mk(M), mk(M)
+    Itv = mk(M) if G.ntau else None
+    Jtv = mk(G.ntau) if G.ntau else None
+    L = lib()
+    nb = L.kbe_collision_both_workspace(N, G.nt, G.ntau, n, m0, m1)
+    ws = _ws(nb, dev)
+    _check(L.kbe_collision_both(ctypes.byref(G.c()), ctypes.byref(_row(*sig)),
+                                ctypes.byref(W.c()), n, m0, m1, _ptr(IR), _ptr(IL), _ptr(Itv),
+                                _ptr(Jtv), _ptr(IRg), _ptr(ILg), _ptr(ws), nb, _stream(dev)),
+           "kbe_collision_both")
+    return IR, IL, Itv, Jtv, IRg, ILg
 
 
 def collision_noalloc(G: Green, sig, W: Weights, n: int, m0: int = 0, m1: Optional[int] = None,

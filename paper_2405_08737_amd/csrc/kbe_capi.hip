@@ -281,6 +281,31 @@ kbe_status kbe_collision(const kbe_green *G, const kbe_sigma_row *S, const kbe_w
                     "kbe_collision");
 }
 
+size_t kbe_collision_both_workspace(int32_t N, int32_t nt, int32_t ntau, int32_t n, int32_t m0,
+                                    int32_t m1) {
+  if (N < 1 || N > KBE_NMAX || n < 0 || m0 < 0 || m1 < m0 || ntau < 0) return 0;
+  return kbe::collision_ws_bytes(N, nt, ntau, n, m0, m1, KBE_OUT_ALL | kbe::KBE_INT_BOTH);
+}
+
+kbe_status kbe_collision_both(const kbe_green *G, const kbe_sigma_row *S, const kbe_wts *W,
+                              int32_t n, int32_t m0, int32_t m1, kbe_c128 *IR, kbe_c128 *IL,
+                              kbe_c128 *Itv, kbe_c128 *Jtv, kbe_c128 *IRg, kbe_c128 *ILg,
+                              void *ws, size_t ws_bytes, void *stream) {
+  kbe_status s = check_common(G, S, W, n, m0, m1, KBE_OUT_ALL | KBE_GREATER);
+  if (s != KBE_OK) return s;
+  const bool M = m1 > m0, th = G->ntau > 0;
+  if (M && (!IR || !IL || !IRg || !ILg)) return fail(KBE_EINVAL, "IR, IL, IRg or ILg is NULL");
+  if (M && th && !Itv) return fail(KBE_EINVAL, "Itv is NULL");
+  if (th && !Jtv) return fail(KBE_EINVAL, "Jtv is NULL");
+  const size_t need = kbe_collision_both_workspace(G->N, G->nt, G->ntau, n, m0, m1);
+  if (need > 0 && (!ws || ws_bytes < need))
+    return fail(KBE_ENOMEM, "workspace %zu bytes < %zu", ws_bytes, need);
+  kbe::Params p = make_params(G, S, W, n, m0, m1, KBE_OUT_ALL);
+  return hip_status(kbe::launch_collision_both(p, IR, IL, th ? Itv : nullptr, th ? Jtv : nullptr,
+                                               IRg, ILg, ws, (hipStream_t)stream),
+                    "kbe_collision_both");
+}
+
 // ---------------------------------------------------------------------------------------
 // kbe_collision_noalloc: kbe_collision with its workspace in a fixed device array.
 //

@@ -404,3 +404,28 @@ def test_sigma_batch_argument_errors():
     for k in ("kp", "rdiag", "u", "ret", "les"):
         assert call([item(**{k: None})]) == 1 and "NULL" in err()
     assert call([item(tv=None)]) == 1 and "tv" in err()
+
+
+def test_collision_both_argument_errors_and_workspace():
+    L = kbe.lib()
+    a = L.kbe_collision_workspace(4, 20, 6, 19, 0, 20, kbe.OUT_ALL)
+    b = L.kbe_collision_both_workspace(4, 20, 6, 19, 0, 20)
+    assert b > a > 0
+    assert L.kbe_collision_both_workspace(0, 20, 6, 19, 0, 20) == 0
+
+    def call(G=None, S=None, W=None, n=7, m0=0, m1=8, outs=(FAKE,) * 6, ws_bytes=1 << 40):
+        G = G or green()
+        S = S or row()
+        W = W or wts()
+        return L.kbe_collision_both(ctypes.byref(G), ctypes.byref(S), ctypes.byref(W), n, m0, m1,
+                                    *outs, FAKE, ws_bytes, None)
+
+    assert call(n=8) == 2 and "n = 8" in err()
+    assert call(m0=3, m1=2) == 2
+    assert call(S=kbe._Row(FAKE, None, FAKE)) == 1 and "les" in err()
+    assert call(S=kbe._Row(None, FAKE, FAKE)) == 1 and "ret" in err()
+    for k in range(6):
+        o = [FAKE] * 6
+        o[k] = None
+        assert call(outs=tuple(o)) == 1 and "NULL" in err()
+    assert call(ws_bytes=16) == 3

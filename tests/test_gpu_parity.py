@@ -168,6 +168,43 @@ def test_sigma_batch_matches_oracle_and_rows(gpu):
             assert np.array_equal(x, to_host(o)), (si, n)
 
 
+@pytest.mark.parametrize("N,nt,ntau,mr", [(2, 70, 9, None), (5, 140, 6, (10, 90)),
+                                          (8, 300, 20, (7, 290)), (8, 40, 0, None),
+                                          (16, 300, 17, None), (16, 280, 9, (30, 270)),
+                                          (16, 30, 6, (12, 12)), (12, 50, 7, (3, 41))])
+def test_both_forms_match_oracle(gpu, N, nt, ntau, mr):
+    """kbe_collision_both (the propagations' call: the lesser form's four outputs and the greater
+    form's I^R and I^< from one pass) against the oracle's lesser and greater forms, whole,
+    partial and empty m-ranges, with and without a thermal branch, on every kernel path (MFMA
+    task at N = 16, small-block tasks at N <= 8, generic otherwise)."""
+    kbe = gpu
+    case = Case(N=N, nt=nt, ntau=ntau, beta=4.0, seed=900 + N)
+    t, order, kp, rd, tv, mat = case.host()
+    G = oracle.Green(kp, rd, tv if ntau else None, mat if ntau else None)
+    W = oracle.Weights.build(t, order, case.beta if ntau else None, ntau, case.tau_order)
+    n = nt - 1
+    sig = synth.sigma_row(case.seed + 3, N, n, ntau, t)
+    m0, m1 = mr if mr else (0, n + 1)
+    Gd = device_green(kp, rd, tv, mat)
+    sigd = tuple(to_dev(x) if x.size else None for x in sig)
+    out = kbe.collision_both(Gd, sigd, device_weights(W), n, m0, m1)
+    les = oracle.collision(G, sig, W, n, m0, m1, oracle.F_ALL)
+    gre = oracle.collision(G, sig, W, n, m0, m1, oracle.F_IR | oracle.F_IL | oracle.F_GREATER)
+    rng = range(m0, m1)
+    sl = scales(kp, rd, tv if ntau else None, mat, sig, W, n, rng, range(ntau))
+    sg = scales(kp, rd, tv if ntau else None, mat, sig, W, n, rng, range(ntau), greater=True)
+    for name, g, r, sc in zip(("IR", "IL", "Itv", "Jtv", "IR", "IL"), out,
+                              (les[0], les[1], les[2], les[3], gre[0], gre[1]),
+                              (sl["IR"], sl["IL"], sl["Itv"], sl["Jtv"], sg["IR"], sg["IL"])):
+        if g is None:
+            assert not ntau and name in ("Itv", "Jtv")
+            continue
+        if m1 == m0 and name != "Jtv":
+            assert g.shape[0] == 0
+            continue
+        assert_blocks_close(to_host(g), r, sc, name)
+
+
 def test_collision_parity_small(gpu):
     """N = 2, nt = 64, ntau = 64, beta = 10, order 5: every output for every m."""
     kbe = gpu
