@@ -39,6 +39,9 @@ CASES = [
     dict(h0=chain(16), u=0.8, mu=0.4, beta=3.0, ntau=33),
     dict(h0=chain(4, [0.1, 0.0, -0.2, 0.3]), u=1.0, mu=0.6, beta=3.0, ntau=20),
     dict(h0=chain(12), u=[0.5 + 0.05 * i for i in range(12)], mu=0.3, beta=2.5, ntau=17),
+    # the smallest tau grids (the two end points; three points)
+    dict(h0=chain(2), u=1.0, mu=0.5, beta=1.0, ntau=2),
+    dict(h0=chain(6, [0.1] * 6), u=0.9, mu=0.2, beta=2.0, ntau=3),
     # the propagation workload: 8 sites, U = 1, beta = 10, 256 tau points, half filling
     dict(h0=chain(8), u=1.0, mu=0.5, beta=10.0, ntau=256),
 ]
