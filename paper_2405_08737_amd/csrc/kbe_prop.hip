@@ -1048,99 +1048,115 @@ __global__ void ad_keep(PA a, AA b, int n) {
 //   u <  j + 1                      : w_j[s] Sigma^R(t_j,t_s) G^{<,>}(t_s,t_n), s = u;
 //   u <  j + n + 2                  : w_n[s] Sigma^{<,>}(t_j,t_s) G^A(t_s,t_n), s = u - j - 1;
 //   u <  j + n + 2 + ntau           : -i wtau[l] Sigma^](t_j,tau_l) G^[(tau_l,t_n), l = u - j - n - 2;
-// each thread one element of the block for every lanes-th term, the lanes summed in LDS in a
-// fixed order, and writes its chunk's partial sums of C^< (ret + les + mixed) and C^> (the same
-// with G^>, Sigma^>).  Stage two sums the chunks in order.  The result does not depend on the
+// each thread one element of the block for every lanes-th term (the term's blocks staged in LDS
+// by its lane group, one element per thread), the lanes summed in LDS in a fixed order, and
+// writes its chunk's partial sums of C^< (ret + les + mixed) and C^> (the same with G^>,
+// Sigma^>).  Stage two sums the chunks in order.  The result does not depend on the
 // launch beyond the rounding of the fixed summation order.
 constexpr int UCH = 64;
+static_assert(KBE_NMAX * KBE_NMAX <= 256, "ad_upper_part: one block element per thread");
 
 __host__ __device__ __forceinline__ int upper_terms(int j, int n, int ntau) { return j + n + 2 + ntau; }
 
 __global__ void __launch_bounds__(256) ad_upper_part(PA a, AA b, int n, int j0) {
-  const int64_t E = E_(a);
+  const int64_t E = E_(a);  // <= 256 (N <= KBE_NMAX)
   const int N = a.N;
   const int jj = blockIdx.y, j = j0 + jj, chunk = blockIdx.x, tid = threadIdx.x;
-  const int lanes = E <= 256 ? 256 / (int)E : 1;
-  const int lane = E <= 256 ? tid / (int)E : 0;
+  const int lanes = 256 / (int)E;
+  const int lane = tid / (int)E, q = tid % (int)E, r = q / N, c = q % N;
+  const bool act = lane < lanes;
   const int u0 = chunk * UCH, uend = min(u0 + UCH, upper_terms(j, n, a.ntau));
   const double *wj = b.w + (int64_t)j * a.nt, *wn = b.w + (int64_t)n * a.nt;
+  const int J = a.ntau - 1;
+  // the blocks of each lane group's current term, staged element by element (coalesced) and
+  // then read from LDS by the group's threads
+  __shared__ cd blk[3][256];
   __shared__ cd red[2][256];
-  for (int64_t q0 = 0; q0 < E; q0 += 256) {
-    const int64_t q = E <= 256 ? tid % E : q0 + tid;
-    const bool act = lane < lanes && q < E;
-    cd cl = czero(), cg = czero();
-    if (act) {
-      const int r = (int)(q / N), c = (int)(q % N);
-      for (int u = u0 + lane; u < uend; u += lanes) {
-        if (u <= j) {
-          const int s = u;
-          const kbe_c128 *SR = b.Sret + ((int64_t)j * a.nt + s) * E;
-          const kbe_c128 *GL = a.kp + ((int64_t)s * a.ldt + n) * E;    // G^<(s,n)
-          const kbe_c128 *GRns = a.kp + ((int64_t)n * a.ldt + s) * E;  // G^R(n,s), s < n
-          cd x = czero(), y = czero();
-          for (int k = 0; k < N; ++k) {
-            const cd sr = ld(SR + r * N + k);
-            const cd gl = ld(GL + k * N + c);
-            const cd gg = gl - cj(ld(GRns + c * N + k));  // G^>(s,n) = kp[s][n] - kp[n][s]^dagger
-            x = x + sr * gl;
-            y = y + sr * gg;
-          }
-          cl = cl + wj[s] * x;
-          cg = cg + wj[s] * y;
-        } else if (u <= j + n + 1) {
-          const int s = u - j - 1;
-          const kbe_c128 *GA = s < n ? a.kp + ((int64_t)n * a.ldt + s) * E : a.rdiag + n * E;
-          cd x = czero(), y = czero();
-          for (int k = 0; k < N; ++k) {
-            cd sl, sg;
-            if (s <= j) {
-              sl = ld(b.Sles + ((int64_t)j * a.nt + s) * E + r * N + k);
-              sg = sl + ld(b.Sret + ((int64_t)j * a.nt + s) * E + r * N + k);
-            } else {
-              const cd l = ld(b.Sles + ((int64_t)s * a.nt + j) * E + k * N + r);
-              const cd g = l + ld(b.Sret + ((int64_t)s * a.nt + j) * E + k * N + r);
-              sl = -cj(l);
-              sg = -cj(g);
-            }
-            const cd ga = cj(ld(GA + c * N + k));  // G^A(s,n)[k][c] = conj(G^R(n,s)[c][k])
-            x = x + sl * ga;
-            y = y + sg * ga;
-          }
-          cl = cl + wn[s] * x;
-          cg = cg + wn[s] * y;
-        } else {
-          const int l = u - j - n - 2, J = a.ntau - 1;
-          const kbe_c128 *S = b.Stv + ((int64_t)j * a.ntau + l) * E;
-          const kbe_c128 *T = a.tv + ((int64_t)n * a.ntau + (J - l)) * E;
-          cd x = czero();
-          for (int k = 0; k < N; ++k) x = x + ld(S + r * N + k) * cj(ld(T + c * N + k));
-          x = mul_mi(a.wtau_[l] * x);
-          cl = cl + x;
-          cg = cg + x;
+  cd cl = czero(), cg = czero();
+  const int iters = (UCH + lanes - 1) / lanes;
+  for (int it = 0; it < iters; ++it) {
+    const int u = u0 + lane + it * lanes;
+    const bool has = act && u < uend;
+    if (has) {
+      const kbe_c128 *P0, *P1, *P2 = nullptr;
+      if (u <= j) {  // Sigma^R(t_j,t_s), G^<(s,n) = kp[s][n], G^R(n,s) = kp[n][s]
+        const int s = u;
+        P0 = b.Sret + ((int64_t)j * a.nt + s) * E;
+        P1 = a.kp + ((int64_t)s * a.ldt + n) * E;
+        P2 = a.kp + ((int64_t)n * a.ldt + s) * E;
+      } else if (u <= j + n + 1) {  // Sigma^<, Sigma^R at (t_j,t_s) or (t_s,t_j); G^R(n,s)
+        const int s = u - j - 1;
+        const int64_t row = s <= j ? (int64_t)j * a.nt + s : (int64_t)s * a.nt + j;
+        P0 = b.Sles + row * E;
+        P1 = b.Sret + row * E;
+        P2 = s < n ? a.kp + ((int64_t)n * a.ldt + s) * E : a.rdiag + n * E;
+      } else {  // Sigma^](t_j,tau_l), G^](t_n,tau_{J-l})
+        const int l = u - j - n - 2;
+        P0 = b.Stv + ((int64_t)j * a.ntau + l) * E;
+        P1 = a.tv + ((int64_t)n * a.ntau + (J - l)) * E;
+      }
+      blk[0][tid] = ld(P0 + q);
+      blk[1][tid] = ld(P1 + q);
+      if (P2) blk[2][tid] = ld(P2 + q);
+    }
+    __syncthreads();
+    if (has) {
+      const cd *B0 = blk[0] + lane * E, *B1 = blk[1] + lane * E, *B2 = blk[2] + lane * E;
+      if (u <= j) {
+        const int s = u;
+        cd x = czero(), y = czero();
+        for (int k = 0; k < N; ++k) {
+          const cd sr = B0[r * N + k];
+          const cd gl = B1[k * N + c];
+          const cd gg = gl - cj(B2[c * N + k]);  // G^>(s,n) = kp[s][n] - kp[n][s]^dagger
+          x = x + sr * gl;
+          y = y + sr * gg;
         }
+        cl = cl + wj[s] * x;
+        cg = cg + wj[s] * y;
+      } else if (u <= j + n + 1) {
+        const int s = u - j - 1;
+        cd x = czero(), y = czero();
+        for (int k = 0; k < N; ++k) {
+          cd sl, sg;
+          if (s <= j) {
+            sl = B0[r * N + k];
+            sg = sl + B1[r * N + k];
+          } else {
+            const cd l = B0[k * N + r];
+            const cd g = l + B1[k * N + r];
+            sl = -cj(l);
+            sg = -cj(g);
+          }
+          const cd ga = cj(B2[c * N + k]);  // G^A(s,n)[k][c] = conj(G^R(n,s)[c][k])
+          x = x + sl * ga;
+          y = y + sg * ga;
+        }
+        cl = cl + wn[s] * x;
+        cg = cg + wn[s] * y;
+      } else {
+        const int l = u - j - n - 2;
+        cd x = czero();
+        for (int k = 0; k < N; ++k) x = x + B0[r * N + k] * cj(B1[c * N + k]);
+        x = mul_mi(a.wtau_[l] * x);
+        cl = cl + x;
+        cg = cg + x;
       }
     }
-    kbe_c128 *out = b.upart + (((int64_t)chunk * QM + jj) * 2) * E;
-    if (lanes == 1) {
-      if (act) {
-        st(out + q, cl);
-        st(out + E + q, cg);
-      }
-      continue;
-    }
-    red[0][tid] = cl;
-    red[1][tid] = cg;
     __syncthreads();
-    if (tid < E) {
-      cd sl = red[0][tid], sg = red[1][tid];
-      for (int i = 1; i < lanes; ++i) {
-        sl = sl + red[0][i * E + tid];
-        sg = sg + red[1][i * E + tid];
-      }
-      st(out + tid, sl);
-      st(out + E + tid, sg);
+  }
+  kbe_c128 *out = b.upart + (((int64_t)chunk * QM + jj) * 2) * E;
+  red[0][tid] = cl;
+  red[1][tid] = cg;
+  __syncthreads();
+  if (tid < E) {
+    cd sl = red[0][tid], sg = red[1][tid];
+    for (int i = 1; i < lanes; ++i) {
+      sl = sl + red[0][i * E + tid];
+      sg = sg + red[1][i * E + tid];
     }
-    __syncthreads();
+    st(out + tid, sl);
+    st(out + E + tid, sg);
   }
 }
 
