@@ -358,7 +358,9 @@ def graph_pair(kbe, torch, G, u, n, t, order, w, reps=10):
 def greater_form(kbe, torch, G, u, n, t, order, w, cot, gG, reps=3):
     """The greater form of Eq. KBE2 (KBE_GREATER) on the headline row: kbe_collision and
     kbe_collision_vjp (overwrite mode) back to back, against the lesser form in the same run;
-    and kbe_collision_both (both forms from one pass) against the lesser form alone."""
+    and kbe_collision_both and its adjoint kbe_collision_both_vjp (both forms from one pass each;
+    the adjoint accumulates, so it is compared with the lesser adjoint in accumulate mode) against
+    the lesser form alone."""
     W = kbe.weights(t, order, G.ntau, w.beta, w.tau_order, device=G.device)
     sig = kbe.sigma_2b(G, u, n)
     ev = lambda: torch.cuda.Event(enable_timing=True)
@@ -393,10 +395,35 @@ def greater_form(kbe, torch, G, u, n, t, order, w, cot, gG, reps=3):
     e1.record()
     torch.cuda.synchronize()
     both = e0.elapsed_time(e1) / reps
-    out["both_forms"] = {"collision_ms": both,
-                         "over_lesser": both / out["lesser"]["collision_ms"],
-                         "over_separate_calls": both / (out["lesser"]["collision_ms"] +
-                                                        out["greater"]["collision_ms"])}
+    cot6 = (cot[0], cot[1], cot[2], cot[3], cot[0], cot[1])
+    bv = lambda: kbe.collision_both_vjp(G, sig, W, n, 0, n + 1, cot6, gG)
+    bv()
+    torch.cuda.synchronize()
+    e0, e1 = ev(), ev()
+    e0.record()
+    for _ in range(reps):
+        bv()
+    e1.record()
+    torch.cuda.synchronize()
+    both_vjp = e0.elapsed_time(e1) / reps
+    # the lesser adjoint in the same (accumulate) mode, for the comparison of the adjoints
+    lv = lambda: kbe.collision_vjp(G, sig, W, n, 0, n + 1, cot, kbe.OUT_ALL, gG)
+    lv()
+    torch.cuda.synchronize()
+    e0, e1 = ev(), ev()
+    e0.record()
+    for _ in range(reps):
+        lv()
+    e1.record()
+    torch.cuda.synchronize()
+    les_acc = e0.elapsed_time(e1) / reps
+    out["both_forms"] = {"collision_ms": both, "collision_vjp_ms": both_vjp,
+                         "lesser_collision_vjp_accumulate_ms": les_acc,
+                         "over_lesser": {"collision_ms": both / out["lesser"]["collision_ms"],
+                                         "collision_vjp_ms": both_vjp / les_acc},
+                         "forward_over_separate_calls":
+                             both / (out["lesser"]["collision_ms"] +
+                                     out["greater"]["collision_ms"])}
     return out
 
 

@@ -367,6 +367,35 @@ kbe_status kbe_collision_both(const kbe_green *G, const kbe_sigma_row *S, const 
                               void *ws, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * kbe_collision_both_vjp — adjoint of kbe_collision_both (the propagations'
+ * adjoint call).
+ *
+ * By linearity the gradient is the lesser form's adjoint with the summed
+ * cotangents of the terms the forms share (gIR + gIRg, gIL + gILg, gItv, gJtv)
+ * plus the adjoint of the greater form's own terms (the G^R part of G^> in I^R,
+ * the Sigma^R part of Sigma^> in I^<) with gIRg and gILg: two passes over the
+ * history instead of the lesser and the greater adjoints' four.
+ *
+ * Arguments: as kbe_collision_both for G, S, W, n, m0, m1; the cotangents gIR,
+ * gIL, gIRg, gILg [m1-m0][N][N], gItv [m1-m0][N][N] and gJtv [ntau][N][N]
+ * (both when ntau > 0); gG (G's shape) receives the Green's-function gradient
+ * by accumulation (there is no overwrite mode: the greater form's terms reach
+ * blocks outside the lesser form's); gS (ret, les [n+1][N][N], tv [ntau][N][N])
+ * is overwritten with the self-energy gradient; ws: device workspace of
+ * kbe_collision_both_vjp_workspace(...) bytes.  Complex gradients as in
+ * kbe_collision_vjp.  Errors: as kbe_collision_vjp.
+ * ------------------------------------------------------------------------- */
+size_t kbe_collision_both_vjp_workspace(int32_t N, int32_t nt, int32_t ntau, int32_t n,
+                                        int32_t m0, int32_t m1);
+kbe_status kbe_collision_both_vjp(const kbe_green *G, const kbe_sigma_row *S, const kbe_wts *W,
+                                  int32_t n, int32_t m0, int32_t m1, const kbe_c128 *gIR,
+                                  const kbe_c128 *gIL, const kbe_c128 *gItv,
+                                  const kbe_c128 *gJtv, const kbe_c128 *gIRg,
+                                  const kbe_c128 *gILg, const kbe_green *gG,
+                                  const kbe_sigma_row *gS, void *ws, size_t ws_bytes,
+                                  void *stream);
+
+/* ---------------------------------------------------------------------------
  * kbe_collision_noalloc — kbe_collision for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc): the same integrals, arguments and errors as

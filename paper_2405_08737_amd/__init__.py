@@ -111,7 +111,8 @@ class _BatchVjpItem(ctypes.Structure):
 
 EXPORTS = ("kbe_weights_workspace", "kbe_weights", "kbe_sigma_2b", "kbe_collision_workspace",
            "kbe_collision", "kbe_collision_noalloc", "kbe_collision_both_workspace",
-           "kbe_collision_both", "kbe_collision_vjp_workspace",
+           "kbe_collision_both", "kbe_collision_both_vjp_workspace", "kbe_collision_both_vjp",
+           "kbe_collision_vjp_workspace",
            "kbe_collision_vjp",
            "kbe_sigma_2b_vjp_workspace", "kbe_sigma_2b_vjp", "kbe_sigma_2b_full",
            "kbe_sigma_2b_batch",
@@ -151,6 +152,9 @@ def lib():
             "kbe_collision_noalloc": (I32, [G, R, W, I32, I32, I32, U32, P, P, P, P, P]),
             "kbe_collision_both_workspace": (SZ, [I32, I32, I32, I32, I32, I32]),
             "kbe_collision_both": (I32, [G, R, W, I32, I32, I32, P, P, P, P, P, P, P, SZ, P]),
+            "kbe_collision_both_vjp_workspace": (SZ, [I32, I32, I32, I32, I32, I32]),
+            "kbe_collision_both_vjp": (I32, [G, R, W, I32, I32, I32, P, P, P, P, P, P, G, R, P,
+                                             SZ, P]),
             "kbe_collision_vjp_workspace": (SZ, [I32, I32, I32, I32, I32, I32, U32]),
             "kbe_collision_vjp": (I32, [G, R, W, I32, I32, I32, U32, P, P, P, P, G, R, P, SZ, P]),
             "kbe_sigma_2b_vjp_workspace": (SZ, [I32, I32, I32]),
@@ -403,6 +407,28 @@ def collision_vjp(G: Green, sig, W: Weights, n: int, m0: int, m1: int, cot, flag
                                n, m0, m1, flags, _ptr(gIR), _ptr(gIL), _ptr(gItv), _ptr(gJ),
                                ctypes.byref(gG.c()), ctypes.byref(_row(gret, gles, gstv)),
                                _ptr(ws), nb, _stream(dev)), "kbe_collision_vjp")
+    return gG, (gret, gles, gstv)
+
+
+def collision_both_vjp(G: Green, sig, W: Weights, n: int, m0: int, m1: int, cot,
+                       gG: Optional[Green] = None):
+    """kbe_collision_both_vjp: cot = (gIR, gIL, gItv, gJtv, gIRg, gILg) (gItv, gJtv None without a
+    thermal branch); returns (gG, (gret, gles, gstv)); gG is accumulated into (or created zero)."""
+    N, dev = G.N, G.device
+    if gG is None:
+        gG = G.zeros_like()
+    gret = torch.empty((n + 1, N, N), dtype=torch.complex128, device=dev)
+    gles = torch.empty_like(gret)
+    gstv = torch.empty((G.ntau, N, N), dtype=torch.complex128, device=dev) if G.ntau else None
+    gIR, gIL, gItv, gJ, gIRg, gILg = cot
+    L = lib()
+    nb = L.kbe_collision_both_vjp_workspace(N, G.nt, G.ntau, n, m0, m1)
+    ws = _ws(nb, dev)
+    _check(L.kbe_collision_both_vjp(ctypes.byref(G.c()), ctypes.byref(_row(*sig)),
+                                    ctypes.byref(W.c()), n, m0, m1, _ptr(gIR), _ptr(gIL),
+                                    _ptr(gItv), _ptr(gJ), _ptr(gIRg), _ptr(gILg),
+                                    ctypes.byref(gG.c()), ctypes.byref(_row(gret, gles, gstv)),
+                                    _ptr(ws), nb, _stream(dev)), "kbe_collision_both_vjp")
     return gG, (gret, gles, gstv)
 
 

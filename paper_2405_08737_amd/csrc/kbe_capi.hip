@@ -409,6 +409,96 @@ kbe_status kbe_collision_vjp(const kbe_green *G, const kbe_sigma_row *S, const k
 }
 
 // ---------------------------------------------------------------------------------------
+// Adjoint of both forms: the lesser adjoint on the summed cotangents, then the greater form's
+// own terms.  Workspace: [collision adjoint][gIR + gIRg][gIL + gILg][the second pass's gS].
+// ---------------------------------------------------------------------------------------
+namespace {
+constexpr unsigned FG_EXTRA = KBE_OUT_IR | KBE_OUT_IL | KBE_GREATER | kbe::KBE_INT_GREXTRA;
+
+size_t al256c(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t both_vjp_layout(int N, int nt, int ntau, int n, int m0, int m1, size_t off[5]) {
+  const size_t E = (size_t)N * N * sizeof(kbe_c128);
+  const size_t a = kbe::collision_vjp_ws_bytes(N, nt, ntau, n, m0, m1, KBE_OUT_ALL);
+  const size_t b = kbe::collision_vjp_ws_bytes(N, nt, ntau, n, m0, m1, FG_EXTRA);
+  size_t t = al256c(a > b ? a : b);
+  off[0] = t;  // gIR + gIRg
+  t += al256c((size_t)(m1 - m0) * E);
+  off[1] = t;  // gIL + gILg
+  t += al256c((size_t)(m1 - m0) * E);
+  off[2] = t;  // second pass: gS ret
+  t += al256c((size_t)(n + 1) * E);
+  off[3] = t;  // les
+  t += al256c((size_t)(n + 1) * E);
+  off[4] = t;  // tv
+  t += al256c((size_t)(ntau > 0 ? ntau : 1) * E);
+  return t;
+}
+}  // namespace
+
+size_t kbe_collision_both_vjp_workspace(int32_t N, int32_t nt, int32_t ntau, int32_t n,
+                                        int32_t m0, int32_t m1) {
+  if (N < 1 || N > KBE_NMAX || n < 0 || m0 < 0 || m1 < m0 || ntau < 0) return 0;
+  size_t off[5];
+  return both_vjp_layout(N, nt, ntau, n, m0, m1, off);
+}
+
+kbe_status kbe_collision_both_vjp(const kbe_green *G, const kbe_sigma_row *S, const kbe_wts *W,
+                                  int32_t n, int32_t m0, int32_t m1, const kbe_c128 *gIR,
+                                  const kbe_c128 *gIL, const kbe_c128 *gItv,
+                                  const kbe_c128 *gJtv, const kbe_c128 *gIRg,
+                                  const kbe_c128 *gILg, const kbe_green *gG,
+                                  const kbe_sigma_row *gS, void *ws, size_t ws_bytes,
+                                  void *stream) {
+  kbe_status s = check_common(G, S, W, n, m0, m1, KBE_OUT_ALL | KBE_GREATER);
+  if (s != KBE_OK) return s;
+  if ((s = check_same_shape(G, gG, "gG")) != KBE_OK) return s;
+  const bool M = m1 > m0, th = G->ntau > 0;
+  if (M && (!gIR || !gIL || !gIRg || !gILg))
+    return fail(KBE_EINVAL, "gIR, gIL, gIRg or gILg is NULL");
+  if (M && th && !gItv) return fail(KBE_EINVAL, "gItv is NULL");
+  if (th && !gJtv) return fail(KBE_EINVAL, "gJtv is NULL");
+  if (!gS || !gS->ret || !gS->les) return fail(KBE_EINVAL, "gS row is NULL");
+  if (th && !gS->tv) return fail(KBE_EINVAL, "gS->tv is NULL with ntau > 0");
+  size_t off[5];
+  const size_t need = both_vjp_layout(G->N, G->nt, G->ntau, n, m0, m1, off);
+  if (!ws || ws_bytes < need) return fail(KBE_ENOMEM, "workspace %zu bytes < %zu", ws_bytes, need);
+  const hipStream_t st = (hipStream_t)stream;
+  char *w = (char *)ws;
+  const int64_t E = (int64_t)G->N * G->N, cnt = (int64_t)(m1 - m0) * E;
+  kbe_c128 *cIR = (kbe_c128 *)(w + off[0]), *cIL = (kbe_c128 *)(w + off[1]);
+  hipError_t e = kbe::launch_add_blocks(gIR, gIRg, cIR, M ? cnt : 0, st);
+  if (e == hipSuccess) e = kbe::launch_add_blocks(gIL, gILg, cIL, M ? cnt : 0, st);
+  if ((s = hip_status(e, "kbe_collision_both_vjp")) != KBE_OK) return s;
+  kbe::Params p = make_params(G, S, W, n, m0, m1, KBE_OUT_ALL);
+  p.gIR = cIR;
+  p.gIL = cIL;
+  p.gItv = gItv;
+  p.gJ = gJtv;
+  p.gkp = gG->kp;
+  p.grdiag = gG->rdiag;
+  p.gtv = gG->tv;
+  s = hip_status(kbe::launch_collision_vjp(p, KBE_OUT_ALL, gG->mat, gS, ws, st),
+                 "kbe_collision_both_vjp");
+  if (s != KBE_OK) return s;
+  kbe::Params q = make_params(G, S, W, n, m0, m1, FG_EXTRA);
+  q.gIR = gIRg;
+  q.gIL = gILg;
+  q.gkp = gG->kp;
+  q.grdiag = gG->rdiag;
+  q.gtv = gG->tv;
+  kbe_sigma_row g2{(kbe_c128 *)(w + off[2]), (kbe_c128 *)(w + off[3]),
+                   th ? (kbe_c128 *)(w + off[4]) : nullptr};
+  s = hip_status(kbe::launch_collision_vjp(q, FG_EXTRA, gG->mat, &g2, ws, st),
+                 "kbe_collision_both_vjp");
+  if (s != KBE_OK) return s;
+  const int64_t rows = (int64_t)(n + 1) * E;
+  e = kbe::launch_add_blocks(gS->ret, g2.ret, gS->ret, rows, st);
+  if (e == hipSuccess) e = kbe::launch_add_blocks(gS->les, g2.les, gS->les, rows, st);
+  return hip_status(e, "kbe_collision_both_vjp");
+}
+
+// ---------------------------------------------------------------------------------------
 // Weights from a device-resident grid; step weights; the fixed-grid propagation.
 // ---------------------------------------------------------------------------------------
 size_t kbe_weights_dev_workspace(int32_t nt, int32_t ntau) {

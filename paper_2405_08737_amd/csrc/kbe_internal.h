@@ -26,6 +26,8 @@ hipError_t launch_interval_weights(double *t, int n, double tn, int kam, int kab
 // Self-energy and its adjoint (kbe_sigma.hip).
 hipError_t launch_sigma_row(const kbe_green *G, const double *u, int n, const kbe_sigma_row *out,
                             hipStream_t st);
+hipError_t launch_add_blocks(const kbe_c128 *a, const kbe_c128 *b, kbe_c128 *out, int64_t cnt,
+                             hipStream_t st);
 hipError_t launch_sigma_batch(const kbe_sigma_batch_item *items_dev, int count, int64_t max_elems,
                               hipStream_t st);
 hipError_t launch_sigma_full(const kbe_green *G, const double *u, const kbe_green *S,

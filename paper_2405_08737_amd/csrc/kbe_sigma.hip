@@ -87,6 +87,21 @@ hipError_t launch_sigma_batch(const kbe_sigma_batch_item *items_dev, int count, 
   return hipGetLastError();
 }
 
+// out = a + b elementwise (out may be a or b).
+__global__ void __launch_bounds__(256) add_blocks_kernel(const kbe_c128 *a, const kbe_c128 *b,
+                                                         kbe_c128 *out, int64_t cnt) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < cnt) st(out + idx, ld(a + idx) + ld(b + idx));
+}
+
+hipError_t launch_add_blocks(const kbe_c128 *a, const kbe_c128 *b, kbe_c128 *out, int64_t cnt,
+                             hipStream_t st) {
+  if (cnt <= 0) return hipSuccess;
+  hipLaunchKernelGGL(add_blocks_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, a,
+                     b, out, cnt);
+  return hipGetLastError();
+}
+
 hipError_t launch_sigma_row(const kbe_green *G, const double *u, int n, const kbe_sigma_row *out,
                             hipStream_t st) {
   SigArgs a{G->N, G->ntau, G->ntau - 1, n, G->ldt, G->kp, G->rdiag, G->tv, u};

@@ -429,3 +429,28 @@ def test_collision_both_argument_errors_and_workspace():
         o[k] = None
         assert call(outs=tuple(o)) == 1 and "NULL" in err()
     assert call(ws_bytes=16) == 3
+
+
+def test_collision_both_vjp_argument_errors_and_workspace():
+    L = kbe.lib()
+    a = L.kbe_collision_vjp_workspace(4, 20, 6, 19, 0, 20, kbe.OUT_ALL)
+    b = L.kbe_collision_both_vjp_workspace(4, 20, 6, 19, 0, 20)
+    assert b > a > 0
+    assert L.kbe_collision_both_vjp_workspace(4, 20, 6, 19, 5, 4) == 0
+
+    def call(n=7, m0=0, m1=8, cot=(FAKE,) * 6, gG=None, gS=None, ws_bytes=1 << 40):
+        G, S, W = green(), row(), wts()
+        gG = gG or green()
+        gS = gS or row()
+        return L.kbe_collision_both_vjp(ctypes.byref(G), ctypes.byref(S), ctypes.byref(W), n, m0,
+                                        m1, *cot, ctypes.byref(gG), ctypes.byref(gS), FAKE,
+                                        ws_bytes, None)
+
+    assert call(n=8) == 2
+    assert call(gG=green(N=3)) == 1 and "shape" in err()
+    for k in range(6):
+        c = [FAKE] * 6
+        c[k] = None
+        assert call(cot=tuple(c)) == 1 and "NULL" in err()
+    assert call(gS=kbe._Row(FAKE, None, FAKE)) == 1 and "gS" in err()
+    assert call(ws_bytes=16) == 3

@@ -267,3 +267,41 @@ def test_autograd_wrappers_and_finite_differences(gpu, greater):
         fd = (loss_gpu(torch.tensor(1.7 + h, dtype=torch.float64, device="cuda"), kp0)
               - loss_gpu(torch.tensor(1.7 - h, dtype=torch.float64, device="cuda"), kp0)) / (2 * h)
     assert abs(fd.item() - U.grad.item()) < 1e-7 * abs(U.grad.item())
+
+
+@pytest.mark.parametrize("N,nt,ntau,m0,m1", [(16, 120, 10, 0, 120), (16, 80, 6, 10, 70),
+                                             (8, 90, 12, 5, 80), (6, 60, 0, 0, 60),
+                                             (3, 70, 6, 10, 50), (12, 40, 5, 0, 40)])
+def test_both_forms_vjp_matches_oracle(gpu, N, nt, ntau, m0, m1):
+    """kbe_collision_both_vjp (the lesser adjoint on the summed cotangents plus the greater form's
+    own terms) against the sum of the oracle's lesser adjoint (cotangents of IR, IL, Itv, Jtv) and
+    greater adjoint (cotangents of the greater IR, IL), every gradient array, pure gradients, on
+    every kernel path and on partial ranges."""
+    kbe = gpu
+    print("both vjp", N, nt, ntau, m0, m1, flush=True)
+    case = Case(N=N, nt=nt, ntau=ntau, beta=3.0 if ntau else 0.0, seed=70 + N)
+    t, order, kp, rd, tv, mat = case.host()
+    n = nt - 1
+    W = oracle.Weights.build(t, order, case.beta, ntau, case.tau_order)
+    sig = synth.sigma_row(case.seed, N, n, ntau, t)
+    M = m1 - m0
+    c = [synth.normal(11, k, (M, N, N)) for k in range(3)] + \
+        [synth.normal(11, 3, (ntau, N, N))] + [synth.normal(11, 4 + k, (M, N, N)) for k in range(2)]
+    z = lambda *sh: np.zeros(sh, np.complex128)
+    Go = oracle.Green(kp, rd, tv, mat)
+    les = oracle.collision_vjp(Go, sig, W, n, m0, m1, tuple(c[:4]), oracle.F_ALL)
+    gre = oracle.collision_vjp(Go, sig, W, n, m0, m1, (c[4], c[5], z(M, N, N), z(ntau, N, N)),
+                               oracle.F_IR | oracle.F_IL | oracle.F_GREATER, grads=les[:4])
+    ref = (gre[0], gre[1], gre[2], gre[3], les[4] + gre[4], les[5] + gre[5], les[6])
+    s1 = vjp_scales(kp, rd, tv, mat, sig, W, n, m0, m1, tuple(c[:4]), oracle.F_ALL)
+    s2 = vjp_scales(kp, rd, tv, mat, sig, W, n, m0, m1, (c[4], c[5], None, None),
+                    oracle.F_IR | oracle.F_IL | oracle.F_GREATER)
+    scale = {k: s1[k] + s2[k] for k in s1}
+    base = tuple(np.zeros(x.shape, np.complex128) for x in (kp, rd, tv, mat))
+    Gd = device_green(kp, rd, tv, mat)
+    cot = tuple(to_dev(x) if x.size else None for x in c)
+    if not ntau:
+        cot = (cot[0], cot[1], None, None, cot[4], cot[5])
+    sigd = tuple(to_dev(x) if x.size else None for x in sig)
+    got = kbe.collision_both_vjp(Gd, sigd, device_weights(W), n, m0, m1, cot)
+    check_gradients(ref, got, base, scale)
