@@ -478,9 +478,6 @@ kbe_status kbe_collision_both_vjp(const kbe_green *G, const kbe_sigma_row *S, co
   p.gkp = gG->kp;
   p.grdiag = gG->rdiag;
   p.gtv = gG->tv;
-  s = hip_status(kbe::launch_collision_vjp(p, KBE_OUT_ALL, gG->mat, gS, ws, st),
-                 "kbe_collision_both_vjp");
-  if (s != KBE_OK) return s;
   kbe::Params q = make_params(G, S, W, n, m0, m1, FG_EXTRA);
   q.gIR = gIRg;
   q.gIL = gILg;
@@ -489,7 +486,8 @@ kbe_status kbe_collision_both_vjp(const kbe_green *G, const kbe_sigma_row *S, co
   q.gtv = gG->tv;
   kbe_sigma_row g2{(kbe_c128 *)(w + off[2]), (kbe_c128 *)(w + off[3]),
                    th ? (kbe_c128 *)(w + off[4]) : nullptr};
-  s = hip_status(kbe::launch_collision_vjp(q, FG_EXTRA, gG->mat, &g2, ws, st),
+  s = hip_status(kbe::launch_collision_vjp_pair(p, KBE_OUT_ALL, q, FG_EXTRA, gG->mat, gS, &g2,
+                                                ws, st),
                  "kbe_collision_both_vjp");
   if (s != KBE_OK) return s;
   const int64_t rows = (int64_t)(n + 1) * E;

@@ -1263,11 +1263,81 @@ grad_mfma16(Params p, int row_len, int nseg) {
 constexpr int GSEG8 = 64;   // blocks per workgroup segment (64 beat 32, 128 and 256)
 constexpr int XLD8 = 9;     // LDS row stride of a staged 8x8 block, in complex numbers
 
-// TS as in grad_mfma16: 0 the common terms, 1 and 2 the greater form's extra terms.
+// Term sets of grad_mfma8<TS>: 0 the terms both forms share (at most two per block, X ids
+// 0..3), 1 the greater form's extra terms (at most three, X ids 0..2), 2 both sets in one pass
+// (at most five): the shared terms with the first parameter set's cotangents and the extra
+// terms with the second's, whose gIR(a), gIL(a) are staged as X ids 4, 5.
+template <int TS> struct Gr8 {
+  static constexpr int NT = TS == 0 ? 2 : TS == 1 ? 3 : 5;  // terms per block, at most
+  static constexpr int NX = TS == 2 ? 6 : 4;                // staged X blocks per row
+};
+
+template <int NT> struct GradRec8 {
+  const kbe_c128 *y[NT];  // Y of each term (term 0's Y again for absent terms)
+  kbe_c128 *dst;
+  double cr[NT], ci[NT];  // scalars (0 for absent terms)
+  int x[NT], nt;
+  int acc;  // add the block's current value (accumulate mode, or a block an earlier pass wrote)
+};
+
+// The record of block j0 + tid of row a.  TS = 1 adds to what the TS = 0 pass wrote
+// (accumulate mode, or a block that pass reached); TS = 2 writes each block once with both
+// sets' terms, the shared terms first.
 template <int TS>
-__global__ void __launch_bounds__(256) grad_mfma8(Params p, int row_len, int nseg) {
-  __shared__ cd xs[4][8 * XLD8];
-  __shared__ GradRec rec[GSEG8];
+__device__ __forceinline__ void fill_grad_rec8(const Params &p, const Params &pg, int a, int j0,
+                                               int len, int tid, GradRec8<Gr8<TS>::NT> &g) {
+  constexpr int NT = Gr8<TS>::NT;
+  GradTerm t[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) t[k] = GradTerm{-1, czero(), p.ret};
+  kbe_c128 *d = p.gkp;
+  int nt = 0, acc = !p.overwrite;
+  if (tid < len) {
+    const int j = j0 + tid;
+    if constexpr (TS == 0) {
+      nt = grad_row_terms(p, a, j, t[0], t[1], d);
+    } else if constexpr (TS == 1) {
+      nt = grad_row_terms_gr(p, a, j, t[0], t[1], t[2], d);
+      GradTerm u0, u1;
+      kbe_c128 *dd;
+      acc = acc || grad_row_terms(p, a, j, u0, u1, dd) > 0;
+    } else {
+      kbe_c128 *dg = pg.gkp;
+      const int n0 = grad_row_terms(p, a, j, t[0], t[1], d);
+      GradTerm u[3];
+      const int n1 = grad_row_terms_gr(pg, a, j, u[0], u[1], u[2], dg);
+      if (n0 == 0) d = dg;  // the same block: both sets address it alike
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        if (k >= n1) break;
+        GradTerm v = u[k];
+        if (v.xid > 0) v.xid += 3;  // pg's gIR(a), gIL(a)
+        if (n0 == 0) t[k] = v;
+        else if (n0 == 1) t[k + 1] = v;
+        else t[k + 2] = v;
+      }
+      nt = n0 + n1;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NT; ++k) {
+    g.y[k] = k < nt ? t[k].Y : t[0].Y;
+    g.cr[k] = k < nt ? t[k].c.re : 0.0;
+    g.ci[k] = k < nt ? t[k].c.im : 0.0;
+    g.x[k] = k < nt && t[k].xid >= 0 ? t[k].xid : 0;
+  }
+  g.dst = d;
+  g.nt = nt;
+  g.acc = acc;
+}
+
+// TS: the term set (Gr8).  pg is read by TS = 2 only (the greater form's extra terms; its Sigma
+// row, gradients, row range and mode are those of p).
+template <int TS>
+__global__ void __launch_bounds__(256) grad_mfma8(Params p, Params pg, int row_len, int nseg) {
+  constexpr int NTM = Gr8<TS>::NT, NX = Gr8<TS>::NX;
+  __shared__ cd xs[NX][8 * XLD8];
+  __shared__ GradRec8<NTM> rec[GSEG8];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int N = p.N;
   const int per_xcd = (int)((gridDim.x + 7) / 8);
@@ -1276,18 +1346,23 @@ __global__ void __launch_bounds__(256) grad_mfma8(Params p, int row_len, int nse
   const int seg = L / (p.n + 1), a = L % (p.n + 1);
   const int64_t E = bsz(p);
   const bool ina = a >= p.m0 && a < p.m1;
-  {  // stage the row's X blocks (Sigma^R(a), gIR(a), gIL(a), gItv(a)), zero-padded to 8 x 8
-    const int x = tid >> 6, r = (tid >> 3) & 7, c = tid & 7;
+  // stage the row's X blocks (Sigma^R(a), gIR(a), gIL(a), gItv(a); TS = 2 also pg's gIR(a),
+  // gIL(a)), zero-padded to 8 x 8
+  for (int s = tid; s < NX * 64; s += 256) {
+    const int x = s >> 6, r = (s >> 3) & 7, c = s & 7;
     const bool present = x == 0 || (x == 1 && p.fIR && ina) || (x == 2 && p.fIL && ina) ||
-                         (x == 3 && p.fITV && ina);
+                         (x == 3 && p.fITV && ina) || (x == 4 && pg.fIR && ina) ||
+                         (x == 5 && pg.fIL && ina);
     const kbe_c128 *X = x == 0 ? p.ret + a * E
                         : x == 1 ? p.gIR + (a - p.m0) * E
                         : x == 2 ? p.gIL + (a - p.m0) * E
-                                 : p.gItv + (a - p.m0) * E;
+                        : x == 3 ? p.gItv + (a - p.m0) * E
+                        : x == 4 ? pg.gIR + (a - p.m0) * E
+                                 : pg.gIL + (a - p.m0) * E;
     xs[x][r * XLD8 + c] = (present && r < N && c < N) ? ld(X + r * N + c) : czero();
   }
   const int j0 = seg * GSEG8, len = (j0 + GSEG8 < row_len ? j0 + GSEG8 : row_len) - j0;
-  if (tid < GSEG8) fill_grad_rec<TS>(p, a, j0, len, tid, rec[tid]);
+  if (tid < GSEG8) fill_grad_rec8<TS>(p, pg, a, j0, len, tid, rec[tid]);
   __syncthreads();
   const int lj = lane & 3, lb = (lane >> 2) & 3, lk = lane >> 4;
   const int ti = lb >> 1, tj = lb & 1;
@@ -1298,33 +1373,43 @@ __global__ void __launch_bounds__(256) grad_mfma8(Params p, int row_len, int nse
   // D element: row 4 ti + lk, column 4 tj + lj
   const bool dv = 4 * ti + lk < N && bc < N;
   const int dof = dv ? (4 * ti + lk) * N + bc : 0;
-  constexpr int NTM = TS == 0 ? 2 : 3;  // terms per block, at most
   cd yn[NTM][2];  // raw Y of [term][kc] of the block after the current one
+  cd dn = czero();  // that block's current destination value, when it adds to it
+  auto adds = [&](int q) {  // wave-uniform: does block q add to its destination's value?
+    if constexpr (TS == 1) return __builtin_amdgcn_readfirstlane(rec[q].acc) != 0;
+    else return !p.overwrite;
+  };
   auto fetch = [&](int q) {
-    const kbe_c128 *Y[3] = {uniform_ptr(rec[q].y0), uniform_ptr(rec[q].y1),
-                            uniform_ptr(rec[q].y2)};
+    const int cnt = __builtin_amdgcn_readfirstlane(rec[q].nt);
 #pragma unroll
     for (int tm = 0; tm < NTM; ++tm) {
-      yn[tm][0] = ldg(Y[tm] + bo0);
-      yn[tm][1] = ldg(Y[tm] + bo1);
+      if (TS == 2 && tm > 1 && tm >= cnt) break;  // wave-uniform: present terms' loads only
+      const kbe_c128 *Y = uniform_ptr(rec[q].y[tm]);
+      yn[tm][0] = ldg(Y + bo0);
+      yn[tm][1] = ldg(Y + bo1);
     }
+    if (cnt > 0 && adds(q) && dv) dn = ldg(uniform_ptr(rec[q].dst) + dof);
   };
   int q = __builtin_amdgcn_readfirstlane(wave);
   if (q < len) fetch(q);
   for (; q < len; q += 4) {
     const int cnt = __builtin_amdgcn_readfirstlane(rec[q].nt);
     kbe_c128 *const cdst = (kbe_c128 *)uniform_ptr(rec[q].dst);
-    const cd cs[3] = {{rec[q].c0r, rec[q].c0i}, {rec[q].c1r, rec[q].c1i},
-                      {rec[q].c2r, rec[q].c2i}};
-    const cd *xt[3] = {xs[__builtin_amdgcn_readfirstlane(rec[q].x0)],
-                       xs[__builtin_amdgcn_readfirstlane(rec[q].x1)],
-                       xs[__builtin_amdgcn_readfirstlane(rec[q].x2)]};
+    cd cs[NTM];
+    const cd *xt[NTM];
+#pragma unroll
+    for (int tm = 0; tm < NTM; ++tm) {
+      cs[tm] = cd{rec[q].cr[tm], rec[q].ci[tm]};
+      xt[tm] = xs[__builtin_amdgcn_readfirstlane(rec[q].x[tm])];
+    }
     cd y[NTM][2];
 #pragma unroll
     for (int tm = 0; tm < NTM; ++tm) {
+      if (TS == 2 && tm > 1 && tm >= cnt) break;
       y[tm][0] = cs[tm] * (bv0 ? yn[tm][0] : czero());
       y[tm][1] = cs[tm] * (bv1 ? yn[tm][1] : czero());
     }
+    const cd dcur = dn;  // this block's destination value (loaded with its Y)
     fetch(q + 4 < len ? q + 4 : len - 1);  // next block's loads before this block's work
     if (cnt == 0) continue;
     __builtin_amdgcn_sched_barrier(0);
@@ -1347,11 +1432,7 @@ __global__ void __launch_bounds__(256) grad_mfma8(Params p, int row_len, int nse
     cd r{k1 + k3, k1 + k2};
     if (dv) {
       kbe_c128 *d = cdst + dof;
-      if constexpr (TS == 0) {
-        if (!p.overwrite) r = r + ldg(d);
-      } else if (__builtin_amdgcn_readfirstlane(rec[q].acc)) {
-        r = r + ldg(d);
-      }
+      if (adds(q)) r = r + dcur;
       dvec2 w;
       w.x = r.re;
       w.y = r.im;
@@ -1693,10 +1774,11 @@ hipError_t launch_collision_both(const Params &p, kbe_c128 *IRl, kbe_c128 *ILl, 
   return hipGetLastError();
 }
 
-hipError_t launch_collision_vjp(const Params &p, unsigned flags, kbe_c128 *gmat,
-                                const kbe_sigma_row *gS, void *ws, hipStream_t st) {
+namespace {
+// The self-energy (and G^M) gradients of an adjoint call: the stream task pass and its reduces.
+void vjp_sums(const Params &p, unsigned flags, kbe_c128 *gmat, const kbe_sigma_row *gS,
+              void *ws, hipStream_t st) {
   const int kind = path_kind(p.N, flags);
-  const bool mfma = kind == KIND_MFMA;
   FusedPlan pl;
   plan_adjoint(p.N, p.ntau, p.n, p.m0, p.m1, flags, kind, pl);
   char *w = (char *)ws;
@@ -1719,11 +1801,26 @@ hipError_t launch_collision_vjp(const Params &p, unsigned flags, kbe_c128 *gmat,
     if (p.fJTV) reduce_into(p, pl, {G_MAT1, G_MAT2}, w, p.ntau, gmat, !p.overwrite, r);
     reduce_launch(p, r, st);
   }
-  // Green's-function gradients
+}
+
+void launch_grad8(int TS, const Params &p, const Params &pg, int row_len, hipStream_t st) {
+  const int nseg = (row_len + GSEG8 - 1) / GSEG8;
+  const int64_t tasks = (int64_t)(p.n + 1) * nseg;
+  const dim3 grid((unsigned)(8 * ((tasks + 7) / 8)));
+  if (TS == 0) hipLaunchKernelGGL(grad_mfma8<0>, grid, dim3(256), 0, st, p, pg, row_len, nseg);
+  else if (TS == 1) hipLaunchKernelGGL(grad_mfma8<1>, grid, dim3(256), 0, st, p, pg, row_len, nseg);
+  else hipLaunchKernelGGL(grad_mfma8<2>, grid, dim3(256), 0, st, p, pg, row_len, nseg);
+}
+
+// The Green's-function gradients of an adjoint call.  The greater form adds its extra terms
+// (those beyond the terms the forms share); at 5 <= N <= 8 both sets go in one pass.
+void vjp_grads(const Params &p, unsigned flags, hipStream_t st) {
+  const int kind = path_kind(p.N, flags);
+  const bool extra = flags & KBE_INT_GREXTRA;
   const int64_t n1 = p.n + 1;
   const int64_t nblk = n1 * n1 + n1 + (p.ntau > 0 ? n1 * p.ntau : 0);
   const int row_len = p.n + 2 + p.ntau;  // kp row, tv row, rdiag
-  if (mfma) {
+  if (kind == KIND_MFMA) {
     const int nseg = (row_len + GSEG - 1) / GSEG;
     const int64_t tasks = (int64_t)(p.n + 1) * nseg;
     if (!extra)
@@ -1733,21 +1830,46 @@ hipError_t launch_collision_vjp(const Params &p, unsigned flags, kbe_c128 *gmat,
       hipLaunchKernelGGL(grad_mfma16<1>, dim3((unsigned)(8 * ((tasks + 7) / 8))), dim3(256), 0,
                          st, p, row_len, nseg);
   } else if (kind >= 5 && kind <= 8) {
-    const int nseg = (row_len + GSEG8 - 1) / GSEG8;
-    const int64_t tasks = (int64_t)(p.n + 1) * nseg;
-    if (!extra)
-      hipLaunchKernelGGL(grad_mfma8<0>, dim3((unsigned)(8 * ((tasks + 7) / 8))), dim3(256), 0,
-                         st, p, row_len, nseg);
-    if (flags & KBE_GREATER)  // the greater form's extra terms, in one more pass
-      hipLaunchKernelGGL(grad_mfma8<1>, dim3((unsigned)(8 * ((tasks + 7) / 8))), dim3(256), 0,
-                         st, p, row_len, nseg);
-  } else if (!extra) {
-    const int64_t th = nblk * p.N * p.N;
-    hipLaunchKernelGGL(grad_generic, dim3((unsigned)((th + 255) / 256)), dim3(256), 0, st, p, nblk);
+    launch_grad8(extra ? 1 : (flags & KBE_GREATER) ? 2 : 0, p, p, row_len, st);
+  } else {
+    if (!extra) {
+      const int64_t th = nblk * p.N * p.N;
+      hipLaunchKernelGGL(grad_generic, dim3((unsigned)((th + 255) / 256)), dim3(256), 0, st, p,
+                         nblk);
+    }
+    if (flags & KBE_GREATER) {  // adds to what it wrote
+      const int64_t nk = n1 * n1 + n1, tk = nk * p.N * p.N;  // kp and rdiag blocks
+      hipLaunchKernelGGL(grad_greater, dim3((unsigned)((tk + 255) / 256)), dim3(256), 0, st, p,
+                         nk);
+    }
   }
-  if ((flags & KBE_GREATER) && !mfma && !(kind >= 5 && kind <= 8)) {  // adds to what it wrote
-    const int64_t nk = n1 * n1 + n1, tk = nk * p.N * p.N;  // kp and rdiag blocks
-    hipLaunchKernelGGL(grad_greater, dim3((unsigned)((tk + 255) / 256)), dim3(256), 0, st, p, nk);
+}
+}  // namespace
+
+hipError_t launch_collision_vjp(const Params &p, unsigned flags, kbe_c128 *gmat,
+                                const kbe_sigma_row *gS, void *ws, hipStream_t st) {
+  vjp_sums(p, flags, gmat, gS, ws, st);
+  vjp_grads(p, flags, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_collision_vjp_pair(const Params &p, unsigned flags, const Params &pg,
+                                     unsigned gflags, kbe_c128 *gmat, const kbe_sigma_row *gS,
+                                     const kbe_sigma_row *gSg, void *ws, hipStream_t st) {
+  vjp_sums(p, flags, gmat, gS, ws, st);
+  vjp_sums(pg, gflags, gmat, gSg, ws, st);  // stream-ordered after the first pass's reduces
+  const int kind = path_kind(p.N, flags);
+  // one pass when the two sets share everything but their cotangents and flags
+  const bool same = p.N == pg.N && p.n == pg.n && p.m0 == pg.m0 && p.m1 == pg.m1 &&
+                    p.ntau == pg.ntau && p.ret == pg.ret && p.w == pg.w && p.gkp == pg.gkp &&
+                    p.grdiag == pg.grdiag && p.gtv == pg.gtv && p.ldt == pg.ldt &&
+                    p.overwrite == pg.overwrite;
+  if (same && kind >= 5 && kind <= 8 && kind == path_kind(pg.N, gflags) &&
+      !(flags & KBE_GREATER) && (gflags & KBE_INT_GREXTRA)) {
+    launch_grad8(2, p, pg, p.n + 2 + p.ntau, st);
+  } else {
+    vjp_grads(p, flags, st);
+    vjp_grads(pg, gflags, st);
   }
   return hipGetLastError();
 }

@@ -63,6 +63,14 @@ size_t collision_ws_bytes_rows(int N, int nt, int ntau, unsigned flags);
 size_t collision_vjp_ws_bytes_rows(int N, int nt, int ntau, unsigned flags);
 hipError_t launch_collision_vjp(const Params &p, unsigned flags, kbe_c128 *gmat,
                                 const kbe_sigma_row *gS, void *ws, hipStream_t st);
+// The lesser form's adjoint (p, flags; accumulate mode) and the greater form's extra terms on
+// their own cotangents (pg, gflags = KBE_OUT_IR | KBE_OUT_IL | KBE_GREATER | KBE_INT_GREXTRA,
+// gradients into gS and gSg), as two launch_collision_vjp calls would compute them; pg differs
+// from p in its cotangents and flags only.  At 5 <= N <= 8 the Green's-function gradients of
+// both take one pass.
+hipError_t launch_collision_vjp_pair(const Params &p, unsigned flags, const Params &pg,
+                                     unsigned gflags, kbe_c128 *gmat, const kbe_sigma_row *gS,
+                                     const kbe_sigma_row *gSg, void *ws, hipStream_t st);
 
 // Batches of history rows (kbe_batch.hip).
 int batch_default_chunk();

@@ -705,19 +705,19 @@ hipError_t evaluate_vjp(Ctx &x, int n, int mode, double *gu, double *gamp) {
   // Both forms by linearity: the lesser form's adjoint with the summed cotangents (the terms
   // the forms share, I^R's and the Sigma^< part of I^<, enter C^< and C^> alike, as I^] does:
   // CbT = CbL + CbG), then the greater form's further terms with its own cotangent.
+  Params pg = p;
   set_flags(p, FL, th);
   p.gIR = x.a.CbT;
   p.gIL = x.a.CbT;
   p.gItv = x.a.CbT;
   p.gJ = x.a.Jbar;
-  e = launch_collision_vjp(p, FL, x.gG.mat, &x.gSL, x.ws + x.L.vws, x.st);
-  if (e != hipSuccess) return e;
-  set_flags(p, FG, th);
-  p.gIR = x.a.CbG;
-  p.gIL = x.a.CbG;
-  p.gItv = nullptr;
-  p.gJ = nullptr;
-  e = launch_collision_vjp(p, FG | KBE_INT_GREXTRA, x.gG.mat, &x.gSG, x.ws + x.L.vws, x.st);
+  set_flags(pg, FG, th);
+  pg.gIR = x.a.CbG;
+  pg.gIL = x.a.CbG;
+  pg.gItv = nullptr;
+  pg.gJ = nullptr;
+  e = launch_collision_vjp_pair(p, FL, pg, FG | KBE_INT_GREXTRA, x.gG.mat, &x.gSL, &x.gSG,
+                                x.ws + x.L.vws, x.st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(prop_gs_add, dim3(blocks((int64_t)(n + 1) * E)), dim3(256), 0, x.st, x.a, n);
   return launch_sigma_row_vjp(&x.Gc, x.a.u, n, &x.gSL, &x.gG, gu, x.ws + x.L.sws, x.st);
