@@ -1082,14 +1082,26 @@ __device__ __forceinline__ int grad_row_terms_gr(const Params &p, int a, int j, 
   return nt;
 }
 
+// Term sets of the gradient kernels (grad_mfma16<TS>, grad_mfma8<TS>): 0 the terms both forms
+// share (at most two per block, X ids 0..3), 1 the greater form's extra terms (at most three,
+// X ids 0..2), 2 both sets in one pass: the shared terms with the first parameter set's
+// cotangents and the extra terms with the second's, whose gIR(a), gIL(a) are staged as X ids
+// 4, 5.  At most four then: a kp block below the diagonal has one shared term and at most three
+// extra ones, rdiag one and two, the other blocks no extra term.
+template <int TS> struct GradSet {
+  static constexpr int NT = TS == 0 ? 2 : TS == 1 ? 3 : 4;  // terms per block, at most
+  static constexpr int NX = TS == 2 ? 6 : 4;                // staged X blocks per row
+};
+
 // Per-block term record of a segment, built once per workgroup in LDS.
-struct GradRec {
-  const kbe_c128 *y0, *y1, *y2;  // Y of terms 0..2 (term 0's Y again for absent terms)
+template <int NT> struct GradRec {
+  const kbe_c128 *y[NT];  // Y of each term (term 0's Y again for absent terms)
   kbe_c128 *dst;
-  double c0r, c0i, c1r, c1i, c2r, c2i;  // scalars (0 for absent terms)
-  int x0, x1, x2, nt;
+  double cr[NT], ci[NT];  // scalars (0 for absent terms)
+  int x[NT], nt;
   int acc;  // add the block's current value (accumulate mode, or a block an earlier pass wrote)
 };
+
 
 __device__ __forceinline__ const kbe_c128 *uniform_ptr(const kbe_c128 *q) {
   const uint64_t v = (uint64_t)q;
@@ -1103,190 +1115,13 @@ __device__ __forceinline__ d4g mfma16f(double a, double b, d4g c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// The record of block j0 + tid of row a.  TS = 0: the terms of both forms' common part
-// (grad_row_terms); TS = 1: the greater form's extra terms (grad_row_terms_gr), which add to what
-// the TS = 0 pass wrote (accumulate mode, or a block that pass reached).
-template <int TS>
-__device__ __forceinline__ void fill_grad_rec(const Params &p, int a, int j0, int len, int tid,
-                                              GradRec &g) {
-  GradTerm t0{-1, czero(), p.ret}, t1 = t0, t2 = t0;
-  kbe_c128 *d = p.gkp;
-  int nt = 0, acc = !p.overwrite;
-  if (tid < len) {
-    if constexpr (TS == 0) {
-      nt = grad_row_terms(p, a, j0 + tid, t0, t1, d);
-    } else {
-      nt = grad_row_terms_gr(p, a, j0 + tid, t0, t1, t2, d);
-      GradTerm u0, u1;
-      kbe_c128 *dd;
-      acc = acc || grad_row_terms(p, a, j0 + tid, u0, u1, dd) > 0;
-    }
-  }
-  g.y0 = t0.Y;
-  g.y1 = nt > 1 ? t1.Y : t0.Y;
-  g.y2 = nt > 2 ? t2.Y : t0.Y;
-  g.dst = d;
-  g.c0r = t0.c.re;
-  g.c0i = t0.c.im;
-  g.c1r = nt > 1 ? t1.c.re : 0.0;
-  g.c1i = nt > 1 ? t1.c.im : 0.0;
-  g.c2r = nt > 2 ? t2.c.re : 0.0;
-  g.c2i = nt > 2 ? t2.c.im : 0.0;
-  g.x0 = t0.xid < 0 ? 0 : t0.xid;
-  g.x1 = nt > 1 ? t1.xid : 0;
-  g.x2 = nt > 2 ? t2.xid : 0;
-  g.nt = nt;
-  g.acc = acc;
-}
-
-// TS = 0: the terms of both forms' common part; TS = 1: the greater form's extra terms, run
-// after TS = 0 and adding to what it wrote.  At most two terms per block for TS = 0, three for
-// TS = 1.
-template <int TS>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
-grad_mfma16(Params p, int row_len, int nseg) {
-  __shared__ cd xs[4][16 * QLD];
-  __shared__ GradRec rec[GSEG];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int lk = lane >> 4, lc = lane & 15;
-  // Workgroups are dealt round-robin to the 8 XCDs; XCD x walks the segment-major range
-  // [x per_xcd, (x+1) per_xcd) of (segment, row) pairs, so the column operands (Y) its L2 holds
-  // belong to about one segment at a time.  The results bypass the caches (streaming stores) so
-  // that they do not evict those operands.
-  const int per_xcd = (int)((gridDim.x + 7) / 8);
-  const int L = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-  if (L >= (p.n + 1) * nseg) return;  // whole workgroup: before any barrier
-  const int seg = L / (p.n + 1), a = L % (p.n + 1);
-  const int64_t E = bsz(p);
-  const bool ina = a >= p.m0 && a < p.m1;
-  {  // stage the row's X blocks: Sigma^R(a), gIR(a), gIL(a), gItv(a) (zeros when absent)
-    const int r = tid >> 4, c = tid & 15;
-    xs[0][r * QLD + c] = ld(p.ret + a * E + tid);
-    xs[1][r * QLD + c] = (p.fIR && ina) ? ld(p.gIR + (a - p.m0) * E + tid) : czero();
-    xs[2][r * QLD + c] = (p.fIL && ina) ? ld(p.gIL + (a - p.m0) * E + tid) : czero();
-    xs[3][r * QLD + c] = (p.fITV && ina) ? ld(p.gItv + (a - p.m0) * E + tid) : czero();
-  }
-  const int j0 = seg * GSEG, len = (j0 + GSEG < row_len ? j0 + GSEG : row_len) - j0;
-  if (tid < GSEG) fill_grad_rec<TS>(p, a, j0, len, tid, rec[tid]);
-  __syncthreads();
-  constexpr int NTM = TS == 0 ? 2 : 3;  // terms per block, at most
-  cd yn[NTM][4];  // raw Y slabs of the block after the current one
-  // Every record's Y pointers are valid (a block without terms points at Sigma^R(0)), so the
-  // prefetch is unconditional; past the end of the segment it re-reads the last record.
-  auto fetch = [&](int q) {
-    const kbe_c128 *Y[3] = {uniform_ptr(rec[q].y0), uniform_ptr(rec[q].y1),
-                            uniform_ptr(rec[q].y2)};
-#pragma unroll
-    for (int kc = 0; kc < 4; ++kc)
-#pragma unroll
-      for (int tm = 0; tm < NTM; ++tm) yn[tm][kc] = ldg(Y[tm] + (4 * kc + lk) * 16 + lc);
-  };
-  // A block's result is held for one iteration and written one 16 x 4 slab per inner step of
-  // the next block, so each wave's stores spread over its products instead of a burst.
-  cd prev[4];
-  kbe_c128 *pdst = nullptr;
-  int pacc = 0;
-  auto put = [&](int r) {  // rows l/16 + 4 r of the held result
-    kbe_c128 *d = pdst + (lk + 4 * r) * 16 + lc;
-    cd v = prev[r];
-    if constexpr (TS == 0) {
-      if (!p.overwrite) v = v + ldg(d);
-    } else if (pacc) {
-      v = v + ldg(d);
-    }
-    dvec2 w;
-    w.x = v.re;
-    w.y = v.im;
-    __builtin_nontemporal_store(w, (g_dvec2 *)(void *)d);
-  };
-  int q = __builtin_amdgcn_readfirstlane(wave);
-  if (q < len) fetch(q);
-  for (; q < len; q += 4) {
-    const int cnt = __builtin_amdgcn_readfirstlane(rec[q].nt);
-    kbe_c128 *const cdst = (kbe_c128 *)uniform_ptr(rec[q].dst);
-    const cd cs[3] = {{rec[q].c0r, rec[q].c0i}, {rec[q].c1r, rec[q].c1i},
-                      {rec[q].c2r, rec[q].c2i}};
-    const cd *xt[3] = {xs[__builtin_amdgcn_readfirstlane(rec[q].x0)],
-                       xs[__builtin_amdgcn_readfirstlane(rec[q].x1)],
-                       xs[__builtin_amdgcn_readfirstlane(rec[q].x2)]};
-    cd y[NTM][4];
-#pragma unroll
-    for (int kc = 0; kc < 4; ++kc)
-#pragma unroll
-      for (int tm = 0; tm < NTM; ++tm) y[tm][kc] = cs[tm] * yn[tm][kc];
-    // issue the next block's loads before this block's products and stores
-    fetch(q + 4 < len ? q + 4 : len - 1);
-    if (cnt == 0) continue;
-    // Three real products per complex one (Gauss): with A = conj(X), for each k-chunk
-    //   K1 += (xr - xi) yr,   K2 += xr (yi - yr),   K3 += xi (yr + yi);
-    // then Re = K1 + K3 and Im = K1 + K2.  Both terms of the block share the accumulators.
-    // v_mfma_f64_16x16x4: lane l supplies A[l%16][4 kc + l/16] = conj(X[4 kc + l/16][l%16]) and
-    // B[4 kc + l/16][l%16] = c Y[..], and holds D[l/16 + 4 r][l%16].
-    d4g k1 = {0, 0, 0, 0}, k2 = {0, 0, 0, 0}, k3 = {0, 0, 0, 0};
-#pragma unroll
-    for (int kc = 0; kc < 4; ++kc) {
-#pragma unroll
-      for (int term = 0; term < NTM; ++term) {
-        if (term >= cnt) break;  // wave-uniform
-        const cd *x = xt[term];
-        const cd yv = y[term][kc];
-        const cd u = x[(4 * kc + lk) * QLD + lc];
-        const double ys = yv.im - yv.re, yp = yv.re + yv.im;
-        __builtin_amdgcn_sched_barrier(0);
-        k1 = mfma16f(u.re - u.im, yv.re, k1);
-        k2 = mfma16f(u.re, ys, k2);
-        k3 = mfma16f(u.im, yp, k3);
-        __builtin_amdgcn_sched_barrier(0);
-      }
-      if (pdst) put(kc);
-      __builtin_amdgcn_sched_barrier(0);
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) prev[r] = cd{k1[r] + k3[r], k1[r] + k2[r]};
-    pdst = cdst;
-    if constexpr (TS != 0) pacc = __builtin_amdgcn_readfirstlane(rec[q].acc);
-  }
-  if (pdst) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) put(r);
-  }
-}
-
-// MFMA version for 5 <= N <= 8.  Blocks are zero-padded to 8 x 8 and one v_mfma_f64_4x4x4
-// instruction computes all four 4 x 4 tiles (ti, tj) of an 8 x 8 product (instruction block
-// b = 2 ti + tj), so a block costs two k-chunks of three real products per term.  Lane roles:
-//   A[b][i][k] = conj(X[4 kc + k][4 ti + i])  at lane 4b + i + 16k   (read from LDS),
-//   B[b][k][j] = c Y[4 kc + k][4 tj + j]      at lane 4b + j + 16k   (loaded from the cache),
-//   D[b][i][j] = out[4 ti + i][4 tj + j]      at lane 4b + j + 16i,
-// so lanes 8r .. 8r+7 of a store hold a whole row of the block (128 contiguous bytes at N = 8).
-// Work split, records, prefetch and streaming stores as in grad_mfma16.
-constexpr int GSEG8 = 64;   // blocks per workgroup segment (64 beat 32, 128 and 256)
-constexpr int XLD8 = 9;     // LDS row stride of a staged 8x8 block, in complex numbers
-
-// Term sets of grad_mfma8<TS>: 0 the terms both forms share (at most two per block, X ids
-// 0..3), 1 the greater form's extra terms (at most three, X ids 0..2), 2 both sets in one pass
-// (at most five): the shared terms with the first parameter set's cotangents and the extra
-// terms with the second's, whose gIR(a), gIL(a) are staged as X ids 4, 5.
-template <int TS> struct Gr8 {
-  static constexpr int NT = TS == 0 ? 2 : TS == 1 ? 3 : 5;  // terms per block, at most
-  static constexpr int NX = TS == 2 ? 6 : 4;                // staged X blocks per row
-};
-
-template <int NT> struct GradRec8 {
-  const kbe_c128 *y[NT];  // Y of each term (term 0's Y again for absent terms)
-  kbe_c128 *dst;
-  double cr[NT], ci[NT];  // scalars (0 for absent terms)
-  int x[NT], nt;
-  int acc;  // add the block's current value (accumulate mode, or a block an earlier pass wrote)
-};
-
 // The record of block j0 + tid of row a.  TS = 1 adds to what the TS = 0 pass wrote
 // (accumulate mode, or a block that pass reached); TS = 2 writes each block once with both
 // sets' terms, the shared terms first.
 template <int TS>
-__device__ __forceinline__ void fill_grad_rec8(const Params &p, const Params &pg, int a, int j0,
-                                               int len, int tid, GradRec8<Gr8<TS>::NT> &g) {
-  constexpr int NT = Gr8<TS>::NT;
+__device__ __forceinline__ void fill_grad_rec(const Params &p, const Params &pg, int a, int j0,
+                                              int len, int tid, GradRec<GradSet<TS>::NT> &g) {
+  constexpr int NT = GradSet<TS>::NT;
   GradTerm t[5];
 #pragma unroll
   for (int k = 0; k < 5; ++k) t[k] = GradTerm{-1, czero(), p.ret};
@@ -1331,13 +1166,185 @@ __device__ __forceinline__ void fill_grad_rec8(const Params &p, const Params &pg
   g.acc = acc;
 }
 
-// TS: the term set (Gr8).  pg is read by TS = 2 only (the greater form's extra terms; its Sigma
+// TS: the term set (GradSet); TS = 1 runs after TS = 0 and adds to what it wrote.  pg is read by
+// TS = 2 only (the greater form's extra terms; its Sigma row, gradients, row range and mode are
+// those of p).  The Y of terms 0 and 1 are loaded a block ahead (TS = 1: terms 0..2); TS = 2
+// loads terms 2 and 3 (blocks below the diagonal and rdiag) at the start of their block, ahead
+// of the next block's loads, and multiplies them after terms 0 and 1.
+// ACC (TS = 0): accumulate mode; a block's current values are loaded as soon as its result is
+// held, ahead of its stores (for TS = 1 and 2 the registers this needs cost more than the early
+// loads gain: they load them at the store).
+template <int TS, bool ACC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+grad_mfma16(Params p, Params pg, int row_len, int nseg) {
+  constexpr int NTR = GradSet<TS>::NT, NX = GradSet<TS>::NX;
+  constexpr int NTM = TS == 1 ? 3 : 2;  // terms whose Y are loaded a block ahead
+  __shared__ cd xs[NX][16 * QLD];
+  __shared__ GradRec<NTR> rec[GSEG];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lk = lane >> 4, lc = lane & 15;
+  // Workgroups are dealt round-robin to the 8 XCDs; XCD x walks the segment-major range
+  // [x per_xcd, (x+1) per_xcd) of (segment, row) pairs, so the column operands (Y) its L2 holds
+  // belong to about one segment at a time.  The results bypass the caches (streaming stores) so
+  // that they do not evict those operands.
+  const int per_xcd = (int)((gridDim.x + 7) / 8);
+  const int L = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (L >= (p.n + 1) * nseg) return;  // whole workgroup: before any barrier
+  const int seg = L / (p.n + 1), a = L % (p.n + 1);
+  const int64_t E = bsz(p);
+  const bool ina = a >= p.m0 && a < p.m1;
+  {  // stage the row's X blocks: Sigma^R(a), gIR(a), gIL(a), gItv(a) (zeros when absent), and
+     // for TS = 2 pg's gIR(a), gIL(a)
+    const int r = tid >> 4, c = tid & 15;
+    xs[0][r * QLD + c] = ld(p.ret + a * E + tid);
+    xs[1][r * QLD + c] = (p.fIR && ina) ? ld(p.gIR + (a - p.m0) * E + tid) : czero();
+    xs[2][r * QLD + c] = (p.fIL && ina) ? ld(p.gIL + (a - p.m0) * E + tid) : czero();
+    xs[3][r * QLD + c] = (p.fITV && ina) ? ld(p.gItv + (a - p.m0) * E + tid) : czero();
+    if constexpr (NX > 4) {
+      xs[4][r * QLD + c] = (pg.fIR && ina) ? ld(pg.gIR + (a - p.m0) * E + tid) : czero();
+      xs[5][r * QLD + c] = (pg.fIL && ina) ? ld(pg.gIL + (a - p.m0) * E + tid) : czero();
+    }
+  }
+  const int j0 = seg * GSEG, len = (j0 + GSEG < row_len ? j0 + GSEG : row_len) - j0;
+  if (tid < GSEG) fill_grad_rec<TS>(p, pg, a, j0, len, tid, rec[tid]);
+  __syncthreads();
+  cd yn[NTM][4];  // raw Y slabs of the block after the current one
+  // Every record's Y pointers are valid (a block without terms points at Sigma^R(0)), so the
+  // prefetch is unconditional; past the end of the segment it re-reads the last record.
+  auto fetch = [&](int q) {
+    const kbe_c128 *Y[NTM];
+#pragma unroll
+    for (int tm = 0; tm < NTM; ++tm) Y[tm] = uniform_ptr(rec[q].y[tm]);
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc)
+#pragma unroll
+      for (int tm = 0; tm < NTM; ++tm) yn[tm][kc] = ldg(Y[tm] + (4 * kc + lk) * 16 + lc);
+  };
+  // A block's result is held for one iteration and written one 16 x 4 slab per inner step of
+  // the next block, so each wave's stores spread over its products instead of a burst.
+  cd prev[4], dprev[4];
+  kbe_c128 *pdst = nullptr;
+  int pacc = 0;
+  auto put = [&](int r) {  // rows l/16 + 4 r of the held result
+    kbe_c128 *d = pdst + (lk + 4 * r) * 16 + lc;
+    cd v = prev[r];
+    if constexpr (ACC && TS == 0) {
+      v = v + dprev[r];
+    } else if (pacc) {
+      v = v + ldg(d);
+    }
+    dvec2 w;
+    w.x = v.re;
+    w.y = v.im;
+    __builtin_nontemporal_store(w, (g_dvec2 *)(void *)d);
+  };
+  // Three real products per complex one (Gauss): with A = conj(X), for each k-chunk
+  //   K1 += (xr - xi) yr,   K2 += xr (yi - yr),   K3 += xi (yr + yi);
+  // then Re = K1 + K3 and Im = K1 + K2.  All terms of the block share the accumulators.
+  // v_mfma_f64_16x16x4: lane l supplies A[l%16][4 kc + l/16] = conj(X[4 kc + l/16][l%16]) and
+  // B[4 kc + l/16][l%16] = c Y[..], and holds D[l/16 + 4 r][l%16].
+  d4g k1, k2, k3;
+  auto product = [&](const cd *x, cd yv, int kc) {
+    const cd u = x[(4 * kc + lk) * QLD + lc];
+    const double ys = yv.im - yv.re, yp = yv.re + yv.im;
+    __builtin_amdgcn_sched_barrier(0);
+    k1 = mfma16f(u.re - u.im, yv.re, k1);
+    k2 = mfma16f(u.re, ys, k2);
+    k3 = mfma16f(u.im, yp, k3);
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  int q = __builtin_amdgcn_readfirstlane(wave);
+  if (q < len) fetch(q);
+  for (; q < len; q += 4) {
+    const int cnt = __builtin_amdgcn_readfirstlane(rec[q].nt);
+    kbe_c128 *const cdst = (kbe_c128 *)uniform_ptr(rec[q].dst);
+    cd cs[NTR];
+    const cd *xt[NTR];
+#pragma unroll
+    for (int tm = 0; tm < NTR; ++tm) {
+      cs[tm] = cd{rec[q].cr[tm], rec[q].ci[tm]};
+      xt[tm] = xs[__builtin_amdgcn_readfirstlane(rec[q].x[tm])];
+    }
+    cd y[NTM][4];
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc)
+#pragma unroll
+      for (int tm = 0; tm < NTM; ++tm) y[tm][kc] = cs[tm] * yn[tm][kc];
+    cd z[2][4];  // TS = 2: raw Y of terms 2 and 3 of this block
+    if constexpr (TS == 2) {
+      if (cnt > 2) {  // wave-uniform; term 3's Y is term 0's when absent
+        const kbe_c128 *Z0 = uniform_ptr(rec[q].y[2]), *Z1 = uniform_ptr(rec[q].y[3]);
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) {
+          z[0][kc] = ldg(Z0 + (4 * kc + lk) * 16 + lc);
+          z[1][kc] = ldg(Z1 + (4 * kc + lk) * 16 + lc);
+        }
+      }
+    }
+    // issue the next block's loads before this block's products and stores
+    fetch(q + 4 < len ? q + 4 : len - 1);
+    if (cnt == 0) continue;
+    k1 = d4g{0, 0, 0, 0};
+    k2 = d4g{0, 0, 0, 0};
+    k3 = d4g{0, 0, 0, 0};
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) {
+#pragma unroll
+      for (int term = 0; term < NTM; ++term) {
+        if (term >= cnt) break;  // wave-uniform
+        product(xt[term], y[term][kc], kc);
+      }
+      if (pdst) put(kc);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if constexpr (TS == 2) {
+      if (cnt > 2) {
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) {
+#pragma unroll
+          for (int t2 = 0; t2 < 2; ++t2) {
+            if (2 + t2 >= cnt) break;  // wave-uniform
+            product(xt[2 + t2], cs[2 + t2] * z[t2][kc], kc);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) prev[r] = cd{k1[r] + k3[r], k1[r] + k2[r]};
+    pdst = cdst;
+    if constexpr (ACC && TS == 0) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dprev[r] = ldg(pdst + (lk + 4 * r) * 16 + lc);
+    } else if constexpr (TS == 1) {
+      pacc = __builtin_amdgcn_readfirstlane(rec[q].acc);
+    } else if constexpr (TS == 2) {
+      pacc = !p.overwrite;
+    }
+  }
+  if (pdst) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) put(r);
+  }
+}
+
+// MFMA version for 5 <= N <= 8.  Blocks are zero-padded to 8 x 8 and one v_mfma_f64_4x4x4
+// instruction computes all four 4 x 4 tiles (ti, tj) of an 8 x 8 product (instruction block
+// b = 2 ti + tj), so a block costs two k-chunks of three real products per term.  Lane roles:
+//   A[b][i][k] = conj(X[4 kc + k][4 ti + i])  at lane 4b + i + 16k   (read from LDS),
+//   B[b][k][j] = c Y[4 kc + k][4 tj + j]      at lane 4b + j + 16k   (loaded from the cache),
+//   D[b][i][j] = out[4 ti + i][4 tj + j]      at lane 4b + j + 16i,
+// so lanes 8r .. 8r+7 of a store hold a whole row of the block (128 contiguous bytes at N = 8).
+// Work split, records, prefetch and streaming stores as in grad_mfma16.
+constexpr int GSEG8 = 64;   // blocks per workgroup segment (64 beat 32, 128 and 256)
+constexpr int XLD8 = 9;     // LDS row stride of a staged 8x8 block, in complex numbers
+
+// TS: the term set (GradSet).  pg is read by TS = 2 only (the greater form's extra terms; its Sigma
 // row, gradients, row range and mode are those of p).
 template <int TS>
 __global__ void __launch_bounds__(256) grad_mfma8(Params p, Params pg, int row_len, int nseg) {
-  constexpr int NTM = Gr8<TS>::NT, NX = Gr8<TS>::NX;
+  constexpr int NTM = GradSet<TS>::NT, NX = GradSet<TS>::NX;
   __shared__ cd xs[NX][8 * XLD8];
-  __shared__ GradRec8<NTM> rec[GSEG8];
+  __shared__ GradRec<NTM> rec[GSEG8];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int N = p.N;
   const int per_xcd = (int)((gridDim.x + 7) / 8);
@@ -1362,7 +1369,7 @@ __global__ void __launch_bounds__(256) grad_mfma8(Params p, Params pg, int row_l
     xs[x][r * XLD8 + c] = (present && r < N && c < N) ? ld(X + r * N + c) : czero();
   }
   const int j0 = seg * GSEG8, len = (j0 + GSEG8 < row_len ? j0 + GSEG8 : row_len) - j0;
-  if (tid < GSEG8) fill_grad_rec8<TS>(p, pg, a, j0, len, tid, rec[tid]);
+  if (tid < GSEG8) fill_grad_rec<TS>(p, pg, a, j0, len, tid, rec[tid]);
   __syncthreads();
   const int lj = lane & 3, lb = (lane >> 2) & 3, lk = lane >> 4;
   const int ti = lb >> 1, tj = lb & 1;
@@ -1803,6 +1810,20 @@ void vjp_sums(const Params &p, unsigned flags, kbe_c128 *gmat, const kbe_sigma_r
   }
 }
 
+void launch_grad16(int TS, const Params &p, const Params &pg, int row_len, hipStream_t st) {
+  const int nseg = (row_len + GSEG - 1) / GSEG;
+  const int64_t tasks = (int64_t)(p.n + 1) * nseg;
+  const dim3 grid((unsigned)(8 * ((tasks + 7) / 8)));
+  if (TS == 0 && p.overwrite)
+    hipLaunchKernelGGL((grad_mfma16<0, false>), grid, dim3(256), 0, st, p, pg, row_len, nseg);
+  else if (TS == 0)
+    hipLaunchKernelGGL((grad_mfma16<0, true>), grid, dim3(256), 0, st, p, pg, row_len, nseg);
+  else if (TS == 1)
+    hipLaunchKernelGGL((grad_mfma16<1, false>), grid, dim3(256), 0, st, p, pg, row_len, nseg);
+  else
+    hipLaunchKernelGGL((grad_mfma16<2, false>), grid, dim3(256), 0, st, p, pg, row_len, nseg);
+}
+
 void launch_grad8(int TS, const Params &p, const Params &pg, int row_len, hipStream_t st) {
   const int nseg = (row_len + GSEG8 - 1) / GSEG8;
   const int64_t tasks = (int64_t)(p.n + 1) * nseg;
@@ -1821,14 +1842,7 @@ void vjp_grads(const Params &p, unsigned flags, hipStream_t st) {
   const int64_t nblk = n1 * n1 + n1 + (p.ntau > 0 ? n1 * p.ntau : 0);
   const int row_len = p.n + 2 + p.ntau;  // kp row, tv row, rdiag
   if (kind == KIND_MFMA) {
-    const int nseg = (row_len + GSEG - 1) / GSEG;
-    const int64_t tasks = (int64_t)(p.n + 1) * nseg;
-    if (!extra)
-      hipLaunchKernelGGL(grad_mfma16<0>, dim3((unsigned)(8 * ((tasks + 7) / 8))), dim3(256), 0,
-                         st, p, row_len, nseg);
-    if (flags & KBE_GREATER)  // the greater form's extra terms, in one more pass
-      hipLaunchKernelGGL(grad_mfma16<1>, dim3((unsigned)(8 * ((tasks + 7) / 8))), dim3(256), 0,
-                         st, p, row_len, nseg);
+    launch_grad16(extra ? 1 : (flags & KBE_GREATER) ? 2 : 0, p, p, row_len, st);
   } else if (kind >= 5 && kind <= 8) {
     launch_grad8(extra ? 1 : (flags & KBE_GREATER) ? 2 : 0, p, p, row_len, st);
   } else {
@@ -1864,9 +1878,10 @@ hipError_t launch_collision_vjp_pair(const Params &p, unsigned flags, const Para
                     p.ntau == pg.ntau && p.ret == pg.ret && p.w == pg.w && p.gkp == pg.gkp &&
                     p.grdiag == pg.grdiag && p.gtv == pg.gtv && p.ldt == pg.ldt &&
                     p.overwrite == pg.overwrite;
-  if (same && kind >= 5 && kind <= 8 && kind == path_kind(pg.N, gflags) &&
-      !(flags & KBE_GREATER) && (gflags & KBE_INT_GREXTRA)) {
-    launch_grad8(2, p, pg, p.n + 2 + p.ntau, st);
+  if (same && (kind == KIND_MFMA || (kind >= 5 && kind <= 8)) &&
+      kind == path_kind(pg.N, gflags) && !(flags & KBE_GREATER) && (gflags & KBE_INT_GREXTRA)) {
+    if (kind == KIND_MFMA) launch_grad16(2, p, pg, p.n + 2 + p.ntau, st);
+    else launch_grad8(2, p, pg, p.n + 2 + p.ntau, st);
   } else {
     vjp_grads(p, flags, st);
     vjp_grads(pg, gflags, st);
