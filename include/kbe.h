@@ -374,7 +374,9 @@ kbe_status kbe_collision_both(const kbe_green *G, const kbe_sigma_row *S, const 
  * cotangents of the terms the forms share (gIR + gIRg, gIL + gILg, gItv, gJtv)
  * plus the adjoint of the greater form's own terms (the G^R part of G^> in I^R,
  * the Sigma^R part of Sigma^> in I^<) with gIRg and gILg: two passes over the
- * history instead of the lesser and the greater adjoints' four.
+ * history for the self-energy gradients, and for the Green's-function gradient
+ * one pass that writes each block once with both sets of terms (N = 16 and
+ * 5 <= N <= 8; two at other N).
  *
  * Arguments: as kbe_collision_both for G, S, W, n, m0, m1; the cotangents gIR,
  * gIL, gIRg, gILg [m1-m0][N][N], gItv [m1-m0][N][N] and gJtv [ntau][N][N]
