@@ -818,7 +818,7 @@ struct AA {                        // adaptive-only arrays
   double rtol, atol;
 };
 
-constexpr int NPART = 256;  // workgroups of a norm launch, at most (each fences and counts once)
+constexpr int NPART = 1024;  // workgroups of a norm launch, at most (each fences and counts once)
 
 __global__ void ad_set_t(double *t, int n, double v) {
   if (threadIdx.x == 0) t[n] = v;
@@ -870,7 +870,8 @@ __global__ void __launch_bounds__(256) ad_choose(PA a, AA b, int n, int K, int64
     const kbe_c128 *gl = a.kp + ((int64_t)sidx * a.ldt + n) * E;  // G^<(t_n,t_s) = -gl^dagger
     const kbe_c128 *sl = b.sles + sidx * E, *sr = b.sret + sidx * E;
     cd acc = czero();
-    for (int k = 0; k < N; ++k) {
+#pragma unroll 8
+    for (int k = 0; k < N; ++k) {  // unrolled: the loads of several k are issued together
       acc = acc - ld(gr + r * N + k) * cj(ld(sl + c * N + k));   // G^R (-Sigma^<^dagger)
       // G^<(t_n,t_s): -kp[s][n]^dagger, or kp[n][n] itself on the diagonal
       const cd g = sidx < n ? -cj(ld(gl + k * N + r)) : ld(gl + r * N + k);
@@ -895,7 +896,9 @@ __global__ void __launch_bounds__(256) ad_choose(PA a, AA b, int n, int K, int64
     const double *Lk = a.amt + (int64_t)(k - 1) * KM, *Lk1 = a.amt + (int64_t)(k - 2) * KM;
     for (int64_t q = lane; q < E; q += 64) {
       cd ik = czero(), ik1 = czero();
+#pragma unroll 4
       for (int i = 0; i < k; ++i) ik = ik + Lk[i] * ld(b.ubuf + (int64_t)(K - k + i) * E + q);
+#pragma unroll 4
       for (int i = 0; i < k - 1; ++i) ik1 = ik1 + Lk1[i] * ld(b.ubuf + (int64_t)(K - k + 1 + i) * E + q);
       const cd d = ik - ik1;
       part += d.re * d.re + d.im * d.im;
