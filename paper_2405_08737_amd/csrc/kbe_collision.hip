@@ -65,6 +65,9 @@ enum Cls {
   // both forms in one call (the propagations): I^< of the greater form reads the Sigma^> row
   // through its own class, beside C_IL on the Sigma^< row
   C_ILX,   // I^<, s <= m:  w[m][s] Sigma^>(s) G^R(m,s)^dagger
+  // the greater form's extra adjoint terms when gIR and gIL are one array (KBE_INT_SAMECOT):
+  // B_L and B_GRU on their shared blocks kp[m][s], m > s, with weight w[m][s] - w[n][s]
+  B_LGU,   // m >= s: (w[m][s] - [m > s] w[n][s]) gIL(m) G^R(m,s)  (G^R(s,s) = rdiag[s])
   NCLS
 };
 enum Op { OP_N = 0, OP_H = 1, OP_HN = 2 };
@@ -98,7 +101,7 @@ __host__ __device__ __forceinline__ void cls_range(const Params &p, int o, int &
     case B_R1: lo = o > p.m0 ? o : p.m0; hi = p.m1; break;
     case B_R2: lo = p.m0; hi = o < p.m1 ? o : p.m1; break;
     case B_R3: lo = 0; hi = p.ntau; break;
-    case B_L: lo = o > p.m0 ? o : p.m0; hi = p.m1; break;
+    case B_L: case B_LGU: lo = o > p.m0 ? o : p.m0; hi = p.m1; break;
     case B_T1: lo = p.m0; hi = p.m1; break;
     case B_T2A: lo = o; hi = p.ntau; break;       // output l, terms j >= l
     case B_T2B: lo = 0; hi = o + 1; break;        // output l, terms j <= l
@@ -124,7 +127,7 @@ __host__ __device__ __forceinline__ const kbe_c128 *cls_Q(const Params &p, int t
     case C_ILX: return p.sgt + t * E;
     case C_ITV: case C_JM1: case C_JM2: case G_MAT1: case G_MAT2: return p.stv + t * E;
     case B_R1: case B_R2: case B_GRL: case B_GRD: case B_GRU: return p.gIR + (t - p.m0) * E;
-    case B_L: return p.gIL + (t - p.m0) * E;
+    case B_L: case B_LGU: return p.gIL + (t - p.m0) * E;
     case B_T1: return p.gItv + (t - p.m0) * E;
     case B_R3: case B_T2A: case B_T2B: return p.gJ + t * E;
   }
@@ -178,7 +181,7 @@ __host__ __device__ __forceinline__ void cls_wpP(const Params &p, int o, int t, 
     case B_GRL: w = p.w + ((int64_t)p.n * p.nt + o); P = kp_blk(p, o, t); break;
     case B_GRD: w = p.w + ((int64_t)p.n * p.nt + o); P = p.rdiag + o * E; break;
     case B_GRU: w = p.w + ((int64_t)p.n * p.nt + o); P = kp_blk(p, t, o); break;
-    case B_L:
+    case B_L: case B_LGU:
       w = p.w + ((int64_t)t * p.nt + o);
       P = t > o ? kp_blk(p, t, o) : p.rdiag + o * E;
       break;
@@ -206,12 +209,21 @@ __host__ __device__ __forceinline__ void cls_wpP(const Params &p, int o, int t, 
   }
 }
 
+// The weight a term subtracts from the one cls_wpP addresses (B_LGU below the diagonal: B_GRU's
+// w[n][s]); 0 for every other class.  Read only for a term inside its output's range.
+template <int CLS>
+__device__ __forceinline__ double cls_w2(const Params &p, int o, int t) {
+  if constexpr (CLS == B_LGU) return t > o ? p.w[(int64_t)p.n * p.nt + o] : 0.0;
+  else return 0.0;
+}
+
 template <int CLS>
 __device__ __forceinline__ void cls_wP(const Params &p, int o, int t, double &w,
                                        const kbe_c128 *&P) {
   const double *wp;
   cls_wpP<CLS>(p, o, t, wp, P);
   w = *wp;
+  if constexpr (CLS == B_LGU) w -= cls_w2<CLS>(p, o, t);
 }
 
 // Complex weight c = f w and block P of term t of output o.
@@ -230,7 +242,7 @@ __device__ __forceinline__ void range_rt(int cls, const Params &p, int o, int &l
     KBE_CASE(C_JM2) KBE_CASE(B_R1) KBE_CASE(B_R2) KBE_CASE(B_R3) KBE_CASE(B_L) KBE_CASE(B_T1)
     KBE_CASE(B_T2A) KBE_CASE(B_T2B) KBE_CASE(G_MAT1) KBE_CASE(G_MAT2) KBE_CASE(C_GRL)
     KBE_CASE(C_GRD) KBE_CASE(C_GRU) KBE_CASE(B_GRL) KBE_CASE(B_GRD)
-    KBE_CASE(B_GRU) KBE_CASE(C_ILX)
+    KBE_CASE(B_GRU) KBE_CASE(C_ILX) KBE_CASE(B_LGU)
 #undef KBE_CASE
     default: lo = hi = 0;
   }
@@ -390,7 +402,7 @@ __device__ __forceinline__ void wg_task_small(const Params &p, int nout, int ngr
     // The weight of an absent term is zeroed when the term is computed, not here, so that
     // nothing waits for a prefetch before its use.
     struct Term {
-      double w[ML];
+      double w[ML], w2[ML];  // w2: the weight subtracted (cls_w2; B_LGU only)
       bool in[ML];
       cd x[ML];
     };
@@ -404,6 +416,7 @@ __device__ __forceinline__ void wg_task_small(const Params &p, int nout, int ngr
         wp = tm.in[u] ? wp : p.w;
         P = tm.in[u] ? P : p.rdiag;
         tm.w[u] = *wp;
+        if constexpr (CLS == B_LGU) tm.w2[u] = tm.in[u] ? cls_w2<CLS>(p, o0 + slot * ML + u, t) : 0.0;
         tm.x[u] = ld(P + e);
       }
     };
@@ -413,7 +426,8 @@ __device__ __forceinline__ void wg_task_small(const Params &p, int nout, int ngr
 #pragma unroll
       for (int u = 0; u < ML; ++u) {
         const cd xx = OP == OP_H ? cj(tm.x[u]) : tm.x[u];
-        const double wu = tm.in[u] ? tm.w[u] : 0.0;
+        double wu = tm.in[u] ? tm.w[u] : 0.0;
+        if constexpr (CLS == B_LGU) wu -= tm.w2[u];
         if (FI == 0) y[u] = (FR * wu) * xx;
         else y[u] = cd{-(FI * wu) * xx.im, (FI * wu) * xx.re};
       }
@@ -794,6 +808,9 @@ __global__ void __launch_bounds__(256) stream_fused(Params p, FusedPlan pl, char
           KBE_CASE(B_T2A) KBE_CASE(B_T2B) KBE_CASE(G_MAT1) KBE_CASE(G_MAT2)
         }
         switch (pl.cls[k]) { KBE_CASE(B_GRL) KBE_CASE(B_GRD) KBE_CASE(B_GRU) }
+        if constexpr (KIND != KIND_MFMA) {  // never planned on the MFMA path
+          switch (pl.cls[k]) { KBE_CASE(B_LGU) }
+        }
       }
 #undef KBE_CASE
       lds_barrier();  // LDS tiles and range scratch are reused by the next task
@@ -1568,12 +1585,15 @@ static size_t plan_adjoint_sc(int N, int ntau, int n, int m0, int m1, unsigned f
   const bool th = ntau > 0, M = m1 > m0;
   const bool fITV = (flags & KBE_OUT_ITV) && th, fJTV = (flags & KBE_OUT_JTV) && th;
   if (flags & KBE_INT_GREXTRA) {  // only the greater form's terms beyond the lesser form's
+    // one class for B_L and B_GRU when they share their operand (small-block and generic tasks)
+    const bool merge = (flags & KBE_INT_SAMECOT) && kind != KIND_MFMA &&
+                       (flags & KBE_OUT_IR) && (flags & KBE_OUT_IL);
     if ((flags & KBE_OUT_IR) && M) {
       plan_add(pl, B_GRL, n + 1, m1, E, off);
       plan_add(pl, B_GRD, n + 1, m1, E, off);
-      plan_add(pl, B_GRU, n + 1, m1, E, off);
+      if (!merge) plan_add(pl, B_GRU, n + 1, m1, E, off);
     }
-    if ((flags & KBE_OUT_IL) && M) plan_add(pl, B_L, n + 1, m1, E, off);
+    if ((flags & KBE_OUT_IL) && M) plan_add(pl, merge ? B_LGU : B_L, n + 1, m1, E, off);
     pl.qoff = (int64_t)off;
     return off + 256;
   }
@@ -1615,7 +1635,12 @@ size_t collision_ws_bytes(int N, int nt, int ntau, int n, int m0, int m1, unsign
 size_t collision_vjp_ws_bytes(int N, int nt, int ntau, int n, int m0, int m1, unsigned flags) {
   (void)nt;
   FusedPlan pl;
-  return plan_adjoint(N, ntau, n, m0, m1, flags, path_kind(N, flags), pl);
+  const size_t b = plan_adjoint(N, ntau, n, m0, m1, flags, path_kind(N, flags), pl);
+  if (!(flags & KBE_INT_GREXTRA)) return b;
+  // the launch merges two classes when the cotangents are one array (fewer tasks, possibly
+  // shorter chunks): enough for either plan
+  const size_t b2 = plan_adjoint(N, ntau, n, m0, m1, flags | KBE_INT_SAMECOT, path_kind(N, flags), pl);
+  return b > b2 ? b : b2;
 }
 
 // The most any whole-row call (m in [0, n]) at n < nt needs: what a propagation over nt points
@@ -1787,7 +1812,9 @@ void vjp_sums(const Params &p, unsigned flags, kbe_c128 *gmat, const kbe_sigma_r
               void *ws, hipStream_t st) {
   const int kind = path_kind(p.N, flags);
   FusedPlan pl;
-  plan_adjoint(p.N, p.ntau, p.n, p.m0, p.m1, flags, kind, pl);
+  const unsigned pf =
+      flags | (((flags & KBE_INT_GREXTRA) && p.gIR == p.gIL) ? KBE_INT_SAMECOT : 0u);
+  plan_adjoint(p.N, p.ntau, p.n, p.m0, p.m1, pf, kind, pl);
   char *w = (char *)ws;
   launch_kind<true>(kind, p, pl, w, st);
   // self-energy gradients: overwritten
@@ -1795,7 +1822,7 @@ void vjp_sums(const Params &p, unsigned flags, kbe_c128 *gmat, const kbe_sigma_r
   r.SC = pl.SC;
   const bool extra = flags & KBE_INT_GREXTRA;
   if (extra) {  // the Sigma^R part of Sigma^> in I^< and the G^R terms; nothing reaches Sigma^<
-    reduce_into(p, pl, {B_GRL, B_GRD, B_GRU, B_L}, w, p.n + 1, gS->ret, false, r);
+    reduce_into(p, pl, {B_GRL, B_GRD, B_GRU, B_L, B_LGU}, w, p.n + 1, gS->ret, false, r);
     reduce_into(p, pl, {}, w, p.n + 1, gS->les, false, r);
     reduce_launch(p, r, st);
   } else if (flags & KBE_GREATER)  // Sigma^> = Sigma^R + Sigma^< in I^<: its terms also reach gSigma^R
@@ -2022,7 +2049,7 @@ extern "C" int64_t kbe_internal_audit_tasks(int32_t N, int32_t nt, int32_t ntau,
       case C_ILX: q = &sgtb; break;
       case C_ITV: case C_JM1: case C_JM2: case G_MAT1: case G_MAT2: q = &stvb; break;
       case B_R1: case B_R2: case B_GRL: case B_GRD: case B_GRU: q = &gIRb; break;
-      case B_L: q = &gILb; break;
+      case B_L: case B_LGU: q = &gILb; break;
       case B_T1: q = &gItvb; break;
       default: q = &gJb; break;  // B_R3, B_T2A, B_T2B
     }
@@ -2033,7 +2060,7 @@ extern "C" int64_t kbe_internal_audit_tasks(int32_t N, int32_t nt, int32_t ntau,
       KBE_CASE(C_JM1) KBE_CASE(C_JM2) KBE_CASE(B_R1) KBE_CASE(B_R2) KBE_CASE(B_R3) KBE_CASE(B_L)
       KBE_CASE(B_T1) KBE_CASE(B_T2A) KBE_CASE(B_T2B) KBE_CASE(G_MAT1) KBE_CASE(G_MAT2)
       KBE_CASE(C_GRL) KBE_CASE(C_GRD) KBE_CASE(C_GRU) KBE_CASE(B_GRL) KBE_CASE(B_GRD)
-      KBE_CASE(B_GRU) KBE_CASE(C_ILX)
+      KBE_CASE(B_GRU) KBE_CASE(C_ILX) KBE_CASE(B_LGU)
 #undef KBE_CASE
       default: ++bad;
     }

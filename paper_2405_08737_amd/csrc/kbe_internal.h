@@ -54,6 +54,10 @@ constexpr unsigned KBE_INT_BOTH = 0x10000u;
 // mode only): the G^R terms of I^R and the Sigma^R part of Sigma^> in I^<.  The adjoint of both
 // forms is the lesser form's adjoint on the summed cotangents plus this on the greater form's.
 constexpr unsigned KBE_INT_GREXTRA = 0x20000u;
+// With KBE_INT_GREXTRA, set by the library when the cotangents of I^R and I^< are one array
+// (the propagations): I^<'s Sigma^R terms and the G^R terms of I^R below the diagonal then share
+// operand, streamed block and output, and run as one class.
+constexpr unsigned KBE_INT_SAMECOT = 0x40000u;
 hipError_t launch_collision_both(const Params &p, kbe_c128 *IRl, kbe_c128 *ILl, kbe_c128 *Itv,
                                  kbe_c128 *Jtv, kbe_c128 *IRg, kbe_c128 *ILg, void *ws,
                                  hipStream_t st);

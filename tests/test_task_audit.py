@@ -18,6 +18,7 @@ OUT_ALL, GREATER, FORCE_GENERIC = 0xF, 0x400, 0x100
 OUT_IR_IL = 0x3
 BOTH = 0x10000  # library-internal: both forms in one call (the propagations), forward only
 GREXTRA = 0x20000  # library-internal: the greater form's adjoint beyond the lesser form's
+SAMECOT = 0x40000  # library-internal, with GREXTRA: gIR and gIL are one array (B_L, B_GRU merged)
 
 
 def audit(N, nt, ntau, n, m0, m1, flags, adjoint, ldt=None):
@@ -82,13 +83,21 @@ def test_both_forms_tasks_stay_inside_their_arrays(N, nt, ntau, n, m0, m1):
 
 @pytest.mark.parametrize("N,nt,ntau,n,m0,m1", CASES)
 def test_greater_extra_adjoint_tasks_stay_inside_their_arrays(N, nt, ntau, n, m0, m1):
-    """The propagations' adjoint of the greater form's further terms alone (library-internal)."""
+    """The propagations' adjoint of the greater form's further terms alone (library-internal),
+    also with one cotangent array for I^R and I^< (two classes merged off the MFMA path)."""
     for extra in (0, FORCE_GENERIC):
         bad, checked = audit(N, nt, ntau, n, m0, m1, OUT_IR_IL | GREATER | GREXTRA | extra, 1)
         assert checked > 0
         assert bad == 0, f"{bad} of {checked} addresses outside their arrays"
         full = audit(N, nt, ntau, n, m0, m1, OUT_IR_IL | GREATER | extra, 1)[1]
         assert checked < full
+        bad2, merged = audit(N, nt, ntau, n, m0, m1,
+                             OUT_IR_IL | GREATER | GREXTRA | SAMECOT | extra, 1)
+        assert bad2 == 0, f"{bad2} of {merged} addresses outside their arrays"
+        if N == 16 and not extra:  # the MFMA path keeps the two classes
+            assert merged == checked
+        elif m1 > m0 + 1:  # the merged class reads B_GRU's blocks once, with B_L's
+            assert 0 < merged < checked
 
 
 def test_padded_row_stride():
