@@ -631,31 +631,39 @@ __device__ __forceinline__ void term_compute(const TermOps<MO> &ts, const TermP<
   }
 }
 
-// One workgroup = chunk ch x output groups 4*gb .. 4*gb+3.  qbuf: 2 x 16 x QLD complex in LDS.
+// One workgroup = chunk ch x output groups 4*gb .. 4*gb+3.  qbuf: 4 x 16 x QLD complex in LDS.
 // All 256 threads reach every barrier: the term range is uniform over the workgroup.  The
 // barriers order LDS only, so the global prefetches of the next term stay in flight across
-// them.
-template <int CLS>
+// them.  CB >= 0: the tasks also compute class CB, whose terms are a subset of CLS's with the
+// same streamed block and operation (C_GRU beside C_IL / C_ILX): its Q staged beside CLS's
+// (qbuf + 32 QLD), its own weights and accumulators, its partials into baseB.
+template <int CLS, int CB = -1>
 __device__ __forceinline__ void wg_task_mfma16(const Params &p, int nout, int ngroup, int ch,
                                                int gb, int SC, kbe_c128 *base, cd *qbuf,
-                                               int *rng) {
+                                               int *rng, kbe_c128 *baseB = nullptr) {
   constexpr int MO = MO_MFMA;
+  constexpr bool DUAL = CB >= 0;
+  constexpr int CB_ = DUAL ? CB : CLS;
+  static_assert(!DUAL || cls_op<CB_>() == cls_op<CLS>(), "paired classes share the operation");
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lr = lane & 3, lk = lane >> 4, lc = lane & 15;
   const int g = gb * 4 + wave;
   const int o0 = g * MO;
   const int no = g < ngroup ? (nout - o0 < MO ? nout - o0 : MO) : 0;
-  int lo[MO], hi[MO];
+  int lo[MO], hi[MO], lob[MO], hib[MO];
   int wlo = 1 << 30, whi = 0;
 #pragma unroll
   for (int u = 0; u < MO; ++u) {
     lo[u] = 0;
     hi[u] = 0;
+    lob[u] = 0;
+    hib[u] = 0;
     if (u < no) {
       cls_range<CLS>(p, o0 + u, lo[u], hi[u]);
       wlo = lo[u] < wlo ? lo[u] : wlo;
       whi = hi[u] > whi ? hi[u] : whi;
+      if constexpr (DUAL) cls_range<CB_>(p, o0 + u, lob[u], hib[u]);  // inside [lo, hi)
     }
   }
   // workgroup union of the term ranges, clipped to the chunk
@@ -672,39 +680,54 @@ __device__ __forceinline__ void wg_task_mfma16(const Params &p, int nout, int ng
   T0 = __builtin_amdgcn_readfirstlane(T0 > ch * SC ? T0 : ch * SC);
   T1 = __builtin_amdgcn_readfirstlane(T1 < (ch + 1) * SC ? T1 : (ch + 1) * SC);
   double k1[MO][4], k2[MO][4], k3[MO][4];
+  double b1[MO][4], b2[MO][4], b3[MO][4];  // CB's accumulators
 #pragma unroll
   for (int u = 0; u < MO; ++u)
 #pragma unroll
-    for (int ti = 0; ti < 4; ++ti) k1[u][ti] = k2[u][ti] = k3[u][ti] = 0.0;
+    for (int ti = 0; ti < 4; ++ti) {
+      k1[u][ti] = k2[u][ti] = k3[u][ti] = 0.0;
+      b1[u][ti] = b2[u][ti] = b3[u][ti] = 0.0;
+    }
+  cd *const qb = qbuf + 32 * QLD;  // CB's Q buffers
   if (T0 < T1) {
     const int qrow = tid >> 4, qcol = tid & 15;  // this thread stages element (qrow, qcol)
-    TermOps<MO> ta, tb;
+    TermOps<MO> ta, tb, wa, wb;  // wa, wb: CB's weights (its blocks are CLS's)
     TermP<MO> pa, pb;
     // prologue: Q(T0) into buffer 0, slabs of T0 into pa
     qbuf[qrow * QLD + qcol] = ld(cls_Q<CLS>(p, T0) + tid);
+    if constexpr (DUAL) qb[qrow * QLD + qcol] = ld(cls_Q<CB_>(p, T0) + tid);
     term_setup<CLS, MO>(p, o0, T0, lo, hi, no, ta);
+    if constexpr (DUAL) term_setup<CB_, MO>(p, o0, T0, lob, hib, no, wa);
     term_loadP<CLS, MO>(ta, lk, lc, pa);
     for (int t = T0; t < T1; t += 2) {
       // even term t: compute from (ta, pa, buffer 0); prefetch t+1 into (tb, pb, buffer 1).
       // The prefetch is unconditional: past the range it re-reads the last term (unused).
       const int t1 = t + 1 < T1 ? t + 1 : T1 - 1;
-      cd qn = ld(cls_Q<CLS>(p, t1) + tid);
+      cd qn = ld(cls_Q<CLS>(p, t1) + tid), qnb;
+      if constexpr (DUAL) qnb = ld(cls_Q<CB_>(p, t1) + tid);
       term_setup<CLS, MO>(p, o0, t1, lo, hi, no, tb);
+      if constexpr (DUAL) term_setup<CB_, MO>(p, o0, t1, lob, hib, no, wb);
       term_loadP<CLS, MO>(tb, lk, lc, pb);
       lds_barrier();
       __builtin_amdgcn_sched_barrier(0);
       term_compute<CLS, MO>(ta, pa, qbuf, lr, lk, k1, k2, k3);
+      if constexpr (DUAL) term_compute<CB_, MO>(wa, pa, qb, lr, lk, b1, b2, b3);
       qbuf[16 * QLD + qrow * QLD + qcol] = qn;
+      if constexpr (DUAL) qb[16 * QLD + qrow * QLD + qcol] = qnb;
       if (t + 1 >= T1) break;
       // odd term t+1: compute from (tb, pb, buffer 1); prefetch t+2 into (ta, pa, buffer 0)
       const int t2 = t + 2 < T1 ? t + 2 : T1 - 1;
       qn = ld(cls_Q<CLS>(p, t2) + tid);
+      if constexpr (DUAL) qnb = ld(cls_Q<CB_>(p, t2) + tid);
       term_setup<CLS, MO>(p, o0, t2, lo, hi, no, ta);
+      if constexpr (DUAL) term_setup<CB_, MO>(p, o0, t2, lob, hib, no, wa);
       term_loadP<CLS, MO>(ta, lk, lc, pa);
       lds_barrier();
       __builtin_amdgcn_sched_barrier(0);
       term_compute<CLS, MO>(tb, pb, qbuf + 16 * QLD, lr, lk, k1, k2, k3);
+      if constexpr (DUAL) term_compute<CB_, MO>(wb, pb, qb + 16 * QLD, lr, lk, b1, b2, b3);
       qbuf[qrow * QLD + qcol] = qn;
+      if constexpr (DUAL) qb[qrow * QLD + qcol] = qnb;
     }
   }
   const int64_t E = bsz(p);
@@ -715,6 +738,16 @@ __device__ __forceinline__ void wg_task_mfma16(const Params &p, int nout, int ng
 #pragma unroll
     for (int ti = 0; ti < 4; ++ti)
       st(out + (4 * ti + lk) * 16 + lc, cd{k1[u][ti] - k3[u][ti], k1[u][ti] + k2[u][ti]});
+  }
+  if constexpr (DUAL) {
+#pragma unroll
+    for (int u = 0; u < MO; ++u) {
+      if (u >= no || hib[u] <= lob[u] || hib[u] <= ch * SC || lob[u] >= (ch + 1) * SC) continue;
+      kbe_c128 *out = baseB + ((int64_t)ch * nout + o0 + u) * E;
+#pragma unroll
+      for (int ti = 0; ti < 4; ++ti)
+        st(out + (4 * ti + lk) * 16 + lc, cd{b1[u][ti] - b3[u][ti], b1[u][ti] + b2[u][ti]});
+    }
   }
 }
 
@@ -727,6 +760,10 @@ __device__ __forceinline__ void wg_task_mfma16(const Params &p, int nout, int ng
 struct FusedPlan {
   int ncls, SC, MO;
   int cls[12], nout[12], nchunk[12], ngroup[12];
+  // pair[k] >= 0: class k's tasks also compute class pair[k] (C_GRU beside C_IL or C_ILX on the
+  // MFMA path: the same streamed blocks and outputs), whose entry holds its partial array and
+  // has no tasks of its own
+  int pair[12];
   int64_t first[13];
   int64_t off[12];  // byte offset of each class's partials [nchunk][nout][N*N] in the workspace
   int64_t qoff;     // byte offset of the 8 queue heads
@@ -739,7 +776,7 @@ constexpr int KIND_GENERIC = 0, KIND_MFMA = 16;
 
 template <int KIND>
 __host__ __device__ constexpr int kind_lds() {  // complex numbers of LDS per workgroup
-  if constexpr (KIND == KIND_MFMA) return 2 * 16 * QLD;
+  if constexpr (KIND == KIND_MFMA) return 4 * 16 * QLD;  // two classes' Q, double-buffered
   else if constexpr (KIND >= 1 && KIND <= 8) return SmallCfg<KIND>::LDS;
   else return 1;
 }
@@ -752,6 +789,13 @@ __device__ __forceinline__ void run_task(const Params &p, const FusedPlan &pl, i
   const int gb = (int)(lb / nch);
   kbe_c128 *base = (kbe_c128 *)(ws + pl.off[k]);
   if constexpr (KIND == KIND_MFMA) {
+    if constexpr (CLS == C_IL || CLS == C_ILX) {
+      if (pl.pair[k] >= 0) {  // C_GRU on the same tasks
+        wg_task_mfma16<CLS, C_GRU>(p, pl.nout[k], pl.ngroup[k], ch, gb, pl.SC, base, qbuf, rng,
+                                   (kbe_c128 *)(ws + pl.off[pl.pair[k]]));
+        return;
+      }
+    }
     wg_task_mfma16<CLS>(p, pl.nout[k], pl.ngroup[k], ch, gb, pl.SC, base, qbuf, rng);
   } else if constexpr (KIND >= 1 && KIND <= 8) {
     wg_task_small<KIND, CLS>(p, pl.nout[k], pl.ngroup[k], ch, gb, pl.SC, base, qbuf, rng);
@@ -1515,7 +1559,22 @@ static FusedPlan plan_init(int N, int kind, int SC) {
   FusedPlan pl{};
   pl.SC = SC;
   pl.MO = outputs_per_wave(N, kind);
+  for (int k = 0; k < 12; ++k) pl.pair[k] = -1;
   return pl;
+}
+
+// Class cls computed by the tasks of entry partner (same outputs and chunks): an entry for its
+// partial array, with no tasks.
+static void plan_add_pair(FusedPlan &pl, int cls, int partner, int E, size_t &off) {
+  const int k = pl.ncls++;
+  pl.cls[k] = cls;
+  pl.nout[k] = pl.nout[partner];
+  pl.nchunk[k] = pl.nchunk[partner];
+  pl.ngroup[k] = pl.ngroup[partner];
+  pl.off[k] = (int64_t)off;
+  pl.first[k + 1] = pl.first[k];
+  off += al256(sizeof(kbe_c128) * (size_t)pl.nchunk[k] * pl.nout[k] * E);
+  pl.pair[partner] = k;
 }
 
 // Small-block calls with few tasks (the early rows of a propagation) use shorter term chunks, so
@@ -1543,17 +1602,22 @@ static size_t plan_forward_sc(int N, int ntau, int n, int m0, int m1, unsigned f
   const bool th = ntau > 0;
   const bool both = flags & KBE_INT_BOTH;
   const bool gr = (flags & KBE_GREATER) || both;
+  // MFMA path: C_GRU rides on the tasks of the greater form's I^< class (C_IL on the Sigma^> row,
+  // or C_ILX beside the lesser form), which stream the same blocks kp[m][s], s < m
+  const bool pairgu = gr && kind == KIND_MFMA && (flags & KBE_OUT_IR) && (flags & KBE_OUT_IL) &&
+                      m1 > 1 && M > 0;
   if (flags & KBE_OUT_IR) {
     plan_add(pl, C_IRC, M, m1, E, off);
     if (n > m0) plan_add(pl, C_IRR, M, n + 1, E, off);
     if (gr) {
       if (n > m0) plan_add(pl, C_GRL, M, n + 1, E, off);
       plan_add(pl, C_GRD, M, m1, E, off);
-      if (m1 > 1) plan_add(pl, C_GRU, M, m1 - 1, E, off);
+      if (m1 > 1 && !pairgu) plan_add(pl, C_GRU, M, m1 - 1, E, off);
     }
   }
   if (flags & KBE_OUT_IL) plan_add(pl, C_IL, M, m1, E, off);  // greater form: Q = Sigma^> row
   if (both && (flags & KBE_OUT_IL)) plan_add(pl, C_ILX, M, m1, E, off);
+  if (pairgu) plan_add_pair(pl, C_GRU, pl.ncls - 1, E, off);
   if ((flags & KBE_OUT_ITV) && th) plan_add(pl, C_ITV, M, ntau, E, off);
   if ((flags & KBE_OUT_JTV) && th) {
     plan_add(pl, C_JR, ntau, n + 1, E, off);
@@ -1939,10 +2003,12 @@ struct AuditArr {
   }
 };
 
-template <int CLS>
+// CQ2 >= 0: the tasks also stage class CQ2's operand (from qa2) for every term of the union
+// (a paired class, FusedPlan::pair).
+template <int CLS, int CQ2 = -1>
 void audit_class(const Params &p, const FusedPlan &pl, int k, int kind, const AuditArr *qa,
                  const AuditArr *const *pa, int npa, const AuditArr *wa, int nwa,
-                 int64_t &bad, int64_t &checked) {
+                 int64_t &bad, int64_t &checked, const AuditArr *qa2 = nullptr) {
   const int nch = pl.nchunk[k], nout = pl.nout[k], ngroup = pl.ngroup[k];
   const int64_t ntask = (int64_t)nch * ((ngroup + 3) / 4);
   for (int64_t lb = 0; lb < ntask; ++lb) {
@@ -1985,6 +2051,10 @@ void audit_class(const Params &p, const FusedPlan &pl, int k, int kind, const Au
       for (int t = a; t < b; ++t) {
         ++checked;
         bad += !qa->in(cls_Q<CLS>(p, t));
+        if constexpr (CQ2 >= 0) {
+          ++checked;
+          bad += !qa2->in(cls_Q<CQ2>(p, t));
+        }
       }
     }
   }
@@ -2052,6 +2122,16 @@ extern "C" int64_t kbe_internal_audit_tasks(int32_t N, int32_t nt, int32_t ntau,
       case B_L: case B_LGU: q = &gILb; break;
       case B_T1: q = &gItvb; break;
       default: q = &gJb; break;  // B_R3, B_T2A, B_T2B
+    }
+    if (pl.pair[k] >= 0) {  // C_GRU on the tasks of C_IL or C_ILX (MFMA path)
+      if (pl.cls[pl.pair[k]] != C_GRU) ++bad;
+      if (pl.cls[k] == C_IL)
+        audit_class<C_IL, C_GRU>(p, pl, k, kind, q, Pall, 5, Wall, 3, bad, checked, &retb);
+      else if (pl.cls[k] == C_ILX)
+        audit_class<C_ILX, C_GRU>(p, pl, k, kind, q, Pall, 5, Wall, 3, bad, checked, &retb);
+      else
+        ++bad;
+      continue;
     }
     switch (pl.cls[k]) {
 #define KBE_CASE(C) \
