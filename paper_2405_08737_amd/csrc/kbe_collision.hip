@@ -635,8 +635,8 @@ __device__ __forceinline__ void term_compute(const TermOps<MO> &ts, const TermP<
 // All 256 threads reach every barrier: the term range is uniform over the workgroup.  The
 // barriers order LDS only, so the global prefetches of the next term stay in flight across
 // them.  CB >= 0: the tasks also compute class CB, whose terms are a subset of CLS's with the
-// same streamed block and operation (C_GRU beside C_IL / C_ILX): its Q staged beside CLS's
-// (qbuf + 32 QLD), its own weights and accumulators, its partials into baseB.
+// same streamed block and operation (C_GRU beside C_IL / C_ILX, B_GRU beside B_L): its Q staged
+// beside CLS's (qbuf + 32 QLD), its own weights and accumulators, its partials into baseB.
 template <int CLS, int CB = -1>
 __device__ __forceinline__ void wg_task_mfma16(const Params &p, int nout, int ngroup, int ch,
                                                int gb, int SC, kbe_c128 *base, cd *qbuf,
@@ -760,9 +760,9 @@ __device__ __forceinline__ void wg_task_mfma16(const Params &p, int nout, int ng
 struct FusedPlan {
   int ncls, SC, MO;
   int cls[12], nout[12], nchunk[12], ngroup[12];
-  // pair[k] >= 0: class k's tasks also compute class pair[k] (C_GRU beside C_IL or C_ILX on the
-  // MFMA path: the same streamed blocks and outputs), whose entry holds its partial array and
-  // has no tasks of its own
+  // pair[k] >= 0: class k's tasks also compute class pair[k] (on the MFMA path C_GRU beside C_IL
+  // or C_ILX, B_GRU beside B_L: the same streamed blocks and outputs), whose entry holds its
+  // partial array and has no tasks of its own
   int pair[12];
   int64_t first[13];
   int64_t off[12];  // byte offset of each class's partials [nchunk][nout][N*N] in the workspace
@@ -789,10 +789,11 @@ __device__ __forceinline__ void run_task(const Params &p, const FusedPlan &pl, i
   const int gb = (int)(lb / nch);
   kbe_c128 *base = (kbe_c128 *)(ws + pl.off[k]);
   if constexpr (KIND == KIND_MFMA) {
-    if constexpr (CLS == C_IL || CLS == C_ILX) {
-      if (pl.pair[k] >= 0) {  // C_GRU on the same tasks
-        wg_task_mfma16<CLS, C_GRU>(p, pl.nout[k], pl.ngroup[k], ch, gb, pl.SC, base, qbuf, rng,
-                                   (kbe_c128 *)(ws + pl.off[pl.pair[k]]));
+    if constexpr (CLS == C_IL || CLS == C_ILX || CLS == B_L) {
+      if (pl.pair[k] >= 0) {  // C_GRU (B_GRU) on the same tasks
+        constexpr int CB = CLS == B_L ? B_GRU : C_GRU;
+        wg_task_mfma16<CLS, CB>(p, pl.nout[k], pl.ngroup[k], ch, gb, pl.SC, base, qbuf, rng,
+                                (kbe_c128 *)(ws + pl.off[pl.pair[k]]));
         return;
       }
     }
@@ -1648,6 +1649,10 @@ static size_t plan_adjoint_sc(int N, int ntau, int n, int m0, int m1, unsigned f
   size_t off = 0;
   const bool th = ntau > 0, M = m1 > m0;
   const bool fITV = (flags & KBE_OUT_ITV) && th, fJTV = (flags & KBE_OUT_JTV) && th;
+  // B_L and B_GRU stream the same blocks kp[m][s], m > s, into the same output s: on the MFMA
+  // path B_GRU rides on B_L's tasks (FusedPlan::pair)
+  const bool pairgu = (flags & KBE_GREATER) && kind == KIND_MFMA && (flags & KBE_OUT_IR) &&
+                      (flags & KBE_OUT_IL) && M;
   if (flags & KBE_INT_GREXTRA) {  // only the greater form's terms beyond the lesser form's
     // one class for B_L and B_GRU when they share their operand (small-block and generic tasks)
     const bool merge = (flags & KBE_INT_SAMECOT) && kind != KIND_MFMA &&
@@ -1655,9 +1660,10 @@ static size_t plan_adjoint_sc(int N, int ntau, int n, int m0, int m1, unsigned f
     if ((flags & KBE_OUT_IR) && M) {
       plan_add(pl, B_GRL, n + 1, m1, E, off);
       plan_add(pl, B_GRD, n + 1, m1, E, off);
-      if (!merge) plan_add(pl, B_GRU, n + 1, m1, E, off);
+      if (!merge && !pairgu) plan_add(pl, B_GRU, n + 1, m1, E, off);
     }
     if ((flags & KBE_OUT_IL) && M) plan_add(pl, merge ? B_LGU : B_L, n + 1, m1, E, off);
+    if (pairgu) plan_add_pair(pl, B_GRU, pl.ncls - 1, E, off);
     pl.qoff = (int64_t)off;
     return off + 256;
   }
@@ -1667,11 +1673,12 @@ static size_t plan_adjoint_sc(int N, int ntau, int n, int m0, int m1, unsigned f
     if (flags & KBE_GREATER) {
       plan_add(pl, B_GRL, n + 1, m1, E, off);
       plan_add(pl, B_GRD, n + 1, m1, E, off);
-      plan_add(pl, B_GRU, n + 1, m1, E, off);
+      if (!pairgu) plan_add(pl, B_GRU, n + 1, m1, E, off);
     }
   }
   if (fJTV) plan_add(pl, B_R3, n + 1, ntau, E, off);
   if ((flags & KBE_OUT_IL) && M) plan_add(pl, B_L, n + 1, m1, E, off);
+  if (pairgu) plan_add_pair(pl, B_GRU, pl.ncls - 1, E, off);
   if (fITV && M) plan_add(pl, B_T1, ntau, m1, E, off);
   if (fJTV) {
     plan_add(pl, B_T2A, ntau, ntau, E, off);
@@ -2123,12 +2130,14 @@ extern "C" int64_t kbe_internal_audit_tasks(int32_t N, int32_t nt, int32_t ntau,
       case B_T1: q = &gItvb; break;
       default: q = &gJb; break;  // B_R3, B_T2A, B_T2B
     }
-    if (pl.pair[k] >= 0) {  // C_GRU on the tasks of C_IL or C_ILX (MFMA path)
-      if (pl.cls[pl.pair[k]] != C_GRU) ++bad;
-      if (pl.cls[k] == C_IL)
+    if (pl.pair[k] >= 0) {  // C_GRU (B_GRU) on the tasks of C_IL, C_ILX (B_L); MFMA path
+      const int pc = pl.cls[pl.pair[k]];
+      if (pl.cls[k] == C_IL && pc == C_GRU)
         audit_class<C_IL, C_GRU>(p, pl, k, kind, q, Pall, 5, Wall, 3, bad, checked, &retb);
-      else if (pl.cls[k] == C_ILX)
+      else if (pl.cls[k] == C_ILX && pc == C_GRU)
         audit_class<C_ILX, C_GRU>(p, pl, k, kind, q, Pall, 5, Wall, 3, bad, checked, &retb);
+      else if (pl.cls[k] == B_L && pc == B_GRU)
+        audit_class<B_L, B_GRU>(p, pl, k, kind, q, Pall, 5, Wall, 3, bad, checked, &gIRb);
       else
         ++bad;
       continue;
