@@ -22,8 +22,14 @@
 //   * wg_task_mfma16 (N = 16): FP64 matrix cores (v_mfma_f64_4x4x4, layout below), three real
 //     products per complex one (three accumulators per output); Q staged in LDS per term,
 //     the streamed blocks prefetched into registers a term ahead.
+//   * wg_task_small (N <= 8): vector ALU; a wave holds 64 / N^2 streamed blocks side by side,
+//     each lane one element of a block and its share of every output row (the sum over that
+//     element's index taken once per task through LDS); Q staged in LDS in batches of terms.
 //   * task_generic (any N <= 16): vector ALU, one output per wave, one output element per lane,
 //     several terms per wave for small N summed across lanes at the end.
+// On the MFMA path a class can carry a second one on its tasks (FusedPlan::pair): the greater
+// form's C_GRU beside C_IL / C_ILX and B_GRU beside B_L read the same streamed blocks into the
+// same outputs, each with its own Q, weights, accumulators and partials.
 #include <map>
 #include <mutex>
 #include <tuple>
