@@ -1407,8 +1407,13 @@ constexpr int GSEG8 = 64;   // blocks per workgroup segment (64 beat 32, 128 and
 constexpr int XLD8 = 9;     // LDS row stride of a staged 8x8 block, in complex numbers
 
 // TS: the term set (GradSet).  pg is read by TS = 2 only (the greater form's extra terms; its Sigma
-// row, gradients, row range and mode are those of p).
-template <int TS>
+// row, gradients, row range and mode are those of p).  ACC: blocks add to their current values
+// (accumulate mode; TS = 1: the blocks whose record says so), which are loaded with the block's
+// operands.  Each wave walks every fourth block of the segment with the next block's loads in
+// flight, alternating between two register sets (the loop is unrolled by two, so no prefetched
+// value is copied: a copy would wait for its load); every load is unconditional (an absent
+// term re-reads term 0's block, which the cache holds), so each wait covers exactly one set.
+template <int TS, bool ACC>
 __global__ void __launch_bounds__(256) grad_mfma8(Params p, Params pg, int row_len, int nseg) {
   constexpr int NTM = GradSet<TS>::NT, NX = GradSet<TS>::NX;
   __shared__ cd xs[NX][8 * XLD8];
@@ -1448,71 +1453,75 @@ __global__ void __launch_bounds__(256) grad_mfma8(Params p, Params pg, int row_l
   // D element: row 4 ti + lk, column 4 tj + lj
   const bool dv = 4 * ti + lk < N && bc < N;
   const int dof = dv ? (4 * ti + lk) * N + bc : 0;
-  cd yn[NTM][2];  // raw Y of [term][kc] of the block after the current one
-  cd dn = czero();  // that block's current destination value, when it adds to it
-  auto adds = [&](int q) {  // wave-uniform: does block q add to its destination's value?
-    if constexpr (TS == 1) return __builtin_amdgcn_readfirstlane(rec[q].acc) != 0;
-    else return !p.overwrite;
+  struct Ops {
+    cd y[NTM][2];  // raw Y of [term][kc]
+    cd d;          // the destination's current value (ACC)
   };
-  auto fetch = [&](int q) {
-    const int cnt = __builtin_amdgcn_readfirstlane(rec[q].nt);
+  auto fetch = [&](int q, Ops &f) {
 #pragma unroll
     for (int tm = 0; tm < NTM; ++tm) {
-      if (TS == 2 && tm > 1 && tm >= cnt) break;  // wave-uniform: present terms' loads only
       const kbe_c128 *Y = uniform_ptr(rec[q].y[tm]);
-      yn[tm][0] = ldg(Y + bo0);
-      yn[tm][1] = ldg(Y + bo1);
+      f.y[tm][0] = ldg(Y + bo0);
+      f.y[tm][1] = ldg(Y + bo1);
     }
-    if (cnt > 0 && adds(q) && dv) dn = ldg(uniform_ptr(rec[q].dst) + dof);
+    if constexpr (ACC) f.d = ldg(uniform_ptr(rec[q].dst) + dof);
   };
-  int q = __builtin_amdgcn_readfirstlane(wave);
-  if (q < len) fetch(q);
-  for (; q < len; q += 4) {
+  // Registers that a store reads may be rewritten only after the store, and the wait for it
+  // counts every earlier load too.  So the stored value is not formed in f.d's registers, and
+  // each set's stored value (w) and address (wp) stay live until the other set's loads have
+  // been issued.
+  auto keep = [](const dvec2 &w) { asm volatile("" ::"v"(w.x), "v"(w.y)); };
+  auto keep_p = [](uint64_t a) { asm volatile("" ::"v"(a)); };
+  auto work = [&](int q, const Ops &f, dvec2 &w, uint64_t &wp) {
     const int cnt = __builtin_amdgcn_readfirstlane(rec[q].nt);
+    if (cnt == 0) return;
     kbe_c128 *const cdst = (kbe_c128 *)uniform_ptr(rec[q].dst);
-    cd cs[NTM];
-    const cd *xt[NTM];
-#pragma unroll
-    for (int tm = 0; tm < NTM; ++tm) {
-      cs[tm] = cd{rec[q].cr[tm], rec[q].ci[tm]};
-      xt[tm] = xs[__builtin_amdgcn_readfirstlane(rec[q].x[tm])];
-    }
-    cd y[NTM][2];
-#pragma unroll
-    for (int tm = 0; tm < NTM; ++tm) {
-      if (TS == 2 && tm > 1 && tm >= cnt) break;
-      y[tm][0] = cs[tm] * (bv0 ? yn[tm][0] : czero());
-      y[tm][1] = cs[tm] * (bv1 ? yn[tm][1] : czero());
-    }
-    const cd dcur = dn;  // this block's destination value (loaded with its Y)
-    fetch(q + 4 < len ? q + 4 : len - 1);  // next block's loads before this block's work
-    if (cnt == 0) continue;
-    __builtin_amdgcn_sched_barrier(0);
     // three real products per complex one, A = conj(X) (see grad_mfma16):
     //   K1 += (xr - xi) yr,  K2 += xr (yi - yr),  K3 += xi (yr + yi);  Re = K1 + K3, Im = K1 + K2
     double k1 = 0.0, k2 = 0.0, k3 = 0.0;
 #pragma unroll
     for (int term = 0; term < NTM; ++term) {
       if (term >= cnt) break;  // wave-uniform
-      const cd *x = xt[term];
+      const cd c{rec[q].cr[term], rec[q].ci[term]};
+      const cd *x = xs[__builtin_amdgcn_readfirstlane(rec[q].x[term])];
 #pragma unroll
       for (int kc = 0; kc < 2; ++kc) {
         const cd u = x[(4 * kc + lk) * XLD8 + 4 * ti + lj];
-        const cd v = y[term][kc];
+        const cd v = c * ((kc == 0 ? bv0 : bv1) ? f.y[term][kc] : czero());
         k1 = mfma4(u.re - u.im, v.re, k1);
         k2 = mfma4(u.re, v.im - v.re, k2);
         k3 = mfma4(u.im, v.re + v.im, k3);
       }
     }
     cd r{k1 + k3, k1 + k2};
-    if (dv) {
-      kbe_c128 *d = cdst + dof;
-      if (adds(q)) r = r + dcur;
-      dvec2 w;
-      w.x = r.re;
-      w.y = r.im;
-      __builtin_nontemporal_store(w, (g_dvec2 *)(void *)d);
+    if constexpr (ACC) {
+      if (TS != 1 || __builtin_amdgcn_readfirstlane(rec[q].acc)) r = r + f.d;
     }
+    w.x = r.re;
+    w.y = r.im;
+    wp = (uint64_t)(cdst + dof);
+    if (dv) __builtin_nontemporal_store(w, (g_dvec2 *)wp);
+    if constexpr (ACC) keep(dvec2{f.d.re, f.d.im});  // the sum is not formed in f.d's registers
+  };
+  Ops A, B;
+  dvec2 wA{0.0, 0.0}, wB{0.0, 0.0};  // each set's last stored value and its address
+  uint64_t pA = 0, pB = 0;
+  int q = __builtin_amdgcn_readfirstlane(wave);
+  if (q < len) fetch(q, A);
+  for (; q < len; q += 8) {
+    // block q from A; block q + 4's loads into B first (past the segment: the last block again)
+    fetch(q + 4 < len ? q + 4 : len - 1, B);
+    keep(wB);
+    keep_p(pB);
+    __builtin_amdgcn_sched_barrier(0);
+    work(q, A, wA, pA);
+    __builtin_amdgcn_sched_barrier(0);
+    if (q + 4 >= len) break;
+    fetch(q + 8 < len ? q + 8 : len - 1, A);
+    keep(wA);
+    keep_p(pA);
+    __builtin_amdgcn_sched_barrier(0);
+    work(q + 4, B, wB, pB);
     __builtin_amdgcn_sched_barrier(0);
   }
 }
@@ -1932,9 +1941,17 @@ void launch_grad8(int TS, const Params &p, const Params &pg, int row_len, hipStr
   const int nseg = (row_len + GSEG8 - 1) / GSEG8;
   const int64_t tasks = (int64_t)(p.n + 1) * nseg;
   const dim3 grid((unsigned)(8 * ((tasks + 7) / 8)));
-  if (TS == 0) hipLaunchKernelGGL(grad_mfma8<0>, grid, dim3(256), 0, st, p, pg, row_len, nseg);
-  else if (TS == 1) hipLaunchKernelGGL(grad_mfma8<1>, grid, dim3(256), 0, st, p, pg, row_len, nseg);
-  else hipLaunchKernelGGL(grad_mfma8<2>, grid, dim3(256), 0, st, p, pg, row_len, nseg);
+  const bool acc = !p.overwrite;
+  if (TS == 0 && acc)
+    hipLaunchKernelGGL((grad_mfma8<0, true>), grid, dim3(256), 0, st, p, pg, row_len, nseg);
+  else if (TS == 0)
+    hipLaunchKernelGGL((grad_mfma8<0, false>), grid, dim3(256), 0, st, p, pg, row_len, nseg);
+  else if (TS == 1)  // the records say which blocks add
+    hipLaunchKernelGGL((grad_mfma8<1, true>), grid, dim3(256), 0, st, p, pg, row_len, nseg);
+  else if (acc)
+    hipLaunchKernelGGL((grad_mfma8<2, true>), grid, dim3(256), 0, st, p, pg, row_len, nseg);
+  else
+    hipLaunchKernelGGL((grad_mfma8<2, false>), grid, dim3(256), 0, st, p, pg, row_len, nseg);
 }
 
 // The Green's-function gradients of an adjoint call.  The greater form adds its extra terms

@@ -264,10 +264,12 @@ __global__ void __launch_bounds__(256) sigma_row_vjp_kernel(SigVjpArgs v) {
     st(px, ld(px) + gl * cj(2.0 * U * (x * cj(y))) + cj(gm) * (U * (y * y)));
     contrib = (cj(gl) * (x * x * cj(y))).re;
   }
-  // stage 1 of the interaction gradient: per-block partial sums in a fixed order
-  __shared__ double sc[256];
+  // stage 1 of the interaction gradient: per-block partial sums in a fixed order; each entry's
+  // shares toward gu_i and gu_j are formed here, so the serial sums read LDS only
+  __shared__ double sa[256], sb[256];
   __shared__ int si[256], sj[256];
-  sc[threadIdx.x] = contrib;
+  sa[threadIdx.x] = a.u[cjx] * contrib;  // toward gu_i
+  sb[threadIdx.x] = a.u[ci] * contrib;   // toward gu_j
   si[threadIdx.x] = ci;
   sj[threadIdx.x] = cjx;
   __syncthreads();
@@ -275,8 +277,8 @@ __global__ void __launch_bounds__(256) sigma_row_vjp_kernel(SigVjpArgs v) {
     const int q = threadIdx.x;
     double acc = 0.0;
     for (int t = 0; t < 256; ++t) {
-      if (si[t] == q) acc += a.u[sj[t]] * sc[t];
-      if (sj[t] == q) acc += a.u[si[t]] * sc[t];
+      if (si[t] == q) acc += sa[t];
+      if (sj[t] == q) acc += sb[t];
     }
     v.part[(int64_t)blockIdx.x * N + q] = acc;
   }
