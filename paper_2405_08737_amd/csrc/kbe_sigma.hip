@@ -264,23 +264,21 @@ __global__ void __launch_bounds__(256) sigma_row_vjp_kernel(SigVjpArgs v) {
     st(px, ld(px) + gl * cj(2.0 * U * (x * cj(y))) + cj(gm) * (U * (y * y)));
     contrib = (cj(gl) * (x * x * cj(y))).re;
   }
-  // stage 1 of the interaction gradient: per-block partial sums in a fixed order; each entry's
-  // shares toward gu_i and gu_j are formed here, so the serial sums read LDS only
-  __shared__ double sa[256], sb[256];
-  __shared__ int si[256], sj[256];
-  sa[threadIdx.x] = a.u[cjx] * contrib;  // toward gu_i
-  sb[threadIdx.x] = a.u[ci] * contrib;   // toward gu_j
-  si[threadIdx.x] = ci;
-  sj[threadIdx.x] = cjx;
+  // stage 1 of the interaction gradient: per-block partial sums in a fixed order.  Each entry
+  // adds u_j c to gu_i and u_i c to gu_j; for every orbital q the wave sums its lanes' shares by
+  // a fixed butterfly, then the four waves' sums are added in order.
+  __shared__ double ws[4][KBE_NMAX];
+  const double sa = a.u[cjx] * contrib, sb = a.u[ci] * contrib;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int q = 0; q < N; ++q) {
+    double x = (ci == q ? sa : 0.0) + (cjx == q ? sb : 0.0);
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    if (lane == 0) ws[wv][q] = x;
+  }
   __syncthreads();
   if ((int)threadIdx.x < N) {
     const int q = threadIdx.x;
-    double acc = 0.0;
-    for (int t = 0; t < 256; ++t) {
-      if (si[t] == q) acc += sa[t];
-      if (sj[t] == q) acc += sb[t];
-    }
-    v.part[(int64_t)blockIdx.x * N + q] = acc;
+    v.part[(int64_t)blockIdx.x * N + q] = ((ws[0][q] + ws[1][q]) + ws[2][q]) + ws[3][q];
   }
 }
 
