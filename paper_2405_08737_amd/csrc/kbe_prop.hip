@@ -271,11 +271,13 @@ __global__ void prop_rhs(PA a, int n, int mode) {
     const int m = kind == EU ? idx : n;
     const kbe_c128 *X = a.kp + ((int64_t)m * a.ldt + n) * E;
     cd s = czero();
+#pragma unroll 8
     for (int k = 0; k < N; ++k) s = s + ld(X + r * N + k) * ld(ep + k * N + c);
     f = mul_i(s - cj(Cl(m, c, r)));
   } else if (kind == ER) {  // -i (eps X + C^> - C^<)
     const kbe_c128 *X = a.kp + ((int64_t)n * a.ldt + idx) * E;
     cd s = czero();
+#pragma unroll 8
     for (int k = 0; k < N; ++k) s = s + ld(ep + r * N + k) * ld(X + k * N + c);
     f = mul_mi(s + Cg(idx, r, c) - Cl(idx, r, c));
   } else if (kind == EBR) {  // -i (eps (-i 1) + C^>(n,n) - C^<(n,n))
@@ -289,6 +291,7 @@ __global__ void prop_rhs(PA a, int n, int mode) {
   } else {  // ET: -i (eps X + J)
     const kbe_c128 *X = a.tv + ((int64_t)n * a.ntau + idx) * E;
     cd s = czero();
+#pragma unroll 8
     for (int k = 0; k < N; ++k) s = s + ld(ep + r * N + k) * ld(X + k * N + c);
     f = mul_mi(s + ld(a.Jtv + (int64_t)idx * E + q));
   }
@@ -468,7 +471,8 @@ __global__ void prop_eps_part(PA a, int n) {
   const int ch = (int)(gid / E), q = (int)(gid % E);
   const int e1 = (ch + 1) * EPC < ne ? (ch + 1) * EPC : ne;
   cd s = czero();
-  for (int e = ch * EPC; e < e1; ++e) s = s + ld(a.epart + (int64_t)e * E + q);
+#pragma unroll 8
+  for (int e = ch * EPC; e < e1; ++e) s = s + ld(a.epart + (int64_t)e * E + q);  // loads issued together, added in order
   st(a.epp + gid, s);
 }
 
@@ -478,7 +482,8 @@ __global__ void prop_eps_vjp(PA a, int n, double *gu, double *gamp) {
   if (q >= E) return;
   const int nch = (nelem(a, n) + EPC - 1) / EPC;
   cd s = czero();
-  for (int ch = 0; ch < nch; ++ch) s = s + ld(a.epp + (int64_t)ch * E + q);
+#pragma unroll 8
+  for (int ch = 0; ch < nch; ++ch) s = s + ld(a.epp + (int64_t)ch * E + q);  // added in order
   const int r = q / a.N, c = q % a.N;
   if (r == c) {  // eps_rr += -i u_r D_rr
     kbe_c128 *g = a.gkp + ((int64_t)n * a.ldt + n) * E + q;
